@@ -1,0 +1,123 @@
+/*
+ * liblds — MI355X (gfx950) library for the convex-programming locally
+ * densest subgraph method of arXiv 2504.10937 (LDScvx / LTDScvx).
+ *
+ * C ABI: plain pointers and sizes, no C++ types, no exceptions.  Every call
+ * returns an lds_status; on failure the outputs are left untouched and
+ * lds_last_error() returns a message (thread-local).  Device work is issued
+ * on the HIP stream passed as `hip_stream` (a hipStream_t, NULL = the legacy
+ * default stream).
+ *
+ * Vertex ids are the caller's ids 0..n-1 (int32).  Inside the library
+ * vertices are renumbered; every tie that the method breaks is broken on the
+ * caller's ids (see lds_frank_wolfe).
+ *
+ * Modes: LDS_EDGE   = edge density |E|/|V| (Section 3, Eq. cp),
+ *        LDS_TRIANGLE = triangle density |T|/|V| (Section 6, Eq. trcp).
+ *
+ * Exact arithmetic.  Frank-Wolfe with step gamma_i = 2/(i+2) keeps every load
+ * r_u^(i) and every split alpha^(i) on the common denominator
+ * D_i = (i+1)(i+2) (edges) or 3(i+1)(i+2) (triangles); the library stores the
+ * integer numerators, so every decision (argmin of r over a pattern) is
+ * exact and results do not depend on launch configuration or batching.
+ * Float views are produced on output only.
+ */
+#ifndef LDS_H
+#define LDS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lds_graph_s* lds_graph;
+
+typedef enum { LDS_EDGE = 2, LDS_TRIANGLE = 3 } lds_mode;
+
+typedef enum {
+    LDS_OK = 0,
+    LDS_E_INVALID = 1,  /* bad argument (ids out of range, n < 0, iters < 0, ...) */
+    LDS_E_NOMEM = 2,    /* device or host allocation failed */
+    LDS_E_DEVICE = 3,   /* HIP runtime error */
+    LDS_E_OVERFLOW = 4, /* an exact numerator would exceed 64 bits (see lds_frank_wolfe) */
+    LDS_E_BUSY = 5      /* resource in use (server slots, budget) */
+} lds_status;
+
+/* Flags of lds_create_graph. */
+#define LDS_INPUT_DEVICE 1u /* src/dst are device pointers (else host) */
+#define LDS_STRICT 2u       /* self-loops and duplicate pairs are errors (else dropped) */
+
+/* Thread-local message describing the last failing call ("" if none). */
+const char* lds_last_error(void);
+
+/* Optional device allocator used for all library-owned device memory
+ * (e.g. PyTorch's caching allocator).  alloc(bytes, stream, ctx) returns a
+ * device pointer or NULL; free(ptr, ctx) releases it.  Pass NULLs to return
+ * to hipMalloc/hipFree.  Must be set before any graph is created. */
+typedef void* (*lds_alloc_fn)(size_t bytes, void* hip_stream, void* ctx);
+typedef void (*lds_free_fn)(void* ptr, void* ctx);
+lds_status lds_set_allocator(lds_alloc_fn alloc, lds_free_fn free_fn, void* ctx);
+
+/* Graph ingest (the undirected simple graph G=(V,E) of Section 3).
+ * n: number of vertices (0 <= n < 2^31).  src/dst: npairs int32 endpoint
+ * ids in [0,n), host or device memory (LDS_INPUT_DEVICE); the caller keeps
+ * ownership and may free them on return.  Pairs are undirected; self-loops
+ * and duplicates are dropped unless LDS_STRICT (then LDS_E_INVALID).
+ * On success *out owns its device memory until lds_destroy_graph. */
+lds_status lds_create_graph(int64_t n, int64_t npairs, const int32_t* src, const int32_t* dst, uint32_t flags,
+                            void* hip_stream, lds_graph* out);
+lds_status lds_destroy_graph(lds_graph g);
+
+/* n, number of unique edges m, number of triangles (-1 until listed) and
+ * the device bytes the graph currently holds.  Any output may be NULL. */
+lds_status lds_graph_info(lds_graph g, int64_t* n, int64_t* m, int64_t* n_triangles, size_t* device_bytes);
+
+/* Triangle listing: the set T of Eq. (trcp) / Alg. 6 (the paper uses T but
+ * does not say how it is obtained).  Lists T on the device (once; cached in
+ * the graph) and returns |T|.  If tri_out (host, 3*|T| int32) is non-NULL
+ * and cap >= |T|, writes every triangle as ascending caller ids (a<b<c), in
+ * lexicographic order.  If tcount_out (host, n int64) is non-NULL, writes
+ * t_u per vertex. */
+lds_status lds_triangles(lds_graph g, int64_t* n_triangles, int32_t* tri_out, int64_t cap, int64_t* tcount_out,
+                         void* hip_stream);
+
+/* Frank-Wolfe on CP(G) (Alg. 1, edges) or on the triangle program (Alg. 6),
+ * `iters` >= 0 iterations from the initial split alpha = 1/2 (resp. 1/3).
+ * Iteration i gives every pattern's unit weight to its vertex of smallest
+ * r^(i-1) (synchronous: all decisions read r^(i-1)); exact ties go to the
+ * larger caller id.  Then alpha <- (1-gamma) alpha + gamma alpha_hat with
+ * gamma = 2/(i+2), and r = sum alpha, i.e. r <- (1-gamma) r + gamma b where
+ * b_u counts the units u received.
+ * Outputs (each optional, NULL to skip), all indexed by caller id:
+ *   r_out    device float[n]: r_u^(iters) rounded to FP32 (from the exact
+ *            rational, via FP64)
+ *   r64_out  host double[n]: r_u^(iters) rounded to FP64
+ *   num_out  host uint64[n]: exact numerator A_u with r_u = A_u / D_iters
+ *   gap_out  host double[iters]: FW duality gap at r^(i-1), i = 1..iters,
+ *            2 (sum_u r_u^2 - sum_patterns min_{u in p} r_u), evaluated
+ *            from exact integer sums
+ * The state (loads, splits) stays on the device for lds_splits /
+ * lds_extract.  Returns LDS_E_OVERFLOW if a numerator could exceed the
+ * 64-bit packed key (max degree (resp. triangle count) times the largest
+ * per-vertex increment). */
+lds_status lds_frank_wolfe(lds_graph g, lds_mode mode, int32_t iters, float* r_out, double* r64_out,
+                           uint64_t* num_out, double* gap_out, void* hip_stream);
+
+/* Exact split numerators alpha_{x,p} * D of the last lds_frank_wolfe run
+ * (Eq. cp / Eq. trcp variables).  One entry per incidence (vertex x,
+ * pattern p): edges 2m entries, triangles 3|T| entries.  verts_out (host
+ * int32, h entries per incidence: x first, then the other vertices of p, as
+ * caller ids) and num_out (host uint64 per incidence).  Entries appear in an
+ * unspecified order.  cap = capacity in incidences. */
+lds_status lds_splits(lds_graph g, lds_mode mode, int32_t* verts_out, uint64_t* num_out, int64_t cap,
+                      int64_t* count_out, void* hip_stream);
+
+/* Denominator D_iters of the loads after `iters` iterations. */
+uint64_t lds_denominator(lds_mode mode, int32_t iters);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LDS_H */

@@ -1,0 +1,190 @@
+"""Python binding of liblds (include/lds.h): argument marshalling only.
+
+Every computation runs in the gfx950 library; this module only converts
+numpy arrays / torch tensors to pointers and statuses to exceptions.  The
+library must be built (``python -m paper_2504_10937_amd.build`` or
+``__graft_entry__.build()``); importing a function that needs it raises if it
+is missing — there is no fallback path.
+
+Names follow the C ABI: lds_create_graph, lds_frank_wolfe, ...
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblds.so")
+
+LDS_EDGE = 2
+LDS_TRIANGLE = 3
+LDS_INPUT_DEVICE = 1
+LDS_STRICT = 2
+STATUS = {0: "LDS_OK", 1: "LDS_E_INVALID", 2: "LDS_E_NOMEM", 3: "LDS_E_DEVICE", 4: "LDS_E_OVERFLOW",
+          5: "LDS_E_BUSY"}
+
+_lib = None
+
+
+class LdsError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+def load():
+    """Load liblds.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("liblds.so is not built (run `python -m paper_2504_10937_amd.build`)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32, u32, u64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64
+    st = ctypes.c_int
+    sig = {
+        "lds_last_error": (ctypes.c_char_p, []),
+        "lds_set_allocator": (st, [vp, vp, vp]),
+        "lds_create_graph": (st, [i64, i64, vp, vp, u32, vp, vp]),
+        "lds_destroy_graph": (st, [vp]),
+        "lds_graph_info": (st, [vp, vp, vp, vp, vp]),
+        "lds_triangles": (st, [vp, vp, vp, i64, vp, vp]),
+        "lds_frank_wolfe": (st, [vp, st, i32, vp, vp, vp, vp, vp]),
+        "lds_splits": (st, [vp, st, vp, vp, i64, vp, vp]),
+        "lds_denominator": (u64, [st, i32]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status != 0:
+        raise LdsError(status, load().lds_last_error().decode(errors="replace"))
+
+
+def _stream(stream):
+    """hipStream_t of a torch stream (or the current torch stream)."""
+    if stream is not None:
+        return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except ImportError:
+        pass
+    return None
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        return ctypes.c_void_p(a.data_ptr())
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+class Graph:
+    """Owning handle of an lds_graph."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("graph destroyed")
+        return self._h
+
+    def destroy(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.lds_destroy_graph(self._h)
+        self._h = None
+
+    def __del__(self):
+        self.destroy()
+
+    def info(self):
+        return lds_graph_info(self)
+
+
+def lds_create_graph(n, src, dst, flags=0, stream=None):
+    """Ingest an undirected graph from int32 endpoint arrays (numpy on the
+    host, or torch tensors on the device)."""
+    L = load()
+    on_dev = hasattr(src, "is_cuda") and src.is_cuda
+    if on_dev:
+        import torch
+        src = src.to(torch.int32).contiguous()
+        dst = dst.to(torch.int32).contiguous()
+        flags |= LDS_INPUT_DEVICE
+        npairs = src.numel()
+    else:
+        src = np.ascontiguousarray(src, dtype=np.int32)
+        dst = np.ascontiguousarray(dst, dtype=np.int32)
+        npairs = len(src)
+    if npairs != (dst.numel() if on_dev else len(dst)):
+        raise ValueError("src and dst differ in length")
+    h = ctypes.c_void_p()
+    _check(L.lds_create_graph(int(n), int(npairs), _ptr(src), _ptr(dst), flags, _stream(stream), ctypes.byref(h)))
+    return Graph(h)
+
+
+def lds_destroy_graph(g):
+    g.destroy()
+
+
+def lds_graph_info(g):
+    n, m, t = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    b = ctypes.c_size_t()
+    _check(load().lds_graph_info(g.handle, ctypes.byref(n), ctypes.byref(m), ctypes.byref(t), ctypes.byref(b)))
+    return {"n": n.value, "m": m.value, "triangles": t.value, "device_bytes": b.value}
+
+
+def lds_triangles(g, want_list=False, want_counts=False, stream=None):
+    """List triangles on the device -> (|T|, (|T|,3) int32 or None, (n,) int64 or None)."""
+    L = load()
+    T = ctypes.c_int64()
+    _check(L.lds_triangles(g.handle, ctypes.byref(T), None, 0, None, _stream(stream)))
+    tri = cnt = None
+    if want_list or want_counts:
+        n = lds_graph_info(g)["n"]
+        tri = np.empty((T.value, 3), np.int32) if want_list else None
+        cnt = np.empty(n, np.int64) if want_counts else None
+        _check(L.lds_triangles(g.handle, ctypes.byref(T), _ptr(tri), T.value, _ptr(cnt), _stream(stream)))
+    return T.value, tri, cnt
+
+
+def lds_frank_wolfe(g, mode, iters, r_out=None, want_r64=False, want_num=False, want_gap=False, stream=None):
+    """Run `iters` Frank-Wolfe iterations.  r_out: optional device float32
+    tensor (n,).  Returns dict with 'r64', 'num', 'gap' as requested."""
+    L = load()
+    n = lds_graph_info(g)["n"]
+    r64 = np.empty(n, np.float64) if want_r64 else None
+    num = np.empty(n, np.uint64) if want_num else None
+    gap = np.empty(iters, np.float64) if want_gap else None
+    if r_out is not None and (r_out.numel() < n or not r_out.is_cuda):
+        raise ValueError("r_out must be a device tensor with n elements")
+    _check(L.lds_frank_wolfe(g.handle, mode, int(iters), _ptr(r_out), _ptr(r64), _ptr(num), _ptr(gap),
+                             _stream(stream)))
+    return {"r64": r64, "num": num, "gap": gap, "D": lds_denominator(mode, iters)}
+
+
+def lds_splits(g, mode, stream=None):
+    """Exact split numerators per incidence -> (verts (k,h) caller ids, num (k,))."""
+    L = load()
+    cnt = ctypes.c_int64()
+    _check(L.lds_splits(g.handle, mode, None, None, 0, ctypes.byref(cnt), _stream(stream)))
+    k = cnt.value
+    verts = np.empty((k, mode), np.int32)
+    num = np.empty(k, np.uint64)
+    if k:
+        _check(L.lds_splits(g.handle, mode, _ptr(verts), _ptr(num), k, ctypes.byref(cnt), _stream(stream)))
+    return verts, num
+
+
+def lds_denominator(mode, iters):
+    return int(load().lds_denominator(mode, int(iters)))

@@ -1,0 +1,205 @@
+// C ABI of liblds (declared in include/lds.h): argument checking, error
+// translation (C++ exceptions never cross the boundary), allocator hooks.
+#include "lds.h"
+
+#include <algorithm>
+#include <array>
+#include <memory>
+#include <atomic>
+#include <cstring>
+#include <mutex>
+
+#include "graph.hpp"
+
+struct lds_graph_s {
+    lds::Graph g;
+    std::mutex mu;  // a graph is not meant to be shared between threads; this makes misuse safe
+};
+
+namespace lds {
+
+namespace {
+thread_local std::string t_last_error;
+lds_alloc_fn g_alloc = nullptr;
+lds_free_fn g_free = nullptr;
+void* g_ctx = nullptr;
+std::atomic<int64_t> g_live{0};
+}  // namespace
+
+void set_last_error(const std::string& msg) { t_last_error = msg; }
+
+void* dev_alloc(size_t bytes, hipStream_t s) {
+    void* p = nullptr;
+    if (g_alloc) {
+        p = g_alloc(bytes, (void*)s, g_ctx);
+        if (!p) throw Error(ST_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    } else {
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            throw Error(ST_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+        }
+    }
+    g_live.fetch_add(1);
+    return p;
+}
+
+void dev_free(void* p) {
+    if (!p) return;
+    if (g_free)
+        g_free(p, g_ctx);
+    else
+        (void)hipFree(p);
+    g_live.fetch_sub(1);
+}
+
+}  // namespace lds
+
+#define API_TRY try {
+#define API_CATCH                                                   \
+    }                                                               \
+    catch (const lds::Error& e) {                                   \
+        lds::set_last_error(e.what());                              \
+        return (lds_status)e.code;                                  \
+    }                                                               \
+    catch (const std::bad_alloc&) {                                 \
+        lds::set_last_error("host allocation failed");              \
+        return LDS_E_NOMEM;                                         \
+    }                                                               \
+    catch (const std::exception& e) {                               \
+        lds::set_last_error(e.what());                              \
+        return LDS_E_DEVICE;                                        \
+    }                                                               \
+    return LDS_OK;
+
+extern "C" {
+
+const char* lds_last_error(void) { return lds::t_last_error.c_str(); }
+
+lds_status lds_set_allocator(lds_alloc_fn alloc, lds_free_fn free_fn, void* ctx) {
+    API_TRY
+    LDS_CHECK((alloc == nullptr) == (free_fn == nullptr), lds::ST_INVALID, "alloc and free must both be set or both NULL");
+    LDS_CHECK(lds::g_live.load() == 0, lds::ST_BUSY, "device memory is live: destroy all graphs first");
+    lds::g_alloc = alloc;
+    lds::g_free = free_fn;
+    lds::g_ctx = ctx;
+    API_CATCH
+}
+
+lds_status lds_create_graph(int64_t n, int64_t npairs, const int32_t* src, const int32_t* dst, uint32_t flags,
+                            void* hip_stream, lds_graph* out) {
+    API_TRY
+    LDS_CHECK(out != nullptr, lds::ST_INVALID, "out must not be NULL");
+    LDS_CHECK((flags & ~(LDS_INPUT_DEVICE | LDS_STRICT)) == 0, lds::ST_INVALID, "unknown flags");
+    std::unique_ptr<lds_graph_s> h(new lds_graph_s());
+    lds::build_graph(h->g, n, npairs, src, dst, (flags & LDS_INPUT_DEVICE) != 0, (flags & LDS_STRICT) != 0,
+                     (hipStream_t)hip_stream);
+    *out = h.release();
+    API_CATCH
+}
+
+lds_status lds_destroy_graph(lds_graph g) {
+    API_TRY
+    if (g) {
+        (void)hipStreamSynchronize(g->g.stream);
+        delete g;
+    }
+    API_CATCH
+}
+
+lds_status lds_graph_info(lds_graph g, int64_t* n, int64_t* m, int64_t* n_triangles, size_t* device_bytes) {
+    API_TRY
+    LDS_CHECK(g != nullptr, lds::ST_INVALID, "graph is NULL");
+    std::lock_guard<std::mutex> lk(g->mu);
+    if (n) *n = g->g.n;
+    if (m) *m = g->g.m;
+    if (n_triangles) *n_triangles = g->g.T;
+    if (device_bytes) *device_bytes = g->g.device_bytes();
+    API_CATCH
+}
+
+lds_status lds_triangles(lds_graph g, int64_t* n_triangles, int32_t* tri_out, int64_t cap, int64_t* tcount_out,
+                         void* hip_stream) {
+    API_TRY
+    LDS_CHECK(g != nullptr, lds::ST_INVALID, "graph is NULL");
+    std::lock_guard<std::mutex> lk(g->mu);
+    hipStream_t s = (hipStream_t)hip_stream;
+    lds::Graph& G = g->g;
+    if (G.T < 0) lds::list_triangles(G, s);
+    if (n_triangles) *n_triangles = G.T;
+    const int64_t n = G.n, T = G.T;
+    std::vector<int32_t> orig(n);
+    if ((tri_out || tcount_out) && n > 0) {
+        LDS_HIP(hipMemcpyAsync(orig.data(), G.orig_of.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        LDS_HIP(hipStreamSynchronize(s));
+    }
+    if (tri_out) {
+        LDS_CHECK(cap >= T, lds::ST_INVALID, "tri_out capacity is smaller than the triangle count");
+        std::vector<int32_t> t(3 * T);
+        if (T > 0) {
+            LDS_HIP(hipMemcpyAsync(t.data(), G.tri.p, 3 * T * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            LDS_HIP(hipStreamSynchronize(s));
+        }
+        std::vector<std::array<int32_t, 3>> v((size_t)T);
+        for (int64_t i = 0; i < T; ++i) {
+            std::array<int32_t, 3> x{orig[t[3 * i]], orig[t[3 * i + 1]], orig[t[3 * i + 2]]};
+            std::sort(x.begin(), x.end());
+            v[i] = x;
+        }
+        std::sort(v.begin(), v.end());
+        for (int64_t i = 0; i < T; ++i)
+            for (int j = 0; j < 3; ++j) tri_out[3 * i + j] = v[i][j];
+    }
+    if (tcount_out) {
+        std::vector<int32_t> tc(n);
+        if (n > 0) {
+            LDS_HIP(hipMemcpyAsync(tc.data(), G.tcount.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            LDS_HIP(hipStreamSynchronize(s));
+        }
+        for (int64_t i = 0; i < n; ++i) tcount_out[orig[i]] = tc[i];
+    }
+    API_CATCH
+}
+
+lds_status lds_frank_wolfe(lds_graph g, lds_mode mode, int32_t iters, float* r_out, double* r64_out,
+                           uint64_t* num_out, double* gap_out, void* hip_stream) {
+    API_TRY
+    LDS_CHECK(g != nullptr, lds::ST_INVALID, "graph is NULL");
+    LDS_CHECK(mode == LDS_EDGE || mode == LDS_TRIANGLE, lds::ST_INVALID, "mode must be LDS_EDGE or LDS_TRIANGLE");
+    LDS_CHECK(iters >= 0, lds::ST_INVALID, "iters must be >= 0");
+    std::lock_guard<std::mutex> lk(g->mu);
+    hipStream_t s = (hipStream_t)hip_stream;
+    lds::Graph& G = g->g;
+    lds::fw_run(G, (int)mode, iters, gap_out != nullptr, s);
+    if (r_out || r64_out || num_out) lds::fw_loads(G, (int)mode, r_out, r64_out, num_out, s);
+    if (gap_out) {
+        const auto& f = G.fw[mode == LDS_EDGE ? 0 : 1];
+        std::copy(f.gap.begin(), f.gap.end(), gap_out);
+    }
+    API_CATCH
+}
+
+lds_status lds_splits(lds_graph g, lds_mode mode, int32_t* verts_out, uint64_t* num_out, int64_t cap,
+                      int64_t* count_out, void* hip_stream) {
+    API_TRY
+    LDS_CHECK(g != nullptr, lds::ST_INVALID, "graph is NULL");
+    LDS_CHECK(mode == LDS_EDGE || mode == LDS_TRIANGLE, lds::ST_INVALID, "mode must be LDS_EDGE or LDS_TRIANGLE");
+    std::lock_guard<std::mutex> lk(g->mu);
+    lds::Graph& G = g->g;
+    const lds::SweepPlan& p = (mode == LDS_EDGE) ? G.edge_plan : G.tri_plan;
+    LDS_CHECK(mode == LDS_EDGE || G.T >= 0, lds::ST_INVALID, "no triangle state: run lds_frank_wolfe first");
+    if (count_out) *count_out = p.nslots;
+    if (verts_out || num_out) {
+        LDS_CHECK(verts_out && num_out, lds::ST_INVALID, "verts_out and num_out must both be given");
+        LDS_CHECK(cap >= p.nslots, lds::ST_INVALID, "capacity is smaller than the incidence count");
+        lds::fw_splits(G, (int)mode, verts_out, num_out, (hipStream_t)hip_stream);
+    }
+    API_CATCH
+}
+
+uint64_t lds_denominator(lds_mode mode, int32_t iters) {
+    if (iters < 0) return 0;
+    return (uint64_t)(mode == LDS_TRIANGLE ? 3 : 1) * (uint64_t)(iters + 1) * (uint64_t)(iters + 2);
+}
+
+}  // extern "C"

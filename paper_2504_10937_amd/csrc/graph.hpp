@@ -1,0 +1,104 @@
+// Internal graph and Frank-Wolfe state of the LDS / LTDS library.
+//
+// Vertex numbering.  Callers use their own ("original") ids 0..n-1.  Inside
+// the library vertices are renumbered by degree, descending, ties by
+// original id ascending, so that vertices with the most incident slots come
+// first (high-degree rows become the "hub" prefix processed one workgroup
+// per row) and isolated vertices come last.  Every decision that the method
+// takes on ties uses the ORIGINAL id, never the internal one.
+//
+// Incidence CSR.  The Frank-Wolfe sweep is a pull over "slots": for edges
+// (h = 2) every vertex u has one slot per incident edge holding the other
+// endpoint; for triangles (h = 3) one slot per incident triangle holding the
+// other two vertices.  Rows are "compact": only vertices with at least one
+// slot, ordered by slot count (descending), mapped to internal ids by rowid.
+//
+// Sweep plan.  Rows with more than kChunk slots are hubs, one workgroup
+// each.  The remaining rows are cut into chunks: chunk c holds the rows whose
+// first slot lies in [c*kChunk, (c+1)*kChunk) (relative to the first
+// non-hub slot), so a chunk spans fewer than 2*kChunk slots and always
+// starts at a row start.  Each chunk is one wave64.  The decision bits of one
+// iteration are stored per chunk from a 64-bit-word-aligned offset (cwo),
+// followed by the hub rows (hwo); a per-chunk "head" bitmap marks row starts.
+#pragma once
+#include "common.hpp"
+
+namespace lds {
+
+constexpr int kChunk = 1024;  // target slots per wave; spans < 2*kChunk = 32 words
+
+struct SweepPlan {
+    int h = 2;                  // pattern arity: 2 edges, 3 triangles
+    int64_t nrows = 0;          // compact rows
+    int64_t nslots = 0;
+    const int32_t* rid = nullptr;  // compact row -> internal vertex (nullptr: identity)
+    const int64_t* rp = nullptr;   // nrows + 1 slot offsets
+    const int32_t* py = nullptr;   // nslots * (h - 1) vertex ids (internal)
+    DBuf<int32_t> own_rid;         // storage when the plan owns rid / rp / py
+    DBuf<int64_t> own_rp;
+    DBuf<int32_t> own_py;
+    int64_t n_hub = 0;          // rows [0, n_hub) are hubs
+    DBuf<int64_t> hwo;          // n_hub + 1 word offsets (relative to hub region)
+    int64_t n_chunks = 0;
+    DBuf<int64_t> chunk_row;    // n_chunks + 1 (compact row index)
+    DBuf<int64_t> cwo;          // n_chunks + 1 word offsets
+    DBuf<uint64_t> head;        // chunk_words words: row-start flags
+    int64_t chunk_words = 0, hub_words = 0, total_words = 0;
+    DBuf<int64_t> bitbase;      // per compact row: bit index of its first slot
+    size_t device_bytes() const {
+        return own_rid.bytes() + own_rp.bytes() + own_py.bytes() + hwo.bytes() + chunk_row.bytes() + cwo.bytes() +
+               head.bytes() + bitbase.bytes();
+    }
+    unsigned blocks() const { return (unsigned)(n_hub + (n_chunks + 3) / 4); }
+};
+
+struct FwState {
+    int iters = 0;               // iterations run
+    int cur = 0;                 // keys live in K[cur]
+    DBuf<uint64_t> K[2];         // packed keys (A << B) | (idmask - orig_id), internal order
+    DBuf<uint64_t> bits;         // iters * total_words decision words
+    DBuf<uint64_t> partial;      // iters * blocks * 4 gap partial sums
+    std::vector<double> gap, lb; // per iteration, filled on request
+    size_t device_bytes() const {
+        return K[0].bytes() + K[1].bytes() + bits.bytes() + partial.bytes();
+    }
+};
+
+struct Graph {
+    int64_t n = 0, m = 0;        // vertices, unique undirected edges
+    int64_t n_nz = 0;            // vertices with degree > 0 (internal ids [0, n_nz))
+    int idbits = 1;              // B: bits of the packed original-id code
+    int vbits = 1;               // bits to hold values 0..n
+    int32_t max_deg = 0;
+    DBuf<int32_t> orig_of;       // internal -> original id
+    DBuf<int32_t> int_of;        // original -> internal id
+    DBuf<int32_t> deg;           // internal order
+    DBuf<int64_t> rowptr;        // symmetric CSR, internal ids, n + 1
+    DBuf<int32_t> col;           // 2m, ascending per row
+    SweepPlan edge_plan;         // slots = CSR (rowid identity over [0, n_nz))
+    // triangles (built on first use)
+    int64_t T = -1;
+    DBuf<int32_t> tri;           // 3T internal ids, per triangle (a > b > c internal)
+    DBuf<int32_t> tcount;        // per internal vertex
+    int64_t t_max = 0;
+    SweepPlan tri_plan;
+    FwState fw[2];               // [0] edges, [1] triangles
+    hipStream_t stream = nullptr;
+    size_t device_bytes() const;
+};
+
+// ingest.hip
+void build_graph(Graph& g, int64_t n, int64_t npairs, const int32_t* src, const int32_t* dst, bool on_device,
+                 bool strict, hipStream_t s);
+void build_sweep_plan(SweepPlan& p, hipStream_t s);  // needs h, nrows, nslots, rowptr, pay, rowid
+
+// triangles.hip
+void list_triangles(Graph& g, hipStream_t s);
+
+// fw.hip
+unsigned __int128 fw_max_numerator(const Graph& g, int mode, int iters);
+void fw_run(Graph& g, int mode, int iters, bool want_gap, hipStream_t s);
+void fw_loads(const Graph& g, int mode, float* r32_dev, double* r64_host, uint64_t* A_host, hipStream_t s);
+void fw_splits(const Graph& g, int mode, int32_t* verts_host, uint64_t* num_host, hipStream_t s);
+
+}  // namespace lds

@@ -1,0 +1,244 @@
+// Triangle listing for the triangle-density program (Eq. trcp, Alg. 6 use
+// the triangle set T; the paper does not say how T is obtained).
+//
+// Orientation: internal ids are sorted by degree (descending), so orienting
+// every edge towards the smaller internal id points it at the endpoint of
+// larger degree; out-lists N+(x) = {y in N(x) : y < x} are the prefixes of
+// the ascending CSR rows and have length O(sqrt(m)).  A triangle with
+// internal ids a > b > c is found exactly once, from the oriented edge
+// (a -> b), as the element c of N+(a) ∩ N+(b).
+//
+// Per oriented edge, one thread probes the shorter out-list against the
+// longer one by binary search.  A count pass, an exclusive scan and a write
+// pass give a deterministic order (oriented edges in CSR order, c ascending).
+// The incidence CSR for the Frank-Wolfe pull sweep then holds, for every
+// vertex with t_u > 0 (rows ordered by t_u descending), the other two
+// vertices of each of its triangles, in triangle order.
+#include "graph.hpp"
+
+namespace lds {
+
+namespace {
+
+constexpr int kT = 256;
+
+__device__ inline int64_t lower_bound_i32(const int32_t* a, int64_t lo, int64_t hi, int32_t x) {
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (a[mid] < x) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// out-degree of every vertex: number of neighbours with a smaller internal id
+__global__ void k_outdeg(const int64_t* rp, const int32_t* col, int64_t n, int32_t* outdeg) {
+    const int64_t u = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (u >= n) return;
+    outdeg[u] = (int32_t)(lower_bound_i32(col, rp[u], rp[u + 1], (int32_t)u) - rp[u]);
+}
+
+// slot s of row u is an oriented edge u -> v iff v < u; emit / count the
+// common out-neighbours of u and v (all are < v since N+(v) < v)
+template <bool WRITE>
+__global__ void k_tri_edges(const int64_t* rp, const int32_t* col, const int32_t* outdeg, int64_t n, int64_t ns,
+                            uint32_t* cnt, const uint64_t* off, int32_t* tri) {
+    const int64_t s = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (s >= ns) return;
+    // row of slot s
+    int64_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (rp[mid] <= s) lo = mid; else hi = mid - 1;
+    }
+    const int32_t u = (int32_t)lo;
+    const int32_t v = col[s];
+    uint32_t c = 0;
+    if (v < u) {
+        const int64_t ua = rp[u], ub = rp[u] + outdeg[u];
+        const int64_t va = rp[v], vb = rp[v] + outdeg[v];
+        // probe the shorter list against the longer
+        const bool ushort = (ub - ua) <= (vb - va);
+        const int64_t pa = ushort ? ua : va, pb = ushort ? ub : vb;
+        const int64_t qa = ushort ? va : ua, qb = ushort ? vb : ub;
+        uint64_t o = WRITE ? off[s] : 0;
+        int64_t q = qa;
+        for (int64_t i = pa; i < pb; ++i) {
+            const int32_t w = col[i];
+            if (w >= v) break;  // lists ascending; common elements are < v
+            q = lower_bound_i32(col, q, qb, w);
+            if (q < qb && col[q] == w) {
+                if (WRITE) {
+                    tri[3 * o + 0] = u;
+                    tri[3 * o + 1] = v;
+                    tri[3 * o + 2] = w;
+                    ++o;
+                }
+                ++c;
+            }
+        }
+    }
+    if (!WRITE) cnt[s] = c;
+}
+
+__global__ void k_tcount(const int32_t* tri, int64_t T, int32_t* tc) {
+    const int64_t t = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (t >= T) return;
+    atomicAdd(&tc[tri[3 * t]], 1);
+    atomicAdd(&tc[tri[3 * t + 1]], 1);
+    atomicAdd(&tc[tri[3 * t + 2]], 1);
+}
+
+__global__ void k_tmax(const int32_t* tc, int64_t n, int* out, unsigned long long* nz) {
+    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+    int d = (i < n) ? tc[i] : 0;
+    for (int off = 32; off > 0; off >>= 1) d = max(d, __shfl_xor(d, off, 64));
+    unsigned long long c = __popcll(__ballot(i < n && tc[i] > 0));
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(out, d);
+        if (c) atomicAdd(nz, c);
+    }
+}
+
+// rows: vertices with t > 0 ordered by t descending, internal id ascending
+__global__ void k_row_keys(const int32_t* tc, int64_t n, int vb, int32_t tmax, uint64_t* keys) {
+    const int64_t u = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (u >= n) return;
+    // vertices without triangles sort last (key above every t > 0 key)
+    const uint64_t t = (uint64_t)tc[u];
+    keys[u] = ((t > 0 ? (uint64_t)(tmax - (int32_t)t) : (uint64_t)tmax) << vb) | (uint64_t)u;
+}
+
+__global__ void k_row_apply(const uint64_t* keys, int64_t nrows, int vb, const int32_t* tc, int32_t* rid,
+                            int32_t* row_of, uint32_t* rcount) {
+    const int64_t r = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (r >= nrows) return;
+    const int32_t u = (int32_t)(keys[r] & ((1ull << vb) - 1));
+    rid[r] = u;
+    row_of[u] = (int32_t)r;
+    rcount[r] = (uint32_t)tc[u];
+}
+
+__global__ void k_inc_keys(const int32_t* tri, int64_t T, const int32_t* row_of, int tb, uint64_t* keys) {
+    const int64_t t = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (t >= T) return;
+    for (int j = 0; j < 3; ++j) keys[3 * t + j] = ((uint64_t)row_of[tri[3 * t + j]] << tb) | (uint64_t)t;
+}
+
+__global__ void k_inc_pay(const uint64_t* keys, int64_t ns, int tb, const int32_t* tri, const int32_t* rid,
+                          int32_t* pay) {
+    const int64_t s = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (s >= ns) return;
+    const uint64_t k = keys[s];
+    const int64_t t = (int64_t)(k & ((1ull << tb) - 1));
+    const int32_t x = rid[k >> tb];
+    const int32_t a = tri[3 * t], b = tri[3 * t + 1], c = tri[3 * t + 2];
+    int32_t p, q;
+    if (x == a) { p = b; q = c; } else if (x == b) { p = a; q = c; } else { p = a; q = b; }
+    pay[2 * s] = p;
+    pay[2 * s + 1] = q;
+}
+
+__global__ void k_set_last(int64_t* rowptr, int64_t idx, const uint64_t* total) { rowptr[idx] = (int64_t)*total; }
+
+template <class T>
+T d2h(const T* p, hipStream_t s) {
+    T v;
+    LDS_HIP(hipMemcpyAsync(&v, p, sizeof(T), hipMemcpyDeviceToHost, s));
+    LDS_HIP(hipStreamSynchronize(s));
+    return v;
+}
+
+}  // namespace
+
+void list_triangles(Graph& g, hipStream_t s) {
+    const int64_t n = g.n, ns = 2 * g.m;
+    g.tcount.alloc(n, s);
+    if (n) LDS_HIP(hipMemsetAsync(g.tcount.p, 0, n * sizeof(int32_t), s));
+    int64_t T = 0;
+    if (ns > 0) {
+        DBuf<int32_t> outdeg;
+        outdeg.alloc(n, s);
+        k_outdeg<<<grid_for(n, kT), kT, 0, s>>>(g.rowptr.p, g.col.p, n, outdeg.p);
+        LDS_HIP(hipGetLastError());
+        DBuf<uint32_t> cnt;
+        DBuf<uint64_t> off, tot;
+        cnt.alloc(ns, s);
+        off.alloc(ns, s);
+        tot.alloc(1, s);
+        k_tri_edges<false><<<grid_for(ns, kT), kT, 0, s>>>(g.rowptr.p, g.col.p, outdeg.p, n, ns, cnt.p, nullptr,
+                                                         nullptr);
+        LDS_HIP(hipGetLastError());
+        exclusive_scan_u32_to_u64(cnt.p, off.p, ns, tot.p, s);
+        T = (int64_t)d2h(tot.p, s);
+        cnt.release();
+        g.tri.alloc(3 * T, s);
+        if (T > 0) {
+            k_tri_edges<true><<<grid_for(ns, kT), kT, 0, s>>>(g.rowptr.p, g.col.p, outdeg.p, n, ns, nullptr, off.p,
+                                                            g.tri.p);
+            LDS_HIP(hipGetLastError());
+            k_tcount<<<grid_for(T, kT), kT, 0, s>>>(g.tri.p, T, g.tcount.p);
+            LDS_HIP(hipGetLastError());
+        }
+    }
+    g.T = T;
+    // incidence CSR
+    SweepPlan& p = g.tri_plan;
+    p.h = 3;
+    DBuf<int> tmax;
+    DBuf<unsigned long long> nz;
+    tmax.alloc(1, s);
+    nz.alloc(1, s);
+    LDS_HIP(hipMemsetAsync(tmax.p, 0, sizeof(int), s));
+    LDS_HIP(hipMemsetAsync(nz.p, 0, sizeof(unsigned long long), s));
+    if (n > 0) {
+        k_tmax<<<grid_for(n, kT), kT, 0, s>>>(g.tcount.p, n, tmax.p, nz.p);
+        LDS_HIP(hipGetLastError());
+    }
+    g.t_max = d2h(tmax.p, s);
+    const int64_t nrows = (int64_t)d2h(nz.p, s);
+    p.nrows = nrows;
+    p.nslots = 3 * T;
+    p.own_rid.alloc(nrows, s);
+    p.own_rp.alloc(nrows + 1, s);
+    p.own_py.alloc(2 * 3 * T, s);
+    DBuf<int32_t> row_of;
+    row_of.alloc(n, s);
+    DBuf<uint32_t> rcount;
+    rcount.alloc(nrows, s);
+    if (nrows > 0) {
+        const int vb = g.vbits;
+        DBuf<uint64_t> rk, rt;
+        rk.alloc(n, s);
+        rt.alloc(n, s);
+        k_row_keys<<<grid_for(n, kT), kT, 0, s>>>(g.tcount.p, n, vb, (int32_t)g.t_max, rk.p);
+        LDS_HIP(hipGetLastError());
+        radix_sort_u64(rk.p, nullptr, n, vb + bits_for((uint64_t)g.t_max), rt.p, nullptr, s);
+        k_row_apply<<<grid_for(nrows, kT), kT, 0, s>>>(rk.p, nrows, vb, g.tcount.p, p.own_rid.p, row_of.p,
+                                                      rcount.p);
+        LDS_HIP(hipGetLastError());
+    }
+    DBuf<uint64_t> tot;
+    tot.alloc(1, s);
+    exclusive_scan_u32_to_u64(rcount.p, (uint64_t*)p.own_rp.p, nrows, tot.p, s);
+    k_set_last<<<1, 1, 0, s>>>(p.own_rp.p, nrows, tot.p);
+    LDS_HIP(hipGetLastError());
+    if (T > 0) {
+        const int tb = bits_for((uint64_t)(T - 1)) > 0 ? bits_for((uint64_t)(T - 1)) : 1;
+        const int rb = bits_for((uint64_t)nrows);
+        LDS_CHECK(tb + rb <= 64, ST_OVERFLOW, "triangle incidence key exceeds 64 bits");
+        DBuf<uint64_t> ik, it;
+        ik.alloc(3 * T, s);
+        it.alloc(3 * T, s);
+        k_inc_keys<<<grid_for(T, kT), kT, 0, s>>>(g.tri.p, T, row_of.p, tb, ik.p);
+        LDS_HIP(hipGetLastError());
+        radix_sort_u64(ik.p, nullptr, 3 * T, tb + rb, it.p, nullptr, s);
+        k_inc_pay<<<grid_for(3 * T, kT), kT, 0, s>>>(ik.p, 3 * T, tb, g.tri.p, p.own_rid.p, p.own_py.p);
+        LDS_HIP(hipGetLastError());
+    }
+    p.rid = p.own_rid.p;
+    p.rp = p.own_rp.p;
+    p.py = p.own_py.p;
+    build_sweep_plan(p, s);
+}
+
+}  // namespace lds

@@ -1,0 +1,192 @@
+"""GPU parity: ingest, triangle listing and the Frank-Wolfe sweeps (Alg. 1,
+Alg. 6) against the CPU oracle, element by element, exact."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_helpers import announce, check_fw
+
+pytestmark = pytest.mark.gpu
+
+lds = pytest.importorskip("paper_2504_10937_amd")
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def running_example():
+    with open(os.path.join(GOLD, "running_example.json")) as f:
+        d = json.load(f)
+    e = np.array(d["edges"], np.int32)
+    return d["n"], e[:, 0].copy(), e[:, 1].copy()
+
+
+@pytest.mark.parametrize("mode", [2, 3])
+@pytest.mark.parametrize("iters", [0, 1, 2, 5, 200])
+def test_running_example(mode, iters):
+    announce("running_example", mode, iters)
+    n, s, d = running_example()
+    check_fw(n, s, d, mode, iters)
+
+
+SMALL = [
+    ("er", dict(n=40, p=0.2, seed=1)),
+    ("er", dict(n=64, p=0.5, seed=2)),
+    ("pl", dict(n=500, beta=2.3, avg_deg=6.0, n_blocks=3, s_lo=10, s_hi=20, p_block=0.6, seed=3)),
+    ("hk", dict(n=800, mper=5, p_triad=0.6, seed=4)),
+]
+
+
+def make(kind, kw):
+    if kind == "er":
+        return synth.erdos_renyi(**kw)
+    if kind == "pl":
+        return synth.powerlaw_planted(**kw)
+    return synth.holme_kim(**kw)
+
+
+@pytest.mark.parametrize("mode", [2, 3])
+@pytest.mark.parametrize("case", range(len(SMALL)))
+def test_small_graphs(mode, case):
+    kind, kw = SMALL[case]
+    announce("small", kind, kw, mode)
+    n, s, d = make(kind, kw)
+    check_fw(n, s, d, mode, 37)
+
+
+@pytest.mark.parametrize("mode", [2, 3])
+def test_lds_small_workload(mode):
+    """Chung-Lu n=2000 with 10 planted blocks, N=200 (the small LDS workload)."""
+    n, s, d, _, iters, _ = synth.workload("lds_small")
+    announce("lds_small", mode, iters)
+    check_fw(n, s, d, mode, iters)
+
+
+def test_hub_rows_edges_and_triangles():
+    """Rows longer than one chunk (hub workgroup path): a wheel (hub in 3000
+    edges and 3000 triangles) plus a star and a random background."""
+    rng = np.random.default_rng(5)
+    k = 3000
+    hub = np.zeros(k, np.int32)
+    rim = np.arange(1, k + 1, dtype=np.int32)
+    cyc_a = rim
+    cyc_b = np.roll(rim, -1)
+    star = np.full(2500, k + 1, np.int32)
+    leaves = np.arange(k + 2, k + 2 + 2500, dtype=np.int32)
+    n = k + 2 + 2500
+    ra = rng.integers(0, n, 20000).astype(np.int32)
+    rb = rng.integers(0, n, 20000).astype(np.int32)
+    s = np.concatenate([hub, cyc_a, star, ra])
+    d = np.concatenate([rim, cyc_b, leaves, rb])
+    for mode in (2, 3):
+        announce("hubs", mode)
+        check_fw(n, s, d, mode, 25)
+
+
+def test_many_chunks_powerlaw():
+    n, s, d = synth.powerlaw_planted(30000, 2.1, 20.0, 20, 20, 200, 0.3, seed=8)
+    for mode in (2, 3):
+        announce("chunks", mode)
+        check_fw(n, s, d, mode, 12)
+
+
+def test_triangle_listing_matches_oracle():
+    for kind, kw in SMALL + [("pl", dict(n=20000, beta=2.3, avg_deg=12.0, n_blocks=10, s_lo=20, s_hi=60,
+                                          p_block=0.5, seed=9))]:
+        announce("triangles", kind, kw)
+        n, s, d = make(kind, kw)
+        G = oracle.Graph(n, s, d)
+        tri_o, cnt_o = oracle.triangles(G)
+        g = lds.lds_create_graph(n, s, d)
+        T, tri, cnt = lds.lds_triangles(g, want_list=True, want_counts=True)
+        assert T == len(tri_o)
+        np.testing.assert_array_equal(tri, tri_o)
+        np.testing.assert_array_equal(cnt, cnt_o)
+
+
+def test_kn_triangle_count():
+    n = 40
+    u, v = np.triu_indices(n, 1)
+    g = lds.lds_create_graph(n, u.astype(np.int32), v.astype(np.int32))
+    T, _, cnt = lds.lds_triangles(g, want_counts=True)
+    assert T == n * (n - 1) * (n - 2) // 6
+    assert (cnt == (n - 1) * (n - 2) // 2).all()
+
+
+def test_ingest_hygiene_and_info():
+    announce("ingest")
+    # duplicates in both orientations and self-loops are dropped
+    s = np.array([0, 1, 1, 2, 2, 3, 4], np.int32)
+    d = np.array([1, 0, 1, 3, 3, 2, 4], np.int32)
+    g = lds.lds_create_graph(6, s, d)
+    info = lds.lds_graph_info(g)
+    assert info["n"] == 6 and info["m"] == 2 and info["triangles"] == -1
+    check_fw(6, s, d, 2, 4, gpu_graph=g)
+    with pytest.raises(lds.LdsError) as e:
+        lds.lds_create_graph(6, s, d, flags=lds.LDS_STRICT)
+    assert e.value.status == 1
+    with pytest.raises(lds.LdsError) as e:
+        lds.lds_create_graph(3, np.array([0], np.int32), np.array([3], np.int32))
+    assert e.value.status == 1
+    with pytest.raises(lds.LdsError):
+        lds.lds_create_graph(-1, s, d)
+
+
+def test_empty_and_edgeless():
+    announce("empty")
+    for n in (0, 1, 7):
+        g = lds.lds_create_graph(n, np.zeros(0, np.int32), np.zeros(0, np.int32))
+        for mode in (2, 3):
+            out = lds.lds_frank_wolfe(g, mode, 5, want_num=True, want_r64=True, want_gap=True)
+            assert (out["num"] == 0).all() and (out["r64"] == 0).all() and (out["gap"] == 0).all()
+        assert lds.lds_triangles(g)[0] == 0
+    # a single edge and a single triangle
+    check_fw(2, np.array([0], np.int32), np.array([1], np.int32), 2, 9)
+    check_fw(3, np.array([0, 1, 2], np.int32), np.array([1, 2, 0], np.int32), 3, 9)
+
+
+def test_device_input_and_float_view():
+    announce("device input")
+    n, s, d, _, _, _ = synth.workload("lds_small")
+    ts = torch.from_numpy(s).cuda()
+    td = torch.from_numpy(d).cuda()
+    g = lds.lds_create_graph(n, ts, td)
+    r = torch.empty(n, dtype=torch.float32, device="cuda")
+    out = lds.lds_frank_wolfe(g, 2, 50, r_out=r, want_num=True)
+    torch.cuda.synchronize()
+    want = (out["num"].astype(np.float64) / out["D"]).astype(np.float32)
+    np.testing.assert_array_equal(r.cpu().numpy(), want)
+    G = oracle.Graph(n, s, d)
+    np.testing.assert_array_equal(out["num"], oracle.fw_exact(G, 2, 50, with_gap=False, with_split=False)["A"])
+
+
+def test_deterministic_reruns():
+    announce("determinism")
+    n, s, d = synth.powerlaw_planted(20000, 2.1, 16.0, 10, 20, 100, 0.4, seed=12)
+    g = lds.lds_create_graph(n, s, d)
+    for mode in (2, 3):
+        a = lds.lds_frank_wolfe(g, mode, 30, want_num=True, want_gap=True)
+        va, na = lds.lds_splits(g, mode)
+        b = lds.lds_frank_wolfe(g, mode, 30, want_num=True, want_gap=True)
+        vb, nb = lds.lds_splits(g, mode)
+        np.testing.assert_array_equal(a["num"], b["num"])
+        np.testing.assert_array_equal(a["gap"], b["gap"])
+        np.testing.assert_array_equal(va, vb)
+        np.testing.assert_array_equal(na, nb)
+
+
+def test_overflow_is_reported():
+    announce("overflow")
+    n = 1 << 20
+    s = np.zeros(1000, np.int32)
+    d = np.arange(1, 1001, dtype=np.int32)
+    g = lds.lds_create_graph(n, s, d)
+    with pytest.raises(lds.LdsError) as e:
+        lds.lds_frank_wolfe(g, 2, 2_000_000)
+    assert e.value.status == 4
