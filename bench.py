@@ -1,0 +1,162 @@
+#!/usr/bin/env python3
+"""Benchmark of the Frank-Wolfe hot path (LDS, Alg. 1) on one MI355X.
+
+One step = one pass of the hot path over one synthetic graph whose edge
+list is already resident in HBM: device ingest (canonical simple graph,
+degree renumbering, CSR, sweep plan), N Frank-Wolfe iterations with the
+exact duality gap, and the float view of the loads.  The metric is
+edge-updates per second, m * N / step time.  The dominant kernel is the FW
+sweep; its roofline line uses the sweep launches' HIP-event time and the
+algorithmic bytes of one launch (8.25 B per edge-update: two 4-byte slot ids
+and two decision bits; 16 B per row: own key read and new key written).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload lds_large]
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    with open(os.path.join(ROOT, "paper_2504_10937_amd", "csrc", "fw.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(workload):
+    """HBM bytes per sweep launch from the committed rocprofv3 PMC summary, if
+    it was taken on the current sweep kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "fw_sweep_%s_pmc.md" % workload)
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    h = re.search(r"kernel source sha256\[:16\]:\s*`?([0-9a-f]{16})", txt)
+    b = re.search(r"HBM bytes per launch \(scaled\):\s*([0-9.eE+]+)", txt)
+    if not h or not b or h.group(1) != kernel_source_hash():
+        return None
+    return float(b.group(1))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="lds_large")
+    ap.add_argument("--cpu-iters", type=int, default=4, help="FW iterations of the oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--iters", type=int, default=0, help="override the workload's FW iteration count")
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="first run one device copy of this many MiB (a known-size kernel for counter scaling)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only (one process, one MI355X); "
+              "--gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import synth
+    import paper_2504_10937_amd as lds
+
+    assert torch.cuda.is_available(), "no HIP device"
+    lds.load()
+    lds.lds_set_allocator(True)  # library buffers from torch's caching allocator
+    if args.copy_calib_mib:
+        x = torch.empty(args.copy_calib_mib * 1024 * 1024 // 4, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
+    n, src, dst, mode, iters, k = synth.workload(args.workload)
+    if args.iters:
+        iters = args.iters
+    log("workload %s: n=%d pairs=%d mode=%d N=%d" % (args.workload, n, len(src), mode, iters))
+    ts = torch.from_numpy(src).cuda()
+    td = torch.from_numpy(dst).cuda()
+    r = torch.empty(n, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step():
+        g = lds.lds_create_graph(n, ts, td, stream=stream)
+        lds.lds_frank_wolfe(g, mode, iters, r_out=r, want_gap=True, stream=stream)
+        fw_ms, launches = lds.lds_fw_elapsed(g, mode)
+        info = lds.lds_graph_info(g)
+        sw = lds.lds_sweep_info(g, mode, stream=stream)
+        g.destroy()
+        return fw_ms, launches, info, sw
+
+    for i in range(args.warmup):
+        step()
+        log("warmup %d done" % i)
+    torch.cuda.synchronize()
+    fw_ms = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ms, launches, info, sw = step()
+        fw_ms.append(ms)
+        log("step %d: sweep launches %.3f ms" % (i, ms))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    m = info["m"]
+    units = m if mode == 2 else info["triangles"]
+    value = units * iters / (ms_step / 1e3)
+    fw_mean = sum(fw_ms) / len(fw_ms)
+    per_launch_s = fw_mean / 1e3 / max(launches, 1)
+    slot_bytes = 4 * (mode - 1)
+    alg_bytes = sw["slots"] * slot_bytes + sw["slots"] / 8.0 + sw["rows"] * 16.0
+    achieved = alg_bytes / per_launch_s / 1e9
+    traffic = measured_traffic(args.workload)
+    out = {
+        "metric": "FW edge-updates/s" if mode == 2 else "FW triangle-updates/s",
+        "value": value,
+        "unit": "edge-updates/s" if mode == 2 else "triangle-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "m": m, "triangles": info["triangles"], "fw_iters": iters,
+                   "mode": "edge" if mode == 2 else "triangle", "step": "ingest+fw(gap)+float view"},
+        "fw_only_updates_per_s": units * iters / (fw_mean / 1e3),
+        "fw_sweep_ms_per_launch": per_launch_s * 1e3,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "alg_bytes_per_launch": alg_bytes, "kernel": "k_fw_sweep"},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        log("cpu baseline: oracle ingest (untimed)")
+        G = oracle.Graph(n, src, dst)
+        t = time.perf_counter()
+        oracle.fw_exact(G, mode, args.cpu_iters, with_gap=True, with_split=False)
+        dt = time.perf_counter() - t
+        cpu_units = G.m if mode == 2 else oracle.num_patterns(G, mode)
+        out["cpu_baseline"] = {
+            "value": cpu_units * args.cpu_iters / dt, "unit": out["unit"], "cores": 1, "kind": "oracle",
+            "sample": "%s graph (n=%d, m=%d), %d of the %d FW iterations incl. exact gap, single thread, "
+                      "%.1f s" % (args.workload, n, G.m, args.cpu_iters, iters, dt)}
+        log("cpu baseline: %.3g %s" % (out["cpu_baseline"]["value"], out["unit"]))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -114,6 +114,21 @@ lds_status lds_frank_wolfe(lds_graph g, lds_mode mode, int32_t iters, float* r_o
 lds_status lds_splits(lds_graph g, lds_mode mode, int32_t* verts_out, uint64_t* num_out, int64_t cap,
                       int64_t* count_out, void* hip_stream);
 
+/* GPU time of the sweep launches of the last lds_frank_wolfe call for this
+ * graph and mode, from HIP events recorded on that call's stream right before
+ * the first and after the last sweep launch (waits for the end event).
+ * *launches = number of sweep launches (= iters when the graph has
+ * patterns).  Any output may be NULL. */
+lds_status lds_fw_elapsed(lds_graph g, lds_mode mode, float* ms, int32_t* launches);
+
+/* Shape of the sweep over incidence slots (Alg. 1 / Alg. 6 pull form):
+ * rows (vertices with >= 1 incidence), slots (2m or 3|T|), hub rows (one
+ * workgroup each), row-aligned chunks (one wave64 each) and decision words
+ * per iteration (64 slots per word, word-aligned per chunk / hub row).
+ * For LDS_TRIANGLE the triangles are listed first if needed. */
+lds_status lds_sweep_info(lds_graph g, lds_mode mode, int64_t* rows, int64_t* slots, int64_t* hub_rows,
+                          int64_t* chunks, int64_t* words, void* hip_stream);
+
 /* Denominator D_iters of the loads after `iters` iterations. */
 uint64_t lds_denominator(lds_mode mode, int32_t iters);
 

@@ -52,6 +52,8 @@ def load():
         "lds_frank_wolfe": (st, [vp, st, i32, vp, vp, vp, vp, vp]),
         "lds_splits": (st, [vp, st, vp, vp, i64, vp, vp]),
         "lds_denominator": (u64, [st, i32]),
+        "lds_fw_elapsed": (st, [vp, st, vp, vp]),
+        "lds_sweep_info": (st, [vp, st, vp, vp, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -188,3 +190,50 @@ def lds_splits(g, mode, stream=None):
 
 def lds_denominator(mode, iters):
     return int(load().lds_denominator(mode, int(iters)))
+
+
+def lds_fw_elapsed(g, mode):
+    """(GPU ms of the sweep launches of the last FW run, number of launches)."""
+    ms = ctypes.c_float()
+    k = ctypes.c_int32()
+    _check(load().lds_fw_elapsed(g.handle, mode, ctypes.byref(ms), ctypes.byref(k)))
+    return ms.value, k.value
+
+
+def lds_sweep_info(g, mode, stream=None):
+    """Sweep shape -> dict(rows, slots, hub_rows, chunks, words)."""
+    v = [ctypes.c_int64() for _ in range(5)]
+    _check(load().lds_sweep_info(g.handle, mode, *[ctypes.byref(x) for x in v], _stream(stream)))
+    return dict(zip(("rows", "slots", "hub_rows", "chunks", "words"), (x.value for x in v)))
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+_allocator_refs = None
+
+
+def lds_set_allocator(use_torch=True):
+    """Route the library's device allocations through PyTorch's caching
+    allocator (use_torch=True) or back to hipMalloc/hipFree.  No graph may be
+    alive when switching."""
+    global _allocator_refs
+    L = load()
+    if not use_torch:
+        _check(L.lds_set_allocator(None, None, None))
+        _allocator_refs = None
+        return
+    import torch
+    dev = torch.cuda.current_device()
+
+    def _alloc(nbytes, stream, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), dev, int(stream or 0))
+        except Exception:
+            return None
+
+    def _free(ptr, ctx):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    refs = (_ALLOC_FN(_alloc), _FREE_FN(_free))
+    _check(L.lds_set_allocator(ctypes.cast(refs[0], ctypes.c_void_p), ctypes.cast(refs[1], ctypes.c_void_p), None))
+    _allocator_refs = refs

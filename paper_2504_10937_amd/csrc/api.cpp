@@ -197,6 +197,38 @@ lds_status lds_splits(lds_graph g, lds_mode mode, int32_t* verts_out, uint64_t* 
     API_CATCH
 }
 
+lds_status lds_fw_elapsed(lds_graph g, lds_mode mode, float* ms, int32_t* launches) {
+    API_TRY
+    LDS_CHECK(g != nullptr, lds::ST_INVALID, "graph is NULL");
+    LDS_CHECK(mode == LDS_EDGE || mode == LDS_TRIANGLE, lds::ST_INVALID, "mode must be LDS_EDGE or LDS_TRIANGLE");
+    std::lock_guard<std::mutex> lk(g->mu);
+    const auto& f = g->g.fw[mode == LDS_EDGE ? 0 : 1];
+    LDS_CHECK(f.ev[0] != nullptr, lds::ST_INVALID, "no Frank-Wolfe run recorded for this mode");
+    if (ms) {
+        LDS_HIP(hipEventSynchronize(f.ev[1]));
+        LDS_HIP(hipEventElapsedTime(ms, f.ev[0], f.ev[1]));
+    }
+    if (launches) *launches = f.launches;
+    API_CATCH
+}
+
+lds_status lds_sweep_info(lds_graph g, lds_mode mode, int64_t* rows, int64_t* slots, int64_t* hub_rows,
+                          int64_t* chunks, int64_t* words, void* hip_stream) {
+    API_TRY
+    LDS_CHECK(g != nullptr, lds::ST_INVALID, "graph is NULL");
+    LDS_CHECK(mode == LDS_EDGE || mode == LDS_TRIANGLE, lds::ST_INVALID, "mode must be LDS_EDGE or LDS_TRIANGLE");
+    std::lock_guard<std::mutex> lk(g->mu);
+    lds::Graph& G = g->g;
+    if (mode == LDS_TRIANGLE && G.T < 0) lds::list_triangles(G, (hipStream_t)hip_stream);
+    const lds::SweepPlan& p = (mode == LDS_EDGE) ? G.edge_plan : G.tri_plan;
+    if (rows) *rows = p.nrows;
+    if (slots) *slots = p.nslots;
+    if (hub_rows) *hub_rows = p.n_hub;
+    if (chunks) *chunks = p.n_chunks;
+    if (words) *words = p.total_words;
+    API_CATCH
+}
+
 uint64_t lds_denominator(lds_mode mode, int32_t iters) {
     if (iters < 0) return 0;
     return (uint64_t)(mode == LDS_TRIANGLE ? 3 : 1) * (uint64_t)(iters + 1) * (uint64_t)(iters + 2);

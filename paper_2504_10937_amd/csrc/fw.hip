@@ -44,10 +44,13 @@ struct SweepArgs {
     int64_t chunk_words;
     const uint64_t* Kin;
     uint64_t* Kout;
+    const uint16_t* Qin;  // 16-bit codes of the loads (see qcode)
+    uint16_t* Qout;
     uint64_t* bits;      // this iteration's decision words
     uint64_t inc;
     int B;
     uint64_t* partial;   // 4 words per workgroup (or nullptr)
+    int ncache;          // codes staged in LDS: min(n, kCacheQ)
 };
 
 __device__ inline uint64_t readlane64(uint64_t v, int lane) {
@@ -71,111 +74,240 @@ __device__ inline u128 wave_sum128(u128 x) {
     return x;
 }
 
-// does the row vertex (key Ku) win the pattern stored at slot s?
-template <int H>
-__device__ inline bool slot_wins(const uint64_t* __restrict__ K, uint64_t Ku, const int32_t* __restrict__ py,
-                                 int64_t s);
-template <>
-__device__ inline bool slot_wins<2>(const uint64_t* __restrict__ K, uint64_t Ku, const int32_t* __restrict__ py,
-                                    int64_t s) {
-    return Ku < K[py[s]];
-}
-template <>
-__device__ inline bool slot_wins<3>(const uint64_t* __restrict__ K, uint64_t Ku, const int32_t* __restrict__ py,
-                                    int64_t s) {
-    const int2 p = reinterpret_cast<const int2*>(py)[s];
-    return Ku < K[p.x] && Ku < K[p.y];
+// 16-bit monotone code of a load numerator: a pseudo-float with the 6-bit
+// position of the leading one and the next 10 bits (0 for A = 0).  A < A'
+// implies qcode(A) <= qcode(A'), so different codes decide a comparison of
+// packed keys exactly and equal codes fall back to the 64-bit keys.  The code
+// array is a quarter of the key array, so the gathered working set stays in
+// the L2 caches far more often.
+__device__ inline uint16_t qcode(uint64_t A) {
+    if (A == 0) return 0;
+    const int e = 63 - __clzll(A);
+    const uint64_t mant = (e >= 10) ? (A >> (e - 10)) : (A << (10 - e));
+    return (uint16_t)(((uint32_t)e << 10) | (uint32_t)(mant & 0x3FFu));
 }
 
+// does the row vertex (key ku, code qu) beat the vertex with code qv, whose
+// 64-bit key is gathered only when the codes tie?
+__device__ inline bool beats(uint64_t ku, uint16_t qu, uint16_t qv, const uint64_t* __restrict__ K, int32_t v) {
+    if (qu != qv) return qu < qv;
+    return ku < K[v];
+}
+
+// the h-1 other vertices of the pattern stored at a slot; the slot arrays
+// are streamed once per iteration, so they are read non-temporally to keep
+// the caches for the gathered keys
+template <int H>
+struct Slot {
+    int32_t v[H - 1];
+};
+
+template <int H>
+__device__ inline Slot<H> load_slot(const int32_t* __restrict__ py, int64_t s);
+template <>
+__device__ inline Slot<2> load_slot<2>(const int32_t* __restrict__ py, int64_t s) {
+    Slot<2> r;
+    r.v[0] = __builtin_nontemporal_load(py + s);
+    return r;
+}
+template <>
+__device__ inline Slot<3> load_slot<3>(const int32_t* __restrict__ py, int64_t s) {
+    const long long x = __builtin_nontemporal_load(reinterpret_cast<const long long*>(py) + s);
+    Slot<3> r;
+    r.v[0] = (int32_t)(uint32_t)(unsigned long long)x;
+    r.v[1] = (int32_t)(uint32_t)((unsigned long long)x >> 32);
+    return r;
+}
+
+#ifndef LDS_SWEEP_WORDS
+#define LDS_SWEEP_WORDS 8
+#endif
+#ifndef LDS_SWEEP_THREADS
+#define LDS_SWEEP_THREADS 1024
+#endif
+#ifndef LDS_SWEEP_CACHE
+#define LDS_SWEEP_CACHE 65536
+#endif
+#ifndef LDS_SWEEP_WG_PER_CU
+#define LDS_SWEEP_WG_PER_CU 1
+#endif
+constexpr int kG = LDS_SWEEP_WORDS;         // 64-slot words of a chunk in flight per wave
+constexpr int kHubU = 4;                    // slots per thread in flight in a hub row
+constexpr int kPT = LDS_SWEEP_THREADS;      // threads of a persistent workgroup
+constexpr int kWaves = kPT / 64;
+constexpr int kCacheQ = LDS_SWEEP_CACHE;    // codes of the first (highest-degree) vertices staged in LDS
+constexpr int kWgPerCU = LDS_SWEEP_WG_PER_CU;
+
+// code of vertex v: from the LDS copy for the hot prefix, else from memory
+__device__ inline uint16_t qload(const uint16_t* __restrict__ qc, int nc, const uint16_t* __restrict__ Q,
+                                 uint32_t v) {
+    uint16_t q;
+    if (v < (uint32_t)nc)
+        q = qc[v];
+    else
+        q = Q[v];
+    return q;
+}
+
+// Persistent sweep: one workgroup per CU.  The workgroup first copies the
+// codes of the kCacheQ highest-degree vertices (internal ids [0, kCacheQ))
+// into LDS; those vertices take most of the gathers of a power-law graph.
+// It then processes hub rows (whole workgroup each) and chunks (one wave
+// each), both strided over the grid.
 template <int H, bool IDENT, bool GAP>
-__global__ __launch_bounds__(256) void k_fw_sweep(SweepArgs a) {
-    __shared__ uint64_t red[4][4];
-    __shared__ uint32_t hcnt[4];
+__global__ __launch_bounds__(kPT) void k_fw_sweep(SweepArgs a) {
+    extern __shared__ uint16_t qc[];
+    __shared__ uint64_t red[kWaves][4];
+    __shared__ uint32_t hcnt[kWaves];
+    __shared__ uint64_t words[kWaves][32];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nc = a.ncache;
+    for (int i = threadIdx.x; i < nc; i += kPT) qc[i] = a.Qin[i];
+    __syncthreads();
     u128 sq = 0, mn = 0;
-    if ((int64_t)blockIdx.x < a.n_hub) {
-        // ---- hub row: one workgroup
-        const int64_t r = blockIdx.x;
-        const int32_t u = IDENT ? (int32_t)r : a.rid[r];
+    // ---- hub rows: one workgroup each, 4096 slots per step
+    for (int64_t r = blockIdx.x; r < a.n_hub; r += gridDim.x) {
+        const uint32_t u = IDENT ? (uint32_t)r : (uint32_t)a.rid[r];
         const int64_t s0 = a.rp[r], s1 = a.rp[r + 1];
         const uint64_t Ku = a.Kin[u];
+        const uint16_t Qu = qcode(Ku >> a.B);
         uint64_t* bw = a.bits + a.chunk_words + a.hwo[r];
         uint32_t cnt = 0;
-        for (int64_t base = s0; base < s1; base += 256) {
-            const int64_t s = base + threadIdx.x;
-            const bool win = (s < s1) && slot_wins<H>(a.Kin, Ku, a.py, s);
-            const uint64_t W = __ballot(win);
-            if (lane == 0 && base + 64 * w < s1) bw[(base - s0) / 64 + w] = W;
-            cnt += (uint32_t)__popcll(W);
+        for (int64_t base = s0; base < s1; base += (int64_t)kPT * kHubU) {
+            Slot<H> sl[kHubU];
+            bool in[kHubU];
+#pragma unroll
+            for (int k = 0; k < kHubU; ++k) {
+                const int64_t s = base + (int64_t)k * kPT + threadIdx.x;
+                in[k] = s < s1;
+                if (in[k]) sl[k] = load_slot<H>(a.py, s);
+            }
+            uint16_t qv[kHubU][H - 1];
+#pragma unroll
+            for (int k = 0; k < kHubU; ++k)
+#pragma unroll
+                for (int q = 0; q < H - 1; ++q)
+                    qv[k][q] = in[k] ? qload(qc, nc, a.Qin, (uint32_t)sl[k].v[q]) : (uint16_t)0;
+#pragma unroll
+            for (int k = 0; k < kHubU; ++k) {
+                bool win = in[k];
+#pragma unroll
+                for (int q = 0; q < H - 1; ++q) win = win && beats(Ku, Qu, qv[k][q], a.Kin, sl[k].v[q]);
+                const uint64_t W = __ballot(win);
+                const int64_t wb = base + (int64_t)k * kPT + 64 * w;  // first slot of this wave's word
+                if (lane == 0 && wb < s1) __builtin_nontemporal_store(W, bw + (wb - s0) / 64);
+                cnt += (uint32_t)__popcll(W);
+            }
         }
         if (lane == 0) hcnt[w] = cnt;
         __syncthreads();
         if (threadIdx.x == 0) {
-            const uint64_t tot = (uint64_t)hcnt[0] + hcnt[1] + hcnt[2] + hcnt[3];
-            a.Kout[u] = Ku + ((tot * a.inc) << a.B);
+            uint64_t tot = 0;
+            for (int q = 0; q < kWaves; ++q) tot += hcnt[q];
+            const uint64_t Kn = Ku + ((tot * a.inc) << a.B);
+            a.Kout[u] = Kn;
+            a.Qout[u] = qcode(Kn >> a.B);
             if (GAP) {
                 const uint64_t A = Ku >> a.B;
-                sq = (u128)A * A;
-                mn = (u128)A * tot;
+                sq += (u128)A * A;
+                mn += (u128)A * tot;
             }
         }
-    } else {
-        // ---- chunk: one wave64
-        const int64_t c = ((int64_t)blockIdx.x - a.n_hub) * 4 + w;
-        if (c < a.n_chunks) {
-            const int64_t r0 = a.chunk_row[c], r1 = a.chunk_row[c + 1];
-            if (r0 < r1) {
-                const int64_t s0 = a.rp[r0], s1 = a.rp[r1];
-                const int64_t w0 = a.cwo[c];
-                const int nw = (int)(a.cwo[c + 1] - w0);
-                const uint64_t hreg = (lane < nw) ? a.head[w0 + lane] : 0ull;
-                const uint64_t le = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
-                int64_t rowbase = r0 - 1;  // row of the slot just before this word
-                uint32_t carry = 0;        // wins of the still-open row from earlier words
-                uint64_t mybits = 0;
-                for (int t = 0; t < nw; ++t) {
-                    const uint64_t Hd = readlane64(hreg, t);
-                    const uint64_t Hn = (t + 1 < nw) ? readlane64(hreg, t + 1) : 1ull;
-                    const int64_t s = s0 + (int64_t)t * 64 + lane;
-                    const bool valid = s < s1;
-                    const int64_t row = rowbase + __popcll(Hd & le);
-                    bool win = false;
-                    uint64_t Ku = 0;
-                    int32_t u = 0;
-                    if (valid) {
-                        u = IDENT ? (int32_t)row : a.rid[row];
-                        Ku = a.Kin[u];
-                        win = slot_wins<H>(a.Kin, Ku, a.py, s);
-                    }
-                    const uint64_t W = __ballot(win);
-                    if (lane == t) mybits = W;
-                    // lanes whose slot is the last of its row
-                    const int64_t rem = s1 - (s0 + (int64_t)t * 64);
-                    uint64_t E = (Hd >> 1) | (Hn << 63);
-                    if (rem < 64) E |= 1ull << (rem - 1);
-                    if (valid && ((E >> lane) & 1ull)) {
-                        const uint64_t hb = Hd & le;
-                        const int st = hb ? 63 - __clzll(hb) : 0;
-                        const uint64_t seg = le & (~0ull << st);
-                        const uint32_t cnt = (uint32_t)__popcll(W & seg) + (hb ? 0u : carry);
-                        a.Kout[u] = Ku + (((uint64_t)cnt * a.inc) << a.B);
-                        if (GAP) {
-                            const uint64_t A = Ku >> a.B;
-                            sq += (u128)A * A;
-                            mn += (u128)A * cnt;
+        __syncthreads();  // hcnt is reused by the next hub row
+    }
+    // ---- chunks: one wave each
+    //   A. decision words: kG words per batch, slot payloads then codes in
+    //      flight; each word's ballot is kept by lane t
+    //   B. one lane per row: popcount of the row's slot range in the chunk's
+    //      decision words (staged in LDS), key and code update
+    for (int64_t c = (int64_t)blockIdx.x * kWaves + w; c < a.n_chunks; c += (int64_t)gridDim.x * kWaves) {
+        const int64_t r0 = a.chunk_row[c], r1 = a.chunk_row[c + 1];
+        if (r0 >= r1) continue;
+        const int64_t s0 = a.rp[r0], s1 = a.rp[r1];
+        const int64_t w0 = a.cwo[c];
+        const int nw = (int)(a.cwo[c + 1] - w0);  // <= 32: a chunk spans < 2048 slots
+        const int nsl = (int)(s1 - s0);
+        const int32_t* __restrict__ pyc = a.py + s0 * (H - 1);
+        const uint64_t hreg = (lane < nw) ? __builtin_nontemporal_load(a.head + w0 + lane) : 0ull;
+        const uint64_t le = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+        int32_t rowrel = -1;  // chunk-relative row of the slot before the current word
+        uint64_t mybits = 0;
+        for (int t0 = 0; t0 < nw; t0 += kG) {
+            uint64_t Hw[kG];
+#pragma unroll
+            for (int j = 0; j < kG; ++j) Hw[j] = readlane64(hreg, t0 + j);  // t0 + j < 40
+            Slot<H> sl[kG];
+            uint32_t uu[kG];
+            bool val[kG];
+            int32_t rb = rowrel;
+#pragma unroll
+            for (int j = 0; j < kG; ++j) {
+                const int off = (t0 + j) * 64 + lane;
+                val[j] = off < nsl;
+                const int32_t row = rb + (int32_t)__popcll(Hw[j] & le);
+                rb += (int32_t)__popcll(Hw[j]);
+                uu[j] = 0;
+                if (val[j]) {
+                    sl[j] = load_slot<H>(pyc, off);
+                    uu[j] = IDENT ? (uint32_t)(r0 + row) : (uint32_t)a.rid[r0 + row];
+                }
+            }
+            rowrel = rb;
+            uint16_t qu[kG], qv[kG][H - 1];
+#pragma unroll
+            for (int j = 0; j < kG; ++j) {
+                qu[j] = val[j] ? qload(qc, nc, a.Qin, uu[j]) : (uint16_t)0;
+#pragma unroll
+                for (int q = 0; q < H - 1; ++q)
+                    qv[j][q] = val[j] ? qload(qc, nc, a.Qin, (uint32_t)sl[j].v[q]) : (uint16_t)0;
+            }
+#pragma unroll
+            for (int j = 0; j < kG; ++j) {
+                if (t0 + j < nw) {
+                    bool win = val[j];
+#pragma unroll
+                    for (int q = 0; q < H - 1; ++q) {
+                        if (qu[j] != qv[j][q]) {
+                            win = win && (qu[j] < qv[j][q]);
+                        } else if (win) {
+                            win = a.Kin[uu[j]] < a.Kin[(uint32_t)sl[j].v[q]];
                         }
                     }
-                    if (t + 1 < nw && !(Hn & 1ull)) {
-                        const int lh = Hd ? 63 - __clzll(Hd) : -1;
-                        carry = (lh < 0) ? carry + (uint32_t)__popcll(W) : (uint32_t)__popcll(W & (~0ull << lh));
-                    } else {
-                        carry = 0;
-                    }
-                    rowbase += __popcll(Hd);
+                    const uint64_t W = __ballot(win);
+                    if (lane == t0 + j) mybits = W;
                 }
-                if (lane < nw) a.bits[w0 + lane] = mybits;
             }
         }
+        if (lane < nw) {
+            __builtin_nontemporal_store(mybits, a.bits + w0 + lane);
+            words[w][lane] = mybits;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        for (int64_t rbase = r0; rbase < r1; rbase += 64) {
+            const int64_t r = rbase + lane;
+            if (r < r1) {
+                const int sa = (int)(a.rp[r] - s0), sb = (int)(a.rp[r + 1] - s0);  // sb > sa
+                uint32_t cnt = 0;
+                for (int wd = sa >> 6; wd <= ((sb - 1) >> 6); ++wd) {
+                    const int lo = max(sa - wd * 64, 0), hi = min(sb - wd * 64, 64);
+                    const uint64_t mk = ((hi >= 64) ? ~0ull : ((1ull << hi) - 1ull)) & (~0ull << lo);
+                    cnt += (uint32_t)__popcll(words[w][wd] & mk);
+                }
+                const uint32_t u = IDENT ? (uint32_t)r : (uint32_t)a.rid[r];
+                const uint64_t Ku = a.Kin[u];
+                const uint64_t Kn = Ku + (((uint64_t)cnt * a.inc) << a.B);
+                a.Kout[u] = Kn;
+                a.Qout[u] = qcode(Kn >> a.B);
+                if (GAP) {
+                    const uint64_t A = Ku >> a.B;
+                    sq += (u128)A * A;
+                    mn += (u128)A * cnt;
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();  // words[w] is rewritten by the next chunk
     }
     if (GAP) {
         sq = wave_sum128(sq);
@@ -189,7 +321,7 @@ __global__ __launch_bounds__(256) void k_fw_sweep(SweepArgs a) {
         __syncthreads();
         if (threadIdx.x == 0) {
             u128 S = 0, M = 0;
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < kWaves; ++q) {
                 S += ((u128)red[q][1] << 64) | red[q][0];
                 M += ((u128)red[q][3] << 64) | red[q][2];
             }
@@ -238,13 +370,15 @@ __global__ __launch_bounds__(256) void k_gap_reduce(const uint64_t* partial, int
 // initial keys: A0 = deg (edges, r0 = deg/2 with D0 = 2) or 2 t_u (triangles,
 // r0 = t_u/3 with D0 = 6), packed with the original-id code
 __global__ void k_init_keys(const int32_t* count, int mult, const int32_t* orig_of, int64_t n, int B,
-                            uint64_t* K0, uint64_t* K1) {
+                            uint64_t* K0, uint64_t* K1, uint16_t* Q0, uint16_t* Q1) {
     const int64_t u = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (u >= n) return;
     const uint64_t idm = (1ull << B) - 1ull;
-    const uint64_t k = ((uint64_t)count[u] * (uint64_t)mult << B) | (idm - (uint64_t)orig_of[u]);
+    const uint64_t A = (uint64_t)count[u] * (uint64_t)mult;
+    const uint64_t k = (A << B) | (idm - (uint64_t)orig_of[u]);
     K0[u] = k;
     K1[u] = k;
+    Q0[u] = Q1[u] = qcode(A);
 }
 
 __global__ void k_loads(const uint64_t* K, const int32_t* orig_of, int64_t n, int B, double D, float* r32,
@@ -288,10 +422,36 @@ uint64_t denom(int mode, int64_t i) { return (uint64_t)(mode == 3 ? 3 : 1) * (ui
 
 template <int H, bool IDENT>
 void launch_sweep(const SweepArgs& a, unsigned blocks, bool gap, hipStream_t s) {
-    if (gap)
-        k_fw_sweep<H, IDENT, true><<<blocks, 256, 0, s>>>(a);
-    else
-        k_fw_sweep<H, IDENT, false><<<blocks, 256, 0, s>>>(a);
+    const size_t lds = (size_t)a.ncache * sizeof(uint16_t);
+    if (gap) {
+        static bool attr = false;
+        if (!attr) {
+            LDS_HIP(hipFuncSetAttribute((const void*)k_fw_sweep<H, IDENT, true>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, kCacheQ * 2 + 16));
+            attr = true;
+        }
+        k_fw_sweep<H, IDENT, true><<<blocks, kPT, lds, s>>>(a);
+    } else {
+        static bool attr = false;
+        if (!attr) {
+            LDS_HIP(hipFuncSetAttribute((const void*)k_fw_sweep<H, IDENT, false>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, kCacheQ * 2 + 16));
+            attr = true;
+        }
+        k_fw_sweep<H, IDENT, false><<<blocks, kPT, lds, s>>>(a);
+    }
+}
+
+// one persistent workgroup per compute unit
+unsigned sweep_grid() {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        LDS_HIP(hipGetDevice(&dev));
+        LDS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        if (cus <= 0) cus = 1;
+    }
+    return (unsigned)(cus * kWgPerCU);
 }
 
 }  // namespace
@@ -318,16 +478,19 @@ void fw_run(Graph& g, int mode, int iters, bool want_gap, hipStream_t s) {
     if (f.K[0].n != (size_t)n) {
         f.K[0].alloc(n, s);
         f.K[1].alloc(n, s);
+        f.Q[0].alloc(n, s);
+        f.Q[1].alloc(n, s);
     }
     if (n > 0) {
         const int32_t* cnt = (mode == 2) ? g.deg.p : g.tcount.p;
-        k_init_keys<<<grid_for(n, 256), 256, 0, s>>>(cnt, mode == 2 ? 1 : 2, g.orig_of.p, n, B, f.K[0].p, f.K[1].p);
+        k_init_keys<<<grid_for(n, 256), 256, 0, s>>>(cnt, mode == 2 ? 1 : 2, g.orig_of.p, n, B, f.K[0].p, f.K[1].p,
+                                                    f.Q[0].p, f.Q[1].p);
         LDS_HIP(hipGetLastError());
     }
     f.cur = 0;
     const size_t nbits = (size_t)iters * (size_t)p.total_words;
     if (f.bits.n < nbits) f.bits.alloc(nbits, s);
-    const unsigned blocks = p.blocks();
+    const unsigned blocks = sweep_grid();
     const size_t npart = want_gap ? (size_t)iters * blocks * 4 : 0;
     if (f.partial.n < npart) f.partial.alloc(npart, s);
     SweepArgs a{};
@@ -342,9 +505,18 @@ void fw_run(Graph& g, int mode, int iters, bool want_gap, hipStream_t s) {
     a.head = p.head.p;
     a.chunk_words = p.chunk_words;
     a.B = B;
+    a.ncache = (int)std::min<int64_t>(n, kCacheQ);
+    if (!f.ev[0]) {
+        LDS_HIP(hipEventCreate(&f.ev[0]));
+        LDS_HIP(hipEventCreate(&f.ev[1]));
+    }
+    LDS_HIP(hipEventRecord(f.ev[0], s));
+    f.launches = 0;
     for (int i = 1; i <= iters && blocks > 0 && p.nrows > 0; ++i) {
         a.Kin = f.K[f.cur].p;
         a.Kout = f.K[f.cur ^ 1].p;
+        a.Qin = f.Q[f.cur].p;
+        a.Qout = f.Q[f.cur ^ 1].p;
         a.bits = f.bits.p + (size_t)(i - 1) * p.total_words;
         a.inc = denom(mode, i) - denom(mode, i - 1);
         a.partial = want_gap ? f.partial.p + (size_t)(i - 1) * blocks * 4 : nullptr;
@@ -354,7 +526,9 @@ void fw_run(Graph& g, int mode, int iters, bool want_gap, hipStream_t s) {
             launch_sweep<3, false>(a, blocks, want_gap, s);
         LDS_HIP(hipGetLastError());
         f.cur ^= 1;
+        ++f.launches;
     }
+    LDS_HIP(hipEventRecord(f.ev[1], s));
     f.iters = iters;
     f.gap.assign(want_gap ? iters : 0, 0.0);
     f.lb.assign(want_gap ? iters : 0, 0.0);

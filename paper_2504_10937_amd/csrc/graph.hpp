@@ -49,18 +49,20 @@ struct SweepPlan {
         return own_rid.bytes() + own_rp.bytes() + own_py.bytes() + hwo.bytes() + chunk_row.bytes() + cwo.bytes() +
                head.bytes() + bitbase.bytes();
     }
-    unsigned blocks() const { return (unsigned)(n_hub + (n_chunks + 3) / 4); }
 };
 
 struct FwState {
     int iters = 0;               // iterations run
     int cur = 0;                 // keys live in K[cur]
     DBuf<uint64_t> K[2];         // packed keys (A << B) | (idmask - orig_id), internal order
+    DBuf<uint16_t> Q[2];         // 16-bit monotone codes of A (gathered first)
     DBuf<uint64_t> bits;         // iters * total_words decision words
     DBuf<uint64_t> partial;      // iters * blocks * 4 gap partial sums
     std::vector<double> gap, lb; // per iteration, filled on request
+    hipEvent_t ev[2] = {nullptr, nullptr};  // around the sweep launches of the last run
+    int launches = 0;
     size_t device_bytes() const {
-        return K[0].bytes() + K[1].bytes() + bits.bytes() + partial.bytes();
+        return K[0].bytes() + K[1].bytes() + Q[0].bytes() + Q[1].bytes() + bits.bytes() + partial.bytes();
     }
 };
 
@@ -74,7 +76,8 @@ struct Graph {
     DBuf<int32_t> int_of;        // original -> internal id
     DBuf<int32_t> deg;           // internal order
     DBuf<int64_t> rowptr;        // symmetric CSR, internal ids, n + 1
-    DBuf<int32_t> col;           // 2m, ascending per row
+    DBuf<int32_t> col;           // 2m; ascending per row once col_sorted
+    bool col_sorted = false;
     SweepPlan edge_plan;         // slots = CSR (rowid identity over [0, n_nz))
     // triangles (built on first use)
     int64_t T = -1;
@@ -85,12 +88,14 @@ struct Graph {
     FwState fw[2];               // [0] edges, [1] triangles
     hipStream_t stream = nullptr;
     size_t device_bytes() const;
+    ~Graph();
 };
 
 // ingest.hip
 void build_graph(Graph& g, int64_t n, int64_t npairs, const int32_t* src, const int32_t* dst, bool on_device,
                  bool strict, hipStream_t s);
 void build_sweep_plan(SweepPlan& p, hipStream_t s);  // needs h, nrows, nslots, rowptr, pay, rowid
+void sort_rows(Graph& g, hipStream_t s);             // CSR rows ascending (triangle listing)
 
 // triangles.hip
 void list_triangles(Graph& g, hipStream_t s);

@@ -10,24 +10,25 @@ namespace {
 
 constexpr int kT = 256;
 
+// every pair becomes two keys (a,b) and (b,a): sorting them gives the
+// symmetric CSR in original ids, with duplicates adjacent
 __global__ void k_canon(const int32_t* src, const int32_t* dst, int64_t np, int64_t n, int vbits, int strict,
                         uint64_t* keys, unsigned* err) {
     const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
     if (i >= np) return;
-    int64_t a = src[i], b = dst[i];
+    const int64_t a = src[i], b = dst[i];
     const uint64_t sentinel = ((uint64_t)n << vbits) | (uint64_t)n;
+    uint64_t k0 = sentinel, k1 = sentinel;
     if (a < 0 || b < 0 || a >= n || b >= n) {
         atomicOr(err, 1u);
-        keys[i] = sentinel;
-        return;
-    }
-    if (a == b) {
+    } else if (a == b) {
         if (strict) atomicOr(err, 2u);
-        keys[i] = sentinel;
-        return;
+    } else {
+        k0 = ((uint64_t)a << vbits) | (uint64_t)b;
+        k1 = ((uint64_t)b << vbits) | (uint64_t)a;
     }
-    if (a > b) { int64_t t = a; a = b; b = t; }
-    keys[i] = ((uint64_t)a << vbits) | (uint64_t)b;
+    keys[2 * i] = k0;
+    keys[2 * i + 1] = k1;
 }
 
 __global__ void k_unique_flags(const uint64_t* keys, int64_t np, uint64_t sentinel, int strict, uint32_t* flag,
@@ -47,12 +48,20 @@ __global__ void k_compact(const uint64_t* keys, const uint32_t* flag, const uint
     out[pos[i]] = keys[i];
 }
 
-__global__ void k_degree(const uint64_t* ukeys, int64_t m, int vbits, int32_t* deg) {
-    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
-    if (i >= m) return;
-    const uint64_t k = ukeys[i], mask = (1ull << vbits) - 1;
-    atomicAdd(&deg[k >> vbits], 1);
-    atomicAdd(&deg[k & mask], 1);
+// run boundaries of the sorted symmetric keys: first slot and one-past-last
+// slot of every row that has slots
+__global__ void k_row_bounds(const uint64_t* sk, int64_t ns, int vbits, int64_t* rstart, int64_t* rend) {
+    const int64_t j = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (j >= ns) return;
+    const uint64_t row = sk[j] >> vbits;
+    if (j == 0 || (sk[j - 1] >> vbits) != row) rstart[row] = j;
+    if (j == ns - 1 || (sk[j + 1] >> vbits) != row) rend[row] = j + 1;
+}
+
+__global__ void k_row_deg(const int64_t* rstart, const int64_t* rend, int64_t n, int32_t* deg) {
+    const int64_t v = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (v >= n) return;
+    deg[v] = (int32_t)(rend[v] - rstart[v]);
 }
 
 __global__ void k_maxdeg(const int32_t* deg, int64_t n, int* out, unsigned long long* nz) {
@@ -84,19 +93,35 @@ __global__ void k_relabel_apply(const uint64_t* keys, int64_t n, int vbits, cons
     deg_int[i] = deg_orig[o];
 }
 
-__global__ void k_csr_keys(const uint64_t* ukeys, int64_t m, int vbits, const int32_t* int_of, uint64_t* out) {
-    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
-    if (i >= m) return;
-    const uint64_t k = ukeys[i], mask = (1ull << vbits) - 1;
-    const uint64_t a = (uint64_t)int_of[k >> vbits], b = (uint64_t)int_of[k & mask];
-    out[2 * i] = (a << vbits) | b;
-    out[2 * i + 1] = (b << vbits) | a;
+// slot j of original row o moves to internal row int_of[o], same offset
+// within the row; its column is renumbered
+__global__ void k_permute(const uint64_t* sk, int64_t ns, int vbits, const int64_t* rstart, const int32_t* int_of,
+                          const int64_t* rowptr, int32_t* col) {
+    const int64_t j = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (j >= ns) return;
+    const uint64_t k = sk[j], mask = (1ull << vbits) - 1;
+    const int64_t o = (int64_t)(k >> vbits);
+    const int32_t i = int_of[o];
+    col[rowptr[i] + (j - rstart[o])] = int_of[k & mask];
 }
 
-__global__ void k_csr_cols(const uint64_t* keys, int64_t ns, int vbits, int32_t* col) {
-    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
-    if (i >= ns) return;
-    col[i] = (int32_t)(keys[i] & ((1ull << vbits) - 1));
+// (row, col) keys of the internal CSR, for sorting every row ascending
+__global__ void k_row_col_keys(const int64_t* rowptr, const int32_t* col, int64_t n, int64_t ns, int vbits,
+                               uint64_t* keys) {
+    const int64_t s = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (s >= ns) return;
+    int64_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (rowptr[mid] <= s) lo = mid; else hi = mid - 1;
+    }
+    keys[s] = ((uint64_t)lo << vbits) | (uint64_t)col[s];
+}
+
+__global__ void k_key_cols(const uint64_t* keys, int64_t ns, int vbits, int32_t* col) {
+    const int64_t s = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (s >= ns) return;
+    col[s] = (int32_t)(keys[s] & ((1ull << vbits) - 1));
 }
 
 __global__ void k_set_last(int64_t* rowptr, int64_t idx, const uint64_t* total) { rowptr[idx] = (int64_t)*total; }
@@ -236,7 +261,8 @@ void build_graph(Graph& g, int64_t n, int64_t npairs, const int32_t* src, const 
     const int vb = g.vbits;
     const uint64_t sentinel = ((uint64_t)n << vb) | (uint64_t)n;
 
-    // 1. pairs -> canonical keys, sort, unique
+    // 1. both orientations of every pair -> sort -> drop duplicates and
+    //    self-loops: the symmetric CSR in original ids, rows ascending
     DBuf<int32_t> dsrc, ddst;
     const int32_t *ps = src, *pd = dst;
     if (!on_device && npairs > 0) {
@@ -250,43 +276,56 @@ void build_graph(Graph& g, int64_t n, int64_t npairs, const int32_t* src, const 
     DBuf<unsigned> err;
     err.alloc(1, s);
     LDS_HIP(hipMemsetAsync(err.p, 0, sizeof(unsigned), s));
-    DBuf<uint64_t> ukeys;
-    int64_t m = 0;
+    DBuf<uint64_t> skeys;
+    int64_t ns = 0;
     if (npairs > 0) {
+        const int64_t nk = 2 * npairs;
         DBuf<uint64_t> keys, tmp;
-        keys.alloc(npairs, s);
-        tmp.alloc(npairs, s);
+        keys.alloc(nk, s);
+        tmp.alloc(nk, s);
         k_canon<<<grid_for(npairs, kT), kT, 0, s>>>(ps, pd, npairs, n, vb, strict, keys.p, err.p);
         LDS_HIP(hipGetLastError());
         dsrc.release();
         ddst.release();
-        radix_sort_u64(keys.p, nullptr, npairs, 2 * vb, tmp.p, nullptr, s);
+        radix_sort_u64(keys.p, nullptr, nk, 2 * vb, tmp.p, nullptr, s);
         DBuf<uint32_t> flag;
-        flag.alloc(npairs, s);
-        k_unique_flags<<<grid_for(npairs, kT), kT, 0, s>>>(keys.p, npairs, sentinel, strict, flag.p, err.p);
+        flag.alloc(nk, s);
+        k_unique_flags<<<grid_for(nk, kT), kT, 0, s>>>(keys.p, nk, sentinel, strict, flag.p, err.p);
         LDS_HIP(hipGetLastError());
         DBuf<uint64_t> total;
         total.alloc(1, s);
-        exclusive_scan_u32_to_u64(flag.p, tmp.p, npairs, total.p, s);
-        m = (int64_t)d2h(total.p, s);
-        ukeys.alloc(m, s);
-        k_compact<<<grid_for(npairs, kT), kT, 0, s>>>(keys.p, flag.p, tmp.p, npairs, ukeys.p);
+        exclusive_scan_u32_to_u64(flag.p, tmp.p, nk, total.p, s);
+        ns = (int64_t)d2h(total.p, s);
+        skeys.alloc(ns, s);
+        k_compact<<<grid_for(nk, kT), kT, 0, s>>>(keys.p, flag.p, tmp.p, nk, skeys.p);
         LDS_HIP(hipGetLastError());
     }
     const unsigned e = d2h(err.p, s);
     LDS_CHECK(!(e & 1u), ST_INVALID, "vertex id out of range [0, n)");
     LDS_CHECK(!(e & 2u), ST_INVALID, "self-loop in strict mode");
     LDS_CHECK(!(e & 4u), ST_INVALID, "duplicate pair in strict mode");
-    g.m = m;
+    g.m = ns / 2;
 
-    // 2. degrees and renumbering (degree desc, original id asc)
+    // 2. degrees from the row runs (no atomics), renumbering by degree desc,
+    //    original id asc
     DBuf<int32_t> deg_orig;
+    DBuf<int64_t> rstart, rend;
     deg_orig.alloc(n, s);
-    if (n) LDS_HIP(hipMemsetAsync(deg_orig.p, 0, n * sizeof(int32_t), s));
-    if (m > 0) {
-        k_degree<<<grid_for(m, kT), kT, 0, s>>>(ukeys.p, m, vb, deg_orig.p);
+    rstart.alloc(n, s);
+    rend.alloc(n, s);
+    if (n) {
+        LDS_HIP(hipMemsetAsync(rstart.p, 0, n * sizeof(int64_t), s));
+        LDS_HIP(hipMemsetAsync(rend.p, 0, n * sizeof(int64_t), s));
+    }
+    if (ns > 0) {
+        k_row_bounds<<<grid_for(ns, kT), kT, 0, s>>>(skeys.p, ns, vb, rstart.p, rend.p);
         LDS_HIP(hipGetLastError());
     }
+    if (n > 0) {
+        k_row_deg<<<grid_for(n, kT), kT, 0, s>>>(rstart.p, rend.p, n, deg_orig.p);
+        LDS_HIP(hipGetLastError());
+    }
+    rend.release();
     DBuf<int> dmax;
     DBuf<unsigned long long> nz;
     dmax.alloc(1, s);
@@ -314,9 +353,11 @@ void build_graph(Graph& g, int64_t n, int64_t npairs, const int32_t* src, const 
         LDS_HIP(hipGetLastError());
     }
 
-    // 3. symmetric CSR in internal ids
+    // 3. symmetric CSR in internal ids (row order within a row is not sorted;
+    //    sort_rows() sorts when the triangle listing needs it)
     g.rowptr.alloc(n + 1, s);
-    g.col.alloc(2 * m, s);
+    g.col.alloc(ns, s);
+    g.col_sorted = false;
     {
         DBuf<uint64_t> total;
         total.alloc(1, s);
@@ -324,27 +365,43 @@ void build_graph(Graph& g, int64_t n, int64_t npairs, const int32_t* src, const 
         k_set_last<<<1, 1, 0, s>>>(g.rowptr.p, n, total.p);
         LDS_HIP(hipGetLastError());
     }
-    if (m > 0) {
-        DBuf<uint64_t> ck, ct;
-        ck.alloc(2 * m, s);
-        ct.alloc(2 * m, s);
-        k_csr_keys<<<grid_for(m, kT), kT, 0, s>>>(ukeys.p, m, vb, g.int_of.p, ck.p);
-        LDS_HIP(hipGetLastError());
-        ukeys.release();
-        radix_sort_u64(ck.p, nullptr, 2 * m, 2 * vb, ct.p, nullptr, s);
-        k_csr_cols<<<grid_for(2 * m, kT), kT, 0, s>>>(ck.p, 2 * m, vb, g.col.p);
+    if (ns > 0) {
+        k_permute<<<grid_for(ns, kT), kT, 0, s>>>(skeys.p, ns, vb, rstart.p, g.int_of.p, g.rowptr.p, g.col.p);
         LDS_HIP(hipGetLastError());
     }
+    skeys.release();
 
     // 4. edge sweep plan: rows are internal vertices [0, n_nz), degree-sorted
     SweepPlan& p = g.edge_plan;
     p.h = 2;
     p.nrows = g.n_nz;
-    p.nslots = 2 * m;
+    p.nslots = ns;
     p.rid = nullptr;
     p.rp = g.rowptr.p;
     p.py = g.col.p;
     build_sweep_plan(p, s);
+}
+
+void sort_rows(Graph& g, hipStream_t s) {
+    if (g.col_sorted) return;
+    const int64_t ns = 2 * g.m;
+    if (ns > 0) {
+        DBuf<uint64_t> k, t;
+        k.alloc(ns, s);
+        t.alloc(ns, s);
+        k_row_col_keys<<<grid_for(ns, kT), kT, 0, s>>>(g.rowptr.p, g.col.p, g.n, ns, g.vbits, k.p);
+        LDS_HIP(hipGetLastError());
+        radix_sort_u64(k.p, nullptr, ns, 2 * g.vbits, t.p, nullptr, s);
+        k_key_cols<<<grid_for(ns, kT), kT, 0, s>>>(k.p, ns, g.vbits, g.col.p);
+        LDS_HIP(hipGetLastError());
+    }
+    g.col_sorted = true;
+}
+
+Graph::~Graph() {
+    for (auto& f : fw)
+        for (auto& e : f.ev)
+            if (e) (void)hipEventDestroy(e);
 }
 
 size_t Graph::device_bytes() const {

@@ -152,6 +152,7 @@ T d2h(const T* p, hipStream_t s) {
 
 void list_triangles(Graph& g, hipStream_t s) {
     const int64_t n = g.n, ns = 2 * g.m;
+    sort_rows(g, s);
     g.tcount.alloc(n, s);
     if (n) LDS_HIP(hipMemsetAsync(g.tcount.p, 0, n * sizeof(int32_t), s));
     int64_t T = 0;
