@@ -114,6 +114,32 @@ lds_status lds_frank_wolfe(lds_graph g, lds_mode mode, int32_t iters, float* r_o
 lds_status lds_splits(lds_graph g, lds_mode mode, int32_t* verts_out, uint64_t* num_out, int64_t cap,
                       int64_t* count_out, void* hip_stream);
 
+/* Alg. 2, lines 2-4, on the state of the last lds_frank_wolfe run of this
+ * mode: sort of the vertices by r descending (ties: caller id ascending),
+ * prefix pattern counts and the candidate set I.  Host outputs, each
+ * optional: order_out[j] = caller id at 0-based position j (n entries);
+ * E_out[j] = number of edges (triangles) induced by the first j+1 vertices;
+ * inI_out[j] = 1 iff j+1 = argmax_{k >= j+1} E_{k-1}/k with ties to the larger
+ * index, i.e. E_j/(j+1) exceeds every later E_k/(k+1). */
+lds_status lds_sort_prefix(lds_graph g, lds_mode mode, int32_t* order_out, int64_t* E_out, uint8_t* inI_out,
+                           void* hip_stream);
+
+/* Alg. 2, lines 5-14: stable groups (Def. 5 for edges, Def. trsg for
+ * triangles) from the candidates of lds_sort_prefix.  A candidate run is
+ * merged with the next one until it is a stable group of the restricted
+ * solution: every edge (triangle) touching the tested group gives its weight
+ * only to its vertices in the lowest group it touches (accepted groups above,
+ * the tested group, all vertices below), shares freed from higher vertices go
+ * to the lowest-r vertex of that group; a group is accepted iff its
+ * restricted loads are strictly below every accepted vertex and strictly
+ * above every vertex below.  Outputs (host): *ngroups; gstart/gend (cap
+ * entries): 0-based position range [start, end) of each group, top first;
+ * lo_out/hi_out (n entries, by caller id): restricted min / max numerator of
+ * the vertex's group (bounds of Lemma phi-bounds, over D_iters), -1 for
+ * vertices of the unaccepted tail.  Any output may be NULL. */
+lds_status lds_stable_groups(lds_graph g, lds_mode mode, int64_t* ngroups, int64_t* gstart, int64_t* gend, int64_t cap,
+                             int64_t* lo_out, int64_t* hi_out, void* hip_stream);
+
 /* GPU time of the sweep launches of the last lds_frank_wolfe call for this
  * graph and mode, from HIP events recorded on that call's stream right before
  * the first and after the last sweep launch (waits for the end event).

@@ -53,6 +53,8 @@ def load():
         "lds_splits": (st, [vp, st, vp, vp, i64, vp, vp]),
         "lds_denominator": (u64, [st, i32]),
         "lds_fw_elapsed": (st, [vp, st, vp, vp]),
+        "lds_sort_prefix": (st, [vp, st, vp, vp, vp, vp]),
+        "lds_stable_groups": (st, [vp, st, vp, vp, vp, i64, vp, vp, vp]),
         "lds_sweep_info": (st, [vp, st, vp, vp, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
@@ -190,6 +192,30 @@ def lds_splits(g, mode, stream=None):
 
 def lds_denominator(mode, iters):
     return int(load().lds_denominator(mode, int(iters)))
+
+
+def lds_sort_prefix(g, mode, stream=None):
+    """Alg. 2 lines 2-4 on the last FW state -> (order (caller ids by position), E, inI)."""
+    n = lds_graph_info(g)["n"]
+    order = np.empty(n, np.int32)
+    E = np.empty(n, np.int64)
+    inI = np.empty(n, np.uint8)
+    _check(load().lds_sort_prefix(g.handle, mode, _ptr(order), _ptr(E), _ptr(inI), _stream(stream)))
+    return order, E, inI.astype(bool)
+
+
+def lds_stable_groups(g, mode, stream=None):
+    """Alg. 2 stable groups -> (groups [(start, end)], lo (n,), hi (n,)) with
+    lo/hi numerators over D (-1: no bounds), indexed by caller id."""
+    n = lds_graph_info(g)["n"]
+    ng = ctypes.c_int64()
+    gs = np.empty(max(n, 1), np.int64)
+    ge = np.empty(max(n, 1), np.int64)
+    lo = np.empty(n, np.int64)
+    hi = np.empty(n, np.int64)
+    _check(load().lds_stable_groups(g.handle, mode, ctypes.byref(ng), _ptr(gs), _ptr(ge), len(gs), _ptr(lo), _ptr(hi),
+                                    _stream(stream)))
+    return [(int(gs[i]), int(ge[i])) for i in range(ng.value)], lo, hi
 
 
 def lds_fw_elapsed(g, mode):

@@ -197,6 +197,64 @@ lds_status lds_splits(lds_graph g, lds_mode mode, int32_t* verts_out, uint64_t* 
     API_CATCH
 }
 
+lds_status lds_sort_prefix(lds_graph g, lds_mode mode, int32_t* order_out, int64_t* E_out, uint8_t* inI_out,
+                           void* hip_stream) {
+    API_TRY
+    LDS_CHECK(g != nullptr, lds::ST_INVALID, "graph is NULL");
+    LDS_CHECK(mode == LDS_EDGE || mode == LDS_TRIANGLE, lds::ST_INVALID, "mode must be LDS_EDGE or LDS_TRIANGLE");
+    std::lock_guard<std::mutex> lk(g->mu);
+    hipStream_t s = (hipStream_t)hip_stream;
+    lds::Graph& G = g->g;
+    lds::sg_sort_prefix(G, (int)mode, s);
+    const lds::SgState& q = G.sg[mode == LDS_EDGE ? 0 : 1];
+    const int64_t n = G.n;
+    if (n > 0 && order_out) {
+        std::vector<int32_t> ord(n), orig(n);
+        LDS_HIP(hipMemcpyAsync(ord.data(), q.order.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        LDS_HIP(hipMemcpyAsync(orig.data(), G.orig_of.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        LDS_HIP(hipStreamSynchronize(s));
+        for (int64_t j = 0; j < n; ++j) order_out[j] = orig[ord[j]];
+    }
+    if (n > 0 && E_out) LDS_HIP(hipMemcpyAsync(E_out, q.E.p, n * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    if (n > 0 && inI_out) LDS_HIP(hipMemcpyAsync(inI_out, q.inI.p, n, hipMemcpyDeviceToHost, s));
+    LDS_HIP(hipStreamSynchronize(s));
+    API_CATCH
+}
+
+lds_status lds_stable_groups(lds_graph g, lds_mode mode, int64_t* ngroups, int64_t* gstart, int64_t* gend, int64_t cap,
+                             int64_t* lo_out, int64_t* hi_out, void* hip_stream) {
+    API_TRY
+    LDS_CHECK(g != nullptr, lds::ST_INVALID, "graph is NULL");
+    LDS_CHECK(mode == LDS_EDGE || mode == LDS_TRIANGLE, lds::ST_INVALID, "mode must be LDS_EDGE or LDS_TRIANGLE");
+    std::lock_guard<std::mutex> lk(g->mu);
+    hipStream_t s = (hipStream_t)hip_stream;
+    lds::Graph& G = g->g;
+    lds::sg_stable_groups(G, (int)mode, s);
+    const lds::SgState& q = G.sg[mode == LDS_EDGE ? 0 : 1];
+    const int64_t ng = (int64_t)q.gstart.size(), n = G.n;
+    if (ngroups) *ngroups = ng;
+    if (gstart || gend) {
+        LDS_CHECK(cap >= ng, lds::ST_INVALID, "group capacity too small");
+        for (int64_t i = 0; i < ng; ++i) {
+            if (gstart) gstart[i] = q.gstart[i];
+            if (gend) gend[i] = q.gend[i];
+        }
+    }
+    if (n > 0 && (lo_out || hi_out)) {
+        std::vector<int64_t> lo(n), hi(n);
+        std::vector<int32_t> orig(n);
+        LDS_HIP(hipMemcpyAsync(lo.data(), q.lo.p, n * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        LDS_HIP(hipMemcpyAsync(hi.data(), q.hi.p, n * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        LDS_HIP(hipMemcpyAsync(orig.data(), G.orig_of.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        LDS_HIP(hipStreamSynchronize(s));
+        for (int64_t i = 0; i < n; ++i) {
+            if (lo_out) lo_out[orig[i]] = lo[i];
+            if (hi_out) hi_out[orig[i]] = hi[i];
+        }
+    }
+    API_CATCH
+}
+
 lds_status lds_fw_elapsed(lds_graph g, lds_mode mode, float* ms, int32_t* launches) {
     API_TRY
     LDS_CHECK(g != nullptr, lds::ST_INVALID, "graph is NULL");

@@ -418,7 +418,7 @@ __global__ void k_splits(const int64_t* rp, const int32_t* rid, const int32_t* p
     num[s] = a;
 }
 
-uint64_t denom(int mode, int64_t i) { return (uint64_t)(mode == 3 ? 3 : 1) * (uint64_t)(i + 1) * (uint64_t)(i + 2); }
+uint64_t denom(int mode, int64_t i) { return fw_denom(mode, i); }
 
 template <int H, bool IDENT>
 void launch_sweep(const SweepArgs& a, unsigned blocks, bool gap, hipStream_t s) {
@@ -488,6 +488,7 @@ void fw_run(Graph& g, int mode, int iters, bool want_gap, hipStream_t s) {
         LDS_HIP(hipGetLastError());
     }
     f.cur = 0;
+    g.sg[mode == 2 ? 0 : 1].valid = false;
     const size_t nbits = (size_t)iters * (size_t)p.total_words;
     if (f.bits.n < nbits) f.bits.alloc(nbits, s);
     const unsigned blocks = sweep_grid();

@@ -27,6 +27,12 @@ namespace lds {
 
 constexpr int kChunk = 1024;  // target slots per wave; spans < 2*kChunk = 32 words
 
+// denominator of the loads after i iterations with gamma_i = 2/(i+2):
+// (i+1)(i+2) for edges (mode 2), 3(i+1)(i+2) for triangles (mode 3)
+inline uint64_t fw_denom(int mode, int64_t i) {
+    return (uint64_t)(mode == 3 ? 3 : 1) * (uint64_t)(i + 1) * (uint64_t)(i + 2);
+}
+
 struct SweepPlan {
     int h = 2;                  // pattern arity: 2 edges, 3 triangles
     int64_t nrows = 0;          // compact rows
@@ -37,6 +43,8 @@ struct SweepPlan {
     DBuf<int32_t> own_rid;         // storage when the plan owns rid / rp / py
     DBuf<int64_t> own_rp;
     DBuf<int32_t> own_py;
+    DBuf<int32_t> own_tos;         // triangles: slot -> triangle index
+    int64_t n_big = 0;             // rows [0, n_big) have >= 64 slots (rows are ordered by slot count)
     int64_t n_hub = 0;          // rows [0, n_hub) are hubs
     DBuf<int64_t> hwo;          // n_hub + 1 word offsets (relative to hub region)
     int64_t n_chunks = 0;
@@ -46,7 +54,7 @@ struct SweepPlan {
     int64_t chunk_words = 0, hub_words = 0, total_words = 0;
     DBuf<int64_t> bitbase;      // per compact row: bit index of its first slot
     size_t device_bytes() const {
-        return own_rid.bytes() + own_rp.bytes() + own_py.bytes() + hwo.bytes() + chunk_row.bytes() + cwo.bytes() +
+        return own_rid.bytes() + own_rp.bytes() + own_py.bytes() + own_tos.bytes() + hwo.bytes() + chunk_row.bytes() + cwo.bytes() +
                head.bytes() + bitbase.bytes();
     }
 };
@@ -63,6 +71,25 @@ struct FwState {
     int launches = 0;
     size_t device_bytes() const {
         return K[0].bytes() + K[1].bytes() + Q[0].bytes() + Q[1].bytes() + bits.bytes() + partial.bytes();
+    }
+};
+
+// Sort, prefix counts and stable groups (Alg. 2) of the last FW run of a mode
+struct SgState {
+    bool valid = false;
+    int iters = -1;
+    DBuf<int32_t> order;         // position -> internal vertex (r descending, caller id ascending)
+    DBuf<int64_t> pos;           // internal vertex -> position
+    DBuf<int64_t> E;             // patterns inside the first j+1 positions
+    DBuf<uint8_t> inI;           // position j+1 (1-based) is a strict suffix maximum of E/j
+    DBuf<uint32_t> a_slot;       // split numerator of every incidence slot
+    DBuf<uint32_t> a_tri;        // triangles: the three split numerators per triangle
+    std::vector<int64_t> gstart, gend;  // accepted groups (position ranges)
+    DBuf<int64_t> lo, hi;        // per internal vertex: restricted min / max of its group, -1 if none
+    int64_t rounds = 0, verifications = 0;
+    size_t device_bytes() const {
+        return order.bytes() + pos.bytes() + E.bytes() + inI.bytes() + a_slot.bytes() + a_tri.bytes() + lo.bytes() +
+               hi.bytes();
     }
 };
 
@@ -86,6 +113,7 @@ struct Graph {
     int64_t t_max = 0;
     SweepPlan tri_plan;
     FwState fw[2];               // [0] edges, [1] triangles
+    SgState sg[2];               // sort / prefix / stable groups of the last run per mode
     hipStream_t stream = nullptr;
     size_t device_bytes() const;
     ~Graph();
@@ -99,6 +127,10 @@ void sort_rows(Graph& g, hipStream_t s);             // CSR rows ascending (tria
 
 // triangles.hip
 void list_triangles(Graph& g, hipStream_t s);
+
+// sg.hip
+void sg_sort_prefix(Graph& g, int mode, hipStream_t s);
+void sg_stable_groups(Graph& g, int mode, hipStream_t s);
 
 // fw.hip
 unsigned __int128 fw_max_numerator(const Graph& g, int mode, int iters);

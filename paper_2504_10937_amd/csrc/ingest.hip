@@ -134,6 +134,13 @@ __global__ void k_count_hubs(const int64_t* rp, int64_t nrows, unsigned long lon
     if ((threadIdx.x & 63) == 0 && c) atomicAdd(cnt, c);
 }
 
+__global__ void k_count_big(const int64_t* rp, int64_t nrows, unsigned long long* cnt) {
+    const int64_t r = (int64_t)blockIdx.x * kT + threadIdx.x;
+    const bool big = r < nrows && (rp[r + 1] - rp[r]) >= 64;
+    unsigned long long c = __popcll(__ballot(big));
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(cnt, c);
+}
+
 __global__ void k_hub_words(const int64_t* rp, int64_t n_hub, uint64_t* words) {
     const int64_t r = (int64_t)blockIdx.x * kT + threadIdx.x;
     if (r >= n_hub) return;
@@ -196,6 +203,10 @@ void build_sweep_plan(SweepPlan& p, hipStream_t s) {
     if (nrows > 0) k_count_hubs<<<grid_for(nrows, kT), kT, 0, s>>>(p.rp, nrows, cnt.p);
     LDS_HIP(hipGetLastError());
     p.n_hub = (int64_t)d2h(cnt.p, s);
+    LDS_HIP(hipMemsetAsync(cnt.p, 0, sizeof(unsigned long long), s));
+    if (nrows > 0) k_count_big<<<grid_for(nrows, kT), kT, 0, s>>>(p.rp, nrows, cnt.p);
+    LDS_HIP(hipGetLastError());
+    p.n_big = (int64_t)d2h(cnt.p, s);
     // hub word offsets
     p.hwo.alloc(p.n_hub + 1, s);
     if (p.n_hub > 0) {
@@ -408,6 +419,7 @@ size_t Graph::device_bytes() const {
     size_t b = orig_of.bytes() + int_of.bytes() + deg.bytes() + rowptr.bytes() + col.bytes() +
                edge_plan.device_bytes() + tri.bytes() + tcount.bytes() + tri_plan.device_bytes();
     for (const auto& f : fw) b += f.device_bytes();
+    for (const auto& x : sg) b += x.device_bytes();
     return b;
 }
 

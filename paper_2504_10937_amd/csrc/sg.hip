@@ -1,0 +1,572 @@
+// Alg. 2 (ExtractSG) on the device: sort of the converged loads, prefix
+// pattern counts, the candidate index set I, and the stable-group scan with
+// Def. 5 (edges) / Def. trsg (triangles).
+//
+// a7  Sort: vertices by r descending, ties by caller id ascending.  The
+//     packed keys K = (A << B) | (2^B - 1 - id) are distinct and ordered like
+//     (r asc, id desc), so one ascending radix sort of K read backwards gives
+//     the order.
+// a8  Prefix: c_j = patterns whose latest vertex (largest position) is at
+//     position j, a per-row count on the incidence CSR; E = inclusive scan;
+//     j+1 (1-based) is in I iff E_j/(j+1) is strictly above every later
+//     E_k/(k+1) (argmax with ties to the larger index).
+// a9  Stable groups.  Candidates are the runs ending at I.  A pending group
+//     S = [S0, b) is tested with the restriction: every pattern touching S or
+//     the vertices below gives weight only to its vertices in the lowest group
+//     it touches (accepted groups above < S < everything below), and the
+//     shares freed from higher vertices go to the lowest-r vertex of that
+//     group.  S is accepted iff max_S r' < min r' of the last accepted group
+//     and max_{below} r' < min_S r'.  Restricted loads below S depend only on
+//     b, and for a fixed S0 the tests at different b are independent, so the
+//     scan runs in rounds (one per accepted group): find, in order, the
+//     boundaries b that pass two necessary conditions
+//        (1) T_x < minH for every x in [S0, b), where T_x is x's restricted
+//            load when S ends right after x (max_S r' >= max T_x, and the
+//            restricted loads of S only grow with b, so the first violation
+//            ends the whole scan);
+//        (2) R of the first vertex below < T of the last vertex of S, where R_w
+//            is w's restricted load when everything before w is above it
+//            (max_below >= R_first, min_S <= T_last);
+//     and verify each exactly with one pass over all patterns, accepting the
+//     first that passes.  All quantities are integer numerators over D_N.
+#include <algorithm>
+#include <climits>
+
+#include "graph.hpp"
+
+namespace lds {
+
+namespace {
+
+constexpr int kT = 256;
+
+template <class T>
+T d2h(const T* p, hipStream_t s) {
+    T v;
+    LDS_HIP(hipMemcpyAsync(&v, p, sizeof(T), hipMemcpyDeviceToHost, s));
+    LDS_HIP(hipStreamSynchronize(s));
+    return v;
+}
+
+__device__ inline int64_t shfl_xor_i64(int64_t v, int m) {
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)(uint64_t)v, m, 64);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)((uint64_t)v >> 32), m, 64);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// ---------------------------------------------------------------- a7 sort
+__global__ void k_sort_init(const uint64_t* K, int64_t n, uint64_t* keys, uint32_t* vals) {
+    const int64_t u = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (u >= n) return;
+    keys[u] = K[u];
+    vals[u] = (uint32_t)u;
+}
+
+__global__ void k_order(const uint32_t* vals, int64_t n, int32_t* order, int64_t* pos) {
+    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (i >= n) return;
+    const int64_t j = n - 1 - i;  // ascending keys read backwards: r descending
+    order[j] = (int32_t)vals[i];
+    pos[vals[i]] = j;
+}
+
+// --------------------------------------------------- split numerators per slot
+// a = a0 + sum_i inc_i [slot won in iteration i], walking the sweep plan so
+// that the bit position of a slot is known without a row search
+__global__ void k_slot_splits(const int64_t* rp, int64_t n_hub, const int64_t* hwo, int64_t n_chunks,
+                              const int64_t* chunk_row, const int64_t* cwo, int64_t chunk_words, const uint64_t* bits,
+                              int64_t total_words, int iters, int tri, uint32_t* a_slot) {
+    const int64_t b = blockIdx.x;
+    int64_t s0, s1, bit0;
+    if (b < n_hub) {
+        s0 = rp[b];
+        s1 = rp[b + 1];
+        bit0 = (chunk_words + hwo[b]) * 64;
+    } else {
+        const int64_t c = b - n_hub;
+        if (c >= n_chunks) return;
+        s0 = rp[chunk_row[c]];
+        s1 = rp[chunk_row[c + 1]];
+        bit0 = cwo[c] * 64;
+    }
+    for (int64_t s = s0 + threadIdx.x; s < s1; s += kT) {
+        const int64_t p = bit0 + (s - s0);
+        uint64_t a = tri ? 2 : 1;
+        for (int i = 1; i <= iters; ++i) {
+            const uint64_t wd = bits[(int64_t)(i - 1) * total_words + p / 64];
+            if ((wd >> (p % 64)) & 1ull) a += (uint64_t)(tri ? 6 : 2) * (uint64_t)(i + 1);
+        }
+        a_slot[s] = (uint32_t)a;
+    }
+}
+
+// triangles: index of the slot's row vertex within tri[t] (the slot holds the
+// other two in triangle order)
+__device__ inline int tri_index(const int32_t* tri, int64_t t, int32_t v, int32_t w) {
+    return (tri[3 * t] != v) ? 0 : ((tri[3 * t + 1] != w) ? 1 : 2);
+}
+
+__global__ void k_tri_splits(const int32_t* py, const int32_t* tos, const int32_t* tri, const uint32_t* a_slot,
+                             int64_t ns, uint32_t* a_tri) {
+    const int64_t s = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (s >= ns) return;
+    const int64_t t = tos[s];
+    a_tri[3 * t + tri_index(tri, t, py[2 * s], py[2 * s + 1])] = a_slot[s];
+}
+
+// ----------------------------------------------------- row passes (a8, a9)
+enum PassKind { PASS_COUNT = 0, PASS_R = 1, PASS_T = 2, PASS_V = 3 };
+
+struct PassArgs {
+    int kind;
+    const int32_t* rid;
+    const int64_t* rp;
+    const int32_t* py;
+    const int32_t* tos;
+    const int32_t* tri;
+    const uint32_t* a_slot;
+    const uint32_t* a_tri;
+    const int64_t* pos;
+    int64_t nrows, n_big;
+    uint64_t D;
+    int64_t S0, b;   // PASS_T: S0; PASS_V: S0 and b
+    int64_t* out;    // by position
+};
+
+__device__ inline int grp(int64_t p, int64_t t1, int64_t t2) { return p < t1 ? 0 : (p < t2 ? 1 : 2); }
+
+// contribution of slot s to its row vertex x (position px)
+template <int H>
+__device__ inline int64_t slot_value(const PassArgs& a, int64_t s, int64_t px);
+
+template <>
+__device__ inline int64_t slot_value<2>(const PassArgs& a, int64_t s, int64_t px) {
+    const int64_t py = a.pos[a.py[s]];
+    if (a.kind == PASS_COUNT) return py < px ? 1 : 0;
+    int64_t t1, t2;
+    if (a.kind == PASS_R) { t1 = px; t2 = px; }
+    else if (a.kind == PASS_T) { t1 = a.S0; t2 = px + 1; }
+    else { t1 = a.S0; t2 = a.b; }
+    const int gx = grp(px, t1, t2), gy = grp(py, t1, t2);
+    if (gx < gy) return 0;                    // the other end is lower: it takes the unit
+    if (gy < gx) return (int64_t)a.D;         // x alone in the lowest group: the whole unit
+    return (int64_t)a.a_slot[s];
+}
+
+template <>
+__device__ inline int64_t slot_value<3>(const PassArgs& a, int64_t s, int64_t px) {
+    const int32_t v = a.py[2 * s], w = a.py[2 * s + 1];
+    const int64_t pv = a.pos[v], pw = a.pos[w];
+    if (a.kind == PASS_COUNT) return (pv < px && pw < px) ? 1 : 0;
+    int64_t t1, t2;
+    if (a.kind == PASS_R) { t1 = px; t2 = px; }
+    else if (a.kind == PASS_T) { t1 = a.S0; t2 = px + 1; }
+    else { t1 = a.S0; t2 = a.b; }
+    const int gx = grp(px, t1, t2), gv = grp(pv, t1, t2), gw = grp(pw, t1, t2);
+    const int gl = max(gx, max(gv, gw));
+    if (gx < gl) return 0;
+    const int64_t t = a.tos[s];
+    const int jx = tri_index(a.tri, t, v, w);
+    const int jv = (jx == 0) ? 1 : 0, jw = (jx == 2) ? 1 : 2;
+    const int64_t ax = a.a_tri[3 * t + jx], av = a.a_tri[3 * t + jv], aw = a.a_tri[3 * t + jw];
+    const int64_t freed = (gv < gl ? av : 0) + (gw < gl ? aw : 0);
+    // receiver of the freed shares: the latest vertex of the lowest group
+    bool recv = true;
+    if (gv == gl && pv > px) recv = false;
+    if (gw == gl && pw > px) recv = false;
+    return ax + (recv ? freed : 0);
+}
+
+// rows [0, n_big): one wave per row; the rest: one thread per row
+template <int H>
+__global__ __launch_bounds__(kT) void k_rowpass(PassArgs a) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t nbb = (a.n_big + 3) / 4;
+    const int64_t minpos = (a.kind == PASS_T || a.kind == PASS_V) ? a.S0 : 0;
+    if ((int64_t)blockIdx.x < nbb) {
+        const int64_t r = (int64_t)blockIdx.x * 4 + w;
+        if (r >= a.n_big) return;
+        const int32_t x = a.rid ? a.rid[r] : (int32_t)r;
+        const int64_t px = a.pos[x];
+        if (px < minpos) return;
+        int64_t acc = 0;
+        for (int64_t s = a.rp[r] + lane; s < a.rp[r + 1]; s += 64) acc += slot_value<H>(a, s, px);
+        for (int m = 32; m > 0; m >>= 1) acc += shfl_xor_i64(acc, m);
+        if (lane == 0) a.out[px] = acc;
+    } else {
+        const int64_t r = a.n_big + ((int64_t)blockIdx.x - nbb) * kT + threadIdx.x;
+        if (r >= a.nrows) return;
+        const int32_t x = a.rid ? a.rid[r] : (int32_t)r;
+        const int64_t px = a.pos[x];
+        if (px < minpos) return;
+        int64_t acc = 0;
+        for (int64_t s = a.rp[r]; s < a.rp[r + 1]; ++s) acc += slot_value<H>(a, s, px);
+        a.out[px] = acc;
+    }
+}
+
+__global__ void k_inclusive(const uint64_t* excl, const int64_t* c, int64_t n, int64_t* E) {
+    const int64_t j = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (j < n) E[j] = (int64_t)excl[j] + c[j];
+}
+
+// ---------------------------------------------- strict suffix maxima of E/j
+// fraction (num, den), den = 0 means "minus infinity"
+__device__ inline bool frac_gt(int64_t an, int64_t ad, int64_t bn, int64_t bd) {
+    if (bd == 0) return ad != 0;
+    if (ad == 0) return false;
+    return (__int128)an * bd > (__int128)bn * ad;
+}
+
+constexpr int kTile = 4096;
+
+__global__ __launch_bounds__(kT) void k_tile_fmax(const int64_t* E, int64_t n, int64_t* tn, int64_t* td) {
+    __shared__ int64_t sn[kT], sd[kT];
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    int64_t bn = 0, bd = 0;
+    for (int k = 0; k < kTile / kT; ++k) {
+        const int64_t j = base + (int64_t)k * kT + threadIdx.x;
+        if (j < n && frac_gt(E[j], j + 1, bn, bd)) { bn = E[j]; bd = j + 1; }
+    }
+    sn[threadIdx.x] = bn;
+    sd[threadIdx.x] = bd;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < kT; ++i)
+            if (frac_gt(sn[i], sd[i], bn, bd)) { bn = sn[i]; bd = sd[i]; }
+        tn[blockIdx.x] = bn;
+        td[blockIdx.x] = bd;
+    }
+}
+
+// carry (cn, cd) = max over all later tiles; each thread owns 16 consecutive
+// positions, walked backwards after a block-level suffix max of thread maxima
+__global__ __launch_bounds__(kT) void k_tile_inI(const int64_t* E, int64_t n, const int64_t* cn_, const int64_t* cd_,
+                                               uint8_t* inI) {
+    __shared__ int64_t sn[kT], sd[kT];
+    const int per = kTile / kT;
+    const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * per;
+    int64_t bn = 0, bd = 0;
+    for (int k = 0; k < per; ++k) {
+        const int64_t j = base + k;
+        if (j < n && frac_gt(E[j], j + 1, bn, bd)) { bn = E[j]; bd = j + 1; }
+    }
+    sn[threadIdx.x] = bn;
+    sd[threadIdx.x] = bd;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // exclusive suffix max over threads, seeded with the later tiles' max
+        int64_t rn = cn_[blockIdx.x], rd = cd_[blockIdx.x];
+        for (int i = kT - 1; i >= 0; --i) {
+            const int64_t xn = sn[i], xd = sd[i];
+            sn[i] = rn;
+            sd[i] = rd;
+            if (frac_gt(xn, xd, rn, rd)) { rn = xn; rd = xd; }
+        }
+    }
+    __syncthreads();
+    int64_t rn = sn[threadIdx.x], rd = sd[threadIdx.x];
+    for (int k = per - 1; k >= 0; --k) {
+        const int64_t j = base + k;
+        if (j >= n) continue;
+        const bool in = frac_gt(E[j], j + 1, rn, rd);
+        inI[j] = in ? 1 : 0;
+        if (in) { rn = E[j]; rd = j + 1; }
+    }
+}
+
+// ------------------------------------------------------ a9 round helpers
+// first position j in [lo, hi) with v[j] >= thr (result: atomic min into *out)
+__global__ void k_first_ge(const int64_t* v, int64_t lo, int64_t hi, int64_t thr, unsigned long long* out) {
+    const int64_t j = lo + (int64_t)blockIdx.x * kT + threadIdx.x;
+    const bool hit = j < hi && v[j] >= thr;
+    const uint64_t m = __ballot(hit);
+    if (m && (threadIdx.x & 63) == (int)__ffsll((unsigned long long)m) - 1) atomicMin(out, (unsigned long long)j);
+}
+
+// candidate boundaries b = j + 1 for j in [lo, hi): j + 1 in I and (b == n or
+// R[b] < T[j]); flags are compacted in order by a scan
+__global__ void k_cand_flags(const uint8_t* inI, const int64_t* R, const int64_t* T, int64_t lo, int64_t hi, int64_t n,
+                             uint32_t* flag) {
+    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+    const int64_t j = lo + i;
+    if (j >= hi) return;
+    bool c = inI[j] != 0;
+    if (c && j + 1 < n) c = R[j + 1] < T[j];
+    flag[i] = c ? 1u : 0u;
+}
+
+__global__ void k_cand_compact(const uint32_t* flag, const uint64_t* off, int64_t lo, int64_t cnt, int64_t* list,
+                               int64_t cap) {
+    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (i >= cnt || !flag[i]) return;
+    const uint64_t o = off[i];
+    if ((int64_t)o < cap) list[o] = lo + i + 1;
+}
+
+// min and max of v over [lo, hi) (out[0] min, out[1] max, pre-set by host)
+__global__ __launch_bounds__(kT) void k_minmax(const int64_t* v, int64_t lo, int64_t hi, long long* out) {
+    const int64_t j = lo + (int64_t)blockIdx.x * kT + threadIdx.x;
+    long long mn = LLONG_MAX, mx = LLONG_MIN;
+    if (j < hi) mn = mx = v[j];
+    for (int m = 32; m > 0; m >>= 1) {
+        mn = min(mn, (long long)shfl_xor_i64(mn, m));
+        mx = max(mx, (long long)shfl_xor_i64(mx, m));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (mn != LLONG_MAX) atomicMin(out, mn);
+        if (mx != LLONG_MIN) atomicMax(out + 1, mx);
+    }
+}
+
+__global__ void k_set_bounds(const int32_t* order, int64_t lo, int64_t hi, int64_t mn, int64_t mx, int64_t* blo,
+                             int64_t* bhi) {
+    const int64_t j = lo + (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (j >= hi) return;
+    blo[order[j]] = mn;
+    bhi[order[j]] = mx;
+}
+
+__global__ void k_fill_i64(int64_t* p, int64_t n, int64_t v) {
+    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+template <int H>
+void row_pass(const SweepPlan& p, const PassArgs& a, hipStream_t s) {
+    const int64_t nbb = (p.n_big + 3) / 4;
+    const int64_t nsm = (p.nrows - p.n_big + kT - 1) / kT;
+    const int64_t blocks = nbb + nsm;
+    if (blocks <= 0) return;
+    k_rowpass<H><<<grid_for(blocks, 1), kT, 0, s>>>(a);
+    LDS_HIP(hipGetLastError());
+}
+
+void run_pass(const Graph& g, int mode, PassArgs a, hipStream_t s) {
+    const SweepPlan& p = (mode == 2) ? g.edge_plan : g.tri_plan;
+    a.rid = p.rid;
+    a.rp = p.rp;
+    a.py = p.py;
+    a.tos = p.own_tos.p;
+    a.tri = g.tri.p;
+    a.nrows = p.nrows;
+    a.n_big = p.n_big;
+    if (mode == 2)
+        row_pass<2>(p, a, s);
+    else
+        row_pass<3>(p, a, s);
+}
+
+}  // namespace
+
+void sg_sort_prefix(Graph& g, int mode, hipStream_t s) {
+    FwState& f = g.fw[mode == 2 ? 0 : 1];
+    SgState& q = g.sg[mode == 2 ? 0 : 1];
+    LDS_CHECK(f.K[0].n == (size_t)g.n && f.ev[0] != nullptr, ST_INVALID,
+              "no Frank-Wolfe state: call lds_frank_wolfe first");
+    const SweepPlan& p = (mode == 2) ? g.edge_plan : g.tri_plan;
+    const int64_t n = g.n;
+    q.valid = false;
+    q.iters = f.iters;
+    q.order.alloc(n, s);
+    q.pos.alloc(n, s);
+    q.E.alloc(n, s);
+    q.inI.alloc(n, s);
+    if (n == 0) {
+        q.valid = true;
+        return;
+    }
+    // a7: sort
+    {
+        DBuf<uint64_t> k, kt;
+        DBuf<uint32_t> v, vt;
+        k.alloc(n, s);
+        kt.alloc(n, s);
+        v.alloc(n, s);
+        vt.alloc(n, s);
+        k_sort_init<<<grid_for(n, kT), kT, 0, s>>>(f.K[f.cur].p, n, k.p, v.p);
+        LDS_HIP(hipGetLastError());
+        const int kb = g.idbits + bits_for((uint64_t)fw_max_numerator(g, mode, f.iters));
+        radix_sort_u64(k.p, v.p, n, std::min(kb, 64), kt.p, vt.p, s);
+        k_order<<<grid_for(n, kT), kT, 0, s>>>(v.p, n, q.order.p, q.pos.p);
+        LDS_HIP(hipGetLastError());
+    }
+    // per-slot split numerators (and per triangle)
+    q.a_slot.alloc(p.nslots, s);
+    if (p.nslots > 0 && f.iters >= 0) {
+        const int64_t blocks = p.n_hub + p.n_chunks;
+        k_slot_splits<<<grid_for(blocks, 1), kT, 0, s>>>(p.rp, p.n_hub, p.hwo.p, p.n_chunks, p.chunk_row.p, p.cwo.p,
+                                                         p.chunk_words, f.bits.p, p.total_words, f.iters, mode == 3,
+                                                         q.a_slot.p);
+        LDS_HIP(hipGetLastError());
+    }
+    if (mode == 3) {
+        q.a_tri.alloc(3 * g.T, s);
+        if (g.T > 0) {
+            k_tri_splits<<<grid_for(p.nslots, kT), kT, 0, s>>>(p.py, p.own_tos.p, g.tri.p, q.a_slot.p, p.nslots,
+                                                              q.a_tri.p);
+            LDS_HIP(hipGetLastError());
+        }
+    }
+    // a8: counts by position, prefix, suffix maxima
+    DBuf<int64_t> c;
+    c.alloc(n, s);
+    k_fill_i64<<<grid_for(n, kT), kT, 0, s>>>(c.p, n, 0);
+    LDS_HIP(hipGetLastError());
+    PassArgs a{};
+    a.kind = PASS_COUNT;
+    a.a_slot = q.a_slot.p;
+    a.a_tri = q.a_tri.p;
+    a.pos = q.pos.p;
+    a.D = fw_denom(mode, f.iters);
+    a.out = c.p;
+    run_pass(g, mode, a, s);
+    {
+        DBuf<uint64_t> ex;
+        ex.alloc(n, s);
+        exclusive_scan_u64((const uint64_t*)c.p, ex.p, n, nullptr, s);
+        k_inclusive<<<grid_for(n, kT), kT, 0, s>>>(ex.p, c.p, n, q.E.p);
+        LDS_HIP(hipGetLastError());
+    }
+    const int64_t tiles = (n + kTile - 1) / kTile;
+    DBuf<int64_t> tn, td;
+    tn.alloc(tiles, s);
+    td.alloc(tiles, s);
+    k_tile_fmax<<<grid_for(tiles, 1), kT, 0, s>>>(q.E.p, n, tn.p, td.p);
+    LDS_HIP(hipGetLastError());
+    std::vector<int64_t> hn(tiles), hd(tiles), cn(tiles), cd(tiles);
+    LDS_HIP(hipMemcpyAsync(hn.data(), tn.p, tiles * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    LDS_HIP(hipMemcpyAsync(hd.data(), td.p, tiles * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    LDS_HIP(hipStreamSynchronize(s));
+    {
+        int64_t rn = 0, rd = 0;  // max over later tiles (den 0: minus infinity)
+        for (int64_t t = tiles - 1; t >= 0; --t) {
+            cn[t] = rn;
+            cd[t] = rd;
+            const bool gt = (rd == 0) ? hd[t] != 0 : (hd[t] != 0 && (__int128)hn[t] * rd > (__int128)rn * hd[t]);
+            if (gt) { rn = hn[t]; rd = hd[t]; }
+        }
+    }
+    LDS_HIP(hipMemcpyAsync(tn.p, cn.data(), tiles * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    LDS_HIP(hipMemcpyAsync(td.p, cd.data(), tiles * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    k_tile_inI<<<grid_for(tiles, 1), kT, 0, s>>>(q.E.p, n, tn.p, td.p, q.inI.p);
+    LDS_HIP(hipGetLastError());
+    LDS_HIP(hipStreamSynchronize(s));
+    q.valid = true;
+    q.gstart.clear();
+    q.gend.clear();
+}
+
+void sg_stable_groups(Graph& g, int mode, hipStream_t s) {
+    SgState& q = g.sg[mode == 2 ? 0 : 1];
+    const FwState& f = g.fw[mode == 2 ? 0 : 1];
+    if (!q.valid || q.iters != f.iters) sg_sort_prefix(g, mode, s);
+    const int64_t n = g.n;
+    q.gstart.clear();
+    q.gend.clear();
+    q.lo.alloc(n, s);
+    q.hi.alloc(n, s);
+    q.rounds = q.verifications = 0;
+    if (n == 0) return;
+    k_fill_i64<<<grid_for(n, kT), kT, 0, s>>>(q.lo.p, n, -1);
+    k_fill_i64<<<grid_for(n, kT), kT, 0, s>>>(q.hi.p, n, -1);
+    LDS_HIP(hipGetLastError());
+    DBuf<int64_t> R, T, V;
+    R.alloc(n, s);
+    T.alloc(n, s);
+    V.alloc(n, s);
+    k_fill_i64<<<grid_for(n, kT), kT, 0, s>>>(R.p, n, 0);
+    k_fill_i64<<<grid_for(n, kT), kT, 0, s>>>(T.p, n, 0);
+    k_fill_i64<<<grid_for(n, kT), kT, 0, s>>>(V.p, n, 0);
+    LDS_HIP(hipGetLastError());
+    PassArgs a{};
+    a.a_slot = q.a_slot.p;
+    a.a_tri = q.a_tri.p;
+    a.pos = q.pos.p;
+    a.D = fw_denom(mode, f.iters);
+    a.kind = PASS_R;
+    a.out = R.p;
+    run_pass(g, mode, a, s);
+
+    constexpr int64_t kCap = 256;
+    DBuf<unsigned long long> first;
+    DBuf<long long> mm;
+    DBuf<uint32_t> flag;
+    DBuf<uint64_t> off, total;
+    DBuf<int64_t> list;
+    first.alloc(1, s);
+    mm.alloc(4, s);
+    flag.alloc(n, s);
+    off.alloc(n, s);
+    total.alloc(1, s);
+    list.alloc(kCap, s);
+    int64_t S0 = 0, minH = -1;
+    std::vector<int64_t> cand;
+    while (S0 < n) {
+        ++q.rounds;
+        // restricted load T_x of every x >= S0 when S = [S0, pos x]
+        a.kind = PASS_T;
+        a.S0 = S0;
+        a.out = T.p;
+        run_pass(g, mode, a, s);
+        // stop: first j >= S0 with T_j >= minH (every b > j fails)
+        int64_t jstop = n;
+        if (minH >= 0) {
+            const unsigned long long init = ~0ull;
+            LDS_HIP(hipMemcpyAsync(first.p, &init, sizeof(init), hipMemcpyHostToDevice, s));
+            k_first_ge<<<grid_for(n - S0, kT), kT, 0, s>>>(T.p, S0, n, minH, first.p);
+            LDS_HIP(hipGetLastError());
+            const unsigned long long r = d2h(first.p, s);
+            if (r != ~0ull) jstop = (int64_t)r;
+        }
+        // candidate boundaries b in (S0, jstop], in order
+        bool accepted = false;
+        int64_t from = S0;
+        while (!accepted && from < jstop) {
+            const int64_t cnt = jstop - from;
+            k_cand_flags<<<grid_for(cnt, kT), kT, 0, s>>>(q.inI.p, R.p, T.p, from, jstop, n, flag.p);
+            LDS_HIP(hipGetLastError());
+            exclusive_scan_u32_to_u64(flag.p, off.p, cnt, total.p, s);
+            k_cand_compact<<<grid_for(cnt, kT), kT, 0, s>>>(flag.p, off.p, from, cnt, list.p, kCap);
+            LDS_HIP(hipGetLastError());
+            const int64_t nc = (int64_t)d2h(total.p, s);
+            if (nc == 0) break;
+            const int64_t take = std::min(nc, kCap);
+            cand.resize(take);
+            LDS_HIP(hipMemcpyAsync(cand.data(), list.p, take * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+            LDS_HIP(hipStreamSynchronize(s));
+            for (int64_t ci = 0; ci < take && !accepted; ++ci) {
+                const int64_t b = cand[ci];
+                ++q.verifications;
+                a.kind = PASS_V;
+                a.S0 = S0;
+                a.b = b;
+                a.out = V.p;
+                run_pass(g, mode, a, s);
+                const long long init[4] = {LLONG_MAX, LLONG_MIN, LLONG_MAX, LLONG_MIN};
+                LDS_HIP(hipMemcpyAsync(mm.p, init, sizeof(init), hipMemcpyHostToDevice, s));
+                k_minmax<<<grid_for(b - S0, kT), kT, 0, s>>>(V.p, S0, b, mm.p);
+                if (b < n) k_minmax<<<grid_for(n - b, kT), kT, 0, s>>>(V.p, b, n, mm.p + 2);
+                LDS_HIP(hipGetLastError());
+                long long h[4];
+                LDS_HIP(hipMemcpyAsync(h, mm.p, sizeof(h), hipMemcpyDeviceToHost, s));
+                LDS_HIP(hipStreamSynchronize(s));
+                const bool ok = (minH < 0 || h[1] < minH) && (b == n || h[3] < h[0]);
+                if (ok) {
+                    k_set_bounds<<<grid_for(b - S0, kT), kT, 0, s>>>(q.order.p, S0, b, h[0], h[1], q.lo.p, q.hi.p);
+                    LDS_HIP(hipGetLastError());
+                    q.gstart.push_back(S0);
+                    q.gend.push_back(b);
+                    minH = h[0];
+                    S0 = b;
+                    accepted = true;
+                }
+            }
+            if (!accepted) from = cand[take - 1];  // continue after the last candidate examined
+        }
+        if (!accepted) break;  // the remaining tail is never accepted: no bounds
+    }
+    LDS_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace lds

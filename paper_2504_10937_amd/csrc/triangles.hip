@@ -125,7 +125,7 @@ __global__ void k_inc_keys(const int32_t* tri, int64_t T, const int32_t* row_of,
 }
 
 __global__ void k_inc_pay(const uint64_t* keys, int64_t ns, int tb, const int32_t* tri, const int32_t* rid,
-                          int32_t* pay) {
+                          int32_t* pay, int32_t* tos) {
     const int64_t s = (int64_t)blockIdx.x * kT + threadIdx.x;
     if (s >= ns) return;
     const uint64_t k = keys[s];
@@ -136,6 +136,7 @@ __global__ void k_inc_pay(const uint64_t* keys, int64_t ns, int tb, const int32_
     if (x == a) { p = b; q = c; } else if (x == b) { p = a; q = c; } else { p = a; q = b; }
     pay[2 * s] = p;
     pay[2 * s + 1] = q;
+    tos[s] = (int32_t)t;
 }
 
 __global__ void k_set_last(int64_t* rowptr, int64_t idx, const uint64_t* total) { rowptr[idx] = (int64_t)*total; }
@@ -233,7 +234,9 @@ void list_triangles(Graph& g, hipStream_t s) {
         k_inc_keys<<<grid_for(T, kT), kT, 0, s>>>(g.tri.p, T, row_of.p, tb, ik.p);
         LDS_HIP(hipGetLastError());
         radix_sort_u64(ik.p, nullptr, 3 * T, tb + rb, it.p, nullptr, s);
-        k_inc_pay<<<grid_for(3 * T, kT), kT, 0, s>>>(ik.p, 3 * T, tb, g.tri.p, p.own_rid.p, p.own_py.p);
+        p.own_tos.alloc(3 * T, s);
+        k_inc_pay<<<grid_for(3 * T, kT), kT, 0, s>>>(ik.p, 3 * T, tb, g.tri.p, p.own_rid.p, p.own_py.p,
+                                                    p.own_tos.p);
         LDS_HIP(hipGetLastError());
     }
     p.rid = p.own_rid.p;

@@ -1,0 +1,96 @@
+"""GPU parity for Alg. 2 (sort, prefix counts, index set I, stable groups and
+their bounds) against the CPU oracle, exact."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_helpers import announce
+
+pytestmark = pytest.mark.gpu
+lds = pytest.importorskip("paper_2504_10937_amd")
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def check_sg(n, s, d, mode, iters):
+    G = oracle.Graph(n, s, d)
+    g = lds.lds_create_graph(n, s, d)
+    out = lds.lds_frank_wolfe(g, mode, iters, want_num=True)
+    ref = oracle.fw_exact(G, mode, iters, with_gap=False)
+    np.testing.assert_array_equal(out["num"], ref["A"])
+    order, E, inI = lds.lds_sort_prefix(g, mode)
+    o_order, o_E, o_inI = oracle.sort_prefix(G, mode, ref["A"])
+    np.testing.assert_array_equal(order, o_order)
+    np.testing.assert_array_equal(E, o_E)
+    np.testing.assert_array_equal(inI, o_inI)
+    groups, lo, hi = lds.lds_stable_groups(g, mode)
+    o_groups, o_lo, o_hi = oracle.extract_sg(G, mode, ref["A"], ref["split"], ref["D"])
+    assert groups == o_groups
+    np.testing.assert_array_equal(lo, o_lo)
+    np.testing.assert_array_equal(hi, o_hi)
+    return g, groups
+
+
+@pytest.mark.parametrize("mode", [2, 3])
+@pytest.mark.parametrize("iters", [1, 5, 60, 2000])
+def test_running_example(mode, iters):
+    announce("sg running example", mode, iters)
+    with open(os.path.join(GOLD, "running_example.json")) as f:
+        d = json.load(f)
+    e = np.array(d["edges"], np.int32)
+    check_sg(d["n"], e[:, 0].copy(), e[:, 1].copy(), mode, iters)
+
+
+@pytest.mark.parametrize("mode", [2, 3])
+def test_lds_small_workload(mode):
+    n, s, d, _, iters, _ = synth.workload("lds_small")
+    announce("sg lds_small", mode)
+    check_sg(n, s, d, mode, iters)
+
+
+CASES = [
+    ("pl", dict(n=3000, beta=2.1, avg_deg=16.0, n_blocks=8, s_lo=30, s_hi=120, p_block=0.3, seed=2), 2, 100),
+    ("pl", dict(n=3000, beta=2.1, avg_deg=16.0, n_blocks=8, s_lo=30, s_hi=120, p_block=0.3, seed=2), 3, 60),
+    ("hk", dict(n=2000, mper=8, p_triad=0.6, seed=3), 3, 200),
+    ("hk", dict(n=2000, mper=8, p_triad=0.6, seed=3), 2, 30),
+    ("er", dict(n=60, p=0.3, seed=4), 2, 3),
+    ("er", dict(n=60, p=0.3, seed=4), 3, 3),
+    ("pl", dict(n=6000, beta=2.3, avg_deg=10.0, n_blocks=3, s_lo=600, s_hi=1500, p_block=0.9, seed=7), 2, 40),
+]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_graphs(case):
+    kind, kw, mode, iters = CASES[case]
+    announce("sg", kind, kw, mode, iters)
+    n, s, d = synth.erdos_renyi(**kw) if kind == "er" else (
+        synth.powerlaw_planted(**kw) if kind == "pl" else synth.holme_kim(**kw))
+    check_sg(n, s, d, mode, iters)
+
+
+def test_empty_and_edgeless():
+    for n in (0, 5):
+        g = lds.lds_create_graph(n, np.zeros(0, np.int32), np.zeros(0, np.int32))
+        for mode in (2, 3):
+            lds.lds_frank_wolfe(g, mode, 3)
+            order, E, inI = lds.lds_sort_prefix(g, mode)
+            assert sorted(order.tolist()) == list(range(n)) and (E == 0).all()
+            groups, lo, hi = lds.lds_stable_groups(g, mode)
+            G = oracle.Graph(n, np.zeros(0, np.int32), np.zeros(0, np.int32))
+            ref = oracle.fw_exact(G, mode, 3, with_gap=False)
+            o_groups, o_lo, o_hi = oracle.extract_sg(G, mode, ref["A"], ref["split"], ref["D"])
+            assert groups == o_groups
+            np.testing.assert_array_equal(lo, o_lo)
+
+
+def test_requires_fw_state():
+    g = lds.lds_create_graph(3, np.array([0, 1], np.int32), np.array([1, 2], np.int32))
+    with pytest.raises(lds.LdsError):
+        lds.lds_sort_prefix(g, 2)
