@@ -58,6 +58,7 @@ def main():
     ap.add_argument("--workload", default="lds_large")
     ap.add_argument("--cpu-iters", type=int, default=4, help="FW iterations of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fw-only", action="store_true", help="leave the sort / prefix / stable groups out of the step")
     ap.add_argument("--iters", type=int, default=0, help="override the workload's FW iteration count")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="first run one device copy of this many MiB (a known-size kernel for counter scaling)")
@@ -90,13 +91,28 @@ def main():
     r = torch.empty(n, dtype=torch.float32, device="cuda")
     stream = torch.cuda.current_stream()
 
+    phases = {}
+
     def step():
+        t = [time.perf_counter()]
         g = lds.lds_create_graph(n, ts, td, stream=stream)
+        if mode == 3:
+            lds.lds_triangles(g, stream=stream)
+        torch.cuda.synchronize()
+        t.append(time.perf_counter())
         lds.lds_frank_wolfe(g, mode, iters, r_out=r, want_gap=True, stream=stream)
+        t.append(time.perf_counter())
+        groups = None
+        if not args.fw_only:
+            groups, _, _ = lds.lds_stable_groups(g, mode, stream=stream)
+        t.append(time.perf_counter())
         fw_ms, launches = lds.lds_fw_elapsed(g, mode)
         info = lds.lds_graph_info(g)
         sw = lds.lds_sweep_info(g, mode, stream=stream)
         g.destroy()
+        for k, (a, b) in zip(("ingest", "fw", "sort_prefix_groups"), zip(t, t[1:])):
+            phases.setdefault(k, []).append((b - a) * 1e3)
+        phases.setdefault("groups", []).append(len(groups) if groups is not None else -1)
         return fw_ms, launches, info, sw
 
     for i in range(args.warmup):
@@ -135,8 +151,9 @@ def main():
         "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "m": m, "triangles": info["triangles"], "fw_iters": iters,
-                   "mode": "edge" if mode == 2 else "triangle", "step": "ingest+fw(gap)+float view"},
+                   "mode": "edge" if mode == 2 else "triangle", "step": "ingest+fw(gap)+float view" + ("" if args.fw_only else "+sort/prefix/stable groups")},
         "fw_only_updates_per_s": units * iters / (fw_mean / 1e3),
+        "phase_ms": {k: sum(v) / len(v) for k, v in phases.items()},
         "fw_sweep_ms_per_launch": per_launch_s * 1e3,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

@@ -44,6 +44,7 @@ struct SweepPlan {
     DBuf<int64_t> own_rp;
     DBuf<int32_t> own_py;
     DBuf<int32_t> own_tos;         // triangles: slot -> triangle index
+    DBuf<int32_t> own_row_of;      // triangles: internal vertex -> compact row, -1 if none
     int64_t n_big = 0;             // rows [0, n_big) have >= 64 slots (rows are ordered by slot count)
     int64_t n_hub = 0;          // rows [0, n_hub) are hubs
     DBuf<int64_t> hwo;          // n_hub + 1 word offsets (relative to hub region)
@@ -54,7 +55,7 @@ struct SweepPlan {
     int64_t chunk_words = 0, hub_words = 0, total_words = 0;
     DBuf<int64_t> bitbase;      // per compact row: bit index of its first slot
     size_t device_bytes() const {
-        return own_rid.bytes() + own_rp.bytes() + own_py.bytes() + own_tos.bytes() + hwo.bytes() + chunk_row.bytes() + cwo.bytes() +
+        return own_rid.bytes() + own_rp.bytes() + own_py.bytes() + own_tos.bytes() + own_row_of.bytes() + hwo.bytes() + chunk_row.bytes() + cwo.bytes() +
                head.bytes() + bitbase.bytes();
     }
 };

@@ -27,8 +27,13 @@
 //        (2) R of the first vertex below < T of the last vertex of S, where R_w
 //            is w's restricted load when everything before w is above it
 //            (max_below >= R_first, min_S <= T_last);
-//     and verify each exactly with one pass over all patterns, accepting the
-//     first that passes.  All quantities are integer numerators over D_N.
+//     and verify each exactly, accepting the first that passes: restricted
+//     loads of S from S's own patterns; the restricted loads of the vertices
+//     below b are kept current as b advances (verification boundaries only
+//     increase) with block maxima for the suffix maximum.
+//     T is kept current by adding, after each acceptance, the change of the
+//     accepted group's patterns.  All quantities are integer numerators over
+//     D_N.
 #include <algorithm>
 #include <climits>
 
@@ -127,6 +132,7 @@ struct PassArgs {
     const uint32_t* a_slot;
     const uint32_t* a_tri;
     const int64_t* pos;
+    const int32_t* row_of;  // triangles: internal vertex -> row (edges: identity below nrows)
     int64_t nrows, n_big;
     uint64_t D;
     int64_t S0, b;   // PASS_T: S0; PASS_V: S0 and b
@@ -332,6 +338,194 @@ __global__ void k_fill_i64(int64_t* p, int64_t n, int64_t v) {
     if (i < n) p[i] = v;
 }
 
+// ---- incremental maintenance of T and restricted verification passes
+// group of position p under thresholds: 0 above (< t1), 1 tested ([t1, t2)), 2 below
+// contribution of pattern vertex k (of h) given positions and split numerators
+template <int H>
+__device__ inline int64_t pat_contrib(int k, const int64_t* p, const int64_t* al, uint64_t D, int64_t t1, int64_t t2) {
+    int g[H];
+    int gl = 0;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        g[i] = grp(p[i], t1, t2);
+        gl = max(gl, g[i]);
+    }
+    if (g[k] < gl) return 0;
+    int64_t freed = 0;
+    bool recv = true;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        if (g[i] < gl) freed += al[i];
+        else if (i != k && p[i] > p[k]) recv = false;
+    }
+    (void)D;
+    return al[k] + (recv ? freed : 0);
+}
+
+// positions, numerators and internal ids of the pattern at slot s of row x
+template <int H>
+__device__ inline void load_pattern(const PassArgs& a, int64_t s, int32_t x, int64_t* p, int64_t* al, int32_t* id);
+template <>
+__device__ inline void load_pattern<2>(const PassArgs& a, int64_t s, int32_t x, int64_t* p, int64_t* al, int32_t* id) {
+    id[0] = x;
+    id[1] = a.py[s];
+    p[0] = a.pos[x];
+    p[1] = a.pos[id[1]];
+    al[0] = a.a_slot[s];
+    al[1] = (int64_t)a.D - al[0];
+}
+template <>
+__device__ inline void load_pattern<3>(const PassArgs& a, int64_t s, int32_t x, int64_t* p, int64_t* al, int32_t* id) {
+    const int32_t v = a.py[2 * s], w = a.py[2 * s + 1];
+    const int64_t t = a.tos[s];
+    const int jx = tri_index(a.tri, t, v, w);
+    const int jv = (jx == 0) ? 1 : 0, jw = (jx == 2) ? 1 : 2;
+    id[0] = x;
+    id[1] = v;
+    id[2] = w;
+    p[0] = a.pos[x];
+    p[1] = a.pos[v];
+    p[2] = a.pos[w];
+    al[0] = a.a_tri[3 * t + jx];
+    al[1] = a.a_tri[3 * t + jv];
+    al[2] = a.a_tri[3 * t + jw];
+}
+
+__device__ inline int64_t row_of_vertex(const PassArgs& a, int32_t x) {
+    if (a.row_of) return a.row_of[x];
+    return (x < a.nrows) ? (int64_t)x : -1;
+}
+
+// After accepting the group at positions [a0, a1): T_y of every vertex y
+// below (pos >= a1) changes only through patterns that contain accepted
+// vertices; each such pattern is handled once, from its latest accepted
+// vertex, adding (contribution after - contribution before) to T_y.
+template <int H>
+__global__ __launch_bounds__(kT) void k_tdelta(PassArgs a, int64_t a0, int64_t a1, const int32_t* order, int64_t* T) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t j = a0 + (int64_t)blockIdx.x * 4 + w;
+    if (j >= a1) return;
+    const int32_t x = order[j];
+    const int64_t r = row_of_vertex(a, x);
+    if (r < 0) return;
+    for (int64_t s = a.rp[r] + lane; s < a.rp[r + 1]; s += 64) {
+        int64_t p[H], al[H];
+        int32_t id[H];
+        load_pattern<H>(a, s, x, p, al, id);
+        bool owner = true;  // x is the latest accepted vertex of the pattern
+#pragma unroll
+        for (int i = 1; i < H; ++i)
+            if (p[i] >= a0 && p[i] < a1 && p[i] > p[0]) owner = false;
+        if (!owner) continue;
+#pragma unroll
+        for (int i = 1; i < H; ++i) {
+            if (p[i] < a1) continue;
+            const int64_t before = pat_contrib<H>(i, p, al, a.D, a0, p[i] + 1);
+            const int64_t after = pat_contrib<H>(i, p, al, a.D, a1, p[i] + 1);
+            if (after != before)
+                atomicAdd((unsigned long long*)&T[p[i]], (unsigned long long)(after - before));
+        }
+    }
+}
+
+// restricted loads for (S0, b) of the vertices at positions list[i] (or
+// [lo, lo + cnt) when list is null), one wave per vertex; written by position
+template <int H>
+__global__ __launch_bounds__(kT) void k_listpass(PassArgs a, const int64_t* list, int64_t lo, int64_t cnt,
+                                                 const int32_t* order, int64_t* out) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t i = (int64_t)blockIdx.x * 4 + w;
+    if (i >= cnt) return;
+    const int64_t j = list ? list[i] : lo + i;
+    const int32_t x = order[j];
+    const int64_t r = row_of_vertex(a, x);
+    int64_t acc = 0;
+    if (r >= 0) {
+        for (int64_t s = a.rp[r] + lane; s < a.rp[r + 1]; s += 64) {
+            int64_t p[H], al[H];
+            int32_t id[H];
+            load_pattern<H>(a, s, x, p, al, id);
+            acc += pat_contrib<H>(0, p, al, a.D, a.S0, a.b);
+        }
+        for (int m = 32; m > 0; m >>= 1) acc += shfl_xor_i64(acc, m);
+    }
+    if (lane == 0) out[j] = acc;
+}
+
+// The restricted load F_w(b) of a vertex below the boundary b (everything
+// before b is above it) only grows with b.  Verification boundaries increase
+// over the whole scan, so F is advanced incrementally: when positions
+// [p0, p1) move above, each of their patterns (handled once, from its latest
+// moving vertex) adds (after - before) to the vertices still below; block
+// maxima over 1024 positions stay valid under these increases.
+constexpr int kFB = 1024;
+
+template <int H>
+__global__ __launch_bounds__(kT) void k_fdelta(PassArgs a, int64_t p0, int64_t p1, const int32_t* order, int64_t* F,
+                                               long long* bmax) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t j = p0 + (int64_t)blockIdx.x * 4 + w;
+    if (j >= p1) return;
+    const int32_t y = order[j];
+    const int64_t r = row_of_vertex(a, y);
+    if (r < 0) return;
+    for (int64_t s = a.rp[r] + lane; s < a.rp[r + 1]; s += 64) {
+        int64_t p[H], al[H];
+        int32_t id[H];
+        load_pattern<H>(a, s, y, p, al, id);
+        bool owner = true;
+#pragma unroll
+        for (int i = 1; i < H; ++i)
+            if (p[i] >= p0 && p[i] < p1 && p[i] > p[0]) owner = false;
+        if (!owner) continue;
+#pragma unroll
+        for (int i = 1; i < H; ++i) {
+            if (p[i] < p1) continue;
+            const int64_t before = pat_contrib<H>(i, p, al, a.D, p0, p0);
+            const int64_t after = pat_contrib<H>(i, p, al, a.D, p1, p1);
+            if (after != before) {
+                const unsigned long long old =
+                    atomicAdd((unsigned long long*)&F[p[i]], (unsigned long long)(after - before));
+                atomicMax(&bmax[p[i] / kFB], (long long)(old + (unsigned long long)(after - before)));
+            }
+        }
+    }
+}
+
+// F at b = 0 (nothing above): the plain load numerators, by position
+__global__ void k_f_init(const uint64_t* K, const int32_t* order, int64_t n, int B, int64_t* F) {
+    const int64_t j = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (j < n) F[j] = (int64_t)(K[order[j]] >> B);
+}
+
+__global__ __launch_bounds__(kT) void k_bmax_init(const int64_t* F, int64_t n, long long* bmax) {
+    const int64_t base = (int64_t)blockIdx.x * kFB;
+    long long mx = LLONG_MIN;
+    for (int64_t j = base + threadIdx.x; j < base + kFB && j < n; j += kT) mx = max(mx, (long long)F[j]);
+    for (int m = 32; m > 0; m >>= 1) mx = max(mx, (long long)shfl_xor_i64(mx, m));
+    __shared__ long long sh[4];
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) bmax[blockIdx.x] = max(max(sh[0], sh[1]), max(sh[2], sh[3]));
+}
+
+// max of F over positions [b, n): the partial block at b plus whole blocks
+__global__ void k_suffix_max(const int64_t* F, const long long* bmax, int64_t b, int64_t n, int64_t nblk,
+                             long long* out) {
+    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+    const int64_t bend = min(n, (b / kFB + 1) * kFB);
+    const int64_t npart = bend - b;
+    long long mx = LLONG_MIN;
+    if (i < npart) {
+        mx = F[b + i];
+    } else {
+        const int64_t blk = b / kFB + 1 + (i - npart);
+        if (blk < nblk) mx = bmax[blk];
+    }
+    for (int m = 32; m > 0; m >>= 1) mx = max(mx, (long long)shfl_xor_i64(mx, m));
+    if ((threadIdx.x & 63) == 0 && mx != LLONG_MIN) atomicMax(out, mx);
+}
+
 template <int H>
 void row_pass(const SweepPlan& p, const PassArgs& a, hipStream_t s) {
     const int64_t nbb = (p.n_big + 3) / 4;
@@ -349,12 +543,26 @@ void run_pass(const Graph& g, int mode, PassArgs a, hipStream_t s) {
     a.py = p.py;
     a.tos = p.own_tos.p;
     a.tri = g.tri.p;
+    a.row_of = p.own_row_of.p;
     a.nrows = p.nrows;
     a.n_big = p.n_big;
     if (mode == 2)
         row_pass<2>(p, a, s);
     else
         row_pass<3>(p, a, s);
+}
+
+PassArgs plan_args(const Graph& g, int mode, PassArgs a) {
+    const SweepPlan& p = (mode == 2) ? g.edge_plan : g.tri_plan;
+    a.rid = p.rid;
+    a.rp = p.rp;
+    a.py = p.py;
+    a.tos = p.own_tos.p;
+    a.tri = g.tri.p;
+    a.row_of = p.own_row_of.p;
+    a.nrows = p.nrows;
+    a.n_big = p.n_big;
+    return a;
 }
 
 }  // namespace
@@ -470,7 +678,6 @@ void sg_stable_groups(Graph& g, int mode, hipStream_t s) {
     if (n == 0) return;
     k_fill_i64<<<grid_for(n, kT), kT, 0, s>>>(q.lo.p, n, -1);
     k_fill_i64<<<grid_for(n, kT), kT, 0, s>>>(q.hi.p, n, -1);
-    LDS_HIP(hipGetLastError());
     DBuf<int64_t> R, T, V;
     R.alloc(n, s);
     T.alloc(n, s);
@@ -484,11 +691,19 @@ void sg_stable_groups(Graph& g, int mode, hipStream_t s) {
     a.a_tri = q.a_tri.p;
     a.pos = q.pos.p;
     a.D = fw_denom(mode, f.iters);
+    // R_w: w's restricted load when every earlier vertex is above it
     a.kind = PASS_R;
     a.out = R.p;
     run_pass(g, mode, a, s);
+    // T_x for S0 = 0; afterwards maintained incrementally (k_tdelta)
+    a.kind = PASS_T;
+    a.S0 = 0;
+    a.out = T.p;
+    run_pass(g, mode, a, s);
+    a = plan_args(g, mode, a);
 
-    constexpr int64_t kCap = 256;
+    constexpr int64_t kCap = 256;       // candidates copied to the host per batch
+    constexpr int64_t kWin = 1 << 16;   // positions searched per window
     DBuf<unsigned long long> first;
     DBuf<long long> mm;
     DBuf<uint32_t> flag;
@@ -496,75 +711,118 @@ void sg_stable_groups(Graph& g, int mode, hipStream_t s) {
     DBuf<int64_t> list;
     first.alloc(1, s);
     mm.alloc(4, s);
-    flag.alloc(n, s);
-    off.alloc(n, s);
+    flag.alloc(kWin, s);
+    off.alloc(kWin, s);
     total.alloc(1, s);
     list.alloc(kCap, s);
     int64_t S0 = 0, minH = -1;
     std::vector<int64_t> cand;
+    auto launch_list = [&](const int64_t* lst, int64_t lo, int64_t cnt) {
+        if (cnt <= 0) return;
+        if (mode == 2)
+            k_listpass<2><<<grid_for(cnt, 4), kT, 0, s>>>(a, lst, lo, cnt, q.order.p, V.p);
+        else
+            k_listpass<3><<<grid_for(cnt, 4), kT, 0, s>>>(a, lst, lo, cnt, q.order.p, V.p);
+        LDS_HIP(hipGetLastError());
+    };
+    // below-boundary restricted loads F, advanced monotonically with b
+    DBuf<int64_t> F;
+    DBuf<long long> bmax;
+    const int64_t nblk = (n + kFB - 1) / kFB;
+    F.alloc(n, s);
+    bmax.alloc(nblk, s);
+    k_f_init<<<grid_for(n, kT), kT, 0, s>>>(f.K[f.cur].p, q.order.p, n, g.idbits, F.p);
+    k_bmax_init<<<grid_for(nblk, 1), kT, 0, s>>>(F.p, n, bmax.p);
+    LDS_HIP(hipGetLastError());
+    int64_t fb = 0;  // F reflects "positions < fb are above"
+    // exact test of S = [S0, b); fills (min_S, max_S)
+    auto verify = [&](int64_t b, long long* mnS, long long* mxS) -> bool {
+        ++q.verifications;
+        const long long init[4] = {LLONG_MAX, LLONG_MIN, LLONG_MIN, LLONG_MIN};
+        LDS_HIP(hipMemcpyAsync(mm.p, init, sizeof(init), hipMemcpyHostToDevice, s));
+        if (b > fb) {
+            if (mode == 2)
+                k_fdelta<2><<<grid_for(b - fb, 4), kT, 0, s>>>(a, fb, b, q.order.p, F.p, bmax.p);
+            else
+                k_fdelta<3><<<grid_for(b - fb, 4), kT, 0, s>>>(a, fb, b, q.order.p, F.p, bmax.p);
+            LDS_HIP(hipGetLastError());
+            fb = b;
+        }
+        if (b < n) {
+            const int64_t cnt = (std::min<int64_t>(n, (b / kFB + 1) * kFB) - b) + (nblk - (b / kFB + 1));
+            k_suffix_max<<<grid_for(cnt, kT), kT, 0, s>>>(F.p, bmax.p, b, n, nblk, mm.p + 2);
+            LDS_HIP(hipGetLastError());
+        }
+        a.S0 = S0;
+        a.b = b;
+        launch_list(nullptr, S0, b - S0);
+        k_minmax<<<grid_for(b - S0, kT), kT, 0, s>>>(V.p, S0, b, mm.p);
+        LDS_HIP(hipGetLastError());
+        long long h[4];
+        LDS_HIP(hipMemcpyAsync(h, mm.p, sizeof(h), hipMemcpyDeviceToHost, s));
+        LDS_HIP(hipStreamSynchronize(s));
+        *mnS = h[0];
+        *mxS = h[1];
+        if (minH >= 0 && !(h[1] < minH)) return false;
+        return b == n || h[2] < h[0];  // max over the vertices below < min_S
+    };
     while (S0 < n) {
         ++q.rounds;
-        // restricted load T_x of every x >= S0 when S = [S0, pos x]
-        a.kind = PASS_T;
-        a.S0 = S0;
-        a.out = T.p;
-        run_pass(g, mode, a, s);
-        // stop: first j >= S0 with T_j >= minH (every b > j fails)
-        int64_t jstop = n;
-        if (minH >= 0) {
-            const unsigned long long init = ~0ull;
-            LDS_HIP(hipMemcpyAsync(first.p, &init, sizeof(init), hipMemcpyHostToDevice, s));
-            k_first_ge<<<grid_for(n - S0, kT), kT, 0, s>>>(T.p, S0, n, minH, first.p);
-            LDS_HIP(hipGetLastError());
-            const unsigned long long r = d2h(first.p, s);
-            if (r != ~0ull) jstop = (int64_t)r;
-        }
-        // candidate boundaries b in (S0, jstop], in order
-        bool accepted = false;
+        bool accepted = false, stop = false;
         int64_t from = S0;
-        while (!accepted && from < jstop) {
-            const int64_t cnt = jstop - from;
-            k_cand_flags<<<grid_for(cnt, kT), kT, 0, s>>>(q.inI.p, R.p, T.p, from, jstop, n, flag.p);
-            LDS_HIP(hipGetLastError());
-            exclusive_scan_u32_to_u64(flag.p, off.p, cnt, total.p, s);
-            k_cand_compact<<<grid_for(cnt, kT), kT, 0, s>>>(flag.p, off.p, from, cnt, list.p, kCap);
-            LDS_HIP(hipGetLastError());
-            const int64_t nc = (int64_t)d2h(total.p, s);
-            if (nc == 0) break;
-            const int64_t take = std::min(nc, kCap);
-            cand.resize(take);
-            LDS_HIP(hipMemcpyAsync(cand.data(), list.p, take * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-            LDS_HIP(hipStreamSynchronize(s));
-            for (int64_t ci = 0; ci < take && !accepted; ++ci) {
-                const int64_t b = cand[ci];
-                ++q.verifications;
-                a.kind = PASS_V;
-                a.S0 = S0;
-                a.b = b;
-                a.out = V.p;
-                run_pass(g, mode, a, s);
-                const long long init[4] = {LLONG_MAX, LLONG_MIN, LLONG_MAX, LLONG_MIN};
-                LDS_HIP(hipMemcpyAsync(mm.p, init, sizeof(init), hipMemcpyHostToDevice, s));
-                k_minmax<<<grid_for(b - S0, kT), kT, 0, s>>>(V.p, S0, b, mm.p);
-                if (b < n) k_minmax<<<grid_for(n - b, kT), kT, 0, s>>>(V.p, b, n, mm.p + 2);
+        long long mnS = 0, mxS = 0;
+        int64_t acc_b = -1;
+        while (!accepted && !stop && from < n) {
+            const int64_t hi = std::min(n, from + kWin);
+            // first j in [from, hi) with T_j >= minH: every boundary after it fails
+            int64_t jst = hi;
+            if (minH >= 0) {
+                const unsigned long long init = ~0ull;
+                LDS_HIP(hipMemcpyAsync(first.p, &init, sizeof(init), hipMemcpyHostToDevice, s));
+                k_first_ge<<<grid_for(hi - from, kT), kT, 0, s>>>(T.p, from, hi, minH, first.p);
                 LDS_HIP(hipGetLastError());
-                long long h[4];
-                LDS_HIP(hipMemcpyAsync(h, mm.p, sizeof(h), hipMemcpyDeviceToHost, s));
-                LDS_HIP(hipStreamSynchronize(s));
-                const bool ok = (minH < 0 || h[1] < minH) && (b == n || h[3] < h[0]);
-                if (ok) {
-                    k_set_bounds<<<grid_for(b - S0, kT), kT, 0, s>>>(q.order.p, S0, b, h[0], h[1], q.lo.p, q.hi.p);
-                    LDS_HIP(hipGetLastError());
-                    q.gstart.push_back(S0);
-                    q.gend.push_back(b);
-                    minH = h[0];
-                    S0 = b;
-                    accepted = true;
+                const unsigned long long r = d2h(first.p, s);
+                if (r != ~0ull) {
+                    jst = (int64_t)r;
+                    stop = true;
                 }
             }
-            if (!accepted) from = cand[take - 1];  // continue after the last candidate examined
+            int64_t lo = from;
+            while (!accepted && lo < jst) {
+                const int64_t cnt = jst - lo;
+                k_cand_flags<<<grid_for(cnt, kT), kT, 0, s>>>(q.inI.p, R.p, T.p, lo, jst, n, flag.p);
+                LDS_HIP(hipGetLastError());
+                exclusive_scan_u32_to_u64(flag.p, off.p, cnt, total.p, s);
+                k_cand_compact<<<grid_for(cnt, kT), kT, 0, s>>>(flag.p, off.p, lo, cnt, list.p, kCap);
+                LDS_HIP(hipGetLastError());
+                const int64_t nc = (int64_t)d2h(total.p, s);
+                if (nc == 0) break;
+                const int64_t take = std::min(nc, kCap);
+                cand.resize(take);
+                LDS_HIP(hipMemcpyAsync(cand.data(), list.p, take * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+                LDS_HIP(hipStreamSynchronize(s));
+                for (int64_t ci = 0; ci < take && !accepted; ++ci) {
+                    if (verify(cand[ci], &mnS, &mxS)) {
+                        accepted = true;
+                        acc_b = cand[ci];
+                    }
+                }
+                if (!accepted) lo = cand[take - 1];  // resume after the last boundary examined
+            }
+            from = hi;
         }
         if (!accepted) break;  // the remaining tail is never accepted: no bounds
+        const int64_t b = acc_b;
+        k_set_bounds<<<grid_for(b - S0, kT), kT, 0, s>>>(q.order.p, S0, b, mnS, mxS, q.lo.p, q.hi.p);
+        if (mode == 2)
+            k_tdelta<2><<<grid_for(b - S0, 4), kT, 0, s>>>(a, S0, b, q.order.p, T.p);
+        else
+            k_tdelta<3><<<grid_for(b - S0, 4), kT, 0, s>>>(a, S0, b, q.order.p, T.p);
+        LDS_HIP(hipGetLastError());
+        q.gstart.push_back(S0);
+        q.gend.push_back(b);
+        minH = mnS;
+        S0 = b;
     }
     LDS_HIP(hipStreamSynchronize(s));
 }

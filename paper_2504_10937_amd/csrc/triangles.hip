@@ -203,8 +203,9 @@ void list_triangles(Graph& g, hipStream_t s) {
     p.own_rid.alloc(nrows, s);
     p.own_rp.alloc(nrows + 1, s);
     p.own_py.alloc(2 * 3 * T, s);
-    DBuf<int32_t> row_of;
+    DBuf<int32_t>& row_of = p.own_row_of;
     row_of.alloc(n, s);
+    if (n) LDS_HIP(hipMemsetAsync(row_of.p, 0xff, n * sizeof(int32_t), s));  // -1: no triangle
     DBuf<uint32_t> rcount;
     rcount.alloc(nrows, s);
     if (nrows > 0) {
