@@ -155,27 +155,33 @@ static int rank_less(const orc_graph *g, int32_t u, int32_t v) {
  * (n counts) may be NULL. */
 int64_t orc_triangles(const orc_graph *g, int32_t *tri, int64_t *tcount) {
     int64_t n = g->n;
+    /* out-lists: neighbours of higher rank */
+    int64_t *ooff = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    int32_t *oadj = (int32_t *)malloc((size_t)(g->m > 0 ? g->m : 1) * sizeof(int32_t));
     uint8_t *mark = (uint8_t *)calloc((size_t)(n > 0 ? n : 1), 1);
-    if (!mark) return -1;
+    if (!ooff || !oadj || !mark) { free(ooff); free(oadj); free(mark); return -1; }
+    for (int32_t u = 0; u < n; u++) {
+        ooff[u + 1] = ooff[u];
+        for (int64_t s = g->off[u]; s < g->off[u + 1]; s++)
+            if (rank_less(g, u, g->adj[s])) oadj[ooff[u + 1]++] = g->adj[s];
+    }
     int64_t cnt = 0, cap = 0;
     tri_t *buf = NULL;
     if (tcount) memset(tcount, 0, (size_t)n * sizeof(int64_t));
     for (int32_t u = 0; u < n; u++) {
-        for (int64_t s = g->off[u]; s < g->off[u + 1]; s++)
-            if (rank_less(g, u, g->adj[s])) mark[g->adj[s]] = 1;
-        for (int64_t s = g->off[u]; s < g->off[u + 1]; s++) {
-            int32_t v = g->adj[s];
-            if (!rank_less(g, u, v)) continue;
-            for (int64_t q = g->off[v]; q < g->off[v + 1]; q++) {
-                int32_t w = g->adj[q];
-                if (!rank_less(g, v, w) || !mark[w]) continue;
-                /* triangle {u, v, w} */
+        for (int64_t s = ooff[u]; s < ooff[u + 1]; s++) mark[oadj[s]] = 1;
+        for (int64_t s = ooff[u]; s < ooff[u + 1]; s++) {
+            int32_t v = oadj[s];
+            for (int64_t q = ooff[v]; q < ooff[v + 1]; q++) {
+                int32_t w = oadj[q];
+                if (!mark[w]) continue;
+                /* triangle {u, v, w}: u -> v -> w and u -> w */
                 if (tcount) { tcount[u]++; tcount[v]++; tcount[w]++; }
                 if (tri) {
                     if (cnt == cap) {
                         int64_t nc = cap ? 2 * cap : 1024;
                         tri_t *nb = (tri_t *)realloc(buf, (size_t)nc * sizeof(tri_t));
-                        if (!nb) { free(buf); free(mark); return -1; }
+                        if (!nb) { free(buf); free(mark); free(ooff); free(oadj); return -1; }
                         buf = nb; cap = nc;
                     }
                     int32_t x[3] = {u, v, w};
@@ -187,9 +193,9 @@ int64_t orc_triangles(const orc_graph *g, int32_t *tri, int64_t *tcount) {
                 cnt++;
             }
         }
-        for (int64_t s = g->off[u]; s < g->off[u + 1]; s++) mark[g->adj[s]] = 0;
+        for (int64_t s = ooff[u]; s < ooff[u + 1]; s++) mark[oadj[s]] = 0;
     }
-    free(mark);
+    free(mark); free(ooff); free(oadj);
     if (tri) {
         qsort(buf, (size_t)cnt, sizeof(tri_t), cmp_tri);
         for (int64_t t = 0; t < cnt; t++) {
