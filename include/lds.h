@@ -158,6 +158,43 @@ lds_status lds_sweep_info(lds_graph g, lds_mode mode, int64_t* rows, int64_t* sl
 /* Denominator D_iters of the loads after `iters` iterations. */
 uint64_t lds_denominator(lds_mode mode, int32_t iters);
 
+/* Result of lds_topk, allocated by the library; release with
+ * lds_result_free.  Set i (0 <= i < count) has the caller ids
+ * vertices[offsets[i] .. offsets[i+1]) in ascending order and the exact
+ * density dens_num[i] / dens_den[i] (reduced fraction: edges (triangles) of
+ * the induced subgraph over its vertex count).  Sets are ordered by density
+ * descending, ties by smallest caller id ascending.  The stats fields report
+ * the work of the search: candidates taken, FW + ExtractSG runs on induced
+ * subgraphs, candidates split by a min cut, min-cut computations and
+ * vertices removed by the pruning rules. */
+typedef struct {
+    int32_t count;
+    int64_t* offsets;   /* count + 1 */
+    int32_t* vertices;  /* offsets[count] */
+    int64_t* dens_num;  /* count */
+    int64_t* dens_den;  /* count */
+    int64_t popped, refinements, flow_splits, maxflows, pruned;
+} lds_result;
+
+/* Top-k LDS (Problem LDS, Section 3; mode LDS_EDGE) or LTDS (Problem LTDS,
+ * Section 6; mode LDS_TRIANGLE) by the LDScvx search (Alg. 5): iters FW
+ * iterations (Alg. 1 / Alg. 6) and ExtractSG (Alg. 2) on the graph give
+ * bounds on every compact number, together with core (tr-core) numbers;
+ * Pruning (Alg. 3) removes vertices outside every LDS; candidates are
+ * verified exactly by IsDensest (one min cut) and IsLDS (Alg. 4) / IsLTDS
+ * (Alg. 7 with ExtMaximal, Alg. 8); a candidate that fails IsDensest is split
+ * by FW + ExtractSG on its induced subgraph (or by the min cut when that does
+ * not split it).  Returns the k densest LDSs (fewer when the graph has fewer
+ * with positive density).  Synchronises the stream: verification runs on the
+ * host.  Replaces the graph's FW state of this mode with an iters-iteration
+ * run.  *out is overwritten; on error it is left zeroed.  LDS_E_INVALID for
+ * k < 1, iters < 0 or a bad mode. */
+lds_status lds_topk(lds_graph g, lds_mode mode, int32_t k, int32_t iters, lds_result* out, void* hip_stream);
+
+/* Frees the arrays of a result filled by lds_topk and zeroes it; NULL and
+ * zeroed results are accepted. */
+void lds_result_free(lds_result* r);
+
 #ifdef __cplusplus
 }
 #endif

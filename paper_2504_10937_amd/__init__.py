@@ -56,6 +56,8 @@ def load():
         "lds_sort_prefix": (st, [vp, st, vp, vp, vp, vp]),
         "lds_stable_groups": (st, [vp, st, vp, vp, vp, i64, vp, vp, vp]),
         "lds_sweep_info": (st, [vp, st, vp, vp, vp, vp, vp, vp]),
+        "lds_topk": (st, [vp, st, i32, i32, vp, vp]),
+        "lds_result_free": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -231,6 +233,34 @@ def lds_sweep_info(g, mode, stream=None):
     v = [ctypes.c_int64() for _ in range(5)]
     _check(load().lds_sweep_info(g.handle, mode, *[ctypes.byref(x) for x in v], _stream(stream)))
     return dict(zip(("rows", "slots", "hub_rows", "chunks", "words"), (x.value for x in v)))
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32), ("offsets", ctypes.POINTER(ctypes.c_int64)),
+                ("vertices", ctypes.POINTER(ctypes.c_int32)), ("dens_num", ctypes.POINTER(ctypes.c_int64)),
+                ("dens_den", ctypes.POINTER(ctypes.c_int64)), ("popped", ctypes.c_int64),
+                ("refinements", ctypes.c_int64), ("flow_splits", ctypes.c_int64), ("maxflows", ctypes.c_int64),
+                ("pruned", ctypes.c_int64)]
+
+
+def lds_topk(g, mode, k, iters, stream=None, with_stats=False):
+    """Top-k LDS (mode 2) / LTDS (mode 3) -> list of (caller ids ascending,
+    Fraction density), densest first; with_stats adds the search counters."""
+    from fractions import Fraction
+    L = load()
+    r = _Result()
+    _check(L.lds_topk(g.handle, mode, int(k), int(iters), ctypes.byref(r), _stream(stream)))
+    try:
+        out = []
+        if r.count > 0:
+            off = np.ctypeslib.as_array(r.offsets, shape=(r.count + 1,)).copy()
+            allv = np.ctypeslib.as_array(r.vertices, shape=(max(int(off[-1]), 1),))[:int(off[-1])].copy()
+            for i in range(r.count):
+                out.append((allv[off[i]:off[i + 1]].copy(), Fraction(int(r.dens_num[i]), int(r.dens_den[i]))))
+        stats = {f: getattr(r, f) for f in ("popped", "refinements", "flow_splits", "maxflows", "pruned")}
+    finally:
+        L.lds_result_free(ctypes.byref(r))
+    return (out, stats) if with_stats else out
 
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)

@@ -6,10 +6,12 @@
 #include <array>
 #include <memory>
 #include <atomic>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 
 #include "graph.hpp"
+#include "topk.hpp"
 
 struct lds_graph_s {
     lds::Graph g;
@@ -290,6 +292,58 @@ lds_status lds_sweep_info(lds_graph g, lds_mode mode, int64_t* rows, int64_t* sl
 uint64_t lds_denominator(lds_mode mode, int32_t iters) {
     if (iters < 0) return 0;
     return (uint64_t)(mode == LDS_TRIANGLE ? 3 : 1) * (uint64_t)(iters + 1) * (uint64_t)(iters + 2);
+}
+
+lds_status lds_topk(lds_graph g, lds_mode mode, int32_t k, int32_t iters, lds_result* out, void* hip_stream) {
+    API_TRY
+    LDS_CHECK(g != nullptr && out != nullptr, lds::ST_INVALID, "graph and out must not be NULL");
+    std::memset(out, 0, sizeof(*out));
+    LDS_CHECK(mode == LDS_EDGE || mode == LDS_TRIANGLE, lds::ST_INVALID, "mode must be LDS_EDGE or LDS_TRIANGLE");
+    LDS_CHECK(k >= 1, lds::ST_INVALID, "k must be >= 1");
+    LDS_CHECK(iters >= 0, lds::ST_INVALID, "iters must be >= 0");
+    std::lock_guard<std::mutex> lk(g->mu);
+    std::vector<lds::TopkSet> sets;
+    lds::TopkStats st;
+    lds::topk_run(g->g, (int)mode, k, iters, (hipStream_t)hip_stream, sets, st);
+    int64_t total = 0;
+    for (const auto& t : sets) total += (int64_t)t.vertices.size();
+    const size_t c = sets.size();
+    lds_result r;
+    std::memset(&r, 0, sizeof(r));
+    r.offsets = (int64_t*)std::malloc((c + 1) * sizeof(int64_t));
+    r.vertices = (int32_t*)std::malloc((size_t)(total > 0 ? total : 1) * sizeof(int32_t));
+    r.dens_num = (int64_t*)std::malloc((c > 0 ? c : 1) * sizeof(int64_t));
+    r.dens_den = (int64_t*)std::malloc((c > 0 ? c : 1) * sizeof(int64_t));
+    if (!r.offsets || !r.vertices || !r.dens_num || !r.dens_den) {
+        lds_result_free(&r);
+        throw lds::Error(lds::ST_NOMEM, "host allocation of the result failed");
+    }
+    r.count = (int32_t)c;
+    int64_t at = 0;
+    for (size_t i = 0; i < c; ++i) {
+        r.offsets[i] = at;
+        std::copy(sets[i].vertices.begin(), sets[i].vertices.end(), r.vertices + at);
+        at += (int64_t)sets[i].vertices.size();
+        r.dens_num[i] = sets[i].num;
+        r.dens_den[i] = sets[i].den;
+    }
+    r.offsets[c] = at;
+    r.popped = st.popped;
+    r.refinements = st.refinements;
+    r.flow_splits = st.flow_splits;
+    r.maxflows = st.maxflows;
+    r.pruned = st.pruned;
+    *out = r;
+    API_CATCH
+}
+
+void lds_result_free(lds_result* r) {
+    if (!r) return;
+    std::free(r->offsets);
+    std::free(r->vertices);
+    std::free(r->dens_num);
+    std::free(r->dens_den);
+    std::memset(r, 0, sizeof(*r));
 }
 
 }  // extern "C"

@@ -1,0 +1,680 @@
+// Top-k LDS (Problem LDS, Section 3) and LTDS (Problem LTDS, Section 6): the
+// LDScvx driver (Alg. 5) and its triangle version, around the device
+// Frank-Wolfe (Alg. 1 / Alg. 6) and stable-group passes (Alg. 2), with every
+// decision taken on the host in exact integer arithmetic.
+//
+//  * Bounds on compact numbers: core(u)/2 <= phi(u) <= core(u) for edges and
+//    tr-core(u)/3 <= phi(u) <= tr-core(u) for triangles (Section 4.3 and its
+//    triangle counterpart), tightened by the stable groups of one FW +
+//    ExtractSG run on the WHOLE graph (Lemma phi-bounds / tr-phi-bounds), so
+//    that they bound phi_G of every vertex; they are the only bounds that the
+//    verification uses.
+//  * Pruning (Alg. 3): rule 1 (Cor. uv-prune) once, then rule 2 (Lemma
+//    uu-prune) with core / tr-core numbers of the residual graph until
+//    nothing changes.
+//  * Candidates are taken in non-increasing order of an upper bound on the
+//    density of any LDS inside them (a vertex of an LDS S has phi = density
+//    of S).  A disconnected candidate is split into its components.
+//  * IsDensest: one min cut at lambda = density(G[S]) on G[S].
+//  * IsLDS (Alg. 4) / IsLTDS (Alg. 7 with ExtMaximal, Alg. 8) on G.
+//  * A candidate that is not self-densest is refined by FW + ExtractSG on
+//    G[S] (Alg. 5 replaces G' by G[S]); if that does not split it, the
+//    maximal maximiser of the min cut (the vertices with phi_{G[S]} at least
+//    density(G[S])) splits it.  An LDS of G inside S is an LDS of G[S], and
+//    both splits keep vertices of equal phi_{G[S]} together, so every LDS
+//    stays whole inside one candidate; a self-densest connected candidate
+//    that contains an LDS is that LDS.
+//  * The search ends when the best remaining upper bound is below the k-th
+//    density found; results are sorted by (density desc, smallest caller id).
+#include <algorithm>
+#include <deque>
+#include <queue>
+
+#include "topk.hpp"
+
+namespace lds {
+
+namespace {
+
+typedef __int128 i128;
+
+struct Frac {
+    int64_t n = 0, d = 1;  // n / d with d > 0
+};
+inline bool lt(const Frac& a, const Frac& b) { return (i128)a.n * b.d < (i128)b.n * a.d; }
+inline int64_t gcd64(int64_t a, int64_t b) {
+    while (b) {
+        const int64_t t = a % b;
+        a = b;
+        b = t;
+    }
+    return a < 0 ? -a : a;
+}
+inline Frac reduce(int64_t n, int64_t d) {
+    const int64_t g = gcd64(n, d);
+    return g ? Frac{n / g, d / g} : Frac{0, 1};
+}
+
+// ------------------------------------------------------------ max flow
+// Dinic's algorithm on int64 capacities.
+struct Flow {
+    std::vector<int64_t> head, nxt, to, cap, level, it;
+    explicit Flow(int64_t nodes) : head(nodes, -1), level(nodes), it(nodes) {}
+    void arc(int64_t a, int64_t b, int64_t c) {
+        to.push_back(b); cap.push_back(c); nxt.push_back(head[a]); head[a] = (int64_t)to.size() - 1;
+        to.push_back(a); cap.push_back(0); nxt.push_back(head[b]); head[b] = (int64_t)to.size() - 1;
+    }
+    bool bfs(int64_t s, int64_t t) {
+        std::fill(level.begin(), level.end(), -1);
+        std::deque<int64_t> q;
+        level[s] = 0;
+        q.push_back(s);
+        while (!q.empty()) {
+            const int64_t x = q.front();
+            q.pop_front();
+            for (int64_t e = head[x]; e >= 0; e = nxt[e])
+                if (cap[e] > 0 && level[to[e]] < 0) {
+                    level[to[e]] = level[x] + 1;
+                    q.push_back(to[e]);
+                }
+        }
+        return level[t] >= 0;
+    }
+    // one augmenting path in the level graph (iterative), 0 when blocked
+    int64_t augment(int64_t s, int64_t t, std::vector<int64_t>& path) {
+        path.clear();
+        int64_t x = s;
+        for (;;) {
+            if (x == t) {
+                int64_t f = INT64_MAX;
+                for (int64_t e : path) f = std::min(f, cap[e]);
+                for (int64_t e : path) {
+                    cap[e] -= f;
+                    cap[e ^ 1] += f;
+                }
+                return f;
+            }
+            int64_t& e = it[x];
+            while (e >= 0 && !(cap[e] > 0 && level[to[e]] == level[x] + 1)) e = nxt[e];
+            if (e >= 0) {
+                path.push_back(e);
+                x = to[e];
+                continue;
+            }
+            if (path.empty()) return 0;  // s is blocked
+            level[x] = -1;               // dead end: retreat
+            const int64_t back = path.back();
+            path.pop_back();
+            x = to[back ^ 1];
+            it[x] = nxt[it[x]];
+        }
+    }
+    int64_t maxflow(int64_t s, int64_t t) {
+        int64_t f = 0;
+        std::vector<int64_t> path;
+        while (bfs(s, t)) {
+            it = head;
+            for (int64_t p; (p = augment(s, t, path)) > 0;) f += p;
+        }
+        return f;
+    }
+    // after maxflow: 1 for nodes on the source side of the minimum cut with
+    // the largest source side (nodes that cannot reach t in the residual)
+    std::vector<char> maximal_source_side(int64_t t) const {
+        std::vector<char> src(head.size(), 1);
+        std::deque<int64_t> q;
+        src[t] = 0;
+        q.push_back(t);
+        while (!q.empty()) {
+            const int64_t y = q.front();
+            q.pop_front();
+            for (int64_t e = head[y]; e >= 0; e = nxt[e]) {
+                const int64_t x = to[e];
+                if (src[x] && cap[e ^ 1] > 0) {  // residual arc x -> y
+                    src[x] = 0;
+                    q.push_back(x);
+                }
+            }
+        }
+        return src;
+    }
+};
+
+// Maximal X ⊆ {0..k-1} maximising q * #patterns inside X - p * |X| (a pattern
+// is inside X when all its members are; -1 pads patterns with fewer than h
+// members, a one-member pattern is a self-loop).  Network: source -> pattern
+// (capacity q), pattern -> member (unbounded), vertex -> sink (p).  Returns
+// the maximum value; inX marks the maximal maximiser.
+int64_t max_excess(int64_t k, int h, const std::vector<int32_t>& pat, int64_t p, int64_t q, std::vector<char>& inX) {
+    const int64_t np = (int64_t)pat.size() / h;
+    const int64_t S = np + k, T = S + 1;
+    Flow f(T + 1);
+    const int64_t INF = INT64_MAX / 4;
+    for (int64_t i = 0; i < np; ++i) {
+        f.arc(S, i, q);
+        for (int j = 0; j < h; ++j)
+            if (pat[h * i + j] >= 0) f.arc(i, np + pat[h * i + j], INF);
+    }
+    for (int64_t v = 0; v < k; ++v) f.arc(np + v, T, p);
+    const int64_t flow = f.maxflow(S, T);
+    const std::vector<char> side = f.maximal_source_side(T);
+    inX.assign(k, 0);
+    for (int64_t v = 0; v < k; ++v) inX[v] = side[np + v];
+    return q * np - flow;
+}
+
+}  // namespace
+
+// ----------------------------------------------------------- host graph
+void HostGraph::load(const Graph& g, int mode, hipStream_t s) {
+    n = g.n;
+    rp.assign(n + 1, 0);
+    col.assign(2 * g.m, 0);
+    orig.assign(n, 0);
+    if (n > 0) {
+        LDS_HIP(hipMemcpyAsync(rp.data(), g.rowptr.p, (n + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        LDS_HIP(hipMemcpyAsync(orig.data(), g.orig_of.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    }
+    if (g.m > 0) LDS_HIP(hipMemcpyAsync(col.data(), g.col.p, 2 * g.m * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    tri.clear();
+    if (mode == 3 && g.T > 0) {
+        tri.assign(3 * g.T, 0);
+        LDS_HIP(hipMemcpyAsync(tri.data(), g.tri.p, 3 * g.T * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    }
+    LDS_HIP(hipStreamSynchronize(s));
+    if (mode == 3) {
+        const int64_t T = (int64_t)tri.size() / 3;
+        trp.assign(n + 1, 0);
+        for (int64_t t = 0; t < 3 * T; ++t) trp[tri[t] + 1]++;
+        for (int64_t u = 0; u < n; ++u) trp[u + 1] += trp[u];
+        tinc.assign(3 * T, 0);
+        std::vector<int64_t> fill(trp.begin(), trp.end() - 1);
+        for (int64_t t = 0; t < T; ++t)
+            for (int j = 0; j < 3; ++j) tinc[fill[tri[3 * t + j]]++] = t;
+    }
+}
+
+
+namespace {
+
+// Peeling with a lazy bucket queue: repeatedly remove a vertex of minimum
+// count; its core number is the largest minimum met so far.  each(u, dec)
+// calls dec(v) once per unit that removing u takes from v's count.
+template <class Each>
+std::vector<int32_t> peel(int64_t n, const std::vector<char>& alive, std::vector<int32_t>& cnt, Each each) {
+    std::vector<int32_t> core(n, 0);
+    int32_t mx = 0;
+    for (int64_t u = 0; u < n; ++u)
+        if (alive[u]) mx = std::max(mx, cnt[u]);
+    std::vector<std::vector<int32_t>> bucket((size_t)mx + 1);
+    for (int64_t u = 0; u < n; ++u)
+        if (alive[u]) bucket[cnt[u]].push_back((int32_t)u);
+    std::vector<char> done(n, 0);
+    int32_t cur = 0, k = 0;
+    auto dec = [&](int32_t v) {
+        if (!alive[v] || done[v]) return;
+        --cnt[v];
+        bucket[cnt[v]].push_back(v);
+        if (cnt[v] < cur) cur = cnt[v];
+    };
+    for (;;) {
+        while (cur <= mx && bucket[cur].empty()) ++cur;
+        if (cur > mx) break;
+        const int32_t u = bucket[cur].back();
+        bucket[cur].pop_back();
+        if (done[u] || cnt[u] != cur) continue;  // stale entry
+        done[u] = 1;
+        k = std::max(k, cur);
+        core[u] = k;
+        each(u, dec);
+    }
+    return core;
+}
+
+// core numbers of the subgraph induced by the alive vertices
+std::vector<int32_t> core_numbers(const HostGraph& h, const std::vector<char>& alive) {
+    std::vector<int32_t> cnt(h.n, 0);
+    for (int64_t u = 0; u < h.n; ++u)
+        if (alive[u])
+            for (int64_t s = h.rp[u]; s < h.rp[u + 1]; ++s) cnt[u] += alive[h.col[s]];
+    return peel(h.n, alive, cnt, [&](int32_t u, auto& dec) {
+        for (int64_t s = h.rp[u]; s < h.rp[u + 1]; ++s) dec(h.col[s]);
+    });
+}
+
+// tr-core numbers: the count is the number of alive triangles at a vertex
+std::vector<int32_t> trcore_numbers(const HostGraph& h, const std::vector<char>& alive) {
+    const int64_t T = (int64_t)h.tri.size() / 3;
+    std::vector<char> tal(T, 0);
+    std::vector<int32_t> cnt(h.n, 0);
+    for (int64_t t = 0; t < T; ++t) {
+        const int32_t* x = &h.tri[3 * t];
+        if (alive[x[0]] && alive[x[1]] && alive[x[2]]) {
+            tal[t] = 1;
+            ++cnt[x[0]];
+            ++cnt[x[1]];
+            ++cnt[x[2]];
+        }
+    }
+    return peel(h.n, alive, cnt, [&](int32_t u, auto& dec) {
+        for (int64_t i = h.trp[u]; i < h.trp[u + 1]; ++i) {
+            const int64_t t = h.tinc[i];
+            if (!tal[t]) continue;
+            tal[t] = 0;
+            for (int j = 0; j < 3; ++j)
+                if (h.tri[3 * t + j] != u) dec(h.tri[3 * t + j]);
+        }
+    });
+}
+
+struct Cand {
+    std::vector<int32_t> vs;  // internal ids
+    Frac ub;                  // upper bound on the density of an LDS inside
+    int64_t seq = 0;          // insertion order: later first among equal bounds
+};
+struct CandLess {
+    bool operator()(const Cand& a, const Cand& b) const {
+        if (lt(a.ub, b.ub)) return true;
+        if (lt(b.ub, a.ub)) return false;
+        return a.seq < b.seq;
+    }
+};
+
+struct Ctx {
+    Graph* g = nullptr;
+    int mode = 2;
+    int iters = 0;
+    hipStream_t s = nullptr;
+    HostGraph h;
+    std::vector<Frac> lo, hi;     // bounds on phi_G, valid for every vertex
+    std::vector<int32_t> loc;     // scratch: internal id -> local index, -1 outside
+    std::vector<int32_t> mark;    // scratch, -1 outside
+    TopkStats* st = nullptr;
+    int64_t seq = 0;
+};
+
+// patterns of G[vs] by local index (edges: pairs, triangles: triples)
+void induced_patterns(Ctx& c, const std::vector<int32_t>& vs, std::vector<int32_t>& pat) {
+    const HostGraph& h = c.h;
+    pat.clear();
+    for (size_t i = 0; i < vs.size(); ++i) c.loc[vs[i]] = (int32_t)i;
+    if (c.mode == 2) {
+        for (size_t i = 0; i < vs.size(); ++i)
+            for (int64_t s = h.rp[vs[i]]; s < h.rp[vs[i] + 1]; ++s) {
+                const int32_t j = c.loc[h.col[s]];
+                if (j > (int32_t)i) {
+                    pat.push_back((int32_t)i);
+                    pat.push_back(j);
+                }
+            }
+    } else {
+        for (size_t i = 0; i < vs.size(); ++i)
+            for (int64_t q = h.trp[vs[i]]; q < h.trp[vs[i] + 1]; ++q) {
+                const int32_t* x = &h.tri[3 * h.tinc[q]];
+                const int32_t a = c.loc[x[0]], b = c.loc[x[1]], d = c.loc[x[2]];
+                if (a < 0 || b < 0 || d < 0) continue;
+                if (std::min(a, std::min(b, d)) != (int32_t)i) continue;  // count each triangle once
+                pat.push_back(a);
+                pat.push_back(b);
+                pat.push_back(d);
+            }
+    }
+    for (int32_t v : vs) c.loc[v] = -1;
+}
+
+// connected components (by edges) of G[vs]
+std::vector<std::vector<int32_t>> components(Ctx& c, const std::vector<int32_t>& vs) {
+    for (int32_t v : vs) c.mark[v] = 0;
+    std::vector<std::vector<int32_t>> out;
+    for (int32_t v0 : vs) {
+        if (c.mark[v0] != 0) continue;
+        std::vector<int32_t> comp{v0};
+        c.mark[v0] = 1;
+        for (size_t i = 0; i < comp.size(); ++i)
+            for (int64_t s = c.h.rp[comp[i]]; s < c.h.rp[comp[i] + 1]; ++s) {
+                const int32_t w = c.h.col[s];
+                if (c.mark[w] == 0) {
+                    c.mark[w] = 1;
+                    comp.push_back(w);
+                }
+            }
+        out.push_back(std::move(comp));
+    }
+    for (int32_t v : vs) c.mark[v] = -1;
+    return out;
+}
+
+// IsDensest: is G[vs] its own densest subgraph?  rho = density(G[vs]);
+// otherwise `denser` receives the maximal maximiser at lambda = rho, the
+// vertices whose compact number in G[vs] is above rho.
+bool is_densest(Ctx& c, const std::vector<int32_t>& vs, Frac* rho, std::vector<int32_t>* denser) {
+    std::vector<int32_t> pat;
+    induced_patterns(c, vs, pat);
+    const int64_t np = (int64_t)pat.size() / c.mode;
+    *rho = reduce(np, (int64_t)vs.size());
+    if (np == 0) return true;
+    std::vector<char> inX;
+    c.st->maxflows++;
+    if (max_excess((int64_t)vs.size(), c.mode, pat, rho->n, rho->d, inX) <= 0) return true;
+    denser->clear();
+    for (size_t i = 0; i < vs.size(); ++i)
+        if (inX[i]) denser->push_back(vs[i]);
+    return false;
+}
+
+// IsLDS (Alg. 4) for edges, IsLTDS (Alg. 7, ExtMaximal Alg. 8) for
+// triangles: is the connected, self-densest G[vs] of density rho a maximal
+// rho-compact connected subgraph of G?
+bool is_lds(Ctx& c, const std::vector<int32_t>& vs, const Frac& rho) {
+    const HostGraph& h = c.h;
+    // Every vertex of an LDS has compact number rho, and none of its
+    // neighbours has a larger one (Lemma lds-out-phi; Thm. cnltds for
+    // triangles).  A neighbour whose lower bound exceeds rho is in the
+    // maximal rho-compact region, so S would not be maximal: in Alg. 4 that
+    // is a self-loop inside S's component, which the proof of Thm. isLDS
+    // rules out; the flow network below leaves such vertices out, so the
+    // test is made here.
+    for (int32_t v : vs) {
+        if (lt(rho, c.lo[v]) || lt(c.hi[v], rho)) return false;
+        for (int64_t s = h.rp[v]; s < h.rp[v + 1]; ++s)
+            if (lt(rho, c.lo[h.col[s]])) return false;
+    }
+    std::vector<int32_t> U(vs.begin(), vs.end());
+    for (int32_t v : vs) c.mark[v] = 1;  // 1: in U
+    bool need_flow = false;
+    std::vector<int32_t> loops;  // edges: one self-loop per edge to a vertex whose lower bound exceeds rho
+    std::vector<int32_t> P;      // triangles: truncated patterns, -1 padded
+    std::vector<char> tvis;
+    if (c.mode == 3) tvis.assign(h.tri.size() / 3, 0);
+    for (size_t qi = 0; qi < U.size(); ++qi) {
+        const int32_t v = U[qi];
+        if (c.mode == 3) {
+            for (int64_t i = h.trp[v]; i < h.trp[v + 1]; ++i) {
+                const int64_t t = h.tinc[i];
+                if (tvis[t]) continue;
+                tvis[t] = 1;
+                const int32_t* x = &h.tri[3 * t];
+                if (lt(c.hi[x[0]], rho) || lt(c.hi[x[1]], rho) || lt(c.hi[x[2]], rho)) continue;  // not valid
+                int32_t M[3] = {-1, -1, -1};
+                int nm = 0;
+                for (int j = 0; j < 3; ++j) {
+                    const int32_t w = x[j];
+                    if (!lt(rho, c.lo[w])) {  // lower bound <= rho
+                        M[nm++] = w;
+                        if (c.mark[w] != 1) {
+                            c.mark[w] = 1;
+                            U.push_back(w);
+                        }
+                    } else {
+                        need_flow = true;
+                    }
+                }
+                if (nm > 0) P.insert(P.end(), M, M + 3);
+            }
+        }
+        for (int64_t s = h.rp[v]; s < h.rp[v + 1]; ++s) {
+            const int32_t w = h.col[s];
+            if (c.mark[w] == 1) continue;
+            if (lt(rho, c.lo[w])) {
+                need_flow = true;
+                if (c.mode == 2) loops.push_back(v);
+            } else if (!lt(c.hi[w], rho)) {  // lower <= rho <= upper
+                c.mark[w] = 1;
+                U.push_back(w);
+            }
+        }
+    }
+    bool ok = true;
+    if (need_flow) {
+        for (size_t i = 0; i < U.size(); ++i) c.loc[U[i]] = (int32_t)i;
+        std::vector<int32_t> pat;
+        if (c.mode == 2) {
+            for (size_t i = 0; i < U.size(); ++i)
+                for (int64_t s = h.rp[U[i]]; s < h.rp[U[i] + 1]; ++s) {
+                    const int32_t j = c.loc[h.col[s]];
+                    if (j > (int32_t)i) {
+                        pat.push_back((int32_t)i);
+                        pat.push_back(j);
+                    }
+                }
+            for (int32_t v : loops) {
+                pat.push_back(c.loc[v]);
+                pat.push_back(-1);
+            }
+        } else {
+            pat.resize(P.size());
+            for (size_t i = 0; i < P.size(); ++i) pat[i] = P[i] >= 0 ? c.loc[P[i]] : -1;
+        }
+        std::vector<char> inX;
+        c.st->maxflows++;
+        max_excess((int64_t)U.size(), c.mode, pat, rho.n, rho.d, inX);
+        // G[vs] must be a connected component of G[X] (no vertex of S has a
+        // self-loop: checked above)
+        for (int32_t v : vs)
+            if (!inX[c.loc[v]]) ok = false;
+        if (ok) {
+            for (int32_t v : vs) c.mark[v] = 2;
+            for (int32_t v : vs)
+                for (int64_t s = h.rp[v]; s < h.rp[v + 1] && ok; ++s) {
+                    const int32_t w = h.col[s];
+                    if (c.mark[w] == 1 && inX[c.loc[w]]) ok = false;
+                }
+        }
+        for (int32_t v : U) c.loc[v] = -1;
+    }
+    for (int32_t v : U) c.mark[v] = -1;
+    return ok;
+}
+
+// largest upper bound on phi_G over vs, capped by `cap`
+Frac bound_of(const Ctx& c, const std::vector<int32_t>& vs, const Frac* cap) {
+    Frac b{0, 1};
+    for (int32_t v : vs)
+        if (lt(b, c.hi[v])) b = c.hi[v];
+    if (cap && lt(*cap, b)) b = *cap;
+    return b;
+}
+
+// stable groups of the last FW run on graph `gg` as candidate vertex sets;
+// map(j) turns gg's internal id into an internal id of the input graph
+template <class Map>
+void collect_groups(Graph& gg, int mode, int iters, hipStream_t s, Map map, std::vector<std::vector<int32_t>>& sets,
+                    std::vector<Frac>& his, std::vector<Frac>* los_per_set) {
+    const SgState& q = gg.sg[mode == 2 ? 0 : 1];
+    const int64_t k = gg.n;
+    std::vector<int32_t> order(k);
+    std::vector<int64_t> lo(k), hi(k);
+    if (k > 0) {
+        LDS_HIP(hipMemcpyAsync(order.data(), q.order.p, k * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        LDS_HIP(hipMemcpyAsync(lo.data(), q.lo.p, k * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        LDS_HIP(hipMemcpyAsync(hi.data(), q.hi.p, k * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        LDS_HIP(hipStreamSynchronize(s));
+    }
+    const int64_t D = (int64_t)fw_denom(mode, iters);
+    int64_t covered = 0;
+    for (size_t gi = 0; gi < q.gstart.size(); ++gi) {
+        std::vector<int32_t> vs;
+        for (int64_t j = q.gstart[gi]; j < q.gend[gi]; ++j) vs.push_back(map(order[j]));
+        const int32_t first = order[q.gstart[gi]];
+        his.push_back(reduce(hi[first], D));
+        if (los_per_set) los_per_set->push_back(reduce(lo[first], D));
+        sets.push_back(std::move(vs));
+        covered = q.gend[gi];
+    }
+    if (covered < k) {  // never-accepted remainder: no bounds
+        std::vector<int32_t> vs;
+        for (int64_t j = covered; j < k; ++j) vs.push_back(map(order[j]));
+        his.push_back(Frac{-1, 1});
+        if (los_per_set) los_per_set->push_back(Frac{-1, 1});
+        sets.push_back(std::move(vs));
+    }
+}
+
+// FW + ExtractSG on G[vs]: the stable groups of the induced subgraph
+void refine(Ctx& c, const std::vector<int32_t>& vs, std::vector<std::vector<int32_t>>& sets, std::vector<Frac>& his) {
+    // local ids follow caller-id order, so FW breaks ties as on the whole graph
+    std::vector<int32_t> sv = vs;
+    std::sort(sv.begin(), sv.end(), [&](int32_t a, int32_t b) { return c.h.orig[a] < c.h.orig[b]; });
+    std::vector<int32_t> src, dst;
+    for (size_t i = 0; i < sv.size(); ++i) c.loc[sv[i]] = (int32_t)i;
+    for (size_t i = 0; i < sv.size(); ++i)
+        for (int64_t s = c.h.rp[sv[i]]; s < c.h.rp[sv[i] + 1]; ++s) {
+            const int32_t j = c.loc[c.h.col[s]];
+            if (j > (int32_t)i) {
+                src.push_back((int32_t)i);
+                dst.push_back(j);
+            }
+        }
+    for (int32_t v : sv) c.loc[v] = -1;
+    Graph sub;
+    build_graph(sub, (int64_t)sv.size(), (int64_t)src.size(), src.data(), dst.data(), false, false, c.s);
+    fw_run(sub, c.mode, c.iters, false, c.s);
+    sg_stable_groups(sub, c.mode, c.s);
+    std::vector<int32_t> orig(sub.n);
+    if (sub.n > 0) {
+        LDS_HIP(hipMemcpyAsync(orig.data(), sub.orig_of.p, sub.n * sizeof(int32_t), hipMemcpyDeviceToHost, c.s));
+        LDS_HIP(hipStreamSynchronize(c.s));
+    }
+    collect_groups(sub, c.mode, c.iters, c.s, [&](int32_t j) { return sv[orig[j]]; }, sets, his, nullptr);
+    c.st->refinements++;
+}
+
+}  // namespace
+
+void topk_run(Graph& g, int mode, int k, int iters, hipStream_t s, std::vector<TopkSet>& out, TopkStats& st) {
+    LDS_CHECK(mode == 2 || mode == 3, ST_INVALID, "mode must be LDS_EDGE or LDS_TRIANGLE");
+    LDS_CHECK(k >= 1, ST_INVALID, "k must be >= 1");
+    LDS_CHECK(iters >= 0, ST_INVALID, "iters must be >= 0");
+    out.clear();
+    st = TopkStats{};
+    const int64_t n = g.n;
+    if (n == 0) return;
+    if (mode == 3 && g.T < 0) list_triangles(g, s);
+    Ctx c;
+    c.g = &g;
+    c.mode = mode;
+    c.iters = iters;
+    c.s = s;
+    c.st = &st;
+    c.h.load(g, mode, s);
+    c.loc.assign(n, -1);
+    c.mark.assign(n, -1);
+    std::vector<char> alive(n, 1);
+    // bounds from core (tr-core) numbers
+    {
+        const std::vector<int32_t> core = (mode == 2) ? core_numbers(c.h, alive) : trcore_numbers(c.h, alive);
+        c.lo.resize(n);
+        c.hi.resize(n);
+        for (int64_t u = 0; u < n; ++u) {
+            c.lo[u] = reduce(core[u], mode);
+            c.hi[u] = Frac{core[u], 1};
+        }
+    }
+    // FW + ExtractSG on the whole graph; group bounds tighten the core bounds
+    fw_run(g, mode, iters, false, s);
+    sg_stable_groups(g, mode, s);
+    std::vector<std::vector<int32_t>> sets;
+    std::vector<Frac> his, los;
+    collect_groups(g, mode, iters, s, [](int32_t j) { return j; }, sets, his, &los);
+    for (size_t i = 0; i < sets.size(); ++i) {
+        if (his[i].n < 0) continue;  // remainder without bounds
+        for (int32_t u : sets[i]) {
+            if (lt(c.lo[u], los[i])) c.lo[u] = los[i];
+            if (lt(his[i], c.hi[u])) c.hi[u] = his[i];
+        }
+    }
+    // Pruning (Alg. 3): rule 1, then rule 2 on the residual graph
+    for (int64_t u = 0; u < n; ++u)
+        for (int64_t e = c.h.rp[u]; e < c.h.rp[u + 1]; ++e)
+            if (lt(c.hi[u], c.lo[c.h.col[e]])) {
+                alive[u] = 0;
+                break;
+            }
+    for (;;) {
+        const std::vector<int32_t> cr = (mode == 2) ? core_numbers(c.h, alive) : trcore_numbers(c.h, alive);
+        bool changed = false;
+        for (int64_t u = 0; u < n; ++u)
+            if (alive[u] && lt(Frac{cr[u], 1}, c.lo[u])) {
+                alive[u] = 0;
+                changed = true;
+            }
+        if (!changed) break;
+    }
+    for (int64_t u = 0; u < n; ++u) st.pruned += alive[u] ? 0 : 1;
+    std::priority_queue<Cand, std::vector<Cand>, CandLess> pq;
+    auto push = [&](std::vector<int32_t>&& vs, const Frac* cap) {
+        if (vs.empty()) return;
+        Cand cd;
+        cd.ub = bound_of(c, vs, cap);
+        cd.vs = std::move(vs);
+        cd.seq = c.seq++;
+        pq.push(std::move(cd));
+    };
+    for (size_t i = 0; i < sets.size(); ++i) {
+        std::vector<int32_t> vs;
+        for (int32_t u : sets[i])
+            if (alive[u]) vs.push_back(u);
+        push(std::move(vs), his[i].n >= 0 ? &his[i] : nullptr);
+    }
+    std::vector<std::pair<Frac, std::vector<int32_t>>> found;
+    std::vector<Frac> dens;  // densities found, for the k-th largest
+    while (!pq.empty()) {
+        Cand cd = std::move(const_cast<Cand&>(pq.top()));
+        pq.pop();
+        st.popped++;
+        if ((int)dens.size() >= k) {
+            std::nth_element(dens.begin(), dens.begin() + (k - 1), dens.end(),
+                             [](const Frac& a, const Frac& b) { return lt(b, a); });
+            if (lt(cd.ub, dens[k - 1])) break;  // no remaining candidate reaches the k-th density
+        }
+        if (cd.ub.n <= 0) break;  // an LDS has positive density
+        std::vector<std::vector<int32_t>> comps = components(c, cd.vs);
+        if (comps.size() > 1) {
+            for (auto& cc : comps) push(std::move(cc), &cd.ub);
+            continue;
+        }
+        Frac rho;
+        std::vector<int32_t> denser;
+        if (is_densest(c, cd.vs, &rho, &denser)) {
+            if (rho.n > 0 && is_lds(c, cd.vs, rho)) {
+                found.push_back({rho, cd.vs});
+                dens.push_back(rho);
+            }
+            continue;
+        }
+        std::vector<std::vector<int32_t>> parts;
+        std::vector<Frac> phis;
+        refine(c, cd.vs, parts, phis);
+        if (parts.size() >= 2) {
+            for (size_t i = 0; i < parts.size(); ++i) {
+                Frac cap = cd.ub;
+                if (phis[i].n >= 0 && lt(phis[i], cap)) cap = phis[i];
+                push(std::move(parts[i]), &cap);
+            }
+            continue;
+        }
+        // FW did not split G[S]: split by the min cut's denser vertex set
+        st.flow_splits++;
+        std::sort(denser.begin(), denser.end());
+        std::vector<int32_t> top, rest;
+        for (int32_t v : cd.vs) (std::binary_search(denser.begin(), denser.end(), v) ? top : rest).push_back(v);
+        push(std::move(rest), &cd.ub);
+        push(std::move(top), &cd.ub);
+    }
+    for (auto& f : found) {
+        TopkSet t;
+        t.num = f.first.n;
+        t.den = f.first.d;
+        for (int32_t v : f.second) t.vertices.push_back(c.h.orig[v]);
+        std::sort(t.vertices.begin(), t.vertices.end());
+        out.push_back(std::move(t));
+    }
+    std::sort(out.begin(), out.end(), [](const TopkSet& a, const TopkSet& b) {
+        const i128 l = (i128)a.num * b.den, r = (i128)b.num * a.den;
+        if (l != r) return l > r;
+        return a.vertices.front() < b.vertices.front();
+    });
+    if ((int64_t)out.size() > k) out.resize(k);
+}
+
+}  // namespace lds

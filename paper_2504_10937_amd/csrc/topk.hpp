@@ -1,0 +1,37 @@
+// Host side of the top-k LDS / LTDS driver (Alg. 5 and its triangle version).
+#pragma once
+#include <vector>
+
+#include "graph.hpp"
+
+namespace lds {
+
+// Host copy of the adjacency (internal ids) and, for triangles, the triangle
+// list with per-vertex incidence lists.
+struct HostGraph {
+    int64_t n = 0;
+    std::vector<int64_t> rp;    // n + 1
+    std::vector<int32_t> col;   // 2m neighbours
+    std::vector<int32_t> orig;  // internal -> caller id
+    std::vector<int32_t> tri;   // 3T (triangles only)
+    std::vector<int64_t> trp;   // n + 1 offsets into tinc
+    std::vector<int64_t> tinc;  // triangle indices incident to each vertex
+    void load(const Graph& g, int mode, hipStream_t s);
+};
+
+struct TopkSet {
+    int64_t num = 0, den = 1;        // reduced exact density
+    std::vector<int32_t> vertices;   // caller ids, ascending
+};
+
+struct TopkStats {
+    int64_t popped = 0;       // candidates taken from the queue
+    int64_t refinements = 0;  // FW + ExtractSG runs on induced subgraphs
+    int64_t flow_splits = 0;  // candidates split by the min cut instead
+    int64_t maxflows = 0;     // min-cut computations (IsDensest + IsLDS)
+    int64_t pruned = 0;       // vertices removed by the two pruning rules
+};
+
+void topk_run(Graph& g, int mode, int k, int iters, hipStream_t s, std::vector<TopkSet>& out, TopkStats& st);
+
+}  // namespace lds

@@ -48,3 +48,14 @@ def test_missing_library_fails_loudly(tmp_path, monkeypatch):
     monkeypatch.setattr(lds, "LIB_PATH", str(tmp_path / "nope.so"))
     with pytest.raises(ImportError):
         lds.load()
+
+
+def test_topk_host_side_errors():
+    import ctypes
+    import paper_2504_10937_amd as lds
+    L = lds.load()
+    r = lds._Result()
+    assert L.lds_topk(None, lds.LDS_EDGE, 3, 10, ctypes.byref(r), None) == 1
+    assert r.count == 0 and not r.offsets
+    L.lds_result_free(ctypes.byref(r))
+    L.lds_result_free(None)
