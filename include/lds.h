@@ -166,7 +166,9 @@ uint64_t lds_denominator(lds_mode mode, int32_t iters);
  * descending, ties by smallest caller id ascending.  The stats fields report
  * the work of the search: candidates taken, FW + ExtractSG runs on induced
  * subgraphs, candidates split by a min cut, min-cut computations and
- * vertices removed by the pruning rules. */
+ * vertices removed by the pruning rules; the ms fields the wall-clock time of
+ * the phases (host copy of the graph, core numbers, first FW + ExtractSG,
+ * pruning, candidate search). */
 typedef struct {
     int32_t count;
     int64_t* offsets;   /* count + 1 */
@@ -174,6 +176,7 @@ typedef struct {
     int64_t* dens_num;  /* count */
     int64_t* dens_den;  /* count */
     int64_t popped, refinements, flow_splits, maxflows, pruned;
+    double ms_copy, ms_core, ms_fw, ms_prune, ms_search;  /* wall-clock phases */
 } lds_result;
 
 /* Top-k LDS (Problem LDS, Section 3; mode LDS_EDGE) or LTDS (Problem LTDS,

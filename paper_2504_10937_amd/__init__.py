@@ -240,7 +240,8 @@ class _Result(ctypes.Structure):
                 ("vertices", ctypes.POINTER(ctypes.c_int32)), ("dens_num", ctypes.POINTER(ctypes.c_int64)),
                 ("dens_den", ctypes.POINTER(ctypes.c_int64)), ("popped", ctypes.c_int64),
                 ("refinements", ctypes.c_int64), ("flow_splits", ctypes.c_int64), ("maxflows", ctypes.c_int64),
-                ("pruned", ctypes.c_int64)]
+                ("pruned", ctypes.c_int64), ("ms_copy", ctypes.c_double), ("ms_core", ctypes.c_double),
+                ("ms_fw", ctypes.c_double), ("ms_prune", ctypes.c_double), ("ms_search", ctypes.c_double)]
 
 
 def lds_topk(g, mode, k, iters, stream=None, with_stats=False):
@@ -257,7 +258,8 @@ def lds_topk(g, mode, k, iters, stream=None, with_stats=False):
             allv = np.ctypeslib.as_array(r.vertices, shape=(max(int(off[-1]), 1),))[:int(off[-1])].copy()
             for i in range(r.count):
                 out.append((allv[off[i]:off[i + 1]].copy(), Fraction(int(r.dens_num[i]), int(r.dens_den[i]))))
-        stats = {f: getattr(r, f) for f in ("popped", "refinements", "flow_splits", "maxflows", "pruned")}
+        stats = {f: getattr(r, f) for f in ("popped", "refinements", "flow_splits", "maxflows", "pruned",
+                                              "ms_copy", "ms_core", "ms_fw", "ms_prune", "ms_search")}
     finally:
         L.lds_result_free(ctypes.byref(r))
     return (out, stats) if with_stats else out

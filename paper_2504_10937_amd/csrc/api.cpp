@@ -333,6 +333,11 @@ lds_status lds_topk(lds_graph g, lds_mode mode, int32_t k, int32_t iters, lds_re
     r.flow_splits = st.flow_splits;
     r.maxflows = st.maxflows;
     r.pruned = st.pruned;
+    r.ms_copy = st.ms_copy;
+    r.ms_core = st.ms_core;
+    r.ms_fw = st.ms_fw;
+    r.ms_prune = st.ms_prune;
+    r.ms_search = st.ms_search;
     *out = r;
     API_CATCH
 }

@@ -27,7 +27,9 @@
 //  * The search ends when the best remaining upper bound is below the k-th
 //    density found; results are sorted by (density desc, smallest caller id).
 #include <algorithm>
-#include <deque>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <queue>
 
 #include "topk.hpp"
@@ -56,81 +58,156 @@ inline Frac reduce(int64_t n, int64_t d) {
 }
 
 // ------------------------------------------------------------ max flow
-// Dinic's algorithm on int64 capacities.
+// Network with arcs in CSR order (arcs of a node are contiguous, each with
+// the index of its reverse arc).  Arcs are collected with arc() and laid out
+// by finalize().
 struct Flow {
-    std::vector<int64_t> head, nxt, to, cap, level, it;
-    explicit Flow(int64_t nodes) : head(nodes, -1), level(nodes), it(nodes) {}
-    void arc(int64_t a, int64_t b, int64_t c) {
-        to.push_back(b); cap.push_back(c); nxt.push_back(head[a]); head[a] = (int64_t)to.size() - 1;
-        to.push_back(a); cap.push_back(0); nxt.push_back(head[b]); head[b] = (int64_t)to.size() - 1;
+    int64_t N;
+    std::vector<int64_t> pa, pb, pc, pd;  // pending arcs: tail, head, capacity, reverse capacity
+    std::vector<int64_t> first, cap, rev;
+    std::vector<int32_t> to;
+    explicit Flow(int64_t nodes) : N(nodes) {}
+    void reserve(size_t arcs) {
+        pa.reserve(arcs);
+        pb.reserve(arcs);
+        pc.reserve(arcs);
+        pd.reserve(arcs);
     }
-    bool bfs(int64_t s, int64_t t) {
-        std::fill(level.begin(), level.end(), -1);
-        std::deque<int64_t> q;
-        level[s] = 0;
-        q.push_back(s);
-        while (!q.empty()) {
-            const int64_t x = q.front();
-            q.pop_front();
-            for (int64_t e = head[x]; e >= 0; e = nxt[e])
-                if (cap[e] > 0 && level[to[e]] < 0) {
-                    level[to[e]] = level[x] + 1;
-                    q.push_back(to[e]);
-                }
+    // arc a -> b of capacity c, paired with b -> a of capacity c_back
+    void arc(int64_t a, int64_t b, int64_t c, int64_t c_back = 0) {
+        pa.push_back(a);
+        pb.push_back(b);
+        pc.push_back(c);
+        pd.push_back(c_back);
+    }
+    void finalize() {
+        const size_t m = pa.size();
+        first.assign(N + 1, 0);
+        for (size_t i = 0; i < m; ++i) {
+            first[pa[i] + 1]++;
+            first[pb[i] + 1]++;
         }
-        return level[t] >= 0;
-    }
-    // one augmenting path in the level graph (iterative), 0 when blocked
-    int64_t augment(int64_t s, int64_t t, std::vector<int64_t>& path) {
-        path.clear();
-        int64_t x = s;
-        for (;;) {
-            if (x == t) {
-                int64_t f = INT64_MAX;
-                for (int64_t e : path) f = std::min(f, cap[e]);
-                for (int64_t e : path) {
-                    cap[e] -= f;
-                    cap[e ^ 1] += f;
-                }
-                return f;
-            }
-            int64_t& e = it[x];
-            while (e >= 0 && !(cap[e] > 0 && level[to[e]] == level[x] + 1)) e = nxt[e];
-            if (e >= 0) {
-                path.push_back(e);
-                x = to[e];
-                continue;
-            }
-            if (path.empty()) return 0;  // s is blocked
-            level[x] = -1;               // dead end: retreat
-            const int64_t back = path.back();
-            path.pop_back();
-            x = to[back ^ 1];
-            it[x] = nxt[it[x]];
+        for (int64_t v = 0; v < N; ++v) first[v + 1] += first[v];
+        std::vector<int64_t> fill(first.begin(), first.end() - 1);
+        to.resize(2 * m);
+        cap.resize(2 * m);
+        rev.resize(2 * m);
+        for (size_t i = 0; i < m; ++i) {
+            const int64_t x = fill[pa[i]]++, y = fill[pb[i]]++;
+            to[x] = (int32_t)pb[i];
+            cap[x] = pc[i];
+            rev[x] = y;
+            to[y] = (int32_t)pa[i];
+            cap[y] = pd[i];
+            rev[y] = x;
         }
+        std::vector<int64_t>().swap(pa);
+        std::vector<int64_t>().swap(pb);
+        std::vector<int64_t>().swap(pc);
+        std::vector<int64_t>().swap(pd);
     }
+    // Maximum preflow by push-relabel (Goldberg and Tarjan), first phase
+    // only, highest-label selection, exact distance labels recomputed by a
+    // backward BFS from t at the start and after every N relabels.  Returns
+    // the flow into t; the minimum cut follows from the residual graph
+    // exactly as after a maximum flow (maximal_source_side).
     int64_t maxflow(int64_t s, int64_t t) {
-        int64_t f = 0;
-        std::vector<int64_t> path;
-        while (bfs(s, t)) {
-            it = head;
-            for (int64_t p; (p = augment(s, t, path)) > 0;) f += p;
+        finalize();
+        std::vector<int64_t> h(N, 0), ex(N, 0), it(first.begin(), first.end() - 1);
+        std::vector<std::vector<int64_t>> bucket(N);
+        int64_t top = -1;
+        std::vector<int64_t> q;
+        q.reserve(N);
+        auto global_relabel = [&]() {
+            std::fill(h.begin(), h.end(), N);
+            h[t] = 0;
+            q.clear();
+            q.push_back(t);
+            for (size_t qi = 0; qi < q.size(); ++qi) {
+                const int64_t y = q[qi];
+                for (int64_t e = first[y]; e < first[y + 1]; ++e) {
+                    const int64_t x = to[e];
+                    if (h[x] == N && x != s && cap[rev[e]] > 0) {
+                        h[x] = h[y] + 1;
+                        q.push_back(x);
+                    }
+                }
+            }
+            for (auto& b : bucket) b.clear();
+            top = -1;
+            for (int64_t v = 0; v < N; ++v)
+                if (v != s && v != t && ex[v] > 0 && h[v] < N) {
+                    bucket[h[v]].push_back(v);
+                    top = std::max(top, h[v]);
+                }
+            std::copy(first.begin(), first.end() - 1, it.begin());
+        };
+        h[s] = N;
+        for (int64_t e = first[s]; e < first[s + 1]; ++e)
+            if (cap[e] > 0) {
+                const int64_t d = cap[e];
+                cap[e] = 0;
+                cap[rev[e]] += d;
+                ex[to[e]] += d;
+            }
+        global_relabel();
+        int64_t relabels = 0;
+        for (;;) {
+            while (top >= 0 && bucket[top].empty()) --top;
+            if (top < 0) break;
+            const int64_t v = bucket[top].back();
+            bucket[top].pop_back();
+            if (h[v] != top || ex[v] == 0) continue;
+            // discharge v
+            const int64_t end = first[v + 1];
+            while (ex[v] > 0) {
+                int64_t& e = it[v];
+                for (; e < end; ++e) {
+                    const int64_t w = to[e];
+                    if (cap[e] > 0 && h[v] == h[w] + 1) {
+                        const int64_t d = std::min(ex[v], cap[e]);
+                        cap[e] -= d;
+                        cap[rev[e]] += d;
+                        ex[v] -= d;
+                        if (ex[w] == 0 && w != t) {
+                            bucket[h[w]].push_back(w);  // v may have been relabelled above top
+                            top = std::max(top, h[w]);
+                        }
+                        ex[w] += d;
+                        if (ex[v] == 0) break;
+                    }
+                }
+                if (ex[v] == 0) break;
+                int64_t mh = 2 * N;
+                for (int64_t e2 = first[v]; e2 < end; ++e2)
+                    if (cap[e2] > 0) mh = std::min(mh, h[to[e2]]);
+                h[v] = mh + 1;
+                it[v] = first[v];
+                ++relabels;
+                if (h[v] >= N) break;  // cannot reach t any more
+            }
+            if (ex[v] > 0 && h[v] < N) {
+                bucket[h[v]].push_back(v);
+                top = std::max(top, h[v]);
+            }
+            if (relabels >= N) {
+                global_relabel();
+                relabels = 0;
+            }
         }
-        return f;
+        return ex[t];
     }
     // after maxflow: 1 for nodes on the source side of the minimum cut with
     // the largest source side (nodes that cannot reach t in the residual)
     std::vector<char> maximal_source_side(int64_t t) const {
-        std::vector<char> src(head.size(), 1);
-        std::deque<int64_t> q;
+        std::vector<char> src(N, 1);
+        std::vector<int64_t> q{t};
         src[t] = 0;
-        q.push_back(t);
-        while (!q.empty()) {
-            const int64_t y = q.front();
-            q.pop_front();
-            for (int64_t e = head[y]; e >= 0; e = nxt[e]) {
+        for (size_t qi = 0; qi < q.size(); ++qi) {
+            const int64_t y = q[qi];
+            for (int64_t e = first[y]; e < first[y + 1]; ++e) {
                 const int64_t x = to[e];
-                if (src[x] && cap[e ^ 1] > 0) {  // residual arc x -> y
+                if (src[x] && cap[rev[e]] > 0) {  // residual arc x -> y
                     src[x] = 0;
                     q.push_back(x);
                 }
@@ -140,7 +217,36 @@ struct Flow {
     }
 };
 
-// Maximal X ⊆ {0..k-1} maximising q * #patterns inside X - p * |X| (a pattern
+// Edges: maximal X ⊆ {0..k-1} maximising q * (|E(X)| + loops(X)) - p * |X|
+// on Goldberg's network: source -> v (capacity q * (deg v + 2 loops v)),
+// v -> sink (2p), each edge an undirected arc of capacity q.  The cut of X
+// is q * sum_v (deg v + 2 loops v) - 2 * (the objective), so the maximal
+// source side of a minimum cut is the maximal maximiser.  pairs: 2 local ids
+// per edge; loops[v]: self-loops at v.  Returns the maximum value.
+int64_t max_excess_edges(int64_t k, const std::vector<int32_t>& pairs, const std::vector<int64_t>& loops, int64_t p,
+                         int64_t q, std::vector<char>& inX) {
+    const int64_t ne = (int64_t)pairs.size() / 2;
+    std::vector<int64_t> w(k, 0);
+    for (int64_t v = 0; v < k; ++v) w[v] = loops.empty() ? 0 : 2 * loops[v];
+    for (int64_t i = 0; i < 2 * ne; ++i) w[pairs[i]]++;
+    const int64_t S = k, T = k + 1;
+    Flow f(k + 2);
+    f.reserve((size_t)(ne + 2 * k));
+    int64_t total = 0;
+    for (int64_t v = 0; v < k; ++v) {
+        if (w[v] > 0) f.arc(S, v, q * w[v]);
+        f.arc(v, T, 2 * p);
+        total += q * w[v];
+    }
+    for (int64_t i = 0; i < ne; ++i) f.arc(pairs[2 * i], pairs[2 * i + 1], q, q);
+    const int64_t flow = f.maxflow(S, T);
+    const std::vector<char> side = f.maximal_source_side(T);
+    inX.assign(k, 0);
+    for (int64_t v = 0; v < k; ++v) inX[v] = side[v];
+    return (total - flow) / 2;
+}
+
+// Triangles: maximal X ⊆ {0..k-1} maximising q * #patterns inside X - p * |X| (a pattern
 // is inside X when all its members are; -1 pads patterns with fewer than h
 // members, a one-member pattern is a self-loop).  Network: source -> pattern
 // (capacity q), pattern -> member (unbounded), vertex -> sink (p).  Returns
@@ -197,36 +303,57 @@ void HostGraph::load(const Graph& g, int mode, hipStream_t s) {
 
 namespace {
 
-// Peeling with a lazy bucket queue: repeatedly remove a vertex of minimum
-// count; its core number is the largest minimum met so far.  each(u, dec)
-// calls dec(v) once per unit that removing u takes from v's count.
+// Peeling in the bin-sort form of Batagelj and Zaversnik: vertices sit in
+// an array sorted by count, bin[c] is the first position with count c;
+// removing the vertex of minimum count v lowers each affected vertex u with
+// cnt[u] > cnt[v] by one (a swap to the front of its bin).  core[v] is cnt[v]
+// when v is removed.  each(v, dec) calls dec(u) once per unit that removing v
+// takes from u's count.
 template <class Each>
 std::vector<int32_t> peel(int64_t n, const std::vector<char>& alive, std::vector<int32_t>& cnt, Each each) {
     std::vector<int32_t> core(n, 0);
     int32_t mx = 0;
+    int64_t na = 0;
     for (int64_t u = 0; u < n; ++u)
-        if (alive[u]) mx = std::max(mx, cnt[u]);
-    std::vector<std::vector<int32_t>> bucket((size_t)mx + 1);
+        if (alive[u]) {
+            mx = std::max(mx, cnt[u]);
+            ++na;
+        }
+    std::vector<int64_t> bin((size_t)mx + 2, 0), pos(n, -1);
+    std::vector<int32_t> vert((size_t)na);
     for (int64_t u = 0; u < n; ++u)
-        if (alive[u]) bucket[cnt[u]].push_back((int32_t)u);
+        if (alive[u]) bin[cnt[u] + 1]++;
+    for (int32_t c = 0; c <= mx; ++c) bin[c + 1] += bin[c];
+    {
+        std::vector<int64_t> fill(bin.begin(), bin.end() - 1);
+        for (int64_t u = 0; u < n; ++u)
+            if (alive[u]) {
+                pos[u] = fill[cnt[u]]++;
+                vert[pos[u]] = (int32_t)u;
+            }
+    }
     std::vector<char> done(n, 0);
-    int32_t cur = 0, k = 0;
-    auto dec = [&](int32_t v) {
-        if (!alive[v] || done[v]) return;
-        --cnt[v];
-        bucket[cnt[v]].push_back(v);
-        if (cnt[v] < cur) cur = cnt[v];
+    int32_t cv = 0;
+    auto dec = [&](int32_t u) {
+        if (!alive[u] || done[u] || cnt[u] <= cv) return;
+        const int32_t du = cnt[u];
+        const int64_t pu = pos[u], pw = bin[du];
+        const int32_t w = vert[pw];
+        if (u != w) {
+            vert[pu] = w;
+            pos[w] = pu;
+            vert[pw] = u;
+            pos[u] = pw;
+        }
+        bin[du]++;
+        cnt[u]--;
     };
-    for (;;) {
-        while (cur <= mx && bucket[cur].empty()) ++cur;
-        if (cur > mx) break;
-        const int32_t u = bucket[cur].back();
-        bucket[cur].pop_back();
-        if (done[u] || cnt[u] != cur) continue;  // stale entry
-        done[u] = 1;
-        k = std::max(k, cur);
-        core[u] = k;
-        each(u, dec);
+    for (int64_t i = 0; i < na; ++i) {
+        const int32_t v = vert[i];
+        cv = cnt[v];
+        core[v] = cv;
+        done[v] = 1;
+        each(v, dec);
     }
     return core;
 }
@@ -355,7 +482,9 @@ bool is_densest(Ctx& c, const std::vector<int32_t>& vs, Frac* rho, std::vector<i
     if (np == 0) return true;
     std::vector<char> inX;
     c.st->maxflows++;
-    if (max_excess((int64_t)vs.size(), c.mode, pat, rho->n, rho->d, inX) <= 0) return true;
+    const int64_t val = (c.mode == 2) ? max_excess_edges((int64_t)vs.size(), pat, {}, rho->n, rho->d, inX)
+                                      : max_excess((int64_t)vs.size(), 3, pat, rho->n, rho->d, inX);
+    if (val <= 0) return true;
     denser->clear();
     for (size_t i = 0; i < vs.size(); ++i)
         if (inX[i]) denser->push_back(vs[i]);
@@ -437,17 +566,19 @@ bool is_lds(Ctx& c, const std::vector<int32_t>& vs, const Frac& rho) {
                         pat.push_back(j);
                     }
                 }
-            for (int32_t v : loops) {
-                pat.push_back(c.loc[v]);
-                pat.push_back(-1);
-            }
         } else {
             pat.resize(P.size());
             for (size_t i = 0; i < P.size(); ++i) pat[i] = P[i] >= 0 ? c.loc[P[i]] : -1;
         }
         std::vector<char> inX;
         c.st->maxflows++;
-        max_excess((int64_t)U.size(), c.mode, pat, rho.n, rho.d, inX);
+        if (c.mode == 2) {
+            std::vector<int64_t> nloop(U.size(), 0);
+            for (int32_t v : loops) nloop[c.loc[v]]++;
+            max_excess_edges((int64_t)U.size(), pat, nloop, rho.n, rho.d, inX);
+        } else {
+            max_excess((int64_t)U.size(), 3, pat, rho.n, rho.d, inX);
+        }
         // G[vs] must be a connected component of G[X] (no vertex of S has a
         // self-loop: checked above)
         for (int32_t v : vs)
@@ -547,6 +678,12 @@ void topk_run(Graph& g, int mode, int k, int iters, hipStream_t s, std::vector<T
     LDS_CHECK(iters >= 0, ST_INVALID, "iters must be >= 0");
     out.clear();
     st = TopkStats{};
+    auto t0 = std::chrono::steady_clock::now();
+    auto lap = [&t0](double* acc) {
+        const auto t1 = std::chrono::steady_clock::now();
+        *acc += std::chrono::duration<double, std::milli>(t1 - t0).count();
+        t0 = t1;
+    };
     const int64_t n = g.n;
     if (n == 0) return;
     if (mode == 3 && g.T < 0) list_triangles(g, s);
@@ -560,6 +697,7 @@ void topk_run(Graph& g, int mode, int k, int iters, hipStream_t s, std::vector<T
     c.loc.assign(n, -1);
     c.mark.assign(n, -1);
     std::vector<char> alive(n, 1);
+    lap(&st.ms_copy);
     // bounds from core (tr-core) numbers
     {
         const std::vector<int32_t> core = (mode == 2) ? core_numbers(c.h, alive) : trcore_numbers(c.h, alive);
@@ -570,6 +708,7 @@ void topk_run(Graph& g, int mode, int k, int iters, hipStream_t s, std::vector<T
             c.hi[u] = Frac{core[u], 1};
         }
     }
+    lap(&st.ms_core);
     // FW + ExtractSG on the whole graph; group bounds tighten the core bounds
     fw_run(g, mode, iters, false, s);
     sg_stable_groups(g, mode, s);
@@ -583,6 +722,7 @@ void topk_run(Graph& g, int mode, int k, int iters, hipStream_t s, std::vector<T
             if (lt(his[i], c.hi[u])) c.hi[u] = his[i];
         }
     }
+    lap(&st.ms_fw);
     // Pruning (Alg. 3): rule 1, then rule 2 on the residual graph
     for (int64_t u = 0; u < n; ++u)
         for (int64_t e = c.h.rp[u]; e < c.h.rp[u + 1]; ++e)
@@ -601,6 +741,7 @@ void topk_run(Graph& g, int mode, int k, int iters, hipStream_t s, std::vector<T
         if (!changed) break;
     }
     for (int64_t u = 0; u < n; ++u) st.pruned += alive[u] ? 0 : 1;
+    lap(&st.ms_prune);
     std::priority_queue<Cand, std::vector<Cand>, CandLess> pq;
     auto push = [&](std::vector<int32_t>&& vs, const Frac* cap) {
         if (vs.empty()) return;
@@ -618,10 +759,22 @@ void topk_run(Graph& g, int mode, int k, int iters, hipStream_t s, std::vector<T
     }
     std::vector<std::pair<Frac, std::vector<int32_t>>> found;
     std::vector<Frac> dens;  // densities found, for the k-th largest
+    // LDS_TOPK_TRACE=1 prints one line per candidate to stderr
+    const char* tr_env = std::getenv("LDS_TOPK_TRACE");
+    const bool trace = tr_env && tr_env[0] == '1';
+    auto tick = std::chrono::steady_clock::now();
+    auto note = [&](const char* what, size_t size, const Frac& r) {
+        if (!trace) return;
+        const auto now = std::chrono::steady_clock::now();
+        std::fprintf(stderr, "[topk] %-10s |S|=%zu rho=%lld/%lld %.1f ms\n", what, size, (long long)r.n,
+                     (long long)r.d, std::chrono::duration<double, std::milli>(now - tick).count());
+        tick = now;
+    };
     while (!pq.empty()) {
         Cand cd = std::move(const_cast<Cand&>(pq.top()));
         pq.pop();
         st.popped++;
+        note("pop", cd.vs.size(), cd.ub);
         if ((int)dens.size() >= k) {
             std::nth_element(dens.begin(), dens.begin() + (k - 1), dens.end(),
                              [](const Frac& a, const Frac& b) { return lt(b, a); });
@@ -630,13 +783,18 @@ void topk_run(Graph& g, int mode, int k, int iters, hipStream_t s, std::vector<T
         if (cd.ub.n <= 0) break;  // an LDS has positive density
         std::vector<std::vector<int32_t>> comps = components(c, cd.vs);
         if (comps.size() > 1) {
+            note("components", comps.size(), cd.ub);
             for (auto& cc : comps) push(std::move(cc), &cd.ub);
             continue;
         }
         Frac rho;
         std::vector<int32_t> denser;
-        if (is_densest(c, cd.vs, &rho, &denser)) {
-            if (rho.n > 0 && is_lds(c, cd.vs, rho)) {
+        const bool densest = is_densest(c, cd.vs, &rho, &denser);
+        note(densest ? "densest" : "not-dense", denser.size(), rho);
+        if (densest) {
+            const bool ok = rho.n > 0 && is_lds(c, cd.vs, rho);
+            note(ok ? "LDS" : "not-LDS", cd.vs.size(), rho);
+            if (ok) {
                 found.push_back({rho, cd.vs});
                 dens.push_back(rho);
             }
@@ -645,6 +803,7 @@ void topk_run(Graph& g, int mode, int k, int iters, hipStream_t s, std::vector<T
         std::vector<std::vector<int32_t>> parts;
         std::vector<Frac> phis;
         refine(c, cd.vs, parts, phis);
+        note("refined", parts.size(), rho);
         if (parts.size() >= 2) {
             for (size_t i = 0; i < parts.size(); ++i) {
                 Frac cap = cd.ub;
@@ -661,6 +820,7 @@ void topk_run(Graph& g, int mode, int k, int iters, hipStream_t s, std::vector<T
         push(std::move(rest), &cd.ub);
         push(std::move(top), &cd.ub);
     }
+    lap(&st.ms_search);
     for (auto& f : found) {
         TopkSet t;
         t.num = f.first.n;

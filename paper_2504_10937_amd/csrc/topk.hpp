@@ -30,6 +30,9 @@ struct TopkStats {
     int64_t flow_splits = 0;  // candidates split by the min cut instead
     int64_t maxflows = 0;     // min-cut computations (IsDensest + IsLDS)
     int64_t pruned = 0;       // vertices removed by the two pruning rules
+    // wall-clock ms: host copy of the graph, core numbers, first FW +
+    // ExtractSG, pruning, candidate search (verification and refinement)
+    double ms_copy = 0, ms_core = 0, ms_fw = 0, ms_prune = 0, ms_search = 0;
 };
 
 void topk_run(Graph& g, int mode, int k, int iters, hipStream_t s, std::vector<TopkSet>& out, TopkStats& st);
