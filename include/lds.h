@@ -158,6 +158,72 @@ lds_status lds_sweep_info(lds_graph g, lds_mode mode, int64_t* rows, int64_t* sl
 /* Denominator D_iters of the loads after `iters` iterations. */
 uint64_t lds_denominator(lds_mode mode, int32_t iters);
 
+/* Current Frank-Wolfe state of a mode without running anything: the loads
+ * left by the last lds_frank_wolfe or lds_batch_run of this graph and mode.
+ * r_out (device float, n, by caller id), r64_out (host double), num_out
+ * (host uint64 numerators over lds_denominator(mode, iters)), gap_out (host,
+ * iters entries; only after a run that computed the gap); *iters_out = the
+ * iteration count of that run.  Any output may be NULL.  LDS_E_INVALID if no
+ * run has been made for the mode. */
+lds_status lds_loads(lds_graph g, lds_mode mode, float* r_out, double* r64_out, uint64_t* num_out, double* gap_out,
+                     int32_t* iters_out, void* hip_stream);
+
+/* ---- Batched Frank-Wolfe over many independent graphs ----------------------
+ * A batch runs lds_frank_wolfe(graphs[i], modes[i], iters[i]) for every i in
+ * one persistent kernel launch, captured into a hipGraph at creation and
+ * replayed by lds_batch_run.  Each workgroup takes whole graphs from a device
+ * work queue (largest first) and runs all their iterations with workgroup
+ * barriers, keys in LDS for graphs with at most lds_vertices vertices.
+ * Graphs whose work (incidences + vertices) * iters exceeds max_kernel_cost
+ * run one by one (lds_frank_wolfe's own launches) on the same stream.  The
+ * arithmetic is exact, so after lds_batch_run every graph holds bit for bit
+ * the state that lds_frank_wolfe leaves (loads, splits, gap); lds_loads,
+ * lds_splits, lds_stable_groups and lds_topk read it. */
+typedef struct lds_batch_s* lds_batch;
+
+/* Launch shape of the batched kernel (lds_tune_default, lds_batch_autotune). */
+typedef struct {
+    int32_t threads;          /* workgroup size: 256, 512 or 1024 */
+    int32_t wg_per_cu;        /* persistent workgroups per compute unit, 1..8 */
+    int32_t lds_vertices;     /* graphs with at most this many vertices keep keys in LDS, 0..8192 */
+    int32_t longest_first;    /* 1: queue ordered by work, largest first */
+    int64_t max_kernel_cost;  /* larger graphs run one by one */
+} lds_tune;
+
+#define LDS_BATCH_GAP 1u /* compute the duality gap of every graph (lds_loads gap_out) */
+
+void lds_tune_default(lds_tune* out);
+
+/* graphs, modes, iters: count entries; a (graph, mode) pair may appear once.
+ * r_out: NULL or count device pointers (each NULL or n floats, by caller
+ * id) that receive the final loads at every run.  tune: NULL = defaults.
+ * The graphs must outlive the batch and must not be used by other calls
+ * while lds_batch_run executes.  Lists triangles and sizes every graph's FW
+ * buffers; synchronises hip_stream. */
+lds_status lds_batch_create(const lds_graph* graphs, const lds_mode* modes, const int32_t* iters, float* const* r_out,
+                            int32_t count, uint32_t flags, const lds_tune* tune, void* hip_stream, lds_batch* out);
+/* One run of the whole batch on hip_stream (asynchronous unless
+ * LDS_BATCH_GAP, which waits for the gap sums). */
+lds_status lds_batch_run(lds_batch b, void* hip_stream);
+/* kernel_graphs / plain_graphs: graphs in the batched kernel / run one by
+ * one; kernel_ms: GPU time of the captured launch of the last run (waits for
+ * it); tune: the launch shape.  Any output may be NULL. */
+lds_status lds_batch_info(lds_batch b, int32_t* kernel_graphs, int32_t* plain_graphs, float* kernel_ms,
+                          lds_tune* tune);
+lds_status lds_batch_destroy(lds_batch b);
+
+/* Autotuner: times the candidate launch shapes (workgroup size x workgroups
+ * per CU, then queue order, then the per-graph work cutoff) on this batch, `reps` timed runs each after one
+ * warm-up, and returns the fastest in *best.  With cache_path, a JSON file
+ * keyed by a coarse signature of the batch (graph count, total work, largest
+ * graph, edge / triangle mix, CU count, each rounded to a power of two) is
+ * read first (no timing when the signature is present, *best_ms = -1) and
+ * updated after timing.  Runs the batch, so it overwrites the graphs' FW
+ * state like lds_batch_run. */
+lds_status lds_batch_autotune(const lds_graph* graphs, const lds_mode* modes, const int32_t* iters, int32_t count,
+                              const char* cache_path, int32_t reps, lds_tune* best, double* best_ms,
+                              void* hip_stream);
+
 /* Result of lds_topk, allocated by the library; release with
  * lds_result_free.  Set i (0 <= i < count) has the caller ids
  * vertices[offsets[i] .. offsets[i+1]) in ascending order and the exact

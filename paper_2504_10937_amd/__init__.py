@@ -58,6 +58,13 @@ def load():
         "lds_sweep_info": (st, [vp, st, vp, vp, vp, vp, vp, vp]),
         "lds_topk": (st, [vp, st, i32, i32, vp, vp]),
         "lds_result_free": (None, [vp]),
+        "lds_loads": (st, [vp, st, vp, vp, vp, vp, vp, vp]),
+        "lds_tune_default": (None, [vp]),
+        "lds_batch_create": (st, [vp, vp, vp, vp, i32, u32, vp, vp, vp]),
+        "lds_batch_run": (st, [vp, vp]),
+        "lds_batch_info": (st, [vp, vp, vp, vp, vp]),
+        "lds_batch_destroy": (st, [vp]),
+        "lds_batch_autotune": (st, [vp, vp, vp, i32, ctypes.c_char_p, i32, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -263,6 +270,116 @@ def lds_topk(g, mode, k, iters, stream=None, with_stats=False):
     finally:
         L.lds_result_free(ctypes.byref(r))
     return (out, stats) if with_stats else out
+
+
+def lds_loads(g, mode, r_out=None, want_r64=False, want_num=False, want_gap=False, stream=None):
+    """Current FW state of a mode (no run) -> dict(iters, r64?, num?, gap?)."""
+    n = lds_graph_info(g)["n"]
+    it = ctypes.c_int32()
+    r64 = np.empty(n, np.float64) if want_r64 else None
+    num = np.empty(n, np.uint64) if want_num else None
+    _check(load().lds_loads(g.handle, mode, _ptr(r_out), _ptr(r64), _ptr(num), None, ctypes.byref(it),
+                            _stream(stream)))
+    out = {"iters": it.value}
+    gap = np.empty(it.value, np.float64) if want_gap else None
+    if want_gap:
+        _check(load().lds_loads(g.handle, mode, None, None, None, _ptr(gap), None, _stream(stream)))
+    out.update({k: v for k, v in (("r64", r64), ("num", num), ("gap", gap)) if v is not None})
+    return out
+
+
+class LdsTune(ctypes.Structure):
+    _fields_ = [("threads", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32), ("lds_vertices", ctypes.c_int32),
+                ("longest_first", ctypes.c_int32), ("max_kernel_cost", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+LDS_BATCH_GAP = 1
+
+
+def lds_tune_default(**kw):
+    t = LdsTune()
+    load().lds_tune_default(ctypes.byref(t))
+    for k, v in kw.items():
+        setattr(t, k, v)
+    return t
+
+
+class Batch:
+    """Owning handle of an lds_batch; keeps its graphs alive."""
+
+    def __init__(self, handle, graphs, r_out):
+        self._h = handle
+        self._graphs = graphs
+        self._r_out = r_out
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("batch destroyed")
+        return self._h
+
+    def destroy(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.lds_batch_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        self.destroy()
+
+
+def _batch_args(graphs, modes, iters):
+    k = len(graphs)
+    hs = (ctypes.c_void_p * max(k, 1))(*[g.handle for g in graphs])
+    ms = (ctypes.c_int * max(k, 1))(*[int(m) for m in modes])
+    its = (ctypes.c_int32 * max(k, 1))(*[int(i) for i in iters])
+    return k, hs, ms, its
+
+
+def lds_batch_create(graphs, modes, iters, r_out=None, gap=False, tune=None, stream=None):
+    """Batch of FW runs (one per (graph, mode, iters)); r_out: optional list
+    of device float tensors (or None entries) that receive the loads."""
+    k, hs, ms, its = _batch_args(graphs, modes, iters)
+    ro = None
+    if r_out is not None:
+        ro = (ctypes.c_void_p * max(k, 1))(*[(t.data_ptr() if t is not None else None) for t in r_out])
+    out = ctypes.c_void_p()
+    _check(load().lds_batch_create(hs, ms, its, ro, k, LDS_BATCH_GAP if gap else 0,
+                                   ctypes.byref(tune) if tune is not None else None, _stream(stream),
+                                   ctypes.byref(out)))
+    return Batch(out.value, list(graphs), r_out)
+
+
+def lds_batch_run(b, stream=None):
+    _check(load().lds_batch_run(b.handle, _stream(stream)))
+
+
+def lds_batch_info(b, want_ms=False):
+    kg, pg = ctypes.c_int32(), ctypes.c_int32()
+    ms = ctypes.c_float()
+    t = LdsTune()
+    _check(load().lds_batch_info(b.handle, ctypes.byref(kg), ctypes.byref(pg),
+                                 ctypes.byref(ms) if want_ms else None, ctypes.byref(t)))
+    out = {"kernel_graphs": kg.value, "plain_graphs": pg.value, "tune": t.as_dict()}
+    if want_ms:
+        out["kernel_ms"] = ms.value
+    return out
+
+
+def lds_batch_destroy(b):
+    b.destroy()
+
+
+def lds_batch_autotune(graphs, modes, iters, cache_path=None, reps=3, stream=None):
+    """Fastest launch shape for this batch -> (LdsTune, best ms or -1 if cached)."""
+    k, hs, ms, its = _batch_args(graphs, modes, iters)
+    t = LdsTune()
+    bm = ctypes.c_double()
+    _check(load().lds_batch_autotune(hs, ms, its, k, cache_path.encode() if cache_path else None, int(reps),
+                                     ctypes.byref(t), ctypes.byref(bm), _stream(stream)))
+    return t, bm.value
 
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)

@@ -10,12 +10,19 @@
 #include <cstring>
 #include <mutex>
 
+#include "batch.hpp"
 #include "graph.hpp"
 #include "topk.hpp"
+#include "tune.hpp"
 
 struct lds_graph_s {
     lds::Graph g;
     std::mutex mu;  // a graph is not meant to be shared between threads; this makes misuse safe
+};
+
+struct lds_batch_s {
+    lds::Batch b;
+    std::vector<lds_graph> handles;  // distinct graphs, sorted (lock order)
 };
 
 namespace lds {
@@ -263,7 +270,7 @@ lds_status lds_fw_elapsed(lds_graph g, lds_mode mode, float* ms, int32_t* launch
     LDS_CHECK(mode == LDS_EDGE || mode == LDS_TRIANGLE, lds::ST_INVALID, "mode must be LDS_EDGE or LDS_TRIANGLE");
     std::lock_guard<std::mutex> lk(g->mu);
     const auto& f = g->g.fw[mode == LDS_EDGE ? 0 : 1];
-    LDS_CHECK(f.ev[0] != nullptr, lds::ST_INVALID, "no Frank-Wolfe run recorded for this mode");
+    LDS_CHECK(f.timed && f.ev[0] != nullptr, lds::ST_INVALID, "no timed lds_frank_wolfe run for this mode");
     if (ms) {
         LDS_HIP(hipEventSynchronize(f.ev[1]));
         LDS_HIP(hipEventElapsedTime(ms, f.ev[0], f.ev[1]));
@@ -349,6 +356,152 @@ void lds_result_free(lds_result* r) {
     std::free(r->dens_num);
     std::free(r->dens_den);
     std::memset(r, 0, sizeof(*r));
+}
+
+lds_status lds_loads(lds_graph g, lds_mode mode, float* r_out, double* r64_out, uint64_t* num_out, double* gap_out,
+                     int32_t* iters_out, void* hip_stream) {
+    API_TRY
+    LDS_CHECK(g != nullptr, lds::ST_INVALID, "graph is NULL");
+    LDS_CHECK(mode == LDS_EDGE || mode == LDS_TRIANGLE, lds::ST_INVALID, "mode must be LDS_EDGE or LDS_TRIANGLE");
+    std::lock_guard<std::mutex> lk(g->mu);
+    lds::Graph& G = g->g;
+    const auto& f = G.fw[mode == LDS_EDGE ? 0 : 1];
+    LDS_CHECK(f.ran, lds::ST_INVALID, "no Frank-Wolfe run for this mode");
+    LDS_CHECK(gap_out == nullptr || (int)f.gap.size() == f.iters, lds::ST_INVALID,
+              "the last run did not compute the gap");
+    if (r_out || r64_out || num_out) lds::fw_loads(G, (int)mode, r_out, r64_out, num_out, (hipStream_t)hip_stream);
+    if (gap_out) std::copy(f.gap.begin(), f.gap.end(), gap_out);
+    if (iters_out) *iters_out = f.iters;
+    API_CATCH
+}
+
+void lds_tune_default(lds_tune* out) {
+    if (!out) return;
+    const lds::BatchTune t;
+    out->threads = t.threads;
+    out->wg_per_cu = t.wg_per_cu;
+    out->lds_vertices = t.lds_vertices;
+    out->longest_first = t.longest_first;
+    out->max_kernel_cost = t.max_kernel_cost;
+}
+
+namespace {
+
+lds::BatchTune to_tune(const lds_tune* t) {
+    lds::BatchTune b;
+    if (t) {
+        b.threads = t->threads;
+        b.wg_per_cu = t->wg_per_cu;
+        b.lds_vertices = t->lds_vertices;
+        b.longest_first = t->longest_first;
+        b.max_kernel_cost = t->max_kernel_cost;
+    }
+    return b;
+}
+
+void from_tune(const lds::BatchTune& b, lds_tune* t) {
+    t->threads = b.threads;
+    t->wg_per_cu = b.wg_per_cu;
+    t->lds_vertices = b.lds_vertices;
+    t->longest_first = b.longest_first;
+    t->max_kernel_cost = b.max_kernel_cost;
+}
+
+// checks the batch arguments and fills the graph list; returns the distinct handles sorted
+std::vector<lds_graph> batch_setup(lds::Batch& b, const lds_graph* graphs, const lds_mode* modes, const int32_t* iters,
+                                   float* const* r_out, int32_t count) {
+    LDS_CHECK(count >= 0, lds::ST_INVALID, "count must be >= 0");
+    LDS_CHECK(count == 0 || (graphs && modes && iters), lds::ST_INVALID, "graphs, modes and iters must be given");
+    std::vector<std::pair<lds_graph, int>> seen;
+    for (int32_t i = 0; i < count; ++i) {
+        LDS_CHECK(graphs[i] != nullptr, lds::ST_INVALID, "graph is NULL");
+        LDS_CHECK(modes[i] == LDS_EDGE || modes[i] == LDS_TRIANGLE, lds::ST_INVALID, "bad mode");
+        LDS_CHECK(iters[i] >= 0, lds::ST_INVALID, "iters must be >= 0");
+        seen.push_back({graphs[i], (int)modes[i]});
+        b.gs.push_back(&graphs[i]->g);
+        b.modes.push_back((int)modes[i]);
+        b.iters.push_back(iters[i]);
+        b.r_out.push_back(r_out ? r_out[i] : nullptr);
+    }
+    std::sort(seen.begin(), seen.end());
+    LDS_CHECK(std::adjacent_find(seen.begin(), seen.end()) == seen.end(), lds::ST_INVALID,
+              "a (graph, mode) pair appears twice in the batch");
+    std::vector<lds_graph> hs;
+    for (auto& x : seen) hs.push_back(x.first);
+    hs.erase(std::unique(hs.begin(), hs.end()), hs.end());
+    return hs;
+}
+
+struct MultiLock {
+    std::vector<std::unique_lock<std::mutex>> locks;
+    explicit MultiLock(const std::vector<lds_graph>& hs) {
+        for (lds_graph h : hs) locks.emplace_back(h->mu);  // sorted: one global order
+    }
+};
+
+}  // namespace
+
+lds_status lds_batch_create(const lds_graph* graphs, const lds_mode* modes, const int32_t* iters, float* const* r_out,
+                            int32_t count, uint32_t flags, const lds_tune* tune, void* hip_stream, lds_batch* out) {
+    API_TRY
+    LDS_CHECK(out != nullptr, lds::ST_INVALID, "out must not be NULL");
+    LDS_CHECK((flags & ~LDS_BATCH_GAP) == 0, lds::ST_INVALID, "unknown flags");
+    std::unique_ptr<lds_batch_s> h(new lds_batch_s());
+    h->handles = batch_setup(h->b, graphs, modes, iters, r_out, count);
+    h->b.want_gap = (flags & LDS_BATCH_GAP) != 0;
+    h->b.tune = to_tune(tune);
+    MultiLock lk(h->handles);
+    lds::batch_build(h->b, (hipStream_t)hip_stream);
+    *out = h.release();
+    API_CATCH
+}
+
+lds_status lds_batch_run(lds_batch b, void* hip_stream) {
+    API_TRY
+    LDS_CHECK(b != nullptr, lds::ST_INVALID, "batch is NULL");
+    MultiLock lk(b->handles);
+    lds::batch_run(b->b, (hipStream_t)hip_stream);
+    API_CATCH
+}
+
+lds_status lds_batch_info(lds_batch b, int32_t* kernel_graphs, int32_t* plain_graphs, float* kernel_ms,
+                          lds_tune* tune) {
+    API_TRY
+    LDS_CHECK(b != nullptr, lds::ST_INVALID, "batch is NULL");
+    if (kernel_graphs) *kernel_graphs = (int32_t)b->b.kernel_items.size();
+    if (plain_graphs) *plain_graphs = (int32_t)b->b.plain_items.size();
+    if (kernel_ms) {
+        LDS_CHECK(b->b.runs > 0, lds::ST_INVALID, "the batch has not run");
+        LDS_HIP(hipEventSynchronize(b->b.ev[1]));
+        LDS_HIP(hipEventElapsedTime(kernel_ms, b->b.ev[0], b->b.ev[1]));
+    }
+    if (tune) from_tune(b->b.tune, tune);
+    API_CATCH
+}
+
+lds_status lds_batch_destroy(lds_batch b) {
+    API_TRY
+    delete b;
+    API_CATCH
+}
+
+lds_status lds_batch_autotune(const lds_graph* graphs, const lds_mode* modes, const int32_t* iters, int32_t count,
+                              const char* cache_path, int32_t reps, lds_tune* best, double* best_ms,
+                              void* hip_stream) {
+    API_TRY
+    LDS_CHECK(best != nullptr, lds::ST_INVALID, "best must not be NULL");
+    LDS_CHECK(reps >= 1, lds::ST_INVALID, "reps must be >= 1");
+    lds_batch_s tmp;
+    tmp.handles = batch_setup(tmp.b, graphs, modes, iters, nullptr, count);
+    MultiLock lk(tmp.handles);
+    bool cached = false;
+    double ms = -1;
+    const lds::BatchTune t =
+        lds::autotune(tmp.b, cache_path ? std::string(cache_path) : std::string(), reps, (hipStream_t)hip_stream,
+                      &cached, &ms);
+    from_tune(t, best);
+    if (best_ms) *best_ms = cached ? -1.0 : ms;
+    API_CATCH
 }
 
 }  // extern "C"

@@ -464,11 +464,11 @@ unsigned __int128 fw_max_numerator(const Graph& g, int mode, int iters) {
     return (unsigned __int128)(uint64_t)g.t_max * (2 + 3 * N * (N + 3));
 }
 
-void fw_run(Graph& g, int mode, int iters, bool want_gap, hipStream_t s) {
+void fw_prepare(Graph& g, int mode, int iters, hipStream_t s) {
     LDS_CHECK(mode == 2 || mode == 3, ST_INVALID, "mode must be LDS_EDGE or LDS_TRIANGLE");
     LDS_CHECK(iters >= 0, ST_INVALID, "iters must be >= 0");
     if (mode == 3 && g.T < 0) list_triangles(g, s);
-    SweepPlan& p = (mode == 2) ? g.edge_plan : g.tri_plan;
+    const SweepPlan& p = (mode == 2) ? g.edge_plan : g.tri_plan;
     FwState& f = g.fw[mode == 2 ? 0 : 1];
     const int B = g.idbits;
     // overflow: the largest numerator must leave B bits for the id code
@@ -481,6 +481,32 @@ void fw_run(Graph& g, int mode, int iters, bool want_gap, hipStream_t s) {
         f.Q[0].alloc(n, s);
         f.Q[1].alloc(n, s);
     }
+    const size_t nbits = (size_t)iters * (size_t)p.total_words;
+    if (f.bits.n < nbits) f.bits.alloc(nbits, s);
+}
+
+void fw_gap_from_sums(FwState& f, int mode, int iters, const uint64_t* sums) {
+    f.gap.assign(iters, 0.0);
+    f.lb.assign(iters, 0.0);
+    for (int i = 1; i <= iters; ++i) {
+        const u128 S = ((u128)sums[4 * (i - 1) + 1] << 64) | sums[4 * (i - 1)];
+        const u128 M = ((u128)sums[4 * (i - 1) + 3] << 64) | sums[4 * (i - 1) + 2];
+        const uint64_t D = denom(mode, i - 1);
+        // (D^2/2) gap = sum A^2 - D * sum_patterns min A  (exact)
+        const u128 num = S - (u128)D * M;
+        const long double LD = (long double)D;
+        const long double gap = 2.0L * (long double)num / (LD * LD);
+        f.gap[i - 1] = (double)gap;
+        f.lb[i - 1] = (double)((long double)S / (LD * LD) - gap);
+    }
+}
+
+void fw_run(Graph& g, int mode, int iters, bool want_gap, hipStream_t s) {
+    fw_prepare(g, mode, iters, s);
+    SweepPlan& p = (mode == 2) ? g.edge_plan : g.tri_plan;
+    FwState& f = g.fw[mode == 2 ? 0 : 1];
+    const int B = g.idbits;
+    const int64_t n = g.n;
     if (n > 0) {
         const int32_t* cnt = (mode == 2) ? g.deg.p : g.tcount.p;
         k_init_keys<<<grid_for(n, 256), 256, 0, s>>>(cnt, mode == 2 ? 1 : 2, g.orig_of.p, n, B, f.K[0].p, f.K[1].p,
@@ -489,8 +515,6 @@ void fw_run(Graph& g, int mode, int iters, bool want_gap, hipStream_t s) {
     }
     f.cur = 0;
     g.sg[mode == 2 ? 0 : 1].valid = false;
-    const size_t nbits = (size_t)iters * (size_t)p.total_words;
-    if (f.bits.n < nbits) f.bits.alloc(nbits, s);
     const unsigned blocks = sweep_grid();
     const size_t npart = want_gap ? (size_t)iters * blocks * 4 : 0;
     if (f.partial.n < npart) f.partial.alloc(npart, s);
@@ -531,8 +555,10 @@ void fw_run(Graph& g, int mode, int iters, bool want_gap, hipStream_t s) {
     }
     LDS_HIP(hipEventRecord(f.ev[1], s));
     f.iters = iters;
-    f.gap.assign(want_gap ? iters : 0, 0.0);
-    f.lb.assign(want_gap ? iters : 0, 0.0);
+    f.ran = true;
+    f.timed = true;
+    f.gap.clear();
+    f.lb.clear();
     if (want_gap && iters > 0) {
         std::vector<uint64_t> sums((size_t)iters * 4, 0);
         if (blocks > 0 && p.nrows > 0) {
@@ -543,17 +569,7 @@ void fw_run(Graph& g, int mode, int iters, bool want_gap, hipStream_t s) {
             LDS_HIP(hipMemcpyAsync(sums.data(), out.p, out.bytes(), hipMemcpyDeviceToHost, s));
             LDS_HIP(hipStreamSynchronize(s));
         }
-        for (int i = 1; i <= iters; ++i) {
-            const u128 S = ((u128)sums[4 * (i - 1) + 1] << 64) | sums[4 * (i - 1)];
-            const u128 M = ((u128)sums[4 * (i - 1) + 3] << 64) | sums[4 * (i - 1) + 2];
-            const uint64_t D = denom(mode, i - 1);
-            // (D^2/2) gap = sum A^2 - D * sum_patterns min A  (exact)
-            const u128 num = S - (u128)D * M;
-            const long double LD = (long double)D;
-            const long double gap = 2.0L * (long double)num / (LD * LD);
-            f.gap[i - 1] = (double)gap;
-            f.lb[i - 1] = (double)((long double)S / (LD * LD) - gap);
-        }
+        fw_gap_from_sums(f, mode, iters, sums.data());
     }
 }
 
@@ -561,7 +577,7 @@ void fw_loads(const Graph& g, int mode, float* r32_dev, double* r64_host, uint64
     const FwState& f = g.fw[mode == 2 ? 0 : 1];
     const int64_t n = g.n;
     if (n == 0) return;
-    LDS_CHECK(f.K[0].n == (size_t)n, ST_INVALID, "no Frank-Wolfe state: call lds_frank_wolfe first");
+    LDS_CHECK(f.ran && f.K[0].n == (size_t)n, ST_INVALID, "no Frank-Wolfe state: call lds_frank_wolfe first");
     const double D = (double)denom(mode, f.iters);
     DBuf<uint64_t> A;
     if (r64_host || A_host) A.alloc(n, s);
@@ -583,7 +599,7 @@ void fw_splits(const Graph& g, int mode, int32_t* verts_host, uint64_t* num_host
     const SweepPlan& p = (mode == 2) ? g.edge_plan : g.tri_plan;
     const int64_t ns = p.nslots;
     if (ns == 0) return;
-    LDS_CHECK(f.K[0].n == (size_t)g.n, ST_INVALID, "no Frank-Wolfe state: call lds_frank_wolfe first");
+    LDS_CHECK(f.ran && f.K[0].n == (size_t)g.n, ST_INVALID, "no Frank-Wolfe state: call lds_frank_wolfe first");
     const int H = mode;
     DBuf<int32_t> v;
     DBuf<uint64_t> a;

@@ -70,6 +70,8 @@ struct FwState {
     std::vector<double> gap, lb; // per iteration, filled on request
     hipEvent_t ev[2] = {nullptr, nullptr};  // around the sweep launches of the last run
     int launches = 0;
+    bool ran = false;            // keys hold the result of a completed run of `iters` iterations
+    bool timed = false;          // ev[] bracket the last run (plain runs only)
     size_t device_bytes() const {
         return K[0].bytes() + K[1].bytes() + Q[0].bytes() + Q[1].bytes() + bits.bytes() + partial.bytes();
     }
@@ -135,6 +137,12 @@ void sg_stable_groups(Graph& g, int mode, hipStream_t s);
 
 // fw.hip
 unsigned __int128 fw_max_numerator(const Graph& g, int mode, int iters);
+// lists triangles if needed, checks the key width and sizes the FW buffers
+// (keys, codes, decision words) for `iters` iterations
+void fw_prepare(Graph& g, int mode, int iters, hipStream_t s);
+// gap and lower bound per iteration from the exact sums sum A^2, sum_patterns min A
+// (4 words per iteration: low/high of each)
+void fw_gap_from_sums(FwState& f, int mode, int iters, const uint64_t* sums);
 void fw_run(Graph& g, int mode, int iters, bool want_gap, hipStream_t s);
 void fw_loads(const Graph& g, int mode, float* r32_dev, double* r64_host, uint64_t* A_host, hipStream_t s);
 void fw_splits(const Graph& g, int mode, int32_t* verts_host, uint64_t* num_host, hipStream_t s);

@@ -570,7 +570,7 @@ PassArgs plan_args(const Graph& g, int mode, PassArgs a) {
 void sg_sort_prefix(Graph& g, int mode, hipStream_t s) {
     FwState& f = g.fw[mode == 2 ? 0 : 1];
     SgState& q = g.sg[mode == 2 ? 0 : 1];
-    LDS_CHECK(f.K[0].n == (size_t)g.n && f.ev[0] != nullptr, ST_INVALID,
+    LDS_CHECK(f.ran && f.K[0].n == (size_t)g.n, ST_INVALID,
               "no Frank-Wolfe state: call lds_frank_wolfe first");
     const SweepPlan& p = (mode == 2) ? g.edge_plan : g.tri_plan;
     const int64_t n = g.n;
