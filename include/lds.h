@@ -264,6 +264,58 @@ lds_status lds_topk(lds_graph g, lds_mode mode, int32_t k, int32_t iters, lds_re
  * zeroed results are accepted. */
 void lds_result_free(lds_result* r);
 
+/* ---- Serving: continuous batching of top-k queries on resident graphs -----
+ * Queries (graph, mode, k, iters) are queued with their arrival time.  A
+ * scheduler thread admits queued queries in arrival order while the device
+ * memory they add (lds_footprint) fits the budget and a slot is free; a
+ * query waits while an earlier query on the same (graph, mode) runs.  All
+ * queries admitted together run their Frank-Wolfe iterations in one batched
+ * launch (as lds_batch_run); worker threads then finish each query
+ * (lds_topk's search, on their own streams) while the scheduler already
+ * admits and launches the next batch.  Each query starts from the canonical
+ * initial point, so its result equals lds_topk(g, mode, k, iters) run alone.
+ * Graphs must stay alive until their queries complete; while the server
+ * runs, the caller's own calls on a graph wait for the server's use of it. */
+typedef struct lds_server_s* lds_server;
+
+typedef struct {
+    uint64_t tag;
+    int32_t status;        /* lds_status of the query */
+    lds_result result;     /* valid when status == LDS_OK; free with lds_result_free */
+    double t_arrive;       /* seconds on the server clock (lds_server_clock) */
+    double t_admit;        /* when the query was admitted (-1 if never) */
+    double t_done;
+    char error[160];       /* message when status != LDS_OK */
+} lds_completion;
+
+typedef struct {
+    int64_t submitted, completed, batches, max_batch, pending, active;
+    size_t inflight_bytes, peak_inflight_bytes;
+} lds_server_info;
+
+/* Device bytes one query adds to its resident graph (FW state for `iters`
+ * iterations, stable-group buffers, temporaries): an upper estimate, used
+ * for admission.  LDS_TRIANGLE needs the triangles listed (lds_triangles). */
+lds_status lds_footprint(lds_graph g, lds_mode mode, int32_t iters, size_t* bytes);
+
+/* hbm_budget: device bytes that admitted queries may add together (0 = 90%
+ * of the device memory free now); max_slots: queries admitted at once;
+ * workers: verification threads (1..64).  A query whose footprint exceeds
+ * the budget completes with LDS_E_NOMEM. */
+lds_status lds_server_create(size_t hbm_budget, int32_t max_slots, int32_t workers, lds_server* out);
+/* t_arrive < 0: now.  For a triangle query on a graph whose triangles are
+ * not listed yet, lists them first (the call waits for it). */
+lds_status lds_server_submit(lds_server s, lds_graph g, lds_mode mode, int32_t k, int32_t iters, uint64_t tag,
+                             double t_arrive);
+/* Up to max completions into out (waits up to wait_s seconds for the first
+ * one when none is ready); *n_out = number written. */
+lds_status lds_server_poll(lds_server s, lds_completion* out, int32_t max, double wait_s, int32_t* n_out);
+lds_status lds_server_clock(lds_server s, double* now);
+lds_status lds_server_stats(lds_server s, lds_server_info* out);
+/* Drops queued queries that were not admitted, waits for the admitted ones
+ * and stops the threads; completions not yet polled are discarded. */
+lds_status lds_server_destroy(lds_server s);
+
 #ifdef __cplusplus
 }
 #endif

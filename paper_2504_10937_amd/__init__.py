@@ -65,6 +65,13 @@ def load():
         "lds_batch_info": (st, [vp, vp, vp, vp, vp]),
         "lds_batch_destroy": (st, [vp]),
         "lds_batch_autotune": (st, [vp, vp, vp, i32, ctypes.c_char_p, i32, vp, vp, vp]),
+        "lds_footprint": (st, [vp, st, i32, vp]),
+        "lds_server_create": (st, [ctypes.c_size_t, i32, i32, vp]),
+        "lds_server_submit": (st, [vp, vp, st, i32, i32, u64, ctypes.c_double]),
+        "lds_server_poll": (st, [vp, vp, i32, ctypes.c_double, vp]),
+        "lds_server_clock": (st, [vp, vp]),
+        "lds_server_stats": (st, [vp, vp]),
+        "lds_server_destroy": (st, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -251,20 +258,25 @@ class _Result(ctypes.Structure):
                 ("ms_fw", ctypes.c_double), ("ms_prune", ctypes.c_double), ("ms_search", ctypes.c_double)]
 
 
+def _sets_of(r):
+    from fractions import Fraction
+    out = []
+    if r.count > 0:
+        off = np.ctypeslib.as_array(r.offsets, shape=(r.count + 1,)).copy()
+        allv = np.ctypeslib.as_array(r.vertices, shape=(max(int(off[-1]), 1),))[:int(off[-1])].copy()
+        for i in range(r.count):
+            out.append((allv[off[i]:off[i + 1]].copy(), Fraction(int(r.dens_num[i]), int(r.dens_den[i]))))
+    return out
+
+
 def lds_topk(g, mode, k, iters, stream=None, with_stats=False):
     """Top-k LDS (mode 2) / LTDS (mode 3) -> list of (caller ids ascending,
     Fraction density), densest first; with_stats adds the search counters."""
-    from fractions import Fraction
     L = load()
     r = _Result()
     _check(L.lds_topk(g.handle, mode, int(k), int(iters), ctypes.byref(r), _stream(stream)))
     try:
-        out = []
-        if r.count > 0:
-            off = np.ctypeslib.as_array(r.offsets, shape=(r.count + 1,)).copy()
-            allv = np.ctypeslib.as_array(r.vertices, shape=(max(int(off[-1]), 1),))[:int(off[-1])].copy()
-            for i in range(r.count):
-                out.append((allv[off[i]:off[i + 1]].copy(), Fraction(int(r.dens_num[i]), int(r.dens_den[i]))))
+        out = _sets_of(r)
         stats = {f: getattr(r, f) for f in ("popped", "refinements", "flow_splits", "maxflows", "pruned",
                                               "ms_copy", "ms_core", "ms_fw", "ms_prune", "ms_search")}
     finally:
@@ -380,6 +392,93 @@ def lds_batch_autotune(graphs, modes, iters, cache_path=None, reps=3, stream=Non
     _check(load().lds_batch_autotune(hs, ms, its, k, cache_path.encode() if cache_path else None, int(reps),
                                      ctypes.byref(t), ctypes.byref(bm), _stream(stream)))
     return t, bm.value
+
+
+class _Completion(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("status", ctypes.c_int32), ("result", _Result),
+                ("t_arrive", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("error", ctypes.c_char * 160)]
+
+
+class _ServerInfo(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("batches", ctypes.c_int64),
+                ("max_batch", ctypes.c_int64), ("pending", ctypes.c_int64), ("active", ctypes.c_int64),
+                ("inflight_bytes", ctypes.c_size_t), ("peak_inflight_bytes", ctypes.c_size_t)]
+
+
+def lds_footprint(g, mode, iters):
+    b = ctypes.c_size_t()
+    _check(load().lds_footprint(g.handle, mode, int(iters), ctypes.byref(b)))
+    return b.value
+
+
+class Server:
+    """Owning handle of an lds_server (continuous-batching query server)."""
+
+    def __init__(self, handle):
+        self._h = handle
+        self._graphs = {}
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("server destroyed")
+        return self._h
+
+    def destroy(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.lds_server_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        self.destroy()
+
+
+def lds_server_create(hbm_budget=0, max_slots=64, workers=8):
+    out = ctypes.c_void_p()
+    _check(load().lds_server_create(int(hbm_budget), int(max_slots), int(workers), ctypes.byref(out)))
+    return Server(out.value)
+
+
+def lds_server_submit(srv, g, mode, k, iters, tag, t_arrive=-1.0):
+    srv._graphs[id(g)] = g  # keep the graph alive while the server may use it
+    _check(load().lds_server_submit(srv.handle, g.handle, mode, int(k), int(iters), int(tag), float(t_arrive)))
+
+
+def lds_server_poll(srv, max_n=256, wait_s=0.0):
+    """-> list of dict(tag, status, sets, t_arrive, t_admit, t_done, error)."""
+    L = load()
+    arr = (_Completion * max(int(max_n), 1))()
+    n = ctypes.c_int32()
+    _check(L.lds_server_poll(srv.handle, arr, int(max_n), float(wait_s), ctypes.byref(n)))
+    out = []
+    for i in range(n.value):
+        c = arr[i]
+        d = {"tag": c.tag, "status": c.status, "t_arrive": c.t_arrive, "t_admit": c.t_admit, "t_done": c.t_done,
+             "error": c.error.decode(errors="replace"), "sets": None}
+        if c.status == 0:
+            try:
+                d["sets"] = _sets_of(c.result)
+            finally:
+                L.lds_result_free(ctypes.byref(c.result))
+        out.append(d)
+    return out
+
+
+def lds_server_clock(srv):
+    t = ctypes.c_double()
+    _check(load().lds_server_clock(srv.handle, ctypes.byref(t)))
+    return t.value
+
+
+def lds_server_stats(srv):
+    x = _ServerInfo()
+    _check(load().lds_server_stats(srv.handle, ctypes.byref(x)))
+    return {f: getattr(x, f) for f, _ in x._fields_}
+
+
+def lds_server_destroy(srv):
+    srv.destroy()
 
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)

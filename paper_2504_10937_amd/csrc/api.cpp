@@ -12,13 +12,11 @@
 
 #include "batch.hpp"
 #include "graph.hpp"
+#include "handles.hpp"
+#include "server.hpp"
 #include "topk.hpp"
 #include "tune.hpp"
 
-struct lds_graph_s {
-    lds::Graph g;
-    std::mutex mu;  // a graph is not meant to be shared between threads; this makes misuse safe
-};
 
 struct lds_batch_s {
     lds::Batch b;
@@ -301,17 +299,10 @@ uint64_t lds_denominator(lds_mode mode, int32_t iters) {
     return (uint64_t)(mode == LDS_TRIANGLE ? 3 : 1) * (uint64_t)(iters + 1) * (uint64_t)(iters + 2);
 }
 
-lds_status lds_topk(lds_graph g, lds_mode mode, int32_t k, int32_t iters, lds_result* out, void* hip_stream) {
-    API_TRY
-    LDS_CHECK(g != nullptr && out != nullptr, lds::ST_INVALID, "graph and out must not be NULL");
-    std::memset(out, 0, sizeof(*out));
-    LDS_CHECK(mode == LDS_EDGE || mode == LDS_TRIANGLE, lds::ST_INVALID, "mode must be LDS_EDGE or LDS_TRIANGLE");
-    LDS_CHECK(k >= 1, lds::ST_INVALID, "k must be >= 1");
-    LDS_CHECK(iters >= 0, lds::ST_INVALID, "iters must be >= 0");
-    std::lock_guard<std::mutex> lk(g->mu);
-    std::vector<lds::TopkSet> sets;
-    lds::TopkStats st;
-    lds::topk_run(g->g, (int)mode, k, iters, (hipStream_t)hip_stream, sets, st);
+namespace {
+
+// lds_result from the driver's sets (host arrays from malloc)
+void fill_result(const std::vector<lds::TopkSet>& sets, const lds::TopkStats& st, lds_result* out) {
     int64_t total = 0;
     for (const auto& t : sets) total += (int64_t)t.vertices.size();
     const size_t c = sets.size();
@@ -345,6 +336,24 @@ lds_status lds_topk(lds_graph g, lds_mode mode, int32_t k, int32_t iters, lds_re
     r.ms_fw = st.ms_fw;
     r.ms_prune = st.ms_prune;
     r.ms_search = st.ms_search;
+    *out = r;
+}
+
+}  // namespace
+
+lds_status lds_topk(lds_graph g, lds_mode mode, int32_t k, int32_t iters, lds_result* out, void* hip_stream) {
+    API_TRY
+    LDS_CHECK(g != nullptr && out != nullptr, lds::ST_INVALID, "graph and out must not be NULL");
+    std::memset(out, 0, sizeof(*out));
+    LDS_CHECK(mode == LDS_EDGE || mode == LDS_TRIANGLE, lds::ST_INVALID, "mode must be LDS_EDGE or LDS_TRIANGLE");
+    LDS_CHECK(k >= 1, lds::ST_INVALID, "k must be >= 1");
+    LDS_CHECK(iters >= 0, lds::ST_INVALID, "iters must be >= 0");
+    std::lock_guard<std::mutex> lk(g->mu);
+    std::vector<lds::TopkSet> sets;
+    lds::TopkStats st;
+    lds::topk_run(g->g, (int)mode, k, iters, (hipStream_t)hip_stream, sets, st);
+    lds_result r;
+    fill_result(sets, st, &r);
     *out = r;
     API_CATCH
 }
@@ -501,6 +510,95 @@ lds_status lds_batch_autotune(const lds_graph* graphs, const lds_mode* modes, co
                       &cached, &ms);
     from_tune(t, best);
     if (best_ms) *best_ms = cached ? -1.0 : ms;
+    API_CATCH
+}
+
+struct lds_server_s {
+    lds::Server* s = nullptr;
+    ~lds_server_s() { delete s; }
+};
+
+lds_status lds_footprint(lds_graph g, lds_mode mode, int32_t iters, size_t* bytes) {
+    API_TRY
+    LDS_CHECK(g != nullptr && bytes != nullptr, lds::ST_INVALID, "graph and bytes must not be NULL");
+    LDS_CHECK(mode == LDS_EDGE || mode == LDS_TRIANGLE, lds::ST_INVALID, "mode must be LDS_EDGE or LDS_TRIANGLE");
+    LDS_CHECK(iters >= 0, lds::ST_INVALID, "iters must be >= 0");
+    std::lock_guard<std::mutex> lk(g->mu);
+    LDS_CHECK(mode == LDS_EDGE || g->g.T >= 0, lds::ST_INVALID, "triangles not listed yet (lds_triangles)");
+    *bytes = lds::topk_footprint(g->g, (int)mode, iters);
+    API_CATCH
+}
+
+lds_status lds_server_create(size_t hbm_budget, int32_t max_slots, int32_t workers, lds_server* out) {
+    API_TRY
+    LDS_CHECK(out != nullptr, lds::ST_INVALID, "out must not be NULL");
+    LDS_CHECK(max_slots >= 1, lds::ST_INVALID, "max_slots must be >= 1");
+    LDS_CHECK(workers >= 1 && workers <= 64, lds::ST_INVALID, "workers must be in [1, 64]");
+    if (hbm_budget == 0) {
+        size_t fr = 0, tot = 0;
+        LDS_HIP(hipMemGetInfo(&fr, &tot));
+        hbm_budget = fr / 10 * 9;
+    }
+    std::unique_ptr<lds_server_s> h(new lds_server_s());
+    h->s = new lds::Server(hbm_budget, max_slots, workers);
+    *out = h.release();
+    API_CATCH
+}
+
+lds_status lds_server_submit(lds_server s, lds_graph g, lds_mode mode, int32_t k, int32_t iters, uint64_t tag,
+                             double t_arrive) {
+    API_TRY
+    LDS_CHECK(s != nullptr, lds::ST_INVALID, "server is NULL");
+    s->s->submit(g, (int)mode, k, iters, tag, t_arrive);
+    API_CATCH
+}
+
+lds_status lds_server_poll(lds_server s, lds_completion* out, int32_t max, double wait_s, int32_t* n_out) {
+    API_TRY
+    LDS_CHECK(s != nullptr && n_out != nullptr, lds::ST_INVALID, "server and n_out must not be NULL");
+    LDS_CHECK(max >= 0 && (max == 0 || out != nullptr), lds::ST_INVALID, "bad output array");
+    std::vector<lds::SDone> got;
+    s->s->poll(got, (size_t)max, wait_s);
+    for (size_t i = 0; i < got.size(); ++i) {
+        lds_completion& c = out[i];
+        std::memset(&c, 0, sizeof(c));
+        c.tag = got[i].tag;
+        c.status = got[i].status;
+        c.t_arrive = got[i].t_arrive;
+        c.t_admit = got[i].t_admit;
+        c.t_done = got[i].t_done;
+        std::strncpy(c.error, got[i].error.c_str(), sizeof(c.error) - 1);
+        if (got[i].status == lds::ST_OK) fill_result(got[i].sets, got[i].st, &c.result);
+    }
+    *n_out = (int32_t)got.size();
+    API_CATCH
+}
+
+lds_status lds_server_clock(lds_server s, double* now) {
+    API_TRY
+    LDS_CHECK(s != nullptr && now != nullptr, lds::ST_INVALID, "server and now must not be NULL");
+    *now = s->s->clock();
+    API_CATCH
+}
+
+lds_status lds_server_stats(lds_server s, lds_server_info* out) {
+    API_TRY
+    LDS_CHECK(s != nullptr && out != nullptr, lds::ST_INVALID, "server and out must not be NULL");
+    const lds::SStats st = s->s->stats();
+    out->submitted = st.submitted;
+    out->completed = st.completed;
+    out->batches = st.batches;
+    out->max_batch = st.max_batch;
+    out->pending = st.pending;
+    out->active = st.active;
+    out->inflight_bytes = st.inflight;
+    out->peak_inflight_bytes = st.peak_inflight;
+    API_CATCH
+}
+
+lds_status lds_server_destroy(lds_server s) {
+    API_TRY
+    delete s;
     API_CATCH
 }
 

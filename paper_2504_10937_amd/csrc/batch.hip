@@ -372,7 +372,7 @@ void batch_build(Batch& b, hipStream_t s) {
         (void)hipGraphDestroy(b.graph);
         b.graph = nullptr;
     }
-    if (!b.cap) LDS_HIP(hipStreamCreateWithFlags(&b.cap, hipStreamNonBlocking));
+    if (b.capture && !b.cap) LDS_HIP(hipStreamCreateWithFlags(&b.cap, hipStreamNonBlocking));
     if (!b.ev[0]) {
         LDS_HIP(hipEventCreate(&b.ev[0]));
         LDS_HIP(hipEventCreate(&b.ev[1]));
@@ -386,6 +386,9 @@ void batch_build(Batch& b, hipStream_t s) {
         case 512: set_lds_limit<512>(lds); break;
         default: set_lds_limit<1024>(lds); break;
     }
+    b.grid = grid;
+    b.lds_bytes = lds;
+    if (!b.capture) return;
     LDS_HIP(hipStreamBeginCapture(b.cap, hipStreamCaptureModeThreadLocal));
     k_zero_i32<<<1, 1, 0, b.cap>>>(b.queue.p);
     switch (t.threads) {
@@ -400,8 +403,22 @@ void batch_build(Batch& b, hipStream_t s) {
     LDS_HIP(ce);
     b.graph = gr;
     LDS_HIP(hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0));
-    b.grid = grid;
 }
+
+namespace {
+void launch_direct(Batch& b, hipStream_t s) {
+    const int32_t nk = (int32_t)b.kernel_items.size();
+    if (nk == 0) return;
+    const BItem* items = reinterpret_cast<const BItem*>(b.items.p);
+    k_zero_i32<<<1, 1, 0, s>>>(b.queue.p);
+    switch (b.tune.threads) {
+        case 256: launch_batch<256>(b.grid, b.lds_bytes, s, items, nk, b.queue.p, b.kmax); break;
+        case 512: launch_batch<512>(b.grid, b.lds_bytes, s, items, nk, b.queue.p, b.kmax); break;
+        default: launch_batch<1024>(b.grid, b.lds_bytes, s, items, nk, b.queue.p, b.kmax); break;
+    }
+    LDS_HIP(hipGetLastError());
+}
+}  // namespace
 
 void batch_run(Batch& b, hipStream_t s) {
     const int count = (int)b.gs.size();
@@ -411,7 +428,11 @@ void batch_run(Batch& b, hipStream_t s) {
         if (!b.r_out.empty() && b.r_out[i]) fw_loads(*b.gs[i], b.modes[i], b.r_out[i], nullptr, nullptr, s);
     }
     LDS_HIP(hipEventRecord(b.ev[0], s));
-    if (b.exec) LDS_HIP(hipGraphLaunch(b.exec, s));
+    if (b.capture) {
+        if (b.exec) LDS_HIP(hipGraphLaunch(b.exec, s));
+    } else {
+        launch_direct(b, s);
+    }
     LDS_HIP(hipEventRecord(b.ev[1], s));
     for (size_t j = 0; j < b.kernel_items.size(); ++j) {
         const int i = b.kernel_items[j];

@@ -22,6 +22,7 @@ struct Batch {
     std::vector<int> modes, iters;
     std::vector<float*> r_out;       // per graph, device, by caller id (may be empty)
     bool want_gap = false;
+    bool capture = true;             // replay a captured hipGraph (else launch directly)
     BatchTune tune;
     std::vector<int> kernel_items;   // indices into gs, in queue order
     std::vector<int> plain_items;    // graphs run one by one
@@ -31,6 +32,7 @@ struct Batch {
     DBuf<uint64_t> sums;             // exact gap sums of the kernel items
     int32_t kmax = 0;
     unsigned grid = 0;
+    size_t lds_bytes = 0;
     hipStream_t cap = nullptr;       // private stream used for capture
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;

@@ -672,7 +672,18 @@ void refine(Ctx& c, const std::vector<int32_t>& vs, std::vector<std::vector<int3
 
 }  // namespace
 
-void topk_run(Graph& g, int mode, int k, int iters, hipStream_t s, std::vector<TopkSet>& out, TopkStats& st) {
+size_t topk_footprint(const Graph& g, int mode, int iters) {
+    const SweepPlan& p = (mode == 2) ? g.edge_plan : g.tri_plan;
+    const size_t n = (size_t)g.n, slots = (size_t)p.nslots;
+    const size_t T = mode == 3 && g.T > 0 ? (size_t)g.T : 0;
+    const size_t fw = 2 * 8 * n + 2 * 2 * n + (size_t)iters * (size_t)p.total_words * 8 + (size_t)iters * 4 * 8 * 1024;
+    const size_t sg = 4 * n + 8 * n + 8 * n + n + 4 * slots + 12 * T + 16 * n;  // order pos E inI a_slot a_tri lo hi
+    const size_t tmp = 24 * n + 24 * n + 8 * n;                                 // sort keys/values, R T V, counts
+    return fw + sg + tmp;
+}
+
+void topk_run(Graph& g, int mode, int k, int iters, hipStream_t s, std::vector<TopkSet>& out, TopkStats& st,
+              bool reuse_fw) {
     LDS_CHECK(mode == 2 || mode == 3, ST_INVALID, "mode must be LDS_EDGE or LDS_TRIANGLE");
     LDS_CHECK(k >= 1, ST_INVALID, "k must be >= 1");
     LDS_CHECK(iters >= 0, ST_INVALID, "iters must be >= 0");
@@ -710,7 +721,8 @@ void topk_run(Graph& g, int mode, int k, int iters, hipStream_t s, std::vector<T
     }
     lap(&st.ms_core);
     // FW + ExtractSG on the whole graph; group bounds tighten the core bounds
-    fw_run(g, mode, iters, false, s);
+    const FwState& fs = g.fw[mode == 2 ? 0 : 1];
+    if (!(reuse_fw && fs.ran && fs.iters == iters)) fw_run(g, mode, iters, false, s);
     sg_stable_groups(g, mode, s);
     std::vector<std::vector<int32_t>> sets;
     std::vector<Frac> his, los;

@@ -35,6 +35,12 @@ struct TopkStats {
     double ms_copy = 0, ms_core = 0, ms_fw = 0, ms_prune = 0, ms_search = 0;
 };
 
-void topk_run(Graph& g, int mode, int k, int iters, hipStream_t s, std::vector<TopkSet>& out, TopkStats& st);
+// reuse_fw: the graph already holds a completed run of `iters` iterations
+// for this mode (e.g. from a batched launch); it is used instead of a new run
+void topk_run(Graph& g, int mode, int k, int iters, hipStream_t s, std::vector<TopkSet>& out, TopkStats& st,
+              bool reuse_fw = false);
+// device bytes a top-k query adds to a resident graph (FW state for `iters`
+// iterations, stable-group buffers and their temporaries), an upper estimate
+size_t topk_footprint(const Graph& g, int mode, int iters);
 
 }  // namespace lds
