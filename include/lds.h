@@ -291,6 +291,7 @@ typedef struct {
 typedef struct {
     int64_t submitted, completed, batches, max_batch, pending, active;
     size_t inflight_bytes, peak_inflight_bytes;
+    double batch_ms;  /* wall time spent in batched FW launches */
 } lds_server_info;
 
 /* Device bytes one query adds to its resident graph (FW state for `iters`

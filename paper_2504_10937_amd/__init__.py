@@ -403,7 +403,8 @@ class _Completion(ctypes.Structure):
 class _ServerInfo(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("batches", ctypes.c_int64),
                 ("max_batch", ctypes.c_int64), ("pending", ctypes.c_int64), ("active", ctypes.c_int64),
-                ("inflight_bytes", ctypes.c_size_t), ("peak_inflight_bytes", ctypes.c_size_t)]
+                ("inflight_bytes", ctypes.c_size_t), ("peak_inflight_bytes", ctypes.c_size_t),
+                ("batch_ms", ctypes.c_double)]
 
 
 def lds_footprint(g, mode, iters):
@@ -459,6 +460,8 @@ def lds_server_poll(srv, max_n=256, wait_s=0.0):
         if c.status == 0:
             try:
                 d["sets"] = _sets_of(c.result)
+                d["stats"] = {f: getattr(c.result, f) for f in ("ms_copy", "ms_core", "ms_fw", "ms_prune",
+                                                                "ms_search", "popped", "refinements")}
             finally:
                 L.lds_result_free(ctypes.byref(c.result))
         out.append(d)

@@ -593,6 +593,7 @@ lds_status lds_server_stats(lds_server s, lds_server_info* out) {
     out->active = st.active;
     out->inflight_bytes = st.inflight;
     out->peak_inflight_bytes = st.peak_inflight;
+    out->batch_ms = st.batch_ms;
     API_CATCH
 }
 

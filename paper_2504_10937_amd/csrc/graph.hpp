@@ -21,6 +21,8 @@
 // iteration are stored per chunk from a 64-bit-word-aligned offset (cwo),
 // followed by the hub rows (hwo); a per-chunk "head" bitmap marks row starts.
 #pragma once
+#include <memory>
+
 #include "common.hpp"
 
 namespace lds {
@@ -96,6 +98,8 @@ struct SgState {
     }
 };
 
+struct HostCache;  // host-side resident data of the top-k search (topk.hpp)
+
 struct Graph {
     int64_t n = 0, m = 0;        // vertices, unique undirected edges
     int64_t n_nz = 0;            // vertices with degree > 0 (internal ids [0, n_nz))
@@ -117,6 +121,7 @@ struct Graph {
     SweepPlan tri_plan;
     FwState fw[2];               // [0] edges, [1] triangles
     SgState sg[2];               // sort / prefix / stable groups of the last run per mode
+    std::shared_ptr<HostCache> host;  // host copy of the adjacency, triangles and core numbers, built on first use
     hipStream_t stream = nullptr;
     size_t device_bytes() const;
     ~Graph();

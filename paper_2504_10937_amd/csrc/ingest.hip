@@ -364,8 +364,10 @@ void build_graph(Graph& g, int64_t n, int64_t npairs, const int32_t* src, const 
         LDS_HIP(hipGetLastError());
     }
 
-    // 3. symmetric CSR in internal ids (row order within a row is not sorted;
-    //    sort_rows() sorts when the triangle listing needs it)
+    // 3. symmetric CSR in internal ids, every row sorted ascending (the
+    //    triangle listing needs sorted rows; sorting here, once, means that the
+    //    slot order of the edge sweep never changes after ingest, so FW state
+    //    stays valid whatever runs later on the graph)
     g.rowptr.alloc(n + 1, s);
     g.col.alloc(ns, s);
     g.col_sorted = false;
@@ -381,6 +383,7 @@ void build_graph(Graph& g, int64_t n, int64_t npairs, const int32_t* src, const 
         LDS_HIP(hipGetLastError());
     }
     skeys.release();
+    sort_rows(g, s);
 
     // 4. edge sweep plan: rows are internal vertices [0, n_nz), degree-sorted
     SweepPlan& p = g.edge_plan;

@@ -30,7 +30,14 @@
 
 namespace lds {
 
+InFlight::~InFlight() {
+    if (done) (void)hipEventDestroy(done);
+}
+
 namespace {
+
+constexpr int kBatchStreams = 4;  // batched launches in flight at once
+constexpr int64_t kServeKernelCost = 1ll << 22;  // (incidences + vertices) * iters kept in the batched kernel
 
 double now_s(std::chrono::steady_clock::time_point t0) {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -54,7 +61,9 @@ struct Server::Impl {
     SStats stats;
     std::thread sched;
     std::vector<std::thread> workers;
-    hipStream_t sched_stream = nullptr;
+    hipStream_t sched_stream = nullptr;   // triangle listing at submission
+    hipStream_t bstream[kBatchStreams] = {};
+    int next_stream = 0;
     int device = 0;
 
     void finish(SQuery& q, SDone&& d) {
@@ -130,19 +139,30 @@ struct Server::Impl {
                 hs.erase(std::unique(hs.begin(), hs.end()), hs.end());
                 std::string err;
                 int code = ST_OK;
+                const auto tb = std::chrono::steady_clock::now();
+                auto fl = std::make_shared<InFlight>();
+                hipStream_t bs = bstream[next_stream];
+                next_stream = (next_stream + 1) % kBatchStreams;
                 try {
+                    // launched, not waited for: the workers wait on the event
                     std::vector<std::unique_lock<std::mutex>> locks;
                     for (lds_graph h : hs) locks.emplace_back(h->mu);
-                    Batch b;
+                    fl->b.reset(new Batch);
+                    Batch& b = *fl->b;
                     b.capture = false;
+                    // latency first: a graph whose FW would keep one
+                    // workgroup busy for more than a few ms runs on its own
+                    // launches (the whole GPU per iteration) instead
+                    b.tune.max_kernel_cost = kServeKernelCost;
                     for (auto& q : adm) {
                         b.gs.push_back(&q.h->g);
                         b.modes.push_back(q.mode);
                         b.iters.push_back(q.iters);
                     }
-                    batch_build(b, sched_stream);
-                    batch_run(b, sched_stream);
-                    LDS_HIP(hipStreamSynchronize(sched_stream));
+                    batch_build(b, bs);
+                    batch_run(b, bs);
+                    LDS_HIP(hipEventCreateWithFlags(&fl->done, hipEventDisableTiming));
+                    LDS_HIP(hipEventRecord(fl->done, bs));
                 } catch (const Error& e) {
                     code = e.code;
                     err = e.what();
@@ -150,7 +170,14 @@ struct Server::Impl {
                     code = ST_DEVICE;
                     err = e.what();
                 }
+                {
+                    std::lock_guard<std::mutex> g(mu);
+                    stats.batch_ms +=
+                        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tb).count();
+                }
                 if (code != ST_OK) {
+                    (void)hipStreamSynchronize(bs);  // nothing of the failed batch may still run
+                    fl.reset();
                     for (auto& q : adm) {
                         SDone d;
                         d.status = code;
@@ -159,7 +186,10 @@ struct Server::Impl {
                     }
                 } else {
                     std::lock_guard<std::mutex> g(mu);
-                    for (auto& q : adm) verify.push_back(std::move(q));
+                    for (auto& q : adm) {
+                        q.fw = fl;
+                        verify.push_back(std::move(q));
+                    }
                     cv_work.notify_all();
                 }
             }
@@ -182,6 +212,7 @@ struct Server::Impl {
             }
             SDone d;
             try {
+                if (q.fw && q.fw->done) LDS_HIP(hipStreamWaitEvent(s, q.fw->done, 0));
                 std::lock_guard<std::mutex> g(q.h->mu);
                 topk_run(q.h->g, q.mode, q.k, q.iters, s, d.sets, d.st, true);
                 d.status = ST_OK;
@@ -195,6 +226,8 @@ struct Server::Impl {
                 d.status = ST_DEVICE;
                 d.error = e.what();
             }
+            if (s) (void)hipStreamSynchronize(s);
+            q.fw.reset();  // the batch's tables are freed with its last query
             finish(q, std::move(d));
         }
         if (s) (void)hipStreamDestroy(s);
@@ -206,6 +239,7 @@ Server::Server(size_t budget, int max_slots, int workers) : p(new Impl) {
     p->max_slots = max_slots;
     LDS_HIP(hipGetDevice(&p->device));
     LDS_HIP(hipStreamCreateWithFlags(&p->sched_stream, hipStreamNonBlocking));
+    for (auto& bs : p->bstream) LDS_HIP(hipStreamCreateWithFlags(&bs, hipStreamNonBlocking));
     p->sched = std::thread([this] { p->scheduler(); });
     for (int i = 0; i < workers; ++i) p->workers.emplace_back([this] { p->worker(); });
 }
@@ -225,6 +259,11 @@ Server::~Server() {
     p->cv_work.notify_all();
     for (auto& t : p->workers)
         if (t.joinable()) t.join();  // the admitted queries are finished
+    for (auto& bs : p->bstream)
+        if (bs) {
+            (void)hipStreamSynchronize(bs);
+            (void)hipStreamDestroy(bs);
+        }
     if (p->sched_stream) (void)hipStreamDestroy(p->sched_stream);
     delete p;
 }

@@ -1,5 +1,6 @@
 // Continuous-batching query server (server.cpp).
 #pragma once
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -8,7 +9,18 @@
 
 namespace lds {
 
+struct Batch;
+
+// a batched FW launch in flight: the batch (its device tables stay alive
+// until every query of it is verified) and the event that marks its end
+struct InFlight {
+    std::unique_ptr<Batch> b;
+    hipEvent_t done = nullptr;
+    ~InFlight();
+};
+
 struct SQuery {
+    std::shared_ptr<InFlight> fw;  // the launch that computed this query's FW state
     lds_graph h = nullptr;
     int mode = 2, k = 1, iters = 0;
     uint64_t tag = 0;
@@ -29,6 +41,7 @@ struct SDone {
 struct SStats {
     int64_t submitted = 0, completed = 0, batches = 0, max_batch = 0, pending = 0, active = 0;
     size_t inflight = 0, peak_inflight = 0;
+    double batch_ms = 0;  // wall time of the scheduler's batched FW launches
 };
 
 class Server {

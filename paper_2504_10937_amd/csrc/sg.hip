@@ -33,7 +33,9 @@
 //     increase) with block maxima for the suffix maximum.
 //     T is kept current by adding, after each acceptance, the change of the
 //     accepted group's patterns.  All quantities are integer numerators over
-//     D_N.
+//     D_N.  The whole scan (search, verification, acceptance, over every
+//     round) is one cooperative kernel whose workgroups meet at grid barriers
+//     between phases; the host only reads the group list at the end.
 #include <algorithm>
 #include <climits>
 
@@ -44,14 +46,6 @@ namespace lds {
 namespace {
 
 constexpr int kT = 256;
-
-template <class T>
-T d2h(const T* p, hipStream_t s) {
-    T v;
-    LDS_HIP(hipMemcpyAsync(&v, p, sizeof(T), hipMemcpyDeviceToHost, s));
-    LDS_HIP(hipStreamSynchronize(s));
-    return v;
-}
 
 __device__ inline int64_t shfl_xor_i64(int64_t v, int m) {
     const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)(uint64_t)v, m, 64);
@@ -281,58 +275,21 @@ __global__ __launch_bounds__(kT) void k_tile_inI(const int64_t* E, int64_t n, co
     }
 }
 
+// exclusive suffix maximum of the tile maxima (one thread; tiles are few)
+__global__ void k_tile_carry(const int64_t* tn, const int64_t* td, int64_t tiles, int64_t* cn, int64_t* cd) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int64_t rn = 0, rd = 0;  // max over later tiles (den 0: minus infinity)
+    for (int64_t t = tiles - 1; t >= 0; --t) {
+        cn[t] = rn;
+        cd[t] = rd;
+        if (frac_gt(tn[t], td[t], rn, rd)) {
+            rn = tn[t];
+            rd = td[t];
+        }
+    }
+}
+
 // ------------------------------------------------------ a9 round helpers
-// first position j in [lo, hi) with v[j] >= thr (result: atomic min into *out)
-__global__ void k_first_ge(const int64_t* v, int64_t lo, int64_t hi, int64_t thr, unsigned long long* out) {
-    const int64_t j = lo + (int64_t)blockIdx.x * kT + threadIdx.x;
-    const bool hit = j < hi && v[j] >= thr;
-    const uint64_t m = __ballot(hit);
-    if (m && (threadIdx.x & 63) == (int)__ffsll((unsigned long long)m) - 1) atomicMin(out, (unsigned long long)j);
-}
-
-// candidate boundaries b = j + 1 for j in [lo, hi): j + 1 in I and (b == n or
-// R[b] < T[j]); flags are compacted in order by a scan
-__global__ void k_cand_flags(const uint8_t* inI, const int64_t* R, const int64_t* T, int64_t lo, int64_t hi, int64_t n,
-                             uint32_t* flag) {
-    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
-    const int64_t j = lo + i;
-    if (j >= hi) return;
-    bool c = inI[j] != 0;
-    if (c && j + 1 < n) c = R[j + 1] < T[j];
-    flag[i] = c ? 1u : 0u;
-}
-
-__global__ void k_cand_compact(const uint32_t* flag, const uint64_t* off, int64_t lo, int64_t cnt, int64_t* list,
-                               int64_t cap) {
-    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
-    if (i >= cnt || !flag[i]) return;
-    const uint64_t o = off[i];
-    if ((int64_t)o < cap) list[o] = lo + i + 1;
-}
-
-// min and max of v over [lo, hi) (out[0] min, out[1] max, pre-set by host)
-__global__ __launch_bounds__(kT) void k_minmax(const int64_t* v, int64_t lo, int64_t hi, long long* out) {
-    const int64_t j = lo + (int64_t)blockIdx.x * kT + threadIdx.x;
-    long long mn = LLONG_MAX, mx = LLONG_MIN;
-    if (j < hi) mn = mx = v[j];
-    for (int m = 32; m > 0; m >>= 1) {
-        mn = min(mn, (long long)shfl_xor_i64(mn, m));
-        mx = max(mx, (long long)shfl_xor_i64(mx, m));
-    }
-    if ((threadIdx.x & 63) == 0) {
-        if (mn != LLONG_MAX) atomicMin(out, mn);
-        if (mx != LLONG_MIN) atomicMax(out + 1, mx);
-    }
-}
-
-__global__ void k_set_bounds(const int32_t* order, int64_t lo, int64_t hi, int64_t mn, int64_t mx, int64_t* blo,
-                             int64_t* bhi) {
-    const int64_t j = lo + (int64_t)blockIdx.x * kT + threadIdx.x;
-    if (j >= hi) return;
-    blo[order[j]] = mn;
-    bhi[order[j]] = mx;
-}
-
 __global__ void k_fill_i64(int64_t* p, int64_t n, int64_t v) {
     const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
     if (i < n) p[i] = v;
@@ -396,62 +353,6 @@ __device__ inline int64_t row_of_vertex(const PassArgs& a, int32_t x) {
     return (x < a.nrows) ? (int64_t)x : -1;
 }
 
-// After accepting the group at positions [a0, a1): T_y of every vertex y
-// below (pos >= a1) changes only through patterns that contain accepted
-// vertices; each such pattern is handled once, from its latest accepted
-// vertex, adding (contribution after - contribution before) to T_y.
-template <int H>
-__global__ __launch_bounds__(kT) void k_tdelta(PassArgs a, int64_t a0, int64_t a1, const int32_t* order, int64_t* T) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t j = a0 + (int64_t)blockIdx.x * 4 + w;
-    if (j >= a1) return;
-    const int32_t x = order[j];
-    const int64_t r = row_of_vertex(a, x);
-    if (r < 0) return;
-    for (int64_t s = a.rp[r] + lane; s < a.rp[r + 1]; s += 64) {
-        int64_t p[H], al[H];
-        int32_t id[H];
-        load_pattern<H>(a, s, x, p, al, id);
-        bool owner = true;  // x is the latest accepted vertex of the pattern
-#pragma unroll
-        for (int i = 1; i < H; ++i)
-            if (p[i] >= a0 && p[i] < a1 && p[i] > p[0]) owner = false;
-        if (!owner) continue;
-#pragma unroll
-        for (int i = 1; i < H; ++i) {
-            if (p[i] < a1) continue;
-            const int64_t before = pat_contrib<H>(i, p, al, a.D, a0, p[i] + 1);
-            const int64_t after = pat_contrib<H>(i, p, al, a.D, a1, p[i] + 1);
-            if (after != before)
-                atomicAdd((unsigned long long*)&T[p[i]], (unsigned long long)(after - before));
-        }
-    }
-}
-
-// restricted loads for (S0, b) of the vertices at positions list[i] (or
-// [lo, lo + cnt) when list is null), one wave per vertex; written by position
-template <int H>
-__global__ __launch_bounds__(kT) void k_listpass(PassArgs a, const int64_t* list, int64_t lo, int64_t cnt,
-                                                 const int32_t* order, int64_t* out) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t i = (int64_t)blockIdx.x * 4 + w;
-    if (i >= cnt) return;
-    const int64_t j = list ? list[i] : lo + i;
-    const int32_t x = order[j];
-    const int64_t r = row_of_vertex(a, x);
-    int64_t acc = 0;
-    if (r >= 0) {
-        for (int64_t s = a.rp[r] + lane; s < a.rp[r + 1]; s += 64) {
-            int64_t p[H], al[H];
-            int32_t id[H];
-            load_pattern<H>(a, s, x, p, al, id);
-            acc += pat_contrib<H>(0, p, al, a.D, a.S0, a.b);
-        }
-        for (int m = 32; m > 0; m >>= 1) acc += shfl_xor_i64(acc, m);
-    }
-    if (lane == 0) out[j] = acc;
-}
-
 // The restricted load F_w(b) of a vertex below the boundary b (everything
 // before b is above it) only grows with b.  Verification boundaries increase
 // over the whole scan, so F is advanced incrementally: when positions
@@ -459,38 +360,6 @@ __global__ __launch_bounds__(kT) void k_listpass(PassArgs a, const int64_t* list
 // moving vertex) adds (after - before) to the vertices still below; block
 // maxima over 1024 positions stay valid under these increases.
 constexpr int kFB = 1024;
-
-template <int H>
-__global__ __launch_bounds__(kT) void k_fdelta(PassArgs a, int64_t p0, int64_t p1, const int32_t* order, int64_t* F,
-                                               long long* bmax) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t j = p0 + (int64_t)blockIdx.x * 4 + w;
-    if (j >= p1) return;
-    const int32_t y = order[j];
-    const int64_t r = row_of_vertex(a, y);
-    if (r < 0) return;
-    for (int64_t s = a.rp[r] + lane; s < a.rp[r + 1]; s += 64) {
-        int64_t p[H], al[H];
-        int32_t id[H];
-        load_pattern<H>(a, s, y, p, al, id);
-        bool owner = true;
-#pragma unroll
-        for (int i = 1; i < H; ++i)
-            if (p[i] >= p0 && p[i] < p1 && p[i] > p[0]) owner = false;
-        if (!owner) continue;
-#pragma unroll
-        for (int i = 1; i < H; ++i) {
-            if (p[i] < p1) continue;
-            const int64_t before = pat_contrib<H>(i, p, al, a.D, p0, p0);
-            const int64_t after = pat_contrib<H>(i, p, al, a.D, p1, p1);
-            if (after != before) {
-                const unsigned long long old =
-                    atomicAdd((unsigned long long*)&F[p[i]], (unsigned long long)(after - before));
-                atomicMax(&bmax[p[i] / kFB], (long long)(old + (unsigned long long)(after - before)));
-            }
-        }
-    }
-}
 
 // F at b = 0 (nothing above): the plain load numerators, by position
 __global__ void k_f_init(const uint64_t* K, const int32_t* order, int64_t n, int B, int64_t* F) {
@@ -509,21 +378,340 @@ __global__ __launch_bounds__(kT) void k_bmax_init(const int64_t* F, int64_t n, l
     if (threadIdx.x == 0) bmax[blockIdx.x] = max(max(sh[0], sh[1]), max(sh[2], sh[3]));
 }
 
-// max of F over positions [b, n): the partial block at b plus whole blocks
-__global__ void k_suffix_max(const int64_t* F, const long long* bmax, int64_t b, int64_t n, int64_t nblk,
-                             long long* out) {
-    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
-    const int64_t bend = min(n, (b / kFB + 1) * kFB);
-    const int64_t npart = bend - b;
-    long long mx = LLONG_MIN;
-    if (i < npart) {
-        mx = F[b + i];
-    } else {
-        const int64_t blk = b / kFB + 1 + (i - npart);
-        if (blk < nblk) mx = bmax[blk];
+// ------------------------------------------- the whole scan on the device
+// One cooperative launch runs every round of the scan: all workgroups are
+// resident (cooperative launch), they work through each phase together and
+// meet at a grid barrier between phases.  Every decision (next candidate,
+// accept, stop) is computed by every workgroup from the same global values
+// read after a barrier, so control flow is uniform and every workgroup
+// reaches every barrier.  Cross-workgroup reductions go through per-workgroup
+// partial records, double-buffered by phase parity.  Barrier waits are
+// bounded: past the spin limit a workgroup raises the error flag and leaves
+// the wait, so the kernel always ends (the host then reports the error).
+constexpr int kRT = 512;                 // threads per workgroup of the scan
+constexpr int kRW = kRT / 64;
+constexpr int64_t kSearchWin = 1 << 15;  // positions searched per phase
+constexpr unsigned kSpinLimit = 1u << 26;
+#ifndef LDS_SCAN_MAX_WG
+#define LDS_SCAN_MAX_WG 32
+#endif
+constexpr int kScanMaxWG = LDS_SCAN_MAX_WG;
+
+struct ScanArgs {
+    PassArgs a;
+    const int32_t* order;
+    const uint8_t* inI;
+    const int64_t* R;
+    int64_t* T;
+    int64_t* F;
+    int64_t* V;            // restricted loads of the pending group, by position
+    long long* bmax;
+    int64_t nblk;
+    int64_t n;
+    int64_t* lo;           // bounds by internal vertex
+    int64_t* hi;
+    int64_t* groups;       // (start, end) per accepted group
+    int64_t* info;         // [0] groups, [1] rounds, [2] verifications, [3] error flag
+    long long* part;       // 2 * gridDim * 4 partial records
+    unsigned* bar;         // [0] arrivals, [1] generation
+};
+
+// Only thread 0 of a workgroup makes the device-scope release / acquire: on
+// a chip with several L2s these write back and invalidate the caches, which
+// the workgroup's threads share; the others order their accesses against it
+// with the workgroup barrier.
+__device__ inline void grid_barrier(const ScanArgs& g, unsigned nwg, int64_t* err) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __syncthreads();
+    if (nwg == 1) {  // one workgroup: its own barrier is enough
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        return;
     }
-    for (int m = 32; m > 0; m >>= 1) mx = max(mx, (long long)shfl_xor_i64(mx, m));
-    if ((threadIdx.x & 63) == 0 && mx != LLONG_MIN) atomicMax(out, mx);
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const unsigned gen = __hip_atomic_load(g.bar + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned arrived = __hip_atomic_fetch_add(g.bar, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (arrived == nwg - 1) {
+            __hip_atomic_store(g.bar, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(g.bar + 1, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            unsigned spins = 0;
+            while (__hip_atomic_load(g.bar + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > kSpinLimit) {
+                    *err = 1;
+                    break;
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// reduce the partial records of phase `ph` (4 values per workgroup: min,
+// max, max, min) into sh[0..3]
+__device__ inline void gather_partials(const ScanArgs& g, int ph, unsigned nwg, long long* sh) {
+    if (threadIdx.x < 64) {
+        long long v0 = LLONG_MAX, v1 = LLONG_MIN, v2 = LLONG_MIN, v3 = LLONG_MAX;
+        const long long* P = g.part + (int64_t)(ph & 1) * nwg * 4;
+        for (unsigned w = threadIdx.x; w < nwg; w += 64) {
+            v0 = min(v0, P[4 * w]);
+            v1 = max(v1, P[4 * w + 1]);
+            v2 = max(v2, P[4 * w + 2]);
+            v3 = min(v3, P[4 * w + 3]);
+        }
+        for (int m = 32; m > 0; m >>= 1) {
+            v0 = min(v0, (long long)shfl_xor_i64(v0, m));
+            v1 = max(v1, (long long)shfl_xor_i64(v1, m));
+            v2 = max(v2, (long long)shfl_xor_i64(v2, m));
+            v3 = min(v3, (long long)shfl_xor_i64(v3, m));
+        }
+        if (threadIdx.x == 0) {
+            sh[0] = v0;
+            sh[1] = v1;
+            sh[2] = v2;
+            sh[3] = v3;
+        }
+    }
+    __syncthreads();
+}
+
+// this workgroup's partial record of phase `ph` from per-thread values
+__device__ inline void put_partial(const ScanArgs& g, int ph, long long v0, long long v1, long long v2, long long v3,
+                                   long long (*sred)[4]) {
+    for (int m = 32; m > 0; m >>= 1) {
+        v0 = min(v0, (long long)shfl_xor_i64(v0, m));
+        v1 = max(v1, (long long)shfl_xor_i64(v1, m));
+        v2 = max(v2, (long long)shfl_xor_i64(v2, m));
+        v3 = min(v3, (long long)shfl_xor_i64(v3, m));
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+        sred[w][0] = v0;
+        sred[w][1] = v1;
+        sred[w][2] = v2;
+        sred[w][3] = v3;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < kRW; ++q) {
+            v0 = min(v0, sred[q][0]);
+            v1 = max(v1, sred[q][1]);
+            v2 = max(v2, sred[q][2]);
+            v3 = min(v3, sred[q][3]);
+        }
+        v0 = min(v0, sred[0][0]);
+        v1 = max(v1, sred[0][1]);
+        v2 = max(v2, sred[0][2]);
+        v3 = min(v3, sred[0][3]);
+        long long* P = g.part + ((int64_t)(ph & 1) * gridDim.x + blockIdx.x) * 4;
+        P[0] = v0;
+        P[1] = v1;
+        P[2] = v2;
+        P[3] = v3;
+    }
+    __syncthreads();
+}
+
+template <int H>
+__global__ __launch_bounds__(kRT) void k_sg_scan(ScanArgs g) {
+    __shared__ long long sred[kRW][4];
+    __shared__ long long sh[4];
+    __shared__ int64_t s_err;
+    const PassArgs& a = g.a;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const unsigned nwg = gridDim.x;
+    const int64_t gw = (int64_t)blockIdx.x * kRW + w;     // global wave index
+    const int64_t nwave = (int64_t)nwg * kRW;
+    const int64_t gt = (int64_t)blockIdx.x * kRT + threadIdx.x;
+    const int64_t nthr = (int64_t)nwg * kRT;
+    const int64_t n = g.n;
+    if (threadIdx.x == 0) s_err = 0;
+    __syncthreads();
+    int ph = 0;
+    int64_t S0 = 0, fb = 0, ng = 0, rounds = 0, verifs = 0;
+    long long minH = 0;
+    bool hasH = false;
+    bool failed = false;
+    while (S0 < n && !failed) {
+        ++rounds;
+        bool accepted = false, stop = false;
+        int64_t from = S0, accb = -1;
+        int64_t vb = S0;  // V holds the restricted loads of [S0, vb) for the boundary vb
+        long long mnS = 0, mxS = 0;
+        while (!accepted && !stop && from < n && !failed) {
+            // phase: first event in [from, from + win): a stop position
+            // (T >= minH) or a candidate boundary
+            const int64_t hi = min(n, from + kSearchWin);
+            long long first = LLONG_MAX;
+            for (int64_t j = from + gt; j < hi; j += nthr) {
+                bool ev = hasH && g.T[j] >= minH;
+                if (!ev && g.inI[j]) ev = (j + 1 == n) || (g.R[j + 1] < g.T[j]);
+                if (ev) {
+                    first = j;
+                    break;  // later positions of this thread are larger
+                }
+            }
+            put_partial(g, ph, first, LLONG_MIN, LLONG_MIN, LLONG_MAX, sred);
+            grid_barrier(g, nwg, &s_err);
+            gather_partials(g, ph, nwg, sh);
+            ++ph;
+            failed = s_err != 0;
+            const long long e = sh[0];
+            if (failed) break;
+            if (e == LLONG_MAX) {
+                from = hi;
+                continue;
+            }
+            if (hasH && g.T[e] >= minH) {
+                stop = true;  // no boundary at or after e can pass
+                break;
+            }
+            const int64_t b = e + 1;
+            ++verifs;
+            // phase: advance the loads below the boundary to b, and the
+            // restricted loads of the pending group S = [S0, b): positions
+            // [vb, b) join S (their loads in full), and the patterns they
+            // share with earlier members change those members' loads
+            if (b > fb) {
+                for (int64_t j = fb + gw; j < b; j += nwave) {
+                    const int32_t y = g.order[j];
+                    const int64_t r = row_of_vertex(a, y);
+                    if (r < 0) continue;
+                    for (int64_t s = a.rp[r] + lane; s < a.rp[r + 1]; s += 64) {
+                        int64_t p[H], al[H];
+                        int32_t id[H];
+                        load_pattern<H>(a, s, y, p, al, id);
+                        bool owner = true;
+#pragma unroll
+                        for (int i = 1; i < H; ++i)
+                            if (p[i] >= fb && p[i] < b && p[i] > p[0]) owner = false;
+                        if (!owner) continue;
+#pragma unroll
+                        for (int i = 1; i < H; ++i) {
+                            if (p[i] < b) continue;
+                            const int64_t before = pat_contrib<H>(i, p, al, a.D, fb, fb);
+                            const int64_t after = pat_contrib<H>(i, p, al, a.D, b, b);
+                            if (after != before) {
+                                const unsigned long long old = atomicAdd((unsigned long long*)&g.F[p[i]],
+                                                                         (unsigned long long)(after - before));
+                                atomicMax(&g.bmax[p[i] / kFB], (long long)(old + (unsigned long long)(after - before)));
+                            }
+                        }
+                    }
+                }
+                fb = b;
+            }
+            for (int64_t j = vb + gw; j < b; j += nwave) {
+                const int32_t x = g.order[j];
+                const int64_t r = row_of_vertex(a, x);
+                int64_t acc = 0;
+                if (r >= 0) {
+                    for (int64_t s = a.rp[r] + lane; s < a.rp[r + 1]; s += 64) {
+                        int64_t p[H], al[H];
+                        int32_t id[H];
+                        load_pattern<H>(a, s, x, p, al, id);
+                        acc += pat_contrib<H>(0, p, al, a.D, S0, b);
+                        bool owner = true;  // x is the latest joining member of the pattern
+#pragma unroll
+                        for (int i = 1; i < H; ++i)
+                            if (p[i] >= vb && p[i] < b && p[i] > p[0]) owner = false;
+                        if (!owner) continue;
+#pragma unroll
+                        for (int i = 1; i < H; ++i) {
+                            if (p[i] < S0 || p[i] >= vb) continue;
+                            const int64_t before = pat_contrib<H>(i, p, al, a.D, S0, vb);
+                            const int64_t after = pat_contrib<H>(i, p, al, a.D, S0, b);
+                            if (after != before)
+                                atomicAdd((unsigned long long*)&g.V[p[i]], (unsigned long long)(after - before));
+                        }
+                    }
+                    for (int m = 32; m > 0; m >>= 1) acc += shfl_xor_i64(acc, m);
+                }
+                if (lane == 0) g.V[j] = acc;
+            }
+            vb = b;
+            grid_barrier(g, nwg, &s_err);
+            // phase: min and max of the restricted loads of S, and the
+            // largest restricted load below b
+            long long vmn = LLONG_MAX, vmx = LLONG_MIN, fmx = LLONG_MIN;
+            for (int64_t j = S0 + gt; j < b; j += nthr) {
+                const long long v = (long long)g.V[j];
+                vmn = min(vmn, v);
+                vmx = max(vmx, v);
+            }
+            if (b < n) {
+                const int64_t bend = min(n, (b / kFB + 1) * kFB);
+                for (int64_t j = b + gt; j < bend; j += nthr) fmx = max(fmx, (long long)g.F[j]);
+                for (int64_t blk = b / kFB + 1 + gt; blk < g.nblk; blk += nthr) fmx = max(fmx, g.bmax[blk]);
+            }
+            put_partial(g, ph, vmn, vmx, fmx, LLONG_MAX, sred);
+            grid_barrier(g, nwg, &s_err);
+            gather_partials(g, ph, nwg, sh);
+            ++ph;
+            failed = s_err != 0;
+            if (failed) break;
+            mnS = sh[0];
+            mxS = sh[1];
+            const long long below = sh[2];
+            bool ok = !(hasH && !(mxS < minH));
+            ok = ok && (b == n || below < mnS);
+            if (ok) {
+                accepted = true;
+                accb = b;
+            } else {
+                from = b;  // resume after the boundary examined
+            }
+        }
+        if (!accepted || failed) break;  // the rest is never accepted: no bounds
+        const int64_t b = accb;
+        // phase: bounds of the accepted group and the change of T below it
+        for (int64_t j = S0 + gt; j < b; j += nthr) {
+            g.lo[g.order[j]] = mnS;
+            g.hi[g.order[j]] = mxS;
+        }
+        for (int64_t j = S0 + gw; j < b; j += nwave) {
+            const int32_t x = g.order[j];
+            const int64_t r = row_of_vertex(a, x);
+            if (r < 0) continue;
+            for (int64_t s = a.rp[r] + lane; s < a.rp[r + 1]; s += 64) {
+                int64_t p[H], al[H];
+                int32_t id[H];
+                load_pattern<H>(a, s, x, p, al, id);
+                bool owner = true;
+#pragma unroll
+                for (int i = 1; i < H; ++i)
+                    if (p[i] >= S0 && p[i] < b && p[i] > p[0]) owner = false;
+                if (!owner) continue;
+#pragma unroll
+                for (int i = 1; i < H; ++i) {
+                    if (p[i] < b) continue;
+                    const int64_t before = pat_contrib<H>(i, p, al, a.D, S0, p[i] + 1);
+                    const int64_t after = pat_contrib<H>(i, p, al, a.D, b, p[i] + 1);
+                    if (after != before)
+                        atomicAdd((unsigned long long*)&g.T[p[i]], (unsigned long long)(after - before));
+                }
+            }
+        }
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            g.groups[2 * ng] = S0;
+            g.groups[2 * ng + 1] = b;
+        }
+        ++ng;
+        grid_barrier(g, nwg, &s_err);
+        failed = s_err != 0;
+        minH = mnS;
+        hasH = true;
+        S0 = b;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        g.info[0] = ng;
+        g.info[1] = rounds;
+        g.info[2] = verifs;
+    }
+    if (threadIdx.x == 0 && s_err) g.info[3] = 1;
 }
 
 template <int H>
@@ -642,24 +830,13 @@ void sg_sort_prefix(Graph& g, int mode, hipStream_t s) {
     td.alloc(tiles, s);
     k_tile_fmax<<<grid_for(tiles, 1), kT, 0, s>>>(q.E.p, n, tn.p, td.p);
     LDS_HIP(hipGetLastError());
-    std::vector<int64_t> hn(tiles), hd(tiles), cn(tiles), cd(tiles);
-    LDS_HIP(hipMemcpyAsync(hn.data(), tn.p, tiles * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    LDS_HIP(hipMemcpyAsync(hd.data(), td.p, tiles * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    LDS_HIP(hipStreamSynchronize(s));
-    {
-        int64_t rn = 0, rd = 0;  // max over later tiles (den 0: minus infinity)
-        for (int64_t t = tiles - 1; t >= 0; --t) {
-            cn[t] = rn;
-            cd[t] = rd;
-            const bool gt = (rd == 0) ? hd[t] != 0 : (hd[t] != 0 && (__int128)hn[t] * rd > (__int128)rn * hd[t]);
-            if (gt) { rn = hn[t]; rd = hd[t]; }
-        }
-    }
-    LDS_HIP(hipMemcpyAsync(tn.p, cn.data(), tiles * sizeof(int64_t), hipMemcpyHostToDevice, s));
-    LDS_HIP(hipMemcpyAsync(td.p, cd.data(), tiles * sizeof(int64_t), hipMemcpyHostToDevice, s));
-    k_tile_inI<<<grid_for(tiles, 1), kT, 0, s>>>(q.E.p, n, tn.p, td.p, q.inI.p);
+    DBuf<int64_t> cn, cd;
+    cn.alloc(tiles, s);
+    cd.alloc(tiles, s);
+    k_tile_carry<<<1, 64, 0, s>>>(tn.p, td.p, tiles, cn.p, cd.p);
     LDS_HIP(hipGetLastError());
-    LDS_HIP(hipStreamSynchronize(s));
+    k_tile_inI<<<grid_for(tiles, 1), kT, 0, s>>>(q.E.p, n, cn.p, cd.p, q.inI.p);
+    LDS_HIP(hipGetLastError());
     q.valid = true;
     q.gstart.clear();
     q.gend.clear();
@@ -678,13 +855,11 @@ void sg_stable_groups(Graph& g, int mode, hipStream_t s) {
     if (n == 0) return;
     k_fill_i64<<<grid_for(n, kT), kT, 0, s>>>(q.lo.p, n, -1);
     k_fill_i64<<<grid_for(n, kT), kT, 0, s>>>(q.hi.p, n, -1);
-    DBuf<int64_t> R, T, V;
+    DBuf<int64_t> R, T;
     R.alloc(n, s);
     T.alloc(n, s);
-    V.alloc(n, s);
     k_fill_i64<<<grid_for(n, kT), kT, 0, s>>>(R.p, n, 0);
     k_fill_i64<<<grid_for(n, kT), kT, 0, s>>>(T.p, n, 0);
-    k_fill_i64<<<grid_for(n, kT), kT, 0, s>>>(V.p, n, 0);
     LDS_HIP(hipGetLastError());
     PassArgs a{};
     a.a_slot = q.a_slot.p;
@@ -695,136 +870,79 @@ void sg_stable_groups(Graph& g, int mode, hipStream_t s) {
     a.kind = PASS_R;
     a.out = R.p;
     run_pass(g, mode, a, s);
-    // T_x for S0 = 0; afterwards maintained incrementally (k_tdelta)
+    // T_x for S0 = 0; afterwards maintained incrementally by the scan
     a.kind = PASS_T;
     a.S0 = 0;
     a.out = T.p;
     run_pass(g, mode, a, s);
     a = plan_args(g, mode, a);
 
-    constexpr int64_t kCap = 256;       // candidates copied to the host per batch
-    constexpr int64_t kWin = 1 << 16;   // positions searched per window
-    DBuf<unsigned long long> first;
-    DBuf<long long> mm;
-    DBuf<uint32_t> flag;
-    DBuf<uint64_t> off, total;
-    DBuf<int64_t> list;
-    first.alloc(1, s);
-    mm.alloc(4, s);
-    flag.alloc(kWin, s);
-    off.alloc(kWin, s);
-    total.alloc(1, s);
-    list.alloc(kCap, s);
-    int64_t S0 = 0, minH = -1;
-    std::vector<int64_t> cand;
-    auto launch_list = [&](const int64_t* lst, int64_t lo, int64_t cnt) {
-        if (cnt <= 0) return;
-        if (mode == 2)
-            k_listpass<2><<<grid_for(cnt, 4), kT, 0, s>>>(a, lst, lo, cnt, q.order.p, V.p);
-        else
-            k_listpass<3><<<grid_for(cnt, 4), kT, 0, s>>>(a, lst, lo, cnt, q.order.p, V.p);
-        LDS_HIP(hipGetLastError());
-    };
-    // below-boundary restricted loads F, advanced monotonically with b
-    DBuf<int64_t> F;
-    DBuf<long long> bmax;
+    // the round loop: one cooperative launch
     const int64_t nblk = (n + kFB - 1) / kFB;
+    DBuf<int64_t> F, Vb, groups, info;
+    DBuf<long long> bmax, part;
+    DBuf<unsigned> bar;
     F.alloc(n, s);
+    Vb.alloc(n, s);
     bmax.alloc(nblk, s);
     k_f_init<<<grid_for(n, kT), kT, 0, s>>>(f.K[f.cur].p, q.order.p, n, g.idbits, F.p);
     k_bmax_init<<<grid_for(nblk, 1), kT, 0, s>>>(F.p, n, bmax.p);
     LDS_HIP(hipGetLastError());
-    int64_t fb = 0;  // F reflects "positions < fb are above"
-    // exact test of S = [S0, b); fills (min_S, max_S)
-    auto verify = [&](int64_t b, long long* mnS, long long* mxS) -> bool {
-        ++q.verifications;
-        const long long init[4] = {LLONG_MAX, LLONG_MIN, LLONG_MIN, LLONG_MIN};
-        LDS_HIP(hipMemcpyAsync(mm.p, init, sizeof(init), hipMemcpyHostToDevice, s));
-        if (b > fb) {
-            if (mode == 2)
-                k_fdelta<2><<<grid_for(b - fb, 4), kT, 0, s>>>(a, fb, b, q.order.p, F.p, bmax.p);
-            else
-                k_fdelta<3><<<grid_for(b - fb, 4), kT, 0, s>>>(a, fb, b, q.order.p, F.p, bmax.p);
-            LDS_HIP(hipGetLastError());
-            fb = b;
-        }
-        if (b < n) {
-            const int64_t cnt = (std::min<int64_t>(n, (b / kFB + 1) * kFB) - b) + (nblk - (b / kFB + 1));
-            k_suffix_max<<<grid_for(cnt, kT), kT, 0, s>>>(F.p, bmax.p, b, n, nblk, mm.p + 2);
-            LDS_HIP(hipGetLastError());
-        }
-        a.S0 = S0;
-        a.b = b;
-        launch_list(nullptr, S0, b - S0);
-        k_minmax<<<grid_for(b - S0, kT), kT, 0, s>>>(V.p, S0, b, mm.p);
-        LDS_HIP(hipGetLastError());
-        long long h[4];
-        LDS_HIP(hipMemcpyAsync(h, mm.p, sizeof(h), hipMemcpyDeviceToHost, s));
-        LDS_HIP(hipStreamSynchronize(s));
-        *mnS = h[0];
-        *mxS = h[1];
-        if (minH >= 0 && !(h[1] < minH)) return false;
-        return b == n || h[2] < h[0];  // max over the vertices below < min_S
-    };
-    while (S0 < n) {
-        ++q.rounds;
-        bool accepted = false, stop = false;
-        int64_t from = S0;
-        long long mnS = 0, mxS = 0;
-        int64_t acc_b = -1;
-        while (!accepted && !stop && from < n) {
-            const int64_t hi = std::min(n, from + kWin);
-            // first j in [from, hi) with T_j >= minH: every boundary after it fails
-            int64_t jst = hi;
-            if (minH >= 0) {
-                const unsigned long long init = ~0ull;
-                LDS_HIP(hipMemcpyAsync(first.p, &init, sizeof(init), hipMemcpyHostToDevice, s));
-                k_first_ge<<<grid_for(hi - from, kT), kT, 0, s>>>(T.p, from, hi, minH, first.p);
-                LDS_HIP(hipGetLastError());
-                const unsigned long long r = d2h(first.p, s);
-                if (r != ~0ull) {
-                    jst = (int64_t)r;
-                    stop = true;
-                }
-            }
-            int64_t lo = from;
-            while (!accepted && lo < jst) {
-                const int64_t cnt = jst - lo;
-                k_cand_flags<<<grid_for(cnt, kT), kT, 0, s>>>(q.inI.p, R.p, T.p, lo, jst, n, flag.p);
-                LDS_HIP(hipGetLastError());
-                exclusive_scan_u32_to_u64(flag.p, off.p, cnt, total.p, s);
-                k_cand_compact<<<grid_for(cnt, kT), kT, 0, s>>>(flag.p, off.p, lo, cnt, list.p, kCap);
-                LDS_HIP(hipGetLastError());
-                const int64_t nc = (int64_t)d2h(total.p, s);
-                if (nc == 0) break;
-                const int64_t take = std::min(nc, kCap);
-                cand.resize(take);
-                LDS_HIP(hipMemcpyAsync(cand.data(), list.p, take * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-                LDS_HIP(hipStreamSynchronize(s));
-                for (int64_t ci = 0; ci < take && !accepted; ++ci) {
-                    if (verify(cand[ci], &mnS, &mxS)) {
-                        accepted = true;
-                        acc_b = cand[ci];
-                    }
-                }
-                if (!accepted) lo = cand[take - 1];  // resume after the last boundary examined
-            }
-            from = hi;
-        }
-        if (!accepted) break;  // the remaining tail is never accepted: no bounds
-        const int64_t b = acc_b;
-        k_set_bounds<<<grid_for(b - S0, kT), kT, 0, s>>>(q.order.p, S0, b, mnS, mxS, q.lo.p, q.hi.p);
-        if (mode == 2)
-            k_tdelta<2><<<grid_for(b - S0, 4), kT, 0, s>>>(a, S0, b, q.order.p, T.p);
-        else
-            k_tdelta<3><<<grid_for(b - S0, 4), kT, 0, s>>>(a, S0, b, q.order.p, T.p);
-        LDS_HIP(hipGetLastError());
-        q.gstart.push_back(S0);
-        q.gend.push_back(b);
-        minH = mnS;
-        S0 = b;
+    static int cus = 0, per[2] = {0, 0};
+    if (!cus) {
+        int dev = 0;
+        LDS_HIP(hipGetDevice(&dev));
+        LDS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        LDS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[0], k_sg_scan<2>, kRT, 0));
+        LDS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[1], k_sg_scan<3>, kRT, 0));
     }
+    const int64_t resident = (int64_t)cus * std::max(1, per[mode == 2 ? 0 : 1]);
+    // few workgroups: each phase is small, and a barrier costs more the more
+    // workgroups meet at it
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>({resident, (int64_t)kScanMaxWG, (n + 16383) / 16384}));
+    groups.alloc(2 * n, s);
+    info.alloc(4, s);
+    part.alloc((size_t)2 * grid * 4, s);
+    bar.alloc(2, s);
+    k_fill_i64<<<1, kT, 0, s>>>(info.p, 4, 0);
+    k_fill_i64<<<1, kT, 0, s>>>((int64_t*)bar.p, 1, 0);
+    LDS_HIP(hipGetLastError());
+    ScanArgs sa{};
+    sa.a = a;
+    sa.order = q.order.p;
+    sa.inI = q.inI.p;
+    sa.R = R.p;
+    sa.T = T.p;
+    sa.F = F.p;
+    sa.V = Vb.p;
+    sa.bmax = bmax.p;
+    sa.nblk = nblk;
+    sa.n = n;
+    sa.lo = q.lo.p;
+    sa.hi = q.hi.p;
+    sa.groups = groups.p;
+    sa.info = info.p;
+    sa.part = part.p;
+    sa.bar = bar.p;
+    void* kargs[] = {&sa};
+    LDS_HIP(hipLaunchCooperativeKernel(mode == 2 ? (const void*)k_sg_scan<2> : (const void*)k_sg_scan<3>,
+                                       dim3((unsigned)grid), dim3(kRT), kargs, 0, s));
+    int64_t hinfo[4];
+    LDS_HIP(hipMemcpyAsync(hinfo, info.p, sizeof(hinfo), hipMemcpyDeviceToHost, s));
     LDS_HIP(hipStreamSynchronize(s));
+    LDS_CHECK(hinfo[3] == 0, ST_DEVICE, "stable-group scan: a grid barrier did not complete");
+    const int64_t ng = hinfo[0];
+    q.rounds = hinfo[1];
+    q.verifications = hinfo[2];
+    std::vector<int64_t> hg((size_t)2 * ng);
+    if (ng > 0) {
+        LDS_HIP(hipMemcpyAsync(hg.data(), groups.p, hg.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        LDS_HIP(hipStreamSynchronize(s));
+    }
+    for (int64_t i = 0; i < ng; ++i) {
+        q.gstart.push_back(hg[2 * i]);
+        q.gend.push_back(hg[2 * i + 1]);
+    }
 }
 
 }  // namespace lds

@@ -408,11 +408,12 @@ struct CandLess {
 };
 
 struct Ctx {
+    explicit Ctx(const HostGraph& hg) : h(hg) {}
     Graph* g = nullptr;
     int mode = 2;
     int iters = 0;
     hipStream_t s = nullptr;
-    HostGraph h;
+    const HostGraph& h;
     std::vector<Frac> lo, hi;     // bounds on phi_G, valid for every vertex
     std::vector<int32_t> loc;     // scratch: internal id -> local index, -1 outside
     std::vector<int32_t> mark;    // scratch, -1 outside
@@ -698,20 +699,31 @@ void topk_run(Graph& g, int mode, int k, int iters, hipStream_t s, std::vector<T
     const int64_t n = g.n;
     if (n == 0) return;
     if (mode == 3 && g.T < 0) list_triangles(g, s);
-    Ctx c;
+    // host data of the graph (built once, kept with the graph)
+    if (!g.host) {
+        auto hc = std::make_shared<HostCache>();
+        hc->h.load(g, mode, s);
+        hc->tri_loaded = (mode == 3);
+        g.host = hc;
+    } else if (mode == 3 && !g.host->tri_loaded) {
+        g.host->h.load(g, 3, s);
+        g.host->tri_loaded = true;
+    }
+    HostCache& hc = *g.host;
+    Ctx c(hc.h);
     c.g = &g;
     c.mode = mode;
     c.iters = iters;
     c.s = s;
     c.st = &st;
-    c.h.load(g, mode, s);
     c.loc.assign(n, -1);
     c.mark.assign(n, -1);
     std::vector<char> alive(n, 1);
     lap(&st.ms_copy);
     // bounds from core (tr-core) numbers
     {
-        const std::vector<int32_t> core = (mode == 2) ? core_numbers(c.h, alive) : trcore_numbers(c.h, alive);
+        std::vector<int32_t>& core = hc.core[mode == 2 ? 0 : 1];
+        if (core.empty()) core = (mode == 2) ? core_numbers(c.h, alive) : trcore_numbers(c.h, alive);
         c.lo.resize(n);
         c.hi.resize(n);
         for (int64_t u = 0; u < n; ++u) {

@@ -19,6 +19,15 @@ struct HostGraph {
     void load(const Graph& g, int mode, hipStream_t s);
 };
 
+// Per-graph host data that does not depend on a query: the adjacency (and
+// triangles once a triangle query has run) and the core / tr-core numbers of
+// the whole graph.  Built by the first top-k call and kept with the graph.
+struct HostCache {
+    HostGraph h;
+    bool tri_loaded = false;
+    std::vector<int32_t> core[2];  // [0] core numbers, [1] tr-core numbers (empty until computed)
+};
+
 struct TopkSet {
     int64_t num = 0, den = 1;        // reduced exact density
     std::vector<int32_t> vertices;   // caller ids, ascending

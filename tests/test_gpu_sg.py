@@ -94,3 +94,22 @@ def test_requires_fw_state():
     g = lds.lds_create_graph(3, np.array([0, 1], np.int32), np.array([1, 2], np.int32))
     with pytest.raises(lds.LdsError):
         lds.lds_sort_prefix(g, 2)
+
+
+def test_edge_state_survives_triangle_listing():
+    """Listing triangles after an edge run leaves the edge state usable: the
+    edge slot order is fixed at ingest."""
+    announce("sg edge state after triangle listing")
+    n, s, d = synth.powerlaw_planted(1500, 2.2, 10.0, n_blocks=4, s_lo=20, s_hi=40, p_block=0.5, seed=11)
+    g = lds.lds_create_graph(n, s, d)
+    lds.lds_frank_wolfe(g, 2, 30)
+    lds.lds_triangles(g)
+    h = lds.lds_create_graph(n, s, d)
+    lds.lds_frank_wolfe(h, 2, 30)
+    for a, b in zip(lds.lds_splits(g, 2), lds.lds_splits(h, 2)):
+        np.testing.assert_array_equal(a, b)
+    ga, lo_a, hi_a = lds.lds_stable_groups(g, 2)
+    gb, lo_b, hi_b = lds.lds_stable_groups(h, 2)
+    assert ga == gb
+    np.testing.assert_array_equal(lo_a, lo_b)
+    np.testing.assert_array_equal(hi_a, hi_b)
