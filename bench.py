@@ -50,6 +50,116 @@ def measured_traffic(workload):
     return float(b.group(1))
 
 
+def bench_batched(lds, torch, synth, np, count):
+    """The uneven-batch workload: graph g = batch member g (seed 1000 + g),
+    even g edge density with 100 FW iterations, odd g triangle density with
+    200.  Batched: one run of the captured persistent launch (tuned launch
+    shape); plain: lds_frank_wolfe graph by graph.  Both start from the
+    canonical initial point; the loads must agree bit for bit."""
+    log("batched: %d graphs" % count)
+    ms = []
+    for i in range(count):
+        n, s, d = synth.batch_member(i)
+        mode = 2 if i % 2 == 0 else 3
+        ms.append((n, s, d, mode, 100 if mode == 2 else 200))
+    gs = [lds.lds_create_graph(n, s, d) for n, s, d, _, _ in ms]
+    modes = [m[3] for m in ms]
+    iters = [m[4] for m in ms]
+    cache = os.path.join(ROOT, "paper_2504_10937_amd", "tune_cache.json")
+    tune, tuned_ms = lds.lds_batch_autotune(gs, modes, iters, cache_path=cache, reps=1)
+    log("batched: tune %s (%s)" % (tune.as_dict(), "cached" if tuned_ms < 0 else "timed"))
+    b = lds.lds_batch_create(gs, modes, iters, tune=tune)
+    lds.lds_batch_run(b)
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        lds.lds_batch_run(b)
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / reps
+    info = lds.lds_batch_info(b, want_ms=True)
+    nums = [lds.lds_loads(g, m, want_num=True)["num"] for g, m in zip(gs, modes)]
+    t0 = time.perf_counter()
+    for g, m, it in zip(gs, modes, iters):
+        lds.lds_frank_wolfe(g, m, it)
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    same = all(np.array_equal(lds.lds_loads(g, m, want_num=True)["num"], a) for g, m, a in zip(gs, modes, nums))
+    work = sum((lds.lds_sweep_info(g, m)["slots"]) * it for g, m, it in zip(gs, modes, iters))
+    for g in gs:
+        g.destroy()
+    del b
+    res = {"graphs": count, "batched_graphs_per_s": count / tb, "plain_graphs_per_s": count / tp,
+           "speedup": tp / tb, "batched_ms": tb * 1e3, "plain_ms": tp * 1e3, "kernel_ms": info["kernel_ms"],
+           "kernel_graphs": info["kernel_graphs"], "plain_path_graphs": info["plain_graphs"],
+           "incidence_updates_per_s": work / tb, "bit_identical": same, "tune": info["tune"]}
+    log("batched: %.1f ms vs plain %.1f ms (x%.1f), identical %s" % (tb * 1e3, tp * 1e3, tp / tb, same))
+    return res
+
+
+def _serve_run(lds, np, srv, gs, pool_n, seconds, qps, seed, tag0):
+    import synth
+    q = synth.queries(int(seconds * qps * 1.5) + 16, qps=qps, pool=len(gs), kmax=10, seed=seed)
+    ta = q["t_arrive"]
+    n = int((ta < seconds).sum())
+    base = lds.lds_server_clock(srv)
+    done = []
+    i = 0
+    while len(done) < n:
+        now = lds.lds_server_clock(srv) - base
+        while i < n and ta[i] <= now:
+            mode = int(q["mode"][i])
+            lds.lds_server_submit(srv, gs[int(q["graph"][i])], mode, int(q["k"][i]), 100 if mode == 2 else 200,
+                                  tag0 + i, base + float(ta[i]))
+            i += 1
+        wait = min(0.05, max(0.0, float(ta[i]) - now)) if i < n else 0.2
+        done.extend(lds.lds_server_poll(srv, 256, wait))
+    lat = np.array([c["t_done"] - c["t_arrive"] for c in done])
+    span = max(c["t_done"] for c in done) - base
+    errs = sum(c["status"] != 0 for c in done)
+    return {"offered_qps": qps, "arrival_window_s": seconds, "queries": n, "errors": errs,
+            "completed_per_s": n / span, "p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "p99_ms": float(np.percentile(lat, 99) * 1e3), "max_ms": float(lat.max() * 1e3)}
+
+
+def bench_serving(lds, torch, synth, np, seconds, qps, low_qps):
+    """The serving workload: a resident pool of 64 graphs (pool member g,
+    seed 5 + g, graph 0 pinned at n = 2M), Poisson arrivals, graph uniform
+    over the pool, LDS / LTDS half and half (100 / 200 FW iterations), k
+    uniform in 1..10.  Latency = completion - arrival on the server clock."""
+    log("serving: building the pool")
+    pool = [synth.pool_member(i) for i in range(64)]
+    gs = [lds.lds_create_graph(*p) for p in pool]
+    for g in gs:
+        lds.lds_triangles(g)
+    torch.cuda.synchronize()
+    srv = lds.lds_server_create(0, max_slots=64, workers=12)
+    # warm-up: one query per (graph, mode), so that each graph's resident
+    # state (FW buffers, host adjacency and core numbers) exists
+    for i, g in enumerate(gs):
+        for m in (2, 3):
+            lds.lds_server_submit(srv, g, m, 3, 100 if m == 2 else 200, 10 ** 9 + 2 * i + m)
+    got = 0
+    while got < 2 * len(gs):
+        got += len(lds.lds_server_poll(srv, 256, 1.0))
+    res = {"pool_graphs": len(gs), "pool_vertices": int(sum(p[0] for p in pool)),
+           "pool_edges": int(sum(len(p[1]) for p in pool))}
+    log("serving: %g QPS for %g s" % (qps, seconds))
+    res["offered"] = _serve_run(lds, np, srv, gs, [p[0] for p in pool], seconds, qps, 5, 0)
+    log("serving: %s" % res["offered"])
+    if low_qps > 0:
+        res["sustained"] = _serve_run(lds, np, srv, gs, [p[0] for p in pool], max(seconds, 8.0), low_qps, 6, 10 ** 6)
+        log("serving: %s" % res["sustained"])
+    st = lds.lds_server_stats(srv)
+    res["batches"] = st["batches"]
+    res["max_batch"] = st["max_batch"]
+    res["peak_inflight_bytes"] = st["peak_inflight_bytes"]
+    lds.lds_server_destroy(srv)
+    for g in gs:
+        g.destroy()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -62,6 +172,12 @@ def main():
     ap.add_argument("--iters", type=int, default=0, help="override the workload's FW iteration count")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="first run one device copy of this many MiB (a known-size kernel for counter scaling)")
+    ap.add_argument("--batch-graphs", type=int, default=4096,
+                    help="graphs of the batched-vs-plain comparison (0: skip)")
+    ap.add_argument("--serve-seconds", type=float, default=5.0, help="arrival window of the serving run (0: skip)")
+    ap.add_argument("--serve-qps", type=float, default=200.0)
+    ap.add_argument("--serve-low-qps", type=float, default=25.0,
+                    help="second serving run at a load the server sustains (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (one process, one MI355X); "
@@ -159,6 +275,10 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "alg_bytes_per_launch": alg_bytes, "kernel": "k_fw_sweep"},
     }
+    if args.batch_graphs > 0:
+        out["batched"] = bench_batched(lds, torch, synth, np, args.batch_graphs)
+    if args.serve_seconds > 0:
+        out["serving"] = bench_serving(lds, torch, synth, np, args.serve_seconds, args.serve_qps, args.serve_low_qps)
     if not args.no_cpu_baseline:
         import oracle
         log("cpu baseline: oracle ingest (untimed)")

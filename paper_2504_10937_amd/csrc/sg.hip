@@ -924,9 +924,17 @@ void sg_stable_groups(Graph& g, int mode, hipStream_t s) {
     sa.info = info.p;
     sa.part = part.p;
     sa.bar = bar.p;
-    void* kargs[] = {&sa};
-    LDS_HIP(hipLaunchCooperativeKernel(mode == 2 ? (const void*)k_sg_scan<2> : (const void*)k_sg_scan<3>,
-                                       dim3((unsigned)grid), dim3(kRT), kargs, 0, s));
+    if (grid == 1) {  // one workgroup needs no co-residency guarantee
+        if (mode == 2)
+            k_sg_scan<2><<<1, kRT, 0, s>>>(sa);
+        else
+            k_sg_scan<3><<<1, kRT, 0, s>>>(sa);
+        LDS_HIP(hipGetLastError());
+    } else {
+        void* kargs[] = {&sa};
+        LDS_HIP(hipLaunchCooperativeKernel(mode == 2 ? (const void*)k_sg_scan<2> : (const void*)k_sg_scan<3>,
+                                           dim3((unsigned)grid), dim3(kRT), kargs, 0, s));
+    }
     int64_t hinfo[4];
     LDS_HIP(hipMemcpyAsync(hinfo, info.p, sizeof(hinfo), hipMemcpyDeviceToHost, s));
     LDS_HIP(hipStreamSynchronize(s));
