@@ -50,7 +50,7 @@ def measured_traffic(workload):
     return float(b.group(1))
 
 
-def bench_batched(lds, torch, synth, np, count):
+def bench_batched(lds, torch, synth, np, count, plain=True):
     """The uneven-batch workload: graph g = batch member g (seed 1000 + g),
     even g edge density with 100 FW iterations, odd g triangle density with
     200.  Batched: one run of the captured persistent launch (tuned launch
@@ -78,13 +78,15 @@ def bench_batched(lds, torch, synth, np, count):
     torch.cuda.synchronize()
     tb = (time.perf_counter() - t0) / reps
     info = lds.lds_batch_info(b, want_ms=True)
-    nums = [lds.lds_loads(g, m, want_num=True)["num"] for g, m in zip(gs, modes)]
-    t0 = time.perf_counter()
-    for g, m, it in zip(gs, modes, iters):
-        lds.lds_frank_wolfe(g, m, it)
-    torch.cuda.synchronize()
-    tp = time.perf_counter() - t0
-    same = all(np.array_equal(lds.lds_loads(g, m, want_num=True)["num"], a) for g, m, a in zip(gs, modes, nums))
+    tp, same = float("nan"), None
+    if plain:
+        nums = [lds.lds_loads(g, m, want_num=True)["num"] for g, m in zip(gs, modes)]
+        t0 = time.perf_counter()
+        for g, m, it in zip(gs, modes, iters):
+            lds.lds_frank_wolfe(g, m, it)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        same = all(np.array_equal(lds.lds_loads(g, m, want_num=True)["num"], a) for g, m, a in zip(gs, modes, nums))
     work = sum((lds.lds_sweep_info(g, m)["slots"]) * it for g, m, it in zip(gs, modes, iters))
     for g in gs:
         g.destroy()
@@ -174,6 +176,8 @@ def main():
                     help="first run one device copy of this many MiB (a known-size kernel for counter scaling)")
     ap.add_argument("--batch-graphs", type=int, default=4096,
                     help="graphs of the batched-vs-plain comparison (0: skip)")
+    ap.add_argument("--no-batch-plain", action="store_true",
+                    help="leave out the per-graph comparison of the batched section (shorter kernel traces)")
     ap.add_argument("--serve-seconds", type=float, default=5.0, help="arrival window of the serving run (0: skip)")
     ap.add_argument("--serve-qps", type=float, default=200.0)
     ap.add_argument("--serve-low-qps", type=float, default=25.0,
@@ -276,7 +280,7 @@ def main():
                      "alg_bytes_per_launch": alg_bytes, "kernel": "k_fw_sweep"},
     }
     if args.batch_graphs > 0:
-        out["batched"] = bench_batched(lds, torch, synth, np, args.batch_graphs)
+        out["batched"] = bench_batched(lds, torch, synth, np, args.batch_graphs, not args.no_batch_plain)
     if args.serve_seconds > 0:
         out["serving"] = bench_serving(lds, torch, synth, np, args.serve_seconds, args.serve_qps, args.serve_low_qps)
     if not args.no_cpu_baseline:

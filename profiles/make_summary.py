@@ -2,6 +2,7 @@
 
 usage: python profiles/make_summary.py <kernel substring> <out.md> <command string>
        <kernel_stats.csv> [<fetch counter_collection.csv> <write counter_collection.csv>]
+       python profiles/make_summary.py --top <N> <out.md> <title> <command string> <kernel_stats.csv>
 
 The FETCH_SIZE / WRITE_SIZE passes must come from runs that first launched a
 device copy of known size (bench.py --copy-calib-mib); the copy's counters
@@ -28,7 +29,22 @@ def copy_value(path, counter):
     return best
 
 
+def top(n, out, title, cmd, stats):
+    rows = list(csv.DictReader(open(stats)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = ["# rocprofv3 --kernel-trace --stats: %s" % title, "", "command: `%s`" % cmd, "",
+             "| kernel | calls | avg us | total ms | % |", "|---|---|---|---|---|"]
+    for r in rows[:n]:
+        name = r["Name"].replace("lds::(anonymous namespace)::", "").split("(")[0][:70]
+        lines.append("| %s | %s | %.1f | %.2f | %.1f |" % (name, r["Calls"], float(r["AverageNs"]) / 1e3,
+                                                         float(r["TotalDurationNs"]) / 1e6, float(r["Percentage"])))
+    open(out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
+    if sys.argv[1] == "--top":
+        return top(int(sys.argv[2]), *sys.argv[3:7])
     kernel, out, cmd, stats = sys.argv[1:5]
     rows = [r for r in csv.DictReader(open(stats)) if kernel in r["Name"]]
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
