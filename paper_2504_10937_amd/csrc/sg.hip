@@ -290,6 +290,11 @@ __global__ void k_tile_carry(const int64_t* tn, const int64_t* td, int64_t tiles
 }
 
 // ------------------------------------------------------ a9 round helpers
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 __global__ void k_fill_i64(int64_t* p, int64_t n, int64_t v) {
     const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
     if (i < n) p[i] = v;
@@ -390,7 +395,7 @@ __global__ __launch_bounds__(kT) void k_bmax_init(const int64_t* F, int64_t n, l
 // the wait, so the kernel always ends (the host then reports the error).
 constexpr int kRT = 512;                 // threads per workgroup of the scan
 constexpr int kRW = kRT / 64;
-constexpr int64_t kSearchWin = 1 << 15;  // positions searched per phase
+constexpr int64_t kSearchWin = 1 << 20;  // largest window of positions searched in one phase
 constexpr unsigned kSpinLimit = 1u << 26;
 #ifndef LDS_SCAN_MAX_WG
 #define LDS_SCAN_MAX_WG 32
@@ -414,7 +419,99 @@ struct ScanArgs {
     int64_t* info;         // [0] groups, [1] rounds, [2] verifications, [3] error flag
     long long* part;       // 2 * gridDim * 4 partial records
     unsigned* bar;         // [0] arrivals, [1] generation
+    // compact records built once per scan (k_slot_records): the row of each
+    // position, and per incidence slot the other vertices' positions and the
+    // split numerators of the pattern, so that a phase streams records
+    // instead of chasing order -> row -> slot -> neighbour -> position
+    const int32_t* rowp;   // row by position, -1 for a vertex without slots
+    const int2* rec2;      // edges: (position of the other end, a_x)
+    const int4* rec3;      // triangles: (position v, position w, a_x, a_v)
+    const uint32_t* rec3w; // triangles: a_w
 };
+
+constexpr int kGL = 16;  // lanes per position in the scan's slot loops
+
+// the pattern at slot s of the vertex at position j, from the records
+template <int H>
+__device__ inline void rec_pattern(const ScanArgs& g, int64_t s, int64_t j, int64_t* p, int64_t* al);
+template <>
+__device__ inline void rec_pattern<2>(const ScanArgs& g, int64_t s, int64_t j, int64_t* p, int64_t* al) {
+    const int2 r = g.rec2[s];
+    p[0] = j;
+    p[1] = r.x;
+    al[0] = (uint32_t)r.y;
+    al[1] = (int64_t)g.a.D - al[0];
+}
+template <>
+__device__ inline void rec_pattern<3>(const ScanArgs& g, int64_t s, int64_t j, int64_t* p, int64_t* al) {
+    const int4 r = g.rec3[s];
+    p[0] = j;
+    p[1] = r.x;
+    p[2] = r.y;
+    al[0] = (uint32_t)r.z;
+    al[1] = (uint32_t)r.w;
+    al[2] = g.rec3w[s];
+}
+
+// Calls f(s, j) for every slot s of the vertices at positions [p0, p1) and
+// then done(j, sum of f) once per position with slots.  Rows with at most
+// kBig slots go to groups of kGL lanes, larger rows to whole waves, so that
+// neither the many short rows nor the few long ones waste lanes.
+constexpr int64_t kBig = 64;
+
+template <class F, class Done>
+__device__ inline void positions_pass(const ScanArgs& g, int64_t p0, int64_t p1, F f, Done done) {
+    const int lane = threadIdx.x & 63;
+    const int lq = threadIdx.x & (kGL - 1);
+    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
+    const int64_t gq = gt / kGL, ngq = nthr / kGL;
+    const int64_t gw = gt / 64, nwave = nthr / 64;
+    // the lanes of a group share j, so they run the same trips and the group
+    // sums read only active lanes
+    for (int64_t j = p0 + gq; j < p1; j += ngq) {
+        const int64_t r = g.rowp[j];
+        if (r < 0) continue;
+        const int64_t s0 = g.a.rp[r], s1 = g.a.rp[r + 1];
+        if (s1 - s0 > kBig) continue;
+        int64_t acc = 0;
+        for (int64_t s = s0 + lq; s < s1; s += kGL) acc += f(s, j);
+        for (int m = kGL / 2; m > 0; m >>= 1) acc += shfl_xor_i64(acc, m);
+        if (lq == 0) done(j, acc);
+    }
+    for (int64_t j = p0 + gw; j < p1; j += nwave) {
+        const int64_t r = g.rowp[j];
+        if (r < 0) continue;
+        const int64_t s0 = g.a.rp[r], s1 = g.a.rp[r + 1];
+        if (s1 - s0 <= kBig) continue;
+        int64_t acc = 0;
+        for (int64_t s = s0 + lane; s < s1; s += 64) acc += f(s, j);
+        for (int m = 32; m > 0; m >>= 1) acc += shfl_xor_i64(acc, m);
+        if (lane == 0) done(j, acc);
+    }
+}
+
+// records of every slot of row r (one wave per row)
+template <int H>
+__global__ __launch_bounds__(kT) void k_slot_records(PassArgs a, int32_t* rowp, int2* rec2, int4* rec3,
+                                                     uint32_t* rec3w) {
+    const int lane = threadIdx.x & 63;
+    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= a.nrows) return;
+    const int32_t x = a.rid ? a.rid[r] : (int32_t)r;
+    if (lane == 0) rowp[a.pos[x]] = (int32_t)r;
+    for (int64_t s = a.rp[r] + lane; s < a.rp[r + 1]; s += 64) {
+        int64_t p[H], al[H];
+        int32_t id[H];
+        load_pattern<H>(a, s, x, p, al, id);
+        if (H == 2) {
+            rec2[s] = make_int2((int)p[1], (int)(uint32_t)al[0]);
+        } else {
+            rec3[s] = make_int4((int)p[1], (int)p[2], (int)(uint32_t)al[0], (int)(uint32_t)al[1]);
+            rec3w[s] = (uint32_t)al[2];
+        }
+    }
+}
 
 // Only thread 0 of a workgroup makes the device-scope release / acquire: on
 // a chip with several L2s these write back and invalidate the caches, which
@@ -515,8 +612,29 @@ __device__ inline void put_partial(const ScanArgs& g, int ph, long long v0, long
     __syncthreads();
 }
 
+// LDS_SCAN_PROF: workgroup 0 accumulates the time of each phase, split into
+// its own work and its barrier wait (info[4..11]); a measurement switch only
+#ifdef LDS_SCAN_PROF
+#define PROF_MARK(k)                                                        \
+    do {                                                                    \
+        if (blockIdx.x == 0 && threadIdx.x == 0) {                          \
+            const uint64_t t_ = __builtin_amdgcn_s_memrealtime();           \
+            prof[k] += t_ - tprev;                                          \
+            tprev = t_;                                                     \
+        }                                                                   \
+    } while (0)
+#else
+#define PROF_MARK(k) \
+    do {             \
+    } while (0)
+#endif
+
 template <int H>
 __global__ __launch_bounds__(kRT) void k_sg_scan(ScanArgs g) {
+#ifdef LDS_SCAN_PROF
+    uint64_t prof[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    uint64_t tprev = __builtin_amdgcn_s_memrealtime();
+#endif
     __shared__ long long sred[kRW][4];
     __shared__ long long sh[4];
     __shared__ int64_t s_err;
@@ -527,6 +645,9 @@ __global__ __launch_bounds__(kRT) void k_sg_scan(ScanArgs g) {
     const int64_t nwave = (int64_t)nwg * kRW;
     const int64_t gt = (int64_t)blockIdx.x * kRT + threadIdx.x;
     const int64_t nthr = (int64_t)nwg * kRT;
+    const int64_t gq = gt / kGL;           // lane group (kGL lanes) index
+    const int64_t ngq = nthr / kGL;
+    const int lq = threadIdx.x & (kGL - 1);
     const int64_t n = g.n;
     if (threadIdx.x == 0) s_err = 0;
     __syncthreads();
@@ -539,12 +660,12 @@ __global__ __launch_bounds__(kRT) void k_sg_scan(ScanArgs g) {
         ++rounds;
         bool accepted = false, stop = false;
         int64_t from = S0, accb = -1;
-        int64_t vb = S0;  // V holds the restricted loads of [S0, vb) for the boundary vb
         long long mnS = 0, mxS = 0;
+        int64_t win = 4 * nthr;  // grows while windows come back empty
         while (!accepted && !stop && from < n && !failed) {
             // phase: first event in [from, from + win): a stop position
             // (T >= minH) or a candidate boundary
-            const int64_t hi = min(n, from + kSearchWin);
+            const int64_t hi = min(n, from + win);
             long long first = LLONG_MAX;
             for (int64_t j = from + gt; j < hi; j += nthr) {
                 bool ev = hasH && g.T[j] >= minH;
@@ -555,7 +676,9 @@ __global__ __launch_bounds__(kRT) void k_sg_scan(ScanArgs g) {
                 }
             }
             put_partial(g, ph, first, LLONG_MIN, LLONG_MIN, LLONG_MAX, sred);
+            PROF_MARK(0);
             grid_barrier(g, nwg, &s_err);
+            PROF_MARK(1);
             gather_partials(g, ph, nwg, sh);
             ++ph;
             failed = s_err != 0;
@@ -563,6 +686,7 @@ __global__ __launch_bounds__(kRT) void k_sg_scan(ScanArgs g) {
             if (failed) break;
             if (e == LLONG_MAX) {
                 from = hi;
+                win = min<int64_t>(2 * win, kSearchWin);
                 continue;
             }
             if (hasH && g.T[e] >= minH) {
@@ -571,69 +695,53 @@ __global__ __launch_bounds__(kRT) void k_sg_scan(ScanArgs g) {
             }
             const int64_t b = e + 1;
             ++verifs;
-            // phase: advance the loads below the boundary to b, and the
-            // restricted loads of the pending group S = [S0, b): positions
-            // [vb, b) join S (their loads in full), and the patterns they
-            // share with earlier members change those members' loads
-            if (b > fb) {
-                for (int64_t j = fb + gw; j < b; j += nwave) {
-                    const int32_t y = g.order[j];
-                    const int64_t r = row_of_vertex(a, y);
-                    if (r < 0) continue;
-                    for (int64_t s = a.rp[r] + lane; s < a.rp[r + 1]; s += 64) {
+            // phase: positions [fb, b) move from below the boundary into the
+            // pending group S = [S0, b).  One walk over their patterns gives
+            // their own restricted loads, advances the loads of the vertices
+            // that stay below b, and changes the loads of S's earlier members
+            // through the patterns they share with the joining vertices (each
+            // pattern handled once, from its latest joining vertex).  The
+            // frontier of the loads below and the end of S always coincide:
+            // both start at the accepted boundary and move to every verified b.
+            {
+                const int64_t f0 = fb;
+                for (int64_t jj = f0 + gt; jj < b; jj += nthr)
+                    if (g.rowp[jj] < 0) g.V[jj] = 0;  // positions without slots have load 0
+                positions_pass(
+                    g, f0, b,
+                    [&](int64_t s, int64_t jj) -> int64_t {
                         int64_t p[H], al[H];
-                        int32_t id[H];
-                        load_pattern<H>(a, s, y, p, al, id);
-                        bool owner = true;
+                        rec_pattern<H>(g, s, jj, p, al);
+                        const int64_t own = pat_contrib<H>(0, p, al, a.D, S0, b);
 #pragma unroll
                         for (int i = 1; i < H; ++i)
-                            if (p[i] >= fb && p[i] < b && p[i] > p[0]) owner = false;
-                        if (!owner) continue;
+                            if (p[i] >= f0 && p[i] < b && p[i] > p[0]) return own;  // not the latest joiner
 #pragma unroll
                         for (int i = 1; i < H; ++i) {
-                            if (p[i] < b) continue;
-                            const int64_t before = pat_contrib<H>(i, p, al, a.D, fb, fb);
-                            const int64_t after = pat_contrib<H>(i, p, al, a.D, b, b);
-                            if (after != before) {
-                                const unsigned long long old = atomicAdd((unsigned long long*)&g.F[p[i]],
-                                                                         (unsigned long long)(after - before));
-                                atomicMax(&g.bmax[p[i] / kFB], (long long)(old + (unsigned long long)(after - before)));
+                            if (p[i] >= b) {  // stays below
+                                const int64_t before = pat_contrib<H>(i, p, al, a.D, f0, f0);
+                                const int64_t after = pat_contrib<H>(i, p, al, a.D, b, b);
+                                if (after != before) {
+                                    const unsigned long long old = atomicAdd((unsigned long long*)&g.F[p[i]],
+                                                                             (unsigned long long)(after - before));
+                                    atomicMax(&g.bmax[p[i] / kFB],
+                                              (long long)(old + (unsigned long long)(after - before)));
+                                }
+                            } else if (p[i] >= S0 && p[i] < f0) {  // earlier member of S
+                                const int64_t before = pat_contrib<H>(i, p, al, a.D, S0, f0);
+                                const int64_t after = pat_contrib<H>(i, p, al, a.D, S0, b);
+                                if (after != before)
+                                    atomicAdd((unsigned long long*)&g.V[p[i]], (unsigned long long)(after - before));
                             }
                         }
-                    }
-                }
+                        return own;
+                    },
+                    [&](int64_t jj, int64_t acc) { g.V[jj] = acc; });
                 fb = b;
             }
-            for (int64_t j = vb + gw; j < b; j += nwave) {
-                const int32_t x = g.order[j];
-                const int64_t r = row_of_vertex(a, x);
-                int64_t acc = 0;
-                if (r >= 0) {
-                    for (int64_t s = a.rp[r] + lane; s < a.rp[r + 1]; s += 64) {
-                        int64_t p[H], al[H];
-                        int32_t id[H];
-                        load_pattern<H>(a, s, x, p, al, id);
-                        acc += pat_contrib<H>(0, p, al, a.D, S0, b);
-                        bool owner = true;  // x is the latest joining member of the pattern
-#pragma unroll
-                        for (int i = 1; i < H; ++i)
-                            if (p[i] >= vb && p[i] < b && p[i] > p[0]) owner = false;
-                        if (!owner) continue;
-#pragma unroll
-                        for (int i = 1; i < H; ++i) {
-                            if (p[i] < S0 || p[i] >= vb) continue;
-                            const int64_t before = pat_contrib<H>(i, p, al, a.D, S0, vb);
-                            const int64_t after = pat_contrib<H>(i, p, al, a.D, S0, b);
-                            if (after != before)
-                                atomicAdd((unsigned long long*)&g.V[p[i]], (unsigned long long)(after - before));
-                        }
-                    }
-                    for (int m = 32; m > 0; m >>= 1) acc += shfl_xor_i64(acc, m);
-                }
-                if (lane == 0) g.V[j] = acc;
-            }
-            vb = b;
+            PROF_MARK(2);
             grid_barrier(g, nwg, &s_err);
+            PROF_MARK(3);
             // phase: min and max of the restricted loads of S, and the
             // largest restricted load below b
             long long vmn = LLONG_MAX, vmx = LLONG_MIN, fmx = LLONG_MIN;
@@ -648,7 +756,9 @@ __global__ __launch_bounds__(kRT) void k_sg_scan(ScanArgs g) {
                 for (int64_t blk = b / kFB + 1 + gt; blk < g.nblk; blk += nthr) fmx = max(fmx, g.bmax[blk]);
             }
             put_partial(g, ph, vmn, vmx, fmx, LLONG_MAX, sred);
+            PROF_MARK(4);
             grid_barrier(g, nwg, &s_err);
+            PROF_MARK(5);
             gather_partials(g, ph, nwg, sh);
             ++ph;
             failed = s_err != 0;
@@ -672,19 +782,14 @@ __global__ __launch_bounds__(kRT) void k_sg_scan(ScanArgs g) {
             g.lo[g.order[j]] = mnS;
             g.hi[g.order[j]] = mxS;
         }
-        for (int64_t j = S0 + gw; j < b; j += nwave) {
-            const int32_t x = g.order[j];
-            const int64_t r = row_of_vertex(a, x);
-            if (r < 0) continue;
-            for (int64_t s = a.rp[r] + lane; s < a.rp[r + 1]; s += 64) {
+        positions_pass(
+            g, S0, b,
+            [&](int64_t s, int64_t jj) -> int64_t {
                 int64_t p[H], al[H];
-                int32_t id[H];
-                load_pattern<H>(a, s, x, p, al, id);
-                bool owner = true;
+                rec_pattern<H>(g, s, jj, p, al);
 #pragma unroll
                 for (int i = 1; i < H; ++i)
-                    if (p[i] >= S0 && p[i] < b && p[i] > p[0]) owner = false;
-                if (!owner) continue;
+                    if (p[i] >= S0 && p[i] < b && p[i] > p[0]) return 0;  // not the latest accepted vertex
 #pragma unroll
                 for (int i = 1; i < H; ++i) {
                     if (p[i] < b) continue;
@@ -693,14 +798,17 @@ __global__ __launch_bounds__(kRT) void k_sg_scan(ScanArgs g) {
                     if (after != before)
                         atomicAdd((unsigned long long*)&g.T[p[i]], (unsigned long long)(after - before));
                 }
-            }
-        }
+                return 0;
+            },
+            [](int64_t, int64_t) {});
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             g.groups[2 * ng] = S0;
             g.groups[2 * ng + 1] = b;
         }
         ++ng;
+        PROF_MARK(6);
         grid_barrier(g, nwg, &s_err);
+        PROF_MARK(7);
         failed = s_err != 0;
         minH = mnS;
         hasH = true;
@@ -712,6 +820,10 @@ __global__ __launch_bounds__(kRT) void k_sg_scan(ScanArgs g) {
         g.info[2] = verifs;
     }
     if (threadIdx.x == 0 && s_err) g.info[3] = 1;
+#ifdef LDS_SCAN_PROF
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        for (int k = 0; k < 8; ++k) g.info[4 + k] = (int64_t)prof[k];
+#endif
 }
 
 template <int H>
@@ -877,6 +989,28 @@ void sg_stable_groups(Graph& g, int mode, hipStream_t s) {
     run_pass(g, mode, a, s);
     a = plan_args(g, mode, a);
 
+    // slot records and the row of every position
+    const SweepPlan& pl = (mode == 2) ? g.edge_plan : g.tri_plan;
+    DBuf<int32_t> rowp;
+    DBuf<int2> rec2;
+    DBuf<int4> rec3;
+    DBuf<uint32_t> rec3w;
+    rowp.alloc(n, s);
+    k_fill_i32<<<grid_for(n, kT), kT, 0, s>>>(rowp.p, n, -1);
+    if (mode == 2)
+        rec2.alloc(pl.nslots, s);
+    else {
+        rec3.alloc(pl.nslots, s);
+        rec3w.alloc(pl.nslots, s);
+    }
+    if (pl.nrows > 0) {
+        if (mode == 2)
+            k_slot_records<2><<<grid_for(pl.nrows, 4), kT, 0, s>>>(a, rowp.p, rec2.p, rec3.p, rec3w.p);
+        else
+            k_slot_records<3><<<grid_for(pl.nrows, 4), kT, 0, s>>>(a, rowp.p, rec2.p, rec3.p, rec3w.p);
+    }
+    LDS_HIP(hipGetLastError());
+
     // the round loop: one cooperative launch
     const int64_t nblk = (n + kFB - 1) / kFB;
     DBuf<int64_t> F, Vb, groups, info;
@@ -901,10 +1035,10 @@ void sg_stable_groups(Graph& g, int mode, hipStream_t s) {
     // workgroups meet at it
     const int64_t grid = std::max<int64_t>(1, std::min<int64_t>({resident, (int64_t)kScanMaxWG, (n + 16383) / 16384}));
     groups.alloc(2 * n, s);
-    info.alloc(4, s);
+    info.alloc(16, s);
     part.alloc((size_t)2 * grid * 4, s);
     bar.alloc(2, s);
-    k_fill_i64<<<1, kT, 0, s>>>(info.p, 4, 0);
+    k_fill_i64<<<1, kT, 0, s>>>(info.p, 16, 0);
     k_fill_i64<<<1, kT, 0, s>>>((int64_t*)bar.p, 1, 0);
     LDS_HIP(hipGetLastError());
     ScanArgs sa{};
@@ -924,6 +1058,10 @@ void sg_stable_groups(Graph& g, int mode, hipStream_t s) {
     sa.info = info.p;
     sa.part = part.p;
     sa.bar = bar.p;
+    sa.rowp = rowp.p;
+    sa.rec2 = rec2.p;
+    sa.rec3 = rec3.p;
+    sa.rec3w = rec3w.p;
     if (grid == 1) {  // one workgroup needs no co-residency guarantee
         if (mode == 2)
             k_sg_scan<2><<<1, kRT, 0, s>>>(sa);
@@ -935,13 +1073,19 @@ void sg_stable_groups(Graph& g, int mode, hipStream_t s) {
         LDS_HIP(hipLaunchCooperativeKernel(mode == 2 ? (const void*)k_sg_scan<2> : (const void*)k_sg_scan<3>,
                                            dim3((unsigned)grid), dim3(kRT), kargs, 0, s));
     }
-    int64_t hinfo[4];
+    int64_t hinfo[16];
     LDS_HIP(hipMemcpyAsync(hinfo, info.p, sizeof(hinfo), hipMemcpyDeviceToHost, s));
     LDS_HIP(hipStreamSynchronize(s));
     LDS_CHECK(hinfo[3] == 0, ST_DEVICE, "stable-group scan: a grid barrier did not complete");
     const int64_t ng = hinfo[0];
     q.rounds = hinfo[1];
     q.verifications = hinfo[2];
+#ifdef LDS_SCAN_PROF
+    std::fprintf(stderr, "[scan] grid %lld rounds %lld verifications %lld | ticks (100 MHz) search %lld+%lld update %lld+%lld minmax %lld+%lld accept %lld+%lld\n",
+                 (long long)grid, (long long)hinfo[1], (long long)hinfo[2], (long long)hinfo[4], (long long)hinfo[5],
+                 (long long)hinfo[6], (long long)hinfo[7], (long long)hinfo[8], (long long)hinfo[9], (long long)hinfo[10],
+                 (long long)hinfo[11]);
+#endif
     std::vector<int64_t> hg((size_t)2 * ng);
     if (ng > 0) {
         LDS_HIP(hipMemcpyAsync(hg.data(), groups.p, hg.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
