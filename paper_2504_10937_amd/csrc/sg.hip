@@ -88,14 +88,24 @@ __global__ void k_slot_splits(const int64_t* rp, int64_t n_hub, const int64_t* h
         s1 = rp[chunk_row[c + 1]];
         bit0 = cwo[c] * 64;
     }
-    for (int64_t s = s0 + threadIdx.x; s < s1; s += kT) {
-        const int64_t p = bit0 + (s - s0);
+    // the 64 slots of a wave share one decision word per iteration (bit0 is
+    // word-aligned and a wave covers 64 consecutive slots), so the word index
+    // is made wave-uniform and each word is read once per wave
+    for (int64_t base = s0; base < s1; base += kT) {
+        const int64_t s = base + threadIdx.x;
+        const int64_t wave_first = base + (threadIdx.x & ~63);
+        if (wave_first >= s1) break;  // the whole wave is past the block (its word would be too)
+        const int64_t p0 = bit0 + (wave_first - s0);
+        const uint32_t wlo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)(p0 / 64));
+        const uint32_t whi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)(p0 / 64) >> 32));
+        const int64_t widx = (int64_t)(((uint64_t)whi << 32) | wlo);
+        const int bit = threadIdx.x & 63;
         uint64_t a = tri ? 2 : 1;
         for (int i = 1; i <= iters; ++i) {
-            const uint64_t wd = bits[(int64_t)(i - 1) * total_words + p / 64];
-            if ((wd >> (p % 64)) & 1ull) a += (uint64_t)(tri ? 6 : 2) * (uint64_t)(i + 1);
+            const uint64_t wd = bits[(int64_t)(i - 1) * total_words + widx];
+            if ((wd >> bit) & 1ull) a += (uint64_t)(tri ? 6 : 2) * (uint64_t)(i + 1);
         }
-        a_slot[s] = (uint32_t)a;
+        if (s < s1) a_slot[s] = (uint32_t)a;
     }
 }
 
