@@ -111,9 +111,16 @@ struct Flow {
     // backward BFS from t at the start and after every N relabels.  Returns
     // the flow into t; the minimum cut follows from the residual graph
     // exactly as after a maximum flow (maximal_source_side).
-    int64_t maxflow(int64_t s, int64_t t) {
+    // init_ex: a preflow already encoded in the arcs' residual capacities
+    // (source arcs saturated): the excess of every node and the flow that
+    // already reached t; nullptr = start from zero flow
+    int64_t maxflow(int64_t s, int64_t t, const std::vector<int64_t>* init_ex = nullptr, int64_t init_t = 0) {
         finalize();
         std::vector<int64_t> h(N, 0), ex(N, 0), it(first.begin(), first.end() - 1);
+        if (init_ex) {
+            for (int64_t v = 0; v < N && v < (int64_t)init_ex->size(); ++v) ex[v] = (*init_ex)[v];
+            ex[t] = init_t;
+        }
         std::vector<std::vector<int64_t>> bucket(N);
         int64_t top = -1;
         std::vector<int64_t> q;
@@ -150,6 +157,7 @@ struct Flow {
                 cap[rev[e]] += d;
                 ex[to[e]] += d;
             }
+        ex[s] = 0;
         global_relabel();
         int64_t relabels = 0;
         for (;;) {
@@ -223,8 +231,19 @@ struct Flow {
 // is q * sum_v (deg v + 2 loops v) - 2 * (the objective), so the maximal
 // source side of a minimum cut is the maximal maximiser.  pairs: 2 local ids
 // per edge; loops[v]: self-loops at v.  Returns the maximum value.
+//
+// split / D (optional, no self-loops): a fractional split of every edge,
+// split[i] / D the share of the pair's first vertex (e.g. the FW numerators
+// over D_N).  The network is then scaled by D and the flow starts from the
+// preflow the split defines: every source arc saturated, q (D - 2 a) on the
+// edge from its first vertex, each vertex sending to the sink what its load
+// allows (2 q A_v up to 2 p D) and keeping the rest, 2 q (A_v - rho D), as
+// excess.  Close to the optimum (a converged FW split) only those excesses
+// remain to be pushed, so the search is short; the cut and value are those of
+// the unscaled network.
 int64_t max_excess_edges(int64_t k, const std::vector<int32_t>& pairs, const std::vector<int64_t>& loops, int64_t p,
-                         int64_t q, std::vector<char>& inX) {
+                         int64_t q, std::vector<char>& inX, const std::vector<uint32_t>* split = nullptr,
+                         int64_t D = 1) {
     const int64_t ne = (int64_t)pairs.size() / 2;
     std::vector<int64_t> w(k, 0);
     for (int64_t v = 0; v < k; ++v) w[v] = loops.empty() ? 0 : 2 * loops[v];
@@ -232,6 +251,36 @@ int64_t max_excess_edges(int64_t k, const std::vector<int32_t>& pairs, const std
     const int64_t S = k, T = k + 1;
     Flow f(k + 2);
     f.reserve((size_t)(ne + 2 * k));
+    int64_t wsum = 0;
+    for (int64_t v = 0; v < k; ++v) wsum += w[v];
+    // the scaled network must stay well inside int64
+    const bool fits = (i128)q * D * (wsum + 1) + (i128)2 * p * D * (k + 1) < ((i128)1 << 61);
+    if (split && loops.empty() && D > 0 && fits) {
+        std::vector<int64_t> A(k, 0), ex(k + 2, 0);
+        for (int64_t i = 0; i < ne; ++i) {
+            const int64_t a = (*split)[i];
+            A[pairs[2 * i]] += a;
+            A[pairs[2 * i + 1]] += D - a;
+        }
+        int64_t total = 0, to_t = 0;
+        for (int64_t v = 0; v < k; ++v) {
+            if (w[v] > 0) f.arc(S, v, 0, q * w[v] * D);  // saturated
+            const int64_t tv = std::min(2 * q * A[v], 2 * p * D);
+            f.arc(v, T, 2 * p * D - tv, tv);
+            ex[v] = 2 * q * A[v] - tv;
+            to_t += tv;
+            total += q * w[v] * D;
+        }
+        for (int64_t i = 0; i < ne; ++i) {
+            const int64_t fl = q * (D - 2 * (int64_t)(*split)[i]);  // net flow first -> second
+            f.arc(pairs[2 * i], pairs[2 * i + 1], q * D - fl, q * D + fl);
+        }
+        const int64_t flow = f.maxflow(S, T, &ex, to_t);
+        const std::vector<char> side = f.maximal_source_side(T);
+        inX.assign(k, 0);
+        for (int64_t v = 0; v < k; ++v) inX[v] = side[v];
+        return (total - flow) / (2 * D);
+    }
     int64_t total = 0;
     for (int64_t v = 0; v < k; ++v) {
         if (w[v] > 0) f.arc(S, v, q * w[v]);
@@ -417,14 +466,19 @@ struct Ctx {
     std::vector<Frac> lo, hi;     // bounds on phi_G, valid for every vertex
     std::vector<int32_t> loc;     // scratch: internal id -> local index, -1 outside
     std::vector<int32_t> mark;    // scratch, -1 outside
+    std::vector<uint32_t> split;  // edges: FW split numerator of every CSR slot (over splitD)
+    int64_t splitD = 1;
     TopkStats* st = nullptr;
     int64_t seq = 0;
 };
 
 // patterns of G[vs] by local index (edges: pairs, triangles: triples)
-void induced_patterns(Ctx& c, const std::vector<int32_t>& vs, std::vector<int32_t>& pat) {
+// split (edges, optional): the FW split numerator of each pair's first vertex
+void induced_patterns(Ctx& c, const std::vector<int32_t>& vs, std::vector<int32_t>& pat,
+                      std::vector<uint32_t>* split = nullptr) {
     const HostGraph& h = c.h;
     pat.clear();
+    if (split) split->clear();
     for (size_t i = 0; i < vs.size(); ++i) c.loc[vs[i]] = (int32_t)i;
     if (c.mode == 2) {
         for (size_t i = 0; i < vs.size(); ++i)
@@ -433,6 +487,7 @@ void induced_patterns(Ctx& c, const std::vector<int32_t>& vs, std::vector<int32_
                 if (j > (int32_t)i) {
                     pat.push_back((int32_t)i);
                     pat.push_back(j);
+                    if (split) split->push_back(c.split[s]);
                 }
             }
     } else {
@@ -477,13 +532,18 @@ std::vector<std::vector<int32_t>> components(Ctx& c, const std::vector<int32_t>&
 // vertices whose compact number in G[vs] is above rho.
 bool is_densest(Ctx& c, const std::vector<int32_t>& vs, Frac* rho, std::vector<int32_t>* denser) {
     std::vector<int32_t> pat;
-    induced_patterns(c, vs, pat);
+    std::vector<uint32_t> split;
+    const bool warm = c.mode == 2 && !c.split.empty();
+    induced_patterns(c, vs, pat, warm ? &split : nullptr);
     const int64_t np = (int64_t)pat.size() / c.mode;
     *rho = reduce(np, (int64_t)vs.size());
     if (np == 0) return true;
     std::vector<char> inX;
     c.st->maxflows++;
-    const int64_t val = (c.mode == 2) ? max_excess_edges((int64_t)vs.size(), pat, {}, rho->n, rho->d, inX)
+    // edges: the min cut starts from the FW split of the whole graph
+    // restricted to G[S] (exact for S = V, a valid preflow for any S)
+    const int64_t val = (c.mode == 2) ? max_excess_edges((int64_t)vs.size(), pat, {}, rho->n, rho->d, inX,
+                                                         warm ? &split : nullptr, c.splitD)
                                       : max_excess((int64_t)vs.size(), 3, pat, rho->n, rho->d, inX);
     if (val <= 0) return true;
     denser->clear();
@@ -739,6 +799,13 @@ void topk_run(Graph& g, int mode, int k, int iters, hipStream_t s, std::vector<T
     std::vector<std::vector<int32_t>> sets;
     std::vector<Frac> his, los;
     collect_groups(g, mode, iters, s, [](int32_t j) { return j; }, sets, his, &los);
+    if (mode == 2 && g.m > 0) {  // the split of every slot, for warm-started min cuts
+        const SgState& q = g.sg[0];
+        c.split.resize(2 * g.m);
+        LDS_HIP(hipMemcpyAsync(c.split.data(), q.a_slot.p, 2 * g.m * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        LDS_HIP(hipStreamSynchronize(s));
+        c.splitD = (int64_t)fw_denom(2, iters);
+    }
     for (size_t i = 0; i < sets.size(); ++i) {
         if (his[i].n < 0) continue;  // remainder without bounds
         for (int32_t u : sets[i]) {

@@ -99,6 +99,12 @@ def erdos_renyi(n, p, seed=0):
     return _take(_load().synth_erdos_renyi(n, p, seed))
 
 
+def barabasi_albert(n, m, seed=0):
+    """Barabasi-Albert preferential attachment with m edges per new vertex
+    (Holme-Kim with triad-formation probability 0) -> (n, src, dst)."""
+    return holme_kim(n, m, 0.0, seed=seed)
+
+
 def batch_member(index, base_seed=1000, n_lo=50.0, n_hi=5000.0):
     """Member `index` of the uneven batch (seed base_seed+index) -> (n, src, dst)."""
     return _take(_load().synth_batch_member(index, base_seed, n_lo, n_hi))
@@ -128,6 +134,10 @@ WORKLOADS = {
                                          s_hi=2000, p_block=0.3, seed=2), 2, 100, 10),
     "ltds_hk": (holme_kim, dict(n=1_000_000, mper=20, p_triad=0.6, seed=3), 3, 200, 10),
 }
+# the density sweep of the scalability experiment (Section 8): n = 1M, density
+# |E|/|V| = 2, 4, ..., 12, LDScvx with the default N = 100 and k = 5
+for _d in range(2, 13, 2):
+    WORKLOADS["ba_d%d" % _d] = (barabasi_albert, dict(n=1_000_000, m=_d, seed=100 + _d), 2, 100, 5)
 
 
 def workload(name):
