@@ -99,6 +99,32 @@ def bench_batched(lds, torch, synth, np, count, plain=True):
     return res
 
 
+def bench_density(lds, torch, synth, densities):
+    """The scalability experiment's density sweep: Barabasi-Albert graphs with
+    n = 1M and density d (m = d n); LDScvx (lds_topk, k = 5, N = 100) end to
+    end from the resident edge list, and the FW sweep rate alone."""
+    res = {}
+    for d in densities:
+        n, s, t, mode, iters, k = synth.workload("ba_d%d" % d)
+        ts, tt = torch.from_numpy(s).cuda(), torch.from_numpy(t).cuda()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = lds.lds_create_graph(n, ts, tt)
+        sets, st = lds.lds_topk(g, mode, k, iters, with_stats=True)
+        t1 = time.perf_counter()
+        fw_ms, launches = 0.0, 0
+        lds.lds_frank_wolfe(g, mode, iters)
+        fw_ms, launches = lds.lds_fw_elapsed(g, mode)
+        m = lds.lds_graph_info(g)["m"]
+        res["ba_d%d" % d] = {"n": n, "m": m, "ldscvx_s": t1 - t0, "lds_found": len(sets),
+                             "top_density": str(sets[0][1]) if sets else None,
+                             "fw_edge_updates_per_s": m * iters / (fw_ms / 1e3),
+                             "phases_ms": {x: round(st[x], 1) for x in ("ms_core", "ms_fw", "ms_prune", "ms_search")}}
+        log("density %d: LDScvx %.2f s, FW %.2f ms" % (d, t1 - t0, fw_ms))
+        g.destroy()
+    return res
+
+
 def _serve_run(lds, np, srv, gs, pool_n, seconds, qps, seed, tag0):
     import synth
     q = synth.queries(int(seconds * qps * 1.5) + 16, qps=qps, pool=len(gs), kmax=10, seed=seed)
@@ -178,6 +204,8 @@ def main():
                     help="graphs of the batched-vs-plain comparison (0: skip)")
     ap.add_argument("--no-batch-plain", action="store_true",
                     help="leave out the per-graph comparison of the batched section (shorter kernel traces)")
+    ap.add_argument("--density-sweep", default="2,6,12",
+                    help="Barabasi-Albert densities of the scalability section (n = 1M; empty: skip)")
     ap.add_argument("--serve-seconds", type=float, default=5.0, help="arrival window of the serving run (0: skip)")
     ap.add_argument("--serve-qps", type=float, default=200.0)
     ap.add_argument("--serve-low-qps", type=float, default=25.0,
@@ -281,6 +309,8 @@ def main():
     }
     if args.batch_graphs > 0:
         out["batched"] = bench_batched(lds, torch, synth, np, args.batch_graphs, not args.no_batch_plain)
+    if args.density_sweep:
+        out["density_sweep"] = bench_density(lds, torch, synth, [int(x) for x in args.density_sweep.split(",")])
     if args.serve_seconds > 0:
         out["serving"] = bench_serving(lds, torch, synth, np, args.serve_seconds, args.serve_qps, args.serve_low_qps)
     if not args.no_cpu_baseline:

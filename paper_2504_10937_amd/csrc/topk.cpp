@@ -300,11 +300,41 @@ int64_t max_excess_edges(int64_t k, const std::vector<int32_t>& pairs, const std
 // members, a one-member pattern is a self-loop).  Network: source -> pattern
 // (capacity q), pattern -> member (unbounded), vertex -> sink (p).  Returns
 // the maximum value; inX marks the maximal maximiser.
-int64_t max_excess(int64_t k, int h, const std::vector<int32_t>& pat, int64_t p, int64_t q, std::vector<char>& inX) {
+// split / D (optional, full patterns only): per pattern member the share of
+// the pattern (summing to D per pattern).  The network is then scaled by D
+// and starts from the preflow of the split: source arcs saturated, q a_j from
+// a pattern to its member j, every vertex sending min(q A_v, p D) to the sink
+// and keeping the rest as excess.
+int64_t max_excess(int64_t k, int h, const std::vector<int32_t>& pat, int64_t p, int64_t q, std::vector<char>& inX,
+                   const std::vector<uint32_t>* split = nullptr, int64_t D = 1) {
     const int64_t np = (int64_t)pat.size() / h;
     const int64_t S = np + k, T = S + 1;
     Flow f(T + 1);
     const int64_t INF = INT64_MAX / 4;
+    const bool fits = (i128)q * D * (np + 1) + (i128)p * D * (k + 1) < ((i128)1 << 61);
+    if (split && D > 0 && fits && (int64_t)split->size() == h * np) {
+        std::vector<int64_t> A(k, 0), ex(T + 1, 0);
+        for (int64_t i = 0; i < np; ++i) {
+            f.arc(S, i, 0, q * D);  // saturated
+            for (int j = 0; j < h; ++j) {
+                const int64_t a = (*split)[h * i + j];
+                f.arc(i, np + pat[h * i + j], INF - q * a, q * a);
+                A[pat[h * i + j]] += a;
+            }
+        }
+        int64_t to_t = 0;
+        for (int64_t v = 0; v < k; ++v) {
+            const int64_t tv = std::min(q * A[v], p * D);
+            f.arc(np + v, T, p * D - tv, tv);
+            ex[np + v] = q * A[v] - tv;
+            to_t += tv;
+        }
+        const int64_t flow = f.maxflow(S, T, &ex, to_t);
+        const std::vector<char> side = f.maximal_source_side(T);
+        inX.assign(k, 0);
+        for (int64_t v = 0; v < k; ++v) inX[v] = side[np + v];
+        return (q * np * D - flow) / D;
+    }
     for (int64_t i = 0; i < np; ++i) {
         f.arc(S, i, q);
         for (int j = 0; j < h; ++j)
@@ -466,7 +496,7 @@ struct Ctx {
     std::vector<Frac> lo, hi;     // bounds on phi_G, valid for every vertex
     std::vector<int32_t> loc;     // scratch: internal id -> local index, -1 outside
     std::vector<int32_t> mark;    // scratch, -1 outside
-    std::vector<uint32_t> split;  // edges: FW split numerator of every CSR slot (over splitD)
+    std::vector<uint32_t> split;  // FW split numerators over splitD: edges per CSR slot, triangles 3 per triangle
     int64_t splitD = 1;
     TopkStats* st = nullptr;
     int64_t seq = 0;
@@ -500,6 +530,12 @@ void induced_patterns(Ctx& c, const std::vector<int32_t>& vs, std::vector<int32_
                 pat.push_back(a);
                 pat.push_back(b);
                 pat.push_back(d);
+                if (split) {
+                    const int64_t t = h.tinc[q];
+                    split->push_back(c.split[3 * t]);
+                    split->push_back(c.split[3 * t + 1]);
+                    split->push_back(c.split[3 * t + 2]);
+                }
             }
     }
     for (int32_t v : vs) c.loc[v] = -1;
@@ -533,7 +569,7 @@ std::vector<std::vector<int32_t>> components(Ctx& c, const std::vector<int32_t>&
 bool is_densest(Ctx& c, const std::vector<int32_t>& vs, Frac* rho, std::vector<int32_t>* denser) {
     std::vector<int32_t> pat;
     std::vector<uint32_t> split;
-    const bool warm = c.mode == 2 && !c.split.empty();
+    const bool warm = !c.split.empty();
     induced_patterns(c, vs, pat, warm ? &split : nullptr);
     const int64_t np = (int64_t)pat.size() / c.mode;
     *rho = reduce(np, (int64_t)vs.size());
@@ -544,7 +580,8 @@ bool is_densest(Ctx& c, const std::vector<int32_t>& vs, Frac* rho, std::vector<i
     // restricted to G[S] (exact for S = V, a valid preflow for any S)
     const int64_t val = (c.mode == 2) ? max_excess_edges((int64_t)vs.size(), pat, {}, rho->n, rho->d, inX,
                                                          warm ? &split : nullptr, c.splitD)
-                                      : max_excess((int64_t)vs.size(), 3, pat, rho->n, rho->d, inX);
+                                      : max_excess((int64_t)vs.size(), 3, pat, rho->n, rho->d, inX,
+                                                   warm ? &split : nullptr, c.splitD);
     if (val <= 0) return true;
     denser->clear();
     for (size_t i = 0; i < vs.size(); ++i)
@@ -799,12 +836,20 @@ void topk_run(Graph& g, int mode, int k, int iters, hipStream_t s, std::vector<T
     std::vector<std::vector<int32_t>> sets;
     std::vector<Frac> his, los;
     collect_groups(g, mode, iters, s, [](int32_t j) { return j; }, sets, his, &los);
-    if (mode == 2 && g.m > 0) {  // the split of every slot, for warm-started min cuts
+    // the FW split (every CSR slot for edges, every triangle's three shares
+    // for triangles), for warm-started min cuts
+    if (mode == 2 && g.m > 0) {
         const SgState& q = g.sg[0];
         c.split.resize(2 * g.m);
         LDS_HIP(hipMemcpyAsync(c.split.data(), q.a_slot.p, 2 * g.m * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         LDS_HIP(hipStreamSynchronize(s));
         c.splitD = (int64_t)fw_denom(2, iters);
+    } else if (mode == 3 && g.T > 0) {
+        const SgState& q = g.sg[1];
+        c.split.resize(3 * g.T);
+        LDS_HIP(hipMemcpyAsync(c.split.data(), q.a_tri.p, 3 * g.T * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        LDS_HIP(hipStreamSynchronize(s));
+        c.splitD = (int64_t)fw_denom(3, iters);
     }
     for (size_t i = 0; i < sets.size(); ++i) {
         if (his[i].n < 0) continue;  // remainder without bounds
