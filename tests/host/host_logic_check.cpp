@@ -1,0 +1,194 @@
+// Host-only checks of the top-k driver's exact building blocks, compiled from
+// the library's own source with its device entry points stubbed out (nothing
+// here touches a GPU).  Each block is compared with a plain definition on
+// small random inputs:
+//   * minimum cuts (edge network, pattern network, both warm-started from
+//     arbitrary splits): the maximum of q*|P(X)| - p*|X| and the union of all
+//     maximisers, by enumeration of every X;
+//   * core and tr-core numbers: largest k such that the vertex lies in a
+//     subgraph whose every vertex has >= k edges (triangles) inside, by
+//     repeated deletion for every k.
+// Prints "ok" and exits 0 when every case agrees.
+#include "../../paper_2504_10937_amd/csrc/topk.cpp"
+
+#include <cstdio>
+#include <random>
+
+namespace lds {
+void* dev_alloc(size_t, hipStream_t) { return nullptr; }
+void dev_free(void*) {}
+Graph::~Graph() {}
+void build_graph(Graph&, int64_t, int64_t, const int32_t*, const int32_t*, bool, bool, hipStream_t) {}
+void list_triangles(Graph&, hipStream_t) {}
+void sg_stable_groups(Graph&, int, hipStream_t) {}
+void fw_run(Graph&, int, int, bool, hipStream_t) {}
+}  // namespace lds
+
+using namespace lds;
+
+// value and union of maximisers of q * (#patterns inside X + loops(X)) - p * |X|
+static int64_t enumerate(int64_t k, int h, const std::vector<int32_t>& pat, const std::vector<int64_t>& loops,
+                         int64_t p, int64_t q, std::vector<char>& X) {
+    auto value = [&](uint32_t m) {
+        int64_t cnt = 0;
+        for (size_t i = 0; i < pat.size() / h; ++i) {
+            bool in = true;
+            for (int j = 0; j < h; ++j) {
+                const int32_t v = pat[h * i + j];
+                if (v >= 0 && !((m >> v) & 1)) in = false;
+            }
+            cnt += in;
+        }
+        if (!loops.empty())
+            for (int64_t v = 0; v < k; ++v)
+                if ((m >> v) & 1) cnt += loops[v];
+        return q * cnt - p * (int64_t)__builtin_popcount(m);
+    };
+    int64_t best = INT64_MIN;
+    for (uint32_t m = 0; m < (1u << k); ++m) best = std::max(best, value(m));
+    uint32_t un = 0;
+    for (uint32_t m = 0; m < (1u << k); ++m)
+        if (value(m) == best) un |= m;
+    X.assign(k, 0);
+    for (int64_t v = 0; v < k; ++v) X[v] = (un >> v) & 1;
+    return best;
+}
+
+// core numbers by definition: for each k, delete vertices with < k edges
+// (triangles) among the remaining until none; survivors have core >= k
+static std::vector<int32_t> core_by_definition(const HostGraph& h, int mode) {
+    std::vector<int32_t> core(h.n, 0);
+    for (int32_t k = 1;; ++k) {
+        std::vector<char> alive(h.n, 1);
+        bool changed = true;
+        while (changed) {
+            changed = false;
+            for (int64_t u = 0; u < h.n; ++u) {
+                if (!alive[u]) continue;
+                int32_t c = 0;
+                if (mode == 2) {
+                    for (int64_t s = h.rp[u]; s < h.rp[u + 1]; ++s) c += alive[h.col[s]];
+                } else {
+                    for (int64_t i = h.trp[u]; i < h.trp[u + 1]; ++i) {
+                        const int32_t* x = &h.tri[3 * h.tinc[i]];
+                        c += alive[x[0]] && alive[x[1]] && alive[x[2]];
+                    }
+                }
+                if (c < k) {
+                    alive[u] = 0;
+                    changed = true;
+                }
+            }
+        }
+        bool any = false;
+        for (int64_t u = 0; u < h.n; ++u)
+            if (alive[u]) {
+                core[u] = k;
+                any = true;
+            }
+        if (!any) return core;
+    }
+}
+
+int main() {
+    std::mt19937_64 rng(12345);
+    int bad = 0, cases = 0;
+    for (int it = 0; it < 1500; ++it) {
+        const int k = 2 + (int)(rng() % 10);
+        const double pe = 0.2 + (double)(rng() % 70) / 100.0;
+        std::vector<int32_t> pairs, tris;
+        std::vector<int64_t> loops(k, 0);
+        for (int a = 0; a < k; ++a)
+            for (int b = a + 1; b < k; ++b)
+                if ((double)(rng() % 1000) < pe * 1000) {
+                    pairs.push_back(a);
+                    pairs.push_back(b);
+                }
+        for (int a = 0; a < k; ++a) loops[a] = (rng() % 3 == 0) ? (int64_t)(rng() % 3) : 0;
+        for (int a = 0; a < k; ++a)
+            for (int b = a + 1; b < k; ++b)
+                for (int c = b + 1; c < k; ++c)
+                    if ((double)(rng() % 1000) < pe * 400) {
+                        tris.push_back(a);
+                        tris.push_back(b);
+                        tris.push_back((rng() % 4) ? c : -1);  // some truncated patterns
+                    }
+        const int64_t p = 1 + (int64_t)(rng() % 20), q = 1 + (int64_t)(rng() % 10);
+        std::vector<char> X, Y;
+        // edge network, with and without self-loops
+        for (int withl = 0; withl < 2; ++withl) {
+            const std::vector<int64_t> L = withl ? loops : std::vector<int64_t>{};
+            ++cases;
+            if (max_excess_edges(k, pairs, L, p, q, X) != enumerate(k, 2, pairs, L, p, q, Y) || X != Y) ++bad;
+        }
+        // edge network warm-started from an arbitrary split
+        {
+            const int64_t D = 2 + (int64_t)(rng() % 50);
+            std::vector<uint32_t> sp(pairs.size() / 2);
+            for (auto& a : sp) a = (uint32_t)(rng() % (uint64_t)(D + 1));
+            ++cases;
+            if (max_excess_edges(k, pairs, {}, p, q, X, &sp, D) != enumerate(k, 2, pairs, {}, p, q, Y) || X != Y)
+                ++bad;
+        }
+        // pattern network (truncated patterns allowed), cold
+        ++cases;
+        if (max_excess(k, 3, tris, p, q, X) != enumerate(k, 3, tris, {}, p, q, Y) || X != Y) ++bad;
+        // pattern network warm-started from arbitrary shares (full patterns)
+        {
+            std::vector<int32_t> full;
+            for (size_t i = 0; i + 2 < tris.size(); i += 3)
+                if (tris[i + 2] >= 0) full.insert(full.end(), tris.begin() + i, tris.begin() + i + 3);
+            const int64_t D = 3 + (int64_t)(rng() % 40);
+            std::vector<uint32_t> sp;
+            for (size_t i = 0; i < full.size(); i += 3) {
+                const int64_t a = (int64_t)(rng() % (uint64_t)(D + 1)), b = (int64_t)(rng() % (uint64_t)(D - a + 1));
+                sp.push_back((uint32_t)a);
+                sp.push_back((uint32_t)b);
+                sp.push_back((uint32_t)(D - a - b));
+            }
+            ++cases;
+            if (max_excess(k, 3, full, p, q, X, &sp, D) != enumerate(k, 3, full, {}, p, q, Y) || X != Y) ++bad;
+        }
+    }
+    // core and tr-core numbers on random graphs
+    for (int it = 0; it < 200; ++it) {
+        HostGraph h;
+        h.n = 5 + (int64_t)(rng() % 40);
+        const double pe = 0.05 + (double)(rng() % 50) / 100.0;
+        std::vector<std::vector<int32_t>> adj(h.n);
+        for (int64_t a = 0; a < h.n; ++a)
+            for (int64_t b = a + 1; b < h.n; ++b)
+                if ((double)(rng() % 1000) < pe * 1000) {
+                    adj[a].push_back((int32_t)b);
+                    adj[b].push_back((int32_t)a);
+                }
+        h.rp.assign(h.n + 1, 0);
+        for (int64_t u = 0; u < h.n; ++u) h.rp[u + 1] = h.rp[u] + (int64_t)adj[u].size();
+        for (int64_t u = 0; u < h.n; ++u) h.col.insert(h.col.end(), adj[u].begin(), adj[u].end());
+        std::vector<std::vector<char>> am(h.n, std::vector<char>(h.n, 0));
+        for (int64_t u = 0; u < h.n; ++u)
+            for (int32_t v : adj[u]) am[u][v] = 1;
+        for (int64_t a = 0; a < h.n; ++a)
+            for (int64_t b = a + 1; b < h.n; ++b)
+                for (int64_t c = b + 1; c < h.n; ++c)
+                    if (am[a][b] && am[b][c] && am[a][c]) {
+                        h.tri.push_back((int32_t)a);
+                        h.tri.push_back((int32_t)b);
+                        h.tri.push_back((int32_t)c);
+                    }
+        const int64_t T = (int64_t)h.tri.size() / 3;
+        h.trp.assign(h.n + 1, 0);
+        for (int64_t t = 0; t < 3 * T; ++t) h.trp[h.tri[t] + 1]++;
+        for (int64_t u = 0; u < h.n; ++u) h.trp[u + 1] += h.trp[u];
+        h.tinc.assign(3 * T, 0);
+        std::vector<int64_t> fill(h.trp.begin(), h.trp.end() - 1);
+        for (int64_t t = 0; t < T; ++t)
+            for (int j = 0; j < 3; ++j) h.tinc[fill[h.tri[3 * t + j]]++] = t;
+        const std::vector<char> alive(h.n, 1);
+        cases += 2;
+        if (core_numbers(h, alive) != core_by_definition(h, 2)) ++bad;
+        if (trcore_numbers(h, alive) != core_by_definition(h, 3)) ++bad;
+    }
+    std::printf("%s: %d of %d cases disagree\n", bad ? "FAIL" : "ok", bad, cases);
+    return bad ? 1 : 0;
+}
