@@ -131,6 +131,27 @@ struct Server::Impl {
                 d.error = "the query's device footprint exceeds the server's memory budget";
                 finish(q, std::move(d));
             }
+            // graphs too large for one workgroup run FW on their worker's own
+            // stream (their many per-iteration launches would otherwise keep
+            // this thread from admitting); the rest share one batched launch
+            std::vector<SQuery> solo;
+            {
+                std::vector<SQuery> keep;
+                for (auto& q : adm) {
+                    int64_t cost = 0;
+                    {
+                        std::lock_guard<std::mutex> g(q.h->mu);
+                        cost = batch_cost(q.h->g, q.mode, q.iters);
+                    }
+                    (cost > kServeKernelCost ? solo : keep).push_back(std::move(q));
+                }
+                adm.swap(keep);
+            }
+            if (!solo.empty()) {
+                std::lock_guard<std::mutex> g(mu);
+                for (auto& q : solo) verify.push_back(std::move(q));
+                cv_work.notify_all();
+            }
             if (!adm.empty()) {
                 // one batched FW launch for everything admitted together
                 std::vector<lds_graph> hs;
@@ -214,7 +235,8 @@ struct Server::Impl {
             try {
                 if (q.fw && q.fw->done) LDS_HIP(hipStreamWaitEvent(s, q.fw->done, 0));
                 std::lock_guard<std::mutex> g(q.h->mu);
-                topk_run(q.h->g, q.mode, q.k, q.iters, s, d.sets, d.st, true);
+                // a query that was not in a batched launch runs its own FW here
+                topk_run(q.h->g, q.mode, q.k, q.iters, s, d.sets, d.st, q.fw != nullptr);
                 d.status = ST_OK;
             } catch (const Error& e) {
                 d.status = e.code;
