@@ -80,7 +80,34 @@ struct Flow {
         pc.push_back(c);
         pd.push_back(c_back);
     }
+    // Direct construction (no pending list): arcs[v] = the number of arc
+    // ends at node v (each arc pair counts once at both of its nodes); then
+    // add() places every pair.
+    std::vector<int64_t> fillp;
+    bool direct = false;
+    void begin(const std::vector<int64_t>& arcs) {
+        direct = true;
+        first.assign(N + 1, 0);
+        for (int64_t v = 0; v < N; ++v) first[v + 1] = first[v] + arcs[v];
+        fillp.assign(first.begin(), first.end() - 1);
+        to.resize(first[N]);
+        cap.resize(first[N]);
+        rev.resize(first[N]);
+    }
+    void add(int64_t a, int64_t b, int64_t c, int64_t c_back = 0) {
+        const int64_t x = fillp[a]++, y = fillp[b]++;
+        to[x] = (int32_t)b;
+        cap[x] = c;
+        rev[x] = y;
+        to[y] = (int32_t)a;
+        cap[y] = c_back;
+        rev[y] = x;
+    }
     void finalize() {
+        if (direct) {
+            std::vector<int64_t>().swap(fillp);
+            return;
+        }
         const size_t m = pa.size();
         first.assign(N + 1, 0);
         for (size_t i = 0; i < m; ++i) {
@@ -245,54 +272,68 @@ int64_t max_excess_edges(int64_t k, const std::vector<int32_t>& pairs, const std
                          int64_t q, std::vector<char>& inX, const std::vector<uint32_t>* split = nullptr,
                          int64_t D = 1) {
     const int64_t ne = (int64_t)pairs.size() / 2;
-    std::vector<int64_t> w(k, 0);
+    std::vector<int64_t> w(k, 0), deg(k, 0);
     for (int64_t v = 0; v < k; ++v) w[v] = loops.empty() ? 0 : 2 * loops[v];
-    for (int64_t i = 0; i < 2 * ne; ++i) w[pairs[i]]++;
-    const int64_t S = k, T = k + 1;
-    Flow f(k + 2);
-    f.reserve((size_t)(ne + 2 * k));
+    for (int64_t i = 0; i < 2 * ne; ++i) {
+        w[pairs[i]]++;
+        deg[pairs[i]]++;
+    }
     int64_t wsum = 0;
     for (int64_t v = 0; v < k; ++v) wsum += w[v];
     // the scaled network must stay well inside int64
-    const bool fits = (i128)q * D * (wsum + 1) + (i128)2 * p * D * (k + 1) < ((i128)1 << 61);
-    if (split && loops.empty() && D > 0 && fits) {
-        std::vector<int64_t> A(k, 0), ex(k + 2, 0);
+    const bool warm = split && loops.empty() && D > 0 &&
+                      (i128)q * D * (wsum + 1) + (i128)2 * p * D * (k + 1) < ((i128)1 << 61);
+    const int64_t sc = warm ? D : 1;  // capacity scale
+    const int64_t S = k, T = k + 1;
+    Flow f(k + 2);
+    {
+        std::vector<int64_t> arcs(k + 2, 0);
+        for (int64_t v = 0; v < k; ++v) {
+            arcs[v] = deg[v] + 1 + (w[v] > 0 ? 1 : 0);
+            arcs[S] += w[v] > 0 ? 1 : 0;
+        }
+        arcs[T] = k;
+        f.begin(arcs);
+    }
+    std::vector<int64_t> A(warm ? k : 0, 0), ex;
+    if (warm)
         for (int64_t i = 0; i < ne; ++i) {
             const int64_t a = (*split)[i];
             A[pairs[2 * i]] += a;
             A[pairs[2 * i + 1]] += D - a;
         }
-        int64_t total = 0, to_t = 0;
-        for (int64_t v = 0; v < k; ++v) {
-            if (w[v] > 0) f.arc(S, v, 0, q * w[v] * D);  // saturated
+    int64_t total = 0, to_t = 0;
+    if (warm) ex.assign(k + 2, 0);
+    for (int64_t v = 0; v < k; ++v) {
+        if (w[v] > 0) {
+            if (warm)
+                f.add(S, v, 0, q * w[v] * sc);  // saturated
+            else
+                f.add(S, v, q * w[v]);
+        }
+        if (warm) {
             const int64_t tv = std::min(2 * q * A[v], 2 * p * D);
-            f.arc(v, T, 2 * p * D - tv, tv);
+            f.add(v, T, 2 * p * D - tv, tv);
             ex[v] = 2 * q * A[v] - tv;
             to_t += tv;
-            total += q * w[v] * D;
+        } else {
+            f.add(v, T, 2 * p);
         }
-        for (int64_t i = 0; i < ne; ++i) {
+        total += q * w[v] * sc;
+    }
+    for (int64_t i = 0; i < ne; ++i) {
+        if (warm) {
             const int64_t fl = q * (D - 2 * (int64_t)(*split)[i]);  // net flow first -> second
-            f.arc(pairs[2 * i], pairs[2 * i + 1], q * D - fl, q * D + fl);
+            f.add(pairs[2 * i], pairs[2 * i + 1], q * D - fl, q * D + fl);
+        } else {
+            f.add(pairs[2 * i], pairs[2 * i + 1], q, q);
         }
-        const int64_t flow = f.maxflow(S, T, &ex, to_t);
-        const std::vector<char> side = f.maximal_source_side(T);
-        inX.assign(k, 0);
-        for (int64_t v = 0; v < k; ++v) inX[v] = side[v];
-        return (total - flow) / (2 * D);
     }
-    int64_t total = 0;
-    for (int64_t v = 0; v < k; ++v) {
-        if (w[v] > 0) f.arc(S, v, q * w[v]);
-        f.arc(v, T, 2 * p);
-        total += q * w[v];
-    }
-    for (int64_t i = 0; i < ne; ++i) f.arc(pairs[2 * i], pairs[2 * i + 1], q, q);
-    const int64_t flow = f.maxflow(S, T);
+    const int64_t flow = warm ? f.maxflow(S, T, &ex, to_t) : f.maxflow(S, T);
     const std::vector<char> side = f.maximal_source_side(T);
     inX.assign(k, 0);
     for (int64_t v = 0; v < k; ++v) inX[v] = side[v];
-    return (total - flow) / 2;
+    return (total - flow) / (2 * sc);
 }
 
 // Triangles: maximal X ⊆ {0..k-1} maximising q * #patterns inside X - p * |X| (a pattern
@@ -311,21 +352,37 @@ int64_t max_excess(int64_t k, int h, const std::vector<int32_t>& pat, int64_t p,
     const int64_t S = np + k, T = S + 1;
     Flow f(T + 1);
     const int64_t INF = INT64_MAX / 4;
-    const bool fits = (i128)q * D * (np + 1) + (i128)p * D * (k + 1) < ((i128)1 << 61);
-    if (split && D > 0 && fits && (int64_t)split->size() == h * np) {
+    const bool warm = split && D > 0 && (int64_t)split->size() == h * np &&
+                      (i128)q * D * (np + 1) + (i128)p * D * (k + 1) < ((i128)1 << 61);
+    {
+        std::vector<int64_t> arcs(T + 1, 0);
+        for (int64_t i = 0; i < np; ++i) {
+            arcs[i] = 1;
+            for (int j = 0; j < h; ++j)
+                if (pat[h * i + j] >= 0) {
+                    arcs[i]++;
+                    arcs[np + pat[h * i + j]]++;
+                }
+        }
+        for (int64_t v = 0; v < k; ++v) arcs[np + v]++;
+        arcs[S] = np;
+        arcs[T] = k;
+        f.begin(arcs);
+    }
+    if (warm) {
         std::vector<int64_t> A(k, 0), ex(T + 1, 0);
         for (int64_t i = 0; i < np; ++i) {
-            f.arc(S, i, 0, q * D);  // saturated
+            f.add(S, i, 0, q * D);  // saturated
             for (int j = 0; j < h; ++j) {
                 const int64_t a = (*split)[h * i + j];
-                f.arc(i, np + pat[h * i + j], INF - q * a, q * a);
+                f.add(i, np + pat[h * i + j], INF - q * a, q * a);
                 A[pat[h * i + j]] += a;
             }
         }
         int64_t to_t = 0;
         for (int64_t v = 0; v < k; ++v) {
             const int64_t tv = std::min(q * A[v], p * D);
-            f.arc(np + v, T, p * D - tv, tv);
+            f.add(np + v, T, p * D - tv, tv);
             ex[np + v] = q * A[v] - tv;
             to_t += tv;
         }
@@ -336,11 +393,11 @@ int64_t max_excess(int64_t k, int h, const std::vector<int32_t>& pat, int64_t p,
         return (q * np * D - flow) / D;
     }
     for (int64_t i = 0; i < np; ++i) {
-        f.arc(S, i, q);
+        f.add(S, i, q);
         for (int j = 0; j < h; ++j)
-            if (pat[h * i + j] >= 0) f.arc(i, np + pat[h * i + j], INF);
+            if (pat[h * i + j] >= 0) f.add(i, np + pat[h * i + j], INF);
     }
-    for (int64_t v = 0; v < k; ++v) f.arc(np + v, T, p);
+    for (int64_t v = 0; v < k; ++v) f.add(np + v, T, p);
     const int64_t flow = f.maxflow(S, T);
     const std::vector<char> side = f.maximal_source_side(T);
     inX.assign(k, 0);
