@@ -49,6 +49,7 @@ def _load():
         "orc_sort_prefix": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, vp, vp]),
         "orc_extract_sg": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, u64, vp, vp, vp, vp, vp]),
         "orc_decompose": (i64, [vp, ctypes.c_int, vp, vp]),
+        "orc_core_numbers": (ctypes.c_int, [vp, ctypes.c_int, vp]),
         "orc_lds_from_phi": (i64, [vp, vp, vp, vp, vp, vp, vp]),
         "orc_brute": (i64, [vp, ctypes.c_int, vp, vp, vp, vp, vp]),
     }
@@ -172,6 +173,15 @@ def extract_sg(G, mode, A, split, D):
         raise RuntimeError("oracle extract_sg failed")
     k = ng.value
     return [(int(gs[i]), int(ge[i])) for i in range(k)], lo, hi
+
+
+def core_numbers(G, mode):
+    """Core numbers (mode 2) / tr-core numbers (mode 3) by the definition
+    (nested k-cores, repeated deletion) -> int64 array."""
+    out = np.empty(G.n, np.int64)
+    if _load().orc_core_numbers(G._h, mode, _p(out)) < 0:
+        raise RuntimeError("oracle core numbers failed")
+    return out
 
 
 def decompose(G, mode):

@@ -229,6 +229,45 @@ static int get_patterns(const orc_graph *g, int mode, patterns *P) {
     return -1;
 }
 
+/* ====================================================== core numbers == */
+/* Core numbers (edges) and tr-core numbers (triangles), used by Pruning
+ * (Alg. 3) and as the initial bounds of the compact numbers: core(u) is the
+ * largest k such that u belongs to the k-core, the largest vertex set in
+ * which every vertex lies in at least k patterns (edges or triangles) whose
+ * vertices are all in the set.  The k-cores are nested, so the k-core is
+ * obtained from the (k-1)-core by deleting, until none is left, vertices
+ * that lie in fewer than k patterns of the remaining set (counted afresh on
+ * every pass).  core[u] = 0 for vertices outside the 1-core.  Returns 0, or -1. */
+int orc_core_numbers(const orc_graph *g, int mode, int64_t *core) {
+    patterns P;
+    if (get_patterns(g, mode, &P)) return -1;
+    const int64_t n = g->n, h = P.h;
+    char *in = (char *)malloc((size_t)(n > 0 ? n : 1));
+    int64_t *cnt = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    if (!in || !cnt) { free(in); free(cnt); free(P.v); return -1; }
+    for (int64_t u = 0; u < n; u++) { in[u] = 1; core[u] = 0; }
+    int64_t left = n;
+    for (int64_t k = 1; left > 0; k++) {
+        int changed = 1;
+        while (changed) {
+            changed = 0;
+            for (int64_t u = 0; u < n; u++) cnt[u] = 0;
+            for (int64_t p = 0; p < P.np; p++) {
+                int all = 1;
+                for (int64_t j = 0; j < h; j++) all = all && in[P.v[h * p + j]];
+                if (all)
+                    for (int64_t j = 0; j < h; j++) cnt[P.v[h * p + j]]++;
+            }
+            for (int64_t u = 0; u < n; u++)
+                if (in[u] && cnt[u] < k) { in[u] = 0; left--; changed = 1; }
+        }
+        for (int64_t u = 0; u < n; u++)
+            if (in[u]) core[u] = k;
+    }
+    free(in); free(cnt); free(P.v);
+    return 0;
+}
+
 /* ============================================================ FW exact == */
 /* Denominator of the loads after iteration i (App.-B style exact form of
  * gamma_i = 2/(i+2)): (i+1)(i+2) for edges, 3(i+1)(i+2) for triangles. */

@@ -328,3 +328,62 @@ def test_prefix_invariants():
     for i in range(0, G.n, 37):
         best = max(range(i, G.n), key=lambda j: (dens[j], j))
         assert inI[best]
+
+
+# ---------------------------------------------------------------- core numbers
+def _core_by_enumeration(n, edges, mode):
+    """core(u) = max over vertex sets X containing u of the smallest number of
+    patterns inside X at a vertex of X (every subset enumerated)."""
+    import itertools
+    adj = [set() for _ in range(n)]
+    for a, b in edges:
+        adj[a].add(b)
+        adj[b].add(a)
+    best = [0] * n
+    for mask in range(1, 1 << n):
+        X = [u for u in range(n) if (mask >> u) & 1]
+        inX = set(X)
+        if mode == 2:
+            cnt = {u: len(adj[u] & inX) for u in X}
+        else:
+            cnt = {u: 0 for u in X}
+            for a, b, c in itertools.combinations(X, 3):
+                if b in adj[a] and c in adj[a] and c in adj[b]:
+                    cnt[a] += 1
+                    cnt[b] += 1
+                    cnt[c] += 1
+        m = min(cnt.values())
+        for u in X:
+            best[u] = max(best[u], m)
+    return best
+
+
+def test_core_numbers_closed_forms():
+    # K_n: every vertex has core n-1 and tr-core C(n-1, 2)
+    for n in (3, 5, 8):
+        s, d = np.triu_indices(n, 1)
+        G = oracle.Graph(n, s.astype(np.int32), d.astype(np.int32))
+        assert (oracle.core_numbers(G, 2) == n - 1).all()
+        assert (oracle.core_numbers(G, 3) == (n - 1) * (n - 2) // 2).all()
+    # star: core 1 everywhere, no triangles; cycle: core 2
+    G = oracle.Graph(6, np.zeros(5, np.int32), np.arange(1, 6, dtype=np.int32))
+    assert list(oracle.core_numbers(G, 2)) == [1] * 6
+    assert list(oracle.core_numbers(G, 3)) == [0] * 6
+    G = oracle.Graph(7, np.arange(7, dtype=np.int32), ((np.arange(7) + 1) % 7).astype(np.int32))
+    assert list(oracle.core_numbers(G, 2)) == [2] * 7
+    # an isolated vertex keeps 0
+    G = oracle.Graph(4, np.array([0, 1], np.int32), np.array([1, 2], np.int32))
+    assert list(oracle.core_numbers(G, 2)) == [1, 1, 1, 0]
+
+
+def test_core_numbers_by_enumeration():
+    rng = np.random.default_rng(3)
+    for trial in range(12):
+        n = int(rng.integers(4, 11))
+        edges = [(a, b) for a in range(n) for b in range(a + 1, n) if rng.random() < 0.45]
+        if not edges:
+            continue
+        e = np.array(edges, np.int32)
+        G = oracle.Graph(n, e[:, 0].copy(), e[:, 1].copy())
+        for mode in (2, 3):
+            assert list(oracle.core_numbers(G, mode)) == _core_by_enumeration(n, edges, mode)
