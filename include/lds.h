@@ -224,6 +224,19 @@ lds_status lds_batch_autotune(const lds_graph* graphs, const lds_mode* modes, co
                               const char* cache_path, int32_t reps, lds_tune* best, double* best_ms,
                               void* hip_stream);
 
+/* Core numbers that bound the compact numbers (Section 4.3): LDS_EDGE gives
+ * the k-core number of every vertex (the largest k such that the vertex lies
+ * in a subgraph whose vertices all have degree >= k in it), LDS_TRIANGLE the
+ * tr-core number (the same with triangles of the subgraph at each vertex);
+ * core / 2 <= phi <= core for edges, tr-core / 3 <= phi <= tr-core for
+ * triangles.  alive: NULL for the whole graph, else n host bytes by caller
+ * id: the numbers of the subgraph induced by the vertices with alive != 0
+ * (the residual graph of Pruning rule 2, Alg. 3), -1 for the other vertices.
+ * core_out: host int64, n entries by caller id.  Runs level-synchronous
+ * peeling on the device on hip_stream and synchronises it; lists the
+ * triangles first if needed (LDS_TRIANGLE). */
+lds_status lds_core_numbers(lds_graph g, lds_mode mode, const uint8_t* alive, int64_t* core_out, void* hip_stream);
+
 /* Result of lds_topk, allocated by the library; release with
  * lds_result_free.  Set i (0 <= i < count) has the caller ids
  * vertices[offsets[i] .. offsets[i+1]) in ascending order and the exact

@@ -59,6 +59,7 @@ def load():
         "lds_topk": (st, [vp, st, i32, i32, vp, vp]),
         "lds_result_free": (None, [vp]),
         "lds_loads": (st, [vp, st, vp, vp, vp, vp, vp, vp]),
+        "lds_core_numbers": (st, [vp, st, vp, vp, vp]),
         "lds_tune_default": (None, [vp]),
         "lds_batch_create": (st, [vp, vp, vp, vp, i32, u32, vp, vp, vp]),
         "lds_batch_run": (st, [vp, vp]),
@@ -297,6 +298,18 @@ def lds_loads(g, mode, r_out=None, want_r64=False, want_num=False, want_gap=Fals
     if want_gap:
         _check(load().lds_loads(g.handle, mode, None, None, None, _ptr(gap), None, _stream(stream)))
     out.update({k: v for k, v in (("r64", r64), ("num", num), ("gap", gap)) if v is not None})
+    return out
+
+
+def lds_core_numbers(g, mode, alive=None, stream=None):
+    """Core (mode 2) / tr-core (mode 3) numbers by caller id -> int64 array;
+    alive (n bools by caller id): those of the induced subgraph, -1 outside."""
+    n = lds_graph_info(g)["n"]
+    out = np.empty(n, np.int64)
+    al = None if alive is None else np.ascontiguousarray(np.asarray(alive, dtype=bool).astype(np.uint8))
+    if al is not None and al.shape != (n,):
+        raise ValueError("alive must have n entries")
+    _check(load().lds_core_numbers(g.handle, mode, _ptr(al), _ptr(out), _stream(stream)))
     return out
 
 

@@ -384,6 +384,16 @@ lds_status lds_loads(lds_graph g, lds_mode mode, float* r_out, double* r64_out, 
     API_CATCH
 }
 
+lds_status lds_core_numbers(lds_graph g, lds_mode mode, const uint8_t* alive, int64_t* core_out, void* hip_stream) {
+    API_TRY
+    LDS_CHECK(g != nullptr, lds::ST_INVALID, "graph is NULL");
+    LDS_CHECK(mode == LDS_EDGE || mode == LDS_TRIANGLE, lds::ST_INVALID, "mode must be LDS_EDGE or LDS_TRIANGLE");
+    LDS_CHECK(core_out != nullptr || g->g.n == 0, lds::ST_INVALID, "core_out is NULL");
+    std::lock_guard<std::mutex> lk(g->mu);
+    lds::core_numbers_caller(g->g, (int)mode, alive, core_out, (hipStream_t)hip_stream);
+    API_CATCH
+}
+
 void lds_tune_default(lds_tune* out) {
     if (!out) return;
     const lds::BatchTune t;

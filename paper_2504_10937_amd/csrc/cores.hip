@@ -1,0 +1,243 @@
+// Core numbers (edges) and tr-core numbers (triangles) on the device, for the
+// initial bounds of the compact numbers and for Pruning (Alg. 3, rule 2 needs
+// the core numbers of the residual graph).
+//
+// Level-synchronous peeling.  cnt[v] = number of patterns (edges or alive
+// triangles) at v among the vertices not yet peeled.  At level k every
+// remaining vertex with cnt <= k gets core k and is peeled; peeling v lowers
+// its neighbours' counts (for triangles: kills each alive triangle of v once,
+// lowering its two other vertices), and a vertex whose count drops to exactly
+// k joins the next frontier of the same level (the decrement from k+1 to k
+// happens once, so it joins once).  When a level's cascade ends, k jumps to
+// the smallest remaining count.  Remaining vertices are kept in a compacted
+// list, so each level costs in proportion to what is left.  The result is
+// unique, so it does not depend on the order of atomics.
+#include <climits>
+
+#include "graph.hpp"
+
+namespace lds {
+
+namespace {
+
+constexpr int kT = 256;
+constexpr int32_t kUnset = -1, kOutside = -2;
+
+__device__ inline void push(int32_t* list, int32_t* count, int32_t v) { list[atomicAdd(count, 1)] = v; }
+
+__global__ void k_init_edges(const int64_t* rowptr, const int32_t* col, int64_t n, const uint8_t* alive,
+                             int32_t* cnt, int32_t* core, int32_t* active, int32_t* na) {
+    const int64_t v = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (v >= n) return;
+    if (alive && !alive[v]) {
+        cnt[v] = 0;
+        core[v] = kOutside;
+        return;
+    }
+    int32_t c = 0;
+    for (int64_t s = rowptr[v]; s < rowptr[v + 1]; ++s) c += (!alive || alive[col[s]]) ? 1 : 0;
+    cnt[v] = c;
+    core[v] = kUnset;
+    push(active, na, (int32_t)v);
+}
+
+__global__ void k_init_vertices(int64_t n, const uint8_t* alive, int32_t* cnt, int32_t* core, int32_t* active,
+                                int32_t* na) {
+    const int64_t v = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (v >= n) return;
+    cnt[v] = 0;
+    if (alive && !alive[v]) {
+        core[v] = kOutside;
+        return;
+    }
+    core[v] = kUnset;
+    push(active, na, (int32_t)v);
+}
+
+__global__ void k_init_triangles(const int32_t* tri, int64_t T, const uint8_t* alive, int32_t* cnt,
+                                 uint32_t* talive) {
+    const int64_t t = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (t >= T) return;
+    const int32_t a = tri[3 * t], b = tri[3 * t + 1], c = tri[3 * t + 2];
+    const bool in = !alive || (alive[a] && alive[b] && alive[c]);
+    talive[t] = in ? 1u : 0u;
+    if (in) {
+        atomicAdd(&cnt[a], 1);
+        atomicAdd(&cnt[b], 1);
+        atomicAdd(&cnt[c], 1);
+    }
+}
+
+// remaining vertices with cnt <= k: core k, into the frontier
+__global__ void k_frontier(const int32_t* active, int32_t na, const int32_t* cnt, int32_t* core, int32_t k,
+                           int32_t* front, int32_t* fc) {
+    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (i >= na) return;
+    const int32_t v = active[i];
+    if (core[v] == kUnset && cnt[v] <= k) {
+        core[v] = k;
+        push(front, fc, v);
+    }
+}
+
+__device__ inline void lower(int32_t* cnt, int32_t* core, int32_t w, int32_t k, int32_t* next, int32_t* nc) {
+    if (core[w] != kUnset) return;
+    const int32_t old = atomicSub(&cnt[w], 1);
+    if (old == k + 1) {
+        core[w] = k;
+        push(next, nc, w);
+    }
+}
+
+// one wave per frontier vertex
+__global__ void k_peel_edges(const int32_t* front, int32_t fc, const int64_t* rowptr, const int32_t* col,
+                             int32_t* cnt, int32_t* core, int32_t k, int32_t* next, int32_t* nc) {
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * (kT / 64) + (threadIdx.x >> 6);
+    if (i >= fc) return;
+    const int32_t v = front[i];
+    for (int64_t s = rowptr[v] + lane; s < rowptr[v + 1]; s += 64) lower(cnt, core, col[s], k, next, nc);
+}
+
+__global__ void k_peel_triangles(const int32_t* front, int32_t fc, const int32_t* row_of, const int64_t* rp,
+                                 const int32_t* py, const int32_t* tos, uint32_t* talive, int32_t* cnt,
+                                 int32_t* core, int32_t k, int32_t* next, int32_t* nc) {
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * (kT / 64) + (threadIdx.x >> 6);
+    if (i >= fc) return;
+    const int32_t r = row_of[front[i]];
+    if (r < 0) return;
+    for (int64_t s = rp[r] + lane; s < rp[r + 1]; s += 64) {
+        if (atomicExch(&talive[tos[s]], 0u) == 0u) continue;  // killed before
+        lower(cnt, core, py[2 * s], k, next, nc);
+        lower(cnt, core, py[2 * s + 1], k, next, nc);
+    }
+}
+
+__global__ void k_min_remaining(const int32_t* active, int32_t na, const int32_t* cnt, const int32_t* core,
+                                int32_t* out) {
+    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+    int32_t m = INT32_MAX;
+    if (i < na) {
+        const int32_t v = active[i];
+        if (core[v] == kUnset) m = cnt[v];
+    }
+    for (int o = 32; o > 0; o >>= 1) m = min(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0 && m != INT32_MAX) atomicMin(out, m);
+}
+
+__global__ void k_compact(const int32_t* active, int32_t na, const int32_t* core, int32_t* out, int32_t* nout) {
+    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (i >= na) return;
+    const int32_t v = active[i];
+    if (core[v] == kUnset) push(out, nout, v);
+}
+
+__global__ void k_set(int32_t* p, int32_t v) { *p = v; }
+
+__global__ void k_alive_internal(const uint8_t* by_caller, const int32_t* orig_of, int64_t n, uint8_t* by_internal) {
+    const int64_t v = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (v < n) by_internal[v] = by_caller[orig_of[v]] ? 1 : 0;
+}
+
+__global__ void k_core_caller(const int32_t* core, const int32_t* orig_of, int64_t n, int64_t* by_caller) {
+    const int64_t v = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (v < n) by_caller[orig_of[v]] = core[v] == kOutside ? -1 : core[v];
+}
+
+int32_t d2h_i32(const int32_t* p, hipStream_t s) {
+    int32_t v = 0;
+    LDS_HIP(hipMemcpyAsync(&v, p, sizeof(v), hipMemcpyDeviceToHost, s));
+    LDS_HIP(hipStreamSynchronize(s));
+    return v;
+}
+
+}  // namespace
+
+void core_numbers_gpu(Graph& g, int mode, const uint8_t* alive, int32_t* core, hipStream_t s) {
+    const int64_t n = g.n;
+    if (n == 0) return;
+    LDS_CHECK(n < INT32_MAX, ST_INVALID, "too many vertices");
+    if (mode == 3 && g.T < 0) list_triangles(g, s);
+    DBuf<int32_t> cnt, act, act2, front, next, ctr;
+    DBuf<uint32_t> talive;
+    cnt.alloc(n, s);
+    act.alloc(n, s);
+    act2.alloc(n, s);
+    front.alloc(n, s);
+    next.alloc(n, s);
+    ctr.alloc(4, s);  // [0] active count, [1] frontier count, [2] next count, [3] minimum
+    k_set<<<1, 1, 0, s>>>(ctr.p, 0);
+    if (mode == 2) {
+        k_init_edges<<<grid_for(n, kT), kT, 0, s>>>(g.rowptr.p, g.col.p, n, alive, cnt.p, core, act.p, ctr.p);
+    } else {
+        k_init_vertices<<<grid_for(n, kT), kT, 0, s>>>(n, alive, cnt.p, core, act.p, ctr.p);
+        if (g.T > 0) {
+            talive.alloc(g.T, s);
+            k_init_triangles<<<grid_for(g.T, kT), kT, 0, s>>>(g.tri.p, g.T, alive, cnt.p, talive.p);
+        }
+    }
+    LDS_HIP(hipGetLastError());
+    const SweepPlan& tp = g.tri_plan;
+    int32_t na = d2h_i32(ctr.p, s);
+    int32_t k = 0;
+    while (na > 0) {
+        k_set<<<1, 1, 0, s>>>(ctr.p + 1, 0);
+        k_frontier<<<grid_for(na, kT), kT, 0, s>>>(act.p, na, cnt.p, core, k, front.p, ctr.p + 1);
+        LDS_HIP(hipGetLastError());
+        int32_t fc = d2h_i32(ctr.p + 1, s);
+        if (fc == 0) {  // nothing at this level: jump to the smallest remaining count
+            k_set<<<1, 1, 0, s>>>(ctr.p + 3, INT32_MAX);
+            k_min_remaining<<<grid_for(na, kT), kT, 0, s>>>(act.p, na, cnt.p, core, ctr.p + 3);
+            LDS_HIP(hipGetLastError());
+            const int32_t m = d2h_i32(ctr.p + 3, s);
+            LDS_CHECK(m != INT32_MAX && m > k, ST_DEVICE, "core peeling: no progress");
+            k = m;
+            continue;
+        }
+        while (fc > 0) {
+            k_set<<<1, 1, 0, s>>>(ctr.p + 2, 0);
+            if (mode == 2)
+                k_peel_edges<<<grid_for(fc, kT / 64), kT, 0, s>>>(front.p, fc, g.rowptr.p, g.col.p, cnt.p, core, k,
+                                                                 next.p, ctr.p + 2);
+            else
+                k_peel_triangles<<<grid_for(fc, kT / 64), kT, 0, s>>>(front.p, fc, tp.own_row_of.p, tp.rp, tp.py,
+                                                                     tp.own_tos.p, talive.p, cnt.p, core, k,
+                                                                     next.p, ctr.p + 2);
+            LDS_HIP(hipGetLastError());
+            fc = d2h_i32(ctr.p + 2, s);
+            std::swap(front.p, next.p);
+        }
+        k_set<<<1, 1, 0, s>>>(ctr.p, 0);
+        k_compact<<<grid_for(na, kT), kT, 0, s>>>(act.p, na, core, act2.p, ctr.p);
+        LDS_HIP(hipGetLastError());
+        na = d2h_i32(ctr.p, s);
+        std::swap(act.p, act2.p);
+        ++k;
+    }
+}
+
+void core_numbers_caller(Graph& g, int mode, const uint8_t* alive_host, int64_t* core_host, hipStream_t s) {
+    const int64_t n = g.n;
+    if (mode == 3 && g.T < 0) list_triangles(g, s);
+    if (n == 0) return;
+    DBuf<uint8_t> al, ai;
+    if (alive_host) {
+        al.alloc(n, s);
+        ai.alloc(n, s);
+        LDS_HIP(hipMemcpyAsync(al.p, alive_host, n, hipMemcpyHostToDevice, s));
+        k_alive_internal<<<grid_for(n, kT), kT, 0, s>>>(al.p, g.orig_of.p, n, ai.p);
+        LDS_HIP(hipGetLastError());
+    }
+    DBuf<int32_t> core;
+    DBuf<int64_t> out;
+    core.alloc(n, s);
+    out.alloc(n, s);
+    core_numbers_gpu(g, mode, ai.p, core.p, s);
+    k_core_caller<<<grid_for(n, kT), kT, 0, s>>>(core.p, g.orig_of.p, n, out.p);
+    LDS_HIP(hipGetLastError());
+    LDS_HIP(hipMemcpyAsync(core_host, out.p, n * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    LDS_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace lds

@@ -140,6 +140,13 @@ void list_triangles(Graph& g, hipStream_t s);
 void sg_sort_prefix(Graph& g, int mode, hipStream_t s);
 void sg_stable_groups(Graph& g, int mode, hipStream_t s);
 
+// cores.hip: core (mode 2) / tr-core (mode 3) numbers of the subgraph induced
+// by alive (device bytes, internal order; nullptr = all vertices) into core
+// (device, internal order; -2 for vertices outside).  Lists triangles if needed.
+void core_numbers_gpu(Graph& g, int mode, const uint8_t* alive, int32_t* core, hipStream_t s);
+// the same with host arrays by caller id (-1 outside); synchronises s
+void core_numbers_caller(Graph& g, int mode, const uint8_t* alive_host, int64_t* core_host, hipStream_t s);
+
 // fw.hip
 unsigned __int128 fw_max_numerator(const Graph& g, int mode, int iters);
 // lists triangles if needed, checks the key width and sizes the FW buffers

@@ -11,7 +11,8 @@
 //    verification uses.
 //  * Pruning (Alg. 3): rule 1 (Cor. uv-prune) once, then rule 2 (Lemma
 //    uu-prune) with core / tr-core numbers of the residual graph until
-//    nothing changes.
+//    nothing changes.  Core numbers come from level-synchronous peeling on
+//    the device (cores.hip).
 //  * Candidates are taken in non-increasing order of an upper bound on the
 //    density of any LDS inside them (a vertex of an LDS S has phi = density
 //    of S).  A disconnected candidate is split into its components.
@@ -439,95 +440,24 @@ void HostGraph::load(const Graph& g, int mode, hipStream_t s) {
 
 namespace {
 
-// Peeling in the bin-sort form of Batagelj and Zaversnik: vertices sit in
-// an array sorted by count, bin[c] is the first position with count c;
-// removing the vertex of minimum count v lowers each affected vertex u with
-// cnt[u] > cnt[v] by one (a swap to the front of its bin).  core[v] is cnt[v]
-// when v is removed.  each(v, dec) calls dec(u) once per unit that removing v
-// takes from u's count.
-template <class Each>
-std::vector<int32_t> peel(int64_t n, const std::vector<char>& alive, std::vector<int32_t>& cnt, Each each) {
-    std::vector<int32_t> core(n, 0);
-    int32_t mx = 0;
-    int64_t na = 0;
-    for (int64_t u = 0; u < n; ++u)
-        if (alive[u]) {
-            mx = std::max(mx, cnt[u]);
-            ++na;
-        }
-    std::vector<int64_t> bin((size_t)mx + 2, 0), pos(n, -1);
-    std::vector<int32_t> vert((size_t)na);
-    for (int64_t u = 0; u < n; ++u)
-        if (alive[u]) bin[cnt[u] + 1]++;
-    for (int32_t c = 0; c <= mx; ++c) bin[c + 1] += bin[c];
-    {
-        std::vector<int64_t> fill(bin.begin(), bin.end() - 1);
-        for (int64_t u = 0; u < n; ++u)
-            if (alive[u]) {
-                pos[u] = fill[cnt[u]]++;
-                vert[pos[u]] = (int32_t)u;
-            }
+// core (mode 2) / tr-core (mode 3) numbers of the subgraph induced by the
+// alive vertices (all when alive is null), by peeling on the device;
+// internal order, -2 for vertices outside
+std::vector<int32_t> device_cores(Graph& g, int mode, const std::vector<char>* alive, hipStream_t s) {
+    const int64_t n = g.n;
+    std::vector<int32_t> out((size_t)n, 0);
+    if (n == 0) return out;
+    DBuf<uint8_t> al;
+    if (alive) {
+        al.alloc(n, s);
+        LDS_HIP(hipMemcpyAsync(al.p, alive->data(), n, hipMemcpyHostToDevice, s));
     }
-    std::vector<char> done(n, 0);
-    int32_t cv = 0;
-    auto dec = [&](int32_t u) {
-        if (!alive[u] || done[u] || cnt[u] <= cv) return;
-        const int32_t du = cnt[u];
-        const int64_t pu = pos[u], pw = bin[du];
-        const int32_t w = vert[pw];
-        if (u != w) {
-            vert[pu] = w;
-            pos[w] = pu;
-            vert[pw] = u;
-            pos[u] = pw;
-        }
-        bin[du]++;
-        cnt[u]--;
-    };
-    for (int64_t i = 0; i < na; ++i) {
-        const int32_t v = vert[i];
-        cv = cnt[v];
-        core[v] = cv;
-        done[v] = 1;
-        each(v, dec);
-    }
-    return core;
-}
-
-// core numbers of the subgraph induced by the alive vertices
-std::vector<int32_t> core_numbers(const HostGraph& h, const std::vector<char>& alive) {
-    std::vector<int32_t> cnt(h.n, 0);
-    for (int64_t u = 0; u < h.n; ++u)
-        if (alive[u])
-            for (int64_t s = h.rp[u]; s < h.rp[u + 1]; ++s) cnt[u] += alive[h.col[s]];
-    return peel(h.n, alive, cnt, [&](int32_t u, auto& dec) {
-        for (int64_t s = h.rp[u]; s < h.rp[u + 1]; ++s) dec(h.col[s]);
-    });
-}
-
-// tr-core numbers: the count is the number of alive triangles at a vertex
-std::vector<int32_t> trcore_numbers(const HostGraph& h, const std::vector<char>& alive) {
-    const int64_t T = (int64_t)h.tri.size() / 3;
-    std::vector<char> tal(T, 0);
-    std::vector<int32_t> cnt(h.n, 0);
-    for (int64_t t = 0; t < T; ++t) {
-        const int32_t* x = &h.tri[3 * t];
-        if (alive[x[0]] && alive[x[1]] && alive[x[2]]) {
-            tal[t] = 1;
-            ++cnt[x[0]];
-            ++cnt[x[1]];
-            ++cnt[x[2]];
-        }
-    }
-    return peel(h.n, alive, cnt, [&](int32_t u, auto& dec) {
-        for (int64_t i = h.trp[u]; i < h.trp[u + 1]; ++i) {
-            const int64_t t = h.tinc[i];
-            if (!tal[t]) continue;
-            tal[t] = 0;
-            for (int j = 0; j < 3; ++j)
-                if (h.tri[3 * t + j] != u) dec(h.tri[3 * t + j]);
-        }
-    });
+    DBuf<int32_t> c;
+    c.alloc(n, s);
+    core_numbers_gpu(g, mode, al.p, c.p, s);
+    LDS_HIP(hipMemcpyAsync(out.data(), c.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    LDS_HIP(hipStreamSynchronize(s));
+    return out;
 }
 
 struct Cand {
@@ -877,7 +807,7 @@ void topk_run(Graph& g, int mode, int k, int iters, hipStream_t s, std::vector<T
     // bounds from core (tr-core) numbers
     {
         std::vector<int32_t>& core = hc.core[mode == 2 ? 0 : 1];
-        if (core.empty()) core = (mode == 2) ? core_numbers(c.h, alive) : trcore_numbers(c.h, alive);
+        if (core.empty()) core = device_cores(g, mode, nullptr, s);
         c.lo.resize(n);
         c.hi.resize(n);
         for (int64_t u = 0; u < n; ++u) {
@@ -924,7 +854,7 @@ void topk_run(Graph& g, int mode, int k, int iters, hipStream_t s, std::vector<T
                 break;
             }
     for (;;) {
-        const std::vector<int32_t> cr = (mode == 2) ? core_numbers(c.h, alive) : trcore_numbers(c.h, alive);
+        const std::vector<int32_t> cr = device_cores(g, mode, &alive, s);
         bool changed = false;
         for (int64_t u = 0; u < n; ++u)
             if (alive[u] && lt(Frac{cr[u], 1}, c.lo[u])) {

@@ -4,10 +4,8 @@
 // small random inputs:
 //   * minimum cuts (edge network, pattern network, both warm-started from
 //     arbitrary splits): the maximum of q*|P(X)| - p*|X| and the union of all
-//     maximisers, by enumeration of every X;
-//   * core and tr-core numbers: largest k such that the vertex lies in a
-//     subgraph whose every vertex has >= k edges (triangles) inside, by
-//     repeated deletion for every k.
+//     maximisers, by enumeration of every X.
+// (Core and tr-core numbers run on the device; their parity is a GPU test.)
 // Prints "ok" and exits 0 when every case agrees.
 #include "../../paper_2504_10937_amd/csrc/topk.cpp"
 
@@ -22,6 +20,7 @@ void build_graph(Graph&, int64_t, int64_t, const int32_t*, const int32_t*, bool,
 void list_triangles(Graph&, hipStream_t) {}
 void sg_stable_groups(Graph&, int, hipStream_t) {}
 void fw_run(Graph&, int, int, bool, hipStream_t) {}
+void core_numbers_gpu(Graph&, int, const uint8_t*, int32_t*, hipStream_t) {}
 }  // namespace lds
 
 using namespace lds;
@@ -52,42 +51,6 @@ static int64_t enumerate(int64_t k, int h, const std::vector<int32_t>& pat, cons
     X.assign(k, 0);
     for (int64_t v = 0; v < k; ++v) X[v] = (un >> v) & 1;
     return best;
-}
-
-// core numbers by definition: for each k, delete vertices with < k edges
-// (triangles) among the remaining until none; survivors have core >= k
-static std::vector<int32_t> core_by_definition(const HostGraph& h, int mode) {
-    std::vector<int32_t> core(h.n, 0);
-    for (int32_t k = 1;; ++k) {
-        std::vector<char> alive(h.n, 1);
-        bool changed = true;
-        while (changed) {
-            changed = false;
-            for (int64_t u = 0; u < h.n; ++u) {
-                if (!alive[u]) continue;
-                int32_t c = 0;
-                if (mode == 2) {
-                    for (int64_t s = h.rp[u]; s < h.rp[u + 1]; ++s) c += alive[h.col[s]];
-                } else {
-                    for (int64_t i = h.trp[u]; i < h.trp[u + 1]; ++i) {
-                        const int32_t* x = &h.tri[3 * h.tinc[i]];
-                        c += alive[x[0]] && alive[x[1]] && alive[x[2]];
-                    }
-                }
-                if (c < k) {
-                    alive[u] = 0;
-                    changed = true;
-                }
-            }
-        }
-        bool any = false;
-        for (int64_t u = 0; u < h.n; ++u)
-            if (alive[u]) {
-                core[u] = k;
-                any = true;
-            }
-        if (!any) return core;
-    }
 }
 
 int main() {
@@ -149,45 +112,6 @@ int main() {
             ++cases;
             if (max_excess(k, 3, full, p, q, X, &sp, D) != enumerate(k, 3, full, {}, p, q, Y) || X != Y) ++bad;
         }
-    }
-    // core and tr-core numbers on random graphs
-    for (int it = 0; it < 200; ++it) {
-        HostGraph h;
-        h.n = 5 + (int64_t)(rng() % 40);
-        const double pe = 0.05 + (double)(rng() % 50) / 100.0;
-        std::vector<std::vector<int32_t>> adj(h.n);
-        for (int64_t a = 0; a < h.n; ++a)
-            for (int64_t b = a + 1; b < h.n; ++b)
-                if ((double)(rng() % 1000) < pe * 1000) {
-                    adj[a].push_back((int32_t)b);
-                    adj[b].push_back((int32_t)a);
-                }
-        h.rp.assign(h.n + 1, 0);
-        for (int64_t u = 0; u < h.n; ++u) h.rp[u + 1] = h.rp[u] + (int64_t)adj[u].size();
-        for (int64_t u = 0; u < h.n; ++u) h.col.insert(h.col.end(), adj[u].begin(), adj[u].end());
-        std::vector<std::vector<char>> am(h.n, std::vector<char>(h.n, 0));
-        for (int64_t u = 0; u < h.n; ++u)
-            for (int32_t v : adj[u]) am[u][v] = 1;
-        for (int64_t a = 0; a < h.n; ++a)
-            for (int64_t b = a + 1; b < h.n; ++b)
-                for (int64_t c = b + 1; c < h.n; ++c)
-                    if (am[a][b] && am[b][c] && am[a][c]) {
-                        h.tri.push_back((int32_t)a);
-                        h.tri.push_back((int32_t)b);
-                        h.tri.push_back((int32_t)c);
-                    }
-        const int64_t T = (int64_t)h.tri.size() / 3;
-        h.trp.assign(h.n + 1, 0);
-        for (int64_t t = 0; t < 3 * T; ++t) h.trp[h.tri[t] + 1]++;
-        for (int64_t u = 0; u < h.n; ++u) h.trp[u + 1] += h.trp[u];
-        h.tinc.assign(3 * T, 0);
-        std::vector<int64_t> fill(h.trp.begin(), h.trp.end() - 1);
-        for (int64_t t = 0; t < T; ++t)
-            for (int j = 0; j < 3; ++j) h.tinc[fill[h.tri[3 * t + j]]++] = t;
-        const std::vector<char> alive(h.n, 1);
-        cases += 2;
-        if (core_numbers(h, alive) != core_by_definition(h, 2)) ++bad;
-        if (trcore_numbers(h, alive) != core_by_definition(h, 3)) ++bad;
     }
     std::printf("%s: %d of %d cases disagree\n", bad ? "FAIL" : "ok", bad, cases);
     return bad ? 1 : 0;

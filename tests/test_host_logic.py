@@ -1,5 +1,5 @@
 """Host-side exact logic of the top-k driver (min cuts with and without warm
-starts, core / tr-core numbers), built from the library's own source with
+starts), built from the library's own source with
 the device entry points stubbed and checked against plain definitions by
 enumeration.  CPU only."""
 import os
