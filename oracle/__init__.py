@@ -44,6 +44,7 @@ def _load():
         "orc_graph_edges": (None, [vp, vp, vp]),
         "orc_graph_degrees": (None, [vp, vp]),
         "orc_triangles": (i64, [vp, vp, vp]),
+        "orc_cliques4": (i64, [vp, vp, vp]),
         "orc_fw_exact": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp]),
         "orc_fw_literal": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, vp, vp]),
         "orc_sort_prefix": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, vp, vp]),
@@ -67,8 +68,9 @@ def _p(a):
 
 def denominator(mode, iters):
     """Common denominator of the loads after `iters` iterations with
-    gamma_i = 2/(i+2): (i+1)(i+2) for edges, 3(i+1)(i+2) for triangles."""
-    return (3 if mode == 3 else 1) * (iters + 1) * (iters + 2)
+    gamma_i = 2/(i+2): (i+1)(i+2) for edges, 3(i+1)(i+2) for triangles,
+    2(i+1)(i+2) for 4-cliques (mode 4)."""
+    return {2: 1, 3: 3, 4: 2}[mode] * (iters + 1) * (iters + 2)
 
 
 class Graph:
@@ -114,12 +116,30 @@ def triangles(G):
     return tri, cnt
 
 
+def cliques4(G):
+    """All 4-cliques as a sorted (Q,4) array of ascending quadruples, plus the
+    per-vertex 4-clique counts."""
+    L = _load()
+    Q = L.orc_cliques4(G._h, None, None)
+    if Q < 0:
+        raise MemoryError
+    q = np.empty((Q, 4), np.int32)
+    cnt = np.empty(G.n, np.int64)
+    L.orc_cliques4(G._h, _p(q), _p(cnt))
+    return q, cnt
+
+
 def num_patterns(G, mode):
-    return G.m if mode == 2 else int(_load().orc_triangles(G._h, None, None))
+    if mode == 2:
+        return G.m
+    if mode == 3:
+        return int(_load().orc_triangles(G._h, None, None))
+    return int(_load().orc_cliques4(G._h, None, None))
 
 
 def fw_exact(G, mode, iters, with_gap=True, with_split=True):
-    """Alg. 1 (mode 2) / Alg. 6 (mode 3) in exact rational form.
+    """Alg. 1 (mode 2) / Alg. 6 (mode 3) / the same iteration over 4-cliques
+    (mode 4) in exact rational form.
 
     Returns dict(A=numerators (n,), D=denominator, split=(P,h) numerators in
     canonical pattern order, gap=(iters,), lb=(iters,))."""

@@ -11,9 +11,14 @@
  *   triangles ........... the set T used by Eq. (trcp) / Alg. 6 (the paper
  *                         does not say how it is listed; forward algorithm
  *                         over a degree orientation, then sorted)
+ *   cliques4 ............ the 4-clique set of the h-clique program that
+ *                         Eq. trcp generalises (h = 4; Section 2 / Section 6
+ *                         cite the k-clique density line of work): every
+ *                         4-clique once, sorted
  *   fw_exact ............ Alg. 1 (edges, Eq. cp) and Alg. 6 (triangles,
  *                         Eq. trcp) with gamma_i = 2/(i+2), decisions on the
- *                         exact rational loads r = A / D_i (A integer)
+ *                         exact rational loads r = A / D_i (A integer); the
+ *                         same iteration over 4-cliques (mode 4)
  *   fw_literal .......... Alg. 1 / Alg. 6 in plain FP64 (alpha, r doubles)
  *   sort_prefix ......... Alg. 2 lines 2-4 (sort by r, prefix densities,
  *                         index set I of suffix argmaxima, ties -> larger j)
@@ -33,6 +38,8 @@
  *     denominator D_i = (i+1)(i+2) (edges) or 3(i+1)(i+2) (triangles); the
  *     numerators are integers: A^(i) = A^(i-1) + 2(i+1) b (edges),
  *     A^(i) = A^(i-1) + 6(i+1) b (triangles), b = units won in iteration i.
+ *     For 4-cliques D_i = 2(i+1)(i+2), D_0 = 4 holds the initial quarter
+ *     shares as numerator 1, and A^(i) = A^(i-1) + 4(i+1) b.
  *   - sort ties (Alg. 2 line 2): original id ascending.
  *   - restriction in ExtractSG: every pattern (edge / triangle) touching the
  *     tested group gives weight only to its vertices in the lowest group it
@@ -206,7 +213,44 @@ int64_t orc_triangles(const orc_graph *g, int32_t *tri, int64_t *tcount) {
     return cnt;
 }
 
-/* patterns (edges or triangles) as flat vertex tuples */
+/* ============================================================ 4-cliques == */
+static int adjacent(const orc_graph *g, int32_t u, int32_t v) {
+    int64_t lo = g->off[u], hi = g->off[u + 1];
+    while (lo < hi) {
+        int64_t mid = (lo + hi) / 2;
+        if (g->adj[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    return lo < g->off[u + 1] && g->adj[lo] == v;
+}
+
+/* Lists all 4-cliques as ascending quadruples (a<b<c<d), sorted
+ * lexicographically: every triangle a<b<c (sorted) is extended by each
+ * d > c adjacent to a, b and c, in ascending order of d, so each 4-clique
+ * appears once, from its three smallest vertices.  Returns the count (or -1).
+ * `q` (4 per clique) and `qcount` (n) may be NULL. */
+int64_t orc_cliques4(const orc_graph *g, int32_t *q, int64_t *qcount) {
+    int64_t T = orc_triangles(g, NULL, NULL);
+    if (T < 0) return -1;
+    int32_t *tri = (int32_t *)malloc((size_t)(3 * T > 0 ? 3 * T : 1) * sizeof(int32_t));
+    if (!tri) return -1;
+    if (orc_triangles(g, tri, NULL) != T) { free(tri); return -1; }
+    if (qcount) memset(qcount, 0, (size_t)g->n * sizeof(int64_t));
+    int64_t cnt = 0;
+    for (int64_t t = 0; t < T; t++) {
+        int32_t a = tri[3 * t], b = tri[3 * t + 1], c = tri[3 * t + 2];
+        for (int64_t s = g->off[c]; s < g->off[c + 1]; s++) {
+            int32_t d = g->adj[s];
+            if (d <= c || !adjacent(g, a, d) || !adjacent(g, b, d)) continue;
+            if (q) { q[4 * cnt] = a; q[4 * cnt + 1] = b; q[4 * cnt + 2] = c; q[4 * cnt + 3] = d; }
+            if (qcount) { qcount[a]++; qcount[b]++; qcount[c]++; qcount[d]++; }
+            cnt++;
+        }
+    }
+    free(tri);
+    return cnt;
+}
+
+/* patterns (edges, triangles or 4-cliques) as flat vertex tuples */
 typedef struct { int h; int64_t np; int32_t *v; } patterns;
 static int get_patterns(const orc_graph *g, int mode, patterns *P) {
     P->h = mode;
@@ -224,6 +268,15 @@ static int get_patterns(const orc_graph *g, int mode, patterns *P) {
         P->v = (int32_t *)malloc((size_t)(3 * T > 0 ? 3 * T : 1) * sizeof(int32_t));
         if (!P->v) return -1;
         if (orc_triangles(g, P->v, NULL) != T) { free(P->v); return -1; }
+        return 0;
+    }
+    if (mode == 4) {
+        int64_t Q = orc_cliques4(g, NULL, NULL);
+        if (Q < 0) return -1;
+        P->np = Q;
+        P->v = (int32_t *)malloc((size_t)(4 * Q > 0 ? 4 * Q : 1) * sizeof(int32_t));
+        if (!P->v) return -1;
+        if (orc_cliques4(g, P->v, NULL) != Q) { free(P->v); return -1; }
         return 0;
     }
     return -1;
@@ -269,38 +322,42 @@ int orc_core_numbers(const orc_graph *g, int mode, int64_t *core) {
 }
 
 /* ============================================================ FW exact == */
-/* Denominator of the loads after iteration i (App.-B style exact form of
- * gamma_i = 2/(i+2)): (i+1)(i+2) for edges, 3(i+1)(i+2) for triangles. */
+/* Denominator of the loads after iteration i (exact form of gamma_i =
+ * 2/(i+2)): (i+1)(i+2) for edges, 3(i+1)(i+2) for triangles, 2(i+1)(i+2)
+ * for 4-cliques (D_0 = 2, 6, 4: the initial 1/h shares are integers). */
 static uint64_t denom(int mode, int64_t i) {
-    return (uint64_t)(mode == 3 ? 3 : 1) * (uint64_t)(i + 1) * (uint64_t)(i + 2);
+    const uint64_t c = mode == 3 ? 3 : (mode == 4 ? 2 : 1);
+    return c * (uint64_t)(i + 1) * (uint64_t)(i + 2);
 }
 
-/* Alg. 1 / Alg. 6.  Outputs after `iters` iterations:
+/* Alg. 1 / Alg. 6 (and the 4-clique iteration, mode 4).  Outputs after
+ * `iters` iterations:
  *   A[u]      numerator of r_u (r_u = A[u] / D_iters)
  *   split[h*p+j] numerator of alpha_{x_j, p} for pattern p's j-th vertex
  *             (patterns in canonical order: edges (u<v) sorted, triangles
- *             (a<b<c) sorted); the h numerators of a pattern sum to D_iters
+ *             (a<b<c) and 4-cliques (a<b<c<d) sorted); the h numerators of
+ *             a pattern sum to D_iters
  *   gap[i-1]  FW duality gap at r^(i-1): 2 (sum r^2 - sum_p min_{x in p} r_x)
  *   lb[i-1]   the matching lower bound on the optimum, sum r^2 - gap
  * Any output pointer may be NULL.  Returns 0, or -1 (allocation / mode). */
 int orc_fw_exact(const orc_graph *g, int mode, int iters, uint64_t *A_out, uint64_t *split_out,
                  double *gap_out, double *lb_out) {
     patterns P;
-    if ((mode != 2 && mode != 3) || iters < 0 || get_patterns(g, mode, &P)) return -1;
+    if ((mode < 2 || mode > 4) || iters < 0 || get_patterns(g, mode, &P)) return -1;
     int h = P.h;
     int64_t n = g->n, np = P.np;
     uint64_t *A = (uint64_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(uint64_t));
     uint64_t *b = (uint64_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(uint64_t));
     uint64_t *sp = (uint64_t *)malloc((size_t)(h * np > 0 ? h * np : 1) * sizeof(uint64_t));
     if (!A || !b || !sp) { free(A); free(b); free(sp); free(P.v); return -1; }
-    /* initial split: 1/h of each pattern to each vertex; D_0 = 2 (edges) or
-     * 6 (triangles), so the numerator is 1 or 2 */
-    uint64_t a0 = (mode == 2) ? 1 : 2;
+    /* initial split: 1/h of each pattern to each vertex; D_0 = 2 (edges), 6
+     * (triangles) or 4 (4-cliques), so the numerator is D_0 / h = 1, 2 or 1 */
+    uint64_t a0 = denom(mode, 0) / (uint64_t)h;
     for (int64_t p = 0; p < np; p++)
         for (int j = 0; j < h; j++) { sp[h * p + j] = a0; A[P.v[h * p + j]] += a0; }
     for (int64_t i = 1; i <= iters; i++) {
         uint64_t Dprev = denom(mode, i - 1);
-        uint64_t inc = denom(mode, i) - Dprev; /* 2(i+1) or 6(i+1) */
+        uint64_t inc = denom(mode, i) - Dprev; /* 2(i+1), 6(i+1) or 4(i+1) */
         memset(b, 0, (size_t)n * sizeof(uint64_t));
         u128 summin = 0;
         for (int64_t p = 0; p < np; p++) {
@@ -342,7 +399,7 @@ int orc_fw_exact(const orc_graph *g, int mode, int iters, uint64_t *A_out, uint6
  * FP64 loads (ties -> larger original id).  Outputs r (n) and alpha (h*np). */
 int orc_fw_literal(const orc_graph *g, int mode, int iters, double *r_out, double *alpha_out) {
     patterns P;
-    if ((mode != 2 && mode != 3) || iters < 0 || get_patterns(g, mode, &P)) return -1;
+    if ((mode < 2 || mode > 4) || iters < 0 || get_patterns(g, mode, &P)) return -1;
     int h = P.h;
     int64_t n = g->n, np = P.np;
     double *r = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));

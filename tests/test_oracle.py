@@ -387,3 +387,119 @@ def test_core_numbers_by_enumeration():
         G = oracle.Graph(n, e[:, 0].copy(), e[:, 1].copy())
         for mode in (2, 3):
             assert list(oracle.core_numbers(G, mode)) == _core_by_enumeration(n, edges, mode)
+
+
+# ------------------------------------------------------- 4-clique program (h = 4)
+def clique_graphs():
+    """small graphs with 4-cliques: dense G(n,p), planted blocks, triadic closure"""
+    out = [synth.erdos_renyi(10 + s % 3, 0.55 + 0.05 * s, seed=40 + s) for s in range(4)]
+    out += [synth.powerlaw_planted(12, 2.3, 3.0, 2, 5, 6, 0.95, seed=50 + s) for s in range(3)]
+    out.append(synth.holme_kim(12, 4, 0.8, seed=8))
+    return out
+
+
+def test_cliques4_by_enumeration():
+    for n, s, d in clique_graphs() + [synth.powerlaw_planted(60, 2.3, 6.0, 2, 8, 12, 0.8, seed=9)]:
+        G = oracle.Graph(n, s, d)
+        u, v = G.edges()
+        E = set(zip(u.tolist(), v.tolist()))
+        want = [q for q in itertools.combinations(range(G.n), 4)
+                if all((q[i], q[j]) in E for i in range(4) for j in range(i + 1, 4))]
+        got, cnt = oracle.cliques4(G)
+        assert [tuple(x) for x in got.tolist()] == want
+        c = np.zeros(G.n, np.int64)
+        for q in want:
+            c[list(q)] += 1
+        assert cnt.tolist() == c.tolist()
+    assert sum(len(oracle.cliques4(oracle.Graph(*g))[0]) for g in clique_graphs()) > 20
+
+
+def test_fw4_hand_iterations_k4_k5():
+    """K4: r0 = 1/4 each (D0 = 4, numerators 1).  Iteration 1: all tie, the
+    largest id wins, inc = 4*2: A = (1,1,1,9) / 12.  Iteration 2: ids 0..2 tie
+    at 1, id 2 wins, inc 12: (1,1,13,9) / 24.  Iteration 3: ids 0, 1 tie, id 1
+    wins, inc 16: (1,17,13,9) / 40.  K5: every vertex lies in 4 of the 5
+    4-cliques, r0 = 1 (A = 4 over D0 = 4)."""
+    k4 = [(a, b) for a in range(4) for b in range(a + 1, 4)]
+    G = oracle.Graph(4, np.array([e[0] for e in k4], np.int32), np.array([e[1] for e in k4], np.int32))
+    want = {0: ([1, 1, 1, 1], 4), 1: ([1, 1, 1, 9], 12), 2: ([1, 1, 13, 9], 24), 3: ([1, 17, 13, 9], 40)}
+    for it, (A, D) in want.items():
+        out = oracle.fw_exact(G, 4, it)
+        assert out["A"].tolist() == A and out["D"] == D
+        assert out["split"].tolist() == [A]  # one clique: its split is the load
+    # the uniform start is optimal on K4: zero gap at r0
+    assert oracle.fw_exact(G, 4, 1)["gap"][0] == 0.0
+    k5 = [(a, b) for a in range(5) for b in range(a + 1, 5)]
+    G = oracle.Graph(5, np.array([e[0] for e in k5], np.int32), np.array([e[1] for e in k5], np.int32))
+    assert oracle.fw_exact(G, 4, 0)["A"].tolist() == [4] * 5
+    # no 4-clique: nothing to route
+    tri = oracle.Graph(3, np.array([0, 1, 0], np.int32), np.array([1, 2, 2], np.int32))
+    out = oracle.fw_exact(tri, 4, 5)
+    assert out["A"].tolist() == [0, 0, 0] and out["split"].shape == (0, 4)
+
+
+def test_fw4_invariants():
+    n, s, d = synth.powerlaw_planted(200, 2.3, 6.0, 3, 8, 14, 0.7, seed=31)
+    G = oracle.Graph(n, s, d)
+    q, cnt = oracle.cliques4(G)
+    assert len(q) > 100
+    out = oracle.fw_exact(G, 4, 50)
+    D = out["D"]
+    assert D == 2 * 51 * 52
+    assert (out["split"].sum(axis=1) == D).all() and (out["split"] >= 0).all()
+    assert int(out["A"].sum()) == D * len(q)
+    r = np.zeros(G.n, np.int64)
+    np.add.at(r, q.reshape(-1), out["split"].astype(np.int64).reshape(-1))
+    assert (r == out["A"].astype(np.int64)).all()
+    assert (out["gap"] >= 0).all()
+    # the first iterate is the initial quarter shares
+    assert (oracle.fw_exact(G, 4, 0)["A"] == cnt).all()
+    # the FP64 transcription takes the same first step
+    r_lit, al_lit = oracle.fw_literal(G, 4, 1)
+    ex = oracle.fw_exact(G, 4, 1)
+    assert np.abs(ex["A"] / ex["D"] - r_lit).max() < 1e-12
+    assert np.abs(ex["split"] / ex["D"] - al_lit).max() < 1e-15
+
+
+def clique_levels(n, cliques):
+    """Optimum of the 4-clique program by brute force over vertex subsets: the
+    nested sets B_1 < B_2 < ... of the density-friendly decomposition, each the
+    largest U above B_{i-1} maximising (c(U) - c(B_{i-1})) / (|U| - |B_{i-1}|),
+    c(U) = 4-cliques inside U; every vertex of B_i \\ B_{i-1} gets that ratio."""
+    masks = [sum(1 << x for x in q) for q in cliques]
+    c = [sum(1 for m in masks if (U & m) == m) for U in range(1 << n)]
+    r = [Fraction(0)] * n
+    B = 0
+    while B != (1 << n) - 1:
+        best, top = None, 0
+        for U in range(1 << n):
+            if U & B != B or U == B:
+                continue
+            lam = Fraction(c[U] - c[B], bin(U).count("1") - bin(B).count("1"))
+            if best is None or lam > best:
+                best, top = lam, U
+            elif lam == best:
+                top |= U
+        for x in range(n):
+            if (top >> x) & 1 and not (B >> x) & 1:
+                r[x] = best
+        B = top
+    return r
+
+
+def test_fw4_converges_to_the_brute_force_optimum():
+    """||r - r*||^2 <= f(r) - f(r*) <= gap(r) for f = sum r^2 (strong convexity
+    and the Frank-Wolfe duality gap), with r* from the decomposition above and
+    the gap computed from its definition 2 (sum r^2 - sum_q min_{x in q} r_x)."""
+    for n, s, d in clique_graphs():
+        G = oracle.Graph(n, s, d)
+        q, _ = oracle.cliques4(G)
+        rstar = np.array([float(x) for x in clique_levels(G.n, q.tolist())])
+        out = oracle.fw_exact(G, 4, 1500, with_gap=False, with_split=False)
+        r = out["A"].astype(np.float64) / out["D"]
+        gap = 2.0 * (np.sum(r * r) - (r[q].min(axis=1).sum() if len(q) else 0.0))
+        assert gap >= -1e-12
+        assert np.sum((r - rstar) ** 2) <= gap + 1e-12
+        assert np.abs(r - rstar).max() < 0.1
+        # the densest 4-clique density is the largest level
+        assert abs(r.max() - rstar.max()) < 0.1
