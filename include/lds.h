@@ -13,11 +13,17 @@
  * caller's ids (see lds_frank_wolfe).
  *
  * Modes: LDS_EDGE   = edge density |E|/|V| (Section 3, Eq. cp),
- *        LDS_TRIANGLE = triangle density |T|/|V| (Section 6, Eq. trcp).
+ *        LDS_TRIANGLE = triangle density |T|/|V| (Section 6, Eq. trcp),
+ *        LDS_CLIQUE4 = 4-clique density |K4|/|V|, the h-clique program that
+ *                      Eq. trcp generalises, with h = 4 (Frank-Wolfe only:
+ *                      lds_frank_wolfe, lds_loads, lds_splits, lds_sweep_info,
+ *                      lds_fw_elapsed, lds_cliques4; the other calls take
+ *                      LDS_EDGE and LDS_TRIANGLE).
  *
  * Exact arithmetic.  Frank-Wolfe with step gamma_i = 2/(i+2) keeps every load
  * r_u^(i) and every split alpha^(i) on the common denominator
- * D_i = (i+1)(i+2) (edges) or 3(i+1)(i+2) (triangles); the library stores the
+ * D_i = (i+1)(i+2) (edges), 3(i+1)(i+2) (triangles) or 2(i+1)(i+2)
+ * (4-cliques); the library stores the
  * integer numerators, so every decision (argmin of r over a pattern) is
  * exact and results do not depend on launch configuration or batching.
  * Float views are produced on output only.
@@ -34,7 +40,7 @@ extern "C" {
 
 typedef struct lds_graph_s* lds_graph;
 
-typedef enum { LDS_EDGE = 2, LDS_TRIANGLE = 3 } lds_mode;
+typedef enum { LDS_EDGE = 2, LDS_TRIANGLE = 3, LDS_CLIQUE4 = 4 } lds_mode;
 
 typedef enum {
     LDS_OK = 0,
@@ -83,8 +89,19 @@ lds_status lds_graph_info(lds_graph g, int64_t* n, int64_t* m, int64_t* n_triang
 lds_status lds_triangles(lds_graph g, int64_t* n_triangles, int32_t* tri_out, int64_t cap, int64_t* tcount_out,
                          void* hip_stream);
 
-/* Frank-Wolfe on CP(G) (Alg. 1, edges) or on the triangle program (Alg. 6),
- * `iters` >= 0 iterations from the initial split alpha = 1/2 (resp. 1/3).
+/* 4-clique listing: the pattern set of the h-clique program (h = 4) that
+ * Eq. (trcp) generalises.  Lists the 4-cliques on the device (once, after the
+ * triangles; cached in the graph) and returns their number.  If q_out (host,
+ * 4 int32 per clique) is non-NULL and cap >= the count, writes every clique
+ * as ascending caller ids (a<b<c<d), in lexicographic order.  If qcount_out
+ * (host, n int64) is non-NULL, writes the number of 4-cliques at each vertex.
+ * LDS_E_OVERFLOW when the count reaches 2^31. */
+lds_status lds_cliques4(lds_graph g, int64_t* n_cliques, int32_t* q_out, int64_t cap, int64_t* qcount_out,
+                        void* hip_stream);
+
+/* Frank-Wolfe on CP(G) (Alg. 1, edges), on the triangle program (Alg. 6) or
+ * on the 4-clique program (the same iteration over 4-cliques), `iters` >= 0
+ * iterations from the initial split alpha = 1/2 (resp. 1/3, 1/4).
  * Iteration i gives every pattern's unit weight to its vertex of smallest
  * r^(i-1) (synchronous: all decisions read r^(i-1)); exact ties go to the
  * larger caller id.  Then alpha <- (1-gamma) alpha + gamma alpha_hat with
@@ -100,14 +117,14 @@ lds_status lds_triangles(lds_graph g, int64_t* n_triangles, int32_t* tri_out, in
  *            from exact integer sums
  * The state (loads, splits) stays on the device for lds_splits /
  * lds_extract.  Returns LDS_E_OVERFLOW if a numerator could exceed the
- * 64-bit packed key (max degree (resp. triangle count) times the largest
- * per-vertex increment). */
+ * 64-bit packed key (max degree (resp. triangle or 4-clique count) times the
+ * largest per-vertex increment). */
 lds_status lds_frank_wolfe(lds_graph g, lds_mode mode, int32_t iters, float* r_out, double* r64_out,
                            uint64_t* num_out, double* gap_out, void* hip_stream);
 
 /* Exact split numerators alpha_{x,p} * D of the last lds_frank_wolfe run
  * (Eq. cp / Eq. trcp variables).  One entry per incidence (vertex x,
- * pattern p): edges 2m entries, triangles 3|T| entries.  verts_out (host
+ * pattern p): edges 2m entries, triangles 3|T|, 4-cliques 4|K4|.  verts_out (host
  * int32, h entries per incidence: x first, then the other vertices of p, as
  * caller ids) and num_out (host uint64 per incidence).  Entries appear in an
  * unspecified order.  cap = capacity in incidences. */

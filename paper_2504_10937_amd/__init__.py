@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "liblds.so")
 
 LDS_EDGE = 2
 LDS_TRIANGLE = 3
+LDS_CLIQUE4 = 4
 LDS_INPUT_DEVICE = 1
 LDS_STRICT = 2
 STATUS = {0: "LDS_OK", 1: "LDS_E_INVALID", 2: "LDS_E_NOMEM", 3: "LDS_E_DEVICE", 4: "LDS_E_OVERFLOW",
@@ -49,6 +50,7 @@ def load():
         "lds_destroy_graph": (st, [vp]),
         "lds_graph_info": (st, [vp, vp, vp, vp, vp]),
         "lds_triangles": (st, [vp, vp, vp, i64, vp, vp]),
+        "lds_cliques4": (st, [vp, vp, vp, i64, vp, vp]),
         "lds_frank_wolfe": (st, [vp, st, i32, vp, vp, vp, vp, vp]),
         "lds_splits": (st, [vp, st, vp, vp, i64, vp, vp]),
         "lds_denominator": (u64, [st, i32]),
@@ -177,6 +179,20 @@ def lds_triangles(g, want_list=False, want_counts=False, stream=None):
         cnt = np.empty(n, np.int64) if want_counts else None
         _check(L.lds_triangles(g.handle, ctypes.byref(T), _ptr(tri), T.value, _ptr(cnt), _stream(stream)))
     return T.value, tri, cnt
+
+
+def lds_cliques4(g, want_list=False, want_counts=False, stream=None):
+    """List 4-cliques on the device -> (Q, (Q,4) int32 or None, (n,) int64 or None)."""
+    L = load()
+    Q = ctypes.c_int64()
+    _check(L.lds_cliques4(g.handle, ctypes.byref(Q), None, 0, None, _stream(stream)))
+    q = cnt = None
+    if want_list or want_counts:
+        n = lds_graph_info(g)["n"]
+        q = np.empty((Q.value, 4), np.int32) if want_list else None
+        cnt = np.empty(n, np.int64) if want_counts else None
+        _check(L.lds_cliques4(g.handle, ctypes.byref(Q), _ptr(q), Q.value, _ptr(cnt), _stream(stream)))
+    return Q.value, q, cnt
 
 
 def lds_frank_wolfe(g, mode, iters, r_out=None, want_r64=False, want_num=False, want_gap=False, stream=None):

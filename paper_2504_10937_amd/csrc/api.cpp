@@ -168,11 +168,55 @@ lds_status lds_triangles(lds_graph g, int64_t* n_triangles, int32_t* tri_out, in
     API_CATCH
 }
 
+lds_status lds_cliques4(lds_graph g, int64_t* n_cliques, int32_t* q_out, int64_t cap, int64_t* qcount_out,
+                        void* hip_stream) {
+    API_TRY
+    LDS_CHECK(g != nullptr, lds::ST_INVALID, "graph is NULL");
+    std::lock_guard<std::mutex> lk(g->mu);
+    hipStream_t s = (hipStream_t)hip_stream;
+    lds::Graph& G = g->g;
+    if (G.Q4 < 0) lds::list_cliques4(G, s);
+    if (n_cliques) *n_cliques = G.Q4;
+    const int64_t n = G.n, Q = G.Q4;
+    std::vector<int32_t> orig(n);
+    if ((q_out || qcount_out) && n > 0) {
+        LDS_HIP(hipMemcpyAsync(orig.data(), G.orig_of.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        LDS_HIP(hipStreamSynchronize(s));
+    }
+    if (q_out) {
+        LDS_CHECK(cap >= Q, lds::ST_INVALID, "q_out capacity is smaller than the 4-clique count");
+        std::vector<int32_t> q(4 * Q);
+        if (Q > 0) {
+            LDS_HIP(hipMemcpyAsync(q.data(), G.q4.p, 4 * Q * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            LDS_HIP(hipStreamSynchronize(s));
+        }
+        std::vector<std::array<int32_t, 4>> v((size_t)Q);
+        for (int64_t i = 0; i < Q; ++i) {
+            std::array<int32_t, 4> x{orig[q[4 * i]], orig[q[4 * i + 1]], orig[q[4 * i + 2]], orig[q[4 * i + 3]]};
+            std::sort(x.begin(), x.end());
+            v[i] = x;
+        }
+        std::sort(v.begin(), v.end());
+        for (int64_t i = 0; i < Q; ++i)
+            for (int j = 0; j < 4; ++j) q_out[4 * i + j] = v[i][j];
+    }
+    if (qcount_out) {
+        std::vector<int32_t> qc(n);
+        if (n > 0) {
+            LDS_HIP(hipMemcpyAsync(qc.data(), G.qcount.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            LDS_HIP(hipStreamSynchronize(s));
+        }
+        for (int64_t i = 0; i < n; ++i) qcount_out[orig[i]] = qc[i];
+    }
+    API_CATCH
+}
+
 lds_status lds_frank_wolfe(lds_graph g, lds_mode mode, int32_t iters, float* r_out, double* r64_out,
                            uint64_t* num_out, double* gap_out, void* hip_stream) {
     API_TRY
     LDS_CHECK(g != nullptr, lds::ST_INVALID, "graph is NULL");
-    LDS_CHECK(mode == LDS_EDGE || mode == LDS_TRIANGLE, lds::ST_INVALID, "mode must be LDS_EDGE or LDS_TRIANGLE");
+    LDS_CHECK(mode == LDS_EDGE || mode == LDS_TRIANGLE || mode == LDS_CLIQUE4, lds::ST_INVALID,
+              "mode must be LDS_EDGE, LDS_TRIANGLE or LDS_CLIQUE4");
     LDS_CHECK(iters >= 0, lds::ST_INVALID, "iters must be >= 0");
     std::lock_guard<std::mutex> lk(g->mu);
     hipStream_t s = (hipStream_t)hip_stream;
@@ -180,7 +224,7 @@ lds_status lds_frank_wolfe(lds_graph g, lds_mode mode, int32_t iters, float* r_o
     lds::fw_run(G, (int)mode, iters, gap_out != nullptr, s);
     if (r_out || r64_out || num_out) lds::fw_loads(G, (int)mode, r_out, r64_out, num_out, s);
     if (gap_out) {
-        const auto& f = G.fw[mode == LDS_EDGE ? 0 : 1];
+        const auto& f = G.fw[lds::mode_slot((int)mode)];
         std::copy(f.gap.begin(), f.gap.end(), gap_out);
     }
     API_CATCH
@@ -190,11 +234,13 @@ lds_status lds_splits(lds_graph g, lds_mode mode, int32_t* verts_out, uint64_t* 
                       int64_t* count_out, void* hip_stream) {
     API_TRY
     LDS_CHECK(g != nullptr, lds::ST_INVALID, "graph is NULL");
-    LDS_CHECK(mode == LDS_EDGE || mode == LDS_TRIANGLE, lds::ST_INVALID, "mode must be LDS_EDGE or LDS_TRIANGLE");
+    LDS_CHECK(mode == LDS_EDGE || mode == LDS_TRIANGLE || mode == LDS_CLIQUE4, lds::ST_INVALID,
+              "mode must be LDS_EDGE, LDS_TRIANGLE or LDS_CLIQUE4");
     std::lock_guard<std::mutex> lk(g->mu);
     lds::Graph& G = g->g;
-    const lds::SweepPlan& p = (mode == LDS_EDGE) ? G.edge_plan : G.tri_plan;
-    LDS_CHECK(mode == LDS_EDGE || G.T >= 0, lds::ST_INVALID, "no triangle state: run lds_frank_wolfe first");
+    const lds::SweepPlan& p = lds::plan_of(G, (int)mode);
+    LDS_CHECK(mode == LDS_EDGE || (mode == LDS_TRIANGLE ? G.T >= 0 : G.Q4 >= 0), lds::ST_INVALID,
+              "no pattern state for this mode: run lds_frank_wolfe first");
     if (count_out) *count_out = p.nslots;
     if (verts_out || num_out) {
         LDS_CHECK(verts_out && num_out, lds::ST_INVALID, "verts_out and num_out must both be given");
@@ -265,9 +311,10 @@ lds_status lds_stable_groups(lds_graph g, lds_mode mode, int64_t* ngroups, int64
 lds_status lds_fw_elapsed(lds_graph g, lds_mode mode, float* ms, int32_t* launches) {
     API_TRY
     LDS_CHECK(g != nullptr, lds::ST_INVALID, "graph is NULL");
-    LDS_CHECK(mode == LDS_EDGE || mode == LDS_TRIANGLE, lds::ST_INVALID, "mode must be LDS_EDGE or LDS_TRIANGLE");
+    LDS_CHECK(mode == LDS_EDGE || mode == LDS_TRIANGLE || mode == LDS_CLIQUE4, lds::ST_INVALID,
+              "mode must be LDS_EDGE, LDS_TRIANGLE or LDS_CLIQUE4");
     std::lock_guard<std::mutex> lk(g->mu);
-    const auto& f = g->g.fw[mode == LDS_EDGE ? 0 : 1];
+    const auto& f = g->g.fw[lds::mode_slot((int)mode)];
     LDS_CHECK(f.timed && f.ev[0] != nullptr, lds::ST_INVALID, "no timed lds_frank_wolfe run for this mode");
     if (ms) {
         LDS_HIP(hipEventSynchronize(f.ev[1]));
@@ -281,11 +328,13 @@ lds_status lds_sweep_info(lds_graph g, lds_mode mode, int64_t* rows, int64_t* sl
                           int64_t* chunks, int64_t* words, void* hip_stream) {
     API_TRY
     LDS_CHECK(g != nullptr, lds::ST_INVALID, "graph is NULL");
-    LDS_CHECK(mode == LDS_EDGE || mode == LDS_TRIANGLE, lds::ST_INVALID, "mode must be LDS_EDGE or LDS_TRIANGLE");
+    LDS_CHECK(mode == LDS_EDGE || mode == LDS_TRIANGLE || mode == LDS_CLIQUE4, lds::ST_INVALID,
+              "mode must be LDS_EDGE, LDS_TRIANGLE or LDS_CLIQUE4");
     std::lock_guard<std::mutex> lk(g->mu);
     lds::Graph& G = g->g;
     if (mode == LDS_TRIANGLE && G.T < 0) lds::list_triangles(G, (hipStream_t)hip_stream);
-    const lds::SweepPlan& p = (mode == LDS_EDGE) ? G.edge_plan : G.tri_plan;
+    if (mode == LDS_CLIQUE4 && G.Q4 < 0) lds::list_cliques4(G, (hipStream_t)hip_stream);
+    const lds::SweepPlan& p = lds::plan_of(G, (int)mode);
     if (rows) *rows = p.nrows;
     if (slots) *slots = p.nslots;
     if (hub_rows) *hub_rows = p.n_hub;
@@ -295,8 +344,8 @@ lds_status lds_sweep_info(lds_graph g, lds_mode mode, int64_t* rows, int64_t* sl
 }
 
 uint64_t lds_denominator(lds_mode mode, int32_t iters) {
-    if (iters < 0) return 0;
-    return (uint64_t)(mode == LDS_TRIANGLE ? 3 : 1) * (uint64_t)(iters + 1) * (uint64_t)(iters + 2);
+    if (iters < 0 || mode < LDS_EDGE || mode > LDS_CLIQUE4) return 0;
+    return lds::fw_denom((int)mode, iters);
 }
 
 namespace {
@@ -371,10 +420,11 @@ lds_status lds_loads(lds_graph g, lds_mode mode, float* r_out, double* r64_out, 
                      int32_t* iters_out, void* hip_stream) {
     API_TRY
     LDS_CHECK(g != nullptr, lds::ST_INVALID, "graph is NULL");
-    LDS_CHECK(mode == LDS_EDGE || mode == LDS_TRIANGLE, lds::ST_INVALID, "mode must be LDS_EDGE or LDS_TRIANGLE");
+    LDS_CHECK(mode == LDS_EDGE || mode == LDS_TRIANGLE || mode == LDS_CLIQUE4, lds::ST_INVALID,
+              "mode must be LDS_EDGE, LDS_TRIANGLE or LDS_CLIQUE4");
     std::lock_guard<std::mutex> lk(g->mu);
     lds::Graph& G = g->g;
-    const auto& f = G.fw[mode == LDS_EDGE ? 0 : 1];
+    const auto& f = G.fw[lds::mode_slot((int)mode)];
     LDS_CHECK(f.ran, lds::ST_INVALID, "no Frank-Wolfe run for this mode");
     LDS_CHECK(gap_out == nullptr || (int)f.gap.size() == f.iters, lds::ST_INVALID,
               "the last run did not compute the gap");

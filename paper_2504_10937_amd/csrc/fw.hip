@@ -1,11 +1,12 @@
 // Frank-Wolfe iterations of Alg. 1 (edges, Eq. cp) and Alg. 6 (triangles,
-// Eq. trcp) on gfx950, in exact integer form.
+// Eq. trcp) on gfx950, in exact integer form, and the same iteration over
+// 4-cliques (the h-clique program that Eq. trcp generalises, h = 4).
 //
 // State.  With gamma_i = 2/(i+2) every load is r_u^(i) = A_u / D_i with the
-// common denominator D_i = (i+1)(i+2) (edges) or 3(i+1)(i+2) (triangles), and
-// the update r <- (1-gamma) r + gamma b becomes A_u += inc_i * b_u with
-// inc_i = D_i - D_{i-1} = 2(i+1) (edges) or 6(i+1) (triangles), b_u = units
-// won in iteration i.  Each vertex carries one packed 64-bit key
+// common denominator D_i = (i+1)(i+2) (edges), 3(i+1)(i+2) (triangles) or
+// 2(i+1)(i+2) (4-cliques), and the update r <- (1-gamma) r + gamma b becomes
+// A_u += inc_i * b_u with inc_i = D_i - D_{i-1} = 2(i+1), 6(i+1) or 4(i+1),
+// b_u = units won in iteration i.  Each vertex carries one packed 64-bit key
 //     K_u = (A_u << B) | (2^B - 1 - orig_id(u)),
 // so "smallest load, ties to the larger original id" is a single unsigned
 // compare, and adding (inc * b) << B updates A without touching the id bits.
@@ -116,6 +117,14 @@ __device__ inline Slot<3> load_slot<3>(const int32_t* __restrict__ py, int64_t s
     Slot<3> r;
     r.v[0] = (int32_t)(uint32_t)(unsigned long long)x;
     r.v[1] = (int32_t)(uint32_t)((unsigned long long)x >> 32);
+    return r;
+}
+template <>
+__device__ inline Slot<4> load_slot<4>(const int32_t* __restrict__ py, int64_t s) {
+    Slot<4> r;
+    r.v[0] = __builtin_nontemporal_load(py + 3 * s);
+    r.v[1] = __builtin_nontemporal_load(py + 3 * s + 1);
+    r.v[2] = __builtin_nontemporal_load(py + 3 * s + 2);
     return r;
 }
 
@@ -367,8 +376,9 @@ __global__ __launch_bounds__(256) void k_gap_reduce(const uint64_t* partial, int
     }
 }
 
-// initial keys: A0 = deg (edges, r0 = deg/2 with D0 = 2) or 2 t_u (triangles,
-// r0 = t_u/3 with D0 = 6), packed with the original-id code
+// initial keys: A0 = deg (edges, r0 = deg/2 with D0 = 2), 2 t_u (triangles,
+// r0 = t_u/3 with D0 = 6) or q_u (4-cliques, r0 = q_u/4 with D0 = 4), packed
+// with the original-id code
 __global__ void k_init_keys(const int32_t* count, int mult, const int32_t* orig_of, int64_t n, int B,
                             uint64_t* K0, uint64_t* K1, uint16_t* Q0, uint16_t* Q1) {
     const int64_t u = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -392,11 +402,11 @@ __global__ void k_loads(const uint64_t* K, const int32_t* orig_of, int64_t n, in
 }
 
 // exact split numerator of every incidence slot from the stored decision
-// words: a = a0 + sum_i inc_i [slot won in iteration i]
+// words: a = a0 + sum_i inc_i [slot won in iteration i], inc_i = incm (i+1)
 template <int H>
 __global__ void k_splits(const int64_t* rp, const int32_t* rid, const int32_t* py, const int64_t* bitbase,
                          int64_t nrows, int64_t nslots, const uint64_t* bits, int64_t total_words, int iters,
-                         int tri, const int32_t* orig_of, int32_t* verts, uint64_t* num) {
+                         uint64_t a0, uint64_t incm, const int32_t* orig_of, int32_t* verts, uint64_t* num) {
     const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (s >= nslots) return;
     // row of slot s: last r with rp[r] <= s
@@ -407,10 +417,10 @@ __global__ void k_splits(const int64_t* rp, const int32_t* rid, const int32_t* p
     }
     const int64_t r = lo;
     const int64_t pos = bitbase[r] + (s - rp[r]);
-    uint64_t a = tri ? 2 : 1;
+    uint64_t a = a0;
     for (int i = 1; i <= iters; ++i) {
         const uint64_t wd = bits[(int64_t)(i - 1) * total_words + pos / 64];
-        if ((wd >> (pos % 64)) & 1ull) a += (uint64_t)(tri ? 6 : 2) * (uint64_t)(i + 1);
+        if ((wd >> (pos % 64)) & 1ull) a += incm * (uint64_t)(i + 1);
     }
     const int32_t x = rid ? rid[r] : (int32_t)r;
     verts[H * s] = orig_of[x];
@@ -458,18 +468,20 @@ unsigned sweep_grid() {
 
 unsigned __int128 fw_max_numerator(const Graph& g, int mode, int iters) {
     // a vertex that wins every incident pattern in every iteration:
-    // deg (1 + sum_i 2(i+1)) or t (2 + sum_i 6(i+1))
+    // deg (1 + sum_i 2(i+1)), t (2 + sum_i 6(i+1)) or q (1 + sum_i 4(i+1))
     const unsigned __int128 N = (unsigned)iters;
     if (mode == 2) return (unsigned __int128)(uint64_t)g.max_deg * (N * N + 3 * N + 1);
-    return (unsigned __int128)(uint64_t)g.t_max * (2 + 3 * N * (N + 3));
+    if (mode == 3) return (unsigned __int128)(uint64_t)g.t_max * (2 + 3 * N * (N + 3));
+    return (unsigned __int128)(uint64_t)g.q_max * (1 + 2 * N * (N + 3));
 }
 
 void fw_prepare(Graph& g, int mode, int iters, hipStream_t s) {
-    LDS_CHECK(mode == 2 || mode == 3, ST_INVALID, "mode must be LDS_EDGE or LDS_TRIANGLE");
+    LDS_CHECK(mode >= 2 && mode <= 4, ST_INVALID, "mode must be LDS_EDGE, LDS_TRIANGLE or LDS_CLIQUE4");
     LDS_CHECK(iters >= 0, ST_INVALID, "iters must be >= 0");
     if (mode == 3 && g.T < 0) list_triangles(g, s);
-    const SweepPlan& p = (mode == 2) ? g.edge_plan : g.tri_plan;
-    FwState& f = g.fw[mode == 2 ? 0 : 1];
+    if (mode == 4 && g.Q4 < 0) list_cliques4(g, s);
+    const SweepPlan& p = plan_of(g, mode);
+    FwState& f = g.fw[mode_slot(mode)];
     const int B = g.idbits;
     // overflow: the largest numerator must leave B bits for the id code
     const u128 amax = fw_max_numerator(g, mode, iters);
@@ -503,18 +515,18 @@ void fw_gap_from_sums(FwState& f, int mode, int iters, const uint64_t* sums) {
 
 void fw_run(Graph& g, int mode, int iters, bool want_gap, hipStream_t s) {
     fw_prepare(g, mode, iters, s);
-    SweepPlan& p = (mode == 2) ? g.edge_plan : g.tri_plan;
-    FwState& f = g.fw[mode == 2 ? 0 : 1];
+    SweepPlan& p = plan_of(g, mode);
+    FwState& f = g.fw[mode_slot(mode)];
     const int B = g.idbits;
     const int64_t n = g.n;
     if (n > 0) {
-        const int32_t* cnt = (mode == 2) ? g.deg.p : g.tcount.p;
-        k_init_keys<<<grid_for(n, 256), 256, 0, s>>>(cnt, mode == 2 ? 1 : 2, g.orig_of.p, n, B, f.K[0].p, f.K[1].p,
+        const int32_t* cnt = (mode == 2) ? g.deg.p : (mode == 3 ? g.tcount.p : g.qcount.p);
+        k_init_keys<<<grid_for(n, 256), 256, 0, s>>>(cnt, mode == 3 ? 2 : 1, g.orig_of.p, n, B, f.K[0].p, f.K[1].p,
                                                     f.Q[0].p, f.Q[1].p);
         LDS_HIP(hipGetLastError());
     }
     f.cur = 0;
-    g.sg[mode == 2 ? 0 : 1].valid = false;
+    g.sg[mode_slot(mode)].valid = false;
     const unsigned blocks = sweep_grid();
     const size_t npart = want_gap ? (size_t)iters * blocks * 4 : 0;
     if (f.partial.n < npart) f.partial.alloc(npart, s);
@@ -547,8 +559,10 @@ void fw_run(Graph& g, int mode, int iters, bool want_gap, hipStream_t s) {
         a.partial = want_gap ? f.partial.p + (size_t)(i - 1) * blocks * 4 : nullptr;
         if (mode == 2)
             launch_sweep<2, true>(a, blocks, want_gap, s);
-        else
+        else if (mode == 3)
             launch_sweep<3, false>(a, blocks, want_gap, s);
+        else
+            launch_sweep<4, false>(a, blocks, want_gap, s);
         LDS_HIP(hipGetLastError());
         f.cur ^= 1;
         ++f.launches;
@@ -574,7 +588,7 @@ void fw_run(Graph& g, int mode, int iters, bool want_gap, hipStream_t s) {
 }
 
 void fw_loads(const Graph& g, int mode, float* r32_dev, double* r64_host, uint64_t* A_host, hipStream_t s) {
-    const FwState& f = g.fw[mode == 2 ? 0 : 1];
+    const FwState& f = g.fw[mode_slot(mode)];
     const int64_t n = g.n;
     if (n == 0) return;
     LDS_CHECK(f.ran && f.K[0].n == (size_t)n, ST_INVALID, "no Frank-Wolfe state: call lds_frank_wolfe first");
@@ -595,8 +609,8 @@ void fw_loads(const Graph& g, int mode, float* r32_dev, double* r64_host, uint64
 }
 
 void fw_splits(const Graph& g, int mode, int32_t* verts_host, uint64_t* num_host, hipStream_t s) {
-    const FwState& f = g.fw[mode == 2 ? 0 : 1];
-    const SweepPlan& p = (mode == 2) ? g.edge_plan : g.tri_plan;
+    const FwState& f = g.fw[mode_slot(mode)];
+    const SweepPlan& p = plan_of(g, mode);
     const int64_t ns = p.nslots;
     if (ns == 0) return;
     LDS_CHECK(f.ran && f.K[0].n == (size_t)g.n, ST_INVALID, "no Frank-Wolfe state: call lds_frank_wolfe first");
@@ -605,12 +619,17 @@ void fw_splits(const Graph& g, int mode, int32_t* verts_host, uint64_t* num_host
     DBuf<uint64_t> a;
     v.alloc((size_t)ns * H, s);
     a.alloc(ns, s);
+    // a0 = D_0 / h; inc_i = D_i - D_{i-1} = incm (i+1) with incm = inc_1 / 2
+    const uint64_t a0 = denom(mode, 0) / (uint64_t)H, incm = (denom(mode, 1) - denom(mode, 0)) / 2;
     if (mode == 2)
         k_splits<2><<<grid_for(ns, 256), 256, 0, s>>>(p.rp, p.rid, p.py, p.bitbase.p, p.nrows, ns, f.bits.p,
-                                                      p.total_words, f.iters, 0, g.orig_of.p, v.p, a.p);
-    else
+                                                      p.total_words, f.iters, a0, incm, g.orig_of.p, v.p, a.p);
+    else if (mode == 3)
         k_splits<3><<<grid_for(ns, 256), 256, 0, s>>>(p.rp, p.rid, p.py, p.bitbase.p, p.nrows, ns, f.bits.p,
-                                                      p.total_words, f.iters, 1, g.orig_of.p, v.p, a.p);
+                                                      p.total_words, f.iters, a0, incm, g.orig_of.p, v.p, a.p);
+    else
+        k_splits<4><<<grid_for(ns, 256), 256, 0, s>>>(p.rp, p.rid, p.py, p.bitbase.p, p.nrows, ns, f.bits.p,
+                                                      p.total_words, f.iters, a0, incm, g.orig_of.p, v.p, a.p);
     LDS_HIP(hipGetLastError());
     LDS_HIP(hipMemcpyAsync(verts_host, v.p, v.bytes(), hipMemcpyDeviceToHost, s));
     LDS_HIP(hipMemcpyAsync(num_host, a.p, a.bytes(), hipMemcpyDeviceToHost, s));

@@ -30,10 +30,15 @@ namespace lds {
 constexpr int kChunk = 1024;  // target slots per wave; spans < 2*kChunk = 32 words
 
 // denominator of the loads after i iterations with gamma_i = 2/(i+2):
-// (i+1)(i+2) for edges (mode 2), 3(i+1)(i+2) for triangles (mode 3)
+// (i+1)(i+2) for edges (mode 2), 3(i+1)(i+2) for triangles (mode 3),
+// 2(i+1)(i+2) for 4-cliques (mode 4); D_0 / h is an integer in each case
 inline uint64_t fw_denom(int mode, int64_t i) {
-    return (uint64_t)(mode == 3 ? 3 : 1) * (uint64_t)(i + 1) * (uint64_t)(i + 2);
+    const uint64_t c = mode == 3 ? 3 : (mode == 4 ? 2 : 1);
+    return c * (uint64_t)(i + 1) * (uint64_t)(i + 2);
 }
+
+// index of a mode's Frank-Wolfe / stable-group state: edges 0, triangles 1, 4-cliques 2
+inline int mode_slot(int mode) { return mode - 2; }
 
 struct SweepPlan {
     int h = 2;                  // pattern arity: 2 edges, 3 triangles
@@ -119,8 +124,14 @@ struct Graph {
     DBuf<int32_t> tcount;        // per internal vertex
     int64_t t_max = 0;
     SweepPlan tri_plan;
-    FwState fw[2];               // [0] edges, [1] triangles
-    SgState sg[2];               // sort / prefix / stable groups of the last run per mode
+    // 4-cliques (built on first use)
+    int64_t Q4 = -1;
+    DBuf<int32_t> q4;            // 4 Q4 internal ids, per clique (a > b > c > d internal)
+    DBuf<int32_t> qcount;        // per internal vertex
+    int64_t q_max = 0;
+    SweepPlan clique_plan;
+    FwState fw[3];               // indexed by mode_slot: edges, triangles, 4-cliques
+    SgState sg[3];               // sort / prefix / stable groups of the last run per mode (edges, triangles)
     std::shared_ptr<HostCache> host;  // host copy of the adjacency, triangles and core numbers, built on first use
     hipStream_t stream = nullptr;
     size_t device_bytes() const;
@@ -135,6 +146,14 @@ void sort_rows(Graph& g, hipStream_t s);             // CSR rows ascending (tria
 
 // triangles.hip
 void list_triangles(Graph& g, hipStream_t s);
+void list_cliques4(Graph& g, hipStream_t s);  // lists triangles first if needed
+
+inline SweepPlan& plan_of(Graph& g, int mode) {
+    return mode == 2 ? g.edge_plan : (mode == 3 ? g.tri_plan : g.clique_plan);
+}
+inline const SweepPlan& plan_of(const Graph& g, int mode) {
+    return mode == 2 ? g.edge_plan : (mode == 3 ? g.tri_plan : g.clique_plan);
+}
 
 // sg.hip
 void sg_sort_prefix(Graph& g, int mode, hipStream_t s);

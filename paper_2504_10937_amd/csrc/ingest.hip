@@ -420,7 +420,8 @@ Graph::~Graph() {
 
 size_t Graph::device_bytes() const {
     size_t b = orig_of.bytes() + int_of.bytes() + deg.bytes() + rowptr.bytes() + col.bytes() +
-               edge_plan.device_bytes() + tri.bytes() + tcount.bytes() + tri_plan.device_bytes();
+               edge_plan.device_bytes() + tri.bytes() + tcount.bytes() + tri_plan.device_bytes() + q4.bytes() +
+               qcount.bytes() + clique_plan.device_bytes();
     for (const auto& f : fw) b += f.device_bytes();
     for (const auto& x : sg) b += x.device_bytes();
     return b;

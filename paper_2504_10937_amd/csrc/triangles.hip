@@ -1,5 +1,6 @@
 // Triangle listing for the triangle-density program (Eq. trcp, Alg. 6 use
-// the triangle set T; the paper does not say how T is obtained).
+// the triangle set T; the paper does not say how T is obtained), and
+// 4-clique listing for the h-clique program that Eq. trcp generalises.
 //
 // Orientation: internal ids are sorted by degree (descending), so orienting
 // every edge towards the smaller internal id points it at the endpoint of
@@ -118,28 +119,82 @@ __global__ void k_row_apply(const uint64_t* keys, int64_t nrows, int vb, const i
     rcount[r] = (uint32_t)tc[u];
 }
 
-__global__ void k_inc_keys(const int32_t* tri, int64_t T, const int32_t* row_of, int tb, uint64_t* keys) {
+template <int H>
+__global__ void k_inc_keys(const int32_t* pat, int64_t np, const int32_t* row_of, int tb, uint64_t* keys) {
     const int64_t t = (int64_t)blockIdx.x * kT + threadIdx.x;
-    if (t >= T) return;
-    for (int j = 0; j < 3; ++j) keys[3 * t + j] = ((uint64_t)row_of[tri[3 * t + j]] << tb) | (uint64_t)t;
+    if (t >= np) return;
+    for (int j = 0; j < H; ++j) keys[H * t + j] = ((uint64_t)row_of[pat[H * t + j]] << tb) | (uint64_t)t;
 }
 
-__global__ void k_inc_pay(const uint64_t* keys, int64_t ns, int tb, const int32_t* tri, const int32_t* rid,
+// slot s: the other H-1 members of its pattern, in pattern order
+template <int H>
+__global__ void k_inc_pay(const uint64_t* keys, int64_t ns, int tb, const int32_t* pat, const int32_t* rid,
                           int32_t* pay, int32_t* tos) {
     const int64_t s = (int64_t)blockIdx.x * kT + threadIdx.x;
     if (s >= ns) return;
     const uint64_t k = keys[s];
     const int64_t t = (int64_t)(k & ((1ull << tb) - 1));
     const int32_t x = rid[k >> tb];
-    const int32_t a = tri[3 * t], b = tri[3 * t + 1], c = tri[3 * t + 2];
-    int32_t p, q;
-    if (x == a) { p = b; q = c; } else if (x == b) { p = a; q = c; } else { p = a; q = b; }
-    pay[2 * s] = p;
-    pay[2 * s + 1] = q;
+    int o = 0;
+    for (int j = 0; j < H; ++j) {
+        const int32_t y = pat[H * t + j];
+        if (y != x) pay[(H - 1) * s + o++] = y;
+    }
     tos[s] = (int32_t)t;
 }
 
 __global__ void k_set_last(int64_t* rowptr, int64_t idx, const uint64_t* total) { rowptr[idx] = (int64_t)*total; }
+
+// 4-cliques: a clique with internal ids a > b > c > d is found exactly once,
+// from its triangle (a, b, c), as the element d of N+(a) ∩ N+(b) ∩ N+(c)
+// (all of N+(c) lies below c).  One thread per triangle walks the shortest
+// of the three out-lists cut at c and probes the other two by binary search
+// with advancing lower bounds; a count pass, a scan and a write pass give
+// the order (triangle order, d ascending).
+template <bool WRITE>
+__global__ void k_clique_tris(const int64_t* rp, const int32_t* col, const int32_t* tri, int64_t T, uint32_t* cnt,
+                              const uint64_t* off, int32_t* q4) {
+    const int64_t t = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (t >= T) return;
+    const int32_t x[3] = {tri[3 * t], tri[3 * t + 1], tri[3 * t + 2]};  // a > b > c
+    const int32_t c = x[2];
+    int64_t lo[3], hi[3];
+    for (int j = 0; j < 3; ++j) {
+        lo[j] = rp[x[j]];
+        hi[j] = lower_bound_i32(col, rp[x[j]], rp[x[j] + 1], c);  // neighbours below c
+    }
+    int sh = 0;
+    for (int j = 1; j < 3; ++j)
+        if (hi[j] - lo[j] < hi[sh] - lo[sh]) sh = j;
+    const int o1 = sh == 0 ? 1 : 0, o2 = sh == 2 ? 1 : 2;
+    int64_t q1 = lo[o1], q2 = lo[o2];
+    uint64_t o = WRITE ? off[t] : 0;
+    uint32_t k = 0;
+    for (int64_t i = lo[sh]; i < hi[sh]; ++i) {
+        const int32_t d = col[i];
+        q1 = lower_bound_i32(col, q1, hi[o1], d);
+        if (q1 >= hi[o1]) break;
+        if (col[q1] != d) continue;
+        q2 = lower_bound_i32(col, q2, hi[o2], d);
+        if (q2 >= hi[o2]) break;
+        if (col[q2] != d) continue;
+        if (WRITE) {
+            q4[4 * o + 0] = x[0];
+            q4[4 * o + 1] = x[1];
+            q4[4 * o + 2] = x[2];
+            q4[4 * o + 3] = d;
+            ++o;
+        }
+        ++k;
+    }
+    if (!WRITE) cnt[t] = k;
+}
+
+__global__ void k_qcount(const int32_t* q4, int64_t Q, int32_t* qc) {
+    const int64_t t = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (t >= Q) return;
+    for (int j = 0; j < 4; ++j) atomicAdd(&qc[q4[4 * t + j]], 1);
+}
 
 template <class T>
 T d2h(const T* p, hipStream_t s) {
@@ -147,6 +202,75 @@ T d2h(const T* p, hipStream_t s) {
     LDS_HIP(hipMemcpyAsync(&v, p, sizeof(T), hipMemcpyDeviceToHost, s));
     LDS_HIP(hipStreamSynchronize(s));
     return v;
+}
+
+// Incidence CSR of a pattern list (H vertices per pattern) for the pull
+// sweep: rows are the vertices with count > 0 ordered by count descending
+// (internal id ascending), each row holding, for every pattern at the
+// vertex, the other H-1 members (in pattern order), patterns in list order.
+template <int H>
+void build_incidence_plan(Graph& g, const int32_t* pat, int64_t np, const int32_t* count, SweepPlan& p,
+                          int64_t& cmax, hipStream_t s) {
+    const int64_t n = g.n;
+    LDS_CHECK(np < (int64_t)INT32_MAX, ST_OVERFLOW, "too many patterns for 32-bit pattern indices");
+    p.h = H;
+    DBuf<int> tmax;
+    DBuf<unsigned long long> nz;
+    tmax.alloc(1, s);
+    nz.alloc(1, s);
+    LDS_HIP(hipMemsetAsync(tmax.p, 0, sizeof(int), s));
+    LDS_HIP(hipMemsetAsync(nz.p, 0, sizeof(unsigned long long), s));
+    if (n > 0) {
+        k_tmax<<<grid_for(n, kT), kT, 0, s>>>(count, n, tmax.p, nz.p);
+        LDS_HIP(hipGetLastError());
+    }
+    cmax = d2h(tmax.p, s);
+    const int64_t nrows = (int64_t)d2h(nz.p, s);
+    p.nrows = nrows;
+    p.nslots = H * np;
+    p.own_rid.alloc(nrows, s);
+    p.own_rp.alloc(nrows + 1, s);
+    p.own_py.alloc((H - 1) * H * np, s);
+    DBuf<int32_t>& row_of = p.own_row_of;
+    row_of.alloc(n, s);
+    if (n) LDS_HIP(hipMemsetAsync(row_of.p, 0xff, n * sizeof(int32_t), s));  // -1: no pattern
+    DBuf<uint32_t> rcount;
+    rcount.alloc(nrows, s);
+    if (nrows > 0) {
+        const int vb = g.vbits;
+        DBuf<uint64_t> rk, rt;
+        rk.alloc(n, s);
+        rt.alloc(n, s);
+        k_row_keys<<<grid_for(n, kT), kT, 0, s>>>(count, n, vb, (int32_t)cmax, rk.p);
+        LDS_HIP(hipGetLastError());
+        radix_sort_u64(rk.p, nullptr, n, vb + bits_for((uint64_t)cmax), rt.p, nullptr, s);
+        k_row_apply<<<grid_for(nrows, kT), kT, 0, s>>>(rk.p, nrows, vb, count, p.own_rid.p, row_of.p, rcount.p);
+        LDS_HIP(hipGetLastError());
+    }
+    DBuf<uint64_t> tot;
+    tot.alloc(1, s);
+    exclusive_scan_u32_to_u64(rcount.p, (uint64_t*)p.own_rp.p, nrows, tot.p, s);
+    k_set_last<<<1, 1, 0, s>>>(p.own_rp.p, nrows, tot.p);
+    LDS_HIP(hipGetLastError());
+    if (np > 0) {
+        const int tb = bits_for((uint64_t)(np - 1)) > 0 ? bits_for((uint64_t)(np - 1)) : 1;
+        const int rb = bits_for((uint64_t)nrows);
+        LDS_CHECK(tb + rb <= 64, ST_OVERFLOW, "pattern incidence key exceeds 64 bits");
+        DBuf<uint64_t> ik, it;
+        ik.alloc(H * np, s);
+        it.alloc(H * np, s);
+        k_inc_keys<H><<<grid_for(np, kT), kT, 0, s>>>(pat, np, row_of.p, tb, ik.p);
+        LDS_HIP(hipGetLastError());
+        radix_sort_u64(ik.p, nullptr, H * np, tb + rb, it.p, nullptr, s);
+        p.own_tos.alloc(H * np, s);
+        k_inc_pay<H><<<grid_for(H * np, kT), kT, 0, s>>>(ik.p, H * np, tb, pat, p.own_rid.p, p.own_py.p,
+                                                       p.own_tos.p);
+        LDS_HIP(hipGetLastError());
+    }
+    p.rid = p.own_rid.p;
+    p.rp = p.own_rp.p;
+    p.py = p.own_py.p;
+    build_sweep_plan(p, s);
 }
 
 }  // namespace
@@ -183,67 +307,36 @@ void list_triangles(Graph& g, hipStream_t s) {
         }
     }
     g.T = T;
-    // incidence CSR
-    SweepPlan& p = g.tri_plan;
-    p.h = 3;
-    DBuf<int> tmax;
-    DBuf<unsigned long long> nz;
-    tmax.alloc(1, s);
-    nz.alloc(1, s);
-    LDS_HIP(hipMemsetAsync(tmax.p, 0, sizeof(int), s));
-    LDS_HIP(hipMemsetAsync(nz.p, 0, sizeof(unsigned long long), s));
-    if (n > 0) {
-        k_tmax<<<grid_for(n, kT), kT, 0, s>>>(g.tcount.p, n, tmax.p, nz.p);
-        LDS_HIP(hipGetLastError());
-    }
-    g.t_max = d2h(tmax.p, s);
-    const int64_t nrows = (int64_t)d2h(nz.p, s);
-    p.nrows = nrows;
-    p.nslots = 3 * T;
-    p.own_rid.alloc(nrows, s);
-    p.own_rp.alloc(nrows + 1, s);
-    p.own_py.alloc(2 * 3 * T, s);
-    DBuf<int32_t>& row_of = p.own_row_of;
-    row_of.alloc(n, s);
-    if (n) LDS_HIP(hipMemsetAsync(row_of.p, 0xff, n * sizeof(int32_t), s));  // -1: no triangle
-    DBuf<uint32_t> rcount;
-    rcount.alloc(nrows, s);
-    if (nrows > 0) {
-        const int vb = g.vbits;
-        DBuf<uint64_t> rk, rt;
-        rk.alloc(n, s);
-        rt.alloc(n, s);
-        k_row_keys<<<grid_for(n, kT), kT, 0, s>>>(g.tcount.p, n, vb, (int32_t)g.t_max, rk.p);
-        LDS_HIP(hipGetLastError());
-        radix_sort_u64(rk.p, nullptr, n, vb + bits_for((uint64_t)g.t_max), rt.p, nullptr, s);
-        k_row_apply<<<grid_for(nrows, kT), kT, 0, s>>>(rk.p, nrows, vb, g.tcount.p, p.own_rid.p, row_of.p,
-                                                      rcount.p);
-        LDS_HIP(hipGetLastError());
-    }
-    DBuf<uint64_t> tot;
-    tot.alloc(1, s);
-    exclusive_scan_u32_to_u64(rcount.p, (uint64_t*)p.own_rp.p, nrows, tot.p, s);
-    k_set_last<<<1, 1, 0, s>>>(p.own_rp.p, nrows, tot.p);
-    LDS_HIP(hipGetLastError());
+    build_incidence_plan<3>(g, g.tri.p, T, g.tcount.p, g.tri_plan, g.t_max, s);
+}
+
+void list_cliques4(Graph& g, hipStream_t s) {
+    if (g.T < 0) list_triangles(g, s);  // also sorts the rows
+    const int64_t n = g.n, T = g.T;
+    g.qcount.alloc(n, s);
+    if (n) LDS_HIP(hipMemsetAsync(g.qcount.p, 0, n * sizeof(int32_t), s));
+    int64_t Q = 0;
     if (T > 0) {
-        const int tb = bits_for((uint64_t)(T - 1)) > 0 ? bits_for((uint64_t)(T - 1)) : 1;
-        const int rb = bits_for((uint64_t)nrows);
-        LDS_CHECK(tb + rb <= 64, ST_OVERFLOW, "triangle incidence key exceeds 64 bits");
-        DBuf<uint64_t> ik, it;
-        ik.alloc(3 * T, s);
-        it.alloc(3 * T, s);
-        k_inc_keys<<<grid_for(T, kT), kT, 0, s>>>(g.tri.p, T, row_of.p, tb, ik.p);
+        DBuf<uint32_t> cnt;
+        DBuf<uint64_t> off, tot;
+        cnt.alloc(T, s);
+        off.alloc(T, s);
+        tot.alloc(1, s);
+        k_clique_tris<false><<<grid_for(T, kT), kT, 0, s>>>(g.rowptr.p, g.col.p, g.tri.p, T, cnt.p, nullptr, nullptr);
         LDS_HIP(hipGetLastError());
-        radix_sort_u64(ik.p, nullptr, 3 * T, tb + rb, it.p, nullptr, s);
-        p.own_tos.alloc(3 * T, s);
-        k_inc_pay<<<grid_for(3 * T, kT), kT, 0, s>>>(ik.p, 3 * T, tb, g.tri.p, p.own_rid.p, p.own_py.p,
-                                                    p.own_tos.p);
-        LDS_HIP(hipGetLastError());
+        exclusive_scan_u32_to_u64(cnt.p, off.p, T, tot.p, s);
+        Q = (int64_t)d2h(tot.p, s);
+        cnt.release();
+        g.q4.alloc(4 * Q, s);
+        if (Q > 0) {
+            k_clique_tris<true><<<grid_for(T, kT), kT, 0, s>>>(g.rowptr.p, g.col.p, g.tri.p, T, nullptr, off.p, g.q4.p);
+            LDS_HIP(hipGetLastError());
+            k_qcount<<<grid_for(Q, kT), kT, 0, s>>>(g.q4.p, Q, g.qcount.p);
+            LDS_HIP(hipGetLastError());
+        }
     }
-    p.rid = p.own_rid.p;
-    p.rp = p.own_rp.p;
-    p.py = p.own_py.p;
-    build_sweep_plan(p, s);
+    g.Q4 = Q;
+    build_incidence_plan<4>(g, g.q4.p, Q, g.qcount.p, g.clique_plan, g.q_max, s);
 }
 
 }  // namespace lds

@@ -19,6 +19,27 @@ def edge_split_map(G):
     return u, v
 
 
+def lex_lower_bound(rows, keys):
+    """first index i with rows[i] >= key (lexicographic), for every key row;
+    rows sorted lexicographically (vectorised binary search)"""
+    N = len(rows)
+    lo = np.zeros(len(keys), np.int64)
+    hi = np.full(len(keys), N, np.int64)
+    while True:
+        active = lo < hi
+        if not active.any():
+            return lo
+        mid = (lo + hi) // 2
+        r = rows[np.minimum(mid, N - 1)]
+        less = np.zeros(len(keys), bool)
+        eq = np.ones(len(keys), bool)
+        for c in range(rows.shape[1]):
+            less |= eq & (r[:, c] < keys[:, c])
+            eq &= r[:, c] == keys[:, c]
+        lo = np.where(active & less, mid + 1, lo)
+        hi = np.where(active & ~less, mid, hi)
+
+
 def check_fw(n, src, dst, mode, iters, gap=True, G=None, gpu_graph=None):
     """Run FW on both sides; assert exact numerators, splits and gap."""
     if G is None:
@@ -45,16 +66,17 @@ def check_fw(n, src, dst, mode, iters, gap=True, G=None, gpu_graph=None):
         want = np.where(x < y, ref["split"][idx, 0], ref["split"][idx, 1])
         np.testing.assert_array_equal(num, want)
     else:
-        tri, _ = oracle.triangles(G)
-        assert len(num) == 3 * len(tri)
-        if len(tri):
-            t64 = tri.astype(np.int64)
-            key_o = (t64[:, 0] * n + t64[:, 1]) * n + t64[:, 2]
+        pats = oracle.triangles(G)[0] if mode == 3 else oracle.cliques4(G)[0]
+        assert len(num) == mode * len(pats)
+        if len(pats):
+            # patterns are sorted ascending tuples: match them by their sorted rows
+            p64 = pats.astype(np.int64)
             s = np.sort(verts.astype(np.int64), axis=1)
-            key = (s[:, 0] * n + s[:, 1]) * n + s[:, 2]
-            idx = np.searchsorted(key_o, key)
-            assert (key_o[idx] == key).all()
-            pos = np.argmax(t64[idx] == verts[:, :1].astype(np.int64), axis=1)
+            order = np.lexsort(p64.T[::-1])
+            assert (order == np.arange(len(p64))).all()  # the oracle's list is lexicographic
+            idx = lex_lower_bound(p64, s)
+            assert (idx < len(p64)).all() and (p64[idx] == s).all()
+            pos = np.argmax(p64[idx] == verts[:, :1].astype(np.int64), axis=1)
             want = ref["split"][idx, pos]
             np.testing.assert_array_equal(num, want)
     return g, G, out, ref
