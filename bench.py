@@ -125,6 +125,40 @@ def bench_density(lds, torch, synth, densities):
     return res
 
 
+def bench_clique4(lds, torch, synth, name):
+    """The 4-clique program (h = 4): device listing of the 4-cliques from the
+    triangles, then N exact FW iterations with the gap; sweep rate against the
+    HBM roofline with the same per-slot byte count as the edge and triangle
+    sweeps (h-1 payload ids, one decision bit, 16 B per row)."""
+    n, s, t, mode, iters, _ = synth.workload(name)
+    ts, tt = torch.from_numpy(s).cuda(), torch.from_numpy(t).cuda()
+    g = lds.lds_create_graph(n, ts, tt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lds.lds_triangles(g)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    Q = lds.lds_cliques4(g)[0]
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    lds.lds_frank_wolfe(g, mode, iters, want_gap=True)
+    t3 = time.perf_counter()
+    fw_ms, launches = lds.lds_fw_elapsed(g, mode)
+    sw = lds.lds_sweep_info(g, mode)
+    per_launch_s = fw_ms / 1e3 / max(launches, 1)
+    alg = sw["slots"] * 12 + sw["slots"] / 8.0 + sw["rows"] * 16.0
+    achieved = alg / per_launch_s / 1e9
+    g.destroy()
+    log("clique4 %s: Q=%d listing %.1f ms, FW %.1f ms" % (name, Q, (t2 - t1) * 1e3, fw_ms))
+    return {"workload": name, "n": n, "cliques4": Q, "fw_iters": iters,
+            "triangle_listing_ms": (t1 - t0) * 1e3, "clique_listing_ms": (t2 - t1) * 1e3,
+            "fw_wall_ms": (t3 - t2) * 1e3, "fw_sweep_ms": fw_ms,
+            "clique_updates_per_s": Q * iters / (fw_ms / 1e3),
+            "sweep_ms_per_launch": per_launch_s * 1e3,
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "alg_bytes_per_launch": alg, "kernel": "k_fw_sweep<4>"}}
+
+
 def _serve_run(lds, np, srv, gs, pool_n, seconds, qps, seed, tag0):
     import synth
     q = synth.queries(int(seconds * qps * 1.5) + 16, qps=qps, pool=len(gs), kmax=10, seed=seed)
@@ -206,6 +240,7 @@ def main():
                     help="leave out the per-graph comparison of the batched section (shorter kernel traces)")
     ap.add_argument("--density-sweep", default="2,6,12",
                     help="Barabasi-Albert densities of the scalability section (n = 1M; empty: skip)")
+    ap.add_argument("--clique4", default="clique4_pl", help="4-clique FW workload ('' to skip)")
     ap.add_argument("--serve-seconds", type=float, default=5.0, help="arrival window of the serving run (0: skip)")
     ap.add_argument("--serve-qps", type=float, default=200.0)
     ap.add_argument("--serve-low-qps", type=float, default=25.0,
@@ -311,6 +346,8 @@ def main():
         out["batched"] = bench_batched(lds, torch, synth, np, args.batch_graphs, not args.no_batch_plain)
     if args.density_sweep:
         out["density_sweep"] = bench_density(lds, torch, synth, [int(x) for x in args.density_sweep.split(",")])
+    if args.clique4:
+        out["clique4"] = bench_clique4(lds, torch, synth, args.clique4)
     if args.serve_seconds > 0:
         out["serving"] = bench_serving(lds, torch, synth, np, args.serve_seconds, args.serve_qps, args.serve_low_qps)
     if not args.no_cpu_baseline:

@@ -134,6 +134,10 @@ WORKLOADS = {
                                          s_hi=2000, p_block=0.3, seed=2), 2, 100, 10),
     "ltds_hk": (holme_kim, dict(n=1_000_000, mper=20, p_triad=0.6, seed=3), 3, 200, 10),
 }
+# 4-clique program (h = 4): power-law background with 200 planted G(s, 0.5)
+# blocks, s in [20, 120]; 1.66e8 4-cliques
+WORKLOADS["clique4_pl"] = (powerlaw_planted, dict(n=1_000_000, beta=2.2, avg_deg=10.0, n_blocks=200, s_lo=20,
+                                                  s_hi=120, p_block=0.5, seed=4), 4, 100, 0)
 # the density sweep of the scalability experiment (Section 8): n = 1M, density
 # |E|/|V| = 2, 4, ..., 12, LDScvx with the default N = 100 and k = 5
 for _d in range(2, 13, 2):

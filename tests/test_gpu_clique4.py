@@ -98,3 +98,53 @@ def test_large_planted():
     g, G, Q = clique_parity(n, s, d)
     assert Q > 10_000_000
     check_fw(n, s, d, lds.LDS_CLIQUE4, 20, G=G, gpu_graph=g)
+
+
+def neighbourhood_triangles(rp, col, u):
+    """4-cliques at u = triangles of the subgraph induced by N(u), counted by
+    the oracle's (enumeration-pinned) triangle listing"""
+    nb = col[rp[u]:rp[u + 1]]
+    if len(nb) < 3:
+        return 0
+    loc = {int(x): i for i, x in enumerate(nb)}
+    src, dst = [], []
+    for x in nb:
+        for y in col[rp[x]:rp[x + 1]]:
+            j = loc.get(int(y))
+            if j is not None and int(x) < int(y):
+                src.append(loc[int(x)])
+                dst.append(j)
+    return len(oracle.triangles(oracle.Graph(len(nb), np.array(src, np.int32), np.array(dst, np.int32)))[0])
+
+
+def test_full_size_workload_properties():
+    """The 4-clique workload (n = 1M, 200 planted blocks, 1.66e8 4-cliques):
+    per-vertex counts at sampled vertices from the triangles of their
+    neighbourhoods; sum of counts = 4 Q; after 100 iterations every numerator
+    is q_u plus multiples of 4 (a0 = 1, increments 4(i+1)), they sum to D Q,
+    and the gap is non-negative and falls."""
+    announce("clique4 full-size properties")
+    n, s, d, mode, iters, _ = synth.workload("clique4_pl")
+    g = lds.lds_create_graph(n, s, d)
+    Q, _, cnt = lds.lds_cliques4(g, want_counts=True)
+    assert int(cnt.sum()) == 4 * Q and Q > 100_000_000
+    G = oracle.Graph(n, s, d)
+    u, v = G.edges()
+    del s, d
+    order = np.argsort(np.concatenate([u, v]), kind="stable")
+    col = np.concatenate([v, u])[order]
+    rp = np.zeros(n + 1, np.int64)
+    np.cumsum(np.bincount(np.concatenate([u, v]), minlength=n), out=rp[1:])
+    deg = np.diff(rp)
+    rng = np.random.default_rng(5)
+    sample = np.concatenate([rng.choice(np.flatnonzero((deg >= 3) & (deg <= 400)), 60, replace=False),
+                             rng.choice(np.flatnonzero(cnt > 1000), 20, replace=False)])
+    for x in sample:
+        if deg[x] <= 400:
+            assert neighbourhood_triangles(rp, col, x) == cnt[x], x
+    out = lds.lds_frank_wolfe(g, mode, iters, want_num=True, want_gap=True)
+    A = out["num"].astype(np.int64)
+    assert ((A - cnt) % 4 == 0).all() and (A >= cnt).all()
+    assert int(out["num"].sum(dtype=np.uint64)) == out["D"] * Q
+    gap = out["gap"]
+    assert (gap >= 0).all() and gap[-1] < gap[0]
