@@ -156,7 +156,8 @@ def bench_clique4(lds, torch, synth, name):
             "clique_updates_per_s": Q * iters / (fw_ms / 1e3),
             "sweep_ms_per_launch": per_launch_s * 1e3,
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": achieved / HBM_PEAK_GBS, "alg_bytes_per_launch": alg, "kernel": "k_fw_sweep<4>"}}
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(name),
+                         "alg_bytes_per_launch": alg, "kernel": "k_fw_sweep<4>"}}
 
 
 def _serve_run(lds, np, srv, gs, pool_n, seconds, qps, seed, tag0):

@@ -33,6 +33,7 @@
 #include <cstdlib>
 #include <queue>
 
+#include "islds.hpp"
 #include "topk.hpp"
 
 namespace lds {
@@ -487,6 +488,7 @@ struct Ctx {
     int64_t splitD = 1;
     TopkStats* st = nullptr;
     int64_t seq = 0;
+    BandScope* scope = nullptr;   // device state of the IsLDS / IsLTDS search
 };
 
 // patterns of G[vs] by local index (edges: pairs, triangles: triples)
@@ -586,99 +588,42 @@ bool is_lds(Ctx& c, const std::vector<int32_t>& vs, const Frac& rho) {
     // triangles).  A neighbour whose lower bound exceeds rho is in the
     // maximal rho-compact region, so S would not be maximal: in Alg. 4 that
     // is a self-loop inside S's component, which the proof of Thm. isLDS
-    // rules out; the flow network below leaves such vertices out, so the
-    // test is made here.
-    for (int32_t v : vs) {
-        if (lt(rho, c.lo[v]) || lt(c.hi[v], rho)) return false;
-        for (int64_t s = h.rp[v]; s < h.rp[v + 1]; ++s)
-            if (lt(rho, c.lo[h.col[s]])) return false;
+    // rules out; the flow network leaves such vertices out, so the device
+    // search rejects S at once.  Otherwise it grows the region U over the
+    // band lower <= rho <= upper, with one self-loop per edge to a vertex
+    // above (edges) or the triangle truncated to its members in the band
+    // (triangles), and returns the network when one is needed.
+    ScopeOut o;
+    if (!scope_band(*c.g, *c.scope, vs, rho.n, rho.d, o, c.s)) return false;
+    if (!o.need_flow) return true;
+    const std::vector<int32_t>& U = o.U;
+    for (size_t i = 0; i < U.size(); ++i) {
+        c.loc[U[i]] = (int32_t)i;
+        c.mark[U[i]] = 1;  // 1: in U
     }
-    std::vector<int32_t> U(vs.begin(), vs.end());
-    for (int32_t v : vs) c.mark[v] = 1;  // 1: in U
-    bool need_flow = false;
-    std::vector<int32_t> loops;  // edges: one self-loop per edge to a vertex whose lower bound exceeds rho
-    std::vector<int32_t> P;      // triangles: truncated patterns, -1 padded
-    std::vector<char> tvis;
-    if (c.mode == 3) tvis.assign(h.tri.size() / 3, 0);
-    for (size_t qi = 0; qi < U.size(); ++qi) {
-        const int32_t v = U[qi];
-        if (c.mode == 3) {
-            for (int64_t i = h.trp[v]; i < h.trp[v + 1]; ++i) {
-                const int64_t t = h.tinc[i];
-                if (tvis[t]) continue;
-                tvis[t] = 1;
-                const int32_t* x = &h.tri[3 * t];
-                if (lt(c.hi[x[0]], rho) || lt(c.hi[x[1]], rho) || lt(c.hi[x[2]], rho)) continue;  // not valid
-                int32_t M[3] = {-1, -1, -1};
-                int nm = 0;
-                for (int j = 0; j < 3; ++j) {
-                    const int32_t w = x[j];
-                    if (!lt(rho, c.lo[w])) {  // lower bound <= rho
-                        M[nm++] = w;
-                        if (c.mark[w] != 1) {
-                            c.mark[w] = 1;
-                            U.push_back(w);
-                        }
-                    } else {
-                        need_flow = true;
-                    }
-                }
-                if (nm > 0) P.insert(P.end(), M, M + 3);
-            }
-        }
-        for (int64_t s = h.rp[v]; s < h.rp[v + 1]; ++s) {
-            const int32_t w = h.col[s];
-            if (c.mark[w] == 1) continue;
-            if (lt(rho, c.lo[w])) {
-                need_flow = true;
-                if (c.mode == 2) loops.push_back(v);
-            } else if (!lt(c.hi[w], rho)) {  // lower <= rho <= upper
-                c.mark[w] = 1;
-                U.push_back(w);
-            }
-        }
-    }
+    std::vector<char> inX;
+    c.st->maxflows++;
+    if (c.mode == 2)
+        max_excess_edges((int64_t)U.size(), o.pat, o.loops, rho.n, rho.d, inX);
+    else
+        max_excess((int64_t)U.size(), 3, o.pat, rho.n, rho.d, inX);
+    // G[S] must be a connected component of G[X] (no vertex of S has a
+    // self-loop: rejected above)
     bool ok = true;
-    if (need_flow) {
-        for (size_t i = 0; i < U.size(); ++i) c.loc[U[i]] = (int32_t)i;
-        std::vector<int32_t> pat;
-        if (c.mode == 2) {
-            for (size_t i = 0; i < U.size(); ++i)
-                for (int64_t s = h.rp[U[i]]; s < h.rp[U[i] + 1]; ++s) {
-                    const int32_t j = c.loc[h.col[s]];
-                    if (j > (int32_t)i) {
-                        pat.push_back((int32_t)i);
-                        pat.push_back(j);
-                    }
-                }
-        } else {
-            pat.resize(P.size());
-            for (size_t i = 0; i < P.size(); ++i) pat[i] = P[i] >= 0 ? c.loc[P[i]] : -1;
-        }
-        std::vector<char> inX;
-        c.st->maxflows++;
-        if (c.mode == 2) {
-            std::vector<int64_t> nloop(U.size(), 0);
-            for (int32_t v : loops) nloop[c.loc[v]]++;
-            max_excess_edges((int64_t)U.size(), pat, nloop, rho.n, rho.d, inX);
-        } else {
-            max_excess((int64_t)U.size(), 3, pat, rho.n, rho.d, inX);
-        }
-        // G[vs] must be a connected component of G[X] (no vertex of S has a
-        // self-loop: checked above)
+    for (int32_t v : vs)
+        if (!inX[c.loc[v]]) ok = false;
+    if (ok) {
+        for (int32_t v : vs) c.mark[v] = 2;
         for (int32_t v : vs)
-            if (!inX[c.loc[v]]) ok = false;
-        if (ok) {
-            for (int32_t v : vs) c.mark[v] = 2;
-            for (int32_t v : vs)
-                for (int64_t s = h.rp[v]; s < h.rp[v + 1] && ok; ++s) {
-                    const int32_t w = h.col[s];
-                    if (c.mark[w] == 1 && inX[c.loc[w]]) ok = false;
-                }
-        }
-        for (int32_t v : U) c.loc[v] = -1;
+            for (int64_t s = h.rp[v]; s < h.rp[v + 1] && ok; ++s) {
+                const int32_t w = h.col[s];
+                if (c.mark[w] == 1 && inX[c.loc[w]]) ok = false;
+            }
     }
-    for (int32_t v : U) c.mark[v] = -1;
+    for (int32_t v : U) {
+        c.loc[v] = -1;
+        c.mark[v] = -1;
+    }
     return ok;
 }
 
@@ -844,6 +789,18 @@ void topk_run(Graph& g, int mode, int k, int iters, hipStream_t s, std::vector<T
             if (lt(c.lo[u], los[i])) c.lo[u] = los[i];
             if (lt(his[i], c.hi[u])) c.hi[u] = his[i];
         }
+    }
+    BandScope scope;
+    {
+        std::vector<int64_t> lon(n), lod(n), hin(n), hid(n);
+        for (int64_t u = 0; u < n; ++u) {
+            lon[u] = c.lo[u].n;
+            lod[u] = c.lo[u].d;
+            hin[u] = c.hi[u].n;
+            hid[u] = c.hi[u].d;
+        }
+        scope_init(g, mode, lon.data(), lod.data(), hin.data(), hid.data(), scope, s);
+        c.scope = &scope;
     }
     lap(&st.ms_fw);
     // Pruning (Alg. 3): rule 1, then rule 2 on the residual graph
