@@ -190,10 +190,26 @@ __global__ void k_clique_tris(const int64_t* rp, const int32_t* col, const int32
     if (!WRITE) cnt[t] = k;
 }
 
-__global__ void k_qcount(const int32_t* q4, int64_t Q, int32_t* qc) {
-    const int64_t t = (int64_t)blockIdx.x * kT + threadIdx.x;
-    if (t >= Q) return;
-    for (int j = 0; j < 4; ++j) atomicAdd(&qc[q4[4 * t + j]], 1);
+// per-vertex 4-clique counts.  Internal ids are ordered by degree, so the
+// vertices in most cliques have the smallest ids: their counts are kept in
+// an LDS histogram per workgroup (one global atomic per workgroup and hub at
+// the end) instead of millions of atomics on a few addresses.
+constexpr int kHubIds = 8192;
+__global__ __launch_bounds__(kT) void k_qcount(const int32_t* q4, int64_t Q, int32_t* qc) {
+    __shared__ int32_t hist[kHubIds];
+    for (int i = threadIdx.x; i < kHubIds; i += kT) hist[i] = 0;
+    __syncthreads();
+    for (int64_t t = (int64_t)blockIdx.x * kT + threadIdx.x; t < Q; t += (int64_t)gridDim.x * kT)
+        for (int j = 0; j < 4; ++j) {
+            const int32_t v = q4[4 * t + j];
+            if (v < kHubIds)
+                atomicAdd(&hist[v], 1);
+            else
+                atomicAdd(&qc[v], 1);
+        }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kHubIds; i += kT)
+        if (hist[i]) atomicAdd(&qc[i], hist[i]);
 }
 
 template <class T>
@@ -331,7 +347,7 @@ void list_cliques4(Graph& g, hipStream_t s) {
         if (Q > 0) {
             k_clique_tris<true><<<grid_for(T, kT), kT, 0, s>>>(g.rowptr.p, g.col.p, g.tri.p, T, nullptr, off.p, g.q4.p);
             LDS_HIP(hipGetLastError());
-            k_qcount<<<grid_for(Q, kT), kT, 0, s>>>(g.q4.p, Q, g.qcount.p);
+            k_qcount<<<std::min<unsigned>(grid_for(Q, kT), 2048u), kT, 0, s>>>(g.q4.p, Q, g.qcount.p);
             LDS_HIP(hipGetLastError());
         }
     }
