@@ -264,7 +264,9 @@ lds_status lds_core_numbers(lds_graph g, lds_mode mode, const uint8_t* alive, in
  * subgraphs, candidates split by a min cut, min-cut computations and
  * vertices removed by the pruning rules; the ms fields the wall-clock time of
  * the phases (host copy of the graph, core numbers, first FW + ExtractSG,
- * pruning, candidate search). */
+ * pruning, candidate search); refine_rounds the batched FW launches that
+ * carried the refinements (candidates that fail IsDensest with the same
+ * bound are refined together). */
 typedef struct {
     int32_t count;
     int64_t* offsets;   /* count + 1 */
@@ -273,6 +275,7 @@ typedef struct {
     int64_t* dens_den;  /* count */
     int64_t popped, refinements, flow_splits, maxflows, pruned;
     double ms_copy, ms_core, ms_fw, ms_prune, ms_search;  /* wall-clock phases */
+    int64_t refine_rounds;
 } lds_result;
 
 /* Top-k LDS (Problem LDS, Section 3; mode LDS_EDGE) or LTDS (Problem LTDS,

@@ -272,7 +272,8 @@ class _Result(ctypes.Structure):
                 ("dens_den", ctypes.POINTER(ctypes.c_int64)), ("popped", ctypes.c_int64),
                 ("refinements", ctypes.c_int64), ("flow_splits", ctypes.c_int64), ("maxflows", ctypes.c_int64),
                 ("pruned", ctypes.c_int64), ("ms_copy", ctypes.c_double), ("ms_core", ctypes.c_double),
-                ("ms_fw", ctypes.c_double), ("ms_prune", ctypes.c_double), ("ms_search", ctypes.c_double)]
+                ("ms_fw", ctypes.c_double), ("ms_prune", ctypes.c_double), ("ms_search", ctypes.c_double),
+                ("refine_rounds", ctypes.c_int64)]
 
 
 def _sets_of(r):
@@ -294,8 +295,8 @@ def lds_topk(g, mode, k, iters, stream=None, with_stats=False):
     _check(L.lds_topk(g.handle, mode, int(k), int(iters), ctypes.byref(r), _stream(stream)))
     try:
         out = _sets_of(r)
-        stats = {f: getattr(r, f) for f in ("popped", "refinements", "flow_splits", "maxflows", "pruned",
-                                              "ms_copy", "ms_core", "ms_fw", "ms_prune", "ms_search")}
+        stats = {f: getattr(r, f) for f in ("popped", "refinements", "refine_rounds", "flow_splits", "maxflows",
+                                              "pruned", "ms_copy", "ms_core", "ms_fw", "ms_prune", "ms_search")}
     finally:
         L.lds_result_free(ctypes.byref(r))
     return (out, stats) if with_stats else out

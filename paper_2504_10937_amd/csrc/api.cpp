@@ -385,6 +385,7 @@ void fill_result(const std::vector<lds::TopkSet>& sets, const lds::TopkStats& st
     r.ms_fw = st.ms_fw;
     r.ms_prune = st.ms_prune;
     r.ms_search = st.ms_search;
+    r.refine_rounds = st.refine_rounds;
     *out = r;
 }
 

@@ -31,8 +31,10 @@
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
+#include <memory>
 #include <queue>
 
+#include "batch.hpp"
 #include "islds.hpp"
 #include "topk.hpp"
 
@@ -672,32 +674,61 @@ void collect_groups(Graph& gg, int mode, int iters, hipStream_t s, Map map, std:
 }
 
 // FW + ExtractSG on G[vs]: the stable groups of the induced subgraph
-void refine(Ctx& c, const std::vector<int32_t>& vs, std::vector<std::vector<int32_t>>& sets, std::vector<Frac>& his) {
-    // local ids follow caller-id order, so FW breaks ties as on the whole graph
-    std::vector<int32_t> sv = vs;
-    std::sort(sv.begin(), sv.end(), [&](int32_t a, int32_t b) { return c.h.orig[a] < c.h.orig[b]; });
-    std::vector<int32_t> src, dst;
-    for (size_t i = 0; i < sv.size(); ++i) c.loc[sv[i]] = (int32_t)i;
-    for (size_t i = 0; i < sv.size(); ++i)
-        for (int64_t s = c.h.rp[sv[i]]; s < c.h.rp[sv[i] + 1]; ++s) {
-            const int32_t j = c.loc[c.h.col[s]];
-            if (j > (int32_t)i) {
-                src.push_back((int32_t)i);
-                dst.push_back(j);
+// Alg. 5 re-runs FW + ExtractSG on G[S] for a popped candidate S that is not
+// self-densest.  The candidates of one round go through the batched FW
+// kernel together (one launch for all of their induced subgraphs, bit for
+// bit the state of per-graph runs), then ExtractSG per subgraph.  Local ids
+// follow caller-id order, so FW breaks ties as on the whole graph.
+void refine_batch(Ctx& c, const std::vector<const std::vector<int32_t>*>& cands,
+                  std::vector<std::vector<std::vector<int32_t>>>& sets, std::vector<std::vector<Frac>>& his) {
+    const size_t nb = cands.size();
+    std::vector<std::unique_ptr<Graph>> subs(nb);
+    std::vector<std::vector<int32_t>> svs(nb);
+    for (size_t b = 0; b < nb; ++b) {
+        std::vector<int32_t>& sv = svs[b];
+        sv = *cands[b];
+        std::sort(sv.begin(), sv.end(), [&](int32_t x, int32_t y) { return c.h.orig[x] < c.h.orig[y]; });
+        std::vector<int32_t> src, dst;
+        for (size_t i = 0; i < sv.size(); ++i) c.loc[sv[i]] = (int32_t)i;
+        for (size_t i = 0; i < sv.size(); ++i)
+            for (int64_t q = c.h.rp[sv[i]]; q < c.h.rp[sv[i] + 1]; ++q) {
+                const int32_t j = c.loc[c.h.col[q]];
+                if (j > (int32_t)i) {
+                    src.push_back((int32_t)i);
+                    dst.push_back(j);
+                }
             }
-        }
-    for (int32_t v : sv) c.loc[v] = -1;
-    Graph sub;
-    build_graph(sub, (int64_t)sv.size(), (int64_t)src.size(), src.data(), dst.data(), false, false, c.s);
-    fw_run(sub, c.mode, c.iters, false, c.s);
-    sg_stable_groups(sub, c.mode, c.s);
-    std::vector<int32_t> orig(sub.n);
-    if (sub.n > 0) {
-        LDS_HIP(hipMemcpyAsync(orig.data(), sub.orig_of.p, sub.n * sizeof(int32_t), hipMemcpyDeviceToHost, c.s));
-        LDS_HIP(hipStreamSynchronize(c.s));
+        for (int32_t v : sv) c.loc[v] = -1;
+        subs[b] = std::make_unique<Graph>();
+        build_graph(*subs[b], (int64_t)sv.size(), (int64_t)src.size(), src.data(), dst.data(), false, false, c.s);
     }
-    collect_groups(sub, c.mode, c.iters, c.s, [&](int32_t j) { return sv[orig[j]]; }, sets, his, nullptr);
-    c.st->refinements++;
+    {
+        Batch bt;
+        for (size_t b = 0; b < nb; ++b) {
+            bt.gs.push_back(subs[b].get());
+            bt.modes.push_back(c.mode);
+            bt.iters.push_back(c.iters);
+        }
+        bt.capture = false;
+        batch_build(bt, c.s);
+        batch_run(bt, c.s);
+        LDS_HIP(hipStreamSynchronize(c.s));
+        c.st->refine_rounds++;
+    }
+    sets.assign(nb, {});
+    his.assign(nb, {});
+    for (size_t b = 0; b < nb; ++b) {
+        Graph& sub = *subs[b];
+        sg_stable_groups(sub, c.mode, c.s);
+        std::vector<int32_t> orig(sub.n);
+        if (sub.n > 0) {
+            LDS_HIP(hipMemcpyAsync(orig.data(), sub.orig_of.p, sub.n * sizeof(int32_t), hipMemcpyDeviceToHost, c.s));
+            LDS_HIP(hipStreamSynchronize(c.s));
+        }
+        const std::vector<int32_t>& sv = svs[b];
+        collect_groups(sub, c.mode, c.iters, c.s, [&](int32_t j) { return sv[orig[j]]; }, sets[b], his[b], nullptr);
+        c.st->refinements++;
+    }
 }
 
 }  // namespace
@@ -850,17 +881,72 @@ void topk_run(Graph& g, int mode, int k, int iters, hipStream_t s, std::vector<T
                      (long long)r.d, std::chrono::duration<double, std::milli>(now - tick).count());
         tick = now;
     };
-    while (!pq.empty()) {
+    // Candidates that fail IsDensest wait in `pend` and are refined together
+    // (one batched FW launch).  The round is closed before a candidate with a
+    // smaller bound is examined, before stopping, and when it is full, so
+    // candidates are still examined in non-increasing order of their bound.
+    struct Pend {
+        Cand cd;
+        Frac rho;
+        std::vector<int32_t> denser;
+    };
+    std::vector<Pend> pend;
+    constexpr size_t kRound = 64;
+    auto flush = [&]() {
+        if (pend.empty()) return;
+        std::vector<const std::vector<int32_t>*> cs;
+        for (const Pend& x : pend) cs.push_back(&x.cd.vs);
+        std::vector<std::vector<std::vector<int32_t>>> parts;
+        std::vector<std::vector<Frac>> phis;
+        refine_batch(c, cs, parts, phis);
+        for (size_t i = 0; i < pend.size(); ++i) {
+            Pend& x = pend[i];
+            note("refined", parts[i].size(), x.rho);
+            if (parts[i].size() >= 2) {
+                for (size_t j = 0; j < parts[i].size(); ++j) {
+                    Frac cap = x.cd.ub;
+                    if (phis[i][j].n >= 0 && lt(phis[i][j], cap)) cap = phis[i][j];
+                    push(std::move(parts[i][j]), &cap);
+                }
+                continue;
+            }
+            // FW did not split G[S]: split by the min cut's denser vertex set
+            st.flow_splits++;
+            std::sort(x.denser.begin(), x.denser.end());
+            std::vector<int32_t> top, rest;
+            for (int32_t v : x.cd.vs)
+                (std::binary_search(x.denser.begin(), x.denser.end(), v) ? top : rest).push_back(v);
+            push(std::move(rest), &x.cd.ub);
+            push(std::move(top), &x.cd.ub);
+        }
+        pend.clear();
+    };
+    for (;;) {
+        if (pq.empty()) {
+            if (pend.empty()) break;
+            flush();
+            continue;
+        }
+        // a candidate with a smaller bound than the waiting ones: refine those first
+        if (!pend.empty() && lt(pq.top().ub, pend.front().cd.ub)) {
+            flush();
+            continue;
+        }
+        bool stop = pq.top().ub.n <= 0;  // an LDS has positive density
+        if (!stop && (int)dens.size() >= k) {
+            std::nth_element(dens.begin(), dens.begin() + (k - 1), dens.end(),
+                             [](const Frac& a, const Frac& b) { return lt(b, a); });
+            stop = lt(pq.top().ub, dens[k - 1]);  // no remaining candidate reaches the k-th density
+        }
+        if (stop) {
+            if (pend.empty()) break;
+            flush();
+            continue;
+        }
         Cand cd = std::move(const_cast<Cand&>(pq.top()));
         pq.pop();
         st.popped++;
         note("pop", cd.vs.size(), cd.ub);
-        if ((int)dens.size() >= k) {
-            std::nth_element(dens.begin(), dens.begin() + (k - 1), dens.end(),
-                             [](const Frac& a, const Frac& b) { return lt(b, a); });
-            if (lt(cd.ub, dens[k - 1])) break;  // no remaining candidate reaches the k-th density
-        }
-        if (cd.ub.n <= 0) break;  // an LDS has positive density
         std::vector<std::vector<int32_t>> comps = components(c, cd.vs);
         if (comps.size() > 1) {
             note("components", comps.size(), cd.ub);
@@ -880,25 +966,8 @@ void topk_run(Graph& g, int mode, int k, int iters, hipStream_t s, std::vector<T
             }
             continue;
         }
-        std::vector<std::vector<int32_t>> parts;
-        std::vector<Frac> phis;
-        refine(c, cd.vs, parts, phis);
-        note("refined", parts.size(), rho);
-        if (parts.size() >= 2) {
-            for (size_t i = 0; i < parts.size(); ++i) {
-                Frac cap = cd.ub;
-                if (phis[i].n >= 0 && lt(phis[i], cap)) cap = phis[i];
-                push(std::move(parts[i]), &cap);
-            }
-            continue;
-        }
-        // FW did not split G[S]: split by the min cut's denser vertex set
-        st.flow_splits++;
-        std::sort(denser.begin(), denser.end());
-        std::vector<int32_t> top, rest;
-        for (int32_t v : cd.vs) (std::binary_search(denser.begin(), denser.end(), v) ? top : rest).push_back(v);
-        push(std::move(rest), &cd.ub);
-        push(std::move(top), &cd.ub);
+        pend.push_back(Pend{std::move(cd), rho, std::move(denser)});
+        if (pend.size() >= kRound) flush();
     }
     lap(&st.ms_search);
     for (auto& f : found) {

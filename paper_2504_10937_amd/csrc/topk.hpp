@@ -36,6 +36,7 @@ struct TopkSet {
 struct TopkStats {
     int64_t popped = 0;       // candidates taken from the queue
     int64_t refinements = 0;  // FW + ExtractSG runs on induced subgraphs
+    int64_t refine_rounds = 0;  // batched FW launches that carried them
     int64_t flow_splits = 0;  // candidates split by the min cut instead
     int64_t maxflows = 0;     // min-cut computations (IsDensest + IsLDS)
     int64_t pruned = 0;       // vertices removed by the two pruning rules

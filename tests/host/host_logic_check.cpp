@@ -21,6 +21,9 @@ void list_triangles(Graph&, hipStream_t) {}
 void sg_stable_groups(Graph&, int, hipStream_t) {}
 void fw_run(Graph&, int, int, bool, hipStream_t) {}
 void core_numbers_gpu(Graph&, int, const uint8_t*, int32_t*, hipStream_t) {}
+Batch::~Batch() {}
+void batch_build(Batch&, hipStream_t) {}
+void batch_run(Batch&, hipStream_t) {}
 void scope_init(Graph&, int, const int64_t*, const int64_t*, const int64_t*, const int64_t*, BandScope&, hipStream_t) {}
 bool scope_band(Graph&, BandScope&, const std::vector<int32_t>&, int64_t, int64_t, ScopeOut&, hipStream_t) {
     return false;

@@ -152,3 +152,37 @@ def test_fw_state_after_topk():
     ref = oracle.fw_exact(G, 2, 30, with_split=False)
     out = lds.lds_frank_wolfe(g, 2, 30, want_num=True)
     np.testing.assert_array_equal(out["num"], ref["A"])
+
+
+def disjoint_copies(c, nk=5, L=5):
+    """c disjoint copies of K_nk with a cycle through L new vertices and the
+    clique's last vertex (cycle vertices have core 2, so pruning keeps them)"""
+    s, t, per = [], [], nk + L
+    for i in range(c):
+        b = i * per
+        for a in range(nk):
+            for d in range(a + 1, nk):
+                s.append(b + a)
+                t.append(b + d)
+        prev = b + nk - 1
+        for j in range(L):
+            s.append(prev)
+            t.append(b + nk + j)
+            prev = b + nk + j
+        s.append(prev)
+        t.append(b + nk - 1)
+    return c * per, np.array(s, np.int32), np.array(t, np.int32)
+
+
+@pytest.mark.parametrize("iters", [0, 1, 2, 3])
+def test_refinements_batched(iters):
+    """With 1 or 3 iterations the whole graph of 6 disjoint copies is one
+    stable group and no vertex is pruned: its 6 components share the bound,
+    each fails IsDensest (16/10 < 2), and their refinements share batched FW
+    launches.  Results equal the oracle's for every iteration count."""
+    announce("topk batched refinements", iters)
+    n, s, t = disjoint_copies(6)
+    got, st = check(n, s, t, 2, 6, iters)
+    assert len(got) == 6 and all(r == 2 for _, r in got)
+    if iters in (1, 3):
+        assert st["refinements"] >= 6 and st["refine_rounds"] < st["refinements"]
