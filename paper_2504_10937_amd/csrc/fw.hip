@@ -19,8 +19,10 @@
 //     slots (stored once, coalesced); row-start flags turn the ballot into
 //     per-row win counts with popcounts (segmented count, no atomics), and
 //     the lane holding a row's last slot writes the row's new key.
-//   * hub workgroups: one 256-thread workgroup per row with more slots than
-//     a chunk; per-wave ballots, LDS reduction, one key write.
+//   * hub pieces: a row with more slots than a chunk is cut into word-aligned
+//     pieces of at most kPiece slots, one wave each, scheduled before the
+//     chunks over all waves; a piece adds its wins to the row's counter and
+//     the wave that completes the row's last piece writes the row's key.
 // The duality-gap terms sum_u A_u^2 and sum_u A_u b_u (= sum over patterns of
 // the winning numerator, i.e. the minimum) are accumulated exactly in 128-bit
 // integers per workgroup and reduced once after the last iteration.
@@ -38,6 +40,10 @@ struct SweepArgs {
     const int32_t* py;
     int64_t n_hub;
     const int64_t* hwo;
+    int64_t n_pieces;
+    const int32_t* hp_row;
+    const int32_t* hp_off;
+    unsigned long long* hub_ctr;  // per hub row: (pieces done << 40) | wins so far
     int64_t n_chunks;
     const int64_t* chunk_row;
     const int64_t* cwo;
@@ -141,7 +147,6 @@ __device__ inline Slot<4> load_slot<4>(const int32_t* __restrict__ py, int64_t s
 #define LDS_SWEEP_WG_PER_CU 1
 #endif
 constexpr int kG = LDS_SWEEP_WORDS;         // 64-slot words of a chunk in flight per wave
-constexpr int kHubU = 4;                    // slots per thread in flight in a hub row
 constexpr int kPT = LDS_SWEEP_THREADS;      // threads of a persistent workgroup
 constexpr int kWaves = kPT / 64;
 constexpr int kCacheQ = LDS_SWEEP_CACHE;    // codes of the first (highest-degree) vertices staged in LDS
@@ -167,62 +172,69 @@ template <int H, bool IDENT, bool GAP>
 __global__ __launch_bounds__(kPT) void k_fw_sweep(SweepArgs a) {
     extern __shared__ uint16_t qc[];
     __shared__ uint64_t red[kWaves][4];
-    __shared__ uint32_t hcnt[kWaves];
     __shared__ uint64_t words[kWaves][32];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int nc = a.ncache;
     for (int i = threadIdx.x; i < nc; i += kPT) qc[i] = a.Qin[i];
     __syncthreads();
     u128 sq = 0, mn = 0;
-    // ---- hub rows: one workgroup each, 4096 slots per step
-    for (int64_t r = blockIdx.x; r < a.n_hub; r += gridDim.x) {
+    // ---- hub rows: cut into word-aligned pieces of <= kPiece slots, one wave
+    //      each.  A piece stores its decision words and adds (1 << 40) + its
+    //      wins to the row's counter with one atomic, so the wave whose add
+    //      completes the row's last piece reads the row's total from the value
+    //      returned, with no fence; it writes the row's key and clears the
+    //      counter for the next sweep.
+    for (int64_t pc = (int64_t)blockIdx.x * kWaves + w; pc < a.n_pieces; pc += (int64_t)gridDim.x * kWaves) {
+        const int64_t r = a.hp_row[pc];
         const uint32_t u = IDENT ? (uint32_t)r : (uint32_t)a.rid[r];
-        const int64_t s0 = a.rp[r], s1 = a.rp[r + 1];
+        const int64_t rs = a.rp[r], re = a.rp[r + 1];
+        const int64_t s0 = rs + a.hp_off[pc], s1 = min(re, s0 + (int64_t)kPiece);
         const uint64_t Ku = a.Kin[u];
         const uint16_t Qu = qcode(Ku >> a.B);
-        uint64_t* bw = a.bits + a.chunk_words + a.hwo[r];
+        uint64_t* bw = a.bits + a.chunk_words + a.hwo[r] + (s0 - rs) / 64;
         uint32_t cnt = 0;
-        for (int64_t base = s0; base < s1; base += (int64_t)kPT * kHubU) {
-            Slot<H> sl[kHubU];
-            bool in[kHubU];
+        for (int64_t base = s0; base < s1; base += 64 * kG) {
+            Slot<H> sl[kG];
+            bool in[kG];
 #pragma unroll
-            for (int k = 0; k < kHubU; ++k) {
-                const int64_t s = base + (int64_t)k * kPT + threadIdx.x;
-                in[k] = s < s1;
-                if (in[k]) sl[k] = load_slot<H>(a.py, s);
+            for (int j = 0; j < kG; ++j) {
+                const int64_t s = base + 64 * j + lane;
+                in[j] = s < s1;
+                if (in[j]) sl[j] = load_slot<H>(a.py, s);
             }
-            uint16_t qv[kHubU][H - 1];
+            uint16_t qv[kG][H - 1];
 #pragma unroll
-            for (int k = 0; k < kHubU; ++k)
+            for (int j = 0; j < kG; ++j)
 #pragma unroll
                 for (int q = 0; q < H - 1; ++q)
-                    qv[k][q] = in[k] ? qload(qc, nc, a.Qin, (uint32_t)sl[k].v[q]) : (uint16_t)0;
+                    qv[j][q] = in[j] ? qload(qc, nc, a.Qin, (uint32_t)sl[j].v[q]) : (uint16_t)0;
 #pragma unroll
-            for (int k = 0; k < kHubU; ++k) {
-                bool win = in[k];
+            for (int j = 0; j < kG; ++j) {
+                bool win = in[j];
 #pragma unroll
-                for (int q = 0; q < H - 1; ++q) win = win && beats(Ku, Qu, qv[k][q], a.Kin, sl[k].v[q]);
+                for (int q = 0; q < H - 1; ++q) win = win && beats(Ku, Qu, qv[j][q], a.Kin, sl[j].v[q]);
                 const uint64_t W = __ballot(win);
-                const int64_t wb = base + (int64_t)k * kPT + 64 * w;  // first slot of this wave's word
+                const int64_t wb = base + 64 * j;  // first slot of this word
                 if (lane == 0 && wb < s1) __builtin_nontemporal_store(W, bw + (wb - s0) / 64);
                 cnt += (uint32_t)__popcll(W);
             }
         }
-        if (lane == 0) hcnt[w] = cnt;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            uint64_t tot = 0;
-            for (int q = 0; q < kWaves; ++q) tot += hcnt[q];
-            const uint64_t Kn = Ku + ((tot * a.inc) << a.B);
-            a.Kout[u] = Kn;
-            a.Qout[u] = qcode(Kn >> a.B);
-            if (GAP) {
-                const uint64_t A = Ku >> a.B;
-                sq += (u128)A * A;
-                mn += (u128)A * tot;
+        if (lane == 0) {
+            const unsigned long long npc = (unsigned long long)((re - rs + kPiece - 1) / kPiece);
+            const unsigned long long old = atomicAdd(a.hub_ctr + r, (1ull << 40) | (unsigned long long)cnt);
+            if ((old >> 40) == npc - 1) {
+                const uint64_t tot = (old & ((1ull << 40) - 1)) + cnt;
+                const uint64_t Kn = Ku + ((tot * a.inc) << a.B);
+                a.Kout[u] = Kn;
+                a.Qout[u] = qcode(Kn >> a.B);
+                if (GAP) {
+                    const uint64_t A = Ku >> a.B;
+                    sq += (u128)A * A;
+                    mn += (u128)A * tot;
+                }
+                atomicExch(a.hub_ctr + r, 0ull);
             }
         }
-        __syncthreads();  // hcnt is reused by the next hub row
     }
     // ---- chunks: one wave each
     //   A. decision words: kG words per batch, slot payloads then codes in
@@ -536,6 +548,10 @@ void fw_run(Graph& g, int mode, int iters, bool want_gap, hipStream_t s) {
     a.py = p.py;
     a.n_hub = p.n_hub;
     a.hwo = p.hwo.p;
+    a.n_pieces = p.n_pieces;
+    a.hp_row = p.hp_row.p;
+    a.hp_off = p.hp_off.p;
+    a.hub_ctr = p.hub_ctr.p;
     a.n_chunks = p.n_chunks;
     a.chunk_row = p.chunk_row.p;
     a.cwo = p.cwo.p;

@@ -28,6 +28,7 @@
 namespace lds {
 
 constexpr int kChunk = 1024;  // target slots per wave; spans < 2*kChunk = 32 words
+constexpr int kPiece = 2048;  // slots of a hub-row piece (a multiple of 64)
 
 // denominator of the loads after i iterations with gamma_i = 2/(i+2):
 // (i+1)(i+2) for edges (mode 2), 3(i+1)(i+2) for triangles (mode 3),
@@ -55,6 +56,10 @@ struct SweepPlan {
     int64_t n_big = 0;             // rows [0, n_big) have >= 64 slots (rows are ordered by slot count)
     int64_t n_hub = 0;          // rows [0, n_hub) are hubs
     DBuf<int64_t> hwo;          // n_hub + 1 word offsets (relative to hub region)
+    int64_t n_pieces = 0;       // hub rows cut into word-aligned pieces of <= kPiece slots, one wave each
+    DBuf<int32_t> hp_row;       // per piece: hub row
+    DBuf<int32_t> hp_off;       // per piece: first slot, relative to the row start (a multiple of 64)
+    DBuf<unsigned long long> hub_ctr;  // n_hub: (pieces done << 40) | wins so far (zero between sweeps)
     int64_t n_chunks = 0;
     DBuf<int64_t> chunk_row;    // n_chunks + 1 (compact row index)
     DBuf<int64_t> cwo;          // n_chunks + 1 word offsets
@@ -63,7 +68,7 @@ struct SweepPlan {
     DBuf<int64_t> bitbase;      // per compact row: bit index of its first slot
     size_t device_bytes() const {
         return own_rid.bytes() + own_rp.bytes() + own_py.bytes() + own_tos.bytes() + own_row_of.bytes() + hwo.bytes() + chunk_row.bytes() + cwo.bytes() +
-               head.bytes() + bitbase.bytes();
+               head.bytes() + bitbase.bytes() + hp_row.bytes() + hp_off.bytes() + hub_ctr.bytes();
     }
 };
 

@@ -147,6 +147,23 @@ __global__ void k_hub_words(const int64_t* rp, int64_t n_hub, uint64_t* words) {
     words[r] = (uint64_t)((rp[r + 1] - rp[r] + 63) / 64);
 }
 
+__global__ void k_hub_pieces(const int64_t* rp, int64_t n_hub, uint32_t* np) {
+    const int64_t r = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (r < n_hub) np[r] = (uint32_t)((rp[r + 1] - rp[r] + kPiece - 1) / kPiece);
+}
+
+__global__ void k_hub_piece_fill(const int64_t* rp, int64_t n_hub, const uint64_t* first, int32_t* hp_row,
+                                 int32_t* hp_off) {
+    const int64_t r = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (r >= n_hub) return;
+    const int64_t len = rp[r + 1] - rp[r];
+    int64_t k = (int64_t)first[r];
+    for (int64_t o = 0; o < len; o += kPiece, ++k) {
+        hp_row[k] = (int32_t)r;
+        hp_off[k] = (int32_t)o;
+    }
+}
+
 __global__ void k_chunk_rows(const int64_t* rp, int64_t nrows, int64_t n_hub, int64_t n_chunks, int64_t* chunk_row) {
     const int64_t r = n_hub + (int64_t)blockIdx.x * kT + threadIdx.x;
     if (r > nrows) return;
@@ -219,6 +236,25 @@ void build_sweep_plan(SweepPlan& p, hipStream_t s) {
     k_set_last<<<1, 1, 0, s>>>(p.hwo.p, p.n_hub, tot.p);
     LDS_HIP(hipGetLastError());
     p.hub_words = (int64_t)d2h(tot.p, s);
+    // hub pieces and their per-row counters
+    p.n_pieces = 0;
+    if (p.n_hub > 0) {
+        DBuf<uint32_t> npc;
+        DBuf<uint64_t> first;
+        npc.alloc(p.n_hub, s);
+        first.alloc(p.n_hub, s);
+        k_hub_pieces<<<grid_for(p.n_hub, kT), kT, 0, s>>>(p.rp, p.n_hub, npc.p);
+        LDS_HIP(hipGetLastError());
+        exclusive_scan_u32_to_u64(npc.p, first.p, p.n_hub, tot.p, s);
+        p.n_pieces = (int64_t)d2h(tot.p, s);
+        LDS_CHECK(p.n_pieces < INT32_MAX, ST_INVALID, "too many hub pieces");
+        p.hp_row.alloc(p.n_pieces, s);
+        p.hp_off.alloc(p.n_pieces, s);
+        k_hub_piece_fill<<<grid_for(p.n_hub, kT), kT, 0, s>>>(p.rp, p.n_hub, first.p, p.hp_row.p, p.hp_off.p);
+        LDS_HIP(hipGetLastError());
+        p.hub_ctr.alloc(p.n_hub, s);
+        LDS_HIP(hipMemsetAsync(p.hub_ctr.p, 0, p.hub_ctr.bytes(), s));
+    }
     // chunks
     int64_t base = 0;
     LDS_HIP(hipMemcpyAsync(&base, p.rp + p.n_hub, sizeof(int64_t), hipMemcpyDeviceToHost, s));
