@@ -8,8 +8,10 @@ is missing — there is no fallback path.
 
 Names follow the C ABI: lds_create_graph, lds_frank_wolfe, ...
 """
+import atexit
 import ctypes
 import os
+import weakref
 
 import numpy as np
 
@@ -25,6 +27,21 @@ STATUS = {0: "LDS_OK", 1: "LDS_E_INVALID", 2: "LDS_E_NOMEM", 3: "LDS_E_DEVICE", 
           5: "LDS_E_BUSY"}
 
 _lib = None
+# live native handles, released at interpreter exit while torch (whose
+# allocator may own their memory) is still usable: servers, then batches,
+# then graphs
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _release_all():
+    global _lib
+    objs = list(_live)
+    for cls in (Server, Batch, Graph):
+        for o in objs:
+            if isinstance(o, cls):
+                o.destroy()
+    _lib = None
 
 
 class LdsError(RuntimeError):
@@ -115,6 +132,7 @@ class Graph:
 
     def __init__(self, handle):
         self._h = handle
+        _live.add(self)
 
     @property
     def handle(self):
@@ -356,6 +374,7 @@ class Batch:
         self._h = handle
         self._graphs = graphs
         self._r_out = r_out
+        _live.add(self)
 
     @property
     def handle(self):
@@ -449,6 +468,7 @@ class Server:
     def __init__(self, handle):
         self._h = handle
         self._graphs = {}
+        _live.add(self)
 
     @property
     def handle(self):
