@@ -125,6 +125,41 @@ def bench_density(lds, torch, synth, densities):
     return res
 
 
+def bench_ltds(lds, torch, synth, name):
+    """The triangle program (Eq. trcp, Alg. 6) on the LTDS workload: device
+    triangle listing, N exact FW iterations with the gap, sort / prefix /
+    stable groups; sweep rate against the HBM roofline (2 payload ids, one
+    decision bit per slot, 16 B per row)."""
+    n, s, t, mode, iters, _ = synth.workload(name)
+    ts, tt = torch.from_numpy(s).cuda(), torch.from_numpy(t).cuda()
+    g = lds.lds_create_graph(n, ts, tt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    T = lds.lds_triangles(g)[0]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lds.lds_frank_wolfe(g, mode, iters, want_gap=True)
+    t2 = time.perf_counter()
+    groups, _, _ = lds.lds_stable_groups(g, mode)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    fw_ms, launches = lds.lds_fw_elapsed(g, mode)
+    sw = lds.lds_sweep_info(g, mode)
+    per_launch_s = fw_ms / 1e3 / max(launches, 1)
+    alg = sw["slots"] * 8 + sw["slots"] / 8.0 + sw["rows"] * 16.0
+    achieved = alg / per_launch_s / 1e9
+    g.destroy()
+    log("ltds %s: T=%d listing %.1f ms, FW %.1f ms, groups %.1f ms" % (name, T, (t1 - t0) * 1e3, fw_ms,
+                                                                   (t3 - t2) * 1e3))
+    return {"workload": name, "n": n, "triangles": T, "fw_iters": iters, "triangle_listing_ms": (t1 - t0) * 1e3,
+            "fw_wall_ms": (t2 - t1) * 1e3, "fw_sweep_ms": fw_ms, "sort_prefix_groups_ms": (t3 - t2) * 1e3,
+            "groups": len(groups), "triangle_updates_per_s": T * iters / (fw_ms / 1e3),
+            "sweep_ms_per_launch": per_launch_s * 1e3,
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(name),
+                         "alg_bytes_per_launch": alg, "kernel": "k_fw_sweep<3>"}}
+
+
 def bench_clique4(lds, torch, synth, name):
     """The 4-clique program (h = 4): device listing of the 4-cliques from the
     triangles, then N exact FW iterations with the gap; sweep rate against the
@@ -241,6 +276,7 @@ def main():
                     help="leave out the per-graph comparison of the batched section (shorter kernel traces)")
     ap.add_argument("--density-sweep", default="2,6,12",
                     help="Barabasi-Albert densities of the scalability section (n = 1M; empty: skip)")
+    ap.add_argument("--ltds", default="ltds_hk", help="triangle (LTDS) workload ('' to skip)")
     ap.add_argument("--clique4", default="clique4_pl", help="4-clique FW workload ('' to skip)")
     ap.add_argument("--serve-seconds", type=float, default=5.0, help="arrival window of the serving run (0: skip)")
     ap.add_argument("--serve-qps", type=float, default=200.0)
@@ -347,6 +383,8 @@ def main():
         out["batched"] = bench_batched(lds, torch, synth, np, args.batch_graphs, not args.no_batch_plain)
     if args.density_sweep:
         out["density_sweep"] = bench_density(lds, torch, synth, [int(x) for x in args.density_sweep.split(",")])
+    if args.ltds:
+        out["ltds"] = bench_ltds(lds, torch, synth, args.ltds)
     if args.clique4:
         out["clique4"] = bench_clique4(lds, torch, synth, args.clique4)
     if args.serve_seconds > 0:
