@@ -734,8 +734,11 @@ __global__ __launch_bounds__(kRT) void k_sg_scan(ScanArgs g) {
                                 if (after != before) {
                                     const unsigned long long old = atomicAdd((unsigned long long*)&g.F[p[i]],
                                                                              (unsigned long long)(after - before));
-                                    atomicMax(&g.bmax[p[i] / kFB],
-                                              (long long)(old + (unsigned long long)(after - before)));
+                                    // block maxima only grow (F only grows, bmax only by atomicMax):
+                                    // a read that is at least the new value, even a stale one, makes
+                                    // the atomic redundant
+                                    const long long nv = (long long)(old + (unsigned long long)(after - before));
+                                    if (nv > g.bmax[p[i] / kFB]) atomicMax(&g.bmax[p[i] / kFB], nv);
                                 }
                             } else if (p[i] >= S0 && p[i] < f0) {  // earlier member of S
                                 const int64_t before = pat_contrib<H>(i, p, al, a.D, S0, f0);
