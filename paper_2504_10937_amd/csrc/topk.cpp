@@ -35,6 +35,7 @@
 #include <queue>
 
 #include "batch.hpp"
+#include "pflow.hpp"
 #include "islds.hpp"
 #include "topk.hpp"
 
@@ -62,6 +63,27 @@ inline Frac reduce(int64_t n, int64_t d) {
 }
 
 // ------------------------------------------------------------ max flow
+// Networks with at least this many nodes use the parallel push-relabel
+// (pflow.hpp) on up to 16 host threads; LDS_FLOW_THREADS overrides the
+// thread count (1: always sequential) and LDS_FLOW_PARALLEL_MIN the size.
+int g_flow_threads = 0;            // 0: not read yet
+int64_t g_flow_parallel_min = -1;  // -1: not read yet
+int flow_threads() {
+    if (g_flow_threads == 0) {
+        const char* e = std::getenv("LDS_FLOW_THREADS");
+        const unsigned hc = std::thread::hardware_concurrency();
+        g_flow_threads = (e && *e) ? std::max(1, std::atoi(e)) : (int)std::min(16u, std::max(1u, hc));
+    }
+    return g_flow_threads;
+}
+int64_t flow_parallel_min_nodes() {
+    if (g_flow_parallel_min < 0) {
+        const char* e = std::getenv("LDS_FLOW_PARALLEL_MIN");
+        g_flow_parallel_min = (e && *e) ? (int64_t)std::atoll(e) : (int64_t)65536;
+    }
+    return g_flow_parallel_min;
+}
+
 // Network with arcs in CSR order (arcs of a node are contiguous, each with
 // the index of its reverse arc).  Arcs are collected with arc() and laid out
 // by finalize().
@@ -147,6 +169,23 @@ struct Flow {
     // already reached t; nullptr = start from zero flow
     int64_t maxflow(int64_t s, int64_t t, const std::vector<int64_t>* init_ex = nullptr, int64_t init_t = 0) {
         finalize();
+        const int threads = flow_threads();
+        if (N >= flow_parallel_min_nodes() && threads > 1) {
+            std::vector<int64_t> ex(N, 0);
+            if (init_ex) {
+                for (int64_t v = 0; v < N && v < (int64_t)init_ex->size(); ++v) ex[v] = (*init_ex)[v];
+                ex[t] = init_t;
+            }
+            for (int64_t e = first[s]; e < first[s + 1]; ++e)
+                if (cap[e] > 0) {
+                    const int64_t d = cap[e];
+                    cap[e] = 0;
+                    cap[rev[e]] += d;
+                    ex[to[e]] += d;
+                }
+            ex[s] = 0;
+            return maxflow_parallel(N, first, to, cap, rev, s, t, ex, threads);
+        }
         std::vector<int64_t> h(N, 0), ex(N, 0), it(first.begin(), first.end() - 1);
         if (init_ex) {
             for (int64_t v = 0; v < N && v < (int64_t)init_ex->size(); ++v) ex[v] = (*init_ex)[v];

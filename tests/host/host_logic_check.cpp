@@ -6,6 +6,9 @@
 //     arbitrary splits): the maximum of q*|P(X)| - p*|X| and the union of all
 //     maximisers, by enumeration of every X.
 // (Core and tr-core numbers run on the device; their parity is a GPU test.)
+// The battery runs twice: with the sequential push-relabel and with every
+// network through the parallel one (pflow.hpp); larger random networks then
+// compare the two directly.
 // Prints "ok" and exits 0 when every case agrees.
 #include "../../paper_2504_10937_amd/csrc/topk.cpp"
 
@@ -60,9 +63,10 @@ static int64_t enumerate(int64_t k, int h, const std::vector<int32_t>& pat, cons
     return best;
 }
 
-int main() {
+// every case of the battery, with the current choice of sequential / parallel min cut
+static int battery(int& cases) {
     std::mt19937_64 rng(12345);
-    int bad = 0, cases = 0;
+    int bad = 0;
     for (int it = 0; it < 1500; ++it) {
         const int k = 2 + (int)(rng() % 10);
         const double pe = 0.2 + (double)(rng() % 70) / 100.0;
@@ -120,6 +124,51 @@ int main() {
             if (max_excess(k, 3, full, p, q, X, &sp, D) != enumerate(k, 3, full, {}, p, q, Y) || X != Y) ++bad;
         }
     }
+    return bad;
+}
+
+// larger random networks: the parallel push-relabel against the sequential
+// one (value and maximal maximiser), cold and warm-started
+static int parallel_vs_sequential(int& cases) {
+    std::mt19937_64 rng(777);
+    int bad = 0;
+    for (int it = 0; it < 40; ++it) {
+        const int64_t k = 200 + (int64_t)(rng() % 3000);
+        const int64_t m = k * (2 + (int64_t)(rng() % 6));
+        std::vector<int32_t> pairs;
+        for (int64_t e = 0; e < m; ++e) {
+            const int32_t a = (int32_t)(rng() % k), b = (int32_t)(rng() % k);
+            if (a == b) continue;
+            pairs.push_back(std::min(a, b));
+            pairs.push_back(std::max(a, b));
+        }
+        const int64_t ne = (int64_t)pairs.size() / 2;
+        // density-like parameters around the graph's own density
+        const int64_t q = k, p = ne + (int64_t)(rng() % 7) - 3;
+        const int64_t D = 6 + (int64_t)(rng() % 100);
+        std::vector<uint32_t> sp(ne);
+        for (auto& x : sp) x = (uint32_t)(rng() % (uint64_t)(D + 1));
+        for (int warm = 0; warm < 2; ++warm) {
+            std::vector<char> X, Y;
+            g_flow_parallel_min = 1 << 30;
+            const int64_t a = max_excess_edges(k, pairs, {}, p, q, X, warm ? &sp : nullptr, D);
+            g_flow_parallel_min = 0;
+            const int64_t b = max_excess_edges(k, pairs, {}, p, q, Y, warm ? &sp : nullptr, D);
+            ++cases;
+            if (a != b || X != Y) ++bad;
+        }
+    }
+    return bad;
+}
+
+int main() {
+    int cases = 0, bad = 0;
+    g_flow_threads = 4;
+    g_flow_parallel_min = 1 << 30;  // sequential push-relabel
+    bad += battery(cases);
+    g_flow_parallel_min = 0;  // every network through the parallel one
+    bad += battery(cases);
+    bad += parallel_vs_sequential(cases);
     std::printf("%s: %d of %d cases disagree\n", bad ? "FAIL" : "ok", bad, cases);
     return bad ? 1 : 0;
 }

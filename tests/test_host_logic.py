@@ -19,7 +19,7 @@ def test_host_logic(tmp_path):
     exe = str(tmp_path / "host_logic_check")
     src = os.path.join(HERE, "host", "host_logic_check.cpp")
     cmd = [hipcc if os.path.exists(hipcc) else "hipcc", "-O2", "-std=c++17", "-I" + os.path.join(ROOT, "include"),
-           "-I" + os.path.join(ROOT, "paper_2504_10937_amd", "csrc"), src, "-o", exe]
+           "-I" + os.path.join(ROOT, "paper_2504_10937_amd", "csrc"), "-pthread", src, "-o", exe]
     r = subprocess.run(cmd, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-2000:]
     r = subprocess.run([exe], capture_output=True, text=True, timeout=300)
