@@ -84,6 +84,20 @@ int64_t flow_parallel_min_nodes() {
     return g_flow_parallel_min;
 }
 
+// f(i0, i1) over [0, n) split into one contiguous range per thread
+template <class F>
+void par_for(int64_t n, F f) {
+    const int T = flow_threads();
+    if (T <= 1 || n < 4096) {
+        f((int64_t)0, n);
+        return;
+    }
+    std::vector<std::thread> pool;
+    for (int k = 1; k < T; ++k) pool.emplace_back([&, k] { f(n * k / T, n * (k + 1) / T); });
+    f((int64_t)0, n / T);
+    for (auto& th : pool) th.join();
+}
+
 // Network with arcs in CSR order (arcs of a node are contiguous, each with
 // the index of its reverse arc).  Arcs are collected with arc() and laid out
 // by finalize().
@@ -122,6 +136,19 @@ struct Flow {
     }
     void add(int64_t a, int64_t b, int64_t c, int64_t c_back = 0) {
         const int64_t x = fillp[a]++, y = fillp[b]++;
+        to[x] = (int32_t)b;
+        cap[x] = c;
+        rev[x] = y;
+        to[y] = (int32_t)a;
+        cap[y] = c_back;
+        rev[y] = x;
+    }
+    // add() from several threads at once: arc positions by atomic increments
+    // (the order of a node's arcs then varies; the flow value and the minimum
+    // cuts do not depend on it)
+    void add_atomic(int64_t a, int64_t b, int64_t c, int64_t c_back) {
+        const int64_t x = __atomic_fetch_add(&fillp[a], 1, __ATOMIC_RELAXED);
+        const int64_t y = __atomic_fetch_add(&fillp[b], 1, __ATOMIC_RELAXED);
         to[x] = (int32_t)b;
         cap[x] = c;
         rev[x] = y;
@@ -315,11 +342,20 @@ int64_t max_excess_edges(int64_t k, const std::vector<int32_t>& pairs, const std
                          int64_t q, std::vector<char>& inX, const std::vector<uint32_t>* split = nullptr,
                          int64_t D = 1) {
     const int64_t ne = (int64_t)pairs.size() / 2;
+    // large networks are built by several threads (atomic counts and arc slots)
+    const bool par = k + 2 >= flow_parallel_min_nodes() && flow_threads() > 1;
     std::vector<int64_t> w(k, 0), deg(k, 0);
-    for (int64_t v = 0; v < k; ++v) w[v] = loops.empty() ? 0 : 2 * loops[v];
-    for (int64_t i = 0; i < 2 * ne; ++i) {
-        w[pairs[i]]++;
-        deg[pairs[i]]++;
+    if (par) {
+        par_for(2 * ne, [&](int64_t i0, int64_t i1) {
+            for (int64_t i = i0; i < i1; ++i) __atomic_fetch_add(&deg[pairs[i]], 1, __ATOMIC_RELAXED);
+        });
+        for (int64_t v = 0; v < k; ++v) w[v] = (loops.empty() ? 0 : 2 * loops[v]) + deg[v];
+    } else {
+        for (int64_t v = 0; v < k; ++v) w[v] = loops.empty() ? 0 : 2 * loops[v];
+        for (int64_t i = 0; i < 2 * ne; ++i) {
+            w[pairs[i]]++;
+            deg[pairs[i]]++;
+        }
     }
     int64_t wsum = 0;
     for (int64_t v = 0; v < k; ++v) wsum += w[v];
@@ -339,12 +375,21 @@ int64_t max_excess_edges(int64_t k, const std::vector<int32_t>& pairs, const std
         f.begin(arcs);
     }
     std::vector<int64_t> A(warm ? k : 0, 0), ex;
-    if (warm)
+    if (warm && par) {
+        par_for(ne, [&](int64_t i0, int64_t i1) {
+            for (int64_t i = i0; i < i1; ++i) {
+                const int64_t a = (*split)[i];
+                __atomic_fetch_add(&A[pairs[2 * i]], a, __ATOMIC_RELAXED);
+                __atomic_fetch_add(&A[pairs[2 * i + 1]], D - a, __ATOMIC_RELAXED);
+            }
+        });
+    } else if (warm) {
         for (int64_t i = 0; i < ne; ++i) {
             const int64_t a = (*split)[i];
             A[pairs[2 * i]] += a;
             A[pairs[2 * i + 1]] += D - a;
         }
+    }
     int64_t total = 0, to_t = 0;
     if (warm) ex.assign(k + 2, 0);
     for (int64_t v = 0; v < k; ++v) {
@@ -364,14 +409,24 @@ int64_t max_excess_edges(int64_t k, const std::vector<int32_t>& pairs, const std
         }
         total += q * w[v] * sc;
     }
-    for (int64_t i = 0; i < ne; ++i) {
-        if (warm) {
-            const int64_t fl = q * (D - 2 * (int64_t)(*split)[i]);  // net flow first -> second
-            f.add(pairs[2 * i], pairs[2 * i + 1], q * D - fl, q * D + fl);
-        } else {
-            f.add(pairs[2 * i], pairs[2 * i + 1], q, q);
+    auto edge_arcs = [&](int64_t i0, int64_t i1, bool atomic) {
+        for (int64_t i = i0; i < i1; ++i) {
+            int64_t c = q, cb = q;
+            if (warm) {
+                const int64_t fl = q * (D - 2 * (int64_t)(*split)[i]);  // net flow first -> second
+                c = q * D - fl;
+                cb = q * D + fl;
+            }
+            if (atomic)
+                f.add_atomic(pairs[2 * i], pairs[2 * i + 1], c, cb);
+            else
+                f.add(pairs[2 * i], pairs[2 * i + 1], c, cb);
         }
-    }
+    };
+    if (par)
+        par_for(ne, [&](int64_t i0, int64_t i1) { edge_arcs(i0, i1, true); });
+    else
+        edge_arcs(0, ne, false);
     const int64_t flow = warm ? f.maxflow(S, T, &ex, to_t) : f.maxflow(S, T);
     const std::vector<char> side = f.maximal_source_side(T);
     inX.assign(k, 0);
