@@ -595,33 +595,60 @@ void induced_patterns(Ctx& c, const std::vector<int32_t>& vs, std::vector<int32_
     pat.clear();
     if (split) split->clear();
     for (size_t i = 0; i < vs.size(); ++i) c.loc[vs[i]] = (int32_t)i;
-    if (c.mode == 2) {
-        for (size_t i = 0; i < vs.size(); ++i)
-            for (int64_t s = h.rp[vs[i]]; s < h.rp[vs[i] + 1]; ++s) {
-                const int32_t j = c.loc[h.col[s]];
-                if (j > (int32_t)i) {
-                    pat.push_back((int32_t)i);
-                    pat.push_back(j);
-                    if (split) split->push_back(c.split[s]);
+    // the patterns whose first (edges) / smallest (triangles) local index is in [i0, i1)
+    auto range = [&](int64_t i0, int64_t i1, std::vector<int32_t>& P, std::vector<uint32_t>* Sp) {
+        if (c.mode == 2) {
+            for (int64_t i = i0; i < i1; ++i)
+                for (int64_t s = h.rp[vs[i]]; s < h.rp[vs[i] + 1]; ++s) {
+                    const int32_t j = c.loc[h.col[s]];
+                    if (j > (int32_t)i) {
+                        P.push_back((int32_t)i);
+                        P.push_back(j);
+                        if (Sp) Sp->push_back(c.split[s]);
+                    }
                 }
-            }
+        } else {
+            for (int64_t i = i0; i < i1; ++i)
+                for (int64_t q = h.trp[vs[i]]; q < h.trp[vs[i] + 1]; ++q) {
+                    const int32_t* x = &h.tri[3 * h.tinc[q]];
+                    const int32_t a = c.loc[x[0]], b = c.loc[x[1]], d = c.loc[x[2]];
+                    if (a < 0 || b < 0 || d < 0) continue;
+                    if (std::min(a, std::min(b, d)) != (int32_t)i) continue;  // count each triangle once
+                    P.push_back(a);
+                    P.push_back(b);
+                    P.push_back(d);
+                    if (Sp) {
+                        const int64_t t = h.tinc[q];
+                        Sp->push_back(c.split[3 * t]);
+                        Sp->push_back(c.split[3 * t + 1]);
+                        Sp->push_back(c.split[3 * t + 2]);
+                    }
+                }
+        }
+    };
+    const int64_t k = (int64_t)vs.size();
+    const int T = flow_threads();
+    if (k < flow_parallel_min_nodes() || T <= 1) {
+        range(0, k, pat, split);
     } else {
-        for (size_t i = 0; i < vs.size(); ++i)
-            for (int64_t q = h.trp[vs[i]]; q < h.trp[vs[i] + 1]; ++q) {
-                const int32_t* x = &h.tri[3 * h.tinc[q]];
-                const int32_t a = c.loc[x[0]], b = c.loc[x[1]], d = c.loc[x[2]];
-                if (a < 0 || b < 0 || d < 0) continue;
-                if (std::min(a, std::min(b, d)) != (int32_t)i) continue;  // count each triangle once
-                pat.push_back(a);
-                pat.push_back(b);
-                pat.push_back(d);
-                if (split) {
-                    const int64_t t = h.tinc[q];
-                    split->push_back(c.split[3 * t]);
-                    split->push_back(c.split[3 * t + 1]);
-                    split->push_back(c.split[3 * t + 2]);
-                }
-            }
+        // contiguous ranges per thread, concatenated in order: the same list
+        std::vector<std::vector<int32_t>> P(T);
+        std::vector<std::vector<uint32_t>> Sp(T);
+        std::vector<std::thread> pool;
+        for (int t = 0; t < T; ++t)
+            pool.emplace_back([&, t] { range(k * t / T, k * (t + 1) / T, P[t], split ? &Sp[t] : nullptr); });
+        for (auto& th : pool) th.join();
+        size_t np = 0, ns = 0;
+        for (int t = 0; t < T; ++t) {
+            np += P[t].size();
+            ns += Sp[t].size();
+        }
+        pat.reserve(np);
+        if (split) split->reserve(ns);
+        for (int t = 0; t < T; ++t) {
+            pat.insert(pat.end(), P[t].begin(), P[t].end());
+            if (split) split->insert(split->end(), Sp[t].begin(), Sp[t].end());
+        }
     }
     for (int32_t v : vs) c.loc[v] = -1;
 }
