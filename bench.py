@@ -125,6 +125,26 @@ def bench_density(lds, torch, synth, densities):
     return res
 
 
+def bench_topk(lds, torch, synth, names):
+    """LDScvx / LTDScvx end to end (lds_topk with the workload's k and N) from
+    the resident edge list of the large edge workload and the LTDS workload."""
+    res = {}
+    for name in names:
+        n, s, t, mode, iters, k = synth.workload(name)
+        ts, tt = torch.from_numpy(s).cuda(), torch.from_numpy(t).cuda()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = lds.lds_create_graph(n, ts, tt)
+        sets, st = lds.lds_topk(g, mode, k, iters, with_stats=True)
+        t1 = time.perf_counter()
+        g.destroy()
+        res[name] = {"k": k, "fw_iters": iters, "mode": "edge" if mode == 2 else "triangle", "seconds": t1 - t0,
+                     "found": len(sets), "top_density": str(sets[0][1]) if sets else None,
+                     "stats": {x: (round(v, 1) if isinstance(v, float) else v) for x, v in st.items()}}
+        log("topk %s: %.2f s, %d sets" % (name, t1 - t0, len(sets)))
+    return res
+
+
 def bench_ltds(lds, torch, synth, name):
     """The triangle program (Eq. trcp, Alg. 6) on the LTDS workload: device
     triangle listing, N exact FW iterations with the gap, sort / prefix /
@@ -277,6 +297,7 @@ def main():
     ap.add_argument("--density-sweep", default="2,6,12",
                     help="Barabasi-Albert densities of the scalability section (n = 1M; empty: skip)")
     ap.add_argument("--ltds", default="ltds_hk", help="triangle (LTDS) workload ('' to skip)")
+    ap.add_argument("--topk", default="lds_large,ltds_hk", help="workloads timed end to end by lds_topk ('' to skip)")
     ap.add_argument("--clique4", default="clique4_pl", help="4-clique FW workload ('' to skip)")
     ap.add_argument("--serve-seconds", type=float, default=5.0, help="arrival window of the serving run (0: skip)")
     ap.add_argument("--serve-qps", type=float, default=200.0)
@@ -385,6 +406,8 @@ def main():
         out["density_sweep"] = bench_density(lds, torch, synth, [int(x) for x in args.density_sweep.split(",")])
     if args.ltds:
         out["ltds"] = bench_ltds(lds, torch, synth, args.ltds)
+    if args.topk:
+        out["topk"] = bench_topk(lds, torch, synth, args.topk.split(","))
     if args.clique4:
         out["clique4"] = bench_clique4(lds, torch, synth, args.clique4)
     if args.serve_seconds > 0:
