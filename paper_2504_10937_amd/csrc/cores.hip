@@ -135,6 +135,116 @@ __global__ void k_compact(const int32_t* active, int32_t na, const int32_t* core
 
 __global__ void k_set(int32_t* p, int32_t v) { *p = v; }
 
+// The rest of the peeling in one workgroup once few vertices remain (small
+// graphs from the start, the dense cores of large ones, the residual graphs of
+// Pruning rule 2): the same levels, frontiers and cascades, separated by
+// workgroup barriers instead of host round trips.  Every level assigns a
+// vertex or jumps to a larger count, so the loops are bounded by the number
+// of remaining vertices; a bound that is ever reached raises err.
+constexpr int kTailT = 1024;
+constexpr int32_t kTailMax = 1 << 13;
+
+template <bool TRI>
+__global__ __launch_bounds__(kTailT) void k_peel_tail(int32_t* act, int32_t* act2, int32_t na, int32_t k,
+                                                      int32_t* front, int32_t* next, const int64_t* rowptr,
+                                                      const int32_t* col, const int32_t* row_of, const int64_t* rp,
+                                                      const int32_t* py, const int32_t* tos, uint32_t* talive,
+                                                      int32_t* cnt, int32_t* core, int32_t* err) {
+    __shared__ int32_t sc[4];  // [0] frontier, [1] next, [2] minimum, [3] remaining
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t bound = 2 * (int64_t)na + 2;
+    for (int64_t it = 0; na > 0; ++it) {
+        if (it > bound) {
+            if (tid == 0) *err = 1;
+            return;
+        }
+        if (tid == 0) sc[0] = 0;
+        __syncthreads();
+        for (int32_t i = tid; i < na; i += kTailT) {
+            const int32_t v = act[i];
+            if (core[v] == kUnset && cnt[v] <= k) {
+                core[v] = k;
+                front[atomicAdd(&sc[0], 1)] = v;
+            }
+        }
+        __syncthreads();
+        int32_t fc = sc[0];
+        if (fc == 0) {  // jump to the smallest remaining count
+            if (tid == 0) sc[2] = INT32_MAX;
+            __syncthreads();
+            for (int32_t i = tid; i < na; i += kTailT) {
+                const int32_t v = act[i];
+                if (core[v] == kUnset) atomicMin(&sc[2], cnt[v]);
+            }
+            __syncthreads();
+            const int32_t m = sc[2];
+            __syncthreads();
+            if (m == INT32_MAX || m <= k) {
+                if (tid == 0) *err = 1;
+                return;
+            }
+            k = m;
+            continue;
+        }
+        int32_t* f = front;
+        int32_t* nx = next;
+        for (int64_t round = 0; fc > 0; ++round) {
+            if (round > na) {
+                if (tid == 0) *err = 1;
+                return;
+            }
+            if (tid == 0) sc[1] = 0;
+            __syncthreads();
+            for (int32_t i = wv; i < fc; i += kTailT / 64) {
+                const int32_t v = f[i];
+                if (!TRI) {
+                    for (int64_t q = rowptr[v] + lane; q < rowptr[v + 1]; q += 64) {
+                        const int32_t w = col[q];
+                        if (core[w] != kUnset) continue;
+                        if (atomicSub(&cnt[w], 1) == k + 1) {
+                            core[w] = k;
+                            nx[atomicAdd(&sc[1], 1)] = w;
+                        }
+                    }
+                } else {
+                    const int32_t r = row_of[v];
+                    if (r < 0) continue;
+                    for (int64_t q = rp[r] + lane; q < rp[r + 1]; q += 64) {
+                        if (atomicExch(&talive[tos[q]], 0u) == 0u) continue;
+                        for (int j = 0; j < 2; ++j) {
+                            const int32_t w = py[2 * q + j];
+                            if (core[w] != kUnset) continue;
+                            if (atomicSub(&cnt[w], 1) == k + 1) {
+                                core[w] = k;
+                                nx[atomicAdd(&sc[1], 1)] = w;
+                            }
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            fc = sc[1];
+            int32_t* tmp = f;
+            f = nx;
+            nx = tmp;
+            __syncthreads();
+        }
+        if (tid == 0) sc[3] = 0;
+        __syncthreads();
+        for (int32_t i = tid; i < na; i += kTailT) {
+            const int32_t v = act[i];
+            if (core[v] == kUnset) act2[atomicAdd(&sc[3], 1)] = v;
+        }
+        __syncthreads();
+        na = sc[3];
+        int32_t* tmp = act;
+        act = act2;
+        act2 = tmp;
+        ++k;
+        __syncthreads();
+    }
+}
+
 __global__ void k_alive_internal(const uint8_t* by_caller, const int32_t* orig_of, int64_t n, uint8_t* by_internal) {
     const int64_t v = (int64_t)blockIdx.x * kT + threadIdx.x;
     if (v < n) by_internal[v] = by_caller[orig_of[v]] ? 1 : 0;
@@ -182,6 +292,20 @@ void core_numbers_gpu(Graph& g, int mode, const uint8_t* alive, int32_t* core, h
     int32_t na = d2h_i32(ctr.p, s);
     int32_t k = 0;
     while (na > 0) {
+        if (na <= kTailMax) {  // the rest in one workgroup, no host round trips
+            k_set<<<1, 1, 0, s>>>(ctr.p + 3, 0);
+            if (mode == 2)
+                k_peel_tail<false><<<1, kTailT, 0, s>>>(act.p, act2.p, na, k, front.p, next.p, g.rowptr.p, g.col.p,
+                                                        nullptr, nullptr, nullptr, nullptr, nullptr, cnt.p, core,
+                                                        ctr.p + 3);
+            else
+                k_peel_tail<true><<<1, kTailT, 0, s>>>(act.p, act2.p, na, k, front.p, next.p, nullptr, nullptr,
+                                                       tp.own_row_of.p, tp.rp, tp.py, tp.own_tos.p, talive.p, cnt.p,
+                                                       core, ctr.p + 3);
+            LDS_HIP(hipGetLastError());
+            LDS_CHECK(d2h_i32(ctr.p + 3, s) == 0, ST_DEVICE, "core peeling: no progress");
+            break;
+        }
         k_set<<<1, 1, 0, s>>>(ctr.p + 1, 0);
         k_frontier<<<grid_for(na, kT), kT, 0, s>>>(act.p, na, cnt.p, core, k, front.p, ctr.p + 1);
         LDS_HIP(hipGetLastError());
