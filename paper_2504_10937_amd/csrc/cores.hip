@@ -68,15 +68,42 @@ __global__ void k_init_triangles(const int32_t* tri, int64_t T, const uint8_t* a
     }
 }
 
+// Device-side counters of the level loop, read by the kernels themselves so
+// that a level's kernels are queued without host round trips (grid-stride
+// loops over counts held in memory).
+enum : int { C_NA = 0, C_F0 = 1, C_F1 = 2, C_K = 3, C_MIN = 4, C_NA2 = 5 };
+
+__global__ void k_level_begin(int32_t* ctr) {
+    ctr[C_MIN] = INT32_MAX;
+    ctr[C_F0] = 0;
+    ctr[C_NA2] = 0;
+}
+
+// smallest count among the remaining vertices
+__global__ void k_min_remaining(const int32_t* active, int32_t* ctr, const int32_t* cnt) {
+    const int32_t na = ctr[C_NA];
+    int32_t m = INT32_MAX;
+    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < na; i += (int64_t)gridDim.x * kT)
+        m = min(m, cnt[active[i]]);
+    for (int o = 32; o > 0; o >>= 1) m = min(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0 && m != INT32_MAX) atomicMin(&ctr[C_MIN], m);
+}
+
+// the level: k, or the smallest remaining count when no vertex is at or below k
+__global__ void k_set_level(int32_t* ctr) {
+    const int32_t m = ctr[C_MIN];
+    if (m != INT32_MAX && m > ctr[C_K]) ctr[C_K] = m;
+}
+
 // remaining vertices with cnt <= k: core k, into the frontier
-__global__ void k_frontier(const int32_t* active, int32_t na, const int32_t* cnt, int32_t* core, int32_t k,
-                           int32_t* front, int32_t* fc) {
-    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
-    if (i >= na) return;
-    const int32_t v = active[i];
-    if (core[v] == kUnset && cnt[v] <= k) {
-        core[v] = k;
-        push(front, fc, v);
+__global__ void k_frontier(const int32_t* active, int32_t* ctr, const int32_t* cnt, int32_t* core, int32_t* front) {
+    const int32_t na = ctr[C_NA], k = ctr[C_K];
+    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < na; i += (int64_t)gridDim.x * kT) {
+        const int32_t v = active[i];
+        if (core[v] == kUnset && cnt[v] <= k) {
+            core[v] = k;
+            push(front, &ctr[C_F0], v);
+        }
     }
 }
 
@@ -89,51 +116,48 @@ __device__ inline void lower(int32_t* cnt, int32_t* core, int32_t w, int32_t k, 
     }
 }
 
-// one wave per frontier vertex
-__global__ void k_peel_edges(const int32_t* front, int32_t fc, const int64_t* rowptr, const int32_t* col,
-                             int32_t* cnt, int32_t* core, int32_t k, int32_t* next, int32_t* nc) {
+// one wave per frontier vertex; fc / nc are counters in memory
+__global__ void k_peel_edges(const int32_t* front, const int32_t* fcp, const int64_t* rowptr, const int32_t* col,
+                             int32_t* cnt, int32_t* core, const int32_t* ctr, int32_t* next, int32_t* ncp) {
     const int lane = threadIdx.x & 63;
-    const int64_t i = (int64_t)blockIdx.x * (kT / 64) + (threadIdx.x >> 6);
-    if (i >= fc) return;
-    const int32_t v = front[i];
-    for (int64_t s = rowptr[v] + lane; s < rowptr[v + 1]; s += 64) lower(cnt, core, col[s], k, next, nc);
+    const int32_t fc = *fcp, k = ctr[C_K];
+    for (int64_t i = (int64_t)blockIdx.x * (kT / 64) + (threadIdx.x >> 6); i < fc; i += (int64_t)gridDim.x * (kT / 64)) {
+        const int32_t v = front[i];
+        for (int64_t s = rowptr[v] + lane; s < rowptr[v + 1]; s += 64) lower(cnt, core, col[s], k, next, ncp);
+    }
 }
 
-__global__ void k_peel_triangles(const int32_t* front, int32_t fc, const int32_t* row_of, const int64_t* rp,
+__global__ void k_peel_triangles(const int32_t* front, const int32_t* fcp, const int32_t* row_of, const int64_t* rp,
                                  const int32_t* py, const int32_t* tos, uint32_t* talive, int32_t* cnt,
-                                 int32_t* core, int32_t k, int32_t* next, int32_t* nc) {
+                                 int32_t* core, const int32_t* ctr, int32_t* next, int32_t* ncp) {
     const int lane = threadIdx.x & 63;
-    const int64_t i = (int64_t)blockIdx.x * (kT / 64) + (threadIdx.x >> 6);
-    if (i >= fc) return;
-    const int32_t r = row_of[front[i]];
-    if (r < 0) return;
-    for (int64_t s = rp[r] + lane; s < rp[r + 1]; s += 64) {
-        if (atomicExch(&talive[tos[s]], 0u) == 0u) continue;  // killed before
-        lower(cnt, core, py[2 * s], k, next, nc);
-        lower(cnt, core, py[2 * s + 1], k, next, nc);
+    const int32_t fc = *fcp, k = ctr[C_K];
+    for (int64_t i = (int64_t)blockIdx.x * (kT / 64) + (threadIdx.x >> 6); i < fc; i += (int64_t)gridDim.x * (kT / 64)) {
+        const int32_t r = row_of[front[i]];
+        if (r < 0) continue;
+        for (int64_t s = rp[r] + lane; s < rp[r + 1]; s += 64) {
+            if (atomicExch(&talive[tos[s]], 0u) == 0u) continue;  // killed before
+            lower(cnt, core, py[2 * s], k, next, ncp);
+            lower(cnt, core, py[2 * s + 1], k, next, ncp);
+        }
     }
 }
 
-__global__ void k_min_remaining(const int32_t* active, int32_t na, const int32_t* cnt, const int32_t* core,
-                                int32_t* out) {
-    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
-    int32_t m = INT32_MAX;
-    if (i < na) {
+__global__ void k_compact(const int32_t* active, int32_t* ctr, const int32_t* core, int32_t* out) {
+    const int32_t na = ctr[C_NA];
+    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < na; i += (int64_t)gridDim.x * kT) {
         const int32_t v = active[i];
-        if (core[v] == kUnset) m = cnt[v];
+        if (core[v] == kUnset) push(out, &ctr[C_NA2], v);
     }
-    for (int o = 32; o > 0; o >>= 1) m = min(m, __shfl_xor(m, o, 64));
-    if ((threadIdx.x & 63) == 0 && m != INT32_MAX) atomicMin(out, m);
 }
 
-__global__ void k_compact(const int32_t* active, int32_t na, const int32_t* core, int32_t* out, int32_t* nout) {
-    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
-    if (i >= na) return;
-    const int32_t v = active[i];
-    if (core[v] == kUnset) push(out, nout, v);
+__global__ void k_level_end(int32_t* ctr) {
+    ctr[C_NA] = ctr[C_NA2];
+    ctr[C_K] += 1;
 }
 
 __global__ void k_set(int32_t* p, int32_t v) { *p = v; }
+__global__ void k_fill8(int32_t* p) { p[threadIdx.x] = 0; }
 
 // The rest of the peeling in one workgroup once few vertices remain (small
 // graphs from the start, the dense cores of large ones, the residual graphs of
@@ -276,8 +300,8 @@ void core_numbers_gpu(Graph& g, int mode, const uint8_t* alive, int32_t* core, h
     act2.alloc(n, s);
     front.alloc(n, s);
     next.alloc(n, s);
-    ctr.alloc(4, s);  // [0] active count, [1] frontier count, [2] next count, [3] minimum
-    k_set<<<1, 1, 0, s>>>(ctr.p, 0);
+    ctr.alloc(8, s);  // C_* counters; [7] error flag of the one-workgroup tail
+    k_fill8<<<1, 8, 0, s>>>(ctr.p);
     if (mode == 2) {
         k_init_edges<<<grid_for(n, kT), kT, 0, s>>>(g.rowptr.p, g.col.p, n, alive, cnt.p, core, act.p, ctr.p);
     } else {
@@ -289,55 +313,61 @@ void core_numbers_gpu(Graph& g, int mode, const uint8_t* alive, int32_t* core, h
     }
     LDS_HIP(hipGetLastError());
     const SweepPlan& tp = g.tri_plan;
-    int32_t na = d2h_i32(ctr.p, s);
-    int32_t k = 0;
-    while (na > 0) {
+    // levels: one host read at the start of a level and one per four cascade
+    // rounds; the rest of a level is queued without waiting
+    const unsigned ge = std::min<unsigned>(grid_for(n, kT), 2048u);       // element loops
+    const unsigned gw = std::min<unsigned>(grid_for(n, kT / 64), 4096u);  // one wave per vertex
+    int32_t* fr[2] = {front.p, next.p};
+    int32_t h[8];
+    auto read_ctr = [&]() {
+        LDS_HIP(hipMemcpyAsync(h, ctr.p, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        LDS_HIP(hipStreamSynchronize(s));
+    };
+    for (int64_t level = 0;; ++level) {
+        read_ctr();
+        const int32_t na = h[C_NA], k = h[C_K];
+        if (na == 0) break;
+        LDS_CHECK(level <= n, ST_DEVICE, "core peeling: no progress");
         if (na <= kTailMax) {  // the rest in one workgroup, no host round trips
-            k_set<<<1, 1, 0, s>>>(ctr.p + 3, 0);
+            k_set<<<1, 1, 0, s>>>(ctr.p + 7, 0);
             if (mode == 2)
                 k_peel_tail<false><<<1, kTailT, 0, s>>>(act.p, act2.p, na, k, front.p, next.p, g.rowptr.p, g.col.p,
                                                         nullptr, nullptr, nullptr, nullptr, nullptr, cnt.p, core,
-                                                        ctr.p + 3);
+                                                        ctr.p + 7);
             else
                 k_peel_tail<true><<<1, kTailT, 0, s>>>(act.p, act2.p, na, k, front.p, next.p, nullptr, nullptr,
                                                        tp.own_row_of.p, tp.rp, tp.py, tp.own_tos.p, talive.p, cnt.p,
-                                                       core, ctr.p + 3);
+                                                       core, ctr.p + 7);
             LDS_HIP(hipGetLastError());
-            LDS_CHECK(d2h_i32(ctr.p + 3, s) == 0, ST_DEVICE, "core peeling: no progress");
+            LDS_CHECK(d2h_i32(ctr.p + 7, s) == 0, ST_DEVICE, "core peeling: no progress");
             break;
         }
-        k_set<<<1, 1, 0, s>>>(ctr.p + 1, 0);
-        k_frontier<<<grid_for(na, kT), kT, 0, s>>>(act.p, na, cnt.p, core, k, front.p, ctr.p + 1);
+        k_level_begin<<<1, 1, 0, s>>>(ctr.p);
+        k_min_remaining<<<ge, kT, 0, s>>>(act.p, ctr.p, cnt.p);
+        k_set_level<<<1, 1, 0, s>>>(ctr.p);
+        k_frontier<<<ge, kT, 0, s>>>(act.p, ctr.p, cnt.p, core, fr[0]);
         LDS_HIP(hipGetLastError());
-        int32_t fc = d2h_i32(ctr.p + 1, s);
-        if (fc == 0) {  // nothing at this level: jump to the smallest remaining count
-            k_set<<<1, 1, 0, s>>>(ctr.p + 3, INT32_MAX);
-            k_min_remaining<<<grid_for(na, kT), kT, 0, s>>>(act.p, na, cnt.p, core, ctr.p + 3);
-            LDS_HIP(hipGetLastError());
-            const int32_t m = d2h_i32(ctr.p + 3, s);
-            LDS_CHECK(m != INT32_MAX && m > k, ST_DEVICE, "core peeling: no progress");
-            k = m;
-            continue;
+        for (int64_t r = 0;;) {
+            for (int j = 0; j < 4; ++j, ++r) {
+                const int cur = (int)(r & 1), nx = cur ^ 1;
+                k_set<<<1, 1, 0, s>>>(ctr.p + C_F0 + nx, 0);
+                if (mode == 2)
+                    k_peel_edges<<<gw, kT, 0, s>>>(fr[cur], ctr.p + C_F0 + cur, g.rowptr.p, g.col.p, cnt.p, core,
+                                                   ctr.p, fr[nx], ctr.p + C_F0 + nx);
+                else
+                    k_peel_triangles<<<gw, kT, 0, s>>>(fr[cur], ctr.p + C_F0 + cur, tp.own_row_of.p, tp.rp, tp.py,
+                                                       tp.own_tos.p, talive.p, cnt.p, core, ctr.p, fr[nx],
+                                                       ctr.p + C_F0 + nx);
+                LDS_HIP(hipGetLastError());
+            }
+            read_ctr();
+            if (h[C_F0 + (int)(r & 1)] == 0) break;  // the frontier the next round would take
+            LDS_CHECK(r <= (int64_t)na + 8, ST_DEVICE, "core peeling: no progress");
         }
-        while (fc > 0) {
-            k_set<<<1, 1, 0, s>>>(ctr.p + 2, 0);
-            if (mode == 2)
-                k_peel_edges<<<grid_for(fc, kT / 64), kT, 0, s>>>(front.p, fc, g.rowptr.p, g.col.p, cnt.p, core, k,
-                                                                 next.p, ctr.p + 2);
-            else
-                k_peel_triangles<<<grid_for(fc, kT / 64), kT, 0, s>>>(front.p, fc, tp.own_row_of.p, tp.rp, tp.py,
-                                                                     tp.own_tos.p, talive.p, cnt.p, core, k,
-                                                                     next.p, ctr.p + 2);
-            LDS_HIP(hipGetLastError());
-            fc = d2h_i32(ctr.p + 2, s);
-            std::swap(front.p, next.p);
-        }
-        k_set<<<1, 1, 0, s>>>(ctr.p, 0);
-        k_compact<<<grid_for(na, kT), kT, 0, s>>>(act.p, na, core, act2.p, ctr.p);
+        k_compact<<<ge, kT, 0, s>>>(act.p, ctr.p, core, act2.p);
+        k_level_end<<<1, 1, 0, s>>>(ctr.p);
         LDS_HIP(hipGetLastError());
-        na = d2h_i32(ctr.p, s);
         std::swap(act.p, act2.p);
-        ++k;
     }
 }
 
