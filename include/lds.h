@@ -115,8 +115,8 @@ lds_status lds_cliques4(lds_graph g, int64_t* n_cliques, int32_t* q_out, int64_t
  *   gap_out  host double[iters]: FW duality gap at r^(i-1), i = 1..iters,
  *            2 (sum_u r_u^2 - sum_patterns min_{u in p} r_u), evaluated
  *            from exact integer sums
- * The state (loads, splits) stays on the device for lds_splits /
- * lds_extract.  Returns LDS_E_OVERFLOW if a numerator could exceed the
+ * The state (loads, splits) stays on the device for lds_loads, lds_splits,
+ * lds_sort_prefix, lds_stable_groups and lds_topk.  Returns LDS_E_OVERFLOW if a numerator could exceed the
  * 64-bit packed key (max degree (resp. triangle or 4-clique count) times the
  * largest per-vertex increment). */
 lds_status lds_frank_wolfe(lds_graph g, lds_mode mode, int32_t iters, float* r_out, double* r64_out,
