@@ -22,12 +22,16 @@
 #pragma once
 #include <algorithm>
 #include <atomic>
+#include <condition_variable>
 #include <cstdint>
+#include <mutex>
 #include <thread>
 #include <vector>
 
 namespace lds {
 
+// Barrier of the pulse threads: a short spin, then a blocking wait, so that a
+// thread preempted by other work in the process does not stall the others.
 class PulseBarrier {
 public:
     explicit PulseBarrier(int n) : n_(n) {}
@@ -35,15 +39,26 @@ public:
         const int gen = gen_.load(std::memory_order_acquire);
         if (count_.fetch_add(1, std::memory_order_acq_rel) == n_ - 1) {
             count_.store(0, std::memory_order_relaxed);
-            gen_.fetch_add(1, std::memory_order_acq_rel);
-        } else {
-            while (gen_.load(std::memory_order_acquire) == gen) std::this_thread::yield();
+            {
+                std::lock_guard<std::mutex> lk(mu_);
+                gen_.fetch_add(1, std::memory_order_acq_rel);
+            }
+            cv_.notify_all();
+            return;
         }
+        for (int i = 0; i < 2000; ++i) {
+            if (gen_.load(std::memory_order_acquire) != gen) return;
+            if (i >= 64) std::this_thread::yield();
+        }
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_.wait(lk, [&] { return gen_.load(std::memory_order_acquire) != gen; });
     }
 
 private:
     const int n_;
     std::atomic<int> count_{0}, gen_{0};
+    std::mutex mu_;
+    std::condition_variable cv_;
 };
 
 // ex: excess per node on entry (source arcs already saturated, ex[s] = 0,

@@ -220,6 +220,7 @@ struct Server::Impl {
 
     void worker() {
         (void)hipSetDevice(device);
+        topk_single_thread(true);  // the other workers use the other cores
         hipStream_t s = nullptr;
         if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) s = nullptr;
         for (;;) {

@@ -28,6 +28,7 @@
 //  * The search ends when the best remaining upper bound is below the k-th
 //    density found; results are sorted by (density desc, smallest caller id).
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
@@ -63,7 +64,8 @@ inline Frac reduce(int64_t n, int64_t d) {
 }
 
 // ------------------------------------------------------------ max flow
-// Networks with at least this many nodes use the parallel push-relabel
+// Networks with at least this many nodes (2^19: below it the sequential one is
+// fast enough, and serving runs several searches at once) use the parallel push-relabel
 // (pflow.hpp) on up to 16 host threads; LDS_FLOW_THREADS overrides the
 // thread count (1: always sequential) and LDS_FLOW_PARALLEL_MIN the size.
 int g_flow_threads = 0;            // 0: not read yet
@@ -79,15 +81,41 @@ int flow_threads() {
 int64_t flow_parallel_min_nodes() {
     if (g_flow_parallel_min < 0) {
         const char* e = std::getenv("LDS_FLOW_PARALLEL_MIN");
-        g_flow_parallel_min = (e && *e) ? (int64_t)std::atoll(e) : (int64_t)65536;
+        g_flow_parallel_min = (e && *e) ? (int64_t)std::atoll(e) : (int64_t)1 << 19;
     }
     return g_flow_parallel_min;
 }
 
-// f(i0, i1) over [0, n) split into one contiguous range per thread
+// Host threads for the large min cuts are shared by every top-k search in the
+// process (the serving workers run several at once): a search takes what is
+// free of the flow_threads() budget and runs sequentially when fewer than two
+// threads are free, so the threads in use never exceed the budget.
+std::atomic<int> g_threads_busy{0};
+struct ThreadGrant {
+    int n = 1;
+    explicit ThreadGrant(int want) {
+        if (topk_threads_single()) return;  // a serving worker: its peers use the other cores
+        const int cap = flow_threads();
+        int cur = g_threads_busy.load();
+        for (;;) {
+            const int take = std::min(want, cap - cur);
+            if (take < 2) return;  // n = 1: sequential
+            if (g_threads_busy.compare_exchange_weak(cur, cur + take)) {
+                n = take;
+                return;
+            }
+        }
+    }
+    ~ThreadGrant() {
+        if (n > 1) g_threads_busy.fetch_sub(n);
+    }
+};
+
+// f(i0, i1) over [0, n) split into one contiguous range per granted thread
 template <class F>
 void par_for(int64_t n, F f) {
-    const int T = flow_threads();
+    ThreadGrant grant(flow_threads());
+    const int T = grant.n;
     if (T <= 1 || n < 4096) {
         f((int64_t)0, n);
         return;
@@ -196,8 +224,9 @@ struct Flow {
     // already reached t; nullptr = start from zero flow
     int64_t maxflow(int64_t s, int64_t t, const std::vector<int64_t>* init_ex = nullptr, int64_t init_t = 0) {
         finalize();
-        const int threads = flow_threads();
-        if (N >= flow_parallel_min_nodes() && threads > 1) {
+        ThreadGrant grant(N >= flow_parallel_min_nodes() ? flow_threads() : 1);
+        const int threads = grant.n;
+        if (threads > 1) {
             std::vector<int64_t> ex(N, 0);
             if (init_ex) {
                 for (int64_t v = 0; v < N && v < (int64_t)init_ex->size(); ++v) ex[v] = (*init_ex)[v];
@@ -505,6 +534,12 @@ int64_t max_excess(int64_t k, int h, const std::vector<int32_t>& pat, int64_t p,
 
 }  // namespace
 
+namespace {
+thread_local bool g_single = false;
+}
+void topk_single_thread(bool on) { g_single = on; }
+bool topk_threads_single() { return g_single; }
+
 // ----------------------------------------------------------- host graph
 void HostGraph::load(const Graph& g, int mode, hipStream_t s) {
     n = g.n;
@@ -627,8 +662,9 @@ void induced_patterns(Ctx& c, const std::vector<int32_t>& vs, std::vector<int32_
         }
     };
     const int64_t k = (int64_t)vs.size();
-    const int T = flow_threads();
-    if (k < flow_parallel_min_nodes() || T <= 1) {
+    ThreadGrant grant(k >= flow_parallel_min_nodes() ? flow_threads() : 1);
+    const int T = grant.n;
+    if (T <= 1) {
         range(0, k, pat, split);
     } else {
         // contiguous ranges per thread, concatenated in order: the same list

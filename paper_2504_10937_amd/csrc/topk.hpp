@@ -45,6 +45,12 @@ struct TopkStats {
     double ms_copy = 0, ms_core = 0, ms_fw = 0, ms_prune = 0, ms_search = 0;
 };
 
+// Min cuts of large networks use extra host threads (a shared budget).  A
+// thread that calls topk_single_thread(true) runs its searches on itself only
+// (the serving workers do: their peers use the other cores).
+void topk_single_thread(bool on);
+bool topk_threads_single();
+
 // reuse_fw: the graph already holds a completed run of `iters` iterations
 // for this mode (e.g. from a batched launch); it is used instead of a new run
 void topk_run(Graph& g, int mode, int k, int iters, hipStream_t s, std::vector<TopkSet>& out, TopkStats& st,
