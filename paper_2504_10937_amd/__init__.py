@@ -255,6 +255,19 @@ def lds_sort_prefix(g, mode, stream=None):
     return order, E, inI.astype(bool)
 
 
+def _host_i64(n):
+    """int64 output array of a device-to-host copy: page-locked (torch's
+    caching host allocator) when a HIP device is present, so that the copy
+    runs at link speed into pages that are reused, not faulted in anew."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return torch.empty(n, dtype=torch.int64, pin_memory=True).numpy()
+    except ImportError:
+        pass
+    return np.empty(n, np.int64)
+
+
 def lds_stable_groups(g, mode, stream=None):
     """Alg. 2 stable groups -> (groups [(start, end)], lo (n,), hi (n,)) with
     lo/hi numerators over D (-1: no bounds), indexed by caller id."""
@@ -262,8 +275,8 @@ def lds_stable_groups(g, mode, stream=None):
     ng = ctypes.c_int64()
     gs = np.empty(max(n, 1), np.int64)
     ge = np.empty(max(n, 1), np.int64)
-    lo = np.empty(n, np.int64)
-    hi = np.empty(n, np.int64)
+    lo = _host_i64(n)
+    hi = _host_i64(n)
     _check(load().lds_stable_groups(g.handle, mode, ctypes.byref(ng), _ptr(gs), _ptr(ge), len(gs), _ptr(lo), _ptr(hi),
                                     _stream(stream)))
     return [(int(gs[i]), int(ge[i])) for i in range(ng.value)], lo, hi

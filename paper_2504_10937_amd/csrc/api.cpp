@@ -284,7 +284,7 @@ lds_status lds_stable_groups(lds_graph g, lds_mode mode, int64_t* ngroups, int64
     lds::Graph& G = g->g;
     lds::sg_stable_groups(G, (int)mode, s);
     const lds::SgState& q = G.sg[mode == LDS_EDGE ? 0 : 1];
-    const int64_t ng = (int64_t)q.gstart.size(), n = G.n;
+    const int64_t ng = (int64_t)q.gstart.size();
     if (ngroups) *ngroups = ng;
     if (gstart || gend) {
         LDS_CHECK(cap >= ng, lds::ST_INVALID, "group capacity too small");
@@ -293,18 +293,7 @@ lds_status lds_stable_groups(lds_graph g, lds_mode mode, int64_t* ngroups, int64
             if (gend) gend[i] = q.gend[i];
         }
     }
-    if (n > 0 && (lo_out || hi_out)) {
-        std::vector<int64_t> lo(n), hi(n);
-        std::vector<int32_t> orig(n);
-        LDS_HIP(hipMemcpyAsync(lo.data(), q.lo.p, n * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        LDS_HIP(hipMemcpyAsync(hi.data(), q.hi.p, n * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        LDS_HIP(hipMemcpyAsync(orig.data(), G.orig_of.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        LDS_HIP(hipStreamSynchronize(s));
-        for (int64_t i = 0; i < n; ++i) {
-            if (lo_out) lo_out[orig[i]] = lo[i];
-            if (hi_out) hi_out[orig[i]] = hi[i];
-        }
-    }
+    lds::sg_copy_bounds(G, (int)mode, lo_out, hi_out, s);
     API_CATCH
 }
 

@@ -163,6 +163,8 @@ inline const SweepPlan& plan_of(const Graph& g, int mode) {
 // sg.hip
 void sg_sort_prefix(Graph& g, int mode, hipStream_t s);
 void sg_stable_groups(Graph& g, int mode, hipStream_t s);
+// lo / hi of the last stable-group scan, by original id, into host memory
+void sg_copy_bounds(const Graph& g, int mode, int64_t* lo_out, int64_t* hi_out, hipStream_t s);
 
 // cores.hip: core (mode 2) / tr-core (mode 3) numbers of the subgraph induced
 // by alive (device bytes, internal order; nullptr = all vertices) into core

@@ -71,41 +71,64 @@ __global__ void k_order(const uint32_t* vals, int64_t n, int32_t* order, int64_t
 
 // --------------------------------------------------- split numerators per slot
 // a = a0 + sum_i inc_i [slot won in iteration i], walking the sweep plan so
-// that the bit position of a slot is known without a row search
-__global__ void k_slot_splits(const int64_t* rp, int64_t n_hub, const int64_t* hwo, int64_t n_chunks,
-                              const int64_t* chunk_row, const int64_t* cwo, int64_t chunk_words, const uint64_t* bits,
-                              int64_t total_words, int iters, int tri, uint32_t* a_slot) {
+// that the bit position of a slot is known without a row search.  A block
+// takes its hub row or chunk in spans of kSpanW decision words (64 slots
+// each).  The span's words of kIterB iterations at a time are staged in LDS
+// by coalesced loads (a wave loads four whole 128-byte segments), and each
+// thread then tests the bits of its slots there (the lanes of a wave read
+// one word: a broadcast), so every decision word is read from memory once
+// per block, by vector loads.
+constexpr int kSpanW = 16;
+constexpr int kIterB = 64;
+
+__global__ __launch_bounds__(kT) void k_slot_splits(const int64_t* rp, int64_t n_hub, const int64_t* hwo, int64_t n_chunks,
+                                                    const int64_t* chunk_row, const int64_t* cwo, int64_t chunk_words,
+                                                    const uint64_t* bits, int64_t total_words, int iters, int tri,
+                                                    uint32_t* a_slot) {
+    __shared__ uint64_t sw[kIterB][kSpanW];
     const int64_t b = blockIdx.x;
-    int64_t s0, s1, bit0;
+    int64_t s0, s1, word0;
     if (b < n_hub) {
         s0 = rp[b];
         s1 = rp[b + 1];
-        bit0 = (chunk_words + hwo[b]) * 64;
+        word0 = chunk_words + hwo[b];
     } else {
         const int64_t c = b - n_hub;
         if (c >= n_chunks) return;
         s0 = rp[chunk_row[c]];
         s1 = rp[chunk_row[c + 1]];
-        bit0 = cwo[c] * 64;
+        word0 = cwo[c];
     }
-    // the 64 slots of a wave share one decision word per iteration (bit0 is
-    // word-aligned and a wave covers 64 consecutive slots), so the word index
-    // is made wave-uniform and each word is read once per wave
-    for (int64_t base = s0; base < s1; base += kT) {
-        const int64_t s = base + threadIdx.x;
-        const int64_t wave_first = base + (threadIdx.x & ~63);
-        if (wave_first >= s1) break;  // the whole wave is past the block (its word would be too)
-        const int64_t p0 = bit0 + (wave_first - s0);
-        const uint32_t wlo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)(p0 / 64));
-        const uint32_t whi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)(p0 / 64) >> 32));
-        const int64_t widx = (int64_t)(((uint64_t)whi << 32) | wlo);
-        const int bit = threadIdx.x & 63;
-        uint64_t a = tri ? 2 : 1;
-        for (int i = 1; i <= iters; ++i) {
-            const uint64_t wd = bits[(int64_t)(i - 1) * total_words + widx];
-            if ((wd >> bit) & 1ull) a += (uint64_t)(tri ? 6 : 2) * (uint64_t)(i + 1);
+    constexpr int kPer = 64 * kSpanW / kT;  // slots per thread and span
+    const int t = threadIdx.x;
+    const uint64_t a0 = tri ? 2 : 1, c2 = tri ? 6 : 2;
+    for (int64_t base = s0; base < s1; base += 64 * kSpanW) {
+        const int64_t w0 = word0 + (base - s0) / 64;
+        const int64_t nw = min<int64_t>(kSpanW, (s1 - base + 63) / 64);
+        uint64_t acc[kPer];
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) acc[q] = a0;
+        for (int i0 = 0; i0 < iters; i0 += kIterB) {
+            const int ni = min(kIterB, iters - i0);
+            __syncthreads();  // the previous batch has been read
+            for (int e = t; e < ni * kSpanW; e += kT) {
+                const int ii = e / kSpanW, ww = e % kSpanW;
+                sw[ii][ww] = (ww < nw) ? bits[(int64_t)(i0 + ii) * total_words + w0 + ww] : 0ull;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < kPer; ++q) {
+                const int local = t + kT * q;
+                const int ww = local >> 6, bit = local & 63;
+                for (int ii = 0; ii < ni; ++ii)
+                    if ((sw[ii][ww] >> bit) & 1ull) acc[q] += c2 * (uint64_t)(i0 + ii + 2);  // iteration i0+ii+1
+            }
         }
-        if (s < s1) a_slot[s] = (uint32_t)a;
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int64_t s = base + t + kT * q;
+            if (s < s1) a_slot[s] = (uint32_t)acc[q];
+        }
     }
 }
 
@@ -429,96 +452,211 @@ struct ScanArgs {
     int64_t* info;         // [0] groups, [1] rounds, [2] verifications, [3] error flag
     long long* part;       // 2 * gridDim * 4 partial records
     unsigned* bar;         // [0] arrivals, [1] generation
-    // compact records built once per scan (k_slot_records): the row of each
-    // position, and per incidence slot the other vertices' positions and the
-    // split numerators of the pattern, so that a phase streams records
-    // instead of chasing order -> row -> slot -> neighbour -> position
-    const int32_t* rowp;   // row by position, -1 for a vertex without slots
+    // compact records built once per scan (k_slot_records), one per
+    // incidence slot, stored in position order: the records of the vertex at
+    // position j are [P[j], P[j+1]), so the patterns of a range of positions
+    // are one contiguous range of records, streamed instead of chased
+    // through order -> row -> slot -> neighbour -> position
+    const int64_t* P;      // n + 1 record offsets by position
+    const int32_t* own;    // position of the record's own vertex
     const int2* rec2;      // edges: (position of the other end, a_x)
     const int4* rec3;      // triangles: (position v, position w, a_x, a_v)
     const uint32_t* rec3w; // triangles: a_w
 };
 
-constexpr int kGL = 16;  // lanes per position in the scan's slot loops
-
-// the pattern at slot s of the vertex at position j, from the records
+// the pattern of record k, from the records
 template <int H>
-__device__ inline void rec_pattern(const ScanArgs& g, int64_t s, int64_t j, int64_t* p, int64_t* al);
+__device__ inline void rec_pattern(const ScanArgs& g, int64_t k, int64_t* p, int64_t* al);
 template <>
-__device__ inline void rec_pattern<2>(const ScanArgs& g, int64_t s, int64_t j, int64_t* p, int64_t* al) {
-    const int2 r = g.rec2[s];
-    p[0] = j;
+__device__ inline void rec_pattern<2>(const ScanArgs& g, int64_t k, int64_t* p, int64_t* al) {
+    const int2 r = g.rec2[k];
+    p[0] = g.own[k];
     p[1] = r.x;
     al[0] = (uint32_t)r.y;
     al[1] = (int64_t)g.a.D - al[0];
 }
 template <>
-__device__ inline void rec_pattern<3>(const ScanArgs& g, int64_t s, int64_t j, int64_t* p, int64_t* al) {
-    const int4 r = g.rec3[s];
-    p[0] = j;
+__device__ inline void rec_pattern<3>(const ScanArgs& g, int64_t k, int64_t* p, int64_t* al) {
+    const int4 r = g.rec3[k];
+    p[0] = g.own[k];
     p[1] = r.x;
     p[2] = r.y;
     al[0] = (uint32_t)r.z;
     al[1] = (uint32_t)r.w;
-    al[2] = g.rec3w[s];
+    al[2] = g.rec3w[k];
 }
 
-// Calls f(s, j) for every slot s of the vertices at positions [p0, p1) and
-// then done(j, sum of f) once per position with slots.  Rows with at most
-// kBig slots go to groups of kGL lanes, larger rows to whole waves, so that
-// neither the many short rows nor the few long ones waste lanes.
-constexpr int64_t kBig = 64;
-
-template <class F, class Done>
-__device__ inline void positions_pass(const ScanArgs& g, int64_t p0, int64_t p1, F f, Done done) {
-    const int lane = threadIdx.x & 63;
-    const int lq = threadIdx.x & (kGL - 1);
-    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
-    const int64_t gq = gt / kGL, ngq = nthr / kGL;
-    const int64_t gw = gt / 64, nwave = nthr / 64;
-    // the lanes of a group share j, so they run the same trips and the group
-    // sums read only active lanes
-    for (int64_t j = p0 + gq; j < p1; j += ngq) {
-        const int64_t r = g.rowp[j];
-        if (r < 0) continue;
-        const int64_t s0 = g.a.rp[r], s1 = g.a.rp[r + 1];
-        if (s1 - s0 > kBig) continue;
-        int64_t acc = 0;
-        for (int64_t s = s0 + lq; s < s1; s += kGL) acc += f(s, j);
-        for (int m = kGL / 2; m > 0; m >>= 1) acc += shfl_xor_i64(acc, m);
-        if (lq == 0) done(j, acc);
-    }
-    for (int64_t j = p0 + gw; j < p1; j += nwave) {
-        const int64_t r = g.rowp[j];
-        if (r < 0) continue;
-        const int64_t s0 = g.a.rp[r], s1 = g.a.rp[r + 1];
-        if (s1 - s0 <= kBig) continue;
-        int64_t acc = 0;
-        for (int64_t s = s0 + lane; s < s1; s += 64) acc += f(s, j);
-        for (int m = 32; m > 0; m >>= 1) acc += shfl_xor_i64(acc, m);
-        if (lane == 0) done(j, acc);
-    }
-}
-
-// records of every slot of row r (one wave per row)
+// Record walks.  A wave takes kRecRows(H) rows of 64 consecutive records per
+// trip (lane l reads record base + 64 u + l of row u, so every load is
+// coalesced) and keeps the loads, the atomics and the reads that depend on
+// them of all its rows in flight together: the walks are bound by the
+// latency of these dependent accesses, not by bandwidth, and a long row no
+// longer runs as one wave's serial loop.
 template <int H>
-__global__ __launch_bounds__(kT) void k_slot_records(PassArgs a, int32_t* rowp, int2* rec2, int4* rec3,
-                                                     uint32_t* rec3w) {
+constexpr int kRecRows = (H == 2) ? 8 : 4;
+
+__device__ inline int32_t shfl_down_i32(int32_t v, int d) { return __shfl_down(v, (unsigned)d, 64); }
+__device__ inline int64_t shfl_down_i64(int64_t v, int d) {
+    const uint32_t lo = (uint32_t)__shfl_down((int)(uint32_t)(uint64_t)v, (unsigned)d, 64);
+    const uint32_t hi = (uint32_t)__shfl_down((int)(uint32_t)((uint64_t)v >> 32), (unsigned)d, 64);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Adds, per position, the values of one row of 64 records into V.  The
+// positions of a row do not decrease from lane to lane, so a segmented
+// suffix sum leaves each position's total in its first lane, which makes
+// the one atomic (V starts at zero and a position's own sum is added once).
+__device__ inline void add_by_position(int64_t* V, int32_t key, int64_t val) {
+    const int lane = threadIdx.x & 63;
+    const int32_t prev = __shfl_up(key, 1u, 64);
+    const bool head = (lane == 0) || prev != key;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int32_t ko = shfl_down_i32(key, off);
+        const int64_t vo = shfl_down_i64(val, off);
+        if (lane + off < 64 && ko == key) val += vo;
+    }
+    if (head && key >= 0 && val != 0) atomicAdd((unsigned long long*)&V[key], (unsigned long long)val);
+}
+
+// Positions [f0, b) move from below the boundary into the pending group
+// S = [S0, b).  One walk over their patterns gives their own restricted
+// loads (into V), advances the loads F of the vertices that stay below b
+// (with the block maxima), and changes the loads of S's earlier members
+// through the patterns they share with the joining vertices.  Each pattern
+// is handled once, from its latest joining vertex.
+template <int H>
+__device__ inline void update_walk(const ScanArgs& g, int64_t S0, int64_t f0, int64_t b) {
+    constexpr int U = kRecRows<H>;
+    const int lane = threadIdx.x & 63;
+    const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int64_t k0 = g.P[f0], k1 = g.P[b];
+    const uint64_t D = g.a.D;
+    for (int64_t kb = k0 + gw * 64 * U; kb < k1; kb += nwave * 64 * U) {
+        int64_t p[U][H], al[U][H];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t k = kb + 64 * u + lane;
+            if (k < k1) rec_pattern<H>(g, k, p[u], al[u]);
+            else p[u][0] = -1;
+        }
+        int64_t own[U], fd[U][H - 1], fo[U][H - 1];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            own[u] = 0;
+#pragma unroll
+            for (int i = 0; i < H - 1; ++i) fd[u][i] = 0;
+            if (p[u][0] < 0) continue;
+            own[u] = pat_contrib<H>(0, p[u], al[u], D, S0, b);
+            bool latest = true;
+#pragma unroll
+            for (int i = 1; i < H; ++i)
+                if (p[u][i] >= f0 && p[u][i] < b && p[u][i] > p[u][0]) latest = false;
+            if (!latest) continue;
+#pragma unroll
+            for (int i = 1; i < H; ++i) {
+                if (p[u][i] >= b) {  // stays below
+                    const int64_t d = pat_contrib<H>(i, p[u], al[u], D, b, b) - pat_contrib<H>(i, p[u], al[u], D, f0, f0);
+                    if (d != 0) {
+                        fd[u][i - 1] = d;
+                        fo[u][i - 1] = (int64_t)atomicAdd((unsigned long long*)&g.F[p[u][i]], (unsigned long long)d);
+                    }
+                } else if (p[u][i] >= S0 && p[u][i] < f0) {  // earlier member of S
+                    const int64_t d =
+                        pat_contrib<H>(i, p[u], al[u], D, S0, b) - pat_contrib<H>(i, p[u], al[u], D, S0, f0);
+                    if (d != 0) atomicAdd((unsigned long long*)&g.V[p[u][i]], (unsigned long long)d);
+                }
+            }
+        }
+        // block maxima only grow (F only grows, bmax only by atomicMax): a
+        // read that is at least the new value, even a stale one, makes the
+        // atomic redundant
+        long long bm[U][H - 1];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int i = 0; i < H - 1; ++i)
+                if (fd[u][i] != 0) bm[u][i] = g.bmax[p[u][i + 1] / kFB];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int i = 0; i < H - 1; ++i)
+                if (fd[u][i] != 0) {
+                    const long long nv = (long long)(fo[u][i] + fd[u][i]);
+                    if (nv > bm[u][i]) atomicMax(&g.bmax[p[u][i + 1] / kFB], nv);
+                }
+#pragma unroll
+        for (int u = 0; u < U; ++u) add_by_position(g.V, (int32_t)p[u][0], own[u]);
+    }
+}
+
+// After S = [S0, b) is accepted: the change of T_x (S ending after x) for
+// the vertices below b, from the patterns of S (each handled once, from its
+// latest vertex in S).
+template <int H>
+__device__ inline void accept_walk(const ScanArgs& g, int64_t S0, int64_t b) {
+    constexpr int U = kRecRows<H>;
+    const int lane = threadIdx.x & 63;
+    const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int64_t k0 = g.P[S0], k1 = g.P[b];
+    const uint64_t D = g.a.D;
+    for (int64_t kb = k0 + gw * 64 * U; kb < k1; kb += nwave * 64 * U) {
+        int64_t p[U][H], al[U][H];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t k = kb + 64 * u + lane;
+            if (k < k1) rec_pattern<H>(g, k, p[u], al[u]);
+            else p[u][0] = -1;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (p[u][0] < 0) continue;
+            bool latest = true;
+#pragma unroll
+            for (int i = 1; i < H; ++i)
+                if (p[u][i] >= S0 && p[u][i] < b && p[u][i] > p[u][0]) latest = false;
+            if (!latest) continue;
+#pragma unroll
+            for (int i = 1; i < H; ++i) {
+                if (p[u][i] < b) continue;
+                const int64_t d = pat_contrib<H>(i, p[u], al[u], D, b, p[u][i] + 1) -
+                                  pat_contrib<H>(i, p[u], al[u], D, S0, p[u][i] + 1);
+                if (d != 0) atomicAdd((unsigned long long*)&g.T[p[u][i]], (unsigned long long)d);
+            }
+        }
+    }
+}
+
+// slots per position (rows are vertices with slots; the rest stay 0)
+__global__ void k_pos_slots(PassArgs a, uint64_t* cnt) {
+    const int64_t r = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (r >= a.nrows) return;
+    const int32_t x = a.rid ? a.rid[r] : (int32_t)r;
+    cnt[a.pos[x]] = (uint64_t)(a.rp[r + 1] - a.rp[r]);
+}
+
+// records of every slot of row r (one wave per row), written in position
+// order: slot s of the row at position px goes to P[px] + (s - rp[r])
+template <int H>
+__global__ __launch_bounds__(kT) void k_slot_records(PassArgs a, const int64_t* P, int32_t* own, int2* rec2,
+                                                     int4* rec3, uint32_t* rec3w) {
     const int lane = threadIdx.x & 63;
     const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (r >= a.nrows) return;
     const int32_t x = a.rid ? a.rid[r] : (int32_t)r;
-    if (lane == 0) rowp[a.pos[x]] = (int32_t)r;
+    const int64_t px = a.pos[x];
+    const int64_t shift = P[px] - a.rp[r];
     for (int64_t s = a.rp[r] + lane; s < a.rp[r + 1]; s += 64) {
         int64_t p[H], al[H];
         int32_t id[H];
         load_pattern<H>(a, s, x, p, al, id);
+        own[shift + s] = (int32_t)px;
         if (H == 2) {
-            rec2[s] = make_int2((int)p[1], (int)(uint32_t)al[0]);
+            rec2[shift + s] = make_int2((int)p[1], (int)(uint32_t)al[0]);
         } else {
-            rec3[s] = make_int4((int)p[1], (int)p[2], (int)(uint32_t)al[0], (int)(uint32_t)al[1]);
-            rec3w[s] = (uint32_t)al[2];
+            rec3[shift + s] = make_int4((int)p[1], (int)p[2], (int)(uint32_t)al[0], (int)(uint32_t)al[1]);
+            rec3w[shift + s] = (uint32_t)al[2];
         }
     }
 }
@@ -655,9 +793,6 @@ __global__ __launch_bounds__(kRT) void k_sg_scan(ScanArgs g) {
     const int64_t nwave = (int64_t)nwg * kRW;
     const int64_t gt = (int64_t)blockIdx.x * kRT + threadIdx.x;
     const int64_t nthr = (int64_t)nwg * kRT;
-    const int64_t gq = gt / kGL;           // lane group (kGL lanes) index
-    const int64_t ngq = nthr / kGL;
-    const int lq = threadIdx.x & (kGL - 1);
     const int64_t n = g.n;
     if (threadIdx.x == 0) s_err = 0;
     __syncthreads();
@@ -705,53 +840,12 @@ __global__ __launch_bounds__(kRT) void k_sg_scan(ScanArgs g) {
             }
             const int64_t b = e + 1;
             ++verifs;
-            // phase: positions [fb, b) move from below the boundary into the
-            // pending group S = [S0, b).  One walk over their patterns gives
-            // their own restricted loads, advances the loads of the vertices
-            // that stay below b, and changes the loads of S's earlier members
-            // through the patterns they share with the joining vertices (each
-            // pattern handled once, from its latest joining vertex).  The
-            // frontier of the loads below and the end of S always coincide:
-            // both start at the accepted boundary and move to every verified b.
-            {
-                const int64_t f0 = fb;
-                for (int64_t jj = f0 + gt; jj < b; jj += nthr)
-                    if (g.rowp[jj] < 0) g.V[jj] = 0;  // positions without slots have load 0
-                positions_pass(
-                    g, f0, b,
-                    [&](int64_t s, int64_t jj) -> int64_t {
-                        int64_t p[H], al[H];
-                        rec_pattern<H>(g, s, jj, p, al);
-                        const int64_t own = pat_contrib<H>(0, p, al, a.D, S0, b);
-#pragma unroll
-                        for (int i = 1; i < H; ++i)
-                            if (p[i] >= f0 && p[i] < b && p[i] > p[0]) return own;  // not the latest joiner
-#pragma unroll
-                        for (int i = 1; i < H; ++i) {
-                            if (p[i] >= b) {  // stays below
-                                const int64_t before = pat_contrib<H>(i, p, al, a.D, f0, f0);
-                                const int64_t after = pat_contrib<H>(i, p, al, a.D, b, b);
-                                if (after != before) {
-                                    const unsigned long long old = atomicAdd((unsigned long long*)&g.F[p[i]],
-                                                                             (unsigned long long)(after - before));
-                                    // block maxima only grow (F only grows, bmax only by atomicMax):
-                                    // a read that is at least the new value, even a stale one, makes
-                                    // the atomic redundant
-                                    const long long nv = (long long)(old + (unsigned long long)(after - before));
-                                    if (nv > g.bmax[p[i] / kFB]) atomicMax(&g.bmax[p[i] / kFB], nv);
-                                }
-                            } else if (p[i] >= S0 && p[i] < f0) {  // earlier member of S
-                                const int64_t before = pat_contrib<H>(i, p, al, a.D, S0, f0);
-                                const int64_t after = pat_contrib<H>(i, p, al, a.D, S0, b);
-                                if (after != before)
-                                    atomicAdd((unsigned long long*)&g.V[p[i]], (unsigned long long)(after - before));
-                            }
-                        }
-                        return own;
-                    },
-                    [&](int64_t jj, int64_t acc) { g.V[jj] = acc; });
-                fb = b;
-            }
+            // phase: positions [fb, b) join the pending group S = [S0, b);
+            // the frontier of the loads below and the end of S always
+            // coincide: both start at the accepted boundary and move to every
+            // verified b
+            update_walk<H>(g, S0, fb, b);
+            fb = b;
             PROF_MARK(2);
             grid_barrier(g, nwg, &s_err);
             PROF_MARK(3);
@@ -795,25 +889,7 @@ __global__ __launch_bounds__(kRT) void k_sg_scan(ScanArgs g) {
             g.lo[g.order[j]] = mnS;
             g.hi[g.order[j]] = mxS;
         }
-        positions_pass(
-            g, S0, b,
-            [&](int64_t s, int64_t jj) -> int64_t {
-                int64_t p[H], al[H];
-                rec_pattern<H>(g, s, jj, p, al);
-#pragma unroll
-                for (int i = 1; i < H; ++i)
-                    if (p[i] >= S0 && p[i] < b && p[i] > p[0]) return 0;  // not the latest accepted vertex
-#pragma unroll
-                for (int i = 1; i < H; ++i) {
-                    if (p[i] < b) continue;
-                    const int64_t before = pat_contrib<H>(i, p, al, a.D, S0, p[i] + 1);
-                    const int64_t after = pat_contrib<H>(i, p, al, a.D, b, p[i] + 1);
-                    if (after != before)
-                        atomicAdd((unsigned long long*)&g.T[p[i]], (unsigned long long)(after - before));
-                }
-                return 0;
-            },
-            [](int64_t, int64_t) {});
+        accept_walk<H>(g, S0, b);
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             g.groups[2 * ng] = S0;
             g.groups[2 * ng + 1] = b;
@@ -1004,12 +1080,14 @@ void sg_stable_groups(Graph& g, int mode, hipStream_t s) {
 
     // slot records and the row of every position
     const SweepPlan& pl = (mode == 2) ? g.edge_plan : g.tri_plan;
-    DBuf<int32_t> rowp;
+    DBuf<int64_t> P;
+    DBuf<int32_t> own;
     DBuf<int2> rec2;
     DBuf<int4> rec3;
     DBuf<uint32_t> rec3w;
-    rowp.alloc(n, s);
-    k_fill_i32<<<grid_for(n, kT), kT, 0, s>>>(rowp.p, n, -1);
+    P.alloc(n + 1, s);
+    k_fill_i64<<<grid_for(n + 1, kT), kT, 0, s>>>(P.p, n + 1, 0);
+    own.alloc(pl.nslots, s);
     if (mode == 2)
         rec2.alloc(pl.nslots, s);
     else {
@@ -1017,10 +1095,12 @@ void sg_stable_groups(Graph& g, int mode, hipStream_t s) {
         rec3w.alloc(pl.nslots, s);
     }
     if (pl.nrows > 0) {
+        k_pos_slots<<<grid_for(pl.nrows, kT), kT, 0, s>>>(a, (uint64_t*)P.p);
+        exclusive_scan_u64((const uint64_t*)P.p, (uint64_t*)P.p, n, (uint64_t*)P.p + n, s);
         if (mode == 2)
-            k_slot_records<2><<<grid_for(pl.nrows, 4), kT, 0, s>>>(a, rowp.p, rec2.p, rec3.p, rec3w.p);
+            k_slot_records<2><<<grid_for(pl.nrows, 4), kT, 0, s>>>(a, P.p, own.p, rec2.p, rec3.p, rec3w.p);
         else
-            k_slot_records<3><<<grid_for(pl.nrows, 4), kT, 0, s>>>(a, rowp.p, rec2.p, rec3.p, rec3w.p);
+            k_slot_records<3><<<grid_for(pl.nrows, 4), kT, 0, s>>>(a, P.p, own.p, rec2.p, rec3.p, rec3w.p);
     }
     LDS_HIP(hipGetLastError());
 
@@ -1031,6 +1111,7 @@ void sg_stable_groups(Graph& g, int mode, hipStream_t s) {
     DBuf<unsigned> bar;
     F.alloc(n, s);
     Vb.alloc(n, s);
+    k_fill_i64<<<grid_for(n, kT), kT, 0, s>>>(Vb.p, n, 0);  // each position's own load is added once
     bmax.alloc(nblk, s);
     k_f_init<<<grid_for(n, kT), kT, 0, s>>>(f.K[f.cur].p, q.order.p, n, g.idbits, F.p);
     k_bmax_init<<<grid_for(nblk, 1), kT, 0, s>>>(F.p, n, bmax.p);
@@ -1071,7 +1152,8 @@ void sg_stable_groups(Graph& g, int mode, hipStream_t s) {
     sa.info = info.p;
     sa.part = part.p;
     sa.bar = bar.p;
-    sa.rowp = rowp.p;
+    sa.P = P.p;
+    sa.own = own.p;
     sa.rec2 = rec2.p;
     sa.rec3 = rec3.p;
     sa.rec3w = rec3w.p;
@@ -1108,6 +1190,29 @@ void sg_stable_groups(Graph& g, int mode, hipStream_t s) {
         q.gstart.push_back(hg[2 * i]);
         q.gend.push_back(hg[2 * i + 1]);
     }
+}
+
+namespace {
+__global__ void k_by_orig(const int64_t* lo, const int64_t* hi, const int32_t* orig_of, int64_t n, int64_t* out) {
+    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (i >= n) return;
+    const int64_t o = orig_of[i];
+    out[o] = lo[i];
+    out[n + o] = hi[i];
+}
+}  // namespace
+
+void sg_copy_bounds(const Graph& g, int mode, int64_t* lo_out, int64_t* hi_out, hipStream_t s) {
+    const SgState& q = g.sg[mode == 2 ? 0 : 1];
+    const int64_t n = g.n;
+    if (n == 0 || (!lo_out && !hi_out)) return;
+    DBuf<int64_t> out;
+    out.alloc((size_t)2 * n, s);
+    k_by_orig<<<grid_for(n, kT), kT, 0, s>>>(q.lo.p, q.hi.p, g.orig_of.p, n, out.p);
+    LDS_HIP(hipGetLastError());
+    if (lo_out) LDS_HIP(hipMemcpyAsync(lo_out, out.p, n * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    if (hi_out) LDS_HIP(hipMemcpyAsync(hi_out, out.p + n, n * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    LDS_HIP(hipStreamSynchronize(s));
 }
 
 }  // namespace lds
