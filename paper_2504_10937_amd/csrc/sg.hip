@@ -37,6 +37,7 @@
 //     round) is one cooperative kernel whose workgroups meet at grid barriers
 //     between phases; the host only reads the group list at the end.
 #include <algorithm>
+#include <cstdlib>
 #include <climits>
 
 #include "graph.hpp"
@@ -323,11 +324,6 @@ __global__ void k_tile_carry(const int64_t* tn, const int64_t* td, int64_t tiles
 }
 
 // ------------------------------------------------------ a9 round helpers
-__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
-    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
-    if (i < n) p[i] = v;
-}
-
 __global__ void k_fill_i64(int64_t* p, int64_t n, int64_t v) {
     const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
     if (i < n) p[i] = v;
@@ -386,11 +382,6 @@ __device__ inline void load_pattern<3>(const PassArgs& a, int64_t s, int32_t x, 
     al[2] = a.a_tri[3 * t + jw];
 }
 
-__device__ inline int64_t row_of_vertex(const PassArgs& a, int32_t x) {
-    if (a.row_of) return a.row_of[x];
-    return (x < a.nrows) ? (int64_t)x : -1;
-}
-
 // The restricted load F_w(b) of a vertex below the boundary b (everything
 // before b is above it) only grows with b.  Verification boundaries increase
 // over the whole scan, so F is advanced incrementally: when positions
@@ -417,23 +408,38 @@ __global__ __launch_bounds__(kT) void k_bmax_init(const int64_t* F, int64_t n, l
 }
 
 // ------------------------------------------- the whole scan on the device
-// One cooperative launch runs every round of the scan: all workgroups are
-// resident (cooperative launch), they work through each phase together and
-// meet at a grid barrier between phases.  Every decision (next candidate,
-// accept, stop) is computed by every workgroup from the same global values
-// read after a barrier, so control flow is uniform and every workgroup
-// reaches every barrier.  Cross-workgroup reductions go through per-workgroup
-// partial records, double-buffered by phase parity.  Barrier waits are
-// bounded: past the spin limit a workgroup raises the error flag and leaves
-// the wait, so the kernel always ends (the host then reports the error).
+// One launch runs every round of the scan.  Workgroup 0 (the leader) holds
+// the control: it searches, verifies and accepts.  A phase with little work
+// (a search window, a walk over few records, the minimum and maximum over a
+// short pending group) runs in the leader alone, and its phases are
+// separated by workgroup barriers only: no device-scope fences, so the
+// leader's caches stay warm and a verification costs a few dependent
+// accesses.  A phase with much work is posted to the whole grid (a
+// cooperative launch, so every workgroup is resident): the leader writes the
+// phase descriptor, releases its writes at device scope and bumps the post
+// counter; the other workgroups (helpers) wait for the post, run their share
+// and meet the leader at a grid barrier, where every workgroup releases and
+// acquires at device scope.  Cross-workgroup reductions go through
+// per-workgroup partial records, double-buffered by phase parity.  Every
+// wait is bounded: past the spin limit a workgroup raises the error flag and
+// leaves the wait, so the kernel always ends and the host reports the error.
+// A helper's wait for a post restarts its count whenever the leader's
+// heartbeat moves, so a long run of leader-only phases is not an error.
 constexpr int kRT = 512;                 // threads per workgroup of the scan
 constexpr int kRW = kRT / 64;
 constexpr int64_t kSearchWin = 1 << 20;  // largest window of positions searched in one phase
 constexpr unsigned kSpinLimit = 1u << 26;
-#ifndef LDS_SCAN_MAX_WG
-#define LDS_SCAN_MAX_WG 32
-#endif
-constexpr int kScanMaxWG = LDS_SCAN_MAX_WG;
+// defaults of the launch shape: at most kScanMaxWG workgroups (one per 16384
+// vertices), and the largest walk (records) and search window / min-max /
+// bounds range (positions) that the leader runs alone (a few trips of its
+// 512 threads).  The environment variables LDS_SCAN_WG, LDS_SCAN_LEAD_RECS
+// and LDS_SCAN_LEAD_POS override them (LDS_SCAN_WG also lifts the one per
+// 16384 vertices cap), e.g. to run the grid phases on small graphs.
+constexpr int kScanMaxWG = 64;
+constexpr int64_t kLeadRecs = 4096;
+constexpr int64_t kLeadPos = 8192;
+
+enum : long long { PH_EXIT = 0, PH_SEARCH = 1, PH_UPDATE = 2, PH_MINMAX = 3, PH_ACCEPT = 4 };
 
 struct ScanArgs {
     PassArgs a;
@@ -451,7 +457,10 @@ struct ScanArgs {
     int64_t* groups;       // (start, end) per accepted group
     int64_t* info;         // [0] groups, [1] rounds, [2] verifications, [3] error flag
     long long* part;       // 2 * gridDim * 4 partial records
-    unsigned* bar;         // [0] arrivals, [1] generation
+    unsigned* bar;         // [0] barrier arrivals, [2] posts, [3] leader heartbeat
+    long long* desc;       // the posted phase: kind, parity, up to six arguments
+    int64_t lead_recs;     // largest walk the leader runs alone
+    int64_t lead_pos;      // largest position range the leader runs alone
     // compact records built once per scan (k_slot_records), one per
     // incidence slot, stored in position order: the records of the vertex at
     // position j are [P[j], P[j+1]), so the patterns of a range of positions
@@ -524,13 +533,12 @@ __device__ inline void add_by_position(int64_t* V, int32_t key, int64_t val) {
 // (with the block maxima), and changes the loads of S's earlier members
 // through the patterns they share with the joining vertices.  Each pattern
 // is handled once, from its latest joining vertex.
+// Records [k0, k1) = [P[f0], P[b]); wave gw of nwave.
 template <int H>
-__device__ inline void update_walk(const ScanArgs& g, int64_t S0, int64_t f0, int64_t b) {
+__device__ inline void update_walk(const ScanArgs& g, int64_t S0, int64_t f0, int64_t b, int64_t k0, int64_t k1,
+                                   int64_t gw, int64_t nwave) {
     constexpr int U = kRecRows<H>;
     const int lane = threadIdx.x & 63;
-    const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    const int64_t k0 = g.P[f0], k1 = g.P[b];
     const uint64_t D = g.a.D;
     for (int64_t kb = k0 + gw * 64 * U; kb < k1; kb += nwave * 64 * U) {
         int64_t p[U][H], al[U][H];
@@ -541,6 +549,7 @@ __device__ inline void update_walk(const ScanArgs& g, int64_t S0, int64_t f0, in
             else p[u][0] = -1;
         }
         int64_t own[U], fd[U][H - 1], fo[U][H - 1];
+        long long bm[U][H - 1];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             own[u] = 0;
@@ -560,6 +569,7 @@ __device__ inline void update_walk(const ScanArgs& g, int64_t S0, int64_t f0, in
                     if (d != 0) {
                         fd[u][i - 1] = d;
                         fo[u][i - 1] = (int64_t)atomicAdd((unsigned long long*)&g.F[p[u][i]], (unsigned long long)d);
+                        bm[u][i - 1] = g.bmax[p[u][i] / kFB];
                     }
                 } else if (p[u][i] >= S0 && p[u][i] < f0) {  // earlier member of S
                     const int64_t d =
@@ -569,14 +579,8 @@ __device__ inline void update_walk(const ScanArgs& g, int64_t S0, int64_t f0, in
             }
         }
         // block maxima only grow (F only grows, bmax only by atomicMax): a
-        // read that is at least the new value, even a stale one, makes the
-        // atomic redundant
-        long long bm[U][H - 1];
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-            for (int i = 0; i < H - 1; ++i)
-                if (fd[u][i] != 0) bm[u][i] = g.bmax[p[u][i + 1] / kFB];
+        // read that is at least the new value, even a stale one or one made
+        // before the add, makes the atomic redundant
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -593,13 +597,12 @@ __device__ inline void update_walk(const ScanArgs& g, int64_t S0, int64_t f0, in
 // After S = [S0, b) is accepted: the change of T_x (S ending after x) for
 // the vertices below b, from the patterns of S (each handled once, from its
 // latest vertex in S).
+// Records [k0, k1) = [P[S0], P[b]); wave gw of nwave.
 template <int H>
-__device__ inline void accept_walk(const ScanArgs& g, int64_t S0, int64_t b) {
+__device__ inline void accept_walk(const ScanArgs& g, int64_t S0, int64_t b, int64_t k0, int64_t k1, int64_t gw,
+                                   int64_t nwave) {
     constexpr int U = kRecRows<H>;
     const int lane = threadIdx.x & 63;
-    const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    const int64_t k0 = g.P[S0], k1 = g.P[b];
     const uint64_t D = g.a.D;
     for (int64_t kb = k0 + gw * 64 * U; kb < k1; kb += nwave * 64 * U) {
         int64_t p[U][H], al[U][H];
@@ -664,7 +667,10 @@ __global__ __launch_bounds__(kT) void k_slot_records(PassArgs a, const int64_t* 
 // Only thread 0 of a workgroup makes the device-scope release / acquire: on
 // a chip with several L2s these write back and invalidate the caches, which
 // the workgroup's threads share; the others order their accesses against it
-// with the workgroup barrier.
+// with the workgroup barrier.  The arrival counter only grows (zeroed per
+// launch): a workgroup arriving at the k-th barrier draws a value in
+// [k nwg, (k+1) nwg) and waits until the counter reaches (k+1) nwg, so one
+// atomic per arrival and no separate generation word.
 __device__ inline void grid_barrier(const ScanArgs& g, unsigned nwg, int64_t* err) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __syncthreads();
@@ -674,19 +680,14 @@ __device__ inline void grid_barrier(const ScanArgs& g, unsigned nwg, int64_t* er
     }
     if (threadIdx.x == 0) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        const unsigned gen = __hip_atomic_load(g.bar + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned arrived = __hip_atomic_fetch_add(g.bar, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (arrived == nwg - 1) {
-            __hip_atomic_store(g.bar, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(g.bar + 1, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            unsigned spins = 0;
-            while (__hip_atomic_load(g.bar + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-                __builtin_amdgcn_s_sleep(2);
-                if (++spins > kSpinLimit) {
-                    *err = 1;
-                    break;
-                }
+        const unsigned arrived = __hip_atomic_fetch_add(g.bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned target = (arrived / nwg + 1) * nwg;
+        unsigned spins = 0;
+        while ((int)(__hip_atomic_load(g.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) < 0) {
+            __builtin_amdgcn_s_sleep(2);
+            if (++spins > kSpinLimit) {
+                *err = 1;
+                break;
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -760,73 +761,209 @@ __device__ inline void put_partial(const ScanArgs& g, int ph, long long v0, long
     __syncthreads();
 }
 
-// LDS_SCAN_PROF: workgroup 0 accumulates the time of each phase, split into
-// its own work and its barrier wait (info[4..11]); a measurement switch only
-#ifdef LDS_SCAN_PROF
-#define PROF_MARK(k)                                                        \
-    do {                                                                    \
-        if (blockIdx.x == 0 && threadIdx.x == 0) {                          \
-            const uint64_t t_ = __builtin_amdgcn_s_memrealtime();           \
-            prof[k] += t_ - tprev;                                          \
-            tprev = t_;                                                     \
-        }                                                                   \
-    } while (0)
-#else
-#define PROF_MARK(k) \
-    do {             \
-    } while (0)
-#endif
+// WG-level reduction of per-thread values into sh[0..3] (min, max, max, min)
+__device__ inline void reduce_local(long long v0, long long v1, long long v2, long long v3, long long (*sred)[4],
+                                    long long* sh) {
+    for (int m = 32; m > 0; m >>= 1) {
+        v0 = min(v0, (long long)shfl_xor_i64(v0, m));
+        v1 = max(v1, (long long)shfl_xor_i64(v1, m));
+        v2 = max(v2, (long long)shfl_xor_i64(v2, m));
+        v3 = min(v3, (long long)shfl_xor_i64(v3, m));
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+        sred[w][0] = v0;
+        sred[w][1] = v1;
+        sred[w][2] = v2;
+        sred[w][3] = v3;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < kRW; ++q) {
+            v0 = min(v0, sred[q][0]);
+            v1 = max(v1, sred[q][1]);
+            v2 = max(v2, sred[q][2]);
+            v3 = min(v3, sred[q][3]);
+        }
+        sh[0] = v0;
+        sh[1] = v1;
+        sh[2] = v2;
+        sh[3] = v3;
+    }
+    __syncthreads();
+}
+
+// First event in [lo, hi) among this thread's positions lo + t + i * nthr:
+// a stop position (T >= minH) or a candidate boundary (in I, and R of the
+// next position below T).  LLONG_MAX: none.
+__device__ inline long long search_part(const ScanArgs& g, int64_t lo, int64_t hi, bool hasH, long long minH,
+                                        int64_t t, int64_t nthr) {
+    for (int64_t j0 = lo + t; j0 < hi; j0 += 4 * nthr) {
+        int64_t Tv[4];
+        uint8_t in[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t j = j0 + u * nthr;
+            Tv[u] = j < hi ? g.T[j] : 0;
+            in[u] = j < hi ? g.inI[j] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t j = j0 + u * nthr;
+            if (j >= hi) break;
+            bool ev = hasH && Tv[u] >= minH;
+            if (!ev && in[u]) ev = (j + 1 == g.n) || (g.R[j + 1] < Tv[u]);
+            if (ev) return j;
+        }
+    }
+    return LLONG_MAX;
+}
+
+// min and max of the restricted loads of S = [S0, b), and the largest
+// restricted load below b, over this thread's share
+__device__ inline void minmax_part(const ScanArgs& g, int64_t S0, int64_t b, int64_t t, int64_t nthr, long long& vmn,
+                                   long long& vmx, long long& fmx) {
+    vmn = LLONG_MAX;
+    vmx = LLONG_MIN;
+    fmx = LLONG_MIN;
+    for (int64_t j = S0 + t; j < b; j += nthr) {
+        const long long v = (long long)g.V[j];
+        vmn = min(vmn, v);
+        vmx = max(vmx, v);
+    }
+    if (b < g.n) {
+        const int64_t bend = min(g.n, (b / kFB + 1) * kFB);
+        for (int64_t j = b + t; j < bend; j += nthr) fmx = max(fmx, (long long)g.F[j]);
+        for (int64_t blk = b / kFB + 1 + t; blk < g.nblk; blk += nthr) fmx = max(fmx, g.bmax[blk]);
+    }
+}
+
+// bounds of the accepted group S = [S0, b) and the change of T below it
+template <int H>
+__device__ inline void accept_part(const ScanArgs& g, int64_t S0, int64_t b, int64_t k0, int64_t k1, long long mnS,
+                                   long long mxS, int64_t t, int64_t nthr, int64_t gw, int64_t nwave) {
+    for (int64_t j = S0 + t; j < b; j += nthr) {
+        const int32_t x = g.order[j];
+        g.lo[x] = mnS;
+        g.hi[x] = mxS;
+    }
+    accept_walk<H>(g, S0, b, k0, k1, gw, nwave);
+}
+
+// this workgroup's share of a posted phase (grid-wide thread and wave indices)
+template <int H>
+__device__ inline void run_posted(const ScanArgs& g, const long long* d, long long (*sred)[4]) {
+    const int64_t t = (int64_t)blockIdx.x * kRT + threadIdx.x, nthr = (int64_t)gridDim.x * kRT;
+    const int64_t gw = t >> 6, nwave = nthr >> 6;
+    const int ph = (int)d[1];
+    if (d[0] == PH_SEARCH) {
+        const long long first = search_part(g, d[2], d[3], d[4] != 0, d[5], t, nthr);
+        put_partial(g, ph, first, LLONG_MIN, LLONG_MIN, LLONG_MAX, sred);
+    } else if (d[0] == PH_UPDATE) {
+        update_walk<H>(g, d[2], d[3], d[4], d[5], d[6], gw, nwave);
+    } else if (d[0] == PH_MINMAX) {
+        long long vmn, vmx, fmx;
+        minmax_part(g, d[2], d[3], t, nthr, vmn, vmx, fmx);
+        put_partial(g, ph, vmn, vmx, fmx, LLONG_MAX, sred);
+    } else if (d[0] == PH_ACCEPT) {
+        accept_part<H>(g, d[2], d[3], d[4], d[5], d[6], d[7], t, nthr, gw, nwave);
+    }
+}
+
+// leader: publish phase descriptor d (uniform over the workgroup) to the helpers
+__device__ inline void post_phase(const ScanArgs& g, unsigned& posted, const long long* d) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __syncthreads();
+    ++posted;
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < 8; ++i) g.desc[i] = d[i];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_store(g.bar + 2, posted, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+__device__ inline void heartbeat(const ScanArgs& g, unsigned& beat) {
+    ++beat;
+    if (threadIdx.x == 0) __hip_atomic_store(g.bar + 3, beat, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 template <int H>
-__global__ __launch_bounds__(kRT) void k_sg_scan(ScanArgs g) {
-#ifdef LDS_SCAN_PROF
-    uint64_t prof[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    uint64_t tprev = __builtin_amdgcn_s_memrealtime();
-#endif
-    __shared__ long long sred[kRW][4];
-    __shared__ long long sh[4];
-    __shared__ int64_t s_err;
-    const PassArgs& a = g.a;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+__device__ void scan_helper(const ScanArgs& g, long long (*sred)[4], int64_t* s_err) {
+    __shared__ long long sd[8];
     const unsigned nwg = gridDim.x;
-    const int64_t gw = (int64_t)blockIdx.x * kRW + w;     // global wave index
-    const int64_t nwave = (int64_t)nwg * kRW;
-    const int64_t gt = (int64_t)blockIdx.x * kRT + threadIdx.x;
-    const int64_t nthr = (int64_t)nwg * kRT;
+    for (unsigned want = 1;; ++want) {
+        if (threadIdx.x == 0) {
+            unsigned beat = __hip_atomic_load(g.bar + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            unsigned spins = 0;
+            bool ok = true;
+            // posts never run ahead by more than one (each posted phase ends at a grid
+            // barrier this workgroup joins), except the final exit after an error
+            while ((int)(__hip_atomic_load(g.bar + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - want) < 0) {
+                __builtin_amdgcn_s_sleep(2);
+                if ((++spins & 63) == 0) {  // the heartbeat is read now and then
+                    const unsigned nb = __hip_atomic_load(g.bar + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (nb != beat) {
+                        beat = nb;
+                        spins = 0;
+                    }
+                }
+                if (spins > kSpinLimit) {
+                    ok = false;
+                    break;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            if (ok) {
+                for (int i = 0; i < 8; ++i) sd[i] = g.desc[i];
+            } else {
+                *s_err = 1;
+                sd[0] = PH_EXIT;
+            }
+        }
+        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        long long d[8];
+        for (int i = 0; i < 8; ++i) d[i] = sd[i];
+        if (d[0] == PH_EXIT) break;
+        run_posted<H>(g, d, sred);
+        grid_barrier(g, nwg, s_err);
+        if (*s_err) break;
+    }
+}
+
+template <int H>
+__device__ void scan_leader(const ScanArgs& g, long long (*sred)[4], long long* sh, int64_t* s_err) {
+    const unsigned nwg = gridDim.x;
+    const bool grid = nwg > 1;
+    const int64_t t = threadIdx.x, w = threadIdx.x >> 6;
     const int64_t n = g.n;
-    if (threadIdx.x == 0) s_err = 0;
-    __syncthreads();
     int ph = 0;
-    int64_t S0 = 0, fb = 0, ng = 0, rounds = 0, verifs = 0;
+    unsigned posted = 0, beat = 0;
+    int64_t S0 = 0, fb = 0, kS0 = 0, kfb = 0, ng = 0, rounds = 0, verifs = 0;
     long long minH = 0;
-    bool hasH = false;
-    bool failed = false;
+    bool hasH = false, failed = false;
     while (S0 < n && !failed) {
         ++rounds;
         bool accepted = false, stop = false;
         int64_t from = S0, accb = -1;
         long long mnS = 0, mxS = 0;
-        int64_t win = 4 * nthr;  // grows while windows come back empty
+        int64_t win = 4 * kRT;  // grows while windows come back empty
         while (!accepted && !stop && from < n && !failed) {
-            // phase: first event in [from, from + win): a stop position
-            // (T >= minH) or a candidate boundary
+            heartbeat(g, beat);
+            // first event in [from, hi)
             const int64_t hi = min(n, from + win);
-            long long first = LLONG_MAX;
-            for (int64_t j = from + gt; j < hi; j += nthr) {
-                bool ev = hasH && g.T[j] >= minH;
-                if (!ev && g.inI[j]) ev = (j + 1 == n) || (g.R[j + 1] < g.T[j]);
-                if (ev) {
-                    first = j;
-                    break;  // later positions of this thread are larger
-                }
+            if (grid && hi - from > g.lead_pos) {
+                const long long d[8] = {PH_SEARCH, ph, from, hi, hasH ? 1 : 0, minH, 0, 0};
+                post_phase(g, posted, d);
+                run_posted<H>(g, d, sred);
+                grid_barrier(g, nwg, s_err);
+                gather_partials(g, ph, nwg, sh);
+            } else {
+                const long long first = search_part(g, from, hi, hasH, minH, t, kRT);
+                reduce_local(first, LLONG_MIN, LLONG_MIN, LLONG_MAX, sred, sh);
             }
-            put_partial(g, ph, first, LLONG_MIN, LLONG_MIN, LLONG_MAX, sred);
-            PROF_MARK(0);
-            grid_barrier(g, nwg, &s_err);
-            PROF_MARK(1);
-            gather_partials(g, ph, nwg, sh);
             ++ph;
-            failed = s_err != 0;
+            failed = *s_err != 0;
             const long long e = sh[0];
             if (failed) break;
             if (e == LLONG_MAX) {
@@ -840,35 +977,38 @@ __global__ __launch_bounds__(kRT) void k_sg_scan(ScanArgs g) {
             }
             const int64_t b = e + 1;
             ++verifs;
-            // phase: positions [fb, b) join the pending group S = [S0, b);
-            // the frontier of the loads below and the end of S always
-            // coincide: both start at the accepted boundary and move to every
-            // verified b
-            update_walk<H>(g, S0, fb, b);
+            // positions [fb, b) join the pending group S = [S0, b); the
+            // frontier of the loads below and the end of S always coincide:
+            // both start at the accepted boundary and move to every verified b
+            const int64_t k1 = g.P[b];
+            if (grid && k1 - kfb > g.lead_recs) {
+                const long long d[8] = {PH_UPDATE, ph, S0, fb, b, kfb, k1, 0};
+                post_phase(g, posted, d);
+                run_posted<H>(g, d, sred);
+                grid_barrier(g, nwg, s_err);
+            } else {
+                update_walk<H>(g, S0, fb, b, kfb, k1, w, kRW);
+                __syncthreads();
+            }
             fb = b;
-            PROF_MARK(2);
-            grid_barrier(g, nwg, &s_err);
-            PROF_MARK(3);
-            // phase: min and max of the restricted loads of S, and the
-            // largest restricted load below b
-            long long vmn = LLONG_MAX, vmx = LLONG_MIN, fmx = LLONG_MIN;
-            for (int64_t j = S0 + gt; j < b; j += nthr) {
-                const long long v = (long long)g.V[j];
-                vmn = min(vmn, v);
-                vmx = max(vmx, v);
+            kfb = k1;
+            failed = *s_err != 0;
+            if (failed) break;
+            // min and max of the restricted loads of S, largest load below b
+            const int64_t mm = (b - S0) + (b < n ? g.nblk - b / kFB : 0);
+            if (grid && mm > g.lead_pos) {
+                const long long d[8] = {PH_MINMAX, ph, S0, b, 0, 0, 0, 0};
+                post_phase(g, posted, d);
+                run_posted<H>(g, d, sred);
+                grid_barrier(g, nwg, s_err);
+                gather_partials(g, ph, nwg, sh);
+            } else {
+                long long vmn, vmx, fmx;
+                minmax_part(g, S0, b, t, kRT, vmn, vmx, fmx);
+                reduce_local(vmn, vmx, fmx, LLONG_MAX, sred, sh);
             }
-            if (b < n) {
-                const int64_t bend = min(n, (b / kFB + 1) * kFB);
-                for (int64_t j = b + gt; j < bend; j += nthr) fmx = max(fmx, (long long)g.F[j]);
-                for (int64_t blk = b / kFB + 1 + gt; blk < g.nblk; blk += nthr) fmx = max(fmx, g.bmax[blk]);
-            }
-            put_partial(g, ph, vmn, vmx, fmx, LLONG_MAX, sred);
-            PROF_MARK(4);
-            grid_barrier(g, nwg, &s_err);
-            PROF_MARK(5);
-            gather_partials(g, ph, nwg, sh);
             ++ph;
-            failed = s_err != 0;
+            failed = *s_err != 0;
             if (failed) break;
             mnS = sh[0];
             mxS = sh[1];
@@ -883,36 +1023,51 @@ __global__ __launch_bounds__(kRT) void k_sg_scan(ScanArgs g) {
             }
         }
         if (!accepted || failed) break;  // the rest is never accepted: no bounds
-        const int64_t b = accb;
-        // phase: bounds of the accepted group and the change of T below it
-        for (int64_t j = S0 + gt; j < b; j += nthr) {
-            g.lo[g.order[j]] = mnS;
-            g.hi[g.order[j]] = mxS;
+        const int64_t b = accb;  // == fb, so P[b] == kfb
+        if (grid && (b - S0 > g.lead_pos || kfb - kS0 > g.lead_recs)) {
+            const long long d[8] = {PH_ACCEPT, ph, S0, b, kS0, kfb, mnS, mxS};
+            post_phase(g, posted, d);
+            run_posted<H>(g, d, sred);
+            grid_barrier(g, nwg, s_err);
+        } else {
+            accept_part<H>(g, S0, b, kS0, kfb, mnS, mxS, t, kRT, w, kRW);
+            __syncthreads();
         }
-        accept_walk<H>(g, S0, b);
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (threadIdx.x == 0) {
             g.groups[2 * ng] = S0;
             g.groups[2 * ng + 1] = b;
         }
         ++ng;
-        PROF_MARK(6);
-        grid_barrier(g, nwg, &s_err);
-        PROF_MARK(7);
-        failed = s_err != 0;
+        failed = *s_err != 0;
         minH = mnS;
         hasH = true;
         S0 = b;
+        kS0 = kfb;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (grid) {
+        const long long d[8] = {PH_EXIT, 0, 0, 0, 0, 0, 0, 0};
+        post_phase(g, posted, d);
+    }
+    if (threadIdx.x == 0) {
         g.info[0] = ng;
         g.info[1] = rounds;
         g.info[2] = verifs;
     }
+}
+
+template <int H>
+__global__ __launch_bounds__(kRT) void k_sg_scan(ScanArgs g) {
+    __shared__ long long sred[kRW][4];
+    __shared__ long long sh[4];
+    __shared__ int64_t s_err;
+    if (threadIdx.x == 0) s_err = 0;
+    __syncthreads();
+    if (blockIdx.x == 0)
+        scan_leader<H>(g, sred, sh, &s_err);
+    else
+        scan_helper<H>(g, sred, &s_err);
+    __syncthreads();
     if (threadIdx.x == 0 && s_err) g.info[3] = 1;
-#ifdef LDS_SCAN_PROF
-    if (blockIdx.x == 0 && threadIdx.x == 0)
-        for (int k = 0; k < 8; ++k) g.info[4 + k] = (int64_t)prof[k];
-#endif
 }
 
 template <int H>
@@ -1125,15 +1280,24 @@ void sg_stable_groups(Graph& g, int mode, hipStream_t s) {
         LDS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[1], k_sg_scan<3>, kRT, 0));
     }
     const int64_t resident = (int64_t)cus * std::max(1, per[mode == 2 ? 0 : 1]);
-    // few workgroups: each phase is small, and a barrier costs more the more
-    // workgroups meet at it
-    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>({resident, (int64_t)kScanMaxWG, (n + 16383) / 16384}));
+    // the helpers only join the large phases; a grid barrier costs more the
+    // more workgroups meet at it
+    auto env_i64 = [](const char* name, int64_t def) {
+        const char* v = std::getenv(name);
+        return (v && *v) ? std::max<int64_t>(0, std::atoll(v)) : def;
+    };
+    const int64_t wg_env = env_i64("LDS_SCAN_WG", 0);
+    const int64_t grid = std::max<int64_t>(
+        1, std::min<int64_t>({resident, wg_env ? wg_env : (int64_t)kScanMaxWG, wg_env ? resident : (n + 16383) / 16384}));
     groups.alloc(2 * n, s);
     info.alloc(16, s);
     part.alloc((size_t)2 * grid * 4, s);
-    bar.alloc(2, s);
+    bar.alloc(4, s);
+    DBuf<long long> desc;
+    desc.alloc(8, s);
     k_fill_i64<<<1, kT, 0, s>>>(info.p, 16, 0);
-    k_fill_i64<<<1, kT, 0, s>>>((int64_t*)bar.p, 1, 0);
+    k_fill_i64<<<1, kT, 0, s>>>((int64_t*)bar.p, 2, 0);
+    k_fill_i64<<<1, kT, 0, s>>>((int64_t*)desc.p, 8, 0);
     LDS_HIP(hipGetLastError());
     ScanArgs sa{};
     sa.a = a;
@@ -1152,6 +1316,9 @@ void sg_stable_groups(Graph& g, int mode, hipStream_t s) {
     sa.info = info.p;
     sa.part = part.p;
     sa.bar = bar.p;
+    sa.desc = desc.p;
+    sa.lead_recs = env_i64("LDS_SCAN_LEAD_RECS", kLeadRecs);
+    sa.lead_pos = env_i64("LDS_SCAN_LEAD_POS", kLeadPos);
     sa.P = P.p;
     sa.own = own.p;
     sa.rec2 = rec2.p;
@@ -1175,12 +1342,6 @@ void sg_stable_groups(Graph& g, int mode, hipStream_t s) {
     const int64_t ng = hinfo[0];
     q.rounds = hinfo[1];
     q.verifications = hinfo[2];
-#ifdef LDS_SCAN_PROF
-    std::fprintf(stderr, "[scan] grid %lld rounds %lld verifications %lld | ticks (100 MHz) search %lld+%lld update %lld+%lld minmax %lld+%lld accept %lld+%lld\n",
-                 (long long)grid, (long long)hinfo[1], (long long)hinfo[2], (long long)hinfo[4], (long long)hinfo[5],
-                 (long long)hinfo[6], (long long)hinfo[7], (long long)hinfo[8], (long long)hinfo[9], (long long)hinfo[10],
-                 (long long)hinfo[11]);
-#endif
     std::vector<int64_t> hg((size_t)2 * ng);
     if (ng > 0) {
         LDS_HIP(hipMemcpyAsync(hg.data(), groups.p, hg.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));

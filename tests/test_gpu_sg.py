@@ -75,6 +75,38 @@ def test_graphs(case):
     check_sg(n, s, d, mode, iters)
 
 
+# launch shapes of the scan: every phase posted to a grid of helpers, and a
+# mix where the leader keeps the small phases (the defaults give one
+# workgroup below 16384 vertices, so these graphs would not reach the grid)
+SHAPES = [
+    {"LDS_SCAN_WG": "8", "LDS_SCAN_LEAD_RECS": "0", "LDS_SCAN_LEAD_POS": "0"},
+    {"LDS_SCAN_WG": "3", "LDS_SCAN_LEAD_RECS": "300", "LDS_SCAN_LEAD_POS": "200"},
+    {"LDS_SCAN_WG": "2", "LDS_SCAN_LEAD_RECS": "4000", "LDS_SCAN_LEAD_POS": "1500"},
+]
+
+
+@pytest.mark.parametrize("shape", range(len(SHAPES)))
+@pytest.mark.parametrize("case", [0, 1, 2, 6])
+def test_grid_shapes(case, shape, monkeypatch):
+    """the leader / helper protocol of the scan, exact against the oracle"""
+    for k, v in SHAPES[shape].items():
+        monkeypatch.setenv(k, v)
+    kind, kw, mode, iters = CASES[case]
+    announce("sg grid", SHAPES[shape], kind, kw, mode, iters)
+    n, s, d = synth.erdos_renyi(**kw) if kind == "er" else (
+        synth.powerlaw_planted(**kw) if kind == "pl" else synth.holme_kim(**kw))
+    check_sg(n, s, d, mode, iters)
+
+
+@pytest.mark.parametrize("mode", [2, 3])
+def test_grid_shapes_lds_small(mode, monkeypatch):
+    for k, v in SHAPES[1].items():
+        monkeypatch.setenv(k, v)
+    n, s, d, _, iters, _ = synth.workload("lds_small")
+    announce("sg grid lds_small", mode)
+    check_sg(n, s, d, mode, iters)
+
+
 def test_empty_and_edgeless():
     for n in (0, 5):
         g = lds.lds_create_graph(n, np.zeros(0, np.int32), np.zeros(0, np.int32))
