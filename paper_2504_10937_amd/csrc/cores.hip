@@ -12,9 +12,13 @@
 // the smallest remaining count.  Remaining vertices are kept in a compacted
 // list, so each level costs in proportion to what is left.  The result is
 // unique, so it does not depend on the order of atomics.
+#include <algorithm>
 #include <climits>
+#include <cstdio>
+#include <cstdlib>
 
 #include "graph.hpp"
+#include "gridsync.hpp"
 
 namespace lds {
 
@@ -68,114 +72,61 @@ __global__ void k_init_triangles(const int32_t* tri, int64_t T, const uint8_t* a
     }
 }
 
-// Device-side counters of the level loop, read by the kernels themselves so
-// that a level's kernels are queued without host round trips (grid-stride
-// loops over counts held in memory).
-enum : int { C_NA = 0, C_F0 = 1, C_F1 = 2, C_K = 3, C_MIN = 4, C_NA2 = 5 };
-
-__global__ void k_level_begin(int32_t* ctr) {
-    ctr[C_MIN] = INT32_MAX;
-    ctr[C_F0] = 0;
-    ctr[C_NA2] = 0;
-}
-
-// smallest count among the remaining vertices
-__global__ void k_min_remaining(const int32_t* active, int32_t* ctr, const int32_t* cnt) {
-    const int32_t na = ctr[C_NA];
-    int32_t m = INT32_MAX;
-    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < na; i += (int64_t)gridDim.x * kT)
-        m = min(m, cnt[active[i]]);
-    for (int o = 32; o > 0; o >>= 1) m = min(m, __shfl_xor(m, o, 64));
-    if ((threadIdx.x & 63) == 0 && m != INT32_MAX) atomicMin(&ctr[C_MIN], m);
-}
-
-// the level: k, or the smallest remaining count when no vertex is at or below k
-__global__ void k_set_level(int32_t* ctr) {
-    const int32_t m = ctr[C_MIN];
-    if (m != INT32_MAX && m > ctr[C_K]) ctr[C_K] = m;
-}
-
-// remaining vertices with cnt <= k: core k, into the frontier
-__global__ void k_frontier(const int32_t* active, int32_t* ctr, const int32_t* cnt, int32_t* core, int32_t* front) {
-    const int32_t na = ctr[C_NA], k = ctr[C_K];
-    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < na; i += (int64_t)gridDim.x * kT) {
-        const int32_t v = active[i];
-        if (core[v] == kUnset && cnt[v] <= k) {
-            core[v] = k;
-            push(front, &ctr[C_F0], v);
-        }
-    }
-}
-
-__device__ inline void lower(int32_t* cnt, int32_t* core, int32_t w, int32_t k, int32_t* next, int32_t* nc) {
-    if (core[w] != kUnset) return;
-    const int32_t old = atomicSub(&cnt[w], 1);
-    if (old == k + 1) {
-        core[w] = k;
-        push(next, nc, w);
-    }
-}
-
-// one wave per frontier vertex; fc / nc are counters in memory
-__global__ void k_peel_edges(const int32_t* front, const int32_t* fcp, const int64_t* rowptr, const int32_t* col,
-                             int32_t* cnt, int32_t* core, const int32_t* ctr, int32_t* next, int32_t* ncp) {
-    const int lane = threadIdx.x & 63;
-    const int32_t fc = *fcp, k = ctr[C_K];
-    for (int64_t i = (int64_t)blockIdx.x * (kT / 64) + (threadIdx.x >> 6); i < fc; i += (int64_t)gridDim.x * (kT / 64)) {
-        const int32_t v = front[i];
-        for (int64_t s = rowptr[v] + lane; s < rowptr[v + 1]; s += 64) lower(cnt, core, col[s], k, next, ncp);
-    }
-}
-
-__global__ void k_peel_triangles(const int32_t* front, const int32_t* fcp, const int32_t* row_of, const int64_t* rp,
-                                 const int32_t* py, const int32_t* tos, uint32_t* talive, int32_t* cnt,
-                                 int32_t* core, const int32_t* ctr, int32_t* next, int32_t* ncp) {
-    const int lane = threadIdx.x & 63;
-    const int32_t fc = *fcp, k = ctr[C_K];
-    for (int64_t i = (int64_t)blockIdx.x * (kT / 64) + (threadIdx.x >> 6); i < fc; i += (int64_t)gridDim.x * (kT / 64)) {
-        const int32_t r = row_of[front[i]];
-        if (r < 0) continue;
-        for (int64_t s = rp[r] + lane; s < rp[r + 1]; s += 64) {
-            if (atomicExch(&talive[tos[s]], 0u) == 0u) continue;  // killed before
-            lower(cnt, core, py[2 * s], k, next, ncp);
-            lower(cnt, core, py[2 * s + 1], k, next, ncp);
-        }
-    }
-}
-
-__global__ void k_compact(const int32_t* active, int32_t* ctr, const int32_t* core, int32_t* out) {
-    const int32_t na = ctr[C_NA];
-    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < na; i += (int64_t)gridDim.x * kT) {
-        const int32_t v = active[i];
-        if (core[v] == kUnset) push(out, &ctr[C_NA2], v);
-    }
-}
-
-__global__ void k_level_end(int32_t* ctr) {
-    ctr[C_NA] = ctr[C_NA2];
-    ctr[C_K] += 1;
-}
+enum : int { C_NA = 0, C_K = 3 };
 
 __global__ void k_set(int32_t* p, int32_t v) { *p = v; }
 __global__ void k_fill8(int32_t* p) { p[threadIdx.x] = 0; }
+__global__ void k_fill16(int32_t* p, int32_t v) { p[threadIdx.x] = v; }
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (i < n) p[i] = v;
+}
 
 // The rest of the peeling in one workgroup once few vertices remain (small
 // graphs from the start, the dense cores of large ones, the residual graphs of
 // Pruning rule 2): the same levels, frontiers and cascades, separated by
-// workgroup barriers instead of host round trips.  Every level assigns a
-// vertex or jumps to a larger count, so the loops are bounded by the number
-// of remaining vertices; a bound that is ever reached raises err.
+// workgroup barriers.  The remaining vertices get local ids (their index in
+// the remaining list; loc maps a vertex to it, -1 for every other vertex), and
+// their counts, peeled flags, remaining lists and frontiers live in LDS, so a
+// level touches global memory only to walk the frontier's adjacency (and, for
+// triangles, to kill each triangle once).  Every level assigns a vertex or
+// jumps to a larger count, so the loops are bounded by the number of
+// remaining vertices; a bound that is ever reached raises err.
 constexpr int kTailT = 1024;
 constexpr int32_t kTailMax = 1 << 13;
+constexpr int kTailU = 4;  // slots per lane in flight in the adjacency walks
 
 template <bool TRI>
-__global__ __launch_bounds__(kTailT) void k_peel_tail(int32_t* act, int32_t* act2, int32_t na, int32_t k,
-                                                      int32_t* front, int32_t* next, const int64_t* rowptr,
-                                                      const int32_t* col, const int32_t* row_of, const int64_t* rp,
-                                                      const int32_t* py, const int32_t* tos, uint32_t* talive,
-                                                      int32_t* cnt, int32_t* core, int32_t* err) {
-    __shared__ int32_t sc[4];  // [0] frontier, [1] next, [2] minimum, [3] remaining
+__global__ __launch_bounds__(kTailT) void k_peel_tail(const int32_t* act, int32_t na, int32_t k, int32_t* loc,
+                                                      const int64_t* rowptr, const int32_t* col,
+                                                      const int32_t* row_of, const int64_t* rp, const int32_t* py,
+                                                      const int32_t* tos, uint32_t* talive, const int32_t* cnt,
+                                                      int32_t* core, int32_t* err) {
+    __shared__ int32_t lcnt[kTailMax];
+    __shared__ uint8_t gone[kTailMax];
+    __shared__ uint16_t lrem[2][kTailMax];  // remaining local ids, double-buffered
+    __shared__ uint16_t lfr[2][kTailMax];   // frontier of a cascade round / the next one
+    __shared__ int32_t sc[4];               // [0] frontier, [1] next, [2] minimum, [3] remaining
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    for (int32_t i = tid; i < na; i += kTailT) {
+        const int32_t v = act[i];
+        loc[v] = i;
+        lcnt[i] = cnt[v];
+        gone[i] = 0;
+        lrem[0][i] = (uint16_t)i;
+    }
+    __syncthreads();
+    // a remaining neighbour w of a peeled vertex loses one pattern; the
+    // decrement from k + 1 to k happens once and puts w into the next frontier
+    auto lower_local = [&](int32_t lw, uint16_t* nx) {
+        if (lw < 0 || gone[lw]) return;
+        if (atomicSub(&lcnt[lw], 1) == k + 1) {
+            gone[lw] = 1;
+            core[act[lw]] = k;
+            nx[atomicAdd(&sc[1], 1)] = (uint16_t)lw;
+        }
+    };
+    int cur = 0;
     const int64_t bound = 2 * (int64_t)na + 2;
     for (int64_t it = 0; na > 0; ++it) {
         if (it > bound) {
@@ -185,10 +136,11 @@ __global__ __launch_bounds__(kTailT) void k_peel_tail(int32_t* act, int32_t* act
         if (tid == 0) sc[0] = 0;
         __syncthreads();
         for (int32_t i = tid; i < na; i += kTailT) {
-            const int32_t v = act[i];
-            if (core[v] == kUnset && cnt[v] <= k) {
-                core[v] = k;
-                front[atomicAdd(&sc[0], 1)] = v;
+            const int32_t l = lrem[cur][i];
+            if (!gone[l] && lcnt[l] <= k) {
+                gone[l] = 1;
+                core[act[l]] = k;
+                lfr[0][atomicAdd(&sc[0], 1)] = (uint16_t)l;
             }
         }
         __syncthreads();
@@ -197,8 +149,8 @@ __global__ __launch_bounds__(kTailT) void k_peel_tail(int32_t* act, int32_t* act
             if (tid == 0) sc[2] = INT32_MAX;
             __syncthreads();
             for (int32_t i = tid; i < na; i += kTailT) {
-                const int32_t v = act[i];
-                if (core[v] == kUnset) atomicMin(&sc[2], cnt[v]);
+                const int32_t l = lrem[cur][i];
+                if (!gone[l]) atomicMin(&sc[2], lcnt[l]);
             }
             __syncthreads();
             const int32_t m = sc[2];
@@ -210,8 +162,7 @@ __global__ __launch_bounds__(kTailT) void k_peel_tail(int32_t* act, int32_t* act
             k = m;
             continue;
         }
-        int32_t* f = front;
-        int32_t* nx = next;
+        int f = 0;
         for (int64_t round = 0; fc > 0; ++round) {
             if (round > na) {
                 if (tid == 0) *err = 1;
@@ -219,54 +170,254 @@ __global__ __launch_bounds__(kTailT) void k_peel_tail(int32_t* act, int32_t* act
             }
             if (tid == 0) sc[1] = 0;
             __syncthreads();
+            uint16_t* nx = lfr[f ^ 1];
             for (int32_t i = wv; i < fc; i += kTailT / 64) {
-                const int32_t v = f[i];
+                const int32_t v = act[lfr[f][i]];
+                int64_t q0, q1;
                 if (!TRI) {
-                    for (int64_t q = rowptr[v] + lane; q < rowptr[v + 1]; q += 64) {
-                        const int32_t w = col[q];
-                        if (core[w] != kUnset) continue;
-                        if (atomicSub(&cnt[w], 1) == k + 1) {
-                            core[w] = k;
-                            nx[atomicAdd(&sc[1], 1)] = w;
-                        }
-                    }
+                    q0 = rowptr[v];
+                    q1 = rowptr[v + 1];
                 } else {
                     const int32_t r = row_of[v];
                     if (r < 0) continue;
-                    for (int64_t q = rp[r] + lane; q < rp[r + 1]; q += 64) {
-                        if (atomicExch(&talive[tos[q]], 0u) == 0u) continue;
-                        for (int j = 0; j < 2; ++j) {
-                            const int32_t w = py[2 * q + j];
-                            if (core[w] != kUnset) continue;
-                            if (atomicSub(&cnt[w], 1) == k + 1) {
-                                core[w] = k;
-                                nx[atomicAdd(&sc[1], 1)] = w;
-                            }
+                    q0 = rp[r];
+                    q1 = rp[r + 1];
+                }
+                for (int64_t qb = q0 + lane; qb < q1; qb += 64 * kTailU) {
+                    if (!TRI) {
+                        int32_t lw[kTailU];
+#pragma unroll
+                        for (int u = 0; u < kTailU; ++u) {
+                            const int64_t q = qb + 64 * u;
+                            lw[u] = q < q1 ? loc[col[q]] : -1;
+                        }
+#pragma unroll
+                        for (int u = 0; u < kTailU; ++u) lower_local(lw[u], nx);
+                    } else {
+                        bool live[kTailU];
+#pragma unroll
+                        for (int u = 0; u < kTailU; ++u) {
+                            const int64_t q = qb + 64 * u;
+                            live[u] = q < q1 && atomicExch(&talive[tos[q]], 0u) != 0u;  // killed once
+                        }
+                        int32_t lw[kTailU][2];
+#pragma unroll
+                        for (int u = 0; u < kTailU; ++u) {
+                            const int64_t q = qb + 64 * u;
+                            lw[u][0] = live[u] ? loc[py[2 * q]] : -1;
+                            lw[u][1] = live[u] ? loc[py[2 * q + 1]] : -1;
+                        }
+#pragma unroll
+                        for (int u = 0; u < kTailU; ++u) {
+                            lower_local(lw[u][0], nx);
+                            lower_local(lw[u][1], nx);
                         }
                     }
                 }
             }
             __syncthreads();
             fc = sc[1];
-            int32_t* tmp = f;
-            f = nx;
-            nx = tmp;
+            f ^= 1;
             __syncthreads();
         }
         if (tid == 0) sc[3] = 0;
         __syncthreads();
         for (int32_t i = tid; i < na; i += kTailT) {
-            const int32_t v = act[i];
-            if (core[v] == kUnset) act2[atomicAdd(&sc[3], 1)] = v;
+            const int32_t l = lrem[cur][i];
+            if (!gone[l]) lrem[cur ^ 1][atomicAdd(&sc[3], 1)] = (uint16_t)l;
         }
         __syncthreads();
         na = sc[3];
+        cur ^= 1;
+        ++k;
+        __syncthreads();
+    }
+}
+
+// The levels of the peeling in one cooperative launch while many vertices
+// remain: every workgroup works through each phase of a level and the
+// workgroups meet at a grid barrier between phases, instead of one host
+// round trip per level and per four cascade rounds.  A level is its cascade
+// rounds (peeling the frontier lowers its neighbours; a count that falls to
+// exactly k joins the next frontier) and one closing phase that compacts the
+// remaining vertices, takes the smallest remaining count and already pushes
+// the next level's frontier: after the cascade every remaining count is at
+// least k + 1, and exactly the vertices at k + 1 open level k + 1.  Only
+// when there are none does the level jump to the smallest count, with one
+// more phase for that frontier.  List counters live in a ring of four
+// indexed by the phase number: a phase pushes into slot ph & 3, which
+// workgroup 0 zeroed during phase ph - 1 (its previous value was read right
+// after barrier ph - 3, which every workgroup has passed by then).  Every
+// decision is taken from values read after a barrier, so control flow is
+// uniform.  It stops once at most tail_max vertices remain and leaves
+// (remaining count, level, which list is current) in ctr for the
+// one-workgroup tail.
+constexpr int kPT = 512;
+constexpr int64_t kPeelMaxWG = 64;
+// ctr words: results, the ring, and per level parity the smallest remaining
+// count (G_MIN) and the next frontier's counter (G_NF), written by a closing
+// phase and reset by the closing phase after next
+enum : int { G_NA = 1, G_K = 2, G_SWAP = 3, G_ERR = 4, G_PHASES = 5, G_RING = 8, G_MIN = 12, G_NF = 14 };
+
+struct PeelArgs {
+    const int64_t* rowptr;
+    const int32_t* col;
+    const int32_t* row_of;
+    const int64_t* rp;
+    const int32_t* py;
+    const int32_t* tos;
+    uint32_t* talive;
+    int32_t* cnt;
+    int32_t* core;
+    int32_t* act;
+    int32_t* act2;
+    int32_t* front;
+    int32_t* next;
+    int32_t* ctr;   // G_* words (16)
+    unsigned* bar;  // grid barrier counter
+    int64_t n;
+    int32_t na, k, tail_max;
+};
+
+__device__ inline void lower(int32_t* cnt, int32_t* core, int32_t w, int32_t k, int32_t* next, int32_t* nc) {
+    if (core[w] != kUnset) return;
+    const int32_t old = atomicSub(&cnt[w], 1);
+    if (old == k + 1) {  // the decrement from k + 1 to k happens once
+        core[w] = k;
+        push(next, nc, w);
+    }
+}
+
+template <bool TRI>
+__global__ __launch_bounds__(kPT) void k_peel_grid(PeelArgs a) {
+    __shared__ int64_t s_err;
+    if (threadIdx.x == 0) s_err = 0;
+    __syncthreads();
+    const unsigned nwg = gridDim.x;
+    const int64_t t = (int64_t)blockIdx.x * kPT + threadIdx.x, nthr = (int64_t)nwg * kPT;
+    const int64_t gw = t >> 6, nwave = nthr >> 6;
+    const int lane = threadIdx.x & 63;
+    int32_t* ring = a.ctr + G_RING;
+    int32_t *act = a.act, *act2 = a.act2;
+    int32_t *f = a.front, *nx = a.next;
+    int32_t na = a.na, k = a.k, fc = 0;
+    unsigned ph = 0;
+    bool bad = false, need_front = true;
+    auto zero_next = [&]() {
+        if (t == 0) ring[(ph + 1) & 3] = 0;
+    };
+    for (int64_t level = 0; na > a.tail_max && !bad; ++level) {
+        if (level > a.n) {
+            bad = true;
+            break;
+        }
+        if (need_front) {
+            // the smallest remaining count (first level: a phase of its own)
+            if (level == 0) {
+                int32_t m = INT32_MAX;
+                for (int64_t i = t; i < na; i += nthr) m = min(m, a.cnt[act[i]]);
+                for (int o = 32; o > 0; o >>= 1) m = min(m, __shfl_xor(m, o, 64));
+                if (lane == 0 && m != INT32_MAX) atomicMin(&a.ctr[G_MIN], m);
+                zero_next();
+                grid_sync(a.bar, nwg, &s_err);
+                ++ph;
+            }
+            const int32_t m = a.ctr[G_MIN + (level & 1)];
+            if (s_err || m == INT32_MAX) {
+                bad = true;
+                break;
+            }
+            if (m > k) k = m;
+            // phase: remaining vertices with cnt <= k get core k, into the frontier
+            int32_t* slot = ring + (ph & 3);
+            for (int64_t i = t; i < na; i += nthr) {
+                const int32_t v = act[i];
+                if (a.core[v] == kUnset && a.cnt[v] <= k) {
+                    a.core[v] = k;
+                    push(f, slot, v);
+                }
+            }
+            zero_next();
+            grid_sync(a.bar, nwg, &s_err);
+            fc = *slot;
+            ++ph;
+        }
+        for (int64_t round = 0; fc > 0 && !bad; ++round) {
+            if (s_err || round > na) {
+                bad = true;
+                break;
+            }
+            int32_t* slot = ring + (ph & 3);
+            for (int64_t i = gw; i < fc; i += nwave) {
+                const int32_t v = f[i];
+                if (!TRI) {
+                    for (int64_t q = a.rowptr[v] + lane; q < a.rowptr[v + 1]; q += 64)
+                        lower(a.cnt, a.core, a.col[q], k, nx, slot);
+                } else {
+                    const int32_t r = a.row_of[v];
+                    if (r < 0) continue;
+                    for (int64_t q = a.rp[r] + lane; q < a.rp[r + 1]; q += 64) {
+                        if (atomicExch(&a.talive[a.tos[q]], 0u) == 0u) continue;  // killed before
+                        lower(a.cnt, a.core, a.py[2 * q], k, nx, slot);
+                        lower(a.cnt, a.core, a.py[2 * q + 1], k, nx, slot);
+                    }
+                }
+            }
+            zero_next();
+            grid_sync(a.bar, nwg, &s_err);
+            fc = *slot;
+            ++ph;
+            int32_t* tmp = f;
+            f = nx;
+            nx = tmp;
+        }
+        if (bad) break;
+        // closing phase: compaction, the smallest remaining count, and the
+        // next level's frontier (remaining vertices at exactly k + 1), into
+        // the words of the next level's parity; the words of this level's
+        // parity were read two phases ago at the latest, so they are reset
+        // here for the level after next
+        int32_t* slot = ring + (ph & 3);
+        const int nl = (int)((level + 1) & 1);
+        if (t == 0) {
+            a.ctr[G_MIN + (nl ^ 1)] = INT32_MAX;
+            a.ctr[G_NF + (nl ^ 1)] = 0;
+        }
+        {
+            int32_t m = INT32_MAX;
+            for (int64_t i = t; i < na; i += nthr) {
+                const int32_t v = act[i];
+                if (a.core[v] != kUnset) continue;
+                push(act2, slot, v);
+                const int32_t c = a.cnt[v];
+                m = min(m, c);
+                if (c == k + 1) {
+                    a.core[v] = k + 1;
+                    push(f, &a.ctr[G_NF + nl], v);
+                }
+            }
+            for (int o = 32; o > 0; o >>= 1) m = min(m, __shfl_xor(m, o, 64));
+            if (lane == 0 && m != INT32_MAX) atomicMin(&a.ctr[G_MIN + nl], m);
+        }
+        zero_next();
+        grid_sync(a.bar, nwg, &s_err);
+        na = *slot;
+        fc = a.ctr[G_NF + nl];
+        ++ph;
         int32_t* tmp = act;
         act = act2;
         act2 = tmp;
         ++k;
-        __syncthreads();
+        need_front = fc == 0;
+        if (s_err) bad = true;
     }
+    if (t == 0) {
+        a.ctr[G_NA] = na;
+        a.ctr[G_K] = k;
+        a.ctr[G_SWAP] = (act == a.act) ? 0 : 1;
+        a.ctr[G_PHASES] = (int32_t)ph;
+    }
+    if (threadIdx.x == 0 && (bad || s_err)) a.ctr[G_ERR] = 1;
 }
 
 __global__ void k_alive_internal(const uint8_t* by_caller, const int32_t* orig_of, int64_t n, uint8_t* by_internal) {
@@ -313,61 +464,83 @@ void core_numbers_gpu(Graph& g, int mode, const uint8_t* alive, int32_t* core, h
     }
     LDS_HIP(hipGetLastError());
     const SweepPlan& tp = g.tri_plan;
-    // levels: one host read at the start of a level and one per four cascade
-    // rounds; the rest of a level is queued without waiting
-    const unsigned ge = std::min<unsigned>(grid_for(n, kT), 2048u);       // element loops
-    const unsigned gw = std::min<unsigned>(grid_for(n, kT / 64), 4096u);  // one wave per vertex
-    int32_t* fr[2] = {front.p, next.p};
     int32_t h[8];
-    auto read_ctr = [&]() {
-        LDS_HIP(hipMemcpyAsync(h, ctr.p, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    LDS_HIP(hipMemcpyAsync(h, ctr.p, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    LDS_HIP(hipStreamSynchronize(s));
+    int32_t na = h[C_NA], k = 0;
+    if (na > kTailMax) {  // the levels with many vertices: one cooperative launch
+        static int cus = 0, per[2] = {0, 0};
+        if (!cus) {
+            int dev = 0;
+            LDS_HIP(hipGetDevice(&dev));
+            LDS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+            LDS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[0], k_peel_grid<false>, kPT, 0));
+            LDS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[1], k_peel_grid<true>, kPT, 0));
+        }
+        // at most kPeelMaxWG workgroups, one per 16384 vertices; LDS_PEEL_WG
+        // overrides both (e.g. to run the grid protocol wide on small graphs)
+        const char* ev = std::getenv("LDS_PEEL_WG");
+        const int64_t forced = (ev && *ev) ? std::max<int64_t>(2, std::atoll(ev)) : 0;
+        const int64_t resident = (int64_t)cus * std::max(1, per[mode == 2 ? 0 : 1]);
+        const int64_t grid = std::max<int64_t>(
+            2, std::min<int64_t>({resident, forced ? forced : kPeelMaxWG, forced ? resident : (na + 16383) / 16384}));
+        LDS_CHECK(resident >= 2, ST_DEVICE, "core peeling: the device cannot hold a cooperative grid");
+        DBuf<int32_t> gc;
+        DBuf<unsigned> bar;
+        gc.alloc(16, s);
+        bar.alloc(2, s);
+        k_fill16<<<1, 16, 0, s>>>(gc.p, 0);
+        k_set<<<1, 1, 0, s>>>(gc.p + G_MIN, INT32_MAX);
+        k_set<<<1, 1, 0, s>>>(gc.p + G_MIN + 1, INT32_MAX);
+        k_fill16<<<1, 2, 0, s>>>((int32_t*)bar.p, 0);
+        LDS_HIP(hipGetLastError());
+        PeelArgs pa{};
+        pa.rowptr = g.rowptr.p;
+        pa.col = g.col.p;
+        pa.row_of = tp.own_row_of.p;
+        pa.rp = tp.rp;
+        pa.py = tp.py;
+        pa.tos = tp.own_tos.p;
+        pa.talive = talive.p;
+        pa.cnt = cnt.p;
+        pa.core = core;
+        pa.act = act.p;
+        pa.act2 = act2.p;
+        pa.front = front.p;
+        pa.next = next.p;
+        pa.ctr = gc.p;
+        pa.bar = bar.p;
+        pa.n = n;
+        pa.na = na;
+        pa.k = 0;
+        pa.tail_max = kTailMax;
+        void* kargs[] = {&pa};
+        LDS_HIP(hipLaunchCooperativeKernel(mode == 2 ? (const void*)k_peel_grid<false> : (const void*)k_peel_grid<true>,
+                                           dim3((unsigned)grid), dim3(kPT), kargs, 0, s));
+        int32_t hg[16];
+        LDS_HIP(hipMemcpyAsync(hg, gc.p, sizeof(hg), hipMemcpyDeviceToHost, s));
         LDS_HIP(hipStreamSynchronize(s));
-    };
-    for (int64_t level = 0;; ++level) {
-        read_ctr();
-        const int32_t na = h[C_NA], k = h[C_K];
-        if (na == 0) break;
-        LDS_CHECK(level <= n, ST_DEVICE, "core peeling: no progress");
-        if (na <= kTailMax) {  // the rest in one workgroup, no host round trips
-            k_set<<<1, 1, 0, s>>>(ctr.p + 7, 0);
-            if (mode == 2)
-                k_peel_tail<false><<<1, kTailT, 0, s>>>(act.p, act2.p, na, k, front.p, next.p, g.rowptr.p, g.col.p,
-                                                        nullptr, nullptr, nullptr, nullptr, nullptr, cnt.p, core,
-                                                        ctr.p + 7);
-            else
-                k_peel_tail<true><<<1, kTailT, 0, s>>>(act.p, act2.p, na, k, front.p, next.p, nullptr, nullptr,
-                                                       tp.own_row_of.p, tp.rp, tp.py, tp.own_tos.p, talive.p, cnt.p,
-                                                       core, ctr.p + 7);
-            LDS_HIP(hipGetLastError());
-            LDS_CHECK(d2h_i32(ctr.p + 7, s) == 0, ST_DEVICE, "core peeling: no progress");
-            break;
-        }
-        k_level_begin<<<1, 1, 0, s>>>(ctr.p);
-        k_min_remaining<<<ge, kT, 0, s>>>(act.p, ctr.p, cnt.p);
-        k_set_level<<<1, 1, 0, s>>>(ctr.p);
-        k_frontier<<<ge, kT, 0, s>>>(act.p, ctr.p, cnt.p, core, fr[0]);
+        LDS_CHECK(hg[G_ERR] == 0, ST_DEVICE, "core peeling: no progress or a grid barrier did not complete");
+        na = hg[G_NA];
+        k = hg[G_K];
+        if (std::getenv("LDS_PEEL_STATS"))
+            std::fprintf(stderr, "[peel] grid %lld phases %d left %d level %d\n", (long long)grid, hg[G_PHASES], na, k);
+        if (hg[G_SWAP]) std::swap(act.p, act2.p);
+    }
+    if (na > 0) {  // the rest in one workgroup
+        LDS_CHECK(na <= kTailMax, ST_DEVICE, "core peeling: too many vertices left for the one-workgroup tail");
+        DBuf<int32_t> loc;
+        loc.alloc(n, s);
+        k_fill_i32<<<grid_for(n, kT), kT, 0, s>>>(loc.p, n, -1);
+        k_set<<<1, 1, 0, s>>>(ctr.p + 7, 0);
+        if (mode == 2)
+            k_peel_tail<false><<<1, kTailT, 0, s>>>(act.p, na, k, loc.p, g.rowptr.p, g.col.p, nullptr, nullptr,
+                                                    nullptr, nullptr, nullptr, cnt.p, core, ctr.p + 7);
+        else
+            k_peel_tail<true><<<1, kTailT, 0, s>>>(act.p, na, k, loc.p, nullptr, nullptr, tp.own_row_of.p, tp.rp,
+                                                   tp.py, tp.own_tos.p, talive.p, cnt.p, core, ctr.p + 7);
         LDS_HIP(hipGetLastError());
-        for (int64_t r = 0;;) {
-            for (int j = 0; j < 4; ++j, ++r) {
-                const int cur = (int)(r & 1), nx = cur ^ 1;
-                k_set<<<1, 1, 0, s>>>(ctr.p + C_F0 + nx, 0);
-                if (mode == 2)
-                    k_peel_edges<<<gw, kT, 0, s>>>(fr[cur], ctr.p + C_F0 + cur, g.rowptr.p, g.col.p, cnt.p, core,
-                                                   ctr.p, fr[nx], ctr.p + C_F0 + nx);
-                else
-                    k_peel_triangles<<<gw, kT, 0, s>>>(fr[cur], ctr.p + C_F0 + cur, tp.own_row_of.p, tp.rp, tp.py,
-                                                       tp.own_tos.p, talive.p, cnt.p, core, ctr.p, fr[nx],
-                                                       ctr.p + C_F0 + nx);
-                LDS_HIP(hipGetLastError());
-            }
-            read_ctr();
-            if (h[C_F0 + (int)(r & 1)] == 0) break;  // the frontier the next round would take
-            LDS_CHECK(r <= (int64_t)na + 8, ST_DEVICE, "core peeling: no progress");
-        }
-        k_compact<<<ge, kT, 0, s>>>(act.p, ctr.p, core, act2.p);
-        k_level_end<<<1, 1, 0, s>>>(ctr.p);
-        LDS_HIP(hipGetLastError());
-        std::swap(act.p, act2.p);
+        LDS_CHECK(d2h_i32(ctr.p + 7, s) == 0, ST_DEVICE, "core peeling: no progress");
     }
 }
 

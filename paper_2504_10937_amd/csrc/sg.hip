@@ -41,6 +41,7 @@
 #include <climits>
 
 #include "graph.hpp"
+#include "gridsync.hpp"
 
 namespace lds {
 
@@ -428,7 +429,7 @@ __global__ __launch_bounds__(kT) void k_bmax_init(const int64_t* F, int64_t n, l
 constexpr int kRT = 512;                 // threads per workgroup of the scan
 constexpr int kRW = kRT / 64;
 constexpr int64_t kSearchWin = 1 << 20;  // largest window of positions searched in one phase
-constexpr unsigned kSpinLimit = 1u << 26;
+constexpr unsigned kSpinLimit = kGridSpinLimit;
 // defaults of the launch shape: at most kScanMaxWG workgroups (one per 16384
 // vertices), and the largest walk (records) and search window / min-max /
 // bounds range (positions) that the leader runs alone (a few trips of its
@@ -664,37 +665,7 @@ __global__ __launch_bounds__(kT) void k_slot_records(PassArgs a, const int64_t* 
     }
 }
 
-// Only thread 0 of a workgroup makes the device-scope release / acquire: on
-// a chip with several L2s these write back and invalidate the caches, which
-// the workgroup's threads share; the others order their accesses against it
-// with the workgroup barrier.  The arrival counter only grows (zeroed per
-// launch): a workgroup arriving at the k-th barrier draws a value in
-// [k nwg, (k+1) nwg) and waits until the counter reaches (k+1) nwg, so one
-// atomic per arrival and no separate generation word.
-__device__ inline void grid_barrier(const ScanArgs& g, unsigned nwg, int64_t* err) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __syncthreads();
-    if (nwg == 1) {  // one workgroup: its own barrier is enough
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        return;
-    }
-    if (threadIdx.x == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        const unsigned arrived = __hip_atomic_fetch_add(g.bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned target = (arrived / nwg + 1) * nwg;
-        unsigned spins = 0;
-        while ((int)(__hip_atomic_load(g.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) < 0) {
-            __builtin_amdgcn_s_sleep(2);
-            if (++spins > kSpinLimit) {
-                *err = 1;
-                break;
-            }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    }
-    __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
+__device__ inline void grid_barrier(const ScanArgs& g, unsigned nwg, int64_t* err) { grid_sync(g.bar, nwg, err); }
 
 // reduce the partial records of phase `ph` (4 values per workgroup: min,
 // max, max, min) into sh[0..3]

@@ -61,6 +61,17 @@ def test_whole_graph(name, mode):
     assert c.min() >= 0
 
 
+@pytest.mark.parametrize("wg", ["2", "7", "64"])
+@pytest.mark.parametrize("name,mode", [("holme_kim_20k", 3), ("powerlaw_30k", 2), ("powerlaw_30k", 3)])
+def test_grid_widths(name, mode, wg, monkeypatch):
+    """the levels with many vertices run as one cooperative launch; its
+    phases and counter ring give the same numbers at any grid width"""
+    monkeypatch.setenv("LDS_PEEL_WG", wg)
+    announce("core numbers grid", name, mode, wg)
+    n, s, d = GRAPHS[name]()
+    check(n, s, d, mode)
+
+
 @pytest.mark.parametrize("mode", [2, 3])
 @pytest.mark.parametrize("seed", [0, 1, 2])
 def test_induced_subgraph(mode, seed):
