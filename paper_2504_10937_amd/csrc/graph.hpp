@@ -152,6 +152,8 @@ void sort_rows(Graph& g, hipStream_t s);             // CSR rows ascending (tria
 // triangles.hip
 void list_triangles(Graph& g, hipStream_t s);
 void list_cliques4(Graph& g, hipStream_t s);  // lists triangles first if needed
+// per-vertex incident triangles (ascending), into host memory: trp (n + 1), tinc (3T)
+void vertex_triangle_lists(const Graph& g, int64_t* trp_host, int32_t* tinc_host, hipStream_t s);
 
 inline SweepPlan& plan_of(Graph& g, int mode) {
     return mode == 2 ? g.edge_plan : (mode == 3 ? g.tri_plan : g.clique_plan);

@@ -557,15 +557,12 @@ void HostGraph::load(const Graph& g, int mode, hipStream_t s) {
         LDS_HIP(hipMemcpyAsync(tri.data(), g.tri.p, 3 * g.T * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     }
     LDS_HIP(hipStreamSynchronize(s));
-    if (mode == 3) {
-        const int64_t T = (int64_t)tri.size() / 3;
-        trp.assign(n + 1, 0);
-        for (int64_t t = 0; t < 3 * T; ++t) trp[tri[t] + 1]++;
-        for (int64_t u = 0; u < n; ++u) trp[u + 1] += trp[u];
-        tinc.assign(3 * T, 0);
-        std::vector<int64_t> fill(trp.begin(), trp.end() - 1);
-        for (int64_t t = 0; t < T; ++t)
-            for (int j = 0; j < 3; ++j) tinc[fill[tri[3 * t + j]]++] = t;
+    trp.clear();
+    tinc.clear();
+    if (mode == 3) {  // each vertex's triangles, listed on the device
+        trp.resize(n + 1);
+        tinc.resize(tri.size());
+        vertex_triangle_lists(g, trp.data(), tinc.data(), s);
     }
 }
 

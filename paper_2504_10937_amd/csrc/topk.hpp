@@ -15,7 +15,7 @@ struct HostGraph {
     std::vector<int32_t> orig;  // internal -> caller id
     std::vector<int32_t> tri;   // 3T (triangles only)
     std::vector<int64_t> trp;   // n + 1 offsets into tinc
-    std::vector<int64_t> tinc;  // triangle indices incident to each vertex
+    std::vector<int32_t> tinc;  // triangle indices incident to each vertex (ascending)
     void load(const Graph& g, int mode, hipStream_t s);
 };
 

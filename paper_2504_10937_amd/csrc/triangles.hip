@@ -291,6 +291,47 @@ void build_incidence_plan(Graph& g, const int32_t* pat, int64_t np, const int32_
 
 }  // namespace
 
+namespace {
+// triangles at each vertex, from the incidence rows (a row's slots are in
+// ascending triangle order, so each list is too)
+__global__ void k_vtx_tcount(const int32_t* row_of, const int64_t* rp, int64_t n, uint64_t* cnt) {
+    const int64_t v = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (v >= n) return;
+    const int32_t r = row_of[v];
+    cnt[v] = r < 0 ? 0 : (uint64_t)(rp[r + 1] - rp[r]);
+}
+
+__global__ void k_vtx_tfill(const int32_t* rid, const int64_t* rp, int64_t nrows, const int32_t* tos,
+                            const uint64_t* off, int32_t* tinc) {
+    const int lane = threadIdx.x & 63;
+    const int64_t r = (int64_t)blockIdx.x * (kT / 64) + (threadIdx.x >> 6);
+    if (r >= nrows) return;
+    const int64_t base = (int64_t)off[rid[r]] - rp[r];
+    for (int64_t q = rp[r] + lane; q < rp[r + 1]; q += 64) tinc[base + q] = tos[q];
+}
+}  // namespace
+
+void vertex_triangle_lists(const Graph& g, int64_t* trp_host, int32_t* tinc_host, hipStream_t s) {
+    const int64_t n = g.n;
+    LDS_CHECK(g.T >= 0, ST_INVALID, "triangles are not listed");
+    if (n == 0) return;
+    const SweepPlan& p = g.tri_plan;
+    DBuf<uint64_t> off;
+    off.alloc(n + 1, s);
+    k_vtx_tcount<<<grid_for(n, kT), kT, 0, s>>>(p.own_row_of.p, p.rp, n, off.p);
+    LDS_HIP(hipGetLastError());
+    exclusive_scan_u64(off.p, off.p, n, off.p + n, s);
+    DBuf<int32_t> tinc;
+    tinc.alloc(3 * g.T, s);
+    if (g.T > 0 && p.nrows > 0) {
+        k_vtx_tfill<<<grid_for(p.nrows, kT / 64), kT, 0, s>>>(p.rid, p.rp, p.nrows, p.own_tos.p, off.p, tinc.p);
+        LDS_HIP(hipGetLastError());
+    }
+    LDS_HIP(hipMemcpyAsync(trp_host, off.p, (n + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    if (g.T > 0) LDS_HIP(hipMemcpyAsync(tinc_host, tinc.p, 3 * g.T * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    LDS_HIP(hipStreamSynchronize(s));
+}
+
 void list_triangles(Graph& g, hipStream_t s) {
     const int64_t n = g.n, ns = 2 * g.m;
     sort_rows(g, s);

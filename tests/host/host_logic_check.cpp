@@ -21,6 +21,7 @@ void dev_free(void*) {}
 Graph::~Graph() {}
 void build_graph(Graph&, int64_t, int64_t, const int32_t*, const int32_t*, bool, bool, hipStream_t) {}
 void list_triangles(Graph&, hipStream_t) {}
+void vertex_triangle_lists(const Graph&, int64_t*, int32_t*, hipStream_t) {}
 void sg_stable_groups(Graph&, int, hipStream_t) {}
 void fw_run(Graph&, int, int, bool, hipStream_t) {}
 void core_numbers_gpu(Graph&, int, const uint8_t*, int32_t*, hipStream_t) {}
