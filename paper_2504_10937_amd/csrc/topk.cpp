@@ -126,6 +126,30 @@ void par_for(int64_t n, F f) {
     for (auto& th : pool) th.join();
 }
 
+// f(u0, u1) over the rows [0, n) of a CSR with offsets rp, one contiguous
+// range of about equal slot count per granted thread (rows are in degree
+// order, so equal row counts would give the first thread every hub)
+template <class F>
+void par_for_rows(const std::vector<int64_t>& rp, int64_t n, F f) {
+    ThreadGrant grant(flow_threads());
+    const int T = grant.n;
+    if (T <= 1 || n < 4096) {
+        f((int64_t)0, n);
+        return;
+    }
+    std::vector<int64_t> cut(T + 1, n);
+    cut[0] = 0;
+    for (int k = 1; k < T; ++k) {
+        const int64_t want = rp[n] / T * k;
+        cut[k] = std::max(cut[k - 1], (int64_t)(std::lower_bound(rp.begin(), rp.begin() + n + 1, want) - rp.begin()));
+        cut[k] = std::min(cut[k], n);
+    }
+    std::vector<std::thread> pool;
+    for (int k = 1; k < T; ++k) pool.emplace_back([&, k] { f(cut[k], cut[k + 1]); });
+    f(cut[0], cut[1]);
+    for (auto& th : pool) th.join();
+}
+
 // Network with arcs in CSR order (arcs of a node are contiguous, each with
 // the index of its reverse arc).  Arcs are collected with arc() and laid out
 // by finalize().
@@ -541,16 +565,32 @@ void topk_single_thread(bool on) { g_single = on; }
 bool topk_threads_single() { return g_single; }
 
 // ----------------------------------------------------------- host graph
+namespace {
+// device -> host copy of count elements into v: the destination pages are
+// faulted in by the granted host threads first (one write per page), then
+// one copy fills them
+template <class V>
+void d2h_fill(V& v, const void* dev, size_t count, hipStream_t s) {
+    v.resize(count);
+    if (count == 0) return;
+    char* p = (char*)v.data();
+    const size_t bytes = count * sizeof(v[0]);
+    par_for((int64_t)((bytes + 4095) / 4096), [&](int64_t a, int64_t b) {
+        for (int64_t i = a; i < b; ++i) p[(size_t)i * 4096] = 0;
+    });
+    LDS_HIP(hipMemcpyAsync(p, dev, bytes, hipMemcpyDeviceToHost, s));
+}
+}  // namespace
+
 void HostGraph::load(const Graph& g, int mode, hipStream_t s) {
     n = g.n;
     rp.assign(n + 1, 0);
-    col.assign(2 * g.m, 0);
     orig.assign(n, 0);
     if (n > 0) {
         LDS_HIP(hipMemcpyAsync(rp.data(), g.rowptr.p, (n + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
         LDS_HIP(hipMemcpyAsync(orig.data(), g.orig_of.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     }
-    if (g.m > 0) LDS_HIP(hipMemcpyAsync(col.data(), g.col.p, 2 * g.m * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    d2h_fill(col, g.col.p, (size_t)(2 * g.m), s);
     tri.clear();
     if (mode == 3 && g.T > 0) {
         tri.assign(3 * g.T, 0);
@@ -612,7 +652,7 @@ struct Ctx {
     std::vector<Frac> lo, hi;     // bounds on phi_G, valid for every vertex
     std::vector<int32_t> loc;     // scratch: internal id -> local index, -1 outside
     std::vector<int32_t> mark;    // scratch, -1 outside
-    std::vector<uint32_t> split;  // FW split numerators over splitD: edges per CSR slot, triangles 3 per triangle
+    host_vec<uint32_t> split;     // FW split numerators over splitD: edges per CSR slot, triangles 3 per triangle
     int64_t splitD = 1;
     TopkStats* st = nullptr;
     int64_t seq = 0;
@@ -957,14 +997,12 @@ void topk_run(Graph& g, int mode, int k, int iters, hipStream_t s, std::vector<T
     // for triangles), for warm-started min cuts
     if (mode == 2 && g.m > 0) {
         const SgState& q = g.sg[0];
-        c.split.resize(2 * g.m);
-        LDS_HIP(hipMemcpyAsync(c.split.data(), q.a_slot.p, 2 * g.m * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        d2h_fill(c.split, q.a_slot.p, (size_t)(2 * g.m), s);
         LDS_HIP(hipStreamSynchronize(s));
         c.splitD = (int64_t)fw_denom(2, iters);
     } else if (mode == 3 && g.T > 0) {
         const SgState& q = g.sg[1];
-        c.split.resize(3 * g.T);
-        LDS_HIP(hipMemcpyAsync(c.split.data(), q.a_tri.p, 3 * g.T * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        d2h_fill(c.split, q.a_tri.p, (size_t)(3 * g.T), s);
         LDS_HIP(hipStreamSynchronize(s));
         c.splitD = (int64_t)fw_denom(3, iters);
     }
@@ -988,22 +1026,29 @@ void topk_run(Graph& g, int mode, int k, int iters, hipStream_t s, std::vector<T
         c.scope = &scope;
     }
     lap(&st.ms_fw);
-    // Pruning (Alg. 3): rule 1, then rule 2 on the residual graph
-    for (int64_t u = 0; u < n; ++u)
-        for (int64_t e = c.h.rp[u]; e < c.h.rp[u + 1]; ++e)
-            if (lt(c.hi[u], c.lo[c.h.col[e]])) {
-                alive[u] = 0;
-                break;
-            }
+    // Pruning (Alg. 3): rule 1, then rule 2 on the residual graph (vertex
+    // ranges over the host threads; each writes only its own vertices)
+    par_for_rows(c.h.rp, n, [&](int64_t u0, int64_t u1) {
+        for (int64_t u = u0; u < u1; ++u)
+            for (int64_t e = c.h.rp[u]; e < c.h.rp[u + 1]; ++e)
+                if (lt(c.hi[u], c.lo[c.h.col[e]])) {
+                    alive[u] = 0;
+                    break;
+                }
+    });
     for (;;) {
         const std::vector<int32_t> cr = device_cores(g, mode, &alive, s);
-        bool changed = false;
-        for (int64_t u = 0; u < n; ++u)
-            if (alive[u] && lt(Frac{cr[u], 1}, c.lo[u])) {
-                alive[u] = 0;
-                changed = true;
-            }
-        if (!changed) break;
+        std::atomic<bool> changed{false};
+        par_for(n, [&](int64_t u0, int64_t u1) {
+            bool ch = false;
+            for (int64_t u = u0; u < u1; ++u)
+                if (alive[u] && lt(Frac{cr[u], 1}, c.lo[u])) {
+                    alive[u] = 0;
+                    ch = true;
+                }
+            if (ch) changed.store(true, std::memory_order_relaxed);
+        });
+        if (!changed.load()) break;
     }
     for (int64_t u = 0; u < n; ++u) st.pruned += alive[u] ? 0 : 1;
     lap(&st.ms_prune);

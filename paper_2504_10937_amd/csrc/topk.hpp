@@ -1,5 +1,7 @@
 // Host side of the top-k LDS / LTDS driver (Alg. 5 and its triangle version).
 #pragma once
+#include <memory>
+#include <utility>
 #include <vector>
 
 #include "graph.hpp"
@@ -8,10 +10,34 @@ namespace lds {
 
 // Host copy of the adjacency (internal ids) and, for triangles, the triangle
 // list with per-vertex incidence lists.
+// Allocator whose value-initialisation leaves memory untouched, for host
+// copies of large device arrays: their pages are faulted in once, by several
+// threads, instead of being zero-filled and then overwritten.
+template <class T>
+struct NoInit : std::allocator<T> {
+    template <class U>
+    struct rebind {
+        using other = NoInit<U>;
+    };
+    NoInit() = default;
+    template <class U>
+    NoInit(const NoInit<U>&) noexcept {}
+    template <class U>
+    void construct(U* p) noexcept {
+        ::new ((void*)p) U;
+    }
+    template <class U, class... A>
+    void construct(U* p, A&&... a) {
+        ::new ((void*)p) U(std::forward<A>(a)...);
+    }
+};
+template <class T>
+using host_vec = std::vector<T, NoInit<T>>;
+
 struct HostGraph {
     int64_t n = 0;
     std::vector<int64_t> rp;    // n + 1
-    std::vector<int32_t> col;   // 2m neighbours
+    host_vec<int32_t> col;      // 2m neighbours
     std::vector<int32_t> orig;  // internal -> caller id
     std::vector<int32_t> tri;   // 3T (triangles only)
     std::vector<int64_t> trp;   // n + 1 offsets into tinc
