@@ -2,6 +2,8 @@
 // undirected simple graph), degree renumbering, symmetric CSR and the sweep
 // plan (hub rows, row-aligned chunks, word offsets and row-start flags) that
 // the Frank-Wolfe kernels stream over.
+#include <rocprim/device/device_segmented_radix_sort.hpp>
+
 #include "graph.hpp"
 
 namespace lds {
@@ -106,24 +108,6 @@ __global__ void k_permute(const uint64_t* sk, int64_t ns, int vbits, const int64
 }
 
 // (row, col) keys of the internal CSR, for sorting every row ascending
-__global__ void k_row_col_keys(const int64_t* rowptr, const int32_t* col, int64_t n, int64_t ns, int vbits,
-                               uint64_t* keys) {
-    const int64_t s = (int64_t)blockIdx.x * kT + threadIdx.x;
-    if (s >= ns) return;
-    int64_t lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi + 1) >> 1;
-        if (rowptr[mid] <= s) lo = mid; else hi = mid - 1;
-    }
-    keys[s] = ((uint64_t)lo << vbits) | (uint64_t)col[s];
-}
-
-__global__ void k_key_cols(const uint64_t* keys, int64_t ns, int vbits, int32_t* col) {
-    const int64_t s = (int64_t)blockIdx.x * kT + threadIdx.x;
-    if (s >= ns) return;
-    col[s] = (int32_t)(keys[s] & ((1ull << vbits) - 1));
-}
-
 __global__ void k_set_last(int64_t* rowptr, int64_t idx, const uint64_t* total) { rowptr[idx] = (int64_t)*total; }
 
 // ------------------------------------------------------------- sweep plan
@@ -436,14 +420,22 @@ void sort_rows(Graph& g, hipStream_t s) {
     if (g.col_sorted) return;
     const int64_t ns = 2 * g.m;
     if (ns > 0) {
-        DBuf<uint64_t> k, t;
-        k.alloc(ns, s);
-        t.alloc(ns, s);
-        k_row_col_keys<<<grid_for(ns, kT), kT, 0, s>>>(g.rowptr.p, g.col.p, g.n, ns, g.vbits, k.p);
-        LDS_HIP(hipGetLastError());
-        radix_sort_u64(k.p, nullptr, ns, 2 * g.vbits, t.p, nullptr, s);
-        k_key_cols<<<grid_for(ns, kT), kT, 0, s>>>(k.p, ns, g.vbits, g.col.p);
-        LDS_HIP(hipGetLastError());
+        // each row is a segment of keys below 2^vbits: a segmented radix sort
+        // (small segments sorted in registers / LDS, large ones by passes)
+        // instead of a global sort of (row, column) keys
+        LDS_CHECK(ns < (int64_t)UINT32_MAX, ST_OVERFLOW, "too many slots for the row sort");
+        DBuf<int32_t> out;
+        out.alloc(ns, s);
+        size_t bytes = 0;
+        LDS_HIP(rocprim::segmented_radix_sort_keys(nullptr, bytes, (const uint32_t*)g.col.p, (uint32_t*)out.p,
+                                                   (unsigned)ns, (unsigned)g.n, g.rowptr.p, g.rowptr.p + 1, 0u,
+                                                   (unsigned)g.vbits, s));
+        DBuf<uint8_t> tmp;
+        tmp.alloc(bytes > 0 ? bytes : 1, s);
+        LDS_HIP(rocprim::segmented_radix_sort_keys(tmp.p, bytes, (const uint32_t*)g.col.p, (uint32_t*)out.p,
+                                                   (unsigned)ns, (unsigned)g.n, g.rowptr.p, g.rowptr.p + 1, 0u,
+                                                   (unsigned)g.vbits, s));
+        std::swap(g.col, out);
     }
     g.col_sorted = true;
 }
