@@ -1,8 +1,8 @@
 """Write a short markdown summary of rocprofv3 output for one kernel.
 
-usage: python profiles/make_summary.py <kernel substring> <out.md> <command string>
+usage: python -m paper_2504_10937_amd.profsummary <kernel substring> <out.md> <command string>
        <kernel_stats.csv> [<fetch counter_collection.csv> <write counter_collection.csv>]
-       python profiles/make_summary.py --top <N> <out.md> <title> <command string> <kernel_stats.csv>
+       python -m paper_2504_10937_amd.profsummary --top <N> <out.md> <title> <command string> <kernel_stats.csv>
 
 The FETCH_SIZE / WRITE_SIZE passes must come from runs that first launched a
 device copy of known size (bench.py --copy-calib-mib); the copy's counters
@@ -47,8 +47,7 @@ def main():
         return top(int(sys.argv[2]), *sys.argv[3:7])
     kernel, out, cmd, stats = sys.argv[1:5]
     rows = [r for r in csv.DictReader(open(stats)) if kernel in r["Name"]]
-    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-    src = open(os.path.join(root, "paper_2504_10937_amd", "csrc", "fw.hip"), "rb").read()
+    src = open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "fw.hip"), "rb").read()
     lines = ["# rocprofv3 summary: %s" % kernel, "",
              "kernel source sha256[:16]: `%s` (paper_2504_10937_amd/csrc/fw.hip)" % hashlib.sha256(src).hexdigest()[:16],
              "", "command: `%s`" % cmd, "", "| kernel | calls | avg ns | min ns | max ns | total % |", "|---|---|---|---|---|---|"]
