@@ -632,6 +632,39 @@ __device__ inline void accept_walk(const ScanArgs& g, int64_t S0, int64_t b, int
     }
 }
 
+// R_x (every earlier vertex above x) and T_x for S0 = 0 (S = [0, x]), from
+// the records in one streaming pass: each record's pattern gives its own
+// vertex its share under those two cuts of the order, summed per position
+// (segmented over the lanes of a row, one atomic per position; R and T start
+// at zero, and positions without records keep it)
+template <int H>
+__global__ __launch_bounds__(kT) void k_rt_records(ScanArgs g, int64_t ns, int64_t* R, int64_t* T) {
+    constexpr int U = 4;
+    const int lane = threadIdx.x & 63;
+    const int64_t gw = ((int64_t)blockIdx.x * kT + threadIdx.x) >> 6, nwave = ((int64_t)gridDim.x * kT) >> 6;
+    const uint64_t D = g.a.D;
+    for (int64_t kb = gw * 64 * U; kb < ns; kb += nwave * 64 * U) {
+        int64_t p[U][H], al[U][H];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t k = kb + 64 * u + lane;
+            if (k < ns) rec_pattern<H>(g, k, p[u], al[u]);
+            else p[u][0] = -1;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            int64_t r = 0, t = 0;
+            if (p[u][0] >= 0) {
+                r = pat_contrib<H>(0, p[u], al[u], D, p[u][0], p[u][0]);
+                t = pat_contrib<H>(0, p[u], al[u], D, 0, p[u][0] + 1);
+            }
+            add_by_position(R, (int32_t)p[u][0], r);
+            add_by_position(T, (int32_t)p[u][0], t);
+        }
+    }
+}
+
+
 // slots per position (rows are vertices with slots; the rest stay 0)
 __global__ void k_pos_slots(PassArgs a, uint64_t* cnt) {
     const int64_t r = (int64_t)blockIdx.x * kT + threadIdx.x;
@@ -1193,15 +1226,6 @@ void sg_stable_groups(Graph& g, int mode, hipStream_t s) {
     a.a_tri = q.a_tri.p;
     a.pos = q.pos.p;
     a.D = fw_denom(mode, f.iters);
-    // R_w: w's restricted load when every earlier vertex is above it
-    a.kind = PASS_R;
-    a.out = R.p;
-    run_pass(g, mode, a, s);
-    // T_x for S0 = 0; afterwards maintained incrementally by the scan
-    a.kind = PASS_T;
-    a.S0 = 0;
-    a.out = T.p;
-    run_pass(g, mode, a, s);
     a = plan_args(g, mode, a);
 
     // slot records and the row of every position
@@ -1227,6 +1251,20 @@ void sg_stable_groups(Graph& g, int mode, hipStream_t s) {
             k_slot_records<2><<<grid_for(pl.nrows, 4), kT, 0, s>>>(a, P.p, own.p, rec2.p, rec3.p, rec3w.p);
         else
             k_slot_records<3><<<grid_for(pl.nrows, 4), kT, 0, s>>>(a, P.p, own.p, rec2.p, rec3.p, rec3w.p);
+        LDS_HIP(hipGetLastError());
+        // R_w (w's restricted load when every earlier vertex is above it) and
+        // T_x for S0 = 0; T is afterwards maintained incrementally by the scan
+        ScanArgs ra{};
+        ra.a = a;
+        ra.own = own.p;
+        ra.rec2 = rec2.p;
+        ra.rec3 = rec3.p;
+        ra.rec3w = rec3w.p;
+        const unsigned rg = std::min<unsigned>(grid_for(pl.nslots, kT * 4), 8192u);
+        if (mode == 2)
+            k_rt_records<2><<<rg, kT, 0, s>>>(ra, pl.nslots, R.p, T.p);
+        else
+            k_rt_records<3><<<rg, kT, 0, s>>>(ra, pl.nslots, R.p, T.p);
     }
     LDS_HIP(hipGetLastError());
 
