@@ -14,7 +14,6 @@
 // unique, so it does not depend on the order of atomics.
 #include <algorithm>
 #include <climits>
-#include <cstdio>
 #include <cstdlib>
 
 #include "graph.hpp"
@@ -257,7 +256,7 @@ constexpr int64_t kPeelMaxWG = 64;
 // ctr words: results, the ring, and per level parity the smallest remaining
 // count (G_MIN) and the next frontier's counter (G_NF), written by a closing
 // phase and reset by the closing phase after next
-enum : int { G_NA = 1, G_K = 2, G_SWAP = 3, G_ERR = 4, G_PHASES = 5, G_RING = 8, G_MIN = 12, G_NF = 14 };
+enum : int { G_NA = 1, G_K = 2, G_SWAP = 3, G_ERR = 4, G_RING = 8, G_MIN = 12, G_NF = 14 };
 
 struct PeelArgs {
     const int64_t* rowptr;
@@ -415,7 +414,6 @@ __global__ __launch_bounds__(kPT) void k_peel_grid(PeelArgs a) {
         a.ctr[G_NA] = na;
         a.ctr[G_K] = k;
         a.ctr[G_SWAP] = (act == a.act) ? 0 : 1;
-        a.ctr[G_PHASES] = (int32_t)ph;
     }
     if (threadIdx.x == 0 && (bad || s_err)) a.ctr[G_ERR] = 1;
 }
@@ -523,8 +521,6 @@ void core_numbers_gpu(Graph& g, int mode, const uint8_t* alive, int32_t* core, h
         LDS_CHECK(hg[G_ERR] == 0, ST_DEVICE, "core peeling: no progress or a grid barrier did not complete");
         na = hg[G_NA];
         k = hg[G_K];
-        if (std::getenv("LDS_PEEL_STATS"))
-            std::fprintf(stderr, "[peel] grid %lld phases %d left %d level %d\n", (long long)grid, hg[G_PHASES], na, k);
         if (hg[G_SWAP]) std::swap(act.p, act2.p);
     }
     if (na > 0) {  // the rest in one workgroup
