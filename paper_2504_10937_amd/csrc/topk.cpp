@@ -155,6 +155,10 @@ void par_for_rows(const std::vector<int64_t>& rp, int64_t n, F f) {
 // by finalize().
 struct Flow {
     int64_t N;
+    // the synchronous parallel push-relabel (pflow.hpp) is used for large
+    // vertex networks; on pattern networks, whose pattern-to-member arcs are
+    // unbounded, it ran several times slower than the sequential one
+    bool allow_parallel = true;
     std::vector<int64_t> pa, pb, pc, pd;  // pending arcs: tail, head, capacity, reverse capacity
     std::vector<int64_t> first, cap, rev;
     std::vector<int32_t> to;
@@ -248,7 +252,7 @@ struct Flow {
     // already reached t; nullptr = start from zero flow
     int64_t maxflow(int64_t s, int64_t t, const std::vector<int64_t>* init_ex = nullptr, int64_t init_t = 0) {
         finalize();
-        ThreadGrant grant(N >= flow_parallel_min_nodes() ? flow_threads() : 1);
+        ThreadGrant grant(allow_parallel && N >= flow_parallel_min_nodes() ? flow_threads() : 1);
         const int threads = grant.n;
         if (threads > 1) {
             std::vector<int64_t> ex(N, 0);
@@ -502,6 +506,7 @@ int64_t max_excess(int64_t k, int h, const std::vector<int32_t>& pat, int64_t p,
     const int64_t np = (int64_t)pat.size() / h;
     const int64_t S = np + k, T = S + 1;
     Flow f(T + 1);
+    f.allow_parallel = false;
     const int64_t INF = INT64_MAX / 4;
     const bool warm = split && D > 0 && (int64_t)split->size() == h * np &&
                       (i128)q * D * (np + 1) + (i128)p * D * (k + 1) < ((i128)1 << 61);

@@ -7,8 +7,9 @@
 //     maximisers, by enumeration of every X.
 // (Core and tr-core numbers run on the device; their parity is a GPU test.)
 // The battery runs twice: with the sequential push-relabel and with every
-// network through the parallel one (pflow.hpp); larger random networks then
-// compare the two directly.
+// vertex network through the parallel one (pflow.hpp; pattern networks always
+// take the sequential one); larger random networks then compare the two
+// directly.
 // Prints "ok" and exits 0 when every case agrees.
 #include "../../paper_2504_10937_amd/csrc/topk.cpp"
 
@@ -167,7 +168,7 @@ int main() {
     g_flow_threads = 4;
     g_flow_parallel_min = 1 << 30;  // sequential push-relabel
     bad += battery(cases);
-    g_flow_parallel_min = 0;  // every network through the parallel one
+    g_flow_parallel_min = 0;  // every vertex network through the parallel one
     bad += battery(cases);
     bad += parallel_vs_sequential(cases);
     std::printf("%s: %d of %d cases disagree\n", bad ? "FAIL" : "ok", bad, cases);
