@@ -288,9 +288,11 @@ typedef struct {
  * by FW + ExtractSG on its induced subgraph (or by the min cut when that does
  * not split it).  Returns the k densest LDSs (fewer when the graph has fewer
  * with positive density).  Synchronises the stream: verification runs on the
- * host; min cuts of networks with at least 524288 nodes use a parallel
- * push-relabel on up to 16 host threads (environment: LDS_FLOW_THREADS sets
- * the thread count, 1 = sequential; LDS_FLOW_PARALLEL_MIN the node count).
+ * host; min cuts of vertex networks (LDS_EDGE) with at least 524288 nodes
+ * use a parallel push-relabel on up to 16 host threads (environment:
+ * LDS_FLOW_THREADS sets the thread count, 1 = sequential;
+ * LDS_FLOW_PARALLEL_MIN the node count); pattern networks (LDS_TRIANGLE) use
+ * the sequential one.
  * Replaces the graph's FW state of this mode with an iters-iteration
  * run.  *out is overwritten; on error it is left zeroed.  LDS_E_INVALID for
  * k < 1, iters < 0 or a bad mode. */
