@@ -288,11 +288,14 @@ typedef struct {
  * by FW + ExtractSG on its induced subgraph (or by the min cut when that does
  * not split it).  Returns the k densest LDSs (fewer when the graph has fewer
  * with positive density).  Synchronises the stream: verification runs on the
- * host; min cuts of vertex networks (LDS_EDGE) with at least 524288 nodes
- * use a parallel push-relabel on up to 16 host threads (environment:
- * LDS_FLOW_THREADS sets the thread count, 1 = sequential;
- * LDS_FLOW_PARALLEL_MIN the node count); pattern networks (LDS_TRIANGLE) use
- * the sequential one.
+ * host, except the min cuts of vertex networks (LDS_EDGE) with at least
+ * 131072 nodes, which run as a push-relabel on the device, on hip_stream
+ * (environment: LDS_FLOW_GPU_MIN sets the node count, LDS_FLOW_GPU_WG the
+ * grid width).  Smaller ones run on the host: from 524288 nodes (when the
+ * device threshold is raised) a parallel push-relabel on up to 16 host
+ * threads (LDS_FLOW_THREADS sets the thread count, 1 = sequential;
+ * LDS_FLOW_PARALLEL_MIN the node count).  Pattern networks (LDS_TRIANGLE)
+ * use the sequential host push-relabel.
  * Replaces the graph's FW state of this mode with an iters-iteration
  * run.  *out is overwritten; on error it is left zeroed.  LDS_E_INVALID for
  * k < 1, iters < 0 or a bad mode. */

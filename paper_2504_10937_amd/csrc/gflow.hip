@@ -1,0 +1,464 @@
+// Maximum preflow on the device for the large vertex networks of IsDensest
+// (a whole-graph candidate of a sparse graph is a tight transportation
+// problem: every sink arc must be filled), by the synchronous push-relabel of
+// the host threads' version (pflow.hpp) laid out for the GPU.
+//
+// One cooperative launch; the workgroups meet at grid barriers between the
+// phases of a pulse, all labels fixed within a phase:
+//   push     every active node v pushes its excess along admissible arcs
+//            (h[w] == h[v] - 1, residual capacity) in arc order: a node
+//            with few arcs on one lane, a large one on a wave whose lanes
+//            take rows of 64 arcs and split the excess by a prefix sum;
+//            two nodes never push along the two arcs of
+//            one pair in the same phase (that would need h[v] == h[w] - 1
+//            and h[w] == h[v] - 1), so only the excess needs atomics;
+//   relabel  a node with excess left and no admissible arc takes 1 + the
+//            smallest label over its residual arcs, from the old labels;
+//   apply    the new labels;
+//   collect  nodes that received excess or were relabelled below N form the
+//            next active list.
+// Exact distance labels come from a level-synchronous backward search from t
+// (nodes claimed by compare-and-swap) at the start and after every N
+// relabels.  The result is a maximum preflow, so the residual graph gives the
+// same minimum cuts as any maximum flow.
+//
+// List counters live in two rings of four words indexed by the phase number:
+// a phase pushes into slot ph & 3, which workgroup 0 zeroed during phase
+// ph - 1; its previous value was read right after barrier ph - 3, and every
+// workgroup has passed that point by then.  Every decision is taken from
+// values read after a barrier, so control flow is uniform.  Waits and loops
+// are bounded; past a bound the kernel raises an error flag and ends.
+#include <algorithm>
+#include <climits>
+#include <cstdlib>
+
+#include "gflow.hpp"
+#include "graph.hpp"
+#include "gridsync.hpp"
+
+namespace lds {
+
+namespace {
+
+constexpr int kFT = 512;
+constexpr int64_t kFlowMaxWG = 64;
+enum : int { F_RING1 = 0, F_RING2 = 4, F_ERR = 8 };
+
+struct FlowArgs {
+    const int64_t* first;
+    const int32_t* to;
+    int64_t* cap;
+    const int64_t* rev;
+    int64_t* ex;
+    int32_t* h;
+    int32_t* hn;
+    uint32_t* queued;
+    int32_t* act;
+    int32_t* act2;
+    int32_t* nxt;
+    int32_t* rel;
+    int32_t* r3;
+    int32_t* ctr;   // F_* words (16)
+    unsigned* bar;  // grid barrier counter
+    int64_t N, s, t;
+};
+
+__device__ inline void push_list(int32_t* list, int32_t* count, int32_t v) { list[atomicAdd(count, 1)] = v; }
+
+__device__ inline int64_t shfl_up_i64(int64_t v, int d) {
+    const uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)(uint64_t)v, (unsigned)d, 64);
+    const uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)((uint64_t)v >> 32), (unsigned)d, 64);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ inline int64_t readlane_i64(int64_t v, int lane) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(uint64_t)v, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), lane);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Calls small(v) on the thread of each node v of list[0, count) with at most
+// kSmallDeg arcs, and big(v) on a whole wave for each larger one: most nodes
+// of these networks have a handful of arcs, so a lane per node keeps 64 of
+// them in flight per wave, while the few hubs get a wave's 64 lanes.  The
+// workgroups take the list in blocks of kFT; a block's large nodes go through
+// a list in LDS.  Every thread of the workgroup must call it.
+constexpr int kSmallDeg = 32;
+constexpr int kLU = 8;  // arcs of a lane's node loaded together
+constexpr int kWU = 4;  // rows of 64 arcs of a wave's node loaded together
+
+template <class SmallF, class BigF>
+__device__ inline void node_pass(const FlowArgs& a, const int32_t* list, int64_t count, int32_t* sbig, int* sbn,
+                                 SmallF small, BigF big) {
+    const int w = threadIdx.x >> 6;
+    for (int64_t b = (int64_t)blockIdx.x * kFT; b < count; b += (int64_t)gridDim.x * kFT) {
+        if (threadIdx.x == 0) *sbn = 0;
+        __syncthreads();
+        const int64_t i = b + threadIdx.x;
+        if (i < count) {
+            const int32_t v = list[i];
+            if (a.first[v + 1] - a.first[v] <= kSmallDeg)
+                small(v);
+            else
+                sbig[atomicAdd(sbn, 1)] = v;
+        }
+        __syncthreads();
+        const int nb = *sbn;
+        for (int j = w; j < nb; j += kFT / 64) big(sbig[j]);
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kFT) void k_maxflow(FlowArgs a) {
+    __shared__ int64_t s_err;
+    __shared__ int32_t sbig[kFT];
+    __shared__ int sbn;
+    if (threadIdx.x == 0) s_err = 0;
+    __syncthreads();
+    const unsigned nwg = gridDim.x;
+    const int64_t gt = (int64_t)blockIdx.x * kFT + threadIdx.x, nthr = (int64_t)nwg * kFT;
+    const int lane = threadIdx.x & 63;
+    const int64_t N = a.N;
+    const int32_t HN = (int32_t)N;
+    int32_t* ring1 = a.ctr + F_RING1;
+    int32_t* ring2 = a.ctr + F_RING2;
+    unsigned ph = 0;
+    bool bad = false;
+    auto end_phase = [&]() {
+        if (gt == 0) {
+            ring1[(ph + 1) & 3] = 0;
+            ring2[(ph + 1) & 3] = 0;
+        }
+        grid_sync(a.bar, nwg, &s_err);
+    };
+    int32_t* act = a.act;
+    int32_t* act2 = a.act2;
+    int32_t na = 0;
+    // exact distance labels by a backward search from t, then the active list
+    auto global_relabel = [&]() {
+        for (int64_t v = gt; v < N; v += nthr) a.h[v] = HN;
+        end_phase();
+        ++ph;
+        int32_t* F = a.nxt;
+        int32_t* G = a.r3;
+        int32_t* slot = ring1 + (ph & 3);
+        if (gt == 0) {
+            a.h[a.t] = 0;
+            F[0] = (int32_t)a.t;
+            *slot = 1;
+        }
+        end_phase();
+        int32_t fc = *slot;
+        ++ph;
+        for (int32_t lvl = 1; fc > 0; ++lvl) {
+            if (s_err || lvl > HN) {
+                bad = true;
+                return;
+            }
+            slot = ring1 + (ph & 3);
+            // x reaches y in the residual graph: the arc x -> y is rev[e]
+            auto claim = [&](int64_t e) {
+                const int32_t x = a.to[e];
+                if (x == a.s || a.cap[a.rev[e]] <= 0 || a.h[x] != HN) return;
+                int32_t want = HN;
+                if (__hip_atomic_compare_exchange_strong(&a.h[x], &want, lvl, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT))
+                    push_list(G, slot, x);
+            };
+            node_pass(
+                a, F, fc, sbig, &sbn,
+                [&](int32_t y) {
+                    const int64_t e1 = a.first[y + 1];
+                    for (int64_t e0 = a.first[y]; e0 < e1; e0 += kLU) {
+                        int32_t x[kLU];
+                        bool ok[kLU];
+#pragma unroll
+                        for (int u = 0; u < kLU; ++u) {
+                            const int64_t e = e0 + u;
+                            ok[u] = e < e1;
+                            x[u] = ok[u] ? a.to[e] : 0;
+                            ok[u] = ok[u] && x[u] != a.s && a.cap[a.rev[e]] > 0;
+                        }
+#pragma unroll
+                        for (int u = 0; u < kLU; ++u) {
+                            if (!ok[u] || a.h[x[u]] != HN) continue;
+                            int32_t want = HN;
+                            if (__hip_atomic_compare_exchange_strong(&a.h[x[u]], &want, lvl, __ATOMIC_RELAXED,
+                                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                                push_list(G, slot, x[u]);
+                        }
+                    }
+                },
+                [&](int32_t y) {
+                    for (int64_t e = a.first[y] + lane; e < a.first[y + 1]; e += 64) claim(e);
+                });
+            end_phase();
+            fc = *slot;
+            ++ph;
+            int32_t* tmp = F;
+            F = G;
+            G = tmp;
+        }
+        slot = ring1 + (ph & 3);
+        for (int64_t v = gt; v < N; v += nthr)
+            if (v != a.s && v != a.t && a.h[v] < HN && a.ex[v] > 0) push_list(act, slot, (int32_t)v);
+        end_phase();
+        na = *slot;
+        ++ph;
+    };
+    global_relabel();
+    int64_t relabels = 0;
+    const int64_t max_pulses = 4 * N + 100000;  // far above what a run needs; a bound, not a budget
+    for (int64_t pulse = 0; na > 0 && !bad; ++pulse) {
+        if (s_err || pulse > max_pulses) {
+            bad = true;
+            break;
+        }
+        // push
+        int32_t* s1 = ring1 + (ph & 3);
+        int32_t* s2 = ring2 + (ph & 3);
+        // pushes d along arc e (v -> w); the receiver joins the next list once
+        auto push_arc = [&](int64_t e, int32_t w, int64_t c, int64_t d) {
+            a.cap[e] = c - d;
+            a.cap[a.rev[e]] += d;
+            atomicAdd((unsigned long long*)&a.ex[w], (unsigned long long)d);
+            if (w != a.t && w != a.s && atomicExch(&a.queued[w], 1u) == 0u) push_list(a.nxt, s1, w);
+        };
+        node_pass(
+            a, act, na, sbig, &sbn,
+            [&](int32_t v) {  // one lane: the arcs in order
+                const int32_t hv = a.h[v];
+                if (hv >= HN) return;
+                const int64_t ev = __hip_atomic_load(&a.ex[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (ev <= 0) return;
+                int64_t rem = ev;
+                const int64_t e1 = a.first[v + 1];
+                for (int64_t e0 = a.first[v]; e0 < e1 && rem > 0; e0 += kLU) {
+                    int64_t c[kLU];
+                    int32_t w[kLU];
+#pragma unroll
+                    for (int u = 0; u < kLU; ++u) {
+                        const bool in = e0 + u < e1;
+                        c[u] = in ? a.cap[e0 + u] : 0;
+                        w[u] = in ? a.to[e0 + u] : 0;
+                    }
+                    bool adm[kLU];
+#pragma unroll
+                    for (int u = 0; u < kLU; ++u) adm[u] = c[u] > 0 && a.h[w[u]] == hv - 1;
+#pragma unroll
+                    for (int u = 0; u < kLU; ++u)
+                        if (adm[u] && rem > 0) {
+                            const int64_t d = min(rem, c[u]);
+                            push_arc(e0 + u, w[u], c[u], d);
+                            rem -= d;
+                        }
+                }
+                if (rem != ev) atomicAdd((unsigned long long*)&a.ex[v], (unsigned long long)(rem - ev));
+                if (rem > 0) push_list(a.rel, s2, v);
+            },
+            [&](int32_t v) {  // one wave: rows of 64 arcs, the excess split in arc order by a prefix sum
+                const int32_t hv = a.h[v];
+                if (hv >= HN) return;
+                const int64_t ev =
+                    readlane_i64(__hip_atomic_load(&a.ex[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), 0);
+                if (ev <= 0) return;
+                int64_t rem = ev;
+                const int64_t e1 = a.first[v + 1];
+                for (int64_t eb = a.first[v]; eb < e1 && rem > 0; eb += 64 * kWU) {
+                    int64_t c[kWU];
+                    int32_t w[kWU];
+#pragma unroll
+                    for (int u = 0; u < kWU; ++u) {
+                        const int64_t e = eb + 64 * u + lane;
+                        c[u] = e < e1 ? a.cap[e] : 0;
+                        w[u] = e < e1 ? a.to[e] : 0;
+                    }
+                    bool adm[kWU];
+#pragma unroll
+                    for (int u = 0; u < kWU; ++u) adm[u] = c[u] > 0 && a.h[w[u]] == hv - 1;
+#pragma unroll
+                    for (int u = 0; u < kWU; ++u) {
+                        if (rem <= 0) break;
+                        const int64_t avail = adm[u] ? c[u] : 0;
+                        int64_t incl = avail;
+                        for (int off = 1; off < 64; off <<= 1) {
+                            const int64_t o = shfl_up_i64(incl, off);
+                            if (lane >= off) incl += o;
+                        }
+                        const int64_t excl = incl - avail;
+                        const int64_t d = adm[u] ? min(avail, max((int64_t)0, rem - excl)) : 0;
+                        if (d > 0) push_arc(eb + 64 * u + lane, w[u], c[u], d);
+                        rem -= min(rem, readlane_i64(incl, 63));
+                    }
+                }
+                if (lane == 0) {
+                    if (rem != ev) atomicAdd((unsigned long long*)&a.ex[v], (unsigned long long)(rem - ev));
+                    if (rem > 0) push_list(a.rel, s2, v);
+                }
+            });
+        end_phase();
+        const int32_t nN = *s1, nR = *s2;
+        ++ph;
+        // relabel, from the old labels
+        node_pass(
+            a, a.rel, nR, sbig, &sbn,
+            [&](int32_t v) {
+                int32_t mh = INT32_MAX;
+                const int64_t e1 = a.first[v + 1];
+                for (int64_t e0 = a.first[v]; e0 < e1; e0 += kLU) {
+                    int32_t w[kLU];
+#pragma unroll
+                    for (int u = 0; u < kLU; ++u) w[u] = (e0 + u < e1 && a.cap[e0 + u] > 0) ? a.to[e0 + u] : -1;
+#pragma unroll
+                    for (int u = 0; u < kLU; ++u)
+                        if (w[u] >= 0) mh = min(mh, a.h[w[u]]);
+                }
+                a.hn[v] = (mh >= HN) ? HN : mh + 1;
+            },
+            [&](int32_t v) {
+                int32_t mh = INT32_MAX;
+                const int64_t e1 = a.first[v + 1];
+                for (int64_t eb = a.first[v] + lane; eb < e1; eb += 64 * kWU) {
+                    int32_t w[kWU];
+#pragma unroll
+                    for (int u = 0; u < kWU; ++u) {
+                        const int64_t e = eb + 64 * u;
+                        w[u] = (e < e1 && a.cap[e] > 0) ? a.to[e] : -1;
+                    }
+#pragma unroll
+                    for (int u = 0; u < kWU; ++u)
+                        if (w[u] >= 0) mh = min(mh, a.h[w[u]]);
+                }
+                for (int o = 32; o > 0; o >>= 1) mh = min(mh, __shfl_xor(mh, o, 64));
+                if (lane == 0) a.hn[v] = (mh >= HN) ? HN : mh + 1;
+            });
+        end_phase();
+        ++ph;
+        // apply the new labels
+        s1 = ring1 + (ph & 3);
+        for (int64_t i = gt; i < nR; i += nthr) {
+            const int32_t v = a.rel[i];
+            a.h[v] = a.hn[v];
+            if (a.h[v] < HN && atomicExch(&a.queued[v], 1u) == 0u) push_list(a.r3, s1, v);
+        }
+        end_phase();
+        const int32_t n3 = *s1;
+        ++ph;
+        relabels += nR;
+        // collect the next active list
+        s1 = ring1 + (ph & 3);
+        for (int64_t i = gt; i < (int64_t)nN + n3; i += nthr) {
+            const int32_t v = i < nN ? a.nxt[i] : a.r3[i - nN];
+            a.queued[v] = 0u;
+            if (a.h[v] < HN && a.ex[v] > 0) push_list(act2, s1, v);
+        }
+        end_phase();
+        na = *s1;
+        ++ph;
+        int32_t* tmp = act;
+        act = act2;
+        act2 = tmp;
+        if (na > 0 && relabels >= N) {
+            relabels = 0;
+            global_relabel();
+        }
+    }
+    if (threadIdx.x == 0 && (bad || s_err)) a.ctr[F_ERR] = 1;
+}
+
+__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+}  // namespace
+
+int64_t maxflow_device(int64_t N, const std::vector<int64_t>& first, const std::vector<int32_t>& to,
+                       std::vector<int64_t>& cap, const std::vector<int64_t>& rev, int64_t s, int64_t t,
+                       const std::vector<int64_t>& ex, hipStream_t st) {
+    LDS_CHECK(N >= 2 && N < INT32_MAX, ST_INVALID, "device max flow: node count out of range");
+    LDS_CHECK((int64_t)first.size() == N + 1 && (int64_t)ex.size() >= N, ST_INVALID, "device max flow: bad network");
+    const int64_t M = first[N];
+    LDS_CHECK((int64_t)to.size() >= M && (int64_t)cap.size() >= M && (int64_t)rev.size() >= M, ST_INVALID,
+              "device max flow: bad arc arrays");
+    DBuf<int64_t> dfirst, dcap, drev, dex;
+    DBuf<int32_t> dto, h, hn, act, act2, nxt, rel, r3, ctr;
+    DBuf<uint32_t> queued;
+    DBuf<unsigned> bar;
+    dfirst.alloc(N + 1, st);
+    dto.alloc(std::max<int64_t>(M, 1), st);
+    dcap.alloc(std::max<int64_t>(M, 1), st);
+    drev.alloc(std::max<int64_t>(M, 1), st);
+    dex.alloc(N, st);
+    h.alloc(N, st);
+    hn.alloc(N, st);
+    queued.alloc(N, st);
+    act.alloc(N, st);
+    act2.alloc(N, st);
+    nxt.alloc(N, st);
+    rel.alloc(N, st);
+    r3.alloc(N, st);
+    ctr.alloc(16, st);
+    bar.alloc(2, st);
+    LDS_HIP(hipMemcpyAsync(dfirst.p, first.data(), (N + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    if (M > 0) {
+        LDS_HIP(hipMemcpyAsync(dto.p, to.data(), M * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        LDS_HIP(hipMemcpyAsync(dcap.p, cap.data(), M * sizeof(int64_t), hipMemcpyHostToDevice, st));
+        LDS_HIP(hipMemcpyAsync(drev.p, rev.data(), M * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    }
+    LDS_HIP(hipMemcpyAsync(dex.p, ex.data(), N * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    k_fill_u32<<<grid_for(N, 256), 256, 0, st>>>(queued.p, N, 0u);
+    k_fill_u32<<<1, 256, 0, st>>>((uint32_t*)ctr.p, 16, 0u);
+    k_fill_u32<<<1, 256, 0, st>>>(bar.p, 2, 0u);
+    LDS_HIP(hipGetLastError());
+    static int cus = 0, per = 0;
+    if (!cus) {
+        int dev = 0;
+        LDS_HIP(hipGetDevice(&dev));
+        LDS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        LDS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_maxflow, kFT, 0));
+    }
+    const int64_t resident = (int64_t)cus * std::max(1, per);
+    // at most kFlowMaxWG workgroups, one per 8192 nodes; LDS_FLOW_GPU_WG
+    // overrides both (e.g. to run the grid protocol wide on small networks)
+    const char* ev = std::getenv("LDS_FLOW_GPU_WG");
+    const int64_t forced = (ev && *ev) ? std::max<int64_t>(1, std::atoll(ev)) : 0;
+    const int64_t grid = std::max<int64_t>(
+        1, std::min<int64_t>({resident, forced ? forced : kFlowMaxWG, forced ? resident : (N + 8191) / 8192}));
+    FlowArgs fa{};
+    fa.first = dfirst.p;
+    fa.to = dto.p;
+    fa.cap = dcap.p;
+    fa.rev = drev.p;
+    fa.ex = dex.p;
+    fa.h = h.p;
+    fa.hn = hn.p;
+    fa.queued = queued.p;
+    fa.act = act.p;
+    fa.act2 = act2.p;
+    fa.nxt = nxt.p;
+    fa.rel = rel.p;
+    fa.r3 = r3.p;
+    fa.ctr = ctr.p;
+    fa.bar = bar.p;
+    fa.N = N;
+    fa.s = s;
+    fa.t = t;
+    if (grid == 1) {  // one workgroup needs no co-residency guarantee
+        k_maxflow<<<1, kFT, 0, st>>>(fa);
+        LDS_HIP(hipGetLastError());
+    } else {
+        void* kargs[] = {&fa};
+        LDS_HIP(hipLaunchCooperativeKernel((const void*)k_maxflow, dim3((unsigned)grid), dim3(kFT), kargs, 0, st));
+    }
+    int32_t err = 0;
+    int64_t flow = 0;
+    LDS_HIP(hipMemcpyAsync(&err, ctr.p + F_ERR, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    LDS_HIP(hipMemcpyAsync(&flow, dex.p + t, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    if (M > 0) LDS_HIP(hipMemcpyAsync(cap.data(), dcap.p, M * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    LDS_HIP(hipStreamSynchronize(st));
+    LDS_CHECK(err == 0, ST_DEVICE, "device max flow: no progress or a grid barrier did not complete");
+    return flow;
+}
+
+}  // namespace lds

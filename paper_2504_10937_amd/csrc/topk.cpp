@@ -36,6 +36,7 @@
 #include <queue>
 
 #include "batch.hpp"
+#include "gflow.hpp"
 #include "pflow.hpp"
 #include "islds.hpp"
 #include "topk.hpp"
@@ -85,6 +86,14 @@ int64_t flow_parallel_min_nodes() {
     }
     return g_flow_parallel_min;
 }
+// Vertex networks with at least this many nodes (2^17) take the device
+// push-relabel (gflow.hip) instead; LDS_FLOW_GPU_MIN overrides it, read at
+// every call.  The stream is the one of the search that builds the network.
+int64_t flow_gpu_min_nodes() {
+    const char* e = std::getenv("LDS_FLOW_GPU_MIN");
+    return (e && *e) ? (int64_t)std::atoll(e) : (int64_t)1 << 17;
+}
+thread_local hipStream_t g_flow_stream = nullptr;
 
 // Host threads for the large min cuts are shared by every top-k search in the
 // process (the serving workers run several at once): a search takes what is
@@ -252,9 +261,10 @@ struct Flow {
     // already reached t; nullptr = start from zero flow
     int64_t maxflow(int64_t s, int64_t t, const std::vector<int64_t>* init_ex = nullptr, int64_t init_t = 0) {
         finalize();
-        ThreadGrant grant(allow_parallel && N >= flow_parallel_min_nodes() ? flow_threads() : 1);
+        const bool gpu = allow_parallel && N >= flow_gpu_min_nodes();
+        ThreadGrant grant(!gpu && allow_parallel && N >= flow_parallel_min_nodes() ? flow_threads() : 1);
         const int threads = grant.n;
-        if (threads > 1) {
+        if (gpu || threads > 1) {
             std::vector<int64_t> ex(N, 0);
             if (init_ex) {
                 for (int64_t v = 0; v < N && v < (int64_t)init_ex->size(); ++v) ex[v] = (*init_ex)[v];
@@ -268,6 +278,7 @@ struct Flow {
                     ex[to[e]] += d;
                 }
             ex[s] = 0;
+            if (gpu) return maxflow_device(N, first, to, cap, rev, s, t, ex, g_flow_stream);
             return maxflow_parallel(N, first, to, cap, rev, s, t, ex, threads);
         }
         std::vector<int64_t> h(N, 0), ex(N, 0), it(first.begin(), first.end() - 1);
@@ -944,6 +955,12 @@ size_t topk_footprint(const Graph& g, int mode, int iters) {
 
 void topk_run(Graph& g, int mode, int k, int iters, hipStream_t s, std::vector<TopkSet>& out, TopkStats& st,
               bool reuse_fw) {
+    // the device min cuts of this search run on its stream
+    struct StreamScope {
+        hipStream_t prev;
+        explicit StreamScope(hipStream_t s) : prev(g_flow_stream) { g_flow_stream = s; }
+        ~StreamScope() { g_flow_stream = prev; }
+    } stream_scope(s);
     LDS_CHECK(mode == 2 || mode == 3, ST_INVALID, "mode must be LDS_EDGE or LDS_TRIANGLE");
     LDS_CHECK(k >= 1, ST_INVALID, "k must be >= 1");
     LDS_CHECK(iters >= 0, ST_INVALID, "iters must be >= 0");

@@ -14,6 +14,7 @@
 #include "../../paper_2504_10937_amd/csrc/topk.cpp"
 
 #include <cstdio>
+#include <cstdlib>
 #include <random>
 
 namespace lds {
@@ -23,6 +24,10 @@ Graph::~Graph() {}
 void build_graph(Graph&, int64_t, int64_t, const int32_t*, const int32_t*, bool, bool, hipStream_t) {}
 void list_triangles(Graph&, hipStream_t) {}
 void vertex_triangle_lists(const Graph&, int64_t*, int32_t*, hipStream_t) {}
+int64_t maxflow_device(int64_t, const std::vector<int64_t>&, const std::vector<int32_t>&, std::vector<int64_t>&,
+                       const std::vector<int64_t>&, int64_t, int64_t, const std::vector<int64_t>&, hipStream_t) {
+    std::abort();  // main() keeps every network on the host
+}
 void sg_stable_groups(Graph&, int, hipStream_t) {}
 void fw_run(Graph&, int, int, bool, hipStream_t) {}
 void core_numbers_gpu(Graph&, int, const uint8_t*, int32_t*, hipStream_t) {}
@@ -164,6 +169,7 @@ static int parallel_vs_sequential(int& cases) {
 }
 
 int main() {
+    setenv("LDS_FLOW_GPU_MIN", "9223372036854775807", 1);  // no device here: host min cuts only
     int cases = 0, bad = 0;
     g_flow_threads = 4;
     g_flow_parallel_min = 1 << 30;  // sequential push-relabel
