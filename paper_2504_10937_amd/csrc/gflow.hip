@@ -61,6 +61,7 @@ struct FlowArgs {
     int32_t* ctr;   // F_* words (16)
     unsigned* bar;  // grid barrier counter
     int64_t N, s, t;
+    int final_search;  // after the flow: labels < N exactly at the nodes that reach t
 };
 
 __device__ inline void push_list(int32_t* list, int32_t* count, int32_t v) { list[atomicAdd(count, 1)] = v; }
@@ -134,8 +135,8 @@ __global__ __launch_bounds__(kFT) void k_maxflow(FlowArgs a) {
     int32_t* act = a.act;
     int32_t* act2 = a.act2;
     int32_t na = 0;
-    // exact distance labels by a backward search from t, then the active list
-    auto global_relabel = [&]() {
+    // exact distance labels by a backward search from t
+    auto search_labels = [&]() {
         for (int64_t v = gt; v < N; v += nthr) a.h[v] = HN;
         end_phase();
         ++ph;
@@ -199,7 +200,12 @@ __global__ __launch_bounds__(kFT) void k_maxflow(FlowArgs a) {
             F = G;
             G = tmp;
         }
-        slot = ring1 + (ph & 3);
+    };
+    // ... then the active list
+    auto global_relabel = [&]() {
+        search_labels();
+        if (bad) return;
+        int32_t* slot = ring1 + (ph & 3);
         for (int64_t v = gt; v < N; v += nthr)
             if (v != a.s && v != a.t && a.h[v] < HN && a.ex[v] > 0) push_list(act, slot, (int32_t)v);
         end_phase();
@@ -363,6 +369,7 @@ __global__ __launch_bounds__(kFT) void k_maxflow(FlowArgs a) {
             global_relabel();
         }
     }
+    if (a.final_search && !bad && !s_err) search_labels();
     if (threadIdx.x == 0 && (bad || s_err)) a.ctr[F_ERR] = 1;
 }
 
@@ -371,46 +378,135 @@ __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
     if (i < n) p[i] = v;
 }
 
-}  // namespace
+// ---- Goldberg's vertex network built on the device (nodes 0..k-1, source
+// S = k, sink T = k + 1): each node's arcs are its edge arcs (slots taken by
+// an atomic cursor, so their order varies; the flow value and the maximal
+// minimum cut do not), then the arc to T, then the reverse of the arc from S.
+// The source arcs are saturated from the start.
+__global__ void k_net_deg(const int32_t* pairs, int64_t ne, int32_t* deg) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= ne) return;
+    atomicAdd(&deg[pairs[2 * i]], 1);
+    atomicAdd(&deg[pairs[2 * i + 1]], 1);
+}
 
-int64_t maxflow_device(int64_t N, const std::vector<int64_t>& first, const std::vector<int32_t>& to,
-                       std::vector<int64_t>& cap, const std::vector<int64_t>& rev, int64_t s, int64_t t,
-                       const std::vector<int64_t>& ex, hipStream_t st) {
-    LDS_CHECK(N >= 2 && N < INT32_MAX, ST_INVALID, "device max flow: node count out of range");
-    LDS_CHECK((int64_t)first.size() == N + 1 && (int64_t)ex.size() >= N, ST_INVALID, "device max flow: bad network");
-    const int64_t M = first[N];
-    LDS_CHECK((int64_t)to.size() >= M && (int64_t)cap.size() >= M && (int64_t)rev.size() >= M, ST_INVALID,
-              "device max flow: bad arc arrays");
-    DBuf<int64_t> dfirst, dcap, drev, dex;
-    DBuf<int32_t> dto, h, hn, act, act2, nxt, rel, r3, ctr;
+__global__ void k_net_shares(const int32_t* pairs, const uint32_t* split, int64_t ne, int64_t D, int64_t* A) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= ne) return;
+    const int64_t a = split[i];
+    atomicAdd((unsigned long long*)&A[pairs[2 * i]], (unsigned long long)a);
+    atomicAdd((unsigned long long*)&A[pairs[2 * i + 1]], (unsigned long long)(D - a));
+}
+
+__global__ void k_net_counts(int64_t k, const int32_t* deg, const int64_t* loops, int64_t* w, uint64_t* cnt) {
+    const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (v >= k) return;
+    const int64_t wv = (loops ? 2 * loops[v] : 0) + deg[v];
+    w[v] = wv;
+    cnt[v] = (uint64_t)deg[v] + 1 + (wv > 0 ? 1 : 0);
+    if (wv > 0) atomicAdd((unsigned long long*)&cnt[k], 1ull);
+}
+
+__global__ void k_net_edges(const int32_t* pairs, const uint32_t* split, int64_t ne, int warm, int64_t q, int64_t D,
+                            const int64_t* first, int32_t* cur, int32_t* to, int64_t* cap, int64_t* rev) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= ne) return;
+    const int32_t a = pairs[2 * i], b = pairs[2 * i + 1];
+    int64_t c = q, cb = q;
+    if (warm) {
+        const int64_t fl = q * (D - 2 * (int64_t)split[i]);  // net flow a -> b
+        c = q * D - fl;
+        cb = q * D + fl;
+    }
+    const int64_t pa = first[a] + atomicAdd(&cur[a], 1), pb = first[b] + atomicAdd(&cur[b], 1);
+    to[pa] = b;
+    to[pb] = a;
+    cap[pa] = c;
+    cap[pb] = cb;
+    rev[pa] = pb;
+    rev[pb] = pa;
+}
+
+__global__ void k_net_nodes(int64_t k, const int32_t* deg, const int64_t* w, const int64_t* A, int warm, int64_t p,
+                            int64_t q, int64_t D, int64_t sc, const int64_t* first, int32_t* curS, int32_t* to,
+                            int64_t* cap, int64_t* rev, int64_t* ex, unsigned long long* to_t) {
+    const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (v >= k) return;
+    const int64_t S = k, T = k + 1;
+    const int64_t e = first[v] + deg[v], eT = first[T] + v;  // v -> T and its reverse
+    to[e] = (int32_t)T;
+    to[eT] = (int32_t)v;
+    rev[e] = eT;
+    rev[eT] = e;
+    int64_t exv = 0;
+    if (warm) {
+        const int64_t tv = min(2 * q * A[v], 2 * p * D);
+        cap[e] = 2 * p * D - tv;
+        cap[eT] = tv;
+        exv = 2 * q * A[v] - tv;
+        atomicAdd(to_t, (unsigned long long)tv);
+    } else {
+        cap[e] = 2 * p;
+        cap[eT] = 0;
+    }
+    if (w[v] > 0) {  // S -> v, saturated
+        const int64_t es = first[S] + atomicAdd(curS, 1), ev = e + 1;
+        to[es] = (int32_t)v;
+        to[ev] = (int32_t)S;
+        rev[es] = ev;
+        rev[ev] = es;
+        cap[es] = 0;
+        cap[ev] = q * w[v] * sc;
+        if (!warm) exv += q * w[v];
+    }
+    ex[v] = exv;
+}
+
+__global__ void k_net_ends(int64_t k, const unsigned long long* to_t, int64_t* ex) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ex[k] = 0;
+        ex[k + 1] = (int64_t)*to_t;
+    }
+}
+
+// the scratch of a device flow over N nodes
+struct FlowScratch {
+    DBuf<int64_t> ex;
+    DBuf<int32_t> h, hn, act, act2, nxt, rel, r3, ctr;
     DBuf<uint32_t> queued;
     DBuf<unsigned> bar;
-    dfirst.alloc(N + 1, st);
-    dto.alloc(std::max<int64_t>(M, 1), st);
-    dcap.alloc(std::max<int64_t>(M, 1), st);
-    drev.alloc(std::max<int64_t>(M, 1), st);
-    dex.alloc(N, st);
-    h.alloc(N, st);
-    hn.alloc(N, st);
-    queued.alloc(N, st);
-    act.alloc(N, st);
-    act2.alloc(N, st);
-    nxt.alloc(N, st);
-    rel.alloc(N, st);
-    r3.alloc(N, st);
-    ctr.alloc(16, st);
-    bar.alloc(2, st);
-    LDS_HIP(hipMemcpyAsync(dfirst.p, first.data(), (N + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
-    if (M > 0) {
-        LDS_HIP(hipMemcpyAsync(dto.p, to.data(), M * sizeof(int32_t), hipMemcpyHostToDevice, st));
-        LDS_HIP(hipMemcpyAsync(dcap.p, cap.data(), M * sizeof(int64_t), hipMemcpyHostToDevice, st));
-        LDS_HIP(hipMemcpyAsync(drev.p, rev.data(), M * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    void alloc(int64_t N, hipStream_t st) {
+        ex.alloc(N, st);
+        h.alloc(N, st);
+        hn.alloc(N, st);
+        queued.alloc(N, st);
+        act.alloc(N, st);
+        act2.alloc(N, st);
+        nxt.alloc(N, st);
+        rel.alloc(N, st);
+        r3.alloc(N, st);
+        ctr.alloc(16, st);
+        bar.alloc(2, st);
+        k_fill_u32<<<grid_for(N, 256), 256, 0, st>>>(queued.p, N, 0u);
+        k_fill_u32<<<1, 256, 0, st>>>((uint32_t*)ctr.p, 16, 0u);
+        k_fill_u32<<<1, 256, 0, st>>>(bar.p, 2, 0u);
+        LDS_HIP(hipGetLastError());
     }
-    LDS_HIP(hipMemcpyAsync(dex.p, ex.data(), N * sizeof(int64_t), hipMemcpyHostToDevice, st));
-    k_fill_u32<<<grid_for(N, 256), 256, 0, st>>>(queued.p, N, 0u);
-    k_fill_u32<<<1, 256, 0, st>>>((uint32_t*)ctr.p, 16, 0u);
-    k_fill_u32<<<1, 256, 0, st>>>(bar.p, 2, 0u);
-    LDS_HIP(hipGetLastError());
+};
+
+// launches the flow over the network in fa (first / to / cap / rev / ex set)
+void run_flow(FlowArgs& fa, FlowScratch& sc, hipStream_t st) {
+    const int64_t N = fa.N;
+    fa.h = sc.h.p;
+    fa.hn = sc.hn.p;
+    fa.queued = sc.queued.p;
+    fa.act = sc.act.p;
+    fa.act2 = sc.act2.p;
+    fa.nxt = sc.nxt.p;
+    fa.rel = sc.rel.p;
+    fa.r3 = sc.r3.p;
+    fa.ctr = sc.ctr.p;
+    fa.bar = sc.bar.p;
     static int cus = 0, per = 0;
     if (!cus) {
         int dev = 0;
@@ -425,25 +521,6 @@ int64_t maxflow_device(int64_t N, const std::vector<int64_t>& first, const std::
     const int64_t forced = (ev && *ev) ? std::max<int64_t>(1, std::atoll(ev)) : 0;
     const int64_t grid = std::max<int64_t>(
         1, std::min<int64_t>({resident, forced ? forced : kFlowMaxWG, forced ? resident : (N + 8191) / 8192}));
-    FlowArgs fa{};
-    fa.first = dfirst.p;
-    fa.to = dto.p;
-    fa.cap = dcap.p;
-    fa.rev = drev.p;
-    fa.ex = dex.p;
-    fa.h = h.p;
-    fa.hn = hn.p;
-    fa.queued = queued.p;
-    fa.act = act.p;
-    fa.act2 = act2.p;
-    fa.nxt = nxt.p;
-    fa.rel = rel.p;
-    fa.r3 = r3.p;
-    fa.ctr = ctr.p;
-    fa.bar = bar.p;
-    fa.N = N;
-    fa.s = s;
-    fa.t = t;
     if (grid == 1) {  // one workgroup needs no co-residency guarantee
         k_maxflow<<<1, kFT, 0, st>>>(fa);
         LDS_HIP(hipGetLastError());
@@ -451,14 +528,97 @@ int64_t maxflow_device(int64_t N, const std::vector<int64_t>& first, const std::
         void* kargs[] = {&fa};
         LDS_HIP(hipLaunchCooperativeKernel((const void*)k_maxflow, dim3((unsigned)grid), dim3(kFT), kargs, 0, st));
     }
+}
+
+int32_t flow_error(const FlowScratch& sc, hipStream_t st) {
     int32_t err = 0;
-    int64_t flow = 0;
-    LDS_HIP(hipMemcpyAsync(&err, ctr.p + F_ERR, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    LDS_HIP(hipMemcpyAsync(&flow, dex.p + t, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    if (M > 0) LDS_HIP(hipMemcpyAsync(cap.data(), dcap.p, M * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    LDS_HIP(hipMemcpyAsync(&err, sc.ctr.p + F_ERR, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     LDS_HIP(hipStreamSynchronize(st));
-    LDS_CHECK(err == 0, ST_DEVICE, "device max flow: no progress or a grid barrier did not complete");
-    return flow;
+    return err;
+}
+
+}  // namespace
+
+int64_t edge_mincut_device(int64_t k, const std::vector<int32_t>& pairs, const std::vector<int64_t>& loops, int64_t p,
+                           int64_t q, bool warm, int64_t D, const std::vector<uint32_t>* split, std::vector<char>& inX,
+                           hipStream_t st) {
+    const int64_t ne = (int64_t)pairs.size() / 2, N = k + 2, S = k, T = k + 1;
+    LDS_CHECK(k >= 1 && N < INT32_MAX, ST_INVALID, "device min cut: node count out of range");
+    LDS_CHECK(!warm || (split && (int64_t)split->size() == ne && loops.empty()), ST_INVALID,
+              "device min cut: a warm start needs one split per pair and no loops");
+    const int64_t sc = warm ? D : 1;
+    DBuf<int32_t> dpairs, deg, cur, dto;
+    DBuf<uint32_t> dsplit;
+    DBuf<int64_t> dloops, w, A, first, dcap, drev;
+    DBuf<unsigned long long> to_t;
+    dpairs.alloc(std::max<int64_t>(2 * ne, 1), st);
+    deg.alloc(N, st);
+    cur.alloc(N, st);
+    w.alloc(k, st);
+    first.alloc(N + 1, st);
+    to_t.alloc(1, st);
+    k_fill_u32<<<grid_for(N, 256), 256, 0, st>>>((uint32_t*)deg.p, N, 0u);
+    k_fill_u32<<<grid_for(N, 256), 256, 0, st>>>((uint32_t*)cur.p, N, 0u);
+    k_fill_u32<<<grid_for(2 * (N + 1), 256), 256, 0, st>>>((uint32_t*)first.p, 2 * (N + 1), 0u);
+    k_fill_u32<<<1, 256, 0, st>>>((uint32_t*)to_t.p, 2, 0u);
+    if (ne > 0)
+        LDS_HIP(hipMemcpyAsync(dpairs.p, pairs.data(), 2 * ne * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    if (!loops.empty()) {
+        dloops.alloc(k, st);
+        LDS_HIP(hipMemcpyAsync(dloops.p, loops.data(), k * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    }
+    if (warm) {
+        dsplit.alloc(std::max<int64_t>(ne, 1), st);
+        A.alloc(k, st);
+        k_fill_u32<<<grid_for(2 * k, 256), 256, 0, st>>>((uint32_t*)A.p, 2 * k, 0u);
+        if (ne > 0) LDS_HIP(hipMemcpyAsync(dsplit.p, split->data(), ne * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+    }
+    if (ne > 0) {
+        k_net_deg<<<grid_for(ne, 256), 256, 0, st>>>(dpairs.p, ne, deg.p);
+        if (warm) k_net_shares<<<grid_for(ne, 256), 256, 0, st>>>(dpairs.p, dsplit.p, ne, D, A.p);
+    }
+    // arc counts per node (S's counted by atomics, T's = k), offsets by a scan
+    k_net_counts<<<grid_for(k, 256), 256, 0, st>>>(k, deg.p, dloops.p, w.p, (uint64_t*)first.p);
+    LDS_HIP(hipMemcpyAsync(first.p + T, &k, sizeof(int64_t), hipMemcpyHostToDevice, st));
+    exclusive_scan_u64((const uint64_t*)first.p, (uint64_t*)first.p, N, (uint64_t*)first.p + N, st);
+    int64_t M = 0;
+    LDS_HIP(hipMemcpyAsync(&M, first.p + N, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    LDS_HIP(hipStreamSynchronize(st));
+    dto.alloc(std::max<int64_t>(M, 1), st);
+    dcap.alloc(std::max<int64_t>(M, 1), st);
+    drev.alloc(std::max<int64_t>(M, 1), st);
+    FlowScratch fs;
+    fs.alloc(N, st);
+    if (ne > 0)
+        k_net_edges<<<grid_for(ne, 256), 256, 0, st>>>(dpairs.p, dsplit.p, ne, warm ? 1 : 0, q, D, first.p, cur.p,
+                                                       dto.p, dcap.p, drev.p);
+    k_net_nodes<<<grid_for(k, 256), 256, 0, st>>>(k, deg.p, w.p, A.p, warm ? 1 : 0, p, q, D, sc, first.p,
+                                                  cur.p + S, dto.p, dcap.p, drev.p, fs.ex.p, to_t.p);
+    k_net_ends<<<1, 64, 0, st>>>(k, to_t.p, fs.ex.p);
+    LDS_HIP(hipGetLastError());
+    FlowArgs fa{};
+    fa.first = first.p;
+    fa.to = dto.p;
+    fa.cap = dcap.p;
+    fa.rev = drev.p;
+    fa.ex = fs.ex.p;
+    fa.N = N;
+    fa.s = S;
+    fa.t = T;
+    fa.final_search = 1;
+    run_flow(fa, fs, st);
+    int64_t flow = 0;
+    std::vector<int32_t> h(k);
+    LDS_HIP(hipMemcpyAsync(&flow, fs.ex.p + T, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    LDS_HIP(hipMemcpyAsync(h.data(), fs.h.p, k * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    LDS_CHECK(flow_error(fs, st) == 0, ST_DEVICE, "device min cut: no progress or a grid barrier did not complete");
+    // the maximal source side: the nodes that cannot reach T in the residual graph
+    inX.assign(k, 0);
+    for (int64_t v = 0; v < k; ++v) inX[v] = h[v] >= (int32_t)N ? 1 : 0;
+    int64_t wsum = 0;
+    for (int64_t v = 0; v < k; ++v) wsum += loops.empty() ? 0 : 2 * loops[v];
+    wsum += 2 * ne;
+    return (q * wsum * sc - flow) / (2 * sc);
 }
 
 }  // namespace lds

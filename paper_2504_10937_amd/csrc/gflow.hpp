@@ -1,4 +1,4 @@
-// Maximum preflow of a large network on the device (gflow.hip).
+// Minimum cuts of large vertex networks on the device (gflow.hip).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -7,14 +7,14 @@
 
 namespace lds {
 
-// The network in CSR order (arcs of a node contiguous, rev[e] the paired
-// arc), residual capacities in cap; ex holds every node's excess with the
-// source arcs already saturated (ex[s] = 0, ex[t] = the flow already at t).
-// On return cap holds the residual capacities of a maximum preflow (so the
-// minimum cuts follow from it as after any maximum flow) and the result is
-// the flow into t.  Synchronises the stream.
-int64_t maxflow_device(int64_t N, const std::vector<int64_t>& first, const std::vector<int32_t>& to,
-                       std::vector<int64_t>& cap, const std::vector<int64_t>& rev, int64_t s, int64_t t,
-                       const std::vector<int64_t>& ex, hipStream_t stream);
+// The edge case of IsDensest entirely on the device: Goldberg's vertex network
+// over k nodes (source -> v with capacity q (deg v + 2 loops v), scaled by D
+// and warm-started from the split when warm, v -> sink 2p, each pair an
+// undirected arc of capacity q) is built from the pairs, the flow runs, and
+// inX receives the maximal source side of a minimum cut.  Returns the maximum
+// of q (|E(X)| + loops(X)) - p |X| (as the host version does).
+int64_t edge_mincut_device(int64_t k, const std::vector<int32_t>& pairs, const std::vector<int64_t>& loops, int64_t p,
+                           int64_t q, bool warm, int64_t D, const std::vector<uint32_t>* split, std::vector<char>& inX,
+                           hipStream_t stream);
 
 }  // namespace lds

@@ -86,9 +86,9 @@ int64_t flow_parallel_min_nodes() {
     }
     return g_flow_parallel_min;
 }
-// Vertex networks with at least this many nodes (2^17) take the device
-// push-relabel (gflow.hip) instead; LDS_FLOW_GPU_MIN overrides it, read at
-// every call.  The stream is the one of the search that builds the network.
+// Vertex networks with at least this many nodes (2^17) are built and cut on
+// the device (gflow.hip) instead; LDS_FLOW_GPU_MIN overrides it, read at
+// every call.  The stream is the one of the search that needs the cut.
 int64_t flow_gpu_min_nodes() {
     const char* e = std::getenv("LDS_FLOW_GPU_MIN");
     return (e && *e) ? (int64_t)std::atoll(e) : (int64_t)1 << 17;
@@ -165,8 +165,9 @@ void par_for_rows(const std::vector<int64_t>& rp, int64_t n, F f) {
 struct Flow {
     int64_t N;
     // the synchronous parallel push-relabel (pflow.hpp) is used for large
-    // vertex networks; on pattern networks, whose pattern-to-member arcs are
-    // unbounded, it ran several times slower than the sequential one
+    // vertex networks built on the host; on pattern networks, whose
+    // pattern-to-member arcs are unbounded, it ran several times slower than
+    // the sequential one
     bool allow_parallel = true;
     std::vector<int64_t> pa, pb, pc, pd;  // pending arcs: tail, head, capacity, reverse capacity
     std::vector<int64_t> first, cap, rev;
@@ -261,10 +262,9 @@ struct Flow {
     // already reached t; nullptr = start from zero flow
     int64_t maxflow(int64_t s, int64_t t, const std::vector<int64_t>* init_ex = nullptr, int64_t init_t = 0) {
         finalize();
-        const bool gpu = allow_parallel && N >= flow_gpu_min_nodes();
-        ThreadGrant grant(!gpu && allow_parallel && N >= flow_parallel_min_nodes() ? flow_threads() : 1);
+        ThreadGrant grant(allow_parallel && N >= flow_parallel_min_nodes() ? flow_threads() : 1);
         const int threads = grant.n;
-        if (gpu || threads > 1) {
+        if (threads > 1) {
             std::vector<int64_t> ex(N, 0);
             if (init_ex) {
                 for (int64_t v = 0; v < N && v < (int64_t)init_ex->size(); ++v) ex[v] = (*init_ex)[v];
@@ -278,7 +278,6 @@ struct Flow {
                     ex[to[e]] += d;
                 }
             ex[s] = 0;
-            if (gpu) return maxflow_device(N, first, to, cap, rev, s, t, ex, g_flow_stream);
             return maxflow_parallel(N, first, to, cap, rev, s, t, ex, threads);
         }
         std::vector<int64_t> h(N, 0), ex(N, 0), it(first.begin(), first.end() - 1);
@@ -410,6 +409,13 @@ int64_t max_excess_edges(int64_t k, const std::vector<int32_t>& pairs, const std
                          int64_t q, std::vector<char>& inX, const std::vector<uint32_t>* split = nullptr,
                          int64_t D = 1) {
     const int64_t ne = (int64_t)pairs.size() / 2;
+    if (k >= 1 && k + 2 >= flow_gpu_min_nodes()) {  // built, cut and read on the device
+        int64_t wsum = 2 * ne;
+        for (const int64_t l : loops) wsum += 2 * l;
+        const bool warm = split && loops.empty() && D > 0 &&
+                          (i128)q * D * (wsum + 1) + (i128)2 * p * D * (k + 1) < ((i128)1 << 61);
+        return edge_mincut_device(k, pairs, loops, p, q, warm, D, split, inX, g_flow_stream);
+    }
     // large networks are built by several threads (atomic counts and arc slots)
     const bool par = k + 2 >= flow_parallel_min_nodes() && flow_threads() > 1;
     std::vector<int64_t> w(k, 0), deg(k, 0);

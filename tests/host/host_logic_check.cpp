@@ -24,8 +24,8 @@ Graph::~Graph() {}
 void build_graph(Graph&, int64_t, int64_t, const int32_t*, const int32_t*, bool, bool, hipStream_t) {}
 void list_triangles(Graph&, hipStream_t) {}
 void vertex_triangle_lists(const Graph&, int64_t*, int32_t*, hipStream_t) {}
-int64_t maxflow_device(int64_t, const std::vector<int64_t>&, const std::vector<int32_t>&, std::vector<int64_t>&,
-                       const std::vector<int64_t>&, int64_t, int64_t, const std::vector<int64_t>&, hipStream_t) {
+int64_t edge_mincut_device(int64_t, const std::vector<int32_t>&, const std::vector<int64_t>&, int64_t, int64_t, bool,
+                           int64_t, const std::vector<uint32_t>*, std::vector<char>&, hipStream_t) {
     std::abort();  // main() keeps every network on the host
 }
 void sg_stable_groups(Graph&, int, hipStream_t) {}
