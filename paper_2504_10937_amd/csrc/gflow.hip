@@ -84,7 +84,10 @@ __device__ inline int64_t readlane_i64(int64_t v, int lane) {
 // them in flight per wave, while the few hubs get a wave's 64 lanes.  The
 // workgroups take the list in blocks of kFT; a block's large nodes go through
 // a list in LDS.  Every thread of the workgroup must call it.
-constexpr int kSmallDeg = 32;
+#ifndef LDS_FLOW_SMALL_DEG
+#define LDS_FLOW_SMALL_DEG 64
+#endif
+constexpr int kSmallDeg = LDS_FLOW_SMALL_DEG;
 constexpr int kLU = 8;  // arcs of a lane's node loaded together
 constexpr int kWU = 4;  // rows of 64 arcs of a wave's node loaded together
 
