@@ -74,8 +74,9 @@ __global__ void k_order(const uint32_t* vals, int64_t n, int32_t* order, int64_t
 // --------------------------------------------------- split numerators per slot
 // a = a0 + sum_i inc_i [slot won in iteration i], walking the sweep plan so
 // that the bit position of a slot is known without a row search.  A block
-// takes its hub row or chunk in spans of kSpanW decision words (64 slots
-// each).  The span's words of kIterB iterations at a time are staged in LDS
+// takes one hub-row piece or one chunk (at most kPiece slots either way, so
+// the largest rows do not serialise in one block) in spans of kSpanW
+// decision words (64 slots each).  The span's words of kIterB iterations at a time are staged in LDS
 // by coalesced loads (a wave loads four whole 128-byte segments), and each
 // thread then tests the bits of its slots there (the lanes of a wave read
 // one word: a broadcast), so every decision word is read from memory once
@@ -83,19 +84,21 @@ __global__ void k_order(const uint32_t* vals, int64_t n, int32_t* order, int64_t
 constexpr int kSpanW = 16;
 constexpr int kIterB = 64;
 
-__global__ __launch_bounds__(kT) void k_slot_splits(const int64_t* rp, int64_t n_hub, const int64_t* hwo, int64_t n_chunks,
+__global__ __launch_bounds__(kT) void k_slot_splits(const int64_t* rp, int64_t n_pieces, const int32_t* hp_row,
+                                                    const int32_t* hp_off, const int64_t* hwo, int64_t n_chunks,
                                                     const int64_t* chunk_row, const int64_t* cwo, int64_t chunk_words,
                                                     const uint64_t* bits, int64_t total_words, int iters, int tri,
                                                     uint32_t* a_slot) {
     __shared__ uint64_t sw[kIterB][kSpanW];
     const int64_t b = blockIdx.x;
     int64_t s0, s1, word0;
-    if (b < n_hub) {
-        s0 = rp[b];
-        s1 = rp[b + 1];
-        word0 = chunk_words + hwo[b];
+    if (b < n_pieces) {  // a hub row's piece (word-aligned, at most kPiece slots)
+        const int64_t r = hp_row[b];
+        s0 = rp[r] + hp_off[b];
+        s1 = min(rp[r + 1], s0 + (int64_t)kPiece);
+        word0 = chunk_words + hwo[r] + hp_off[b] / 64;
     } else {
-        const int64_t c = b - n_hub;
+        const int64_t c = b - n_pieces;
         if (c >= n_chunks) return;
         s0 = rp[chunk_row[c]];
         s1 = rp[chunk_row[c + 1]];
@@ -103,11 +106,15 @@ __global__ __launch_bounds__(kT) void k_slot_splits(const int64_t* rp, int64_t n
     }
     constexpr int kPer = 64 * kSpanW / kT;  // slots per thread and span
     const int t = threadIdx.x;
-    const uint64_t a0 = tri ? 2 : 1, c2 = tri ? 6 : 2;
+    // split numerators are at most D, which the 32-bit per-slot array holds;
+    // each iteration's test is one bit extract and one 24-bit multiply-add
+    // (the increments c2 (i + 1) are far below 2^24)
+    const uint32_t a0 = tri ? 2u : 1u, c2 = tri ? 6u : 2u;
+    const uint32_t* sw32 = reinterpret_cast<const uint32_t*>(&sw[0][0]);
     for (int64_t base = s0; base < s1; base += 64 * kSpanW) {
         const int64_t w0 = word0 + (base - s0) / 64;
         const int64_t nw = min<int64_t>(kSpanW, (s1 - base + 63) / 64);
-        uint64_t acc[kPer];
+        uint32_t acc[kPer];
 #pragma unroll
         for (int q = 0; q < kPer; ++q) acc[q] = a0;
         for (int i0 = 0; i0 < iters; i0 += kIterB) {
@@ -121,15 +128,16 @@ __global__ __launch_bounds__(kT) void k_slot_splits(const int64_t* rp, int64_t n
 #pragma unroll
             for (int q = 0; q < kPer; ++q) {
                 const int local = t + kT * q;
-                const int ww = local >> 6, bit = local & 63;
-                for (int ii = 0; ii < ni; ++ii)
-                    if ((sw[ii][ww] >> bit) & 1ull) acc[q] += c2 * (uint64_t)(i0 + ii + 2);  // iteration i0+ii+1
+                const int half = 2 * (local >> 6) + ((local >> 5) & 1), sh = local & 31;  // 32-bit half of the word
+                uint32_t inc = c2 * (uint32_t)(i0 + 2);                                 // iteration i0 + 1
+                for (int ii = 0; ii < ni; ++ii, inc += c2)
+                    acc[q] += __umul24(__builtin_amdgcn_ubfe(sw32[ii * 2 * kSpanW + half], sh, 1), inc);
             }
         }
 #pragma unroll
         for (int q = 0; q < kPer; ++q) {
             const int64_t s = base + t + kT * q;
-            if (s < s1) a_slot[s] = (uint32_t)acc[q];
+            if (s < s1) a_slot[s] = acc[q];
         }
     }
 }
@@ -1150,10 +1158,10 @@ void sg_sort_prefix(Graph& g, int mode, hipStream_t s) {
     // per-slot split numerators (and per triangle)
     q.a_slot.alloc(p.nslots, s);
     if (p.nslots > 0 && f.iters >= 0) {
-        const int64_t blocks = p.n_hub + p.n_chunks;
-        k_slot_splits<<<grid_for(blocks, 1), kT, 0, s>>>(p.rp, p.n_hub, p.hwo.p, p.n_chunks, p.chunk_row.p, p.cwo.p,
-                                                         p.chunk_words, f.bits.p, p.total_words, f.iters, mode == 3,
-                                                         q.a_slot.p);
+        const int64_t blocks = p.n_pieces + p.n_chunks;
+        k_slot_splits<<<grid_for(blocks, 1), kT, 0, s>>>(p.rp, p.n_pieces, p.hp_row.p, p.hp_off.p, p.hwo.p, p.n_chunks,
+                                                         p.chunk_row.p, p.cwo.p, p.chunk_words, f.bits.p,
+                                                         p.total_words, f.iters, mode == 3, q.a_slot.p);
         LDS_HIP(hipGetLastError());
     }
     if (mode == 3) {
