@@ -70,7 +70,9 @@ lds_status lds_set_allocator(lds_alloc_fn alloc, lds_free_fn free_fn, void* ctx)
  * n: number of vertices (0 <= n < 2^31).  src/dst: npairs int32 endpoint
  * ids in [0,n), host or device memory (LDS_INPUT_DEVICE); the caller keeps
  * ownership and may free them on return.  Pairs are undirected; self-loops
- * and duplicates are dropped unless LDS_STRICT (then LDS_E_INVALID).
+ * and duplicates are dropped unless LDS_STRICT (then LDS_E_INVALID).  At
+ * most 2^31 - 1 unique edges (LDS_E_OVERFLOW beyond: the symmetric CSR's
+ * slots are sorted per row with 32-bit counts).
  * On success *out owns its device memory until lds_destroy_graph. */
 lds_status lds_create_graph(int64_t n, int64_t npairs, const int32_t* src, const int32_t* dst, uint32_t flags,
                             void* hip_stream, lds_graph* out);
