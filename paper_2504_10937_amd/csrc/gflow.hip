@@ -4,7 +4,7 @@
 // the host threads' version (pflow.hpp) laid out for the GPU.
 //
 // One cooperative launch; the workgroups meet at grid barriers between the
-// phases of a pulse, all labels fixed within a phase:
+// two phases of a pulse:
 //   push     every active node v pushes its excess along admissible arcs
 //            (h[w] == h[v] - 1, residual capacity) in arc order: a node
 //            with few arcs on one lane, a large one on a wave whose lanes
@@ -12,22 +12,30 @@
 //            two nodes never push along the two arcs of
 //            one pair in the same phase (that would need h[v] == h[w] - 1
 //            and h[w] == h[v] - 1), so only the excess needs atomics;
-//   relabel  a node with excess left and no admissible arc takes 1 + the
-//            smallest label over its residual arcs, from the old labels;
-//   apply    the new labels;
-//   collect  nodes that received excess or were relabelled below N form the
-//            next active list.
+//            receivers join the next active list;
+//   relabel  a node with excess left (every arc it could push along is
+//            saturated, so each residual arc leads to a label >= its own)
+//            takes 1 + the smallest label over its residual arcs, written
+//            in place, and joins the next active list.  A label read while
+//            its node is relabelled is the old or the new one; both are at
+//            most the new one, so the labelling stays valid, and the new
+//            label still exceeds the old.
+// A node joins a list at most once per pulse: it swaps the pulse's tag into
+// its mark, and only the swap that changes the mark appends it.  Entries
+// whose excess is gone by the next pulse are skipped there.
 // Exact distance labels come from a level-synchronous backward search from t
-// (nodes claimed by compare-and-swap) at the start and after every N
-// relabels.  The result is a maximum preflow, so the residual graph gives the
+// (nodes claimed by compare-and-swap; its first level, t's arcs, spread over
+// the whole grid) at the start and after every N relabels.  The result is a maximum preflow, so the residual graph gives the
 // same minimum cuts as any maximum flow.
 //
 // List counters live in two rings of four words indexed by the phase number:
 // a phase pushes into slot ph & 3, which workgroup 0 zeroed during phase
-// ph - 1; its previous value was read right after barrier ph - 3, and every
-// workgroup has passed that point by then.  Every decision is taken from
-// values read after a barrier, so control flow is uniform.  Waits and loops
-// are bounded; past a bound the kernel raises an error flag and ends.
+// ph - 1 (the relabel phase appends to its push phase's slot); a slot's
+// value is read right after the barrier that ends its last writer, and
+// workgroup 0 zeroes it again two phases later, after every workgroup has
+// passed that read.  Every decision is taken from values read after a
+// barrier, so control flow is uniform.  Waits and loops are bounded; past a
+// bound the kernel raises an error flag and ends.
 #include <algorithm>
 #include <climits>
 #include <cstdlib>
@@ -51,8 +59,7 @@ struct FlowArgs {
     const int64_t* rev;
     int64_t* ex;
     int32_t* h;
-    int32_t* hn;
-    uint32_t* queued;
+    uint32_t* queued;  // the tag of the last pulse whose next list holds the node
     int32_t* act;
     int32_t* act2;
     int32_t* nxt;
@@ -145,33 +152,35 @@ __global__ __launch_bounds__(kFT) void k_maxflow(FlowArgs a) {
         ++ph;
         int32_t* F = a.nxt;
         int32_t* G = a.r3;
+        // x (the tail of arc rev[e], a residual arc into the frontier) takes
+        // label lvl and joins list L, once
+        auto claim = [&](int32_t x, int32_t lvl, int32_t* L, int32_t* slot) {
+            if (a.h[x] != HN) return;
+            int32_t want = HN;
+            if (__hip_atomic_compare_exchange_strong(&a.h[x], &want, lvl, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT))
+                push_list(L, slot, x);
+        };
+        // level 1: t has an arc from nearly every node, so its arcs are
+        // spread over the whole grid
         int32_t* slot = ring1 + (ph & 3);
-        if (gt == 0) {
-            a.h[a.t] = 0;
-            F[0] = (int32_t)a.t;
-            *slot = 1;
+        if (gt == 0) a.h[a.t] = 0;
+        for (int64_t e = a.first[a.t] + gt; e < a.first[a.t + 1]; e += nthr) {
+            const int32_t x = a.to[e];
+            if (x != a.s && a.cap[a.rev[e]] > 0) claim(x, 1, F, slot);
         }
         end_phase();
         int32_t fc = *slot;
         ++ph;
-        for (int32_t lvl = 1; fc > 0; ++lvl) {
+        for (int32_t lvl = 2; fc > 0; ++lvl) {
             if (s_err || lvl > HN) {
                 bad = true;
                 return;
             }
             slot = ring1 + (ph & 3);
-            // x reaches y in the residual graph: the arc x -> y is rev[e]
-            auto claim = [&](int64_t e) {
-                const int32_t x = a.to[e];
-                if (x == a.s || a.cap[a.rev[e]] <= 0 || a.h[x] != HN) return;
-                int32_t want = HN;
-                if (__hip_atomic_compare_exchange_strong(&a.h[x], &want, lvl, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                         __HIP_MEMORY_SCOPE_AGENT))
-                    push_list(G, slot, x);
-            };
             node_pass(
                 a, F, fc, sbig, &sbn,
-                [&](int32_t y) {
+                [&](int32_t y) {  // one lane: the arcs eight at a time
                     const int64_t e1 = a.first[y + 1];
                     for (int64_t e0 = a.first[y]; e0 < e1; e0 += kLU) {
                         int32_t x[kLU];
@@ -184,17 +193,26 @@ __global__ __launch_bounds__(kFT) void k_maxflow(FlowArgs a) {
                             ok[u] = ok[u] && x[u] != a.s && a.cap[a.rev[e]] > 0;
                         }
 #pragma unroll
-                        for (int u = 0; u < kLU; ++u) {
-                            if (!ok[u] || a.h[x[u]] != HN) continue;
-                            int32_t want = HN;
-                            if (__hip_atomic_compare_exchange_strong(&a.h[x[u]], &want, lvl, __ATOMIC_RELAXED,
-                                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-                                push_list(G, slot, x[u]);
-                        }
+                        for (int u = 0; u < kLU; ++u)
+                            if (ok[u]) claim(x[u], lvl, G, slot);
                     }
                 },
-                [&](int32_t y) {
-                    for (int64_t e = a.first[y] + lane; e < a.first[y + 1]; e += 64) claim(e);
+                [&](int32_t y) {  // one wave: rows of 64 arcs, kWU rows at a time
+                    const int64_t e1 = a.first[y + 1];
+                    for (int64_t eb = a.first[y] + lane; eb < e1; eb += 64 * kWU) {
+                        int32_t x[kWU];
+                        bool ok[kWU];
+#pragma unroll
+                        for (int u = 0; u < kWU; ++u) {
+                            const int64_t e = eb + 64 * u;
+                            ok[u] = e < e1;
+                            x[u] = ok[u] ? a.to[e] : 0;
+                            ok[u] = ok[u] && x[u] != a.s && a.cap[a.rev[e]] > 0;
+                        }
+#pragma unroll
+                        for (int u = 0; u < kWU; ++u)
+                            if (ok[u]) claim(x[u], lvl, G, slot);
+                    }
                 });
             end_phase();
             fc = *slot;
@@ -217,21 +235,27 @@ __global__ __launch_bounds__(kFT) void k_maxflow(FlowArgs a) {
     };
     global_relabel();
     int64_t relabels = 0;
-    const int64_t max_pulses = 4 * N + 100000;  // far above what a run needs; a bound, not a budget
+    // far above what a run needs (a bound, not a budget); it also keeps the
+    // pulse tags distinct
+    const int64_t max_pulses = min(4 * N + 100000, (int64_t)0x7ffffff0);
     for (int64_t pulse = 0; na > 0 && !bad; ++pulse) {
         if (s_err || pulse > max_pulses) {
             bad = true;
             break;
         }
-        // push
+        const uint32_t tag = (uint32_t)pulse + 1u;
+        // push; s1 counts the next list over both phases of the pulse
         int32_t* s1 = ring1 + (ph & 3);
         int32_t* s2 = ring2 + (ph & 3);
-        // pushes d along arc e (v -> w); the receiver joins the next list once
+        auto join_next = [&](int32_t v) {
+            if (atomicExch(&a.queued[v], tag) != tag) push_list(act2, s1, v);
+        };
+        // pushes d along arc e (v -> w)
         auto push_arc = [&](int64_t e, int32_t w, int64_t c, int64_t d) {
             a.cap[e] = c - d;
             a.cap[a.rev[e]] += d;
             atomicAdd((unsigned long long*)&a.ex[w], (unsigned long long)d);
-            if (w != a.t && w != a.s && atomicExch(&a.queued[w], 1u) == 0u) push_list(a.nxt, s1, w);
+            if (w != a.t && w != a.s) join_next(w);
         };
         node_pass(
             a, act, na, sbig, &sbn,
@@ -306,9 +330,14 @@ __global__ __launch_bounds__(kFT) void k_maxflow(FlowArgs a) {
                 }
             });
         end_phase();
-        const int32_t nN = *s1, nR = *s2;
+        const int32_t nR = *s2;
         ++ph;
-        // relabel, from the old labels
+        // relabel in place, then join the next list
+        auto relabel_to = [&](int32_t v, int32_t mh) {
+            const int32_t nh = (mh >= HN) ? HN : mh + 1;
+            a.h[v] = nh;
+            if (nh < HN) join_next(v);
+        };
         node_pass(
             a, a.rel, nR, sbig, &sbn,
             [&](int32_t v) {
@@ -322,7 +351,7 @@ __global__ __launch_bounds__(kFT) void k_maxflow(FlowArgs a) {
                     for (int u = 0; u < kLU; ++u)
                         if (w[u] >= 0) mh = min(mh, a.h[w[u]]);
                 }
-                a.hn[v] = (mh >= HN) ? HN : mh + 1;
+                relabel_to(v, mh);
             },
             [&](int32_t v) {
                 int32_t mh = INT32_MAX;
@@ -339,31 +368,12 @@ __global__ __launch_bounds__(kFT) void k_maxflow(FlowArgs a) {
                         if (w[u] >= 0) mh = min(mh, a.h[w[u]]);
                 }
                 for (int o = 32; o > 0; o >>= 1) mh = min(mh, __shfl_xor(mh, o, 64));
-                if (lane == 0) a.hn[v] = (mh >= HN) ? HN : mh + 1;
+                if (lane == 0) relabel_to(v, mh);
             });
-        end_phase();
-        ++ph;
-        // apply the new labels
-        s1 = ring1 + (ph & 3);
-        for (int64_t i = gt; i < nR; i += nthr) {
-            const int32_t v = a.rel[i];
-            a.h[v] = a.hn[v];
-            if (a.h[v] < HN && atomicExch(&a.queued[v], 1u) == 0u) push_list(a.r3, s1, v);
-        }
-        end_phase();
-        const int32_t n3 = *s1;
-        ++ph;
-        relabels += nR;
-        // collect the next active list
-        s1 = ring1 + (ph & 3);
-        for (int64_t i = gt; i < (int64_t)nN + n3; i += nthr) {
-            const int32_t v = i < nN ? a.nxt[i] : a.r3[i - nN];
-            a.queued[v] = 0u;
-            if (a.h[v] < HN && a.ex[v] > 0) push_list(act2, s1, v);
-        }
         end_phase();
         na = *s1;
         ++ph;
+        relabels += nR;
         int32_t* tmp = act;
         act = act2;
         act2 = tmp;
@@ -475,13 +485,12 @@ __global__ void k_net_ends(int64_t k, const unsigned long long* to_t, int64_t* e
 // the scratch of a device flow over N nodes
 struct FlowScratch {
     DBuf<int64_t> ex;
-    DBuf<int32_t> h, hn, act, act2, nxt, rel, r3, ctr;
+    DBuf<int32_t> h, act, act2, nxt, rel, r3, ctr;
     DBuf<uint32_t> queued;
     DBuf<unsigned> bar;
     void alloc(int64_t N, hipStream_t st) {
         ex.alloc(N, st);
         h.alloc(N, st);
-        hn.alloc(N, st);
         queued.alloc(N, st);
         act.alloc(N, st);
         act2.alloc(N, st);
@@ -501,7 +510,6 @@ struct FlowScratch {
 void run_flow(FlowArgs& fa, FlowScratch& sc, hipStream_t st) {
     const int64_t N = fa.N;
     fa.h = sc.h.p;
-    fa.hn = sc.hn.p;
     fa.queued = sc.queued.p;
     fa.act = sc.act.p;
     fa.act2 = sc.act2.p;
