@@ -748,8 +748,62 @@ void induced_patterns(Ctx& c, const std::vector<int32_t>& vs, std::vector<int32_
     for (int32_t v : vs) c.loc[v] = -1;
 }
 
-// connected components (by edges) of G[vs]
+// Is G[vs] connected?  A union-find over host threads: a root is linked
+// below a smaller index by compare-and-swap and finds halve their paths, so
+// every parent index is at most its own and no cycle can form; a link that
+// loses a race is retried from the new roots.  The answer does not depend on
+// the thread count or interleaving.  loc is -1 at every vertex on entry and
+// on return.
+bool induced_connected(const HostGraph& h, std::vector<int32_t>& loc, const std::vector<int32_t>& vs) {
+    const int64_t k = (int64_t)vs.size();
+    if (k <= 1) return true;
+    for (int64_t i = 0; i < k; ++i) loc[vs[i]] = (int32_t)i;
+    std::unique_ptr<std::atomic<int32_t>[]> par(new std::atomic<int32_t>[k]);
+    for (int64_t i = 0; i < k; ++i) par[i].store((int32_t)i, std::memory_order_relaxed);
+    auto find = [&](int32_t x) {
+        for (;;) {
+            int32_t p = par[x].load(std::memory_order_relaxed);
+            if (p == x) return x;
+            const int32_t g = par[p].load(std::memory_order_relaxed);
+            if (g != p) par[x].compare_exchange_weak(p, g, std::memory_order_relaxed);
+            x = g;
+        }
+    };
+    auto unite = [&](int32_t a, int32_t b) {
+        for (;;) {
+            a = find(a);
+            b = find(b);
+            if (a == b) return;
+            if (a < b) std::swap(a, b);
+            int32_t want = a;
+            if (par[a].compare_exchange_strong(want, b, std::memory_order_relaxed)) return;
+        }
+    };
+    // chunks of vs taken from a shared counter (a candidate in degree order
+    // puts every hub in the first range)
+    std::atomic<int64_t> next{0};
+    par_for(k, [&](int64_t, int64_t) {
+        for (;;) {
+            const int64_t c0 = next.fetch_add(4096), c1 = std::min(k, c0 + 4096);
+            if (c0 >= k) break;
+            for (int64_t i = c0; i < c1; ++i)
+                for (int64_t s = h.rp[vs[i]]; s < h.rp[vs[i] + 1]; ++s) {
+                    const int32_t j = loc[h.col[s]];
+                    if (j > (int32_t)i) unite((int32_t)i, j);
+                }
+        }
+    });
+    const int32_t r = find(0);
+    bool ok = true;
+    for (int64_t i = 1; i < k && ok; ++i) ok = find((int32_t)i) == r;
+    for (int32_t v : vs) loc[v] = -1;
+    return ok;
+}
+
+// connected components (by edges) of G[vs]; a large connected G[vs] (the
+// usual case, e.g. a whole graph) is recognised over host threads first
 std::vector<std::vector<int32_t>> components(Ctx& c, const std::vector<int32_t>& vs) {
+    if ((int64_t)vs.size() >= (1 << 16) && induced_connected(c.h, c.loc, vs)) return {vs};
     for (int32_t v : vs) c.mark[v] = 0;
     std::vector<std::vector<int32_t>> out;
     for (int32_t v0 : vs) {

@@ -4,7 +4,9 @@
 // small random inputs:
 //   * minimum cuts (edge network, pattern network, both warm-started from
 //     arbitrary splits): the maximum of q*|P(X)| - p*|X| and the union of all
-//     maximisers, by enumeration of every X.
+//     maximisers, by enumeration of every X;
+//   * connectivity of induced subgraphs (union-find over host threads) by a
+//     breadth-first search.
 // (Core and tr-core numbers run on the device; their parity is a GPU test.)
 // The battery runs twice: with the sequential push-relabel and with every
 // vertex network through the parallel one (pflow.hpp; pattern networks always
@@ -168,6 +170,62 @@ static int parallel_vs_sequential(int& cases) {
     return bad;
 }
 
+// connectivity of induced subgraphs over host threads against a plain BFS,
+// on random sparse graphs (some split into many pieces) and random subsets
+static int connectivity(int& cases) {
+    std::mt19937_64 rng(4242);
+    int bad = 0;
+    for (int it = 0; it < 60; ++it) {
+        const int64_t n = 5000 + (int64_t)(rng() % 30000);
+        const int64_t m = n * (1 + (int64_t)(rng() % 3)) / 2 + (int64_t)(rng() % 8) * n / 8;
+        std::vector<std::vector<int32_t>> adj(n);
+        std::vector<int32_t> vs;
+        const int keep = (it % 3 == 0) ? 100 : 60 + (int)(rng() % 40);  // percent of the vertices
+        for (int32_t v = 0; v < n; ++v)
+            if ((int)(rng() % 100) < keep) vs.push_back(v);
+        for (int64_t e = 0; e < m; ++e) {
+            const int32_t a = (int32_t)(rng() % n), b = (int32_t)(rng() % n);
+            if (a == b) continue;
+            adj[a].push_back(b);
+            adj[b].push_back(a);
+        }
+        if (it % 2 == 0)  // a random spanning tree of G[vs]: connected
+            for (size_t i = 1; i < vs.size(); ++i) {
+                const int32_t a = vs[i], b = vs[rng() % i];
+                adj[a].push_back(b);
+                adj[b].push_back(a);
+            }
+        HostGraph h;
+        h.n = n;
+        h.rp.assign(n + 1, 0);
+        for (int64_t v = 0; v < n; ++v) h.rp[v + 1] = h.rp[v] + (int64_t)adj[v].size();
+        h.col.resize(h.rp[n]);
+        for (int64_t v = 0; v < n; ++v) std::copy(adj[v].begin(), adj[v].end(), h.col.begin() + h.rp[v]);
+        std::vector<int32_t> loc(n, -1);
+        // BFS over G[vs]
+        std::vector<char> in(n, 0), seen(n, 0);
+        for (int32_t v : vs) in[v] = 1;
+        std::vector<int32_t> q{vs.empty() ? 0 : vs[0]};
+        if (!vs.empty()) seen[vs[0]] = 1;
+        for (size_t i = 0; i < q.size() && !vs.empty(); ++i)
+            for (int32_t w : adj[q[i]])
+                if (in[w] && !seen[w]) {
+                    seen[w] = 1;
+                    q.push_back(w);
+                }
+        const bool want = vs.empty() || q.size() == vs.size();
+        if (want != (it % 2 == 0)) ++bad;  // planted trees connect, the sparse rest does not
+        ++cases;
+        if (induced_connected(h, loc, vs) != want) ++bad;
+        for (int32_t x : loc)
+            if (x != -1) {
+                ++bad;
+                break;
+            }
+    }
+    return bad;
+}
+
 int main() {
     setenv("LDS_FLOW_GPU_MIN", "9223372036854775807", 1);  // no device here: host min cuts only
     int cases = 0, bad = 0;
@@ -177,6 +235,7 @@ int main() {
     g_flow_parallel_min = 0;  // every vertex network through the parallel one
     bad += battery(cases);
     bad += parallel_vs_sequential(cases);
+    bad += connectivity(cases);
     std::printf("%s: %d of %d cases disagree\n", bad ? "FAIL" : "ok", bad, cases);
     return bad ? 1 : 0;
 }
