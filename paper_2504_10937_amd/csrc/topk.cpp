@@ -588,11 +588,11 @@ bool topk_threads_single() { return g_single; }
 
 // ----------------------------------------------------------- host graph
 namespace {
-// device -> host copy of count elements into v: the destination pages are
-// faulted in by the granted host threads first (one write per page), then
-// one copy fills them
+// v resized to count elements, left uninitialised, its pages faulted in by
+// the granted host threads (one write per page), ready for one device copy;
+// a copy into untouched pages faults them in one by one on one thread
 template <class V>
-void d2h_fill(V& v, const void* dev, size_t count, hipStream_t s) {
+void host_prefault(V& v, size_t count) {
     v.resize(count);
     if (count == 0) return;
     char* p = (char*)v.data();
@@ -600,7 +600,12 @@ void d2h_fill(V& v, const void* dev, size_t count, hipStream_t s) {
     par_for((int64_t)((bytes + 4095) / 4096), [&](int64_t a, int64_t b) {
         for (int64_t i = a; i < b; ++i) p[(size_t)i * 4096] = 0;
     });
-    LDS_HIP(hipMemcpyAsync(p, dev, bytes, hipMemcpyDeviceToHost, s));
+}
+// device -> host copy of count elements into v
+template <class V>
+void d2h_fill(V& v, const void* dev, size_t count, hipStream_t s) {
+    host_prefault(v, count);
+    if (count) LDS_HIP(hipMemcpyAsync(v.data(), dev, count * sizeof(v[0]), hipMemcpyDeviceToHost, s));
 }
 }  // namespace
 
@@ -614,16 +619,13 @@ void HostGraph::load(const Graph& g, int mode, hipStream_t s) {
     }
     d2h_fill(col, g.col.p, (size_t)(2 * g.m), s);
     tri.clear();
-    if (mode == 3 && g.T > 0) {
-        tri.assign(3 * g.T, 0);
-        LDS_HIP(hipMemcpyAsync(tri.data(), g.tri.p, 3 * g.T * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    }
+    if (mode == 3 && g.T > 0) d2h_fill(tri, g.tri.p, (size_t)(3 * g.T), s);
     LDS_HIP(hipStreamSynchronize(s));
     trp.clear();
     tinc.clear();
     if (mode == 3) {  // each vertex's triangles, listed on the device
         trp.resize(n + 1);
-        tinc.resize(tri.size());
+        host_prefault(tinc, tri.size());
         vertex_triangle_lists(g, trp.data(), tinc.data(), s);
     }
 }

@@ -39,9 +39,9 @@ struct HostGraph {
     std::vector<int64_t> rp;    // n + 1
     host_vec<int32_t> col;      // 2m neighbours
     std::vector<int32_t> orig;  // internal -> caller id
-    std::vector<int32_t> tri;   // 3T (triangles only)
+    host_vec<int32_t> tri;      // 3T (triangles only)
     std::vector<int64_t> trp;   // n + 1 offsets into tinc
-    std::vector<int32_t> tinc;  // triangle indices incident to each vertex (ascending)
+    host_vec<int32_t> tinc;     // triangle indices incident to each vertex (ascending)
     void load(const Graph& g, int mode, hipStream_t s);
 };
 
