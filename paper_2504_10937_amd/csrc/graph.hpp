@@ -167,6 +167,10 @@ void sg_sort_prefix(Graph& g, int mode, hipStream_t s);
 void sg_stable_groups(Graph& g, int mode, hipStream_t s);
 // lo / hi of the last stable-group scan, by original id, into host memory
 void sg_copy_bounds(const Graph& g, int mode, int64_t* lo_out, int64_t* hi_out, hipStream_t s);
+// out[i] = the FW split numerator at idx[i] (edges: CSR slot; triangles:
+// 3 * triangle + member) of the graph's last stable-group run, for host idx /
+// out of n elements; raises on an index out of range
+void gather_split(const Graph& g, int mode, const int64_t* idx, int64_t n, uint32_t* out, hipStream_t s);
 
 // cores.hip: core (mode 2) / tr-core (mode 3) numbers of the subgraph induced
 // by alive (device bytes, internal order; nullptr = all vertices) into core

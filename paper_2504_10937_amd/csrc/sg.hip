@@ -1380,6 +1380,45 @@ __global__ void k_by_orig(const int64_t* lo, const int64_t* hi, const int32_t* o
 }
 }  // namespace
 
+namespace {
+// out[i] = src[idx[i]]; an index outside [0, n_src) raises *err and gives 0
+__global__ void k_gather_u32(const uint32_t* src, int64_t n_src, const int64_t* idx, int64_t n, uint32_t* out,
+                             int32_t* err) {
+    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (i >= n) return;
+    const int64_t j = idx[i];
+    if (j < 0 || j >= n_src) {
+        *err = 1;
+        out[i] = 0;
+        return;
+    }
+    out[i] = src[j];
+}
+}  // namespace
+
+void gather_split(const Graph& g, int mode, const int64_t* idx, int64_t n, uint32_t* out, hipStream_t s) {
+    if (n <= 0) return;
+    const SgState& q = g.sg[mode == 2 ? 0 : 1];
+    const uint32_t* src = mode == 2 ? q.a_slot.p : q.a_tri.p;
+    const int64_t n_src = mode == 2 ? 2 * g.m : 3 * g.T;
+    LDS_CHECK(src != nullptr && n_src > 0, ST_INVALID, "split gather: no split numerators for this mode");
+    DBuf<int64_t> di;
+    DBuf<uint32_t> dout;
+    DBuf<int32_t> err;
+    di.alloc(n, s);
+    dout.alloc(n, s);
+    err.alloc(1, s);
+    LDS_HIP(hipMemsetAsync(err.p, 0, sizeof(int32_t), s));
+    LDS_HIP(hipMemcpyAsync(di.p, idx, n * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    k_gather_u32<<<grid_for(n, kT), kT, 0, s>>>(src, n_src, di.p, n, dout.p, err.p);
+    LDS_HIP(hipGetLastError());
+    int32_t bad = 0;
+    LDS_HIP(hipMemcpyAsync(out, dout.p, n * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    LDS_HIP(hipMemcpyAsync(&bad, err.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    LDS_HIP(hipStreamSynchronize(s));
+    LDS_CHECK(bad == 0, ST_INVALID, "split gather: index out of range");
+}
+
 void sg_copy_bounds(const Graph& g, int mode, int64_t* lo_out, int64_t* hi_out, hipStream_t s) {
     const SgState& q = g.sg[mode == 2 ? 0 : 1];
     const int64_t n = g.n;

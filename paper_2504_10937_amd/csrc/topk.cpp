@@ -676,7 +676,7 @@ struct Ctx {
     std::vector<Frac> lo, hi;     // bounds on phi_G, valid for every vertex
     std::vector<int32_t> loc;     // scratch: internal id -> local index, -1 outside
     std::vector<int32_t> mark;    // scratch, -1 outside
-    host_vec<uint32_t> split;     // FW split numerators over splitD: edges per CSR slot, triangles 3 per triangle
+    bool warm = false;            // the graph's FW split (over splitD) is on the device for warm starts
     int64_t splitD = 1;
     TopkStats* st = nullptr;
     int64_t seq = 0;
@@ -684,15 +684,18 @@ struct Ctx {
 };
 
 // patterns of G[vs] by local index (edges: pairs, triangles: triples)
-// split (edges, optional): the FW split numerator of each pair's first vertex
+// split (optional): the graph's FW split numerators of the patterns (edges:
+// the pair's first vertex's share, triangles: the three members' shares),
+// gathered on the device from the indices collected here
 void induced_patterns(Ctx& c, const std::vector<int32_t>& vs, std::vector<int32_t>& pat,
                       std::vector<uint32_t>* split = nullptr) {
     const HostGraph& h = c.h;
     pat.clear();
     if (split) split->clear();
+    std::vector<int64_t> sidx;  // split indices, in pattern order
     for (size_t i = 0; i < vs.size(); ++i) c.loc[vs[i]] = (int32_t)i;
     // the patterns whose first (edges) / smallest (triangles) local index is in [i0, i1)
-    auto range = [&](int64_t i0, int64_t i1, std::vector<int32_t>& P, std::vector<uint32_t>* Sp) {
+    auto range = [&](int64_t i0, int64_t i1, std::vector<int32_t>& P, std::vector<int64_t>* Sp) {
         if (c.mode == 2) {
             for (int64_t i = i0; i < i1; ++i)
                 for (int64_t s = h.rp[vs[i]]; s < h.rp[vs[i] + 1]; ++s) {
@@ -700,7 +703,7 @@ void induced_patterns(Ctx& c, const std::vector<int32_t>& vs, std::vector<int32_
                     if (j > (int32_t)i) {
                         P.push_back((int32_t)i);
                         P.push_back(j);
-                        if (Sp) Sp->push_back(c.split[s]);
+                        if (Sp) Sp->push_back(s);
                     }
                 }
         } else {
@@ -715,9 +718,9 @@ void induced_patterns(Ctx& c, const std::vector<int32_t>& vs, std::vector<int32_
                     P.push_back(d);
                     if (Sp) {
                         const int64_t t = h.tinc[q];
-                        Sp->push_back(c.split[3 * t]);
-                        Sp->push_back(c.split[3 * t + 1]);
-                        Sp->push_back(c.split[3 * t + 2]);
+                        Sp->push_back(3 * t);
+                        Sp->push_back(3 * t + 1);
+                        Sp->push_back(3 * t + 2);
                     }
                 }
         }
@@ -726,11 +729,11 @@ void induced_patterns(Ctx& c, const std::vector<int32_t>& vs, std::vector<int32_
     ThreadGrant grant(k >= flow_parallel_min_nodes() ? flow_threads() : 1);
     const int T = grant.n;
     if (T <= 1) {
-        range(0, k, pat, split);
+        range(0, k, pat, split ? &sidx : nullptr);
     } else {
         // contiguous ranges per thread, concatenated in order: the same list
         std::vector<std::vector<int32_t>> P(T);
-        std::vector<std::vector<uint32_t>> Sp(T);
+        std::vector<std::vector<int64_t>> Sp(T);
         std::vector<std::thread> pool;
         for (int t = 0; t < T; ++t)
             pool.emplace_back([&, t] { range(k * t / T, k * (t + 1) / T, P[t], split ? &Sp[t] : nullptr); });
@@ -741,13 +744,17 @@ void induced_patterns(Ctx& c, const std::vector<int32_t>& vs, std::vector<int32_
             ns += Sp[t].size();
         }
         pat.reserve(np);
-        if (split) split->reserve(ns);
+        if (split) sidx.reserve(ns);
         for (int t = 0; t < T; ++t) {
             pat.insert(pat.end(), P[t].begin(), P[t].end());
-            if (split) split->insert(split->end(), Sp[t].begin(), Sp[t].end());
+            if (split) sidx.insert(sidx.end(), Sp[t].begin(), Sp[t].end());
         }
     }
     for (int32_t v : vs) c.loc[v] = -1;
+    if (split && !sidx.empty()) {
+        split->resize(sidx.size());
+        gather_split(*c.g, c.mode, sidx.data(), (int64_t)sidx.size(), split->data(), c.s);
+    }
 }
 
 // Is G[vs] connected?  A union-find over host threads: a root is linked
@@ -832,7 +839,7 @@ std::vector<std::vector<int32_t>> components(Ctx& c, const std::vector<int32_t>&
 bool is_densest(Ctx& c, const std::vector<int32_t>& vs, Frac* rho, std::vector<int32_t>* denser) {
     std::vector<int32_t> pat;
     std::vector<uint32_t> split;
-    const bool warm = !c.split.empty();
+    const bool warm = c.warm;
     induced_patterns(c, vs, pat, warm ? &split : nullptr);
     const int64_t np = (int64_t)pat.size() / c.mode;
     *rho = reduce(np, (int64_t)vs.size());
@@ -1078,17 +1085,11 @@ void topk_run(Graph& g, int mode, int k, int iters, hipStream_t s, std::vector<T
     std::vector<Frac> his, los;
     collect_groups(g, mode, iters, s, [](int32_t j) { return j; }, sets, his, &los);
     // the FW split (every CSR slot for edges, every triangle's three shares
-    // for triangles), for warm-started min cuts
-    if (mode == 2 && g.m > 0) {
-        const SgState& q = g.sg[0];
-        d2h_fill(c.split, q.a_slot.p, (size_t)(2 * g.m), s);
-        LDS_HIP(hipStreamSynchronize(s));
-        c.splitD = (int64_t)fw_denom(2, iters);
-    } else if (mode == 3 && g.T > 0) {
-        const SgState& q = g.sg[1];
-        d2h_fill(c.split, q.a_tri.p, (size_t)(3 * g.T), s);
-        LDS_HIP(hipStreamSynchronize(s));
-        c.splitD = (int64_t)fw_denom(3, iters);
+    // for triangles) stays on the device; warm-started min cuts gather the
+    // shares of their candidate's patterns
+    if ((mode == 2 && g.m > 0) || (mode == 3 && g.T > 0)) {
+        c.warm = true;
+        c.splitD = (int64_t)fw_denom(mode, iters);
     }
     for (size_t i = 0; i < sets.size(); ++i) {
         if (his[i].n < 0) continue;  // remainder without bounds

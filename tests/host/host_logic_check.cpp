@@ -31,6 +31,9 @@ int64_t edge_mincut_device(int64_t, const std::vector<int32_t>&, const std::vect
     std::abort();  // main() keeps every network on the host
 }
 void sg_stable_groups(Graph&, int, hipStream_t) {}
+void gather_split(const Graph&, int, const int64_t*, int64_t, uint32_t*, hipStream_t) {
+    std::abort();  // the checks here pass splits to the min cuts directly
+}
 void fw_run(Graph&, int, int, bool, hipStream_t) {}
 void core_numbers_gpu(Graph&, int, const uint8_t*, int32_t*, hipStream_t) {}
 Batch::~Batch() {}
