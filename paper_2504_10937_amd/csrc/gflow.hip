@@ -25,15 +25,16 @@
 // whose excess is gone by the next pulse are skipped there.
 // Exact distance labels come from a level-synchronous backward search from t
 // (nodes claimed by compare-and-swap; its first level, t's arcs, spread over
-// the whole grid) at the start and after every N relabels.  The result is a maximum preflow, so the residual graph gives the
-// same minimum cuts as any maximum flow.
+// the whole grid) at the start and after every N relabels.  The result is a
+// maximum preflow, so the residual graph gives the same minimum cuts as any
+// maximum flow.
 //
 // List counters live in two rings of four words indexed by the phase number:
-// a phase pushes into slot ph & 3, which workgroup 0 zeroed during phase
-// ph - 1 (the relabel phase appends to its push phase's slot); a slot's
-// value is read right after the barrier that ends its last writer, and
-// workgroup 0 zeroes it again two phases later, after every workgroup has
-// passed that read.  Every decision is taken from values read after a
+// phase ph counts into slot ph & 3, which workgroup 0 zeroed during phase
+// ph - 1 (the relabel phase appends to its push phase's slot).  A slot is
+// read right after the barrier that ends its last writer and zeroed again
+// in phase ph + 3, behind a barrier that every workgroup reaches only after
+// that read.  Every decision is taken from values read after a
 // barrier, so control flow is uniform.  Waits and loops are bounded; past a
 // bound the kernel raises an error flag and ends.
 #include <algorithm>
