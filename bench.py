@@ -305,7 +305,7 @@ def main():
                     help="second serving run at a load the server sustains (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (one process, one MI355X); "
+        print("bench.py: the benchmark runs on one GPU only (one process, one MI355X); "
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
