@@ -133,7 +133,7 @@ lds_status lds_frank_wolfe(lds_graph g, lds_mode mode, int32_t iters, float* r_o
 lds_status lds_splits(lds_graph g, lds_mode mode, int32_t* verts_out, uint64_t* num_out, int64_t cap,
                       int64_t* count_out, void* hip_stream);
 
-/* Alg. 2, lines 2-4, on the state of the last lds_frank_wolfe run of this
+/* Alg. 2, sort and prefix step, on the state of the last lds_frank_wolfe run of this
  * mode: sort of the vertices by r descending (ties: caller id ascending),
  * prefix pattern counts and the candidate set I.  Host outputs, each
  * optional: order_out[j] = caller id at 0-based position j (n entries);
@@ -143,7 +143,7 @@ lds_status lds_splits(lds_graph g, lds_mode mode, int32_t* verts_out, uint64_t* 
 lds_status lds_sort_prefix(lds_graph g, lds_mode mode, int32_t* order_out, int64_t* E_out, uint8_t* inI_out,
                            void* hip_stream);
 
-/* Alg. 2, lines 5-14: stable groups (Def. 5 for edges, Def. trsg for
+/* Alg. 2, stable-group scan: stable groups (Def. 5 for edges, Def. trsg for
  * triangles) from the candidates of lds_sort_prefix.  A candidate run is
  * merged with the next one until it is a stable group of the restricted
  * solution: every edge (triangle) touching the tested group gives its weight

@@ -166,7 +166,7 @@ def fw_literal(G, mode, iters):
 
 
 def sort_prefix(G, mode, A):
-    """Alg. 2 lines 2-3 -> (order, E, inI) (0-based positions)."""
+    """Alg. 2, sort by r and prefix densities -> (order, E, inI) (0-based positions)."""
     L = _load()
     A = np.ascontiguousarray(A, dtype=np.uint64)
     order = np.empty(G.n, np.int32)

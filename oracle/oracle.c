@@ -20,9 +20,9 @@
  *                         exact rational loads r = A / D_i (A integer); the
  *                         same iteration over 4-cliques (mode 4)
  *   fw_literal .......... Alg. 1 / Alg. 6 in plain FP64 (alpha, r doubles)
- *   sort_prefix ......... Alg. 2 lines 2-4 (sort by r, prefix densities,
+ *   sort_prefix ......... Alg. 2, sort and prefix step (sort by r, prefix densities,
  *                         index set I of suffix argmaxima, ties -> larger j)
- *   extract_sg .......... Alg. 2 lines 5-14 with Def. 5 / Def. trsg
+ *   extract_sg .......... Alg. 2, stable-group scan, with Def. 5 / Def. trsg
  *   decompose ........... exact compact numbers (Def. 4 / Def. trcn) via
  *                         Thm. 1 / Thm. cp: nested maximal maximisers,
  *                         Dinkelbach iteration on Goldberg-style min cuts
@@ -40,7 +40,7 @@
  *     A^(i) = A^(i-1) + 6(i+1) b (triangles), b = units won in iteration i.
  *     For 4-cliques D_i = 2(i+1)(i+2), D_0 = 4 holds the initial quarter
  *     shares as numerator 1, and A^(i) = A^(i-1) + 4(i+1) b.
- *   - sort ties (Alg. 2 line 2): original id ascending.
+ *   - sort ties (the sort of Alg. 2): original id ascending.
  *   - restriction in ExtractSG: every pattern (edge / triangle) touching the
  *     tested group gives weight only to its vertices in the lowest group it
  *     touches; shares freed from higher vertices go to the lowest-r vertex of
@@ -441,7 +441,7 @@ static int cmp_rdesc(const void *x, const void *y) {
     return (a > b) - (a < b);
 }
 
-/* Alg. 2 lines 2-3.  order[j] = vertex at 0-based position j (r descending,
+/* Alg. 2: sort by r and prefix densities.  order[j] = vertex at 0-based position j (r descending,
  * ties: original id ascending).  E[j] = number of patterns whose vertices all
  * lie in the first j+1 positions (edge count of G[V[1:j+1]], or triangle
  * count).  inI[j] = 1 iff position j+1 (1-based) is argmax_{k >= j+1} of

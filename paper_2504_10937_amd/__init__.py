@@ -246,7 +246,7 @@ def lds_denominator(mode, iters):
 
 
 def lds_sort_prefix(g, mode, stream=None):
-    """Alg. 2 lines 2-4 on the last FW state -> (order (caller ids by position), E, inI)."""
+    """The sort and prefix step of Alg. 2 on the last FW state -> (order (caller ids by position), E, inI)."""
     n = lds_graph_info(g)["n"]
     order = np.empty(n, np.int32)
     E = np.empty(n, np.int64)

@@ -1,7 +1,7 @@
 // Device primitives for gfx950: exclusive prefix sums and a stable LSD radix
 // sort (8-bit digits, 4096-key tiles, wave64 ballot matching for the stable
 // in-tile ranks).  Used by graph ingest, the triangle incidence build and the
-// sort of converged loads (Alg. 2, line 2).
+// sort of converged loads (the first step of Alg. 2).
 #include "common.hpp"
 
 namespace lds {

@@ -111,7 +111,7 @@ def test_running_example_fw_converges_to_phi():
 
 
 def test_running_example_prefix_at_phi():
-    """Alg. 2 lines 2-3 at r* (loads proportional to phi, ties by id):
+    """Alg. 2's sort and prefix densities at r* (loads proportional to phi, ties by id):
     hand-derived E_j and I = {6, 11, 12, 15, 16, 18} (1-based)."""
     d, G = running_example()
     L = 12  # common multiple of all phi denominators
