@@ -47,7 +47,9 @@ typedef enum {
     LDS_E_INVALID = 1,  /* bad argument (ids out of range, n < 0, iters < 0, ...) */
     LDS_E_NOMEM = 2,    /* device or host allocation failed */
     LDS_E_DEVICE = 3,   /* HIP runtime error */
-    LDS_E_OVERFLOW = 4, /* an exact numerator would exceed 64 bits (see lds_frank_wolfe) */
+    LDS_E_OVERFLOW = 4, /* an exact numerator would exceed its width: 64-bit loads (see
+                           lds_frank_wolfe) or 32-bit splits (D_iters > 2^32 - 1, see
+                           lds_sort_prefix) */
     LDS_E_BUSY = 5      /* resource in use (server slots, budget) */
 } lds_status;
 
@@ -139,7 +141,11 @@ lds_status lds_splits(lds_graph g, lds_mode mode, int32_t* verts_out, uint64_t* 
  * optional: order_out[j] = caller id at 0-based position j (n entries);
  * E_out[j] = number of edges (triangles) induced by the first j+1 vertices;
  * inI_out[j] = 1 iff j+1 = argmax_{k >= j+1} E_{k-1}/k with ties to the larger
- * index, i.e. E_j/(j+1) exceeds every later E_k/(k+1). */
+ * index, i.e. E_j/(j+1) exceeds every later E_k/(k+1).
+ * The stable-group pass holds split numerators in 32 bits: LDS_E_OVERFLOW
+ * when the last run's D_iters exceeds 2^32 - 1 (edges from iters = 65535,
+ * triangles from iters = 37836); lds_stable_groups, lds_topk and
+ * lds_server_submit check the same limit before any work. */
 lds_status lds_sort_prefix(lds_graph g, lds_mode mode, int32_t* order_out, int64_t* E_out, uint8_t* inI_out,
                            void* hip_stream);
 
@@ -300,7 +306,8 @@ typedef struct {
  * use the sequential host push-relabel.
  * Replaces the graph's FW state of this mode with an iters-iteration
  * run.  *out is overwritten; on error it is left zeroed.  LDS_E_INVALID for
- * k < 1, iters < 0 or a bad mode. */
+ * k < 1, iters < 0 or a bad mode; LDS_E_OVERFLOW when D_iters exceeds
+ * 2^32 - 1 (see lds_sort_prefix), before any work. */
 lds_status lds_topk(lds_graph g, lds_mode mode, int32_t k, int32_t iters, lds_result* out, void* hip_stream);
 
 /* Frees the arrays of a result filled by lds_topk and zeroes it; NULL and

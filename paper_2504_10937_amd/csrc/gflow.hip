@@ -171,6 +171,10 @@ __global__ __launch_bounds__(kFT) void k_maxflow(FlowArgs a) {
             if (x != a.s && a.cap[a.rev[e]] > 0) claim(x, 1, F, slot);
         }
         end_phase();
+        if (s_err) {  // a barrier gave up: the count may be partial
+            bad = true;
+            return;
+        }
         int32_t fc = *slot;
         ++ph;
         for (int32_t lvl = 2; fc > 0; ++lvl) {
@@ -216,6 +220,10 @@ __global__ __launch_bounds__(kFT) void k_maxflow(FlowArgs a) {
                     }
                 });
             end_phase();
+            if (s_err) {
+                bad = true;
+                return;
+            }
             fc = *slot;
             ++ph;
             int32_t* tmp = F;
@@ -231,6 +239,10 @@ __global__ __launch_bounds__(kFT) void k_maxflow(FlowArgs a) {
         for (int64_t v = gt; v < N; v += nthr)
             if (v != a.s && v != a.t && a.h[v] < HN && a.ex[v] > 0) push_list(act, slot, (int32_t)v);
         end_phase();
+        if (s_err) {
+            bad = true;
+            return;
+        }
         na = *slot;
         ++ph;
     };
@@ -331,6 +343,10 @@ __global__ __launch_bounds__(kFT) void k_maxflow(FlowArgs a) {
                 }
             });
         end_phase();
+        if (s_err) {  // the relabel list may be partial: leave before reading it
+            bad = true;
+            break;
+        }
         const int32_t nR = *s2;
         ++ph;
         // relabel in place, then join the next list
@@ -372,6 +388,10 @@ __global__ __launch_bounds__(kFT) void k_maxflow(FlowArgs a) {
                 if (lane == 0) relabel_to(v, mh);
             });
         end_phase();
+        if (s_err) {
+            bad = true;
+            break;
+        }
         na = *s1;
         ++ph;
         relabels += nR;

@@ -38,6 +38,17 @@ inline uint64_t fw_denom(int mode, int64_t i) {
     return c * (uint64_t)(i + 1) * (uint64_t)(i + 2);
 }
 
+// The split numerator of an incidence never exceeds D_N (it is at most D_N
+// minus the other members' initial shares), and the stable-group pass, the
+// split gathers and the warm-started min cuts hold it in 32 bits.  Raises
+// ST_OVERFLOW when D_iters does not fit, before any work is done: edges from
+// N = 65,535 on, triangles from N = 37,836 on.
+inline void check_split_width(int mode, int64_t iters) {
+    if (iters >= 0 && (uint64_t)(iters + 1) * (uint64_t)(iters + 2) * (mode == 3 ? 3u : (mode == 4 ? 2u : 1u)) >
+                          (uint64_t)UINT32_MAX)
+        throw Error(ST_OVERFLOW, "split numerators of this many iterations exceed 32 bits (D_N > 2^32 - 1)");
+}
+
 // index of a mode's Frank-Wolfe / stable-group state: edges 0, triangles 1, 4-cliques 2
 inline int mode_slot(int mode) { return mode - 2; }
 

@@ -7,8 +7,12 @@
 // the launch): a workgroup arriving at the k-th barrier draws a value in
 // [k nwg, (k+1) nwg) and waits until the counter reaches (k+1) nwg, so one
 // atomic per arrival and no separate generation word.  The wait is bounded:
-// past the spin limit the workgroup sets *err and leaves, so a kernel always
-// ends and its host reports the error.
+// past the spin limit thread 0 sets *err (shared by the workgroup) and the
+// barrier returns without the other workgroups.  Values that other
+// workgroups wrote before the barrier (list counts, frontiers) are then not
+// complete, so every caller tests *err after each barrier before it uses
+// them and leaves its loop when it is set; the kernel ends and its host
+// reports the error.
 #pragma once
 #include <hip/hip_runtime.h>
 

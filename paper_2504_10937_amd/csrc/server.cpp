@@ -296,6 +296,7 @@ void Server::submit(lds_graph h, int mode, int k, int iters, uint64_t tag, doubl
     LDS_CHECK(mode == 2 || mode == 3, ST_INVALID, "mode must be LDS_EDGE or LDS_TRIANGLE");
     LDS_CHECK(k >= 1, ST_INVALID, "k must be >= 1");
     LDS_CHECK(iters >= 0, ST_INVALID, "iters must be >= 0");
+    check_split_width(mode, iters);
     SQuery q;
     q.h = h;
     q.mode = mode;

@@ -1128,6 +1128,7 @@ void sg_sort_prefix(Graph& g, int mode, hipStream_t s) {
     SgState& q = g.sg[mode == 2 ? 0 : 1];
     LDS_CHECK(f.ran && f.K[0].n == (size_t)g.n, ST_INVALID,
               "no Frank-Wolfe state: call lds_frank_wolfe first");
+    check_split_width(mode, f.iters);
     const SweepPlan& p = (mode == 2) ? g.edge_plan : g.tri_plan;
     const int64_t n = g.n;
     q.valid = false;

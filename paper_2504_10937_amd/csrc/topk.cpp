@@ -1033,6 +1033,7 @@ void topk_run(Graph& g, int mode, int k, int iters, hipStream_t s, std::vector<T
     LDS_CHECK(mode == 2 || mode == 3, ST_INVALID, "mode must be LDS_EDGE or LDS_TRIANGLE");
     LDS_CHECK(k >= 1, ST_INVALID, "k must be >= 1");
     LDS_CHECK(iters >= 0, ST_INVALID, "iters must be >= 0");
+    check_split_width(mode, iters);
     out.clear();
     st = TopkStats{};
     auto t0 = std::chrono::steady_clock::now();

@@ -145,3 +145,33 @@ def test_edge_state_survives_triangle_listing():
     assert ga == gb
     np.testing.assert_array_equal(lo_a, lo_b)
     np.testing.assert_array_equal(hi_a, hi_b)
+
+
+def test_split_width_limit():
+    """The stable-group pass keeps split numerators in 32 bits: a run whose
+    D_N exceeds 2^32 - 1 is refused with LDS_E_OVERFLOW before any work
+    (edges from N = 65535, triangles from N = 37836), and the largest N
+    that fits still runs."""
+    announce("split width limit")
+    # K4 plus a pendant edge: triangles and edges
+    s = np.array([0, 0, 0, 1, 1, 2, 3], np.int32)
+    d = np.array([1, 2, 3, 2, 3, 3, 4], np.int32)
+    g = lds.lds_create_graph(5, s, d)
+    for mode, n_bad in ((2, 65535), (3, 37836)):
+        with pytest.raises(lds.LdsError) as e:
+            lds.lds_topk(g, mode, 1, n_bad)
+        assert e.value.status == 4
+    lds.lds_frank_wolfe(g, 3, 37836)
+    with pytest.raises(lds.LdsError) as e:
+        lds.lds_sort_prefix(g, 3)
+    assert e.value.status == 4
+    with pytest.raises(lds.LdsError) as e:
+        lds.lds_stable_groups(g, 3)
+    assert e.value.status == 4
+    out = lds.lds_frank_wolfe(g, 3, 37835, want_num=True)
+    assert lds.lds_denominator(3, 37835) <= 2**32 - 1
+    order, E, inI = lds.lds_sort_prefix(g, 3)
+    assert E[-1] == 4  # K4 holds the graph's four triangles
+    groups, lo, hi = lds.lds_stable_groups(g, 3)
+    assert len(groups) >= 1
+    g.destroy()
