@@ -53,6 +53,8 @@ def _load():
         "orc_core_numbers": (ctypes.c_int, [vp, ctypes.c_int, vp]),
         "orc_lds_from_phi": (i64, [vp, vp, vp, vp, vp, vp, vp]),
         "orc_brute": (i64, [vp, ctypes.c_int, vp, vp, vp, vp, vp]),
+        "orc_kcore": (i64, [vp, ctypes.c_int, i64, vp]),
+        "orc_superlevel": (i64, [vp, ctypes.c_int, i64, i64, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -261,3 +263,61 @@ def brute(G, mode):
         vs = np.array([u for u in range(G.n) if (int(masks[i]) >> u) & 1], np.int32)
         sets.append((vs, Fraction(int(ln[i]), int(ld[i]))))
     return phi, sets
+
+
+def kcore(G, mode, k):
+    """The k-core (mode 2) / k-tr-core (mode 3) by repeated deletion -> bool (n,)."""
+    m = np.empty(G.n, np.uint8)
+    if _load().orc_kcore(G._h, mode, int(k), _p(m)) < 0:
+        raise RuntimeError("oracle kcore failed")
+    return m.astype(bool)
+
+
+def superlevel(G, mode, lam):
+    """{u : phi(u) >= lam} for a Fraction lam >= 0, by one min cut (the
+    maximal maximiser of q|P(U)| - p|U|) -> bool (n,)."""
+    lam = Fraction(lam)
+    u = np.empty(G.n, np.uint8)
+    if _load().orc_superlevel(G._h, mode, lam.numerator, lam.denominator, _p(u)) < 0:
+        raise RuntimeError("oracle superlevel failed")
+    return u.astype(bool)
+
+
+def induced(G, keep):
+    """Induced subgraph G[keep] -> (Graph on 0..k-1, ids (k,) of its vertices in G)."""
+    keep = np.asarray(keep, bool)
+    ids = np.flatnonzero(keep).astype(np.int64)
+    new = np.full(G.n, -1, np.int64)
+    new[ids] = np.arange(len(ids))
+    u, v = G.edges()
+    sel = keep[u] & keep[v]
+    return Graph(len(ids), new[u[sel]].astype(np.int32), new[v[sel]].astype(np.int32)), ids
+
+
+def top_levels(G, mode, lam):
+    """Every LDS (mode 2) / LTDS (mode 3) of G with density >= lam > 0, by
+    (density desc, min vertex asc), without the decomposition of all of G.
+
+    U = {u : phi(u) >= lam} lies in the ceil(lam)-core K (phi <= core), and
+    it is the maximal maximiser of q|P(U)| - p|U| over subsets of K as well
+    as over all of V, so one min cut on G[K] finds it.  The nested maximal
+    maximisers that define phi (Thm. 1 / Thm. cp) down to density lam lie in
+    U, so the decomposition of G[U] gives phi_G on U.  An LDS of density
+    rho >= lam is a component of {phi = rho} inside U with no neighbour of
+    larger phi, and a neighbour outside U has phi < lam <= rho; so the rule
+    of lds_from_phi applied to G[U] finds exactly the LDSs of G with density
+    >= lam.  Returns (sets, |K|, |U|)."""
+    lam = Fraction(lam)
+    if lam <= 0:
+        raise ValueError("lam must be > 0")
+    k = -((-lam.numerator) // lam.denominator)  # ceil
+    K = kcore(G, mode, k)
+    GK, idK = induced(G, K)
+    UK = superlevel(GK, mode, lam)
+    GU, idU = induced(GK, UK)
+    pn, pd = decompose(GU, mode)
+    sets = []
+    for vs, rho in lds_from_phi(GU, pn, pd):
+        sets.append((np.sort(idK[idU[vs]]).astype(np.int32), rho))
+    sets.sort(key=lambda t: (-t[1], int(t[0][0])))
+    return sets, int(K.sum()), int(UK.sum())

@@ -29,6 +29,10 @@
  *   lds_from_phi ........ LDS / LTDS sets from compact numbers (Lemmas
  *                         lds-in-phi, lds-out-phi; Thm. cnltds)
  *   brute ............... Defs. 1-4 and 7-10 by enumeration (n <= 16)
+ *   kcore ............... one k-core (k-tr-core) by repeated deletion, the
+ *                         bound phi(u) <= core(u) of Section 4.3 in set form
+ *   superlevel .......... {u : phi(u) >= p/q} as the maximal maximiser of
+ *                         q |P(U)| - p |U| (one min cut; Thm. 1 / Thm. cp)
  *
  * Readings of silent/ambiguous passages (kept identical on both sides):
  *   - FW ties (Alg. 1, Alg. 6): exact ties in r go to the endpoint with the
@@ -785,6 +789,89 @@ int64_t orc_decompose(const orc_graph *g, int mode, int64_t *phi_num, int64_t *p
     }
     free(inB); free(inU); free(P.v);
     return levels;
+}
+
+/* ================================================ large-graph helpers == */
+/* The k-core (mode 2) or k-tr-core (mode 3): the largest vertex set in which
+ * every vertex lies in at least k patterns (edges / triangles) whose
+ * vertices are all in the set, as used by Pruning (Alg. 3) and the bounds of
+ * Section 4.3.  Obtained from V by deleting, one at a time until none is
+ * left, a vertex that lies in fewer than k patterns of the remaining set;
+ * a deletion removes every pattern through the vertex.  The result does not
+ * depend on the deletion order (the k-core is the union of all vertex sets
+ * with that property).  A vertex u with phi(u) >= rho > 0 lies in a
+ * rho-compact set, where it has at least rho patterns (removing u alone
+ * loses at least rho), so it lies in the ceil(rho)-core: the k-core holds
+ * {u : phi(u) >= lambda} for k = ceil(lambda).  in_core[u] = 1 inside.
+ * Returns the core size, or -1. */
+int64_t orc_kcore(const orc_graph *g, int mode, int64_t k, uint8_t *in_core) {
+    patterns P;
+    if ((mode != 2 && mode != 3) || get_patterns(g, mode, &P)) return -1;
+    const int64_t n = g->n, h = P.h, np = P.np;
+    /* patterns through each vertex (CSR) */
+    int64_t *cnt = (int64_t *)calloc((size_t)(n + 1), sizeof(int64_t));
+    int64_t *po = (int64_t *)calloc((size_t)(n + 1), sizeof(int64_t));
+    int64_t *pl = (int64_t *)malloc((size_t)(h * np > 0 ? h * np : 1) * sizeof(int64_t));
+    uint8_t *palive = (uint8_t *)malloc((size_t)(np > 0 ? np : 1));
+    int64_t *queue = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    uint8_t *queued = (uint8_t *)calloc((size_t)(n > 0 ? n : 1), 1);
+    if (!cnt || !po || !pl || !palive || !queue || !queued) {
+        free(cnt); free(po); free(pl); free(palive); free(queue); free(queued); free(P.v);
+        return -1;
+    }
+    for (int64_t p = 0; p < h * np; p++) po[P.v[p] + 1]++;
+    for (int64_t u = 0; u < n; u++) po[u + 1] += po[u];
+    for (int64_t p = 0; p < np; p++) {
+        palive[p] = 1;
+        for (int64_t j = 0; j < h; j++) {
+            const int32_t x = P.v[h * p + j];
+            pl[po[x] + cnt[x]] = p;
+            cnt[x]++;
+        }
+    }
+    int64_t qh = 0, qt = 0;
+    for (int64_t u = 0; u < n; u++) {
+        in_core[u] = 1;
+        if (cnt[u] < k) { queue[qt++] = u; queued[u] = 1; }
+    }
+    int64_t left = n;
+    while (qh < qt) {
+        const int64_t u = queue[qh++];
+        in_core[u] = 0;
+        left--;
+        for (int64_t e = po[u]; e < po[u + 1]; e++) {
+            const int64_t p = pl[e];
+            if (!palive[p]) continue;
+            palive[p] = 0;
+            for (int64_t j = 0; j < h; j++) {
+                const int32_t w = P.v[h * p + j];
+                if (w == u) continue;
+                cnt[w]--;
+                if (!queued[w] && cnt[w] < k) { queue[qt++] = w; queued[w] = 1; }
+            }
+        }
+    }
+    free(cnt); free(po); free(pl); free(palive); free(queue); free(queued); free(P.v);
+    return left;
+}
+
+/* {u : phi(u) >= p/q} (p >= 0, q >= 1): the maximal maximiser of
+ * q |P(U)| - p |U| over all vertex sets U.  By Thm. 1 / Thm. cp the compact
+ * numbers are the levels of the nested maximal maximisers found by
+ * orc_decompose; at lambda = p/q every level with density >= lambda adds a
+ * non-negative amount and every lower level a negative one, so the maximal
+ * maximiser is the union of the levels with density >= lambda.  One min cut
+ * (best_superset with B empty).  Returns |U|, or -1. */
+int64_t orc_superlevel(const orc_graph *g, int mode, int64_t p, int64_t q, uint8_t *inU) {
+    patterns P;
+    if ((mode != 2 && mode != 3) || p < 0 || q < 1 || get_patterns(g, mode, &P)) return -1;
+    const int64_t n = g->n;
+    uint8_t *inB = (uint8_t *)calloc((size_t)(n > 0 ? n : 1), 1);
+    if (!inB) { free(P.v); return -1; }
+    int64_t dp = 0, ds = 0;
+    const int rc = best_superset(g, &P, inB, p, q, inU, &dp, &ds);
+    free(inB); free(P.v);
+    return rc ? -1 : ds;
 }
 
 /* LDS (mode 2) / LTDS (mode 3) from exact compact numbers: the connected

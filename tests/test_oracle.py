@@ -389,6 +389,63 @@ def test_core_numbers_by_enumeration():
             assert list(oracle.core_numbers(G, mode)) == _core_by_enumeration(n, edges, mode)
 
 
+# ------------------------------------------ large-graph path (k-core, superlevel)
+def _helper_graphs():
+    return small_graphs() + [synth.powerlaw_planted(300, 2.3, 6.0, 3, 8, 20, 0.6, seed=9),
+                             synth.holme_kim(300, 4, 0.6, seed=9)]
+
+
+def test_kcore_matches_core_numbers():
+    """One k-core by deletion equals {core >= k} of the core numbers above
+    (pinned by enumeration), for every k from 0 to one past the largest."""
+    for n, s, d in _helper_graphs():
+        G = oracle.Graph(n, s, d)
+        for mode in (2, 3):
+            core = oracle.core_numbers(G, mode)
+            for k in range(int(core.max()) + 2):
+                np.testing.assert_array_equal(oracle.kcore(G, mode, k), core >= k)
+
+
+def test_superlevel_matches_decomposition():
+    """{phi >= lam} by one min cut equals the union of the decomposition's
+    levels of density >= lam (pinned against brute force above): at every
+    level value (the tie case: the level itself belongs), between levels,
+    at 0 and above the top."""
+    for n, s, d in _helper_graphs():
+        G = oracle.Graph(n, s, d)
+        for mode in (2, 3):
+            pn, pd = oracle.decompose(G, mode)
+            phi = [Fraction(int(a), int(b)) for a, b in zip(pn, pd)]
+            lv = sorted(set(phi))
+            lams = set(lv) | {(a + b) / 2 for a, b in zip(lv, lv[1:])} | {lv[-1] + Fraction(1, 3), Fraction(0)}
+            for lam in sorted(lams):
+                want = np.array([f >= lam for f in phi])
+                np.testing.assert_array_equal(oracle.superlevel(G, mode, lam), want)
+
+
+@pytest.mark.parametrize("mode", [2, 3])
+def test_top_levels_matches_full_top_k(mode):
+    """The large-graph path (k-core, one superlevel min cut, decomposition of
+    the superlevel set only) returns exactly the sets of the full
+    decomposition's LDS / LTDS list with density >= lam, in the same order."""
+    graphs = [synth.workload("lds_small")[:3], synth.powerlaw_planted(1500, 2.1, 10.0, 6, 15, 60, 0.4, seed=21),
+              synth.holme_kim(1200, 6, 0.6, seed=22)]
+    for n, s, d in graphs:
+        G = oracle.Graph(n, s, d)
+        full = oracle.lds_from_phi(G, *oracle.decompose(G, mode))
+        dens = sorted({r for _, r in full}, reverse=True)
+        lams = {dens[0], dens[-1], dens[min(2, len(dens) - 1)], dens[0] / 2}
+        if len(dens) > 1:
+            lams.add((dens[0] + dens[1]) / 2)
+        for lam in sorted(lams):
+            got, K, U = oracle.top_levels(G, mode, lam)
+            want = [(v, r) for v, r in full if r >= lam]
+            assert len(got) == len(want) and U <= K <= n
+            for (gv, gr), (wv, wr) in zip(got, want):
+                assert gr == wr
+                np.testing.assert_array_equal(gv, wv)
+
+
 # ------------------------------------------------------- 4-clique program (h = 4)
 def clique_graphs():
     """small graphs with 4-cliques: dense G(n,p), planted blocks, triadic closure"""
