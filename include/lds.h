@@ -126,6 +126,26 @@ lds_status lds_cliques4(lds_graph g, int64_t* n_cliques, int32_t* q_out, int64_t
 lds_status lds_frank_wolfe(lds_graph g, lds_mode mode, int32_t iters, float* r_out, double* r64_out,
                            uint64_t* num_out, double* gap_out, void* hip_stream);
 
+/* lds_frank_wolfe without any device allocation, for callers that cannot
+ * allocate (tight serving loops, code that must not call hipMalloc): the same
+ * kernels and the same exact result (loads bit for bit; gap within FP64
+ * rounding, as it is formed on the device from the same exact sums).
+ * The graph's FW state for this mode must already be sized for `iters`
+ * iterations by an earlier lds_frank_wolfe (or lds_batch_create) with at
+ * least `iters` iterations, and triangles (4-cliques) must be listed;
+ * otherwise LDS_E_INVALID and nothing runs.  Outputs (optional): r_out
+ * device float[n] by caller id, gap_out host double[iters].  With gap_out
+ * the per-workgroup partial sums live in a fixed 4 MiB device array per GPU
+ * (held until the process ends): iters is limited to
+ * 4 MiB / (8 * (4 * compute units + 5)) = 509 on a 256-CU MI355X
+ * (LDS_E_INVALID beyond).  Every call on one GPU shares that array: calls
+ * with gap_out that overlap in time on the same GPU race and must be
+ * serialised by the caller.  Leaves the state as lds_frank_wolfe does,
+ * except that lds_loads reports no gap afterwards; with gap_out the call
+ * waits for the stream. */
+lds_status lds_frank_wolfe_noalloc(lds_graph g, lds_mode mode, int32_t iters, float* r_out, double* gap_out,
+                                   void* hip_stream);
+
 /* Exact split numerators alpha_{x,p} * D of the last lds_frank_wolfe run
  * (Eq. cp / Eq. trcp variables).  One entry per incidence (vertex x,
  * pattern p): edges 2m entries, triangles 3|T|, 4-cliques 4|K4|.  verts_out (host

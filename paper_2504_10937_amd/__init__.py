@@ -69,6 +69,7 @@ def load():
         "lds_triangles": (st, [vp, vp, vp, i64, vp, vp]),
         "lds_cliques4": (st, [vp, vp, vp, i64, vp, vp]),
         "lds_frank_wolfe": (st, [vp, st, i32, vp, vp, vp, vp, vp]),
+        "lds_frank_wolfe_noalloc": (st, [vp, st, i32, vp, vp, vp]),
         "lds_splits": (st, [vp, st, vp, vp, i64, vp, vp]),
         "lds_denominator": (u64, [st, i32]),
         "lds_fw_elapsed": (st, [vp, st, vp, vp]),
@@ -226,6 +227,19 @@ def lds_frank_wolfe(g, mode, iters, r_out=None, want_r64=False, want_num=False, 
     _check(L.lds_frank_wolfe(g.handle, mode, int(iters), _ptr(r_out), _ptr(r64), _ptr(num), _ptr(gap),
                              _stream(stream)))
     return {"r64": r64, "num": num, "gap": gap, "D": lds_denominator(mode, iters)}
+
+
+def lds_frank_wolfe_noalloc(g, mode, iters, r_out=None, want_gap=False, stream=None):
+    """lds_frank_wolfe without device allocation (the graph's FW state must
+    already be sized for `iters`).  r_out: optional device float32 tensor
+    (n,).  Returns the gap (iters,) or None."""
+    L = load()
+    n = lds_graph_info(g)["n"]
+    if r_out is not None and (r_out.numel() < n or not r_out.is_cuda):
+        raise ValueError("r_out must be a device tensor with n elements")
+    gap = np.empty(iters, np.float64) if want_gap else None
+    _check(L.lds_frank_wolfe_noalloc(g.handle, mode, int(iters), _ptr(r_out), _ptr(gap), _stream(stream)))
+    return gap
 
 
 def lds_splits(g, mode, stream=None):

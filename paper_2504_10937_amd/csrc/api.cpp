@@ -230,6 +230,18 @@ lds_status lds_frank_wolfe(lds_graph g, lds_mode mode, int32_t iters, float* r_o
     API_CATCH
 }
 
+lds_status lds_frank_wolfe_noalloc(lds_graph g, lds_mode mode, int32_t iters, float* r_out, double* gap_out,
+                                   void* hip_stream) {
+    API_TRY
+    LDS_CHECK(g != nullptr, lds::ST_INVALID, "graph is NULL");
+    LDS_CHECK(mode == LDS_EDGE || mode == LDS_TRIANGLE || mode == LDS_CLIQUE4, lds::ST_INVALID,
+              "mode must be LDS_EDGE, LDS_TRIANGLE or LDS_CLIQUE4");
+    LDS_CHECK(iters >= 0, lds::ST_INVALID, "iters must be >= 0");
+    std::lock_guard<std::mutex> lk(g->mu);
+    lds::fw_run_noalloc(g->g, (int)mode, iters, r_out, gap_out, (hipStream_t)hip_stream);
+    API_CATCH
+}
+
 lds_status lds_splits(lds_graph g, lds_mode mode, int32_t* verts_out, uint64_t* num_out, int64_t cap,
                       int64_t* count_out, void* hip_stream) {
     API_TRY

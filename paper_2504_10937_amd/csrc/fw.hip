@@ -28,6 +28,16 @@
 // integers per workgroup and reduced once after the last iteration.
 #include "graph.hpp"
 
+#include <mutex>
+
+// Scratch of lds_frank_wolfe_noalloc, for callers that cannot allocate device
+// memory: the per-workgroup gap partial sums of every iteration, their
+// per-iteration totals and the gap values.  One copy per device (4 MiB),
+// held until the process ends; host code reaches it only through the
+// address hipGetSymbolAddress returns for the current device.
+static constexpr size_t kScratchWords = (size_t)1 << 19;
+static __device__ __align__(256) uint64_t scratch[kScratchWords];
+
 namespace lds {
 
 namespace {
@@ -600,6 +610,143 @@ void fw_run(Graph& g, int mode, int iters, bool want_gap, hipStream_t s) {
             LDS_HIP(hipStreamSynchronize(s));
         }
         fw_gap_from_sums(f, mode, iters, sums.data());
+    }
+}
+
+namespace {
+
+// gap of iteration j + 1 at r^(j) from the exact sums (sum A^2, sum of the
+// patterns' minimum A), over D_j = c (j+1)(j+2):
+// gap = 2 (sum A^2 - D_j sum min A) / D_j^2, rounded to FP64 on the device
+__global__ void k_gap_values(const uint64_t* sums, int iters, uint64_t c, double* gap) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= iters) return;
+    const u128 S = ((u128)sums[4 * j + 1] << 64) | sums[4 * j];
+    const u128 M = ((u128)sums[4 * j + 3] << 64) | sums[4 * j + 2];
+    const uint64_t D = c * (uint64_t)(j + 1) * (uint64_t)(j + 2);
+    const u128 num = S - (u128)D * M;
+    const double nd = (double)(uint64_t)(num >> 64) * 18446744073709551616.0 + (double)(uint64_t)num;
+    const double Dd = (double)D;
+    gap[j] = 2.0 * nd / (Dd * Dd);
+}
+
+// this device's copy of the scratch array, looked up once per device with
+// that device current
+uint64_t* scratch_on_current_device() {
+    constexpr int kMaxDev = 64;
+    static std::mutex mu;
+    static uint64_t* ptr[kMaxDev] = {};
+    int dev = 0;
+    LDS_HIP(hipGetDevice(&dev));
+    LDS_CHECK(dev >= 0 && dev < kMaxDev, ST_DEVICE, "device index out of range for the scratch table");
+    std::lock_guard<std::mutex> lk(mu);
+    if (!ptr[dev]) {
+        void* p = nullptr;
+        LDS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        LDS_CHECK(p != nullptr, ST_DEVICE, "hipGetSymbolAddress returned no address for the scratch array");
+        ptr[dev] = (uint64_t*)p;
+    }
+    return ptr[dev];
+}
+
+}  // namespace
+
+size_t fw_noalloc_max_iters(int with_gap) {
+    if (!with_gap) return (size_t)INT32_MAX;
+    return kScratchWords / ((size_t)sweep_grid() * 4 + 5);
+}
+
+void fw_run_noalloc(Graph& g, int mode, int iters, float* r32_dev, double* gap_host, hipStream_t s) {
+    LDS_CHECK(mode >= 2 && mode <= 4, ST_INVALID, "mode must be LDS_EDGE, LDS_TRIANGLE or LDS_CLIQUE4");
+    LDS_CHECK(iters >= 0, ST_INVALID, "iters must be >= 0");
+    LDS_CHECK(mode != 3 || g.T >= 0, ST_INVALID, "triangles are not listed: run lds_frank_wolfe (or lds_triangles) first");
+    LDS_CHECK(mode != 4 || g.Q4 >= 0, ST_INVALID, "4-cliques are not listed: run lds_frank_wolfe (or lds_cliques4) first");
+    const SweepPlan& p = plan_of(g, mode);
+    FwState& f = g.fw[mode_slot(mode)];
+    const int B = g.idbits;
+    const u128 amax = fw_max_numerator(g, mode, iters);
+    LDS_CHECK(B < 64 && (amax >> (64 - B)) == 0, ST_OVERFLOW, "exact load numerator would overflow the 64-bit key");
+    const int64_t n = g.n;
+    LDS_CHECK(f.K[0].n == (size_t)n && f.K[1].n == (size_t)n && f.Q[0].n == (size_t)n && f.Q[1].n == (size_t)n &&
+                  f.bits.n >= (size_t)iters * (size_t)p.total_words,
+              ST_INVALID,
+              "Frank-Wolfe state is not sized for this many iterations: run lds_frank_wolfe with at least iters "
+              "iterations on this graph and mode first");
+    const unsigned blocks = sweep_grid();
+    const bool gap = gap_host != nullptr && iters > 0;
+    const size_t words = gap ? (size_t)iters * ((size_t)blocks * 4 + 5) : 0;
+    LDS_CHECK(words <= kScratchWords, ST_INVALID,
+              "iters exceeds the no-allocation limit with the gap (" + std::to_string(fw_noalloc_max_iters(1)) +
+                  " iterations)");
+    uint64_t* sc = scratch_on_current_device();
+    uint64_t* partial = sc;
+    uint64_t* sums = sc + (size_t)iters * blocks * 4;
+    double* gapv = reinterpret_cast<double*>(sums + (size_t)iters * 4);
+    if (n > 0) {
+        const int32_t* cnt = (mode == 2) ? g.deg.p : (mode == 3 ? g.tcount.p : g.qcount.p);
+        k_init_keys<<<grid_for(n, 256), 256, 0, s>>>(cnt, mode == 3 ? 2 : 1, g.orig_of.p, n, B, f.K[0].p, f.K[1].p,
+                                                    f.Q[0].p, f.Q[1].p);
+        LDS_HIP(hipGetLastError());
+    }
+    f.cur = 0;
+    g.sg[mode_slot(mode)].valid = false;
+    SweepArgs a{};
+    a.rid = p.rid;
+    a.rp = p.rp;
+    a.py = p.py;
+    a.n_hub = p.n_hub;
+    a.hwo = p.hwo.p;
+    a.n_pieces = p.n_pieces;
+    a.hp_row = p.hp_row.p;
+    a.hp_off = p.hp_off.p;
+    a.hub_ctr = p.hub_ctr.p;
+    a.n_chunks = p.n_chunks;
+    a.chunk_row = p.chunk_row.p;
+    a.cwo = p.cwo.p;
+    a.head = p.head.p;
+    a.chunk_words = p.chunk_words;
+    a.B = B;
+    a.ncache = (int)std::min<int64_t>(n, kCacheQ);
+    const bool any = blocks > 0 && p.nrows > 0;
+    for (int i = 1; i <= iters && any; ++i) {
+        a.Kin = f.K[f.cur].p;
+        a.Kout = f.K[f.cur ^ 1].p;
+        a.Qin = f.Q[f.cur].p;
+        a.Qout = f.Q[f.cur ^ 1].p;
+        a.bits = f.bits.p + (size_t)(i - 1) * p.total_words;
+        a.inc = denom(mode, i) - denom(mode, i - 1);
+        a.partial = gap ? partial + (size_t)(i - 1) * blocks * 4 : nullptr;
+        if (mode == 2)
+            launch_sweep<2, true>(a, blocks, gap, s);
+        else if (mode == 3)
+            launch_sweep<3, false>(a, blocks, gap, s);
+        else
+            launch_sweep<4, false>(a, blocks, gap, s);
+        LDS_HIP(hipGetLastError());
+        f.cur ^= 1;
+    }
+    f.iters = iters;
+    f.ran = true;
+    f.timed = false;
+    f.launches = any ? iters : 0;
+    f.gap.clear();
+    f.lb.clear();
+    if (n > 0 && r32_dev) {
+        k_loads<<<grid_for(n, 256), 256, 0, s>>>(f.K[f.cur].p, g.orig_of.p, n, B, (double)denom(mode, iters), r32_dev,
+                                                 nullptr);
+        LDS_HIP(hipGetLastError());
+    }
+    if (gap) {
+        if (any) {
+            k_gap_reduce<<<iters, 256, 0, s>>>(partial, blocks, sums);
+            LDS_HIP(hipGetLastError());
+            k_gap_values<<<grid_for(iters, 256), 256, 0, s>>>(sums, iters, denom(mode, 0) / 2, gapv);
+            LDS_HIP(hipGetLastError());
+            LDS_HIP(hipMemcpyAsync(gap_host, gapv, (size_t)iters * sizeof(double), hipMemcpyDeviceToHost, s));
+            LDS_HIP(hipStreamSynchronize(s));
+        } else {
+            for (int i = 0; i < iters; ++i) gap_host[i] = 0.0;
+        }
     }
 }
 

@@ -199,6 +199,10 @@ void fw_prepare(Graph& g, int mode, int iters, hipStream_t s);
 // (4 words per iteration: low/high of each)
 void fw_gap_from_sums(FwState& f, int mode, int iters, const uint64_t* sums);
 void fw_run(Graph& g, int mode, int iters, bool want_gap, hipStream_t s);
+// fw_run without any device allocation (lds_frank_wolfe_noalloc): the FW
+// state must already be sized for iters; gap scratch from the device array
+void fw_run_noalloc(Graph& g, int mode, int iters, float* r32_dev, double* gap_host, hipStream_t s);
+size_t fw_noalloc_max_iters(int with_gap);
 void fw_loads(const Graph& g, int mode, float* r32_dev, double* r64_host, uint64_t* A_host, hipStream_t s);
 void fw_splits(const Graph& g, int mode, int32_t* verts_host, uint64_t* num_host, hipStream_t s);
 
