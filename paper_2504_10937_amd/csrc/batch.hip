@@ -297,7 +297,9 @@ void batch_build(Batch& b, hipStream_t s) {
     b.kernel_items.clear();
     b.plain_items.clear();
     for (int i = 0; i < count; ++i) {
-        if (batch_cost(*b.gs[i], b.modes[i], b.iters[i]) <= t.max_kernel_cost)
+        // graphs with a 2D part (large edge plans) take their own launches
+        if (batch_cost(*b.gs[i], b.modes[i], b.iters[i]) <= t.max_kernel_cost &&
+            plan_of(*b.gs[i], b.modes[i]).heavy.n_parts == 0)
             b.kernel_items.push_back(i);
         else
             b.plain_items.push_back(i);

@@ -68,6 +68,22 @@ struct SweepArgs {
     int B;
     uint64_t* partial;   // 4 words per workgroup (or nullptr)
     int ncache;          // codes staged in LDS: min(n, kCacheQ)
+    // 2D part (edge plans of large graphs; n_parts = 0 otherwise)
+    int64_t n_parts;
+    const int32_t* part_blk;
+    const int32_t* part_j0;
+    const int32_t* part_j1;
+    const int64_t* part_lo;
+    const int64_t* part_hi;
+    const int64_t* hseg;
+    const int64_t* hblk_row;
+    const uint32_t* hpay;
+    uint32_t* part_cnt;
+    int64_t hP;
+    int hR, hC;
+    int64_t n_heavy;
+    int64_t hword0;
+    int64_t nv;          // vertices (slabs are clipped to it)
 };
 
 __device__ inline uint64_t readlane64(uint64_t v, int lane) {
@@ -173,6 +189,140 @@ __device__ inline uint16_t qload(const uint16_t* __restrict__ qc, int nc, const 
     return q;
 }
 
+// LDS bytes of the 2D part: block codes (u16) and win counts (u32), two slabs
+constexpr size_t kHeavyLds = (size_t)kHeavyRows * 2 + (size_t)kHeavyRows * 4 + (size_t)2 * kHeavySlab * 2;
+constexpr int kSlabChunks = (kHeavySlab / 8 + kPT - 1) / kPT;  // 16-byte chunks of a slab per thread
+
+// slab j's codes, 16 bytes (8 codes) per chunk, clipped to the vertex count
+__device__ inline void slab_load(const uint16_t* __restrict__ Q, int64_t nv, int64_t first, int C, uint4 (&st)[kSlabChunks]) {
+#pragma unroll
+    for (int q = 0; q < kSlabChunks; ++q) {
+        const int c = (int)threadIdx.x + kPT * q;
+        const int64_t v = first + 8 * (int64_t)c;
+        uint4 x = make_uint4(0, 0, 0, 0);
+        if (8 * c < C) {
+            if (v + 8 <= nv) {
+                x = *reinterpret_cast<const uint4*>(Q + v);
+            } else {
+                uint16_t e[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) e[k] = (v + k < nv) ? Q[v + k] : (uint16_t)0;
+                x.x = e[0] | ((uint32_t)e[1] << 16);
+                x.y = e[2] | ((uint32_t)e[3] << 16);
+                x.z = e[4] | ((uint32_t)e[5] << 16);
+                x.w = e[6] | ((uint32_t)e[7] << 16);
+            }
+        }
+        st[q] = x;
+    }
+}
+
+__device__ inline void slab_store(uint16_t* __restrict__ slab, int C, const uint4 (&st)[kSlabChunks]) {
+#pragma unroll
+    for (int q = 0; q < kSlabChunks; ++q) {
+        const int c = (int)threadIdx.x + kPT * q;
+        if (8 * c < C) reinterpret_cast<uint4*>(slab)[c] = st[q];
+    }
+}
+
+// The 2D part of an edge sweep (heavy rows; see HeavyPlan).  A workgroup
+// takes whole parts.  It stages the block's codes and zeroed win counts in
+// LDS, then walks the part's slabs: slab j's codes sit in one LDS buffer
+// while the next slab's are loaded into registers and stored into the other
+// buffer; the segment's words are decided with both codes from LDS (64-bit
+// keys only on equal codes), each word's ballot is its decision word, and
+// the wins of each run of one row within a word are added to the row's LDS
+// count once.  The part's counts go to part_cnt; k_heavy_finish sums the
+// parts of each row after the sweep.
+template <bool ENABLE>
+__device__ inline void heavy_parts(const SweepArgs& a, uint8_t* dyn, int64_t* sgc) {
+    if constexpr (ENABLE) {
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        const int R = a.hR, C = a.hC;
+        uint16_t* rq = reinterpret_cast<uint16_t*>(dyn);
+        uint32_t* rc = reinterpret_cast<uint32_t*>(dyn + (size_t)kHeavyRows * 2);
+        uint16_t* slabs = reinterpret_cast<uint16_t*>(dyn + (size_t)kHeavyRows * 6);
+        const uint64_t le = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+        for (int64_t pt = blockIdx.x; pt < a.n_parts; pt += gridDim.x) {
+            const int64_t b = a.part_blk[pt];
+            const int64_t j0 = a.part_j0[pt], j1 = a.part_j1[pt];
+            const int64_t lo = a.part_lo[pt], hi = a.part_hi[pt];
+            const int64_t row0 = a.hblk_row[b];
+            const int nr = (int)(a.hblk_row[b + 1] - row0);
+            // the part's segment bounds, clipped to its positions, staged in
+            // LDS when they fit (a few hundred slabs)
+            const int64_t* sgg = a.hseg + b * a.hP;
+            const bool cached = j1 - j0 + 1 <= kWaves * 32;
+            for (int64_t k = threadIdx.x; cached && k <= j1 - j0; k += kPT) sgc[k] = min(max(sgg[j0 + k], lo), hi);
+            for (int i = threadIdx.x; i < nr; i += kPT) {
+                rq[i] = a.Qin[row0 + i];
+                rc[i] = 0u;
+            }
+            __syncthreads();
+            auto bound = [&](int64_t j) { return cached ? sgc[j - j0] : min(max(sgg[j], lo), hi); };
+            auto next_j = [&](int64_t j) {
+                while (j < j1 && bound(j + 1) <= bound(j)) ++j;
+                return j;
+            };
+            int64_t j = next_j(j0);
+            uint4 st[kSlabChunks];
+            if (j < j1) {
+                slab_load(a.Qin, a.nv, j * C, C, st);
+                slab_store(slabs, C, st);
+            }
+            __syncthreads();
+            int cur = 0;
+            while (j < j1) {
+                const int64_t jn = next_j(j + 1);
+                if (jn < j1) slab_load(a.Qin, a.nv, jn * C, C, st);
+                const uint16_t* sl = slabs + (size_t)cur * kHeavySlab;
+                const int64_t q0 = bound(j), q1 = bound(j + 1);
+                const uint64_t* __restrict__ Kin = a.Kin;
+                constexpr int U = 8;
+                for (int64_t base = q0 + (int64_t)64 * U * w; base < q1; base += (int64_t)64 * U * kWaves) {
+                    uint32_t x[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const int64_t pos = base + 64 * u + lane;
+                        x[u] = pos < q1 ? __builtin_nontemporal_load(a.hpay + pos) : 0xffffffffu;
+                    }
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const bool valid = x[u] != 0xffffffffu;
+                        const uint32_t rl = (x[u] >> 16) & 0x7fffu, nl = x[u] & 0xffffu;
+                        bool win = false;
+                        if (valid) {
+                            const uint16_t qu = rq[rl], qv = sl[nl];
+                            win = (qu != qv) ? (qu < qv) : (Kin[row0 + rl] < Kin[j * C + nl]);
+                        }
+                        const uint64_t W = __ballot(win);
+                        const int64_t wpos = base + 64 * u;
+                        if (lane == 0 && wpos < q1) __builtin_nontemporal_store(W, a.bits + a.hword0 + wpos / 64);
+                        // runs of one row within the word (run heads are marked
+                        // in the payload): one LDS add per run
+                        const uint64_t V = __ballot(valid);
+                        const uint64_t Hm = __ballot(valid && (x[u] >> 31));
+                        const uint64_t nv1 = (V >> lane) >> 1, nh1 = (Hm >> lane) >> 1;  // next lane's bits (0 past 63)
+                        const bool last = valid && (!(nv1 & 1ull) || (nh1 & 1ull));
+                        if (last) {
+                            const uint64_t hm = Hm & le;
+                            const uint64_t from = hm ? (~0ull << (63 - __clzll(hm))) : ~0ull;
+                            const uint32_t c = (uint32_t)__popcll(W & le & from);
+                            if (c) atomicAdd(&rc[rl], c);
+                        }
+                    }
+                }
+                if (jn < j1) slab_store(slabs + (size_t)(cur ^ 1) * kHeavySlab, C, st);
+                __syncthreads();
+                cur ^= 1;
+                j = jn;
+            }
+            for (int i = threadIdx.x; i < nr; i += kPT) a.part_cnt[pt * R + i] = rc[i];
+            __syncthreads();
+        }
+    }
+}
+
 // Persistent sweep: one workgroup per CU.  The workgroup first copies the
 // codes of the kCacheQ highest-degree vertices (internal ids [0, kCacheQ))
 // into LDS; those vertices take most of the gathers of a power-law graph.
@@ -185,6 +335,8 @@ __global__ __launch_bounds__(kPT) void k_fw_sweep(SweepArgs a) {
     __shared__ uint64_t words[kWaves][32];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int nc = a.ncache;
+    // the 2D part first (its LDS layout), then the hot codes for the rest
+    heavy_parts<H == 2 && IDENT>(a, reinterpret_cast<uint8_t*>(qc), reinterpret_cast<int64_t*>(&words[0][0]));
     for (int i = threadIdx.x; i < nc; i += kPT) qc[i] = a.Qin[i];
     __syncthreads();
     u128 sq = 0, mn = 0;
@@ -398,6 +550,65 @@ __global__ __launch_bounds__(256) void k_gap_reduce(const uint64_t* partial, int
     }
 }
 
+// After a sweep with a 2D part: every heavy row's wins summed over the parts
+// of its block, its new key and code, and the gap terms of those rows (per
+// workgroup, written after the sweep's own partial sums of the iteration).
+template <bool GAP>
+__global__ __launch_bounds__(256) void k_heavy_finish(const uint32_t* part_cnt, const int32_t* blk_part,
+                                                      const int32_t* row_blk, const int64_t* blk_row, int R,
+                                                      int64_t n_heavy, const uint64_t* Kin, uint64_t* Kout,
+                                                      uint16_t* Qout, uint64_t inc, int B, uint64_t* partial) {
+    __shared__ uint64_t red[4][4];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    u128 sq = 0, mn = 0;
+    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < n_heavy; r += (int64_t)gridDim.x * 256) {
+        const int64_t b = row_blk[r], rl = r - blk_row[b];
+        const int p0 = blk_part[b], p1 = blk_part[b + 1];
+        uint64_t tot = 0;
+        int p = p0;
+        for (; p + 8 <= p1; p += 8) {
+            uint32_t c[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) c[k] = part_cnt[(int64_t)(p + k) * R + rl];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) tot += c[k];
+        }
+        for (; p < p1; ++p) tot += part_cnt[(int64_t)p * R + rl];
+        const uint64_t Ku = Kin[r];
+        const uint64_t Kn = Ku + ((tot * inc) << B);
+        Kout[r] = Kn;
+        Qout[r] = qcode(Kn >> B);
+        if (GAP) {
+            const uint64_t A = Ku >> B;
+            sq += (u128)A * A;
+            mn += (u128)A * tot;
+        }
+    }
+    if (GAP) {
+        sq = wave_sum128(sq);
+        mn = wave_sum128(mn);
+        if (lane == 0) {
+            red[w][0] = (uint64_t)sq;
+            red[w][1] = (uint64_t)(sq >> 64);
+            red[w][2] = (uint64_t)mn;
+            red[w][3] = (uint64_t)(mn >> 64);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            u128 S = 0, M = 0;
+            for (int q = 0; q < 4; ++q) {
+                S += ((u128)red[q][1] << 64) | red[q][0];
+                M += ((u128)red[q][3] << 64) | red[q][2];
+            }
+            uint64_t* o = partial + (int64_t)blockIdx.x * 4;
+            o[0] = (uint64_t)S;
+            o[1] = (uint64_t)(S >> 64);
+            o[2] = (uint64_t)M;
+            o[3] = (uint64_t)(M >> 64);
+        }
+    }
+}
+
 // initial keys: A0 = deg (edges, r0 = deg/2 with D0 = 2), 2 t_u (triangles,
 // r0 = t_u/3 with D0 = 6) or q_u (4-cliques, r0 = q_u/4 with D0 = 4), packed
 // with the original-id code
@@ -438,6 +649,7 @@ __global__ void k_splits(const int64_t* rp, const int32_t* rid, const int32_t* p
         if (rp[mid] <= s) lo = mid; else hi = mid - 1;
     }
     const int64_t r = lo;
+    if (bitbase[r] < 0) return;  // a heavy row: k_splits_heavy
     const int64_t pos = bitbase[r] + (s - rp[r]);
     uint64_t a = a0;
     for (int i = 1; i <= iters; ++i) {
@@ -450,16 +662,43 @@ __global__ void k_splits(const int64_t* rp, const int32_t* rid, const int32_t* p
     num[s] = a;
 }
 
+// the same for the slots of heavy rows (edges), position by position of the
+// 2D part: the slot is csr[pos], its decision bits follow from word0
+__global__ void k_splits_heavy(const uint32_t* csr, const uint32_t* pay, int64_t positions, int64_t word0,
+                               const int64_t* rp, int64_t nrows, const int32_t* py, const uint64_t* bits,
+                               int64_t total_words, int iters, uint64_t a0, uint64_t incm, const int32_t* orig_of,
+                               int32_t* verts, uint64_t* num) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= positions || pay[k] == 0xffffffffu) return;
+    const int64_t s = csr[k];
+    int64_t lo = 0, hi = nrows - 1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) / 2;
+        if (rp[mid] <= s) lo = mid; else hi = mid - 1;
+    }
+    uint64_t a = a0;
+    const int64_t pos = word0 * 64 + k;
+    for (int i = 1; i <= iters; ++i) {
+        const uint64_t wd = bits[(int64_t)(i - 1) * total_words + pos / 64];
+        if ((wd >> (pos % 64)) & 1ull) a += incm * (uint64_t)(i + 1);
+    }
+    verts[2 * s] = orig_of[lo];
+    verts[2 * s + 1] = orig_of[py[s]];
+    num[s] = a;
+}
+
 uint64_t denom(int mode, int64_t i) { return fw_denom(mode, i); }
 
 template <int H, bool IDENT>
 void launch_sweep(const SweepArgs& a, unsigned blocks, bool gap, hipStream_t s) {
-    const size_t lds = (size_t)a.ncache * sizeof(uint16_t);
+    const bool heavy = H == 2 && IDENT && a.n_parts > 0;
+    const size_t lds = std::max((size_t)a.ncache * sizeof(uint16_t), heavy ? kHeavyLds : (size_t)0);
+    const int max_lds = (int)std::max((size_t)kCacheQ * 2 + 16, (H == 2 && IDENT) ? kHeavyLds : (size_t)0);
     if (gap) {
         static bool attr = false;
         if (!attr) {
             LDS_HIP(hipFuncSetAttribute((const void*)k_fw_sweep<H, IDENT, true>,
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, kCacheQ * 2 + 16));
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, max_lds));
             attr = true;
         }
         k_fw_sweep<H, IDENT, true><<<blocks, kPT, lds, s>>>(a);
@@ -467,7 +706,7 @@ void launch_sweep(const SweepArgs& a, unsigned blocks, bool gap, hipStream_t s) 
         static bool attr = false;
         if (!attr) {
             LDS_HIP(hipFuncSetAttribute((const void*)k_fw_sweep<H, IDENT, false>,
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, kCacheQ * 2 + 16));
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, max_lds));
             attr = true;
         }
         k_fw_sweep<H, IDENT, false><<<blocks, kPT, lds, s>>>(a);
@@ -484,6 +723,81 @@ unsigned sweep_grid() {
         if (cus <= 0) cus = 1;
     }
     return (unsigned)(cus * kWgPerCU);
+}
+
+// workgroups of the heavy rows' finishing kernel (0 without a 2D part); its
+// gap partial sums follow the sweep's in each iteration's slice
+unsigned finish_grid(const SweepPlan& p) { return p.heavy.n_parts > 0 ? sweep_grid() : 0u; }
+
+void fill_sweep_args(const Graph& g, const SweepPlan& p, SweepArgs& a) {
+    a = SweepArgs{};
+    a.rid = p.rid;
+    a.rp = p.rp;
+    a.py = p.py;
+    a.n_hub = p.n_hub;
+    a.hwo = p.hwo.p;
+    a.n_pieces = p.n_pieces;
+    a.hp_row = p.hp_row.p;
+    a.hp_off = p.hp_off.p;
+    a.hub_ctr = p.hub_ctr.p;
+    a.n_chunks = p.n_chunks;
+    a.chunk_row = p.chunk_row.p;
+    a.cwo = p.cwo.p;
+    a.head = p.head.p;
+    a.chunk_words = p.chunk_words;
+    a.B = g.idbits;
+    a.ncache = (int)std::min<int64_t>(g.n, kCacheQ);
+    const HeavyPlan& h = p.heavy;
+    a.n_parts = h.n_parts;
+    a.part_blk = h.part_blk.p;
+    a.part_j0 = h.part_j0.p;
+    a.part_j1 = h.part_j1.p;
+    a.part_lo = h.part_lo.p;
+    a.part_hi = h.part_hi.p;
+    a.hseg = h.seg.p;
+    a.hblk_row = h.blk_row.p;
+    a.hpay = h.pay.p;
+    a.part_cnt = h.part_cnt.p;
+    a.hP = h.P;
+    a.hR = h.R;
+    a.hC = h.C;
+    a.n_heavy = h.n_heavy;
+    a.hword0 = h.word0;
+    a.nv = g.n;
+}
+
+// iteration i: the sweep, then the heavy rows' keys; partial = this
+// iteration's gap slice (sweep workgroups, then finishing workgroups) or null
+void sweep_iteration(FwState& f, const SweepPlan& p, SweepArgs& a, int mode, int i, unsigned blocks,
+                     uint64_t* partial, hipStream_t s) {
+    const bool gap = partial != nullptr;
+    a.Kin = f.K[f.cur].p;
+    a.Kout = f.K[f.cur ^ 1].p;
+    a.Qin = f.Q[f.cur].p;
+    a.Qout = f.Q[f.cur ^ 1].p;
+    a.bits = f.bits.p + (size_t)(i - 1) * p.total_words;
+    a.inc = denom(mode, i) - denom(mode, i - 1);
+    a.partial = partial;
+    if (mode == 2)
+        launch_sweep<2, true>(a, blocks, gap, s);
+    else if (mode == 3)
+        launch_sweep<3, false>(a, blocks, gap, s);
+    else
+        launch_sweep<4, false>(a, blocks, gap, s);
+    LDS_HIP(hipGetLastError());
+    const unsigned fb = finish_grid(p);
+    if (fb > 0) {
+        const HeavyPlan& h = p.heavy;
+        uint64_t* fp = gap ? partial + (size_t)blocks * 4 : nullptr;
+        if (gap)
+            k_heavy_finish<true><<<fb, 256, 0, s>>>(h.part_cnt.p, h.blk_part.p, h.row_blk.p, h.blk_row.p, h.R,
+                                                    h.n_heavy, a.Kin, a.Kout, a.Qout, a.inc, a.B, fp);
+        else
+            k_heavy_finish<false><<<fb, 256, 0, s>>>(h.part_cnt.p, h.blk_part.p, h.row_blk.p, h.blk_row.p, h.R,
+                                                     h.n_heavy, a.Kin, a.Kout, a.Qout, a.inc, a.B, fp);
+        LDS_HIP(hipGetLastError());
+    }
+    f.cur ^= 1;
 }
 
 }  // namespace
@@ -550,25 +864,11 @@ void fw_run(Graph& g, int mode, int iters, bool want_gap, hipStream_t s) {
     f.cur = 0;
     g.sg[mode_slot(mode)].valid = false;
     const unsigned blocks = sweep_grid();
-    const size_t npart = want_gap ? (size_t)iters * blocks * 4 : 0;
+    const unsigned gblocks = blocks + finish_grid(p);  // gap partial sums per iteration
+    const size_t npart = want_gap ? (size_t)iters * gblocks * 4 : 0;
     if (f.partial.n < npart) f.partial.alloc(npart, s);
-    SweepArgs a{};
-    a.rid = p.rid;
-    a.rp = p.rp;
-    a.py = p.py;
-    a.n_hub = p.n_hub;
-    a.hwo = p.hwo.p;
-    a.n_pieces = p.n_pieces;
-    a.hp_row = p.hp_row.p;
-    a.hp_off = p.hp_off.p;
-    a.hub_ctr = p.hub_ctr.p;
-    a.n_chunks = p.n_chunks;
-    a.chunk_row = p.chunk_row.p;
-    a.cwo = p.cwo.p;
-    a.head = p.head.p;
-    a.chunk_words = p.chunk_words;
-    a.B = B;
-    a.ncache = (int)std::min<int64_t>(n, kCacheQ);
+    SweepArgs a;
+    fill_sweep_args(g, p, a);
     if (!f.ev[0]) {
         LDS_HIP(hipEventCreate(&f.ev[0]));
         LDS_HIP(hipEventCreate(&f.ev[1]));
@@ -576,21 +876,8 @@ void fw_run(Graph& g, int mode, int iters, bool want_gap, hipStream_t s) {
     LDS_HIP(hipEventRecord(f.ev[0], s));
     f.launches = 0;
     for (int i = 1; i <= iters && blocks > 0 && p.nrows > 0; ++i) {
-        a.Kin = f.K[f.cur].p;
-        a.Kout = f.K[f.cur ^ 1].p;
-        a.Qin = f.Q[f.cur].p;
-        a.Qout = f.Q[f.cur ^ 1].p;
-        a.bits = f.bits.p + (size_t)(i - 1) * p.total_words;
-        a.inc = denom(mode, i) - denom(mode, i - 1);
-        a.partial = want_gap ? f.partial.p + (size_t)(i - 1) * blocks * 4 : nullptr;
-        if (mode == 2)
-            launch_sweep<2, true>(a, blocks, want_gap, s);
-        else if (mode == 3)
-            launch_sweep<3, false>(a, blocks, want_gap, s);
-        else
-            launch_sweep<4, false>(a, blocks, want_gap, s);
-        LDS_HIP(hipGetLastError());
-        f.cur ^= 1;
+        sweep_iteration(f, p, a, mode, i, blocks, want_gap ? f.partial.p + (size_t)(i - 1) * gblocks * 4 : nullptr,
+                        s);
         ++f.launches;
     }
     LDS_HIP(hipEventRecord(f.ev[1], s));
@@ -604,7 +891,7 @@ void fw_run(Graph& g, int mode, int iters, bool want_gap, hipStream_t s) {
         if (blocks > 0 && p.nrows > 0) {
             DBuf<uint64_t> out;
             out.alloc((size_t)iters * 4, s);
-            k_gap_reduce<<<iters, 256, 0, s>>>(f.partial.p, blocks, out.p);
+            k_gap_reduce<<<iters, 256, 0, s>>>(f.partial.p, gblocks, out.p);
             LDS_HIP(hipGetLastError());
             LDS_HIP(hipMemcpyAsync(sums.data(), out.p, out.bytes(), hipMemcpyDeviceToHost, s));
             LDS_HIP(hipStreamSynchronize(s));
@@ -651,10 +938,6 @@ uint64_t* scratch_on_current_device() {
 
 }  // namespace
 
-size_t fw_noalloc_max_iters(int with_gap) {
-    if (!with_gap) return (size_t)INT32_MAX;
-    return kScratchWords / ((size_t)sweep_grid() * 4 + 5);
-}
 
 void fw_run_noalloc(Graph& g, int mode, int iters, float* r32_dev, double* gap_host, hipStream_t s) {
     LDS_CHECK(mode >= 2 && mode <= 4, ST_INVALID, "mode must be LDS_EDGE, LDS_TRIANGLE or LDS_CLIQUE4");
@@ -673,14 +956,15 @@ void fw_run_noalloc(Graph& g, int mode, int iters, float* r32_dev, double* gap_h
               "Frank-Wolfe state is not sized for this many iterations: run lds_frank_wolfe with at least iters "
               "iterations on this graph and mode first");
     const unsigned blocks = sweep_grid();
+    const unsigned gblocks = blocks + finish_grid(p);
     const bool gap = gap_host != nullptr && iters > 0;
-    const size_t words = gap ? (size_t)iters * ((size_t)blocks * 4 + 5) : 0;
+    const size_t words = gap ? (size_t)iters * ((size_t)gblocks * 4 + 5) : 0;
     LDS_CHECK(words <= kScratchWords, ST_INVALID,
-              "iters exceeds the no-allocation limit with the gap (" + std::to_string(fw_noalloc_max_iters(1)) +
-                  " iterations)");
+              "iters exceeds the no-allocation limit with the gap (" +
+                  std::to_string(kScratchWords / ((size_t)gblocks * 4 + 5)) + " iterations for this graph)");
     uint64_t* sc = scratch_on_current_device();
     uint64_t* partial = sc;
-    uint64_t* sums = sc + (size_t)iters * blocks * 4;
+    uint64_t* sums = sc + (size_t)iters * gblocks * 4;
     double* gapv = reinterpret_cast<double*>(sums + (size_t)iters * 4);
     if (n > 0) {
         const int32_t* cnt = (mode == 2) ? g.deg.p : (mode == 3 ? g.tcount.p : g.qcount.p);
@@ -690,41 +974,11 @@ void fw_run_noalloc(Graph& g, int mode, int iters, float* r32_dev, double* gap_h
     }
     f.cur = 0;
     g.sg[mode_slot(mode)].valid = false;
-    SweepArgs a{};
-    a.rid = p.rid;
-    a.rp = p.rp;
-    a.py = p.py;
-    a.n_hub = p.n_hub;
-    a.hwo = p.hwo.p;
-    a.n_pieces = p.n_pieces;
-    a.hp_row = p.hp_row.p;
-    a.hp_off = p.hp_off.p;
-    a.hub_ctr = p.hub_ctr.p;
-    a.n_chunks = p.n_chunks;
-    a.chunk_row = p.chunk_row.p;
-    a.cwo = p.cwo.p;
-    a.head = p.head.p;
-    a.chunk_words = p.chunk_words;
-    a.B = B;
-    a.ncache = (int)std::min<int64_t>(n, kCacheQ);
+    SweepArgs a;
+    fill_sweep_args(g, p, a);
     const bool any = blocks > 0 && p.nrows > 0;
-    for (int i = 1; i <= iters && any; ++i) {
-        a.Kin = f.K[f.cur].p;
-        a.Kout = f.K[f.cur ^ 1].p;
-        a.Qin = f.Q[f.cur].p;
-        a.Qout = f.Q[f.cur ^ 1].p;
-        a.bits = f.bits.p + (size_t)(i - 1) * p.total_words;
-        a.inc = denom(mode, i) - denom(mode, i - 1);
-        a.partial = gap ? partial + (size_t)(i - 1) * blocks * 4 : nullptr;
-        if (mode == 2)
-            launch_sweep<2, true>(a, blocks, gap, s);
-        else if (mode == 3)
-            launch_sweep<3, false>(a, blocks, gap, s);
-        else
-            launch_sweep<4, false>(a, blocks, gap, s);
-        LDS_HIP(hipGetLastError());
-        f.cur ^= 1;
-    }
+    for (int i = 1; i <= iters && any; ++i)
+        sweep_iteration(f, p, a, mode, i, blocks, gap ? partial + (size_t)(i - 1) * gblocks * 4 : nullptr, s);
     f.iters = iters;
     f.ran = true;
     f.timed = false;
@@ -738,7 +992,7 @@ void fw_run_noalloc(Graph& g, int mode, int iters, float* r32_dev, double* gap_h
     }
     if (gap) {
         if (any) {
-            k_gap_reduce<<<iters, 256, 0, s>>>(partial, blocks, sums);
+            k_gap_reduce<<<iters, 256, 0, s>>>(partial, gblocks, sums);
             LDS_HIP(hipGetLastError());
             k_gap_values<<<grid_for(iters, 256), 256, 0, s>>>(sums, iters, denom(mode, 0) / 2, gapv);
             LDS_HIP(hipGetLastError());
@@ -784,9 +1038,15 @@ void fw_splits(const Graph& g, int mode, int32_t* verts_host, uint64_t* num_host
     a.alloc(ns, s);
     // a0 = D_0 / h; inc_i = D_i - D_{i-1} = incm (i+1) with incm = inc_1 / 2
     const uint64_t a0 = denom(mode, 0) / (uint64_t)H, incm = (denom(mode, 1) - denom(mode, 0)) / 2;
-    if (mode == 2)
+    if (mode == 2) {
         k_splits<2><<<grid_for(ns, 256), 256, 0, s>>>(p.rp, p.rid, p.py, p.bitbase.p, p.nrows, ns, f.bits.p,
                                                       p.total_words, f.iters, a0, incm, g.orig_of.p, v.p, a.p);
+        const HeavyPlan& h = p.heavy;
+        if (h.positions > 0)
+            k_splits_heavy<<<grid_for(h.positions, 256), 256, 0, s>>>(h.csr.p, h.pay.p, h.positions, h.word0, p.rp,
+                                                                      p.nrows, p.py, f.bits.p, p.total_words,
+                                                                      f.iters, a0, incm, g.orig_of.p, v.p, a.p);
+    }
     else if (mode == 3)
         k_splits<3><<<grid_for(ns, 256), 256, 0, s>>>(p.rp, p.rid, p.py, p.bitbase.p, p.nrows, ns, f.bits.p,
                                                       p.total_words, f.iters, a0, incm, g.orig_of.p, v.p, a.p);

@@ -29,6 +29,8 @@ namespace lds {
 
 constexpr int kChunk = 1024;  // target slots per wave; spans < 2*kChunk = 32 words
 constexpr int kPiece = 2048;  // slots of a hub-row piece (a multiple of 64)
+constexpr int kHeavyRows = 8192;   // rows of a block of the 2D part (at most 2^16)
+constexpr int kHeavySlab = 24576;  // neighbour ids of a slab of the 2D part (at most 2^16)
 
 // denominator of the loads after i iterations with gamma_i = 2/(i+2):
 // (i+1)(i+2) for edges (mode 2), 3(i+1)(i+2) for triangles (mode 3),
@@ -51,6 +53,41 @@ inline void check_split_width(int mode, int64_t iters) {
 
 // index of a mode's Frank-Wolfe / stable-group state: edges 0, triangles 1, 4-cliques 2
 inline int mode_slot(int mode) { return mode - 2; }
+
+// Heavy rows of a large edge plan, swept in two dimensions.  The rows of
+// degree >= a threshold (a prefix of the degree-ordered ids) are cut into
+// blocks of at most R rows and their neighbours into slabs of C consecutive
+// ids.  Segment (b, j) lists the slots of block b whose neighbour lies in slab
+// j, by (row, neighbour), each as ((row - first row of b) | run head << 15)
+// << 16 | (neighbour - first id of j), where the run head bit marks a row's
+// first slot in the segment, padded to whole 64-slot words.  Blocks hold at
+// most R rows and, where rows are long, fewer (a cap on their slots).  A part is a range of slabs
+// of one block; a workgroup sweeping a part keeps the block's codes and win
+// counts and one slab of codes at a time in LDS, so every code it compares
+// comes from LDS.  The parts of a block leave partial win counts, which a
+// second kernel sums per row.
+struct HeavyPlan {
+    int64_t n_heavy = 0;          // rows [0, n_heavy) (0: no 2D part)
+    int R = 0, C = 0;             // most rows of a block (stride of the per-block arrays), ids per slab
+    int64_t P = 0;                // slabs: ceil(n / C)
+    int64_t n_blocks = 0, n_parts = 0;
+    int64_t positions = 0;        // padded slots of all segments (multiple of 64)
+    int64_t word0 = 0;            // first decision word of the heavy region in an iteration's words
+    DBuf<int64_t> seg;            // n_blocks * P + 1 first positions
+    DBuf<uint32_t> pay;           // positions: packed (row, neighbour), 0xffffffff for padding
+    DBuf<uint32_t> csr;           // positions: CSR slot, 0xffffffff for padding
+    DBuf<int32_t> part_blk, part_j0, part_j1;  // per part: block and slab range [j0, j1)
+    DBuf<int64_t> part_lo, part_hi;            // per part: its positions [lo, hi), within the block's
+    DBuf<int32_t> blk_part;       // n_blocks + 1: first part of each block
+    DBuf<int64_t> blk_row;        // n_blocks + 1: first row of each block
+    DBuf<int32_t> row_blk;        // n_heavy: block of each heavy row
+    DBuf<uint32_t> part_cnt;      // n_parts * R partial win counts (rewritten every sweep)
+    size_t device_bytes() const {
+        return seg.bytes() + pay.bytes() + csr.bytes() + part_blk.bytes() + part_j0.bytes() + part_j1.bytes() +
+               part_lo.bytes() + part_hi.bytes() + blk_part.bytes() + blk_row.bytes() + row_blk.bytes() +
+               part_cnt.bytes();
+    }
+};
 
 struct SweepPlan {
     int h = 2;                  // pattern arity: 2 edges, 3 triangles
@@ -76,10 +113,11 @@ struct SweepPlan {
     DBuf<int64_t> cwo;          // n_chunks + 1 word offsets
     DBuf<uint64_t> head;        // chunk_words words: row-start flags
     int64_t chunk_words = 0, hub_words = 0, total_words = 0;
-    DBuf<int64_t> bitbase;      // per compact row: bit index of its first slot
+    DBuf<int64_t> bitbase;      // per compact row: bit index of its first slot (-1: heavy row)
+    HeavyPlan heavy;            // edge plans of large graphs only
     size_t device_bytes() const {
         return own_rid.bytes() + own_rp.bytes() + own_py.bytes() + own_tos.bytes() + own_row_of.bytes() + hwo.bytes() + chunk_row.bytes() + cwo.bytes() +
-               head.bytes() + bitbase.bytes() + hp_row.bytes() + hp_off.bytes() + hub_ctr.bytes();
+               head.bytes() + bitbase.bytes() + hp_row.bytes() + hp_off.bytes() + hub_ctr.bytes() + heavy.device_bytes();
     }
 };
 
@@ -157,7 +195,8 @@ struct Graph {
 // ingest.hip
 void build_graph(Graph& g, int64_t n, int64_t npairs, const int32_t* src, const int32_t* dst, bool on_device,
                  bool strict, hipStream_t s);
-void build_sweep_plan(SweepPlan& p, hipStream_t s);  // needs h, nrows, nslots, rowptr, pay, rowid
+void build_sweep_plan(SweepPlan& p, hipStream_t s, int64_t n_vertices = 0);  // needs h, nrows, nslots, rowptr, pay, rowid;
+                                                                             // n_vertices > 0 allows the 2D heavy part (edges)
 void sort_rows(Graph& g, hipStream_t s);             // CSR rows ascending (triangle listing)
 
 // triangles.hip
@@ -202,7 +241,6 @@ void fw_run(Graph& g, int mode, int iters, bool want_gap, hipStream_t s);
 // fw_run without any device allocation (lds_frank_wolfe_noalloc): the FW
 // state must already be sized for iters; gap scratch from the device array
 void fw_run_noalloc(Graph& g, int mode, int iters, float* r32_dev, double* gap_host, hipStream_t s);
-size_t fw_noalloc_max_iters(int with_gap);
 void fw_loads(const Graph& g, int mode, float* r32_dev, double* r64_host, uint64_t* A_host, hipStream_t s);
 void fw_splits(const Graph& g, int mode, int32_t* verts_host, uint64_t* num_host, hipStream_t s);
 

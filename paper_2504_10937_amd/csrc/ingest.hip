@@ -6,6 +6,10 @@
 
 #include "graph.hpp"
 
+#include <algorithm>
+#include <cstdlib>
+#include <vector>
+
 namespace lds {
 
 namespace {
@@ -174,16 +178,106 @@ __global__ void k_head(const int64_t* rp, int64_t nrows, int64_t n_hub, const in
 }
 
 __global__ void k_bitbase(const int64_t* rp, int64_t nrows, int64_t n_hub, const int64_t* chunk_row,
-                          const int64_t* cwo, const int64_t* hwo, int64_t chunk_words, int64_t* bitbase) {
+                          const int64_t* cwo, const int64_t* hwo, int64_t chunk_words, bool heavy, int64_t* bitbase) {
     const int64_t r = (int64_t)blockIdx.x * kT + threadIdx.x;
     if (r >= nrows) return;
     if (r < n_hub) {
-        bitbase[r] = (chunk_words + hwo[r]) * 64;
+        bitbase[r] = heavy ? -1 : (chunk_words + hwo[r]) * 64;
     } else {
         const int64_t base = rp[n_hub];
         const int64_t c = (rp[r] - base) / kChunk;
         bitbase[r] = cwo[c] * 64 + (rp[r] - rp[chunk_row[c]]);
     }
+}
+
+// ------------------------------------------------------ heavy 2D part
+// rows with at least deg_min slots: a prefix (rows are ordered by slot count)
+__global__ void k_count_deg(const int64_t* rp, int64_t nrows, int64_t deg_min, unsigned long long* cnt) {
+    const int64_t r = (int64_t)blockIdx.x * kT + threadIdx.x;
+    const bool h = r < nrows && (rp[r + 1] - rp[r]) >= deg_min;
+    unsigned long long c = __popcll(__ballot(h));
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(cnt, c);
+}
+
+// One wave per heavy row walks the row's slots (sorted by neighbour, so each
+// slab's slots form one run).  FILL = false: the length of the run of every
+// (row, slab) pair into len[(b P + j) R + row in block].  FILL = true: with
+// len scanned per (b, j), every slot's position seg + len + index in run, its
+// packed (row, neighbour) and its CSR slot.
+template <bool FILL>
+__global__ void k_heavy_rows(const int64_t* rp, const int32_t* col, int64_t n_heavy, const int32_t* row_blk,
+                             const int64_t* blk_row, int R, int C, int64_t P, uint32_t* len, const int64_t* seg,
+                             uint32_t* pay, uint32_t* csr) {
+    const int lane = threadIdx.x & 63;
+    const int64_t u = ((int64_t)blockIdx.x * kT + threadIdx.x) >> 6;
+    if (u >= n_heavy) return;
+    const int64_t b = row_blk[u], ul = u - blk_row[b];
+    const int64_t s0 = rp[u], s1 = rp[u + 1];
+    int64_t carry_start = s0;  // first slot of the run that continues into this chunk
+    int32_t carry_j = -1;
+    for (int64_t base = s0; base < s1; base += 64) {
+        const int64_t sl = base + lane;
+        const bool valid = sl < s1;
+        const int32_t v = valid ? col[sl] : 0;
+        const int32_t j = valid ? v / C : INT32_MAX;
+        int32_t jprev = __shfl_up(j, 1, 64);
+        if (lane == 0) jprev = carry_j;
+        const bool head = valid && j != jprev;
+        const uint64_t H = __ballot(head);
+        const uint64_t le = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+        const uint64_t m = H & le;
+        const int64_t rs = m ? base + (63 - __clzll(m)) : carry_start;
+        if (FILL) {
+            if (valid) {
+                const int64_t k = (b * P + j);
+                const int64_t pos = seg[k] + (int64_t)len[k * R + ul] + (sl - rs);
+                pay[pos] = (((uint32_t)ul | (sl == rs ? 0x8000u : 0u)) << 16) | (uint32_t)(v - j * C);
+                csr[pos] = (uint32_t)sl;
+            }
+        } else {
+            int32_t jnext = __shfl_down(j, 1, 64);
+            if (lane == 63) jnext = (sl + 1 < s1) ? col[sl + 1] / C : INT32_MAX;
+            if (valid && (sl + 1 == s1 || jnext != j)) len[(b * P + j) * R + ul] = (uint32_t)(sl - rs + 1);
+        }
+        carry_start = __shfl(rs, 63, 64);
+        carry_j = __shfl(j, 63, 64);
+    }
+}
+
+// exclusive scan of each (b, j) row of len (R entries, in place); the
+// segment's slot count padded to whole words into segsz[b P + j]
+__global__ __launch_bounds__(256) void k_heavy_scan(uint32_t* len, int R, uint64_t* segsz) {
+    __shared__ uint32_t part[256];
+    uint32_t* row = len + (int64_t)blockIdx.x * R;
+    const int per = (R + 255) / 256, t = threadIdx.x;
+    uint32_t sum = 0;
+    for (int i = 0; i < per; ++i) {
+        const int k = t * per + i;
+        if (k < R) sum += row[k];
+    }
+    part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const uint32_t x = (t >= off) ? part[t - off] : 0u;
+        __syncthreads();
+        part[t] += x;
+        __syncthreads();
+    }
+    uint32_t run = part[t] - sum;
+    for (int i = 0; i < per; ++i) {
+        const int k = t * per + i;
+        if (k < R) {
+            const uint32_t x = row[k];
+            row[k] = run;
+            run += x;
+        }
+    }
+    if (t == 255) segsz[blockIdx.x] = ((uint64_t)part[255] + 63) / 64 * 64;
+}
+
+__global__ void k_fill_u32v(uint32_t* p, int64_t n, uint32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (i < n) p[i] = v;
 }
 
 template <class T>
@@ -196,33 +290,193 @@ T d2h(const T* p, hipStream_t s) {
 
 }  // namespace
 
-void build_sweep_plan(SweepPlan& p, hipStream_t s) {
+namespace {
+
+int64_t env_int(const char* name, int64_t dflt) {
+    const char* e = std::getenv(name);
+    if (!e || !*e) return dflt;
+    return std::strtoll(e, nullptr, 10);
+}
+
+// The 2D part of a large edge plan (see HeavyPlan), built only when
+// LDS_HEAVY_DEG is set: on the 4M-vertex power-law workload it measured
+// slower than the one-dimensional sweep (1.01 against 0.945 ms per launch
+// with rows of degree >= 128 in it), so it is off by default.  Rows of degree
+// >= LDS_HEAVY_DEG are heavy when their slots number at least
+// LDS_HEAVY_MIN_SLOTS (default 2^22) and the graph has more than one slab;
+// LDS_HEAVY_ROWS (<= 8192) and LDS_HEAVY_SLAB (<= 24576, a multiple of 8)
+// override the block and slab sizes, LDS_HEAVY_PART the positions of a part
+// (default: a quarter of the positions per compute unit, at least 4096).
+// Returns the heavy row count (0: none).
+int64_t build_heavy(SweepPlan& p, int64_t n, hipStream_t s) {
+    HeavyPlan& h = p.heavy;
+    h = HeavyPlan{};
+    if (p.h != 2 || p.rid != nullptr || n <= 0 || p.nrows == 0) return 0;
+    // every row with more than a chunk's slots must be heavy (no hub pieces
+    // then), so the threshold is at most kChunk + 1
+    const int64_t deg_env = env_int("LDS_HEAVY_DEG", 0);
+    if (deg_env <= 0) return 0;  // off unless asked for (see the header comment)
+    const int64_t deg_min = std::min<int64_t>(deg_env, kChunk + 1);
+    const int64_t min_slots = env_int("LDS_HEAVY_MIN_SLOTS", (int64_t)1 << 22);
+    const int R = (int)(std::min<int64_t>(std::max<int64_t>(64, env_int("LDS_HEAVY_ROWS", kHeavyRows)), kHeavyRows) /
+                        64 * 64);
+    const int C = (int)(std::min<int64_t>(std::max<int64_t>(64, env_int("LDS_HEAVY_SLAB", kHeavySlab)), kHeavySlab) /
+                        8 * 8);
+    if (n <= C) return 0;
+    DBuf<unsigned long long> cnt;
+    cnt.alloc(1, s);
+    LDS_HIP(hipMemsetAsync(cnt.p, 0, sizeof(unsigned long long), s));
+    k_count_deg<<<grid_for(p.nrows, kT), kT, 0, s>>>(p.rp, p.nrows, deg_min, cnt.p);
+    LDS_HIP(hipGetLastError());
+    const int64_t nh = (int64_t)d2h(cnt.p, s);
+    if (nh == 0) return 0;
+    int64_t hslots = 0;
+    LDS_HIP(hipMemcpyAsync(&hslots, p.rp + nh, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    LDS_HIP(hipStreamSynchronize(s));
+    if (hslots < min_slots) return 0;
+    h.n_heavy = nh;
+    h.R = R;
+    h.C = C;
+    h.P = (n + C - 1) / C;
+    // blocks: consecutive rows, at most R of them and, for long rows, at most
+    // LDS_HEAVY_BLOCK_SLOTS (default 2^22) slots, so that no block needs a
+    // great many parts
+    const int64_t cap = std::max<int64_t>(1, env_int("LDS_HEAVY_BLOCK_SLOTS", (int64_t)1 << 22));
+    std::vector<int64_t> hrp(nh + 1);
+    LDS_HIP(hipMemcpyAsync(hrp.data(), p.rp, hrp.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    LDS_HIP(hipStreamSynchronize(s));
+    std::vector<int64_t> brow{0};
+    std::vector<int32_t> rblk(nh);
+    for (int64_t u = 0; u < nh; ++u) {
+        const int64_t b0 = brow.back();
+        if (u > b0 && (u - b0 >= R || hrp[u + 1] - hrp[b0] > cap)) brow.push_back(u);
+        rblk[u] = (int32_t)(brow.size() - 1);
+    }
+    brow.push_back(nh);
+    h.n_blocks = (int64_t)brow.size() - 1;
+    h.blk_row.alloc(brow.size(), s);
+    h.row_blk.alloc(nh, s);
+    LDS_HIP(hipMemcpyAsync(h.blk_row.p, brow.data(), brow.size() * 8, hipMemcpyHostToDevice, s));
+    LDS_HIP(hipMemcpyAsync(h.row_blk.p, rblk.data(), rblk.size() * 4, hipMemcpyHostToDevice, s));
+    const int64_t nseg = h.n_blocks * h.P;
+    // run lengths per (block, slab, row), scanned per (block, slab)
+    DBuf<uint32_t> len;
+    len.alloc((size_t)nseg * R, s);
+    LDS_HIP(hipMemsetAsync(len.p, 0, len.bytes(), s));
+    k_heavy_rows<false><<<grid_for(nh * 64, kT), kT, 0, s>>>(p.rp, p.py, nh, h.row_blk.p, h.blk_row.p, R, C, h.P,
+                                                             len.p, nullptr, nullptr, nullptr);
+    LDS_HIP(hipGetLastError());
+    h.seg.alloc(nseg + 1, s);
+    k_heavy_scan<<<(unsigned)nseg, 256, 0, s>>>(len.p, R, (uint64_t*)h.seg.p);
+    LDS_HIP(hipGetLastError());
+    DBuf<uint64_t> tot;
+    tot.alloc(1, s);
+    exclusive_scan_u64((uint64_t*)h.seg.p, (uint64_t*)h.seg.p, nseg, tot.p, s);
+    k_set_last<<<1, 1, 0, s>>>(h.seg.p, nseg, tot.p);
+    LDS_HIP(hipGetLastError());
+    h.positions = (int64_t)d2h(tot.p, s);
+    h.pay.alloc(h.positions, s);
+    h.csr.alloc(h.positions, s);
+    if (h.positions > 0) {
+        k_fill_u32v<<<grid_for(h.positions, kT), kT, 0, s>>>(h.pay.p, h.positions, 0xffffffffu);
+        k_fill_u32v<<<grid_for(h.positions, kT), kT, 0, s>>>(h.csr.p, h.positions, 0xffffffffu);
+        LDS_HIP(hipGetLastError());
+    }
+    k_heavy_rows<true><<<grid_for(nh * 64, kT), kT, 0, s>>>(p.rp, p.py, nh, h.row_blk.p, h.blk_row.p, R, C, h.P,
+                                                            len.p, h.seg.p, h.pay.p, h.csr.p);
+    LDS_HIP(hipGetLastError());
+    // parts: each block's positions cut into near-equal word-aligned ranges
+    std::vector<int64_t> seg(nseg + 1);
+    LDS_HIP(hipMemcpyAsync(seg.data(), h.seg.p, seg.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    LDS_HIP(hipStreamSynchronize(s));
+    int dev = 0, cus = 0;
+    LDS_HIP(hipGetDevice(&dev));
+    LDS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int64_t dflt = (h.positions / std::max<int64_t>(1, 4 * (int64_t)std::max(cus, 1)) + 63) / 64 * 64;
+    const int64_t target = std::max<int64_t>(64, env_int("LDS_HEAVY_PART", std::max<int64_t>(64 * 64, dflt))) / 64 * 64;
+    std::vector<int32_t> pb, pj0, pj1, bp(h.n_blocks + 1, 0);
+    std::vector<int64_t> ps, pe;
+    for (int64_t b = 0; b < h.n_blocks; ++b) {
+        bp[b] = (int32_t)pb.size();
+        const int64_t B0 = seg[b * h.P], B1 = seg[(b + 1) * h.P];
+        const int64_t np = std::max<int64_t>(1, (B1 - B0 + target - 1) / target);
+        for (int64_t k = 0; k < np; ++k) {
+            const int64_t q0 = B0 + (B1 - B0) * k / np / 64 * 64;
+            const int64_t q1 = (k + 1 == np) ? B1 : B0 + (B1 - B0) * (k + 1) / np / 64 * 64;
+            if (q1 <= q0) continue;
+            // slabs whose segments meet [q0, q1)
+            int64_t j0 = 0, j1 = h.P;
+            while (j0 < h.P && seg[b * h.P + j0 + 1] <= q0) ++j0;
+            while (j1 > j0 && seg[b * h.P + j1 - 1] >= q1) --j1;
+            pb.push_back((int32_t)b);
+            pj0.push_back((int32_t)j0);
+            pj1.push_back((int32_t)j1);
+            ps.push_back(q0);
+            pe.push_back(q1);
+        }
+    }
+    bp[h.n_blocks] = (int32_t)pb.size();
+    h.n_parts = (int64_t)pb.size();
+    LDS_CHECK(h.n_parts < INT32_MAX / 2, ST_INVALID, "too many parts in the heavy sweep plan");
+    h.part_blk.alloc(h.n_parts, s);
+    h.part_j0.alloc(h.n_parts, s);
+    h.part_j1.alloc(h.n_parts, s);
+    h.blk_part.alloc(h.n_blocks + 1, s);
+    h.part_cnt.alloc((size_t)h.n_parts * R, s);
+    h.part_lo.alloc(h.n_parts, s);
+    h.part_hi.alloc(h.n_parts, s);
+    LDS_HIP(hipMemcpyAsync(h.part_blk.p, pb.data(), pb.size() * 4, hipMemcpyHostToDevice, s));
+    LDS_HIP(hipMemcpyAsync(h.part_j0.p, pj0.data(), pj0.size() * 4, hipMemcpyHostToDevice, s));
+    LDS_HIP(hipMemcpyAsync(h.part_j1.p, pj1.data(), pj1.size() * 4, hipMemcpyHostToDevice, s));
+    LDS_HIP(hipMemcpyAsync(h.part_lo.p, ps.data(), ps.size() * 8, hipMemcpyHostToDevice, s));
+    LDS_HIP(hipMemcpyAsync(h.part_hi.p, pe.data(), pe.size() * 8, hipMemcpyHostToDevice, s));
+    LDS_HIP(hipMemcpyAsync(h.blk_part.p, bp.data(), bp.size() * 4, hipMemcpyHostToDevice, s));
+    LDS_HIP(hipStreamSynchronize(s));
+    return nh;
+}
+
+}  // namespace
+
+void build_sweep_plan(SweepPlan& p, hipStream_t s, int64_t n_vertices) {
     const int64_t nrows = p.nrows;
+    const int64_t n_heavy = n_vertices > 0 ? build_heavy(p, n_vertices, s) : 0;
     DBuf<unsigned long long> cnt;
     cnt.alloc(1, s);
     LDS_HIP(hipMemsetAsync(cnt.p, 0, sizeof(unsigned long long), s));
     if (nrows > 0) k_count_hubs<<<grid_for(nrows, kT), kT, 0, s>>>(p.rp, nrows, cnt.p);
     LDS_HIP(hipGetLastError());
     p.n_hub = (int64_t)d2h(cnt.p, s);
+    // with a 2D part, every row of more than a chunk's slots is heavy: the
+    // chunks start after the heavy rows and there are no hub pieces
+    if (n_heavy > 0) {
+        LDS_CHECK(n_heavy >= p.n_hub, ST_INVALID, "heavy rows must include every hub row");
+        p.n_hub = n_heavy;
+    }
     LDS_HIP(hipMemsetAsync(cnt.p, 0, sizeof(unsigned long long), s));
     if (nrows > 0) k_count_big<<<grid_for(nrows, kT), kT, 0, s>>>(p.rp, nrows, cnt.p);
     LDS_HIP(hipGetLastError());
     p.n_big = (int64_t)d2h(cnt.p, s);
-    // hub word offsets
+    // hub word offsets (none with a 2D part: its rows have no words there)
     p.hwo.alloc(p.n_hub + 1, s);
-    if (p.n_hub > 0) {
+    if (n_heavy > 0) {
+        LDS_HIP(hipMemsetAsync(p.hwo.p, 0, p.hwo.bytes(), s));
+    } else if (p.n_hub > 0) {
         k_hub_words<<<grid_for(p.n_hub, kT), kT, 0, s>>>(p.rp, p.n_hub, (uint64_t*)p.hwo.p);
         LDS_HIP(hipGetLastError());
     }
     DBuf<uint64_t> tot;
     tot.alloc(1, s);
-    exclusive_scan_u64((uint64_t*)p.hwo.p, (uint64_t*)p.hwo.p, p.n_hub, tot.p, s);
-    k_set_last<<<1, 1, 0, s>>>(p.hwo.p, p.n_hub, tot.p);
-    LDS_HIP(hipGetLastError());
-    p.hub_words = (int64_t)d2h(tot.p, s);
+    if (n_heavy == 0) {
+        exclusive_scan_u64((uint64_t*)p.hwo.p, (uint64_t*)p.hwo.p, p.n_hub, tot.p, s);
+        k_set_last<<<1, 1, 0, s>>>(p.hwo.p, p.n_hub, tot.p);
+        LDS_HIP(hipGetLastError());
+        p.hub_words = (int64_t)d2h(tot.p, s);
+    } else {
+        p.hub_words = 0;
+    }
     // hub pieces and their per-row counters
     p.n_pieces = 0;
-    if (p.n_hub > 0) {
+    if (p.n_hub > 0 && n_heavy == 0) {
         DBuf<uint32_t> npc;
         DBuf<uint64_t> first;
         npc.alloc(p.n_hub, s);
@@ -261,7 +515,8 @@ void build_sweep_plan(SweepPlan& p, hipStream_t s) {
     k_set_last<<<1, 1, 0, s>>>(p.cwo.p, p.n_chunks, tot.p);
     LDS_HIP(hipGetLastError());
     p.chunk_words = (int64_t)d2h(tot.p, s);
-    p.total_words = p.chunk_words + p.hub_words;
+    p.heavy.word0 = p.chunk_words + p.hub_words;
+    p.total_words = p.chunk_words + p.hub_words + p.heavy.positions / 64;
     p.head.alloc(p.chunk_words, s);
     if (p.chunk_words) LDS_HIP(hipMemsetAsync(p.head.p, 0, p.head.bytes(), s));
     if (nrows > p.n_hub) {
@@ -272,7 +527,7 @@ void build_sweep_plan(SweepPlan& p, hipStream_t s) {
     p.bitbase.alloc(nrows, s);
     if (nrows > 0) {
         k_bitbase<<<grid_for(nrows, kT), kT, 0, s>>>(p.rp, nrows, p.n_hub, p.chunk_row.p, p.cwo.p, p.hwo.p,
-                                                    p.chunk_words, p.bitbase.p);
+                                                    p.chunk_words, n_heavy > 0, p.bitbase.p);
         LDS_HIP(hipGetLastError());
     }
     LDS_HIP(hipStreamSynchronize(s));
@@ -413,7 +668,7 @@ void build_graph(Graph& g, int64_t n, int64_t npairs, const int32_t* src, const 
     p.rid = nullptr;
     p.rp = g.rowptr.p;
     p.py = g.col.p;
-    build_sweep_plan(p, s);
+    build_sweep_plan(p, s, n);
 }
 
 void sort_rows(Graph& g, hipStream_t s) {

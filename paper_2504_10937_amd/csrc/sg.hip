@@ -88,21 +88,29 @@ __global__ __launch_bounds__(kT) void k_slot_splits(const int64_t* rp, int64_t n
                                                     const int32_t* hp_off, const int64_t* hwo, int64_t n_chunks,
                                                     const int64_t* chunk_row, const int64_t* cwo, int64_t chunk_words,
                                                     const uint64_t* bits, int64_t total_words, int iters, int tri,
-                                                    uint32_t* a_slot) {
+                                                    int64_t heavy_positions, int64_t heavy_word0,
+                                                    const uint32_t* heavy_csr, uint32_t* a_slot) {
     __shared__ uint64_t sw[kIterB][kSpanW];
     const int64_t b = blockIdx.x;
     int64_t s0, s1, word0;
+    bool heavy = false;  // positions of the 2D part: the slot of position x is heavy_csr[x]
     if (b < n_pieces) {  // a hub row's piece (word-aligned, at most kPiece slots)
         const int64_t r = hp_row[b];
         s0 = rp[r] + hp_off[b];
         s1 = min(rp[r + 1], s0 + (int64_t)kPiece);
         word0 = chunk_words + hwo[r] + hp_off[b] / 64;
-    } else {
+    } else if (b < n_pieces + n_chunks) {
         const int64_t c = b - n_pieces;
-        if (c >= n_chunks) return;
         s0 = rp[chunk_row[c]];
         s1 = rp[chunk_row[c + 1]];
         word0 = cwo[c];
+    } else {
+        const int64_t h = b - n_pieces - n_chunks;
+        s0 = h * (int64_t)kPiece;
+        if (s0 >= heavy_positions) return;
+        s1 = min(heavy_positions, s0 + (int64_t)kPiece);
+        word0 = heavy_word0 + s0 / 64;
+        heavy = true;
     }
     constexpr int kPer = 64 * kSpanW / kT;  // slots per thread and span
     const int t = threadIdx.x;
@@ -137,7 +145,14 @@ __global__ __launch_bounds__(kT) void k_slot_splits(const int64_t* rp, int64_t n
 #pragma unroll
         for (int q = 0; q < kPer; ++q) {
             const int64_t s = base + t + kT * q;
-            if (s < s1) a_slot[s] = acc[q];
+            if (s < s1) {
+                if (!heavy) {
+                    a_slot[s] = acc[q];
+                } else {
+                    const uint32_t x = heavy_csr[s];
+                    if (x != 0xffffffffu) a_slot[x] = acc[q];
+                }
+            }
         }
     }
 }
@@ -1159,10 +1174,12 @@ void sg_sort_prefix(Graph& g, int mode, hipStream_t s) {
     // per-slot split numerators (and per triangle)
     q.a_slot.alloc(p.nslots, s);
     if (p.nslots > 0 && f.iters >= 0) {
-        const int64_t blocks = p.n_pieces + p.n_chunks;
+        const HeavyPlan& hv = p.heavy;
+        const int64_t blocks = p.n_pieces + p.n_chunks + (hv.positions + kPiece - 1) / kPiece;
         k_slot_splits<<<grid_for(blocks, 1), kT, 0, s>>>(p.rp, p.n_pieces, p.hp_row.p, p.hp_off.p, p.hwo.p, p.n_chunks,
                                                          p.chunk_row.p, p.cwo.p, p.chunk_words, f.bits.p,
-                                                         p.total_words, f.iters, mode == 3, q.a_slot.p);
+                                                         p.total_words, f.iters, mode == 3, hv.positions, hv.word0,
+                                                         hv.csr.p, q.a_slot.p);
         LDS_HIP(hipGetLastError());
     }
     if (mode == 3) {
