@@ -31,6 +31,18 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def cpu_model():
+    """the host CPU's model name (from /proc/cpuinfo), or 'unknown'"""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def kernel_source_hash():
     with open(os.path.join(ROOT, "paper_2504_10937_amd", "csrc", "fw.hip"), "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
@@ -294,8 +306,11 @@ def main():
                     help="graphs of the batched-vs-plain comparison (0: skip)")
     ap.add_argument("--no-batch-plain", action="store_true",
                     help="leave out the per-graph comparison of the batched section (shorter kernel traces)")
-    ap.add_argument("--density-sweep", default="2,6,12",
+    ap.add_argument("--density-sweep", default="2,4,6,8,10,12",
                     help="Barabasi-Albert densities of the scalability section (n = 1M; empty: skip)")
+    ap.add_argument("--copy-gib", type=float, default=1.0,
+                    help="GiB copied by the library's streaming copy kernel for the bandwidth ceiling (0: skip)")
+    ap.add_argument("--cpu-reps", type=int, default=3, help="timed repetitions of the oracle sample (median)")
     ap.add_argument("--ltds", default="ltds_hk", help="triangle (LTDS) workload ('' to skip)")
     ap.add_argument("--topk", default="lds_large,ltds_hk", help="workloads timed end to end by lds_topk ('' to skip)")
     ap.add_argument("--clique4", default="clique4_pl", help="4-clique FW workload ('' to skip)")
@@ -400,6 +415,18 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "alg_bytes_per_launch": alg_bytes, "kernel": "k_fw_sweep"},
     }
+    if args.copy_gib > 0:
+        nb = int(args.copy_gib * (1 << 30)) // 16 * 16
+        x = torch.empty(nb // 4, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        x.fill_(1.0)
+        cms = lds.lds_copy_bandwidth(y, x, reps=10)
+        del x, y
+        copy_gbs = 2.0 * nb / (cms / 1e3) / 1e9
+        out["roofline"]["copy_ceiling"] = {"achieved": copy_gbs, "unit": "GB/s", "kernel": "k_copy16",
+                                           "bytes_per_copy": 2 * nb, "ms_per_copy": cms}
+        out["roofline"]["frac_of_copy"] = achieved / copy_gbs
+        log("copy ceiling: %.0f GB/s (%.3f ms per %.2f GiB copy)" % (copy_gbs, cms, args.copy_gib))
     if args.batch_graphs > 0:
         out["batched"] = bench_batched(lds, torch, synth, np, args.batch_graphs, not args.no_batch_plain)
     if args.density_sweep:
@@ -416,14 +443,19 @@ def main():
         import oracle
         log("cpu baseline: oracle ingest (untimed)")
         G = oracle.Graph(n, src, dst)
-        t = time.perf_counter()
-        oracle.fw_exact(G, mode, args.cpu_iters, with_gap=True, with_split=False)
-        dt = time.perf_counter() - t
+        times = []
+        for _ in range(max(1, args.cpu_reps)):
+            t = time.perf_counter()
+            oracle.fw_exact(G, mode, args.cpu_iters, with_gap=True, with_split=False)
+            times.append(time.perf_counter() - t)
+        dt = sorted(times)[len(times) // 2]
         cpu_units = G.m if mode == 2 else oracle.num_patterns(G, mode)
         out["cpu_baseline"] = {
             "value": cpu_units * args.cpu_iters / dt, "unit": out["unit"], "cores": 1, "kind": "oracle",
+            "cpu_model": cpu_model(), "host_threads": os.cpu_count(),
             "sample": "%s graph (n=%d, m=%d), %d of the %d FW iterations incl. exact gap, single thread, "
-                      "%.1f s" % (args.workload, n, G.m, args.cpu_iters, iters, dt)}
+                      "median of %d runs (%s s)" % (args.workload, n, G.m, args.cpu_iters, iters, len(times),
+                                                   ", ".join("%.1f" % x for x in times))}
         log("cpu baseline: %.3g %s" % (out["cpu_baseline"]["value"], out["unit"]))
     print(json.dumps(out), flush=True)
 

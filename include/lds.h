@@ -213,6 +213,27 @@ uint64_t lds_denominator(lds_mode mode, int32_t iters);
 lds_status lds_loads(lds_graph g, lds_mode mode, float* r_out, double* r64_out, uint64_t* num_out, double* gap_out,
                      int32_t* iters_out, void* hip_stream);
 
+/* Certified bounds of the last lds_frank_wolfe run that computed the gap,
+ * per iteration i = 1..iters (host arrays of iters entries, each optional):
+ *   lb_out[i-1]       LB_i = 2 sum_patterns min_u r_u - sum_u r_u^2 at
+ *                     r^(i-1), a lower bound on the optimum f* of Eq. cp /
+ *                     Eq. trcp (f = sum r^2 minus its linear gap);
+ *   cert_gap_out[i-1] Gamma_i = min_{j<=i} f_j - max_{j<=i} LB_j with
+ *                     f_j = sum r^2 at r^(j-1): the certified gap, >= 0
+ *                     and non-increasing in i.
+ * Both follow from the exact integer sums of the sweep (rounded once to
+ * FP64).  LDS_E_INVALID when the last run did not compute the gap. */
+lds_status lds_fw_bounds(lds_graph g, lds_mode mode, double* lb_out, double* cert_gap_out);
+
+/* Measurement: the achievable device-memory bandwidth that the roofline of
+ * the sweep is read against.  Copies `bytes` (a positive multiple of 16)
+ * from src to dst (device pointers, 16-byte aligned, not overlapping) with a
+ * grid-strided 16-byte streaming copy kernel, once untimed and then `reps`
+ * times on hip_stream; *ms_out = mean GPU milliseconds of one copy (HIP
+ * events; 2 * bytes cross HBM per copy).  Waits for the stream. */
+lds_status lds_copy_bandwidth(void* dst, const void* src, size_t bytes, int32_t reps, void* hip_stream,
+                              float* ms_out);
+
 /* ---- Batched Frank-Wolfe over many independent graphs ----------------------
  * A batch runs lds_frank_wolfe(graphs[i], modes[i], iters[i]) for every i in
  * one persistent kernel launch, captured into a hipGraph at creation and

@@ -80,6 +80,8 @@ def load():
         "lds_result_free": (None, [vp]),
         "lds_loads": (st, [vp, st, vp, vp, vp, vp, vp, vp]),
         "lds_core_numbers": (st, [vp, st, vp, vp, vp]),
+        "lds_fw_bounds": (st, [vp, st, vp, vp]),
+        "lds_copy_bandwidth": (st, [vp, vp, ctypes.c_size_t, i32, vp, vp]),
         "lds_tune_default": (None, [vp]),
         "lds_batch_create": (st, [vp, vp, vp, vp, i32, u32, vp, vp, vp]),
         "lds_batch_run": (st, [vp, vp]),
@@ -361,6 +363,27 @@ def lds_loads(g, mode, r_out=None, want_r64=False, want_num=False, want_gap=Fals
         _check(load().lds_loads(g.handle, mode, None, None, None, _ptr(gap), None, _stream(stream)))
     out.update({k: v for k, v in (("r64", r64), ("num", num), ("gap", gap)) if v is not None})
     return out
+
+
+def lds_fw_bounds(g, mode):
+    """Lower bounds LB_i and certified gaps Gamma_i of the last FW run with
+    the gap -> (lb (iters,), cert_gap (iters,))."""
+    it = lds_loads(g, mode)["iters"]
+    lb = np.empty(it, np.float64)
+    cg = np.empty(it, np.float64)
+    _check(load().lds_fw_bounds(g.handle, mode, _ptr(lb), _ptr(cg)))
+    return lb, cg
+
+
+def lds_copy_bandwidth(dst, src, reps=10, stream=None):
+    """Mean GPU ms of one streaming copy src -> dst (device tensors of the
+    same byte size, a multiple of 16) by the library's copy kernel."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes or not (dst.is_cuda and src.is_cuda):
+        raise ValueError("dst and src must be device tensors of the same byte size")
+    ms = ctypes.c_float()
+    _check(load().lds_copy_bandwidth(_ptr(dst), _ptr(src), nbytes, int(reps), _stream(stream), ctypes.byref(ms)))
+    return ms.value
 
 
 def lds_core_numbers(g, mode, alive=None, stream=None):

@@ -436,6 +436,34 @@ lds_status lds_loads(lds_graph g, lds_mode mode, float* r_out, double* r64_out, 
     API_CATCH
 }
 
+lds_status lds_fw_bounds(lds_graph g, lds_mode mode, double* lb_out, double* cert_gap_out) {
+    API_TRY
+    LDS_CHECK(g != nullptr, lds::ST_INVALID, "graph is NULL");
+    LDS_CHECK(mode == LDS_EDGE || mode == LDS_TRIANGLE || mode == LDS_CLIQUE4, lds::ST_INVALID,
+              "mode must be LDS_EDGE, LDS_TRIANGLE or LDS_CLIQUE4");
+    std::lock_guard<std::mutex> lk(g->mu);
+    const auto& f = g->g.fw[lds::mode_slot((int)mode)];
+    LDS_CHECK(f.ran, lds::ST_INVALID, "no Frank-Wolfe run for this mode");
+    LDS_CHECK((int)f.lb.size() == f.iters && (int)f.fval.size() == f.iters, lds::ST_INVALID,
+              "the last run did not compute the gap");
+    double fmin = 0.0, lbmax = 0.0;
+    for (int i = 0; i < f.iters; ++i) {
+        fmin = (i == 0) ? f.fval[i] : std::min(fmin, f.fval[i]);
+        lbmax = (i == 0) ? f.lb[i] : std::max(lbmax, f.lb[i]);
+        if (lb_out) lb_out[i] = f.lb[i];
+        if (cert_gap_out) cert_gap_out[i] = fmin - lbmax;
+    }
+    API_CATCH
+}
+
+lds_status lds_copy_bandwidth(void* dst, const void* src, size_t bytes, int32_t reps, void* hip_stream,
+                              float* ms_out) {
+    API_TRY
+    LDS_CHECK(ms_out != nullptr, lds::ST_INVALID, "ms_out must not be NULL");
+    *ms_out = lds::copy_bandwidth(dst, src, bytes, reps, (hipStream_t)hip_stream);
+    API_CATCH
+}
+
 lds_status lds_core_numbers(lds_graph g, lds_mode mode, const uint8_t* alive, int64_t* core_out, void* hip_stream) {
     API_TRY
     LDS_CHECK(g != nullptr, lds::ST_INVALID, "graph is NULL");

@@ -448,6 +448,7 @@ void batch_run(Batch& b, hipStream_t s) {
         f.timed = false;
         f.gap.clear();
         f.lb.clear();
+        f.fval.clear();
         g.sg[mode == 2 ? 0 : 1].valid = false;
     }
     b.runs++;

@@ -167,7 +167,7 @@ __device__ inline Slot<4> load_slot<4>(const int32_t* __restrict__ py, int64_t s
 #define LDS_SWEEP_THREADS 1024
 #endif
 #ifndef LDS_SWEEP_CACHE
-#define LDS_SWEEP_CACHE 65536
+#define LDS_SWEEP_CACHE 77824
 #endif
 #ifndef LDS_SWEEP_WG_PER_CU
 #define LDS_SWEEP_WG_PER_CU 1
@@ -836,6 +836,7 @@ void fw_prepare(Graph& g, int mode, int iters, hipStream_t s) {
 void fw_gap_from_sums(FwState& f, int mode, int iters, const uint64_t* sums) {
     f.gap.assign(iters, 0.0);
     f.lb.assign(iters, 0.0);
+    f.fval.assign(iters, 0.0);
     for (int i = 1; i <= iters; ++i) {
         const u128 S = ((u128)sums[4 * (i - 1) + 1] << 64) | sums[4 * (i - 1)];
         const u128 M = ((u128)sums[4 * (i - 1) + 3] << 64) | sums[4 * (i - 1) + 2];
@@ -846,6 +847,7 @@ void fw_gap_from_sums(FwState& f, int mode, int iters, const uint64_t* sums) {
         const long double gap = 2.0L * (long double)num / (LD * LD);
         f.gap[i - 1] = (double)gap;
         f.lb[i - 1] = (double)((long double)S / (LD * LD) - gap);
+        f.fval[i - 1] = (double)((long double)S / (LD * LD));
     }
 }
 
@@ -886,6 +888,7 @@ void fw_run(Graph& g, int mode, int iters, bool want_gap, hipStream_t s) {
     f.timed = true;
     f.gap.clear();
     f.lb.clear();
+    f.fval.clear();
     if (want_gap && iters > 0) {
         std::vector<uint64_t> sums((size_t)iters * 4, 0);
         if (blocks > 0 && p.nrows > 0) {
@@ -985,6 +988,7 @@ void fw_run_noalloc(Graph& g, int mode, int iters, float* r32_dev, double* gap_h
     f.launches = any ? iters : 0;
     f.gap.clear();
     f.lb.clear();
+    f.fval.clear();
     if (n > 0 && r32_dev) {
         k_loads<<<grid_for(n, 256), 256, 0, s>>>(f.K[f.cur].p, g.orig_of.p, n, B, (double)denom(mode, iters), r32_dev,
                                                  nullptr);

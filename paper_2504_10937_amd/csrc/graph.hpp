@@ -128,7 +128,7 @@ struct FwState {
     DBuf<uint16_t> Q[2];         // 16-bit monotone codes of A (gathered first)
     DBuf<uint64_t> bits;         // iters * total_words decision words
     DBuf<uint64_t> partial;      // iters * blocks * 4 gap partial sums
-    std::vector<double> gap, lb; // per iteration, filled on request
+    std::vector<double> gap, lb, fval;  // per iteration, filled on request: gap, lower bound, sum r^2 at r^(i-1)
     hipEvent_t ev[2] = {nullptr, nullptr};  // around the sweep launches of the last run
     int launches = 0;
     bool ran = false;            // keys hold the result of a completed run of `iters` iterations
@@ -241,6 +241,9 @@ void fw_run(Graph& g, int mode, int iters, bool want_gap, hipStream_t s);
 // fw_run without any device allocation (lds_frank_wolfe_noalloc): the FW
 // state must already be sized for iters; gap scratch from the device array
 void fw_run_noalloc(Graph& g, int mode, int iters, float* r32_dev, double* gap_host, hipStream_t s);
+
+// copy.hip: mean GPU ms of one 16-byte streaming copy of `bytes` (reps timed copies)
+float copy_bandwidth(void* dst, const void* src, size_t bytes, int reps, hipStream_t s);
 void fw_loads(const Graph& g, int mode, float* r32_dev, double* r64_host, uint64_t* A_host, hipStream_t s);
 void fw_splits(const Graph& g, int mode, int32_t* verts_host, uint64_t* num_host, hipStream_t s);
 

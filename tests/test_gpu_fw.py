@@ -190,3 +190,31 @@ def test_overflow_is_reported():
     with pytest.raises(lds.LdsError) as e:
         lds.lds_frank_wolfe(g, 2, 2_000_000)
     assert e.value.status == 4
+
+
+@pytest.mark.parametrize("mode", [2, 3])
+def test_fw_bounds_certified_gap(mode):
+    """Row a6's bounds: LB_i (a lower bound on the optimum of Eq. cp / Eq.
+    trcp) equals the oracle's, the certified gap Gamma_i = min_{j<=i} f_j -
+    max_{j<=i} LB_j is non-negative and non-increasing, and both bracket the
+    exact optimum f* = sum phi^2 from the oracle's decomposition (Thm. 1 /
+    Thm. cp): LB_i <= f* <= f_i and min_{j<=i} f_j - f* <= Gamma_i."""
+    from fractions import Fraction
+    n, s, d, _, iters, _ = synth.workload("lds_small")
+    announce("fw bounds", mode, iters)
+    G = oracle.Graph(n, s, d)
+    g = lds.lds_create_graph(n, s, d)
+    out = lds.lds_frank_wolfe(g, mode, iters, want_gap=True)
+    lb, cg = lds.lds_fw_bounds(g, mode)
+    ref = oracle.fw_exact(G, mode, iters, with_split=False)
+    f = ref["lb"] + ref["gap"]
+    scale = max(1.0, float(np.abs(f).max()))
+    np.testing.assert_allclose(lb, ref["lb"], rtol=1e-12, atol=1e-12 * scale)
+    want = np.minimum.accumulate(f) - np.maximum.accumulate(ref["lb"])
+    np.testing.assert_allclose(cg, want, rtol=0, atol=1e-10 * scale)
+    assert (cg >= -1e-10 * scale).all() and (np.diff(cg) <= 1e-10 * scale).all()
+    pn, pd = oracle.decompose(G, mode)
+    fstar = float(sum(Fraction(int(a), int(b)) ** 2 for a, b in zip(pn, pd)))
+    assert (lb <= fstar + 1e-9 * scale).all() and (f >= fstar - 1e-9 * scale).all()
+    assert (np.minimum.accumulate(f) - fstar <= cg + 1e-9 * scale).all()
+    g.destroy()
