@@ -227,7 +227,10 @@ def bench_clique4(lds, torch, synth, name):
                          "alg_bytes_per_launch": alg, "kernel": "k_fw_sweep<4>"}}
 
 
-def _serve_run(lds, np, srv, gs, pool_n, seconds, qps, seed, tag0):
+def _serve_run(lds, np, srv, gs, seconds, qps, seed, tag0, keep=0):
+    """Offer a Poisson stream of `qps` queries per second for `seconds`; wait
+    for all of them.  keep: return the result sets of the first `keep`
+    queries (by position in the stream) for the identity check."""
     import synth
     q = synth.queries(int(seconds * qps * 1.5) + 16, qps=qps, pool=len(gs), kmax=10, seed=seed)
     ta = q["t_arrive"]
@@ -247,16 +250,24 @@ def _serve_run(lds, np, srv, gs, pool_n, seconds, qps, seed, tag0):
     lat = np.array([c["t_done"] - c["t_arrive"] for c in done])
     span = max(c["t_done"] for c in done) - base
     errs = sum(c["status"] != 0 for c in done)
-    return {"offered_qps": qps, "arrival_window_s": seconds, "queries": n, "errors": errs,
-            "completed_per_s": n / span, "p50_ms": float(np.percentile(lat, 50) * 1e3),
-            "p99_ms": float(np.percentile(lat, 99) * 1e3), "max_ms": float(lat.max() * 1e3)}
+    res = {"offered_qps": qps, "arrival_window_s": seconds, "queries": n, "errors": errs,
+           "completed_per_s": n / span, "p50_ms": float(np.percentile(lat, 50) * 1e3),
+           "p99_ms": float(np.percentile(lat, 99) * 1e3), "max_ms": float(lat.max() * 1e3)}
+    kept = {c["tag"] - tag0: c["sets"] for c in done if c["tag"] - tag0 < keep}
+    return res, q, kept
 
 
-def bench_serving(lds, torch, synth, np, seconds, qps, low_qps):
+def bench_serving(lds, torch, synth, np, seconds, qps, ladder, plain_sample, p99_bound_ms=2000.0):
     """The serving workload: a resident pool of 64 graphs (pool member g,
     seed 5 + g, graph 0 pinned at n = 2M), Poisson arrivals, graph uniform
     over the pool, LDS / LTDS half and half (100 / 200 FW iterations), k
-    uniform in 1..10.  Latency = completion - arrival on the server clock."""
+    uniform in 1..10.  Latency = completion - arrival on the server clock.
+    Reported: the offered load for `seconds` after a warm-up; the highest
+    offered rate of the ladder whose completions keep up (>= 95% of the
+    offered rate) with p99 within the bound; and the plain baseline: the
+    first `plain_sample` queries of the offered stream through lds_topk one
+    at a time on the same resident graphs, with their results compared to the
+    served ones."""
     log("serving: building the pool")
     pool = [synth.pool_member(i) for i in range(64)]
     gs = [lds.lds_create_graph(*p) for p in pool]
@@ -265,7 +276,7 @@ def bench_serving(lds, torch, synth, np, seconds, qps, low_qps):
     torch.cuda.synchronize()
     srv = lds.lds_server_create(0, max_slots=64, workers=12)
     # warm-up: one query per (graph, mode), so that each graph's resident
-    # state (FW buffers, host adjacency and core numbers) exists
+    # host data (adjacency, core numbers) exists
     for i, g in enumerate(gs):
         for m in (2, 3):
             lds.lds_server_submit(srv, g, m, 3, 100 if m == 2 else 200, 10 ** 9 + 2 * i + m)
@@ -275,16 +286,39 @@ def bench_serving(lds, torch, synth, np, seconds, qps, low_qps):
     res = {"pool_graphs": len(gs), "pool_vertices": int(sum(p[0] for p in pool)),
            "pool_edges": int(sum(len(p[1]) for p in pool))}
     log("serving: %g QPS for %g s" % (qps, seconds))
-    res["offered"] = _serve_run(lds, np, srv, gs, [p[0] for p in pool], seconds, qps, 5, 0)
+    res["offered"], stream, served = _serve_run(lds, np, srv, gs, seconds, qps, 5, 0, keep=plain_sample)
     log("serving: %s" % res["offered"])
-    if low_qps > 0:
-        res["sustained"] = _serve_run(lds, np, srv, gs, [p[0] for p in pool], max(seconds, 8.0), low_qps, 6, 10 ** 6)
-        log("serving: %s" % res["sustained"])
+    steps = []
+    for k, rate in enumerate(ladder):
+        r, _, _ = _serve_run(lds, np, srv, gs, 8.0, rate, 60 + k, 10 ** 6 * (k + 1))
+        steps.append(r)
+        log("serving ladder: %s" % r)
+    res["ladder"] = steps
+    ok = [r["offered_qps"] for r in steps
+          if r["completed_per_s"] >= 0.95 * r["offered_qps"] and r["p99_ms"] <= p99_bound_ms and r["errors"] == 0]
+    res["max_sustained_qps"] = max(ok) if ok else None
+    res["sustain_rule"] = "completions >= 95%% of offered and p99 <= %g ms over an 8 s arrival window" % p99_bound_ms
     st = lds.lds_server_stats(srv)
     res["batches"] = st["batches"]
     res["max_batch"] = st["max_batch"]
     res["peak_inflight_bytes"] = st["peak_inflight_bytes"]
     lds.lds_server_destroy(srv)
+    if plain_sample > 0:
+        m = min(plain_sample, res["offered"]["queries"])
+        same = True
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(m):
+            mode = int(stream["mode"][i])
+            sets = lds.lds_topk(gs[int(stream["graph"][i])], mode, int(stream["k"][i]), 100 if mode == 2 else 200)
+            mine = served.get(i)
+            same = same and mine is not None and len(mine) == len(sets) and all(
+                a[1] == b[1] and np.array_equal(a[0], b[0]) for a, b in zip(mine, sets))
+        tp = time.perf_counter() - t0
+        res["plain"] = {"queries": m, "queries_per_s": m / tp, "identical_to_served": bool(same),
+                        "how": "the offered stream's first queries, lds_topk one at a time on the resident graphs"}
+        res["served_vs_plain"] = res["offered"]["completed_per_s"] / (m / tp)
+        log("serving plain: %d queries at %.1f/s, identical %s" % (m, m / tp, same))
     for g in gs:
         g.destroy()
     return res
@@ -314,10 +348,12 @@ def main():
     ap.add_argument("--ltds", default="ltds_hk", help="triangle (LTDS) workload ('' to skip)")
     ap.add_argument("--topk", default="lds_large,ltds_hk", help="workloads timed end to end by lds_topk ('' to skip)")
     ap.add_argument("--clique4", default="clique4_pl", help="4-clique FW workload ('' to skip)")
-    ap.add_argument("--serve-seconds", type=float, default=5.0, help="arrival window of the serving run (0: skip)")
+    ap.add_argument("--serve-seconds", type=float, default=60.0, help="arrival window of the serving run (0: skip)")
     ap.add_argument("--serve-qps", type=float, default=200.0)
-    ap.add_argument("--serve-low-qps", type=float, default=25.0,
-                    help="second serving run at a load the server sustains (0: skip)")
+    ap.add_argument("--serve-ladder", default="50,100,150",
+                    help="offered rates (QPS) tried for the highest sustained load ('' to skip)")
+    ap.add_argument("--serve-plain", type=int, default=200,
+                    help="queries of the offered stream also run one at a time by lds_topk (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: the benchmark runs on one GPU only (one process, one MI355X); "
@@ -438,7 +474,8 @@ def main():
     if args.clique4:
         out["clique4"] = bench_clique4(lds, torch, synth, args.clique4)
     if args.serve_seconds > 0:
-        out["serving"] = bench_serving(lds, torch, synth, np, args.serve_seconds, args.serve_qps, args.serve_low_qps)
+        out["serving"] = bench_serving(lds, torch, synth, np, args.serve_seconds, args.serve_qps,
+                                       [float(x) for x in args.serve_ladder.split(",") if x], args.serve_plain)
     if not args.no_cpu_baseline:
         import oracle
         log("cpu baseline: oracle ingest (untimed)")

@@ -42,17 +42,28 @@ void set_last_error(const std::string& msg);
 void* dev_alloc(size_t bytes, hipStream_t s);
 void dev_free(void* p);
 
-// Owning device buffer (RAII); memory comes from dev_alloc.
+// Device buffer (RAII); memory comes from dev_alloc.  A buffer may instead
+// borrow another's memory (a per-query view of a resident graph): it is then
+// never freed through it, and its owner must outlive it.
 template <class T>
 struct DBuf {
     T* p = nullptr;
     size_t n = 0;
+    bool own = true;
     DBuf() = default;
     DBuf(const DBuf&) = delete;
     DBuf& operator=(const DBuf&) = delete;
-    DBuf(DBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DBuf(DBuf&& o) noexcept : p(o.p), n(o.n), own(o.own) { o.p = nullptr; o.n = 0; o.own = true; }
     DBuf& operator=(DBuf&& o) noexcept {
-        if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        if (this != &o) {
+            release();
+            p = o.p;
+            n = o.n;
+            own = o.own;
+            o.p = nullptr;
+            o.n = 0;
+            o.own = true;
+        }
         return *this;
     }
     ~DBuf() { release(); }
@@ -61,7 +72,18 @@ struct DBuf {
         n = count;
         p = count ? static_cast<T*>(dev_alloc(count * sizeof(T), s)) : nullptr;
     }
-    void release() { if (p) dev_free(p); p = nullptr; n = 0; }
+    void borrow(const DBuf& o) {
+        release();
+        p = o.p;
+        n = o.n;
+        own = false;
+    }
+    void release() {
+        if (p && own) dev_free(p);
+        p = nullptr;
+        n = 0;
+        own = true;
+    }
     size_t bytes() const { return n * sizeof(T); }
 };
 

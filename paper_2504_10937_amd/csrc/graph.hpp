@@ -187,6 +187,7 @@ struct Graph {
     FwState fw[3];               // indexed by mode_slot: edges, triangles, 4-cliques
     SgState sg[3];               // sort / prefix / stable groups of the last run per mode (edges, triangles)
     std::shared_ptr<HostCache> host;  // host copy of the adjacency, triangles and core numbers, built on first use
+    Graph* origin = nullptr;     // a per-query view: the resident graph whose device data it borrows
     hipStream_t stream = nullptr;
     size_t device_bytes() const;
     ~Graph();
@@ -198,6 +199,11 @@ void build_graph(Graph& g, int64_t n, int64_t npairs, const int32_t* src, const 
 void build_sweep_plan(SweepPlan& p, hipStream_t s, int64_t n_vertices = 0);  // needs h, nrows, nslots, rowptr, pay, rowid;
                                                                              // n_vertices > 0 allows the 2D heavy part (edges)
 void sort_rows(Graph& g, hipStream_t s);             // CSR rows ascending (triangle listing)
+// A per-query view of a resident graph: borrows every device array of g and
+// its sweep plans, with its own Frank-Wolfe and stable-group state and its
+// own sweep counters (zeroed on s), so that queries on one graph run at once.
+// g must outlive the view and must not be changed while it exists.
+std::unique_ptr<Graph> graph_view(Graph& g, hipStream_t s);
 
 // triangles.hip
 void list_triangles(Graph& g, hipStream_t s);

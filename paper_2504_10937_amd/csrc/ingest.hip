@@ -2,12 +2,12 @@
 // undirected simple graph), degree renumbering, symmetric CSR and the sweep
 // plan (hub rows, row-aligned chunks, word offsets and row-start flags) that
 // the Frank-Wolfe kernels stream over.
-#include <rocprim/device/device_segmented_radix_sort.hpp>
 
 #include "graph.hpp"
 
 #include <algorithm>
 #include <cstdlib>
+#include <type_traits>
 #include <vector>
 
 namespace lds {
@@ -188,6 +188,74 @@ __global__ void k_bitbase(const int64_t* rp, int64_t nrows, int64_t n_hub, const
         const int64_t c = (rp[r] - base) / kChunk;
         bitbase[r] = cwo[c] * 64 + (rp[r] - rp[chunk_row[c]]);
     }
+}
+
+// ------------------------------------------------------------- row sort
+// Every CSR row sorted ascending, by row length (rows are ordered by length,
+// descending, so each class is a range of rows): rows of at most S <= 64
+// slots by a bitonic network over S lanes of a wave (64 / S rows per wave);
+// rows of up to 4096 slots by one workgroup with a bitonic network in LDS;
+// longer rows by the library's radix sort of (row, column) keys.
+template <int S>
+__global__ void k_sort_rows_lanes(const int64_t* rp, int64_t r0, int64_t r1, int32_t* col) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * kT + threadIdx.x) >> 6;
+    const int64_t r = r0 + wave * (64 / S) + lane / S;
+    const int e = lane % S;
+    int64_t s0 = 0, len = 0;
+    if (r < r1) {
+        s0 = rp[r];
+        len = rp[r + 1] - s0;
+    }
+    int32_t x = (e < len) ? col[s0 + e] : INT32_MAX;
+#pragma unroll
+    for (int k = 2; k <= S; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const int32_t y = __shfl_xor(x, j, 64);
+            x = (((e & j) == 0) == ((e & k) == 0)) ? min(x, y) : max(x, y);
+        }
+    }
+    if (e < len) col[s0 + e] = x;
+}
+
+__global__ __launch_bounds__(256) void k_sort_rows_block(const int64_t* rp, int64_t r0, int32_t* col) {
+    __shared__ int32_t v[4096];
+    const int64_t r = r0 + blockIdx.x;
+    const int64_t s0 = rp[r];
+    const int len = (int)(rp[r + 1] - s0);
+    int P = 1;
+    while (P < len) P <<= 1;
+    for (int i = threadIdx.x; i < P; i += 256) v[i] = (i < len) ? col[s0 + i] : INT32_MAX;
+    __syncthreads();
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < P; i += 256) {
+                const int q = i ^ j;
+                if (q > i) {
+                    const int32_t a = v[i], b = v[q];
+                    if ((a > b) == ((i & k) == 0)) {
+                        v[i] = b;
+                        v[q] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < len; i += 256) col[s0 + i] = v[i];
+}
+
+// keys (row << 32 | column) of the slots of rows [0, r1) and back
+__global__ void k_row_keys(const int64_t* rp, int64_t r1, const int32_t* col, uint64_t* keys) {
+    for (int64_t r = blockIdx.x; r < r1; r += gridDim.x)
+        for (int64_t q = rp[r] + threadIdx.x; q < rp[r + 1]; q += kT)
+            keys[q - rp[0]] = ((uint64_t)r << 32) | (uint32_t)col[q];
+}
+
+__global__ void k_row_unkeys(const uint64_t* keys, int64_t n, int32_t* col) {
+    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (i < n) col[i] = (int32_t)(uint32_t)keys[i];
 }
 
 // ------------------------------------------------------ heavy 2D part
@@ -673,26 +741,136 @@ void build_graph(Graph& g, int64_t n, int64_t npairs, const int32_t* src, const 
 
 void sort_rows(Graph& g, hipStream_t s) {
     if (g.col_sorted) return;
-    const int64_t ns = 2 * g.m;
+    const int64_t ns = 2 * g.m, n = g.n;
     if (ns > 0) {
-        // each row is a segment of keys below 2^vbits: a segmented radix sort
-        // (small segments sorted in registers / LDS, large ones by passes)
-        // instead of a global sort of (row, column) keys
-        LDS_CHECK(ns < (int64_t)UINT32_MAX, ST_OVERFLOW, "too many slots for the row sort");
-        DBuf<int32_t> out;
-        out.alloc(ns, s);
-        size_t bytes = 0;
-        LDS_HIP(rocprim::segmented_radix_sort_keys(nullptr, bytes, (const uint32_t*)g.col.p, (uint32_t*)out.p,
-                                                   (unsigned)ns, (unsigned)g.n, g.rowptr.p, g.rowptr.p + 1, 0u,
-                                                   (unsigned)g.vbits, s));
-        DBuf<uint8_t> tmp;
-        tmp.alloc(bytes > 0 ? bytes : 1, s);
-        LDS_HIP(rocprim::segmented_radix_sort_keys(tmp.p, bytes, (const uint32_t*)g.col.p, (uint32_t*)out.p,
-                                                   (unsigned)ns, (unsigned)g.n, g.rowptr.p, g.rowptr.p + 1, 0u,
-                                                   (unsigned)g.vbits, s));
-        std::swap(g.col, out);
+        // rows with more than T slots form a prefix (rows are ordered by length)
+        DBuf<unsigned long long> cnt;
+        cnt.alloc(1, s);
+        auto longer = [&](int64_t T) {
+            LDS_HIP(hipMemsetAsync(cnt.p, 0, sizeof(unsigned long long), s));
+            k_count_deg<<<grid_for(n, kT), kT, 0, s>>>(g.rowptr.p, n, T + 1, cnt.p);
+            LDS_HIP(hipGetLastError());
+            return (int64_t)d2h(cnt.p, s);
+        };
+        const int64_t rb = longer(4096), r64 = longer(64), r32 = longer(32), r16 = longer(16), r8 = longer(8),
+                      r4 = longer(4), r1 = longer(1);
+        if (rb > 0) {  // long rows: radix sort of (row, column) keys
+            int64_t nk = 0;
+            LDS_HIP(hipMemcpyAsync(&nk, g.rowptr.p + rb, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+            LDS_HIP(hipStreamSynchronize(s));
+            DBuf<uint64_t> keys, tmp;
+            keys.alloc(nk, s);
+            tmp.alloc(nk, s);
+            k_row_keys<<<(unsigned)std::min<int64_t>(rb, 65535), kT, 0, s>>>(g.rowptr.p, rb, g.col.p, keys.p);
+            LDS_HIP(hipGetLastError());
+            radix_sort_u64(keys.p, nullptr, nk, 32 + bits_for((uint64_t)rb), tmp.p, nullptr, s);
+            k_row_unkeys<<<grid_for(nk, kT), kT, 0, s>>>(keys.p, nk, g.col.p);
+            LDS_HIP(hipGetLastError());
+        }
+        if (r64 > rb) k_sort_rows_block<<<(unsigned)(r64 - rb), 256, 0, s>>>(g.rowptr.p, rb, g.col.p);
+        LDS_HIP(hipGetLastError());
+        auto lanes = [&](auto tag, int64_t a, int64_t b) {
+            constexpr int S = decltype(tag)::value;
+            if (b > a)
+                k_sort_rows_lanes<S><<<grid_for((b - a + 64 / S - 1) / (64 / S) * 64, kT), kT, 0, s>>>(
+                    g.rowptr.p, a, b, g.col.p);
+            LDS_HIP(hipGetLastError());
+        };
+        lanes(std::integral_constant<int, 64>(), r64, r32);
+        lanes(std::integral_constant<int, 32>(), r32, r16);
+        lanes(std::integral_constant<int, 16>(), r16, r8);
+        lanes(std::integral_constant<int, 8>(), r8, r4);
+        lanes(std::integral_constant<int, 4>(), r4, r1);
     }
     g.col_sorted = true;
+}
+
+namespace {
+
+void view_plan(SweepPlan& d, const SweepPlan& p, hipStream_t s) {
+    d.h = p.h;
+    d.nrows = p.nrows;
+    d.nslots = p.nslots;
+    d.rid = p.rid;
+    d.rp = p.rp;
+    d.py = p.py;
+    d.own_rid.borrow(p.own_rid);
+    d.own_rp.borrow(p.own_rp);
+    d.own_py.borrow(p.own_py);
+    d.own_tos.borrow(p.own_tos);
+    d.own_row_of.borrow(p.own_row_of);
+    d.n_big = p.n_big;
+    d.n_hub = p.n_hub;
+    d.hwo.borrow(p.hwo);
+    d.n_pieces = p.n_pieces;
+    d.hp_row.borrow(p.hp_row);
+    d.hp_off.borrow(p.hp_off);
+    if (p.hub_ctr.n) {  // written by every sweep: the view's own, zero between sweeps
+        d.hub_ctr.alloc(p.hub_ctr.n, s);
+        LDS_HIP(hipMemsetAsync(d.hub_ctr.p, 0, d.hub_ctr.bytes(), s));
+    }
+    d.n_chunks = p.n_chunks;
+    d.chunk_row.borrow(p.chunk_row);
+    d.cwo.borrow(p.cwo);
+    d.head.borrow(p.head);
+    d.chunk_words = p.chunk_words;
+    d.hub_words = p.hub_words;
+    d.total_words = p.total_words;
+    d.bitbase.borrow(p.bitbase);
+    const HeavyPlan& h = p.heavy;
+    HeavyPlan& e = d.heavy;
+    e.n_heavy = h.n_heavy;
+    e.R = h.R;
+    e.C = h.C;
+    e.P = h.P;
+    e.n_blocks = h.n_blocks;
+    e.n_parts = h.n_parts;
+    e.positions = h.positions;
+    e.word0 = h.word0;
+    e.seg.borrow(h.seg);
+    e.pay.borrow(h.pay);
+    e.csr.borrow(h.csr);
+    e.part_blk.borrow(h.part_blk);
+    e.part_j0.borrow(h.part_j0);
+    e.part_j1.borrow(h.part_j1);
+    e.part_lo.borrow(h.part_lo);
+    e.part_hi.borrow(h.part_hi);
+    e.blk_part.borrow(h.blk_part);
+    e.blk_row.borrow(h.blk_row);
+    e.row_blk.borrow(h.row_blk);
+    if (h.part_cnt.n) e.part_cnt.alloc(h.part_cnt.n, s);  // rewritten by every sweep
+}
+
+}  // namespace
+
+std::unique_ptr<Graph> graph_view(Graph& g, hipStream_t s) {
+    auto v = std::make_unique<Graph>();
+    v->n = g.n;
+    v->m = g.m;
+    v->n_nz = g.n_nz;
+    v->idbits = g.idbits;
+    v->vbits = g.vbits;
+    v->max_deg = g.max_deg;
+    v->orig_of.borrow(g.orig_of);
+    v->int_of.borrow(g.int_of);
+    v->deg.borrow(g.deg);
+    v->rowptr.borrow(g.rowptr);
+    v->col.borrow(g.col);
+    v->col_sorted = g.col_sorted;
+    view_plan(v->edge_plan, g.edge_plan, s);
+    v->T = g.T;
+    v->tri.borrow(g.tri);
+    v->tcount.borrow(g.tcount);
+    v->t_max = g.t_max;
+    if (g.T >= 0) view_plan(v->tri_plan, g.tri_plan, s);
+    v->Q4 = g.Q4;
+    v->q4.borrow(g.q4);
+    v->qcount.borrow(g.qcount);
+    v->q_max = g.q_max;
+    if (g.Q4 >= 0) view_plan(v->clique_plan, g.clique_plan, s);
+    v->origin = g.origin ? g.origin : &g;
+    v->stream = s;
+    return v;
 }
 
 Graph::~Graph() {

@@ -4,10 +4,12 @@
 //     arrival time; graphs stay resident (CSR, triangle list, FW buffers).
 //   * the scheduler thread admits queued queries in arrival order while the
 //     device-memory budget and the slot count allow (a query's footprint is
-//     the FW / stable-group state it adds to its graph), skipping queries
-//     whose (graph, mode) is busy with an earlier query; all queries admitted
-//     together run their Frank-Wolfe iterations in ONE batched launch (the
-//     persistent kernel of batch.hip), then go to the verification workers.
+//     the FW / stable-group state it adds to its graph); every admitted query
+//     works on its own view of its graph (the graph's device data borrowed,
+//     its own FW and stable-group state), so queries on one graph and mode run
+//     at once; all queries admitted together run their Frank-Wolfe
+//     iterations in ONE batched launch (the persistent kernel of batch.hip),
+//     then go to the verification workers.
 //   * worker threads run the rest of the top-k search (stable groups,
 //     pruning, exact verification, refinements) on their own streams, so the
 //     next batch's kernel overlaps with the verification of the previous one;
@@ -53,7 +55,6 @@ struct Server::Impl {
     std::condition_variable cv_sched, cv_work, cv_done;
     std::deque<SQuery> pending, verify;
     std::deque<SDone> done;
-    std::set<std::pair<lds_graph, int>> busy;
     size_t inflight = 0;
     int active = 0;
     bool stop = false;          // scheduler: admit nothing more
@@ -73,7 +74,6 @@ struct Server::Impl {
         d.t_admit = q.t_admit;
         d.t_done = now_s(t0);
         if (q.admitted) {
-            busy.erase({q.h, q.mode});
             inflight -= q.fp;
             --active;
         }
@@ -99,12 +99,6 @@ struct Server::Impl {
                         it = pending.erase(it);
                         continue;
                     }
-                    bool same = busy.count({it->h, it->mode}) > 0;
-                    for (const auto& a : adm) same = same || (a.h == it->h && a.mode == it->mode);
-                    if (same) {
-                        ++it;
-                        continue;
-                    }
                     size_t add = it->fp;
                     for (const auto& a : adm) add += a.fp;
                     if (inflight + add > budget) break;  // memory is granted in arrival order
@@ -117,7 +111,6 @@ struct Server::Impl {
             for (auto& q : adm) {
                 q.admitted = true;
                 q.t_admit = now_s(t0);
-                busy.insert({q.h, q.mode});
                 inflight += q.fp;
                 ++active;
             }
@@ -154,10 +147,6 @@ struct Server::Impl {
             }
             if (!adm.empty()) {
                 // one batched FW launch for everything admitted together
-                std::vector<lds_graph> hs;
-                for (auto& q : adm) hs.push_back(q.h);
-                std::sort(hs.begin(), hs.end());
-                hs.erase(std::unique(hs.begin(), hs.end()), hs.end());
                 std::string err;
                 int code = ST_OK;
                 const auto tb = std::chrono::steady_clock::now();
@@ -166,8 +155,10 @@ struct Server::Impl {
                 next_stream = (next_stream + 1) % kBatchStreams;
                 try {
                     // launched, not waited for: the workers wait on the event
-                    std::vector<std::unique_lock<std::mutex>> locks;
-                    for (lds_graph h : hs) locks.emplace_back(h->mu);
+                    for (auto& q : adm) {
+                        std::lock_guard<std::mutex> g(q.h->mu);
+                        q.view = graph_view(q.h->g, bs);
+                    }
                     fl->b.reset(new Batch);
                     Batch& b = *fl->b;
                     b.capture = false;
@@ -176,7 +167,7 @@ struct Server::Impl {
                     // launches (the whole GPU per iteration) instead
                     b.tune.max_kernel_cost = kServeKernelCost;
                     for (auto& q : adm) {
-                        b.gs.push_back(&q.h->g);
+                        b.gs.push_back(q.view.get());
                         b.modes.push_back(q.mode);
                         b.iters.push_back(q.iters);
                     }
@@ -235,9 +226,11 @@ struct Server::Impl {
             SDone d;
             try {
                 if (q.fw && q.fw->done) LDS_HIP(hipStreamWaitEvent(s, q.fw->done, 0));
-                std::lock_guard<std::mutex> g(q.h->mu);
-                // a query that was not in a batched launch runs its own FW here
-                topk_run(q.h->g, q.mode, q.k, q.iters, s, d.sets, d.st, q.fw != nullptr);
+                if (!q.view) {  // a query that was not in a batched launch runs its own FW here
+                    std::lock_guard<std::mutex> g(q.h->mu);
+                    q.view = graph_view(q.h->g, s);
+                }
+                topk_run(*q.view, q.mode, q.k, q.iters, s, d.sets, d.st, q.fw != nullptr);
                 d.status = ST_OK;
             } catch (const Error& e) {
                 d.status = e.code;
@@ -250,7 +243,8 @@ struct Server::Impl {
                 d.error = e.what();
             }
             if (s) (void)hipStreamSynchronize(s);
-            q.fw.reset();  // the batch's tables are freed with its last query
+            q.view.reset();  // the query's FW and stable-group state
+            q.fw.reset();    // the batch's tables are freed with its last query
             finish(q, std::move(d));
         }
         if (s) (void)hipStreamDestroy(s);

@@ -21,6 +21,7 @@ struct InFlight {
 
 struct SQuery {
     std::shared_ptr<InFlight> fw;  // the launch that computed this query's FW state
+    std::shared_ptr<Graph> view;   // the query's view of its graph (own FW / stable-group state)
     lds_graph h = nullptr;
     int mode = 2, k = 1, iters = 0;
     uint64_t tag = 0;

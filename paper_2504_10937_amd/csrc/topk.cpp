@@ -41,6 +41,8 @@
 #include "islds.hpp"
 #include "topk.hpp"
 
+#include <mutex>
+
 namespace lds {
 
 namespace {
@@ -1045,17 +1047,29 @@ void topk_run(Graph& g, int mode, int k, int iters, hipStream_t s, std::vector<T
     const int64_t n = g.n;
     if (n == 0) return;
     if (mode == 3 && g.T < 0) list_triangles(g, s);
-    // host data of the graph (built once, kept with the graph)
-    if (!g.host) {
-        auto hc = std::make_shared<HostCache>();
-        hc->h.load(g, mode, s);
-        hc->tri_loaded = (mode == 3);
-        g.host = hc;
-    } else if (mode == 3 && !g.host->tri_loaded) {
-        g.host->h.load(g, 3, s);
-        g.host->tri_loaded = true;
+    // host data of the graph (built once, kept with the resident graph; a
+    // per-query view shares its graph's): the adjacency, the triangles and
+    // the core numbers of this mode are set up under one lock, and only read
+    // afterwards, so that queries on one graph may run at once
+    std::shared_ptr<HostCache> hcp;
+    {
+        static std::mutex setup;
+        std::lock_guard<std::mutex> lk(setup);
+        Graph& hg = g.origin ? *g.origin : g;
+        if (!hg.host) {
+            auto hc = std::make_shared<HostCache>();
+            hc->h.load(g, mode, s);
+            hc->tri_loaded = (mode == 3);
+            hg.host = hc;
+        } else if (mode == 3 && !hg.host->tri_loaded) {
+            hg.host->h.load(g, 3, s);
+            hg.host->tri_loaded = true;
+        }
+        std::vector<int32_t>& core = hg.host->core[mode == 2 ? 0 : 1];
+        if (core.empty()) core = device_cores(g, mode, nullptr, s);
+        hcp = hg.host;
     }
-    HostCache& hc = *g.host;
+    HostCache& hc = *hcp;
     Ctx c(hc.h);
     c.g = &g;
     c.mode = mode;
@@ -1068,8 +1082,7 @@ void topk_run(Graph& g, int mode, int k, int iters, hipStream_t s, std::vector<T
     lap(&st.ms_copy);
     // bounds from core (tr-core) numbers
     {
-        std::vector<int32_t>& core = hc.core[mode == 2 ? 0 : 1];
-        if (core.empty()) core = device_cores(g, mode, nullptr, s);
+        const std::vector<int32_t>& core = hc.core[mode == 2 ? 0 : 1];
         c.lo.resize(n);
         c.hi.resize(n);
         for (int64_t u = 0; u < n; ++u) {

@@ -128,13 +128,19 @@ def test_admission_by_memory_budget():
     assert done[999]["status"] == 2
 
 
-def test_same_graph_queries_serialise():
-    announce("server same graph")
-    inputs = pool(1, start=60)
+@pytest.mark.parametrize("big", [False, True])
+def test_same_graph_queries_run_at_once(big):
+    """Queries on one graph and mode run at once, each on its own view of the
+    graph (its own FW and stable-group state): results equal lds_topk run
+    alone, and queries on the same (graph, mode) overlap in time.  big: a
+    graph whose FW runs on the worker's own launches instead of the batched
+    kernel."""
+    announce("server same graph", big)
+    inputs = [synth.powerlaw_planted(20000, 2.2, 10.0, 6, 20, 80, 0.4, seed=63)] if big else pool(1, start=60)
     g = lds.lds_create_graph(*inputs[0])
-    queries = {t: (0, 2 + t % 2, 1 + t % 10, 20 + 3 * t) for t in range(12)}
+    queries = {t: (0, 2 + t % 2, 1 + t % 10, 20 + 3 * t) for t in range(16)}
     ref = alone(inputs, queries)
-    srv = lds.lds_server_create(0, max_slots=16, workers=4)
+    srv = lds.lds_server_create(0, max_slots=16, workers=6)
     for tag, (gi, mode, k, it) in queries.items():
         lds.lds_server_submit(srv, g, mode, k, it, tag)
     done = drain(srv, len(queries))
@@ -142,6 +148,12 @@ def test_same_graph_queries_serialise():
     for tag, c in done.items():
         assert c["status"] == 0, c["error"]
         same(c["sets"], ref[tag])
+    # some pair of queries on the same (graph, mode) was in flight together
+    spans = [(c["t_admit"], c["t_done"], queries[t][1]) for t, c in done.items()]
+    assert any(a0 < b1 and b0 < a1 and ma == mb
+               for i, (a0, a1, ma) in enumerate(spans) for (b0, b1, mb) in spans[i + 1:])
+    # the graph itself is untouched and usable
+    same(lds.lds_topk(g, 2, 3, 30), alone(inputs, {0: (0, 2, 3, 30)})[0])
 
 
 def test_destroy_with_queued_queries():
