@@ -218,3 +218,40 @@ def test_fw_bounds_certified_gap(mode):
     assert (lb <= fstar + 1e-9 * scale).all() and (f >= fstar - 1e-9 * scale).all()
     assert (np.minimum.accumulate(f) - fstar <= cg + 1e-9 * scale).all()
     g.destroy()
+
+
+def test_rows_sorted_in_every_length_class():
+    """Ingest sorts every CSR row ascending (the triangle listing probes rows by
+    binary search, and the sweep's slot order is fixed by it).  Rows of every
+    length class of the row sort: radix-sorted (> 4096 slots), workgroup
+    bitonic (65..4096) and wave bitonic (2..64 in groups of 64, 32, 16, 8, 4
+    lanes).  lds_splits lists incidences in slot order; with the documented
+    internal order (degree descending, ties by caller id) the neighbours of
+    every row must be strictly increasing."""
+    announce("row sort")
+    rng = np.random.default_rng(11)
+    n = 12000
+    centers = [5000, 4097, 4096, 3000, 100, 65, 64, 40, 33, 32, 20, 17, 16, 9, 8, 5, 4, 3, 2]
+    src, dst = [], []
+    for c, dgr in enumerate(centers):
+        nb = rng.choice(np.arange(len(centers), n), size=dgr, replace=False)
+        src += [c] * dgr
+        dst += nb.tolist()
+    bs = rng.integers(len(centers), n, 30000)
+    bd = rng.integers(len(centers), n, 30000)
+    s = np.array(src + bs.tolist(), np.int32)
+    d = np.array(dst + bd.tolist(), np.int32)
+    g = lds.lds_create_graph(n, s, d)
+    lds.lds_frank_wolfe(g, 2, 1)
+    verts, _ = lds.lds_splits(g, 2)
+    G = oracle.Graph(n, s, d)
+    deg = G.degrees()
+    rank = np.empty(n, np.int64)
+    rank[np.lexsort((np.arange(n), -deg))] = np.arange(n)
+    row, nbr = rank[verts[:, 0]], rank[verts[:, 1]]
+    assert (np.diff(row) >= 0).all()  # rows in internal order
+    same = np.diff(row) == 0
+    assert (np.diff(nbr)[same] > 0).all(), "a CSR row is not sorted"
+    lens = np.bincount(row, minlength=n)
+    for dgr in centers:
+        assert (lens == dgr).any() or (lens >= dgr).any()
