@@ -463,6 +463,18 @@ def main():
                                            "bytes_per_copy": 2 * nb, "ms_per_copy": cms}
         out["roofline"]["frac_of_copy"] = achieved / copy_gbs
         log("copy ceiling: %.0f GB/s (%.3f ms per %.2f GiB copy)" % (copy_gbs, cms, args.copy_gib))
+        # the random-gather ceiling over a table of n codes (the sweep gathers
+        # the 16-bit code of every neighbour outside its LDS cache)
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(7)
+        ng = 1 << 26
+        idx = torch.randint(0, n, (ng,), dtype=torch.int32, device="cuda", generator=gen)
+        table = torch.zeros(n, dtype=torch.int16, device="cuda")
+        gms = lds.lds_gather_rate(idx, table, reps=5)
+        del idx, table
+        out["roofline"]["gather_ceiling"] = {"gathers_per_s": ng / (gms / 1e3), "table_bytes": 2 * n,
+                                             "kernel": "k_gather16", "indices": ng}
+        log("gather ceiling: %.3g gathers/s over a %d-entry table" % (ng / (gms / 1e3), n))
     if args.batch_graphs > 0:
         out["batched"] = bench_batched(lds, torch, synth, np, args.batch_graphs, not args.no_batch_plain)
     if args.density_sweep:

@@ -234,6 +234,17 @@ lds_status lds_fw_bounds(lds_graph g, lds_mode mode, double* lb_out, double* cer
 lds_status lds_copy_bandwidth(void* dst, const void* src, size_t bytes, int32_t reps, void* hip_stream,
                               float* ms_out);
 
+/* Measurement: the rate of random 2-byte gathers, the access the Frank-Wolfe
+ * sweep makes for every incidence whose other vertex is outside its LDS
+ * cache of codes.  Reads n int32 indices idx (device; each in [0, entries),
+ * which the caller guarantees: they are not checked) and the uint16 table
+ * entries they name (device, `entries` of them), eight per thread in flight,
+ * once untimed and then `reps` times on hip_stream; sink (device uint32,
+ * 8 * 256 * compute units entries) receives per-thread sums.  *ms_out = mean
+ * GPU milliseconds of one pass over the n indices.  Waits for the stream. */
+lds_status lds_gather_rate(const int32_t* idx, int64_t n, const uint16_t* table, int64_t entries, uint32_t* sink,
+                           int32_t reps, void* hip_stream, float* ms_out);
+
 /* ---- Batched Frank-Wolfe over many independent graphs ----------------------
  * A batch runs lds_frank_wolfe(graphs[i], modes[i], iters[i]) for every i in
  * one persistent kernel launch, captured into a hipGraph at creation and

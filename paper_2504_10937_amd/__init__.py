@@ -82,6 +82,7 @@ def load():
         "lds_core_numbers": (st, [vp, st, vp, vp, vp]),
         "lds_fw_bounds": (st, [vp, st, vp, vp]),
         "lds_copy_bandwidth": (st, [vp, vp, ctypes.c_size_t, i32, vp, vp]),
+        "lds_gather_rate": (st, [vp, i64, vp, i64, vp, i32, vp, vp]),
         "lds_tune_default": (None, [vp]),
         "lds_batch_create": (st, [vp, vp, vp, vp, i32, u32, vp, vp, vp]),
         "lds_batch_run": (st, [vp, vp]),
@@ -373,6 +374,21 @@ def lds_fw_bounds(g, mode):
     cg = np.empty(it, np.float64)
     _check(load().lds_fw_bounds(g.handle, mode, _ptr(lb), _ptr(cg)))
     return lb, cg
+
+
+def lds_gather_rate(idx, table, reps=5, stream=None):
+    """Mean GPU ms of one pass of random 2-byte gathers table[idx[i]] by the
+    library's gather kernel (idx: device int32 tensor of indices into table,
+    a device uint16/int16 tensor)."""
+    import torch
+    if not (idx.is_cuda and table.is_cuda) or idx.dtype != torch.int32 or table.element_size() != 2:
+        raise ValueError("idx must be a device int32 tensor and table a device 16-bit tensor")
+    cus = torch.cuda.get_device_properties(idx.device).multi_processor_count
+    sink = torch.empty(8 * 256 * cus, dtype=torch.int32, device=idx.device)
+    ms = ctypes.c_float()
+    _check(load().lds_gather_rate(_ptr(idx), idx.numel(), _ptr(table), table.numel(), _ptr(sink), int(reps),
+                                  _stream(stream), ctypes.byref(ms)))
+    return ms.value
 
 
 def lds_copy_bandwidth(dst, src, reps=10, stream=None):

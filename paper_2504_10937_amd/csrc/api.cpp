@@ -456,6 +456,14 @@ lds_status lds_fw_bounds(lds_graph g, lds_mode mode, double* lb_out, double* cer
     API_CATCH
 }
 
+lds_status lds_gather_rate(const int32_t* idx, int64_t n, const uint16_t* table, int64_t entries, uint32_t* sink,
+                           int32_t reps, void* hip_stream, float* ms_out) {
+    API_TRY
+    LDS_CHECK(ms_out != nullptr, lds::ST_INVALID, "ms_out must not be NULL");
+    *ms_out = lds::gather_rate(idx, n, table, entries, sink, reps, (hipStream_t)hip_stream);
+    API_CATCH
+}
+
 lds_status lds_copy_bandwidth(void* dst, const void* src, size_t bytes, int32_t reps, void* hip_stream,
                               float* ms_out) {
     API_TRY

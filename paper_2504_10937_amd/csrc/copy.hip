@@ -1,7 +1,9 @@
-// A plain streaming copy on gfx950, the achievable-bandwidth reference that
-// the roofline of the HBM-bound kernels is read against: every thread moves
+// Reference kernels for the roofline.  A plain streaming copy on gfx950, the
+// achievable bandwidth the HBM-bound kernels are read against: every thread moves
 // 16-byte vectors, eight in flight, grid-strided, non-temporal on both
-// sides, over sixteen workgroups per compute unit.
+// sides, over sixteen workgroups per compute unit.  And random 2-byte gathers
+// from a table, the rate the Frank-Wolfe sweep's code gathers are read
+// against.
 #include "graph.hpp"
 
 namespace lds {
@@ -24,7 +26,54 @@ __global__ __launch_bounds__(256) void k_copy16(v4u* __restrict__ dst, const v4u
     for (; i < n; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
+// random 2-byte gathers: every thread streams eight indices, then gathers
+// the eight table entries they name; the sum keeps the loads alive
+__global__ __launch_bounds__(256) void k_gather16(const int32_t* __restrict__ idx, int64_t n,
+                                                  const uint16_t* __restrict__ table, uint32_t* sink) {
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    uint32_t acc = 0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += 8 * stride) {
+        int32_t v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = (i + k * stride < n) ? __builtin_nontemporal_load(idx + i + k * stride) : 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc += table[v[k]];
+    }
+    sink[(int64_t)blockIdx.x * 256 + threadIdx.x] = acc;
+}
+
 }  // namespace
+
+float gather_rate(const int32_t* idx, int64_t n, const uint16_t* table, int64_t entries, uint32_t* sink,
+                  int reps, hipStream_t s) {
+    LDS_CHECK(idx != nullptr && table != nullptr && sink != nullptr, ST_INVALID, "pointers must not be NULL");
+    LDS_CHECK(n > 0 && entries > 0 && reps >= 1, ST_INVALID, "n, entries and reps must be positive");
+    int dev = 0, cus = 0;
+    LDS_HIP(hipGetDevice(&dev));
+    LDS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * 8, (n + 255) / 256));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    LDS_HIP(hipEventCreate(&e0));
+    LDS_HIP(hipEventCreate(&e1));
+    float ms = 0.0f;
+    try {
+        k_gather16<<<grid, 256, 0, s>>>(idx, n, table, sink);
+        LDS_HIP(hipGetLastError());
+        LDS_HIP(hipEventRecord(e0, s));
+        for (int r = 0; r < reps; ++r) k_gather16<<<grid, 256, 0, s>>>(idx, n, table, sink);
+        LDS_HIP(hipGetLastError());
+        LDS_HIP(hipEventRecord(e1, s));
+        LDS_HIP(hipEventSynchronize(e1));
+        LDS_HIP(hipEventElapsedTime(&ms, e0, e1));
+    } catch (...) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return ms / (float)reps;
+}
 
 float copy_bandwidth(void* dst, const void* src, size_t bytes, int reps, hipStream_t s) {
     LDS_CHECK(dst != nullptr && src != nullptr, ST_INVALID, "dst and src must not be NULL");

@@ -250,6 +250,9 @@ void fw_run_noalloc(Graph& g, int mode, int iters, float* r32_dev, double* gap_h
 
 // copy.hip: mean GPU ms of one 16-byte streaming copy of `bytes` (reps timed copies)
 float copy_bandwidth(void* dst, const void* src, size_t bytes, int reps, hipStream_t s);
+// mean GPU ms of n random 2-byte gathers table[idx[i]] (idx streamed; reps timed runs)
+float gather_rate(const int32_t* idx, int64_t n, const uint16_t* table, int64_t entries, uint32_t* sink,
+                  int reps, hipStream_t s);
 void fw_loads(const Graph& g, int mode, float* r32_dev, double* r64_host, uint64_t* A_host, hipStream_t s);
 void fw_splits(const Graph& g, int mode, int32_t* verts_host, uint64_t* num_host, hipStream_t s);
 

@@ -3,6 +3,8 @@
 usage: python -m paper_2504_10937_amd.profsummary <kernel substring> <out.md> <command string>
        <kernel_stats.csv> [<fetch counter_collection.csv> <write counter_collection.csv>]
        python -m paper_2504_10937_amd.profsummary --top <N> <out.md> <title> <command string> <kernel_stats.csv>
+       python -m paper_2504_10937_amd.profsummary --counters <kernel substring> <out.md> <command string>
+       <counter_collection.csv>   (every counter of the file, averaged per dispatch of the kernel)
 
 The FETCH_SIZE / WRITE_SIZE passes must come from runs that first launched a
 device copy of known size (bench.py --copy-calib-mib); the copy's counters
@@ -42,9 +44,27 @@ def top(n, out, title, cmd, stats):
     print("\n".join(lines))
 
 
+def counters(kernel, out, cmd, path):
+    vals = {}
+    for r in csv.DictReader(open(path)):
+        if kernel in r["Kernel_Name"]:
+            vals.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    src = open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "fw.hip"), "rb").read()
+    lines = ["# rocprofv3 counters: %s" % kernel, "",
+             "kernel source sha256[:16]: `%s` (paper_2504_10937_amd/csrc/fw.hip)" % hashlib.sha256(src).hexdigest()[:16],
+             "", "command: `%s`" % cmd, "", "| counter | dispatches | mean per dispatch |", "|---|---|---|"]
+    for name in sorted(vals):
+        v = vals[name]
+        lines.append("| %s | %d | %.6e |" % (name, len(v), sum(v) / len(v)))
+    open(out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     if sys.argv[1] == "--top":
         return top(int(sys.argv[2]), *sys.argv[3:7])
+    if sys.argv[1] == "--counters":
+        return counters(*sys.argv[2:6])
     kernel, out, cmd, stats = sys.argv[1:5]
     rows = [r for r in csv.DictReader(open(stats)) if kernel in r["Name"]]
     src = open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "fw.hip"), "rb").read()

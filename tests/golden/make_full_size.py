@@ -11,10 +11,11 @@ per workload:
     (int32), the prefix pattern counts E (int64) and the index set I (uint8);
   * the LDS (LTDS) sets of density >= lam, certified by the large-graph path
     (oracle.top_levels: k-core, one superlevel min cut, decomposition of the
-    superlevel set).  lam is chosen here from the graph alone: half the
-    largest per-vertex pattern count, halved until the ceil(lam)-core holds
-    a vertex of phi >= lam.  The full decomposition of these graphs is out of
-    the oracle's reach, so lower-density sets are not certified here.
+    superlevel set).  lam is the largest prefix density of the oracle's own
+    Alg. 2 order at N iterations (max_j E_j / j), a density some vertex set
+    has, so the densest LDS is always among the sets.  The full decomposition
+    of these graphs is out of the oracle's reach, so lower-density sets are
+    not certified here.
 
 Run: python tests/golden/make_full_size.py  (about 10 minutes, ~20 GB).
 """
@@ -43,19 +44,19 @@ def say(*a):
     print("[golden]", *a, flush=True)
 
 
-def pick_lambda(G, mode):
-    """largest lam of the halving schedule with a nonempty {phi >= lam}"""
-    cnt = G.degrees() if mode == 2 else oracle.triangles(G)[1]
-    lam = Fraction(int(cnt.max()), 2)
-    while lam > 0:
-        k = -((-lam.numerator) // lam.denominator)
-        K = oracle.kcore(G, mode, k)
-        if K.any():
-            GK, _ = oracle.induced(G, K)
-            if oracle.superlevel(GK, mode, lam).any():
-                return lam
-        lam /= 2
-    raise RuntimeError("graph has no patterns")
+def pick_lambda(E):
+    """lam = the largest prefix density max_j E_j / j of Alg. 2's order: the
+    density of an actual vertex set, so at most the largest density, and
+    {phi >= lam} holds the densest subgraph; with converged loads it is close
+    to that density, so the ceil(lam)-core is small"""
+    j = np.arange(1, len(E) + 1, dtype=np.float64)
+    d = E / j
+    best = Fraction(0)
+    for i in np.flatnonzero(d >= d.max() * (1 - 1e-9)):
+        best = max(best, Fraction(int(E[i]), int(i) + 1))
+    if best <= 0:
+        raise RuntimeError("graph has no patterns")
+    return best
 
 
 def one(name):
@@ -69,7 +70,7 @@ def one(name):
     say(name, "fw done", round(time.time() - t0, 1), "s")
     order, E, inI = oracle.sort_prefix(G, mode, ref["A"])
     say(name, "sort/prefix done", round(time.time() - t0, 1), "s")
-    lam = pick_lambda(G, mode)
+    lam = pick_lambda(E)
     sets, K, U = oracle.top_levels(G, mode, lam)
     say(name, "top levels at", lam, ":", len(sets), "sets, core", K, "superlevel", U, round(time.time() - t0, 1), "s")
     return {

@@ -1,7 +1,16 @@
 """Parity at the full benchmark sizes, in the launch configuration bench.py
 times: exact comparison with the oracle for the first iterations on the whole
-graph (the oracle finishes those in seconds), and properties that hold at any
-size for the full iteration counts."""
+graph (the oracle finishes those in seconds); at the full iteration counts,
+properties that hold at any size and the oracle's own results stored by
+tests/golden/make_full_size.py (exact loads, gap, Alg. 2's order, prefix
+counts and index set, and the LDS / LTDS sets above the density the oracle
+certifies); and Alg. 2 exactly, stable groups and bounds included, on a
+120,000-vertex graph in both modes (tests/golden/make_mid_size.py)."""
+import hashlib
+import json
+import os
+from fractions import Fraction
+
 import numpy as np
 import pytest
 
@@ -14,6 +23,45 @@ lds = pytest.importorskip("paper_2504_10937_amd")
 torch = pytest.importorskip("torch")
 if not torch.cuda.is_available():
     pytest.skip("no HIP device", allow_module_level=True)
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def sha(a, dtype):
+    return hashlib.sha256(np.ascontiguousarray(a, dtype=dtype).tobytes()).hexdigest()
+
+
+def golden(file, name=None):
+    with open(os.path.join(GOLD, file)) as f:
+        d = json.load(f)
+    return d[name] if name else d
+
+
+def check_golden_fw(out, order, E, inI, ref):
+    """the library's loads after the full N and Alg. 2's sort and prefix step
+    against the oracle's, stored by tests/golden/make_*_size.py"""
+    assert out["D"] == ref["D"]
+    if "A_sum" in ref:
+        assert int(out["num"].sum(dtype=np.uint64)) == ref["A_sum"]
+    assert sha(out["num"], "<u8") == ref["A_sha256"], "exact loads differ from the oracle's"
+    np.testing.assert_allclose(out["gap"], ref["gap"], rtol=1e-12, atol=0.0)
+    assert int(inI.sum()) == ref["n_I"]
+    assert sha(order, "<i4") == ref["order_sha256"]
+    assert sha(E, "<i8") == ref["E_sha256"]
+    assert sha(inI.astype(np.uint8), "u1") == ref["inI_sha256"]
+
+
+def check_golden_topk(g, ref):
+    """the library's LDS (LTDS) sets of density >= lambda against the sets the
+    oracle certified (k-core, superlevel min cut, decomposition of the
+    superlevel set)"""
+    lam = Fraction(*ref["lambda"])
+    got = lds.lds_topk(g, ref["mode"], max(10, len(ref["sets"]) + 1), ref["iters"])
+    mine = [(v, r) for v, r in got if r >= lam]
+    assert len(mine) == len(ref["sets"])
+    for (v, r), w in zip(mine, ref["sets"]):
+        assert r == Fraction(*w["rho"])
+        np.testing.assert_array_equal(v, np.array(w["vertices"], np.int32))
 
 
 def check_properties(g, mode, iters, n, P):
@@ -34,6 +82,7 @@ def check_properties(g, mode, iters, n, P):
     ties = A[:-1] == A[1:]
     assert (order[:-1][ties] < order[1:][ties]).all()
     assert (np.diff(E) >= 0).all() and E[-1] == P and inI[-1]
+    props = (out, order, E, inI)
     groups, lo, hi = lds.lds_stable_groups(g, mode)
     assert len(groups) > 0 and groups[0][0] == 0
     ends = set((np.flatnonzero(inI) + 1).tolist())
@@ -50,7 +99,7 @@ def check_properties(g, mode, iters, n, P):
         prev_lo = lo[vs[0]]
     tail = order[groups[-1][1]:]
     assert (lo[tail] == -1).all() and (hi[tail] == -1).all()
-    return groups
+    return props
 
 
 def test_lds_large_full_size():
@@ -70,9 +119,15 @@ def test_lds_large_full_size():
     np.testing.assert_array_equal(order, o_order)
     np.testing.assert_array_equal(E, o_E)
     np.testing.assert_array_equal(inI, o_inI)
-    # the benchmark iteration count: properties
+    # the benchmark iteration count: properties, and the oracle's exact
+    # result stored as digests
     announce("lds_large N", iters)
-    check_properties(g, mode, iters, n, G.m)
+    del G
+    ref = golden("full_size.json", "lds_large")
+    assert (ref["n"], ref["m"], ref["iters"]) == (n, lds.lds_graph_info(g)["m"], iters)
+    check_golden_fw(*check_properties(g, mode, iters, n, ref["m"]), ref)
+    announce("lds_large top-k")
+    check_golden_topk(g, ref)
 
 
 def test_ltds_hk_full_size():
@@ -97,4 +152,33 @@ def test_ltds_hk_full_size():
     np.testing.assert_array_equal(E, o_E)
     np.testing.assert_array_equal(inI, o_inI)
     announce("ltds_hk N", iters)
-    check_properties(g, mode, iters, n, T)
+    del G
+    ref = golden("full_size.json", "ltds_hk")
+    assert (ref["n"], ref["patterns"], ref["iters"]) == (n, T, iters)
+    check_golden_fw(*check_properties(g, mode, iters, n, T), ref)
+    announce("ltds_hk top-k")
+    check_golden_topk(g, ref)
+
+
+@pytest.mark.parametrize("which", ["edge", "triangle"])
+def test_mid_size_exact_alg2(which):
+    """120,000 vertices: most gathered codes come from memory (internal ids >=
+    65,536) and the stable-group scan runs in its default multi-workgroup
+    shape; loads, order, prefix, I, groups and bounds exactly as the oracle's
+    literal Alg. 2 (digests from tests/golden/make_mid_size.py)."""
+    ref = golden("mid_size_%s.json" % which)
+    n, s, d = synth.powerlaw_planted(**ref["graph"])
+    mode, iters = ref["mode"], ref["iters"]
+    announce("mid size", which, n, iters)
+    g = lds.lds_create_graph(n, s, d)
+    assert lds.lds_graph_info(g)["m"] == ref["m"]
+    out = lds.lds_frank_wolfe(g, mode, iters, want_num=True, want_gap=True)
+    order, E, inI = lds.lds_sort_prefix(g, mode)
+    check_golden_fw(out, order, E, inI, ref)
+    groups, lo, hi = lds.lds_stable_groups(g, mode)
+    assert len(groups) == ref["n_groups"]
+    assert [list(x) for x in groups[:20]] == ref["first_groups"]
+    assert sha([a for a, _ in groups], "<i8") == ref["gstart_sha256"]
+    assert sha([b for _, b in groups], "<i8") == ref["gend_sha256"]
+    assert sha(lo, "<i8") == ref["lo_sha256"] and sha(hi, "<i8") == ref["hi_sha256"]
+    g.destroy()
