@@ -362,6 +362,21 @@ typedef struct {
  * 2^32 - 1 (see lds_sort_prefix), before any work. */
 lds_status lds_topk(lds_graph g, lds_mode mode, int32_t k, int32_t iters, lds_result* out, void* hip_stream);
 
+/* Pruning (Alg. 3, Section 5.2) as lds_topk runs it, without the search:
+ * iters FW iterations and ExtractSG on the graph give bounds on every compact
+ * number (with the core / tr-core bounds of Section 4.3); rule 1 (Cor.
+ * uv-prune) removes every vertex with a neighbour whose lower bound exceeds
+ * its upper bound, then rule 2 (Lemma uu-prune) removes, until nothing
+ * changes, every vertex whose core (tr-core) number in the graph of the
+ * remaining vertices is below its lower bound.  No removed vertex lies in an
+ * LDS (LTDS).  Both rules run on the device.  Outputs (each optional):
+ * rule_out (host int8, n, by caller id) = the rule that removed the vertex
+ * (1 or 2), 0 for the survivors; *pruned_out = removed vertices; *ms_out =
+ * wall-clock ms of the pruning itself.  Replaces the graph's FW state of this
+ * mode with an iters-iteration run; synchronises the stream. */
+lds_status lds_prune(lds_graph g, lds_mode mode, int32_t iters, int8_t* rule_out, int64_t* pruned_out,
+                     double* ms_out, void* hip_stream);
+
 /* Frees the arrays of a result filled by lds_topk and zeroes it; NULL and
  * zeroed results are accepted. */
 void lds_result_free(lds_result* r);

@@ -321,3 +321,32 @@ def top_levels(G, mode, lam):
         sets.append((np.sort(idK[idU[vs]]).astype(np.int32), rho))
     sets.sort(key=lambda t: (-t[1], int(t[0][0])))
     return sets, int(K.sum()), int(UK.sum())
+
+
+def prune(G, mode, lo, hi):
+    """Pruning (Alg. 3, Section 5.2) with bounds lo[u] <= phi(u) <= hi[u]
+    (sequences of Fractions, by vertex): rule 1 (Cor. uv-prune) removes every
+    vertex with a neighbour whose lower bound exceeds its upper bound; then
+    rule 2 (Lemma uu-prune) removes, until nothing changes, every vertex whose
+    core (tr-core) number in the subgraph induced by the remaining vertices
+    is below its lower bound.  -> int8 (n,): 1 / 2 = removed by that rule,
+    0 = kept.  Plain loops: small graphs only."""
+    n = G.n
+    rule = np.zeros(n, np.int8)
+    u, v = G.edges()
+    for a, b in zip(u.tolist(), v.tolist()):
+        if lo[b] > hi[a]:
+            rule[a] = 1
+        if lo[a] > hi[b]:
+            rule[b] = 1
+    while True:
+        keep = rule == 0
+        sub, ids = induced(G, keep)
+        core = core_numbers(sub, mode)
+        changed = False
+        for i, x in enumerate(ids.tolist()):
+            if Fraction(int(core[i])) < lo[x]:
+                rule[x] = 2
+                changed = True
+        if not changed:
+            return rule

@@ -78,6 +78,7 @@ def load():
         "lds_sweep_info": (st, [vp, st, vp, vp, vp, vp, vp, vp]),
         "lds_topk": (st, [vp, st, i32, i32, vp, vp]),
         "lds_result_free": (None, [vp]),
+        "lds_prune": (st, [vp, st, i32, vp, vp, vp, vp]),
         "lds_loads": (st, [vp, st, vp, vp, vp, vp, vp, vp]),
         "lds_core_numbers": (st, [vp, st, vp, vp, vp]),
         "lds_fw_bounds": (st, [vp, st, vp, vp]),
@@ -348,6 +349,18 @@ def lds_topk(g, mode, k, iters, stream=None, with_stats=False):
     finally:
         L.lds_result_free(ctypes.byref(r))
     return (out, stats) if with_stats else out
+
+
+def lds_prune(g, mode, iters, stream=None):
+    """Pruning (Alg. 3) as lds_topk runs it -> (rule (n,) int8 by caller id:
+    1 / 2 = removed by rule 1 / 2, 0 = kept; pruned count; ms)."""
+    n = lds_graph_info(g)["n"]
+    rule = np.empty(max(n, 1), np.int8)
+    cnt = ctypes.c_int64()
+    ms = ctypes.c_double()
+    _check(load().lds_prune(g.handle, mode, int(iters), _ptr(rule), ctypes.byref(cnt), ctypes.byref(ms),
+                            _stream(stream)))
+    return rule[:n], cnt.value, ms.value
 
 
 def lds_loads(g, mode, r_out=None, want_r64=False, want_num=False, want_gap=False, stream=None):

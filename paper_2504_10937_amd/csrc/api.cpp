@@ -409,6 +409,24 @@ lds_status lds_topk(lds_graph g, lds_mode mode, int32_t k, int32_t iters, lds_re
     API_CATCH
 }
 
+lds_status lds_prune(lds_graph g, lds_mode mode, int32_t iters, int8_t* rule_out, int64_t* pruned_out,
+                     double* ms_out, void* hip_stream) {
+    API_TRY
+    LDS_CHECK(g != nullptr, lds::ST_INVALID, "graph is NULL");
+    LDS_CHECK(mode == LDS_EDGE || mode == LDS_TRIANGLE, lds::ST_INVALID, "mode must be LDS_EDGE or LDS_TRIANGLE");
+    LDS_CHECK(iters >= 0, lds::ST_INVALID, "iters must be >= 0");
+    std::lock_guard<std::mutex> lk(g->mu);
+    const int64_t n = g->g.n;
+    std::vector<int8_t> rule((size_t)std::max<int64_t>(n, 1), 0);
+    std::vector<lds::TopkSet> sets;
+    lds::TopkStats st;
+    if (n > 0) lds::topk_run(g->g, (int)mode, 1, iters, (hipStream_t)hip_stream, sets, st, false, rule.data());
+    if (rule_out) std::copy(rule.begin(), rule.begin() + n, rule_out);
+    if (pruned_out) *pruned_out = st.pruned;
+    if (ms_out) *ms_out = st.ms_prune;
+    API_CATCH
+}
+
 void lds_result_free(lds_result* r) {
     if (!r) return;
     std::free(r->offsets);

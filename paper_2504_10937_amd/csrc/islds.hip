@@ -180,6 +180,44 @@ __global__ void k_fill(int32_t* p, int64_t n, int32_t v) {
     if (i < n) p[i] = v;
 }
 
+// Pruning rule 1 (Alg. 3; Cor. uv-prune): u lies in no LDS when one of its
+// neighbours has a lower bound above u's upper bound (then phi of that
+// neighbour exceeds phi(u)).  One wave per vertex, bounds compared exactly.
+__global__ void k_prune_rule1(const int64_t* rp, const int32_t* col, int64_t n, const int64_t* lon, const int64_t* lod,
+                              const int64_t* hin, const int64_t* hid, uint8_t* alive, uint8_t* rule) {
+    const int lane = threadIdx.x & 63;
+    const int64_t u = ((int64_t)blockIdx.x * kT + threadIdx.x) >> 6;
+    if (u >= n) return;
+    const __int128 hn = hin[u], hd = hid[u];
+    bool hit = false;
+    for (int64_t e = rp[u] + lane; e < rp[u + 1] && !hit; e += 64) {
+        const int32_t w = col[e];
+        hit = (__int128)lon[w] * hd > hn * (__int128)lod[w];
+    }
+    if (__ballot(hit) != 0ull && lane == 0) {
+        alive[u] = 0;
+        rule[u] = 1;
+    }
+}
+
+// Pruning rule 2 (Alg. 3; Lemma uu-prune): u lies in no LDS when its core
+// (tr-core) number in the residual graph is below its lower bound
+__global__ void k_prune_rule2(const int32_t* core, int64_t n, const int64_t* lon, const int64_t* lod, uint8_t* alive,
+                              uint8_t* rule, unsigned* changed) {
+    const int64_t u = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (u >= n || !alive[u]) return;
+    if ((__int128)core[u] * lod[u] < (__int128)lon[u]) {
+        alive[u] = 0;
+        rule[u] = 2;
+        atomicAdd(changed, 1u);
+    }
+}
+
+__global__ void k_fill_u8(uint8_t* p, int64_t n, uint8_t v) {
+    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 __global__ void k_fill_u32(uint32_t* p, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
     if (i < n) p[i] = 0u;
@@ -341,6 +379,30 @@ bool scope_band(Graph& g, BandScope& b, const std::vector<int32_t>& S, int64_t r
     if (nt > 0) k_clear_t<<<grid_for(nt, kT), kT, 0, s>>>(b.tlist.p, nt, b.tvis.p);
     LDS_HIP(hipGetLastError());
     return true;
+}
+
+void prune_device(Graph& g, int mode, const BandScope& b, uint8_t* alive, uint8_t* rule, hipStream_t s) {
+    const int64_t n = g.n;
+    if (n == 0) return;
+    k_fill_u8<<<grid_for(n, kT), kT, 0, s>>>(alive, n, 1);
+    k_fill_u8<<<grid_for(n, kT), kT, 0, s>>>(rule, n, 0);
+    k_prune_rule1<<<grid_for(n * 64, kT), kT, 0, s>>>(g.rowptr.p, g.col.p, n, b.lon.p, b.lod.p, b.hin.p, b.hid.p,
+                                                      alive, rule);
+    LDS_HIP(hipGetLastError());
+    DBuf<int32_t> core;
+    core.alloc(n, s);
+    DBuf<unsigned> changed;
+    changed.alloc(1, s);
+    for (;;) {
+        core_numbers_gpu(g, mode, alive, core.p, s);
+        LDS_HIP(hipMemsetAsync(changed.p, 0, sizeof(unsigned), s));
+        k_prune_rule2<<<grid_for(n, kT), kT, 0, s>>>(core.p, n, b.lon.p, b.lod.p, alive, rule, changed.p);
+        LDS_HIP(hipGetLastError());
+        unsigned ch = 0;
+        LDS_HIP(hipMemcpyAsync(&ch, changed.p, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+        LDS_HIP(hipStreamSynchronize(s));
+        if (ch == 0) break;
+    }
 }
 
 }  // namespace lds

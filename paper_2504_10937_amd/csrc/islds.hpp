@@ -33,4 +33,10 @@ void scope_init(Graph& g, int mode, const int64_t* lon, const int64_t* lod, cons
 bool scope_band(Graph& g, BandScope& b, const std::vector<int32_t>& S, int64_t rn, int64_t rd, ScopeOut& o,
                 hipStream_t s);
 
+// Pruning (Alg. 3) with the bounds of b (internal order): rule 1 once, then
+// rule 2 with the core (tr-core) numbers of the residual graph until nothing
+// changes, all on the device.  alive[u] = 0 for pruned vertices; rule[u] = the
+// rule that removed u (1 or 2), 0 for the survivors.
+void prune_device(Graph& g, int mode, const BandScope& b, uint8_t* alive, uint8_t* rule, hipStream_t s);
+
 }  // namespace lds

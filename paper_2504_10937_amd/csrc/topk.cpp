@@ -1025,7 +1025,7 @@ size_t topk_footprint(const Graph& g, int mode, int iters) {
 }
 
 void topk_run(Graph& g, int mode, int k, int iters, hipStream_t s, std::vector<TopkSet>& out, TopkStats& st,
-              bool reuse_fw) {
+              bool reuse_fw, int8_t* prune_out) {
     // the device min cuts of this search run on its stream
     struct StreamScope {
         hipStream_t prev;
@@ -1125,32 +1125,25 @@ void topk_run(Graph& g, int mode, int k, int iters, hipStream_t s, std::vector<T
         c.scope = &scope;
     }
     lap(&st.ms_fw);
-    // Pruning (Alg. 3): rule 1, then rule 2 on the residual graph (vertex
-    // ranges over the host threads; each writes only its own vertices)
-    par_for_rows(c.h.rp, n, [&](int64_t u0, int64_t u1) {
-        for (int64_t u = u0; u < u1; ++u)
-            for (int64_t e = c.h.rp[u]; e < c.h.rp[u + 1]; ++e)
-                if (lt(c.hi[u], c.lo[c.h.col[e]])) {
-                    alive[u] = 0;
-                    break;
-                }
-    });
-    for (;;) {
-        const std::vector<int32_t> cr = device_cores(g, mode, &alive, s);
-        std::atomic<bool> changed{false};
-        par_for(n, [&](int64_t u0, int64_t u1) {
-            bool ch = false;
-            for (int64_t u = u0; u < u1; ++u)
-                if (alive[u] && lt(Frac{cr[u], 1}, c.lo[u])) {
-                    alive[u] = 0;
-                    ch = true;
-                }
-            if (ch) changed.store(true, std::memory_order_relaxed);
-        });
-        if (!changed.load()) break;
+    // Pruning (Alg. 3) on the device with the bounds just staged there: rule
+    // 1, then rule 2 on the residual graph until nothing changes
+    {
+        DBuf<uint8_t> al, rl;
+        al.alloc(n, s);
+        rl.alloc(n, s);
+        prune_device(g, mode, scope, al.p, rl.p, s);
+        LDS_HIP(hipMemcpyAsync(alive.data(), al.p, n, hipMemcpyDeviceToHost, s));
+        if (prune_out) {
+            std::vector<int8_t> rule((size_t)n);
+            LDS_HIP(hipMemcpyAsync(rule.data(), rl.p, n, hipMemcpyDeviceToHost, s));
+            LDS_HIP(hipStreamSynchronize(s));
+            for (int64_t u = 0; u < n; ++u) prune_out[hc.h.orig[u]] = rule[u];
+        }
+        LDS_HIP(hipStreamSynchronize(s));
     }
     for (int64_t u = 0; u < n; ++u) st.pruned += alive[u] ? 0 : 1;
     lap(&st.ms_prune);
+    if (prune_out) return;
     std::priority_queue<Cand, std::vector<Cand>, CandLess> pq;
     auto push = [&](std::vector<int32_t>&& vs, const Frac* cap) {
         if (vs.empty()) return;

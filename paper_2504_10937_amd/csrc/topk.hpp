@@ -79,8 +79,10 @@ bool topk_threads_single();
 
 // reuse_fw: the graph already holds a completed run of `iters` iterations
 // for this mode (e.g. from a batched launch); it is used instead of a new run
+// prune_out (host, n, by caller id): stop after Pruning (Alg. 3) and write
+// the rule that removed each vertex (1 or 2; 0 for the survivors)
 void topk_run(Graph& g, int mode, int k, int iters, hipStream_t s, std::vector<TopkSet>& out, TopkStats& st,
-              bool reuse_fw = false);
+              bool reuse_fw = false, int8_t* prune_out = nullptr);
 // device bytes a top-k query adds to a resident graph (FW state for `iters`
 // iterations, stable-group buffers and their temporaries), an upper estimate
 size_t topk_footprint(const Graph& g, int mode, int iters);

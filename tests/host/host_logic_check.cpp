@@ -40,6 +40,7 @@ Batch::~Batch() {}
 void batch_build(Batch&, hipStream_t) {}
 void batch_run(Batch&, hipStream_t) {}
 void scope_init(Graph&, int, const int64_t*, const int64_t*, const int64_t*, const int64_t*, BandScope&, hipStream_t) {}
+void prune_device(Graph&, int, const BandScope&, uint8_t*, uint8_t*, hipStream_t) {}
 bool scope_band(Graph&, BandScope&, const std::vector<int32_t>&, int64_t, int64_t, ScopeOut&, hipStream_t) {
     return false;
 }

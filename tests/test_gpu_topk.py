@@ -186,3 +186,38 @@ def test_refinements_batched(iters):
     assert len(got) == 6 and all(r == 2 for _, r in got)
     if iters in (1, 3):
         assert st["refinements"] >= 6 and st["refine_rounds"] < st["refinements"]
+
+
+def test_pruning_running_example():
+    """The device pruning (Alg. 3) as lds_topk runs it, on the running example
+    with 200 FW iterations: rule 1 removes r, g and i and rule 2 then removes
+    o, p, q and h, as in Section 5.2's example."""
+    announce("prune running example")
+    d, n, s, t = running_example()
+    g = lds.lds_create_graph(n, s, t)
+    rule, cnt, _ = lds.lds_prune(g, 2, 200)
+    assert sorted(np.flatnonzero(rule == 1).tolist()) == sorted(d["pruned_rule1"])
+    assert sorted(np.flatnonzero(rule == 2).tolist()) == sorted(d["pruned_rule2"])
+    assert cnt == 7
+
+
+@pytest.mark.parametrize("mode", [2, 3])
+def test_pruning_within_exact_pruning(mode):
+    """The library's bounds bracket phi, so what it prunes is also pruned by
+    Alg. 3 with the exact compact numbers as bounds (the oracle's pruning;
+    tighter bounds prune more), and no pruned vertex lies in an LDS."""
+    cases = [synth.workload("lds_small")[:3], synth.holme_kim(1500, 5, 0.6, seed=8),
+             synth.powerlaw_planted(2500, 2.2, 10.0, n_blocks=8, s_lo=15, s_hi=60, p_block=0.4, seed=9)]
+    for n, s, d in cases:
+        announce("prune subset", mode, n)
+        G = oracle.Graph(n, s, d)
+        pn, pd = oracle.decompose(G, mode)
+        phi = [Fraction(int(a), int(b)) for a, b in zip(pn, pd)]
+        exact = oracle.prune(G, mode, phi, phi)
+        g = lds.lds_create_graph(n, s, d)
+        for iters in (5, 100):
+            rule, cnt, _ = lds.lds_prune(g, mode, iters)
+            assert cnt == int((rule != 0).sum())
+            assert (exact[rule != 0] != 0).all()
+            for vs, _ in oracle.lds_from_phi(G, pn, pd):
+                assert (rule[vs] == 0).all()

@@ -389,6 +389,31 @@ def test_core_numbers_by_enumeration():
             assert list(oracle.core_numbers(G, mode)) == _core_by_enumeration(n, edges, mode)
 
 
+# ------------------------------------------------------------- pruning
+def test_pruning_running_example():
+    """Alg. 3 on the running example with the exact compact numbers as both
+    bounds: rule 1 removes r, g and i, rule 2 then removes o, p, q and h
+    (Section 5.2's example)."""
+    d, G = running_example()
+    pn, pd = oracle.decompose(G, 2)
+    phi = [Fraction(int(a), int(b)) for a, b in zip(pn, pd)]
+    rule = oracle.prune(G, 2, phi, phi)
+    assert sorted(np.flatnonzero(rule == 1).tolist()) == sorted(d["pruned_rule1"])
+    assert sorted(np.flatnonzero(rule == 2).tolist()) == sorted(d["pruned_rule2"])
+
+
+@pytest.mark.parametrize("mode", [2, 3])
+def test_pruning_keeps_every_lds(mode):
+    """No vertex of an LDS (LTDS) is removed by Alg. 3 with exact bounds (the
+    rules' claim), on random small graphs against brute force."""
+    for n, s, d in small_graphs():
+        G = oracle.Graph(n, s, d)
+        phi, sets = oracle.brute(G, mode)
+        rule = oracle.prune(G, mode, phi, phi)
+        for vs, _ in sets:
+            assert (rule[vs] == 0).all()
+
+
 # ------------------------------------------ large-graph path (k-core, superlevel)
 def _helper_graphs():
     return small_graphs() + [synth.powerlaw_planted(300, 2.3, 6.0, 3, 8, 20, 0.6, seed=9),
