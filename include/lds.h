@@ -185,6 +185,15 @@ lds_status lds_sort_prefix(lds_graph g, lds_mode mode, int32_t* order_out, int64
 lds_status lds_stable_groups(lds_graph g, lds_mode mode, int64_t* ngroups, int64_t* gstart, int64_t* gend, int64_t cap,
                              int64_t* lo_out, int64_t* hi_out, void* hip_stream);
 
+/* Profile of the last stable-group scan of this graph and mode (host int64
+ * out[14]): [0] accepted groups, [1] rounds (one per accepted group, plus
+ * the last unfinished one), [2] verified boundaries, [3..6] phases of each
+ * kind run by the whole grid (search, update walk, min / max, acceptance;
+ * the rest ran in the leading workgroup alone), [7..10] wall-clock
+ * microseconds spent in each kind, [11] positions searched, [12] records
+ * walked, [13] workgroups of the launch.  LDS_E_INVALID if no scan has run. */
+lds_status lds_sg_scan_info(lds_graph g, lds_mode mode, int64_t* out);
+
 /* GPU time of the sweep launches of the last lds_frank_wolfe call for this
  * graph and mode, from HIP events recorded on that call's stream right before
  * the first and after the last sweep launch (waits for the end event).

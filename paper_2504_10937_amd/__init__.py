@@ -76,6 +76,7 @@ def load():
         "lds_sort_prefix": (st, [vp, st, vp, vp, vp, vp]),
         "lds_stable_groups": (st, [vp, st, vp, vp, vp, i64, vp, vp, vp]),
         "lds_sweep_info": (st, [vp, st, vp, vp, vp, vp, vp, vp]),
+        "lds_sg_scan_info": (st, [vp, st, vp]),
         "lds_topk": (st, [vp, st, i32, i32, vp, vp]),
         "lds_result_free": (None, [vp]),
         "lds_prune": (st, [vp, st, i32, vp, vp, vp, vp]),
@@ -298,6 +299,20 @@ def lds_stable_groups(g, mode, stream=None):
     _check(load().lds_stable_groups(g.handle, mode, ctypes.byref(ng), _ptr(gs), _ptr(ge), len(gs), _ptr(lo), _ptr(hi),
                                     _stream(stream)))
     return [(int(gs[i]), int(ge[i])) for i in range(ng.value)], lo, hi
+
+
+def lds_sg_scan_info(g, mode):
+    """Profile of the last stable-group scan -> dict (groups, rounds,
+    verifications, grid phases and microseconds per phase kind, positions
+    searched, records walked, workgroups)."""
+    out = np.zeros(14, np.int64)
+    _check(load().lds_sg_scan_info(g.handle, mode, _ptr(out)))
+    kinds = ("search", "update", "minmax", "accept")
+    d = {"groups": int(out[0]), "rounds": int(out[1]), "verifications": int(out[2])}
+    d.update({"grid_" + k: int(out[3 + i]) for i, k in enumerate(kinds)})
+    d.update({"us_" + k: int(out[7 + i]) for i, k in enumerate(kinds)})
+    d.update({"searched": int(out[11]), "walked": int(out[12]), "workgroups": int(out[13])})
+    return d
 
 
 def lds_fw_elapsed(g, mode):

@@ -309,6 +309,24 @@ lds_status lds_stable_groups(lds_graph g, lds_mode mode, int64_t* ngroups, int64
     API_CATCH
 }
 
+lds_status lds_sg_scan_info(lds_graph g, lds_mode mode, int64_t* out) {
+    API_TRY
+    LDS_CHECK(g != nullptr && out != nullptr, lds::ST_INVALID, "graph or output is NULL");
+    LDS_CHECK(mode == LDS_EDGE || mode == LDS_TRIANGLE, lds::ST_INVALID, "mode must be LDS_EDGE or LDS_TRIANGLE");
+    std::lock_guard<std::mutex> lk(g->mu);
+    const lds::SgState& q = g->g.sg[mode == LDS_EDGE ? 0 : 1];
+    LDS_CHECK(q.scan_wg > 0, lds::ST_INVALID, "no stable-group scan has run for this mode");
+    out[0] = (int64_t)q.gstart.size();
+    out[1] = q.rounds;
+    out[2] = q.verifications;
+    for (int k = 0; k < 4; ++k) out[3 + k] = q.scan_profile[k];
+    for (int k = 0; k < 4; ++k) out[7 + k] = q.scan_profile[4 + k];
+    out[11] = q.scan_profile[8];
+    out[12] = q.scan_profile[9];
+    out[13] = q.scan_wg;
+    API_CATCH
+}
+
 lds_status lds_fw_elapsed(lds_graph g, lds_mode mode, float* ms, int32_t* launches) {
     API_TRY
     LDS_CHECK(g != nullptr, lds::ST_INVALID, "graph is NULL");

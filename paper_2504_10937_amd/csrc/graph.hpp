@@ -151,6 +151,11 @@ struct SgState {
     std::vector<int64_t> gstart, gend;  // accepted groups (position ranges)
     DBuf<int64_t> lo, hi;        // per internal vertex: restricted min / max of its group, -1 if none
     int64_t rounds = 0, verifications = 0;
+    // last scan's phase profile: grid-wide phases of each kind (search,
+    // update walk, min / max, acceptance), microseconds in each kind,
+    // positions searched, records walked
+    int64_t scan_profile[10] = {};
+    int64_t scan_wg = 0;  // workgroups of the last scan launch (0: none yet)
     size_t device_bytes() const {
         return order.bytes() + pos.bytes() + E.bytes() + inI.bytes() + a_slot.bytes() + a_tri.bytes() + lo.bytes() +
                hi.bytes();

@@ -967,6 +967,10 @@ __device__ void scan_leader(const ScanArgs& g, long long (*sred)[4], long long* 
     int ph = 0;
     unsigned posted = 0, beat = 0;
     int64_t S0 = 0, fb = 0, kS0 = 0, kfb = 0, ng = 0, rounds = 0, verifs = 0;
+    // phase profile: grid-wide phases and wall-clock ticks per kind (search,
+    // update walk, min / max, acceptance), positions searched, records walked
+    int64_t gridc[4] = {0, 0, 0, 0}, searched = 0, walked = 0;
+    long long ticks[4] = {0, 0, 0, 0};
     long long minH = 0;
     bool hasH = false, failed = false;
     while (S0 < n && !failed) {
@@ -979,7 +983,9 @@ __device__ void scan_leader(const ScanArgs& g, long long (*sred)[4], long long* 
             heartbeat(g, beat);
             // first event in [from, hi)
             const int64_t hi = min(n, from + win);
+            long long t0 = (long long)wall_clock64();
             if (grid && hi - from > g.lead_pos) {
+                ++gridc[0];
                 const long long d[8] = {PH_SEARCH, ph, from, hi, hasH ? 1 : 0, minH, 0, 0};
                 post_phase(g, posted, d);
                 run_posted<H>(g, d, sred);
@@ -989,6 +995,8 @@ __device__ void scan_leader(const ScanArgs& g, long long (*sred)[4], long long* 
                 const long long first = search_part(g, from, hi, hasH, minH, t, kRT);
                 reduce_local(first, LLONG_MIN, LLONG_MIN, LLONG_MAX, sred, sh);
             }
+            ticks[0] += (long long)wall_clock64() - t0;
+            searched += hi - from;
             ++ph;
             failed = *s_err != 0;
             const long long e = sh[0];
@@ -1008,7 +1016,10 @@ __device__ void scan_leader(const ScanArgs& g, long long (*sred)[4], long long* 
             // frontier of the loads below and the end of S always coincide:
             // both start at the accepted boundary and move to every verified b
             const int64_t k1 = g.P[b];
+            t0 = (long long)wall_clock64();
+            walked += k1 - kfb;
             if (grid && k1 - kfb > g.lead_recs) {
+                ++gridc[1];
                 const long long d[8] = {PH_UPDATE, ph, S0, fb, b, kfb, k1, 0};
                 post_phase(g, posted, d);
                 run_posted<H>(g, d, sred);
@@ -1017,13 +1028,16 @@ __device__ void scan_leader(const ScanArgs& g, long long (*sred)[4], long long* 
                 update_walk<H>(g, S0, fb, b, kfb, k1, w, kRW);
                 __syncthreads();
             }
+            ticks[1] += (long long)wall_clock64() - t0;
             fb = b;
             kfb = k1;
             failed = *s_err != 0;
             if (failed) break;
             // min and max of the restricted loads of S, largest load below b
             const int64_t mm = (b - S0) + (b < n ? g.nblk - b / kFB : 0);
+            t0 = (long long)wall_clock64();
             if (grid && mm > g.lead_pos) {
+                ++gridc[2];
                 const long long d[8] = {PH_MINMAX, ph, S0, b, 0, 0, 0, 0};
                 post_phase(g, posted, d);
                 run_posted<H>(g, d, sred);
@@ -1034,6 +1048,7 @@ __device__ void scan_leader(const ScanArgs& g, long long (*sred)[4], long long* 
                 minmax_part(g, S0, b, t, kRT, vmn, vmx, fmx);
                 reduce_local(vmn, vmx, fmx, LLONG_MAX, sred, sh);
             }
+            ticks[2] += (long long)wall_clock64() - t0;
             ++ph;
             failed = *s_err != 0;
             if (failed) break;
@@ -1051,7 +1066,10 @@ __device__ void scan_leader(const ScanArgs& g, long long (*sred)[4], long long* 
         }
         if (!accepted || failed) break;  // the rest is never accepted: no bounds
         const int64_t b = accb;  // == fb, so P[b] == kfb
+        const long long t0 = (long long)wall_clock64();
+        walked += kfb - kS0;
         if (grid && (b - S0 > g.lead_pos || kfb - kS0 > g.lead_recs)) {
+            ++gridc[3];
             const long long d[8] = {PH_ACCEPT, ph, S0, b, kS0, kfb, mnS, mxS};
             post_phase(g, posted, d);
             run_posted<H>(g, d, sred);
@@ -1060,6 +1078,7 @@ __device__ void scan_leader(const ScanArgs& g, long long (*sred)[4], long long* 
             accept_part<H>(g, S0, b, kS0, kfb, mnS, mxS, t, kRT, w, kRW);
             __syncthreads();
         }
+        ticks[3] += (long long)wall_clock64() - t0;
         if (threadIdx.x == 0) {
             g.groups[2 * ng] = S0;
             g.groups[2 * ng + 1] = b;
@@ -1079,6 +1098,12 @@ __device__ void scan_leader(const ScanArgs& g, long long (*sred)[4], long long* 
         g.info[0] = ng;
         g.info[1] = rounds;
         g.info[2] = verifs;
+        for (int k = 0; k < 4; ++k) {
+            g.info[4 + k] = gridc[k];
+            g.info[8 + k] = ticks[k];
+        }
+        g.info[12] = searched;
+        g.info[13] = walked;
     }
 }
 
@@ -1377,6 +1402,15 @@ void sg_stable_groups(Graph& g, int mode, hipStream_t s) {
     const int64_t ng = hinfo[0];
     q.rounds = hinfo[1];
     q.verifications = hinfo[2];
+    static int rate_khz = 0;  // wall clock of the device
+    if (!rate_khz) {
+        int dev = 0;
+        LDS_HIP(hipGetDevice(&dev));
+        LDS_HIP(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev));
+    }
+    for (int k = 0; k < 10; ++k) q.scan_profile[k] = hinfo[4 + k];
+    for (int k = 4; k < 8; ++k) q.scan_profile[k] = q.scan_profile[k] * 1000 / std::max(rate_khz, 1);
+    q.scan_wg = grid;
     std::vector<int64_t> hg((size_t)2 * ng);
     if (ng > 0) {
         LDS_HIP(hipMemcpyAsync(hg.data(), groups.p, hg.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
