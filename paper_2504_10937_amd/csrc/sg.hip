@@ -42,6 +42,7 @@
 
 #include "graph.hpp"
 #include "gridsync.hpp"
+#include "wave.hpp"
 
 namespace lds {
 
@@ -411,8 +412,11 @@ __device__ inline void load_pattern<3>(const PassArgs& a, int64_t s, int32_t x, 
 // over the whole scan, so F is advanced incrementally: when positions
 // [p0, p1) move above, each of their patterns (handled once, from its latest
 // moving vertex) adds (after - before) to the vertices still below; block
-// maxima over 1024 positions stay valid under these increases.
+// maxima over 1024 positions, and maxima of 64 blocks (superblocks), stay
+// valid under these increases, so the largest load below b is read from at
+// most 1024 + 64 + n / 65536 values.
 constexpr int kFB = 1024;
+constexpr int kSB = 64;  // blocks per superblock
 
 // F at b = 0 (nothing above): the plain load numerators, by position
 __global__ void k_f_init(const uint64_t* K, const int32_t* order, int64_t n, int B, int64_t* F) {
@@ -424,11 +428,18 @@ __global__ __launch_bounds__(kT) void k_bmax_init(const int64_t* F, int64_t n, l
     const int64_t base = (int64_t)blockIdx.x * kFB;
     long long mx = LLONG_MIN;
     for (int64_t j = base + threadIdx.x; j < base + kFB && j < n; j += kT) mx = max(mx, (long long)F[j]);
-    for (int m = 32; m > 0; m >>= 1) mx = max(mx, (long long)shfl_xor_i64(mx, m));
+    mx = wave::max_all(mx);
     __shared__ long long sh[4];
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = mx;
     __syncthreads();
     if (threadIdx.x == 0) bmax[blockIdx.x] = max(max(sh[0], sh[1]), max(sh[2], sh[3]));
+}
+
+// superblock maxima from the block maxima (one wave per superblock)
+__global__ __launch_bounds__(64) void k_bmax2_init(const long long* bmax, int64_t nblk, long long* bmax2) {
+    const int64_t blk = (int64_t)blockIdx.x * kSB + threadIdx.x;
+    const long long mx = wave::max_all(blk < nblk ? bmax[blk] : LLONG_MIN);
+    if (threadIdx.x == 0) bmax2[blockIdx.x] = mx;
 }
 
 // ------------------------------------------- the whole scan on the device
@@ -474,6 +485,8 @@ struct ScanArgs {
     int64_t* F;
     int64_t* V;            // restricted loads of the pending group, by position
     long long* bmax;
+    long long* bmax2;      // maxima of kSB consecutive blocks
+    int64_t nsb;
     int64_t nblk;
     int64_t n;
     int64_t* lo;           // bounds by internal vertex
@@ -528,27 +541,16 @@ __device__ inline void rec_pattern<3>(const ScanArgs& g, int64_t k, int64_t* p, 
 template <int H>
 constexpr int kRecRows = (H == 2) ? 8 : 4;
 
-__device__ inline int32_t shfl_down_i32(int32_t v, int d) { return __shfl_down(v, (unsigned)d, 64); }
-__device__ inline int64_t shfl_down_i64(int64_t v, int d) {
-    const uint32_t lo = (uint32_t)__shfl_down((int)(uint32_t)(uint64_t)v, (unsigned)d, 64);
-    const uint32_t hi = (uint32_t)__shfl_down((int)(uint32_t)((uint64_t)v >> 32), (unsigned)d, 64);
-    return (int64_t)(((uint64_t)hi << 32) | lo);
-}
 
 // Adds, per position, the values of one row of 64 records into V.  The
-// positions of a row do not decrease from lane to lane, so a segmented
-// suffix sum leaves each position's total in its first lane, which makes
-// the one atomic (V starts at zero and a position's own sum is added once).
+// positions of a row's valid lanes do not decrease from lane to lane and its
+// unused lanes (key -1) come last, so equal keys are contiguous: a segmented
+// prefix sum leaves each position's total in its last lane, which makes the
+// one atomic (V starts at zero and a position's own sum is added once).
+// Called by all 64 lanes.
 __device__ inline void add_by_position(int64_t* V, int32_t key, int64_t val) {
-    const int lane = threadIdx.x & 63;
-    const int32_t prev = __shfl_up(key, 1u, 64);
-    const bool head = (lane == 0) || prev != key;
-    for (int off = 1; off < 64; off <<= 1) {
-        const int32_t ko = shfl_down_i32(key, off);
-        const int64_t vo = shfl_down_i64(val, off);
-        if (lane + off < 64 && ko == key) val += vo;
-    }
-    if (head && key >= 0 && val != 0) atomicAdd((unsigned long long*)&V[key], (unsigned long long)val);
+    val = wave::seg_prefix_sum(key, val);
+    if (wave::run_tail(key) && key >= 0 && val != 0) atomicAdd((unsigned long long*)&V[key], (unsigned long long)val);
 }
 
 // Positions [f0, b) move from below the boundary into the pending group
@@ -611,7 +613,10 @@ __device__ inline void update_walk(const ScanArgs& g, int64_t S0, int64_t f0, in
             for (int i = 0; i < H - 1; ++i)
                 if (fd[u][i] != 0) {
                     const long long nv = (long long)(fo[u][i] + fd[u][i]);
-                    if (nv > bm[u][i]) atomicMax(&g.bmax[p[u][i + 1] / kFB], nv);
+                    if (nv > bm[u][i]) {  // the superblock maximum is raised with its block's
+                        atomicMax(&g.bmax[p[u][i + 1] / kFB], nv);
+                        atomicMax(&g.bmax2[p[u][i + 1] / ((int64_t)kFB * kSB)], nv);
+                    }
                 }
 #pragma unroll
         for (int u = 0; u < U; ++u) add_by_position(g.V, (int32_t)p[u][0], own[u]);
@@ -735,12 +740,10 @@ __device__ inline void gather_partials(const ScanArgs& g, int ph, unsigned nwg, 
             v2 = max(v2, P[4 * w + 2]);
             v3 = min(v3, P[4 * w + 3]);
         }
-        for (int m = 32; m > 0; m >>= 1) {
-            v0 = min(v0, (long long)shfl_xor_i64(v0, m));
-            v1 = max(v1, (long long)shfl_xor_i64(v1, m));
-            v2 = max(v2, (long long)shfl_xor_i64(v2, m));
-            v3 = min(v3, (long long)shfl_xor_i64(v3, m));
-        }
+        v0 = wave::min_all(v0);
+        v1 = wave::max_all(v1);
+        v2 = wave::max_all(v2);
+        v3 = wave::min_all(v3);
         if (threadIdx.x == 0) {
             sh[0] = v0;
             sh[1] = v1;
@@ -754,12 +757,10 @@ __device__ inline void gather_partials(const ScanArgs& g, int ph, unsigned nwg, 
 // this workgroup's partial record of phase `ph` from per-thread values
 __device__ inline void put_partial(const ScanArgs& g, int ph, long long v0, long long v1, long long v2, long long v3,
                                    long long (*sred)[4]) {
-    for (int m = 32; m > 0; m >>= 1) {
-        v0 = min(v0, (long long)shfl_xor_i64(v0, m));
-        v1 = max(v1, (long long)shfl_xor_i64(v1, m));
-        v2 = max(v2, (long long)shfl_xor_i64(v2, m));
-        v3 = min(v3, (long long)shfl_xor_i64(v3, m));
-    }
+    v0 = wave::min_all(v0);
+    v1 = wave::max_all(v1);
+    v2 = wave::max_all(v2);
+    v3 = wave::min_all(v3);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     if (lane == 0) {
         sred[w][0] = v0;
@@ -791,12 +792,10 @@ __device__ inline void put_partial(const ScanArgs& g, int ph, long long v0, long
 // WG-level reduction of per-thread values into sh[0..3] (min, max, max, min)
 __device__ inline void reduce_local(long long v0, long long v1, long long v2, long long v3, long long (*sred)[4],
                                     long long* sh) {
-    for (int m = 32; m > 0; m >>= 1) {
-        v0 = min(v0, (long long)shfl_xor_i64(v0, m));
-        v1 = max(v1, (long long)shfl_xor_i64(v1, m));
-        v2 = max(v2, (long long)shfl_xor_i64(v2, m));
-        v3 = min(v3, (long long)shfl_xor_i64(v3, m));
-    }
+    v0 = wave::min_all(v0);
+    v1 = wave::max_all(v1);
+    v2 = wave::max_all(v2);
+    v3 = wave::min_all(v3);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     if (lane == 0) {
         sred[w][0] = v0;
@@ -822,25 +821,28 @@ __device__ inline void reduce_local(long long v0, long long v1, long long v2, lo
 
 // First event in [lo, hi) among this thread's positions lo + t + i * nthr:
 // a stop position (T >= minH) or a candidate boundary (in I, and R of the
-// next position below T).  LLONG_MAX: none.
+// next position below T), as 2 j + 1 for a stop and 2 j for a candidate, so
+// that the smallest code is the first event.  LLONG_MAX: none.
 __device__ inline long long search_part(const ScanArgs& g, int64_t lo, int64_t hi, bool hasH, long long minH,
                                         int64_t t, int64_t nthr) {
     for (int64_t j0 = lo + t; j0 < hi; j0 += 4 * nthr) {
-        int64_t Tv[4];
+        // every load of the trip at once (R of the next position whether or
+        // not j is in I): the search is bound by their latency
+        int64_t Tv[4], Rn[4];
         uint8_t in[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int64_t j = j0 + u * nthr;
             Tv[u] = j < hi ? g.T[j] : 0;
             in[u] = j < hi ? g.inI[j] : 0;
+            Rn[u] = (j < hi && j + 1 < g.n) ? g.R[j + 1] : LLONG_MIN;
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int64_t j = j0 + u * nthr;
             if (j >= hi) break;
-            bool ev = hasH && Tv[u] >= minH;
-            if (!ev && in[u]) ev = (j + 1 == g.n) || (g.R[j + 1] < Tv[u]);
-            if (ev) return j;
+            if (hasH && Tv[u] >= minH) return 2 * j + 1;
+            if (in[u] && Rn[u] < Tv[u]) return 2 * j;
         }
     }
     return LLONG_MAX;
@@ -860,8 +862,10 @@ __device__ inline void minmax_part(const ScanArgs& g, int64_t S0, int64_t b, int
     }
     if (b < g.n) {
         const int64_t bend = min(g.n, (b / kFB + 1) * kFB);
+        const int64_t sb = b / ((int64_t)kFB * kSB), blk_end = min(g.nblk, (sb + 1) * kSB);
         for (int64_t j = b + t; j < bend; j += nthr) fmx = max(fmx, (long long)g.F[j]);
-        for (int64_t blk = b / kFB + 1 + t; blk < g.nblk; blk += nthr) fmx = max(fmx, g.bmax[blk]);
+        for (int64_t blk = b / kFB + 1 + t; blk < blk_end; blk += nthr) fmx = max(fmx, g.bmax[blk]);
+        for (int64_t q = sb + 1 + t; q < g.nsb; q += nthr) fmx = max(fmx, g.bmax2[q]);
     }
 }
 
@@ -999,14 +1003,15 @@ __device__ void scan_leader(const ScanArgs& g, long long (*sred)[4], long long* 
             searched += hi - from;
             ++ph;
             failed = *s_err != 0;
-            const long long e = sh[0];
+            const long long code = sh[0];
             if (failed) break;
-            if (e == LLONG_MAX) {
+            if (code == LLONG_MAX) {
                 from = hi;
                 win = min<int64_t>(2 * win, kSearchWin);
                 continue;
             }
-            if (hasH && g.T[e] >= minH) {
+            const long long e = code >> 1;
+            if (code & 1) {
                 stop = true;  // no boundary at or after e can pass
                 break;
             }
@@ -1034,7 +1039,7 @@ __device__ void scan_leader(const ScanArgs& g, long long (*sred)[4], long long* 
             failed = *s_err != 0;
             if (failed) break;
             // min and max of the restricted loads of S, largest load below b
-            const int64_t mm = (b - S0) + (b < n ? g.nblk - b / kFB : 0);
+            const int64_t mm = (b - S0) + (b < n ? kFB + kSB + g.nsb - b / ((int64_t)kFB * kSB) : 0);
             t0 = (long long)wall_clock64();
             if (grid && mm > g.lead_pos) {
                 ++gridc[2];
@@ -1330,6 +1335,10 @@ void sg_stable_groups(Graph& g, int mode, hipStream_t s) {
     bmax.alloc(nblk, s);
     k_f_init<<<grid_for(n, kT), kT, 0, s>>>(f.K[f.cur].p, q.order.p, n, g.idbits, F.p);
     k_bmax_init<<<grid_for(nblk, 1), kT, 0, s>>>(F.p, n, bmax.p);
+    const int64_t nsb = (nblk + kSB - 1) / kSB;
+    DBuf<long long> bmax2;
+    bmax2.alloc(nsb, s);
+    k_bmax2_init<<<grid_for(nsb, 1), 64, 0, s>>>(bmax.p, nblk, bmax2.p);
     LDS_HIP(hipGetLastError());
     static int cus = 0, per[2] = {0, 0};
     if (!cus) {
@@ -1368,6 +1377,8 @@ void sg_stable_groups(Graph& g, int mode, hipStream_t s) {
     sa.F = F.p;
     sa.V = Vb.p;
     sa.bmax = bmax.p;
+    sa.bmax2 = bmax2.p;
+    sa.nsb = nsb;
     sa.nblk = nblk;
     sa.n = n;
     sa.lo = q.lo.p;
