@@ -474,7 +474,7 @@ constexpr int kScanMaxWG = 64;
 constexpr int64_t kLeadRecs = 4096;
 constexpr int64_t kLeadPos = 8192;
 
-enum : long long { PH_EXIT = 0, PH_SEARCH = 1, PH_UPDATE = 2, PH_MINMAX = 3, PH_ACCEPT = 4 };
+enum : long long { PH_EXIT = 0, PH_SEARCH = 1, PH_UPDATE = 2, PH_MINMAX = 3, PH_ACCEPT = 4, PH_UNDO = 5 };
 
 struct ScanArgs {
     PassArgs a;
@@ -559,10 +559,14 @@ __device__ inline void add_by_position(int64_t* V, int32_t key, int64_t val) {
 // (with the block maxima), and changes the loads of S's earlier members
 // through the patterns they share with the joining vertices.  Each pattern
 // is handled once, from its latest joining vertex.
+// spec (only when f0 == S0, the first boundary of a round): the joining
+// vertices are all of S, so the walk also applies, ahead of the decision,
+// the change of T that accepting S would make (accept_walk's); a rejected
+// boundary takes it back with accept_walk's negation.
 // Records [k0, k1) = [P[f0], P[b]); wave gw of nwave.
 template <int H>
 __device__ inline void update_walk(const ScanArgs& g, int64_t S0, int64_t f0, int64_t b, int64_t k0, int64_t k1,
-                                   int64_t gw, int64_t nwave) {
+                                   int64_t gw, int64_t nwave, bool spec) {
     constexpr int U = kRecRows<H>;
     const int lane = threadIdx.x & 63;
     const uint64_t D = g.a.D;
@@ -591,6 +595,11 @@ __device__ inline void update_walk(const ScanArgs& g, int64_t S0, int64_t f0, in
 #pragma unroll
             for (int i = 1; i < H; ++i) {
                 if (p[u][i] >= b) {  // stays below
+                    if (spec) {
+                        const int64_t dt = pat_contrib<H>(i, p[u], al[u], D, b, p[u][i] + 1) -
+                                           pat_contrib<H>(i, p[u], al[u], D, S0, p[u][i] + 1);
+                        if (dt != 0) atomicAdd((unsigned long long*)&g.T[p[u][i]], (unsigned long long)dt);
+                    }
                     const int64_t d = pat_contrib<H>(i, p[u], al[u], D, b, b) - pat_contrib<H>(i, p[u], al[u], D, f0, f0);
                     if (d != 0) {
                         fd[u][i - 1] = d;
@@ -625,11 +634,12 @@ __device__ inline void update_walk(const ScanArgs& g, int64_t S0, int64_t f0, in
 
 // After S = [S0, b) is accepted: the change of T_x (S ending after x) for
 // the vertices below b, from the patterns of S (each handled once, from its
-// latest vertex in S).
+// latest vertex in S); sgn = -1 takes back a change applied ahead of a
+// decision that rejected b.
 // Records [k0, k1) = [P[S0], P[b]); wave gw of nwave.
 template <int H>
 __device__ inline void accept_walk(const ScanArgs& g, int64_t S0, int64_t b, int64_t k0, int64_t k1, int64_t gw,
-                                   int64_t nwave) {
+                                   int64_t nwave, int64_t sgn) {
     constexpr int U = kRecRows<H>;
     const int lane = threadIdx.x & 63;
     const uint64_t D = g.a.D;
@@ -654,7 +664,7 @@ __device__ inline void accept_walk(const ScanArgs& g, int64_t S0, int64_t b, int
                 if (p[u][i] < b) continue;
                 const int64_t d = pat_contrib<H>(i, p[u], al[u], D, b, p[u][i] + 1) -
                                   pat_contrib<H>(i, p[u], al[u], D, S0, p[u][i] + 1);
-                if (d != 0) atomicAdd((unsigned long long*)&g.T[p[u][i]], (unsigned long long)d);
+                if (d != 0) atomicAdd((unsigned long long*)&g.T[p[u][i]], (unsigned long long)(sgn * d));
             }
         }
     }
@@ -870,6 +880,7 @@ __device__ inline void minmax_part(const ScanArgs& g, int64_t S0, int64_t b, int
 }
 
 // bounds of the accepted group S = [S0, b) and the change of T below it
+// (records [k0, k1); an empty range when the change was applied ahead)
 template <int H>
 __device__ inline void accept_part(const ScanArgs& g, int64_t S0, int64_t b, int64_t k0, int64_t k1, long long mnS,
                                    long long mxS, int64_t t, int64_t nthr, int64_t gw, int64_t nwave) {
@@ -878,7 +889,7 @@ __device__ inline void accept_part(const ScanArgs& g, int64_t S0, int64_t b, int
         g.lo[x] = mnS;
         g.hi[x] = mxS;
     }
-    accept_walk<H>(g, S0, b, k0, k1, gw, nwave);
+    accept_walk<H>(g, S0, b, k0, k1, gw, nwave, 1);
 }
 
 // this workgroup's share of a posted phase (grid-wide thread and wave indices)
@@ -891,13 +902,15 @@ __device__ inline void run_posted(const ScanArgs& g, const long long* d, long lo
         const long long first = search_part(g, d[2], d[3], d[4] != 0, d[5], t, nthr);
         put_partial(g, ph, first, LLONG_MIN, LLONG_MIN, LLONG_MAX, sred);
     } else if (d[0] == PH_UPDATE) {
-        update_walk<H>(g, d[2], d[3], d[4], d[5], d[6], gw, nwave);
+        update_walk<H>(g, d[2], d[3], d[4], d[5], d[6], gw, nwave, d[7] != 0);
     } else if (d[0] == PH_MINMAX) {
         long long vmn, vmx, fmx;
         minmax_part(g, d[2], d[3], t, nthr, vmn, vmx, fmx);
         put_partial(g, ph, vmn, vmx, fmx, LLONG_MAX, sred);
     } else if (d[0] == PH_ACCEPT) {
         accept_part<H>(g, d[2], d[3], d[4], d[5], d[6], d[7], t, nthr, gw, nwave);
+    } else if (d[0] == PH_UNDO) {
+        accept_walk<H>(g, d[2], d[3], d[4], d[5], gw, nwave, -1);
     }
 }
 
@@ -977,6 +990,7 @@ __device__ void scan_leader(const ScanArgs& g, long long (*sred)[4], long long* 
     long long ticks[4] = {0, 0, 0, 0};
     long long minH = 0;
     bool hasH = false, failed = false;
+    bool spec = false;  // the last update walk applied the change of T of accepting S ahead
     while (S0 < n && !failed) {
         ++rounds;
         bool accepted = false, stop = false;
@@ -1023,14 +1037,18 @@ __device__ void scan_leader(const ScanArgs& g, long long (*sred)[4], long long* 
             const int64_t k1 = g.P[b];
             t0 = (long long)wall_clock64();
             walked += k1 - kfb;
+            // ahead only where the separate acceptance walk would be a grid
+            // phase: a walk the leader runs alone costs less than the extra
+            // atomics of applying it ahead
+            spec = fb == S0 && grid && k1 - kfb > g.lead_recs;
             if (grid && k1 - kfb > g.lead_recs) {
                 ++gridc[1];
-                const long long d[8] = {PH_UPDATE, ph, S0, fb, b, kfb, k1, 0};
+                const long long d[8] = {PH_UPDATE, ph, S0, fb, b, kfb, k1, spec ? 1 : 0};
                 post_phase(g, posted, d);
                 run_posted<H>(g, d, sred);
                 grid_barrier(g, nwg, s_err);
             } else {
-                update_walk<H>(g, S0, fb, b, kfb, k1, w, kRW);
+                update_walk<H>(g, S0, fb, b, kfb, k1, w, kRW, spec);
                 __syncthreads();
             }
             ticks[1] += (long long)wall_clock64() - t0;
@@ -1067,20 +1085,40 @@ __device__ void scan_leader(const ScanArgs& g, long long (*sred)[4], long long* 
                 accb = b;
             } else {
                 from = b;  // resume after the boundary examined
+                if (spec) {  // take back the change of T applied ahead
+                    t0 = (long long)wall_clock64();
+                    walked += kfb - kS0;
+                    if (grid && kfb - kS0 > g.lead_recs) {
+                        ++gridc[3];
+                        const long long d[8] = {PH_UNDO, ph, S0, b, kS0, kfb, 0, 0};
+                        post_phase(g, posted, d);
+                        run_posted<H>(g, d, sred);
+                        grid_barrier(g, nwg, s_err);
+                    } else {
+                        accept_walk<H>(g, S0, b, kS0, kfb, w, kRW, -1);
+                        __syncthreads();
+                    }
+                    ticks[3] += (long long)wall_clock64() - t0;
+                    spec = false;
+                    failed = *s_err != 0;
+                }
             }
         }
         if (!accepted || failed) break;  // the rest is never accepted: no bounds
         const int64_t b = accb;  // == fb, so P[b] == kfb
         const long long t0 = (long long)wall_clock64();
-        walked += kfb - kS0;
-        if (grid && (b - S0 > g.lead_pos || kfb - kS0 > g.lead_recs)) {
+        // the change of T is still to make unless the boundary's update walk
+        // applied it ahead
+        const int64_t k0 = spec ? kfb : kS0;
+        walked += kfb - k0;
+        if (grid && (b - S0 > g.lead_pos || kfb - k0 > g.lead_recs)) {
             ++gridc[3];
-            const long long d[8] = {PH_ACCEPT, ph, S0, b, kS0, kfb, mnS, mxS};
+            const long long d[8] = {PH_ACCEPT, ph, S0, b, k0, kfb, mnS, mxS};
             post_phase(g, posted, d);
             run_posted<H>(g, d, sred);
             grid_barrier(g, nwg, s_err);
         } else {
-            accept_part<H>(g, S0, b, kS0, kfb, mnS, mxS, t, kRT, w, kRW);
+            accept_part<H>(g, S0, b, k0, kfb, mnS, mxS, t, kRT, w, kRW);
             __syncthreads();
         }
         ticks[3] += (long long)wall_clock64() - t0;
