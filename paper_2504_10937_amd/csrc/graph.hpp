@@ -148,6 +148,16 @@ struct SgState {
     DBuf<uint8_t> inI;           // position j+1 (1-based) is a strict suffix maximum of E/j
     DBuf<uint32_t> a_slot;       // split numerator of every incidence slot
     DBuf<uint32_t> a_tri;        // triangles: the three split numerators per triangle
+    // compact per-slot records in position order (the records of the vertex
+    // at position j are [rec_P[j], rec_P[j+1])): the position of the slot's
+    // own vertex, the positions of the pattern's other vertices and the
+    // split numerators.  Built by the sort / prefix pass, which counts from
+    // them, read by the stable-group scan and released after it.
+    DBuf<int64_t> rec_P;         // n + 1
+    DBuf<int32_t> rec_own;
+    DBuf<int2> rec2;             // edges: (position of the other end, a_x)
+    DBuf<int4> rec3;             // triangles: (position v, position w, a_x, a_v)
+    DBuf<uint32_t> rec3w;        // triangles: a_w
     std::vector<int64_t> gstart, gend;  // accepted groups (position ranges)
     DBuf<int64_t> lo, hi;        // per internal vertex: restricted min / max of its group, -1 if none
     int64_t rounds = 0, verifications = 0;
@@ -158,7 +168,7 @@ struct SgState {
     int64_t scan_wg = 0;  // workgroups of the last scan launch (0: none yet)
     size_t device_bytes() const {
         return order.bytes() + pos.bytes() + E.bytes() + inI.bytes() + a_slot.bytes() + a_tri.bytes() + lo.bytes() +
-               hi.bytes();
+               hi.bytes() + rec_P.bytes() + rec_own.bytes() + rec2.bytes() + rec3.bytes() + rec3w.bytes();
     }
 };
 

@@ -7,7 +7,9 @@
 //     (r asc, id desc), so one ascending radix sort of K read backwards gives
 //     the order.
 // a8  Prefix: c_j = patterns whose latest vertex (largest position) is at
-//     position j, a per-row count on the incidence CSR; E = inclusive scan;
+//     position j, counted on the per-slot records, which are stored in
+//     position order (built once here and read again by the scan); E =
+//     inclusive scan;
 //     j+1 (1-based) is in I iff E_j/(j+1) is strictly above every later
 //     E_k/(k+1) (argmax with ties to the larger index).
 // a9  Stable groups.  Candidates are the runs ending at I.  A pending group
@@ -50,11 +52,6 @@ namespace {
 
 constexpr int kT = 256;
 
-__device__ inline int64_t shfl_xor_i64(int64_t v, int m) {
-    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)(uint64_t)v, m, 64);
-    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)((uint64_t)v >> 32), m, 64);
-    return (int64_t)(((uint64_t)hi << 32) | lo);
-}
 
 // ---------------------------------------------------------------- a7 sort
 __global__ void k_sort_init(const uint64_t* K, int64_t n, uint64_t* keys, uint32_t* vals) {
@@ -173,10 +170,8 @@ __global__ void k_tri_splits(const int32_t* py, const int32_t* tos, const int32_
 }
 
 // ----------------------------------------------------- row passes (a8, a9)
-enum PassKind { PASS_COUNT = 0, PASS_R = 1, PASS_T = 2, PASS_V = 3 };
 
 struct PassArgs {
-    int kind;
     const int32_t* rid;
     const int64_t* rp;
     const int32_t* py;
@@ -188,81 +183,9 @@ struct PassArgs {
     const int32_t* row_of;  // triangles: internal vertex -> row (edges: identity below nrows)
     int64_t nrows, n_big;
     uint64_t D;
-    int64_t S0, b;   // PASS_T: S0; PASS_V: S0 and b
-    int64_t* out;    // by position
 };
 
 __device__ inline int grp(int64_t p, int64_t t1, int64_t t2) { return p < t1 ? 0 : (p < t2 ? 1 : 2); }
-
-// contribution of slot s to its row vertex x (position px)
-template <int H>
-__device__ inline int64_t slot_value(const PassArgs& a, int64_t s, int64_t px);
-
-template <>
-__device__ inline int64_t slot_value<2>(const PassArgs& a, int64_t s, int64_t px) {
-    const int64_t py = a.pos[a.py[s]];
-    if (a.kind == PASS_COUNT) return py < px ? 1 : 0;
-    int64_t t1, t2;
-    if (a.kind == PASS_R) { t1 = px; t2 = px; }
-    else if (a.kind == PASS_T) { t1 = a.S0; t2 = px + 1; }
-    else { t1 = a.S0; t2 = a.b; }
-    const int gx = grp(px, t1, t2), gy = grp(py, t1, t2);
-    if (gx < gy) return 0;                    // the other end is lower: it takes the unit
-    if (gy < gx) return (int64_t)a.D;         // x alone in the lowest group: the whole unit
-    return (int64_t)a.a_slot[s];
-}
-
-template <>
-__device__ inline int64_t slot_value<3>(const PassArgs& a, int64_t s, int64_t px) {
-    const int32_t v = a.py[2 * s], w = a.py[2 * s + 1];
-    const int64_t pv = a.pos[v], pw = a.pos[w];
-    if (a.kind == PASS_COUNT) return (pv < px && pw < px) ? 1 : 0;
-    int64_t t1, t2;
-    if (a.kind == PASS_R) { t1 = px; t2 = px; }
-    else if (a.kind == PASS_T) { t1 = a.S0; t2 = px + 1; }
-    else { t1 = a.S0; t2 = a.b; }
-    const int gx = grp(px, t1, t2), gv = grp(pv, t1, t2), gw = grp(pw, t1, t2);
-    const int gl = max(gx, max(gv, gw));
-    if (gx < gl) return 0;
-    const int64_t t = a.tos[s];
-    const int jx = tri_index(a.tri, t, v, w);
-    const int jv = (jx == 0) ? 1 : 0, jw = (jx == 2) ? 1 : 2;
-    const int64_t ax = a.a_tri[3 * t + jx], av = a.a_tri[3 * t + jv], aw = a.a_tri[3 * t + jw];
-    const int64_t freed = (gv < gl ? av : 0) + (gw < gl ? aw : 0);
-    // receiver of the freed shares: the latest vertex of the lowest group
-    bool recv = true;
-    if (gv == gl && pv > px) recv = false;
-    if (gw == gl && pw > px) recv = false;
-    return ax + (recv ? freed : 0);
-}
-
-// rows [0, n_big): one wave per row; the rest: one thread per row
-template <int H>
-__global__ __launch_bounds__(kT) void k_rowpass(PassArgs a) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t nbb = (a.n_big + 3) / 4;
-    const int64_t minpos = (a.kind == PASS_T || a.kind == PASS_V) ? a.S0 : 0;
-    if ((int64_t)blockIdx.x < nbb) {
-        const int64_t r = (int64_t)blockIdx.x * 4 + w;
-        if (r >= a.n_big) return;
-        const int32_t x = a.rid ? a.rid[r] : (int32_t)r;
-        const int64_t px = a.pos[x];
-        if (px < minpos) return;
-        int64_t acc = 0;
-        for (int64_t s = a.rp[r] + lane; s < a.rp[r + 1]; s += 64) acc += slot_value<H>(a, s, px);
-        for (int m = 32; m > 0; m >>= 1) acc += shfl_xor_i64(acc, m);
-        if (lane == 0) a.out[px] = acc;
-    } else {
-        const int64_t r = a.n_big + ((int64_t)blockIdx.x - nbb) * kT + threadIdx.x;
-        if (r >= a.nrows) return;
-        const int32_t x = a.rid ? a.rid[r] : (int32_t)r;
-        const int64_t px = a.pos[x];
-        if (px < minpos) return;
-        int64_t acc = 0;
-        for (int64_t s = a.rp[r]; s < a.rp[r + 1]; ++s) acc += slot_value<H>(a, s, px);
-        a.out[px] = acc;
-    }
-}
 
 __global__ void k_inclusive(const uint64_t* excl, const int64_t* c, int64_t n, int64_t* E) {
     const int64_t j = (int64_t)blockIdx.x * kT + threadIdx.x;
@@ -702,6 +625,33 @@ __global__ __launch_bounds__(kT) void k_rt_records(ScanArgs g, int64_t ns, int64
     }
 }
 
+
+// c_j (a8): the patterns whose latest vertex (largest position) is at
+// position j, from the records: each pattern has one record per vertex, and
+// exactly the one of its latest vertex sees every other position below its
+// own; summed per position like R and T (c starts at zero)
+template <int H>
+__global__ __launch_bounds__(kT) void k_count_records(ScanArgs g, int64_t ns, int64_t* c) {
+    constexpr int U = 4;
+    const int lane = threadIdx.x & 63;
+    const int64_t gw = ((int64_t)blockIdx.x * kT + threadIdx.x) >> 6, nwave = ((int64_t)gridDim.x * kT) >> 6;
+    for (int64_t kb = gw * 64 * U; kb < ns; kb += nwave * 64 * U) {
+        int64_t p[U][H], al[U][H];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t k = kb + 64 * u + lane;
+            if (k < ns) rec_pattern<H>(g, k, p[u], al[u]);
+            else p[u][0] = -1;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            bool latest = p[u][0] >= 0;
+#pragma unroll
+            for (int i = 1; i < H; ++i) latest = latest && p[u][i] < p[u][0];
+            add_by_position(c, (int32_t)p[u][0], latest ? 1 : 0);
+        }
+    }
+}
 
 // slots per position (rows are vertices with slots; the rest stay 0)
 __global__ void k_pos_slots(PassArgs a, uint64_t* cnt) {
@@ -1165,30 +1115,46 @@ __global__ __launch_bounds__(kRT) void k_sg_scan(ScanArgs g) {
     if (threadIdx.x == 0 && s_err) g.info[3] = 1;
 }
 
-template <int H>
-void row_pass(const SweepPlan& p, const PassArgs& a, hipStream_t s) {
-    const int64_t nbb = (p.n_big + 3) / 4;
-    const int64_t nsm = (p.nrows - p.n_big + kT - 1) / kT;
-    const int64_t blocks = nbb + nsm;
-    if (blocks <= 0) return;
-    k_rowpass<H><<<grid_for(blocks, 1), kT, 0, s>>>(a);
+// the records of every slot in position order (needs the order and the
+// split numerators)
+void build_records(Graph& g, int mode, const PassArgs& a, hipStream_t s) {
+    SgState& q = g.sg[mode == 2 ? 0 : 1];
+    const SweepPlan& pl = (mode == 2) ? g.edge_plan : g.tri_plan;
+    const int64_t n = g.n;
+    q.rec_P.alloc(n + 1, s);
+    k_fill_i64<<<grid_for(n + 1, kT), kT, 0, s>>>(q.rec_P.p, n + 1, 0);
+    LDS_HIP(hipGetLastError());
+    q.rec_own.alloc(pl.nslots, s);
+    if (mode == 2) {
+        q.rec2.alloc(pl.nslots, s);
+        q.rec3.release();
+        q.rec3w.release();
+    } else {
+        q.rec2.release();
+        q.rec3.alloc(pl.nslots, s);
+        q.rec3w.alloc(pl.nslots, s);
+    }
+    if (pl.nrows == 0) return;
+    k_pos_slots<<<grid_for(pl.nrows, kT), kT, 0, s>>>(a, (uint64_t*)q.rec_P.p);
+    exclusive_scan_u64((const uint64_t*)q.rec_P.p, (uint64_t*)q.rec_P.p, n, (uint64_t*)q.rec_P.p + n, s);
+    if (mode == 2)
+        k_slot_records<2><<<grid_for(pl.nrows, 4), kT, 0, s>>>(a, q.rec_P.p, q.rec_own.p, q.rec2.p, q.rec3.p,
+                                                               q.rec3w.p);
+    else
+        k_slot_records<3><<<grid_for(pl.nrows, 4), kT, 0, s>>>(a, q.rec_P.p, q.rec_own.p, q.rec2.p, q.rec3.p,
+                                                               q.rec3w.p);
     LDS_HIP(hipGetLastError());
 }
 
-void run_pass(const Graph& g, int mode, PassArgs a, hipStream_t s) {
-    const SweepPlan& p = (mode == 2) ? g.edge_plan : g.tri_plan;
-    a.rid = p.rid;
-    a.rp = p.rp;
-    a.py = p.py;
-    a.tos = p.own_tos.p;
-    a.tri = g.tri.p;
-    a.row_of = p.own_row_of.p;
-    a.nrows = p.nrows;
-    a.n_big = p.n_big;
-    if (mode == 2)
-        row_pass<2>(p, a, s);
-    else
-        row_pass<3>(p, a, s);
+ScanArgs record_args(const SgState& q, const PassArgs& a) {
+    ScanArgs r{};
+    r.a = a;
+    r.P = q.rec_P.p;
+    r.own = q.rec_own.p;
+    r.rec2 = q.rec2.p;
+    r.rec3 = q.rec3.p;
+    r.rec3w = q.rec3w.p;
+    return r;
 }
 
 PassArgs plan_args(const Graph& g, int mode, PassArgs a) {
@@ -1258,19 +1224,28 @@ void sg_sort_prefix(Graph& g, int mode, hipStream_t s) {
             LDS_HIP(hipGetLastError());
         }
     }
-    // a8: counts by position, prefix, suffix maxima
-    DBuf<int64_t> c;
-    c.alloc(n, s);
-    k_fill_i64<<<grid_for(n, kT), kT, 0, s>>>(c.p, n, 0);
-    LDS_HIP(hipGetLastError());
+    // the records of every slot in position order, then a8: counts by
+    // position from them, prefix, suffix maxima
     PassArgs a{};
-    a.kind = PASS_COUNT;
     a.a_slot = q.a_slot.p;
     a.a_tri = q.a_tri.p;
     a.pos = q.pos.p;
     a.D = fw_denom(mode, f.iters);
-    a.out = c.p;
-    run_pass(g, mode, a, s);
+    a = plan_args(g, mode, a);
+    build_records(g, mode, a, s);
+    DBuf<int64_t> c;
+    c.alloc(n, s);
+    k_fill_i64<<<grid_for(n, kT), kT, 0, s>>>(c.p, n, 0);
+    LDS_HIP(hipGetLastError());
+    if (p.nslots > 0) {
+        const ScanArgs ra = record_args(q, a);
+        const unsigned rg = std::min<unsigned>(grid_for(p.nslots, kT * 4), 8192u);
+        if (mode == 2)
+            k_count_records<2><<<rg, kT, 0, s>>>(ra, p.nslots, c.p);
+        else
+            k_count_records<3><<<rg, kT, 0, s>>>(ra, p.nslots, c.p);
+        LDS_HIP(hipGetLastError());
+    }
     {
         DBuf<uint64_t> ex;
         ex.alloc(n, s);
@@ -1322,38 +1297,15 @@ void sg_stable_groups(Graph& g, int mode, hipStream_t s) {
     a.D = fw_denom(mode, f.iters);
     a = plan_args(g, mode, a);
 
-    // slot records and the row of every position
+    // the slot records (kept from the sort / prefix pass unless a scan since
+    // released them)
     const SweepPlan& pl = (mode == 2) ? g.edge_plan : g.tri_plan;
-    DBuf<int64_t> P;
-    DBuf<int32_t> own;
-    DBuf<int2> rec2;
-    DBuf<int4> rec3;
-    DBuf<uint32_t> rec3w;
-    P.alloc(n + 1, s);
-    k_fill_i64<<<grid_for(n + 1, kT), kT, 0, s>>>(P.p, n + 1, 0);
-    own.alloc(pl.nslots, s);
-    if (mode == 2)
-        rec2.alloc(pl.nslots, s);
-    else {
-        rec3.alloc(pl.nslots, s);
-        rec3w.alloc(pl.nslots, s);
-    }
+    if (q.rec_P.n != (size_t)n + 1) build_records(g, mode, a, s);
+    const ScanArgs rv = record_args(q, a);
     if (pl.nrows > 0) {
-        k_pos_slots<<<grid_for(pl.nrows, kT), kT, 0, s>>>(a, (uint64_t*)P.p);
-        exclusive_scan_u64((const uint64_t*)P.p, (uint64_t*)P.p, n, (uint64_t*)P.p + n, s);
-        if (mode == 2)
-            k_slot_records<2><<<grid_for(pl.nrows, 4), kT, 0, s>>>(a, P.p, own.p, rec2.p, rec3.p, rec3w.p);
-        else
-            k_slot_records<3><<<grid_for(pl.nrows, 4), kT, 0, s>>>(a, P.p, own.p, rec2.p, rec3.p, rec3w.p);
-        LDS_HIP(hipGetLastError());
         // R_w (w's restricted load when every earlier vertex is above it) and
         // T_x for S0 = 0; T is afterwards maintained incrementally by the scan
-        ScanArgs ra{};
-        ra.a = a;
-        ra.own = own.p;
-        ra.rec2 = rec2.p;
-        ra.rec3 = rec3.p;
-        ra.rec3w = rec3w.p;
+        const ScanArgs ra = rv;
         const unsigned rg = std::min<unsigned>(grid_for(pl.nslots, kT * 4), 8192u);
         if (mode == 2)
             k_rt_records<2><<<rg, kT, 0, s>>>(ra, pl.nslots, R.p, T.p);
@@ -1428,11 +1380,11 @@ void sg_stable_groups(Graph& g, int mode, hipStream_t s) {
     sa.desc = desc.p;
     sa.lead_recs = env_i64("LDS_SCAN_LEAD_RECS", kLeadRecs);
     sa.lead_pos = env_i64("LDS_SCAN_LEAD_POS", kLeadPos);
-    sa.P = P.p;
-    sa.own = own.p;
-    sa.rec2 = rec2.p;
-    sa.rec3 = rec3.p;
-    sa.rec3w = rec3w.p;
+    sa.P = rv.P;
+    sa.own = rv.own;
+    sa.rec2 = rv.rec2;
+    sa.rec3 = rv.rec3;
+    sa.rec3w = rv.rec3w;
     if (grid == 1) {  // one workgroup needs no co-residency guarantee
         if (mode == 2)
             k_sg_scan<2><<<1, kRT, 0, s>>>(sa);
@@ -1460,6 +1412,12 @@ void sg_stable_groups(Graph& g, int mode, hipStream_t s) {
     for (int k = 0; k < 10; ++k) q.scan_profile[k] = hinfo[4 + k];
     for (int k = 4; k < 8; ++k) q.scan_profile[k] = q.scan_profile[k] * 1000 / std::max(rate_khz, 1);
     q.scan_wg = grid;
+    // the records are only read by the scan (the stream has finished it)
+    q.rec_P.release();
+    q.rec_own.release();
+    q.rec2.release();
+    q.rec3.release();
+    q.rec3w.release();
     std::vector<int64_t> hg((size_t)2 * ng);
     if (ng > 0) {
         LDS_HIP(hipMemcpyAsync(hg.data(), groups.p, hg.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));

@@ -1020,7 +1020,10 @@ size_t topk_footprint(const Graph& g, int mode, int iters) {
     const size_t T = mode == 3 && g.T > 0 ? (size_t)g.T : 0;
     const size_t fw = 2 * 8 * n + 2 * 2 * n + (size_t)iters * (size_t)p.total_words * 8 + (size_t)iters * 4 * 8 * 1024;
     const size_t sg = 4 * n + 8 * n + 8 * n + n + 4 * slots + 12 * T + 16 * n;  // order pos E inI a_slot a_tri lo hi
-    const size_t tmp = 24 * n + 24 * n + 8 * n;                                 // sort keys/values, R T V, counts
+    // sort keys / values, R T F V, counts, and the slot records (own position,
+    // other positions and splits; record offsets by position)
+    const size_t rec = slots * (mode == 2 ? 12 : 24) + 8 * (n + 1);
+    const size_t tmp = 24 * n + 32 * n + 8 * n + rec;
     return fw + sg + tmp;
 }
 
