@@ -115,20 +115,6 @@ __global__ void k_permute(const uint64_t* sk, int64_t ns, int vbits, const int64
 __global__ void k_set_last(int64_t* rowptr, int64_t idx, const uint64_t* total) { rowptr[idx] = (int64_t)*total; }
 
 // ------------------------------------------------------------- sweep plan
-__global__ void k_count_hubs(const int64_t* rp, int64_t nrows, unsigned long long* cnt) {
-    const int64_t r = (int64_t)blockIdx.x * kT + threadIdx.x;
-    const bool hub = r < nrows && (rp[r + 1] - rp[r]) > kChunk;
-    unsigned long long c = __popcll(__ballot(hub));
-    if ((threadIdx.x & 63) == 0 && c) atomicAdd(cnt, c);
-}
-
-__global__ void k_count_big(const int64_t* rp, int64_t nrows, unsigned long long* cnt) {
-    const int64_t r = (int64_t)blockIdx.x * kT + threadIdx.x;
-    const bool big = r < nrows && (rp[r + 1] - rp[r]) >= 64;
-    unsigned long long c = __popcll(__ballot(big));
-    if ((threadIdx.x & 63) == 0 && c) atomicAdd(cnt, c);
-}
-
 __global__ void k_hub_words(const int64_t* rp, int64_t n_hub, uint64_t* words) {
     const int64_t r = (int64_t)blockIdx.x * kT + threadIdx.x;
     if (r >= n_hub) return;
@@ -265,6 +251,26 @@ __global__ void k_count_deg(const int64_t* rp, int64_t nrows, int64_t deg_min, u
     const bool h = r < nrows && (rp[r + 1] - rp[r]) >= deg_min;
     unsigned long long c = __popcll(__ballot(h));
     if ((threadIdx.x & 63) == 0 && c) atomicAdd(cnt, c);
+}
+
+// rows longer than each of a few thresholds: rows are ordered by slot count,
+// descending, so each count is the end of a prefix, found by binary search
+// (one thread per threshold; a count over every row with one atomic per
+// wave spent ~0.3 ms per threshold on the one contended counter)
+constexpr int kLongerThresholds = 7;
+struct LongerThan {
+    int64_t t[kLongerThresholds];
+};
+__global__ void k_rows_longer(const int64_t* rp, int64_t nrows, LongerThan lt, int64_t* cnt) {
+    const int i = threadIdx.x;
+    if (i >= kLongerThresholds) return;
+    int64_t lo = 0, hi = nrows;  // first row with at most t slots
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (rp[mid + 1] - rp[mid] > lt.t[i]) lo = mid + 1;
+        else hi = mid;
+    }
+    cnt[i] = lo;
 }
 
 // One wave per heavy row walks the row's slots (sorted by neighbour, so each
@@ -508,22 +514,26 @@ int64_t build_heavy(SweepPlan& p, int64_t n, hipStream_t s) {
 void build_sweep_plan(SweepPlan& p, hipStream_t s, int64_t n_vertices) {
     const int64_t nrows = p.nrows;
     const int64_t n_heavy = n_vertices > 0 ? build_heavy(p, n_vertices, s) : 0;
-    DBuf<unsigned long long> cnt;
-    cnt.alloc(1, s);
-    LDS_HIP(hipMemsetAsync(cnt.p, 0, sizeof(unsigned long long), s));
-    if (nrows > 0) k_count_hubs<<<grid_for(nrows, kT), kT, 0, s>>>(p.rp, nrows, cnt.p);
-    LDS_HIP(hipGetLastError());
-    p.n_hub = (int64_t)d2h(cnt.p, s);
+    // hub rows (more than a chunk's slots) and big rows (at least 64 slots):
+    // prefixes of the rows, which are ordered by slot count
+    int64_t hub_big[kLongerThresholds] = {0, 0};
+    if (nrows > 0) {
+        const LongerThan lt{{(int64_t)kChunk, 63, 0, 0, 0, 0, 0}};
+        DBuf<int64_t> cnt;
+        cnt.alloc(kLongerThresholds, s);
+        k_rows_longer<<<1, 64, 0, s>>>(p.rp, nrows, lt, cnt.p);
+        LDS_HIP(hipGetLastError());
+        LDS_HIP(hipMemcpyAsync(hub_big, cnt.p, sizeof(hub_big), hipMemcpyDeviceToHost, s));
+        LDS_HIP(hipStreamSynchronize(s));
+    }
+    p.n_hub = hub_big[0];
     // with a 2D part, every row of more than a chunk's slots is heavy: the
     // chunks start after the heavy rows and there are no hub pieces
     if (n_heavy > 0) {
         LDS_CHECK(n_heavy >= p.n_hub, ST_INVALID, "heavy rows must include every hub row");
         p.n_hub = n_heavy;
     }
-    LDS_HIP(hipMemsetAsync(cnt.p, 0, sizeof(unsigned long long), s));
-    if (nrows > 0) k_count_big<<<grid_for(nrows, kT), kT, 0, s>>>(p.rp, nrows, cnt.p);
-    LDS_HIP(hipGetLastError());
-    p.n_big = (int64_t)d2h(cnt.p, s);
+    p.n_big = hub_big[1];
     // hub word offsets (none with a 2D part: its rows have no words there)
     p.hwo.alloc(p.n_hub + 1, s);
     if (n_heavy > 0) {
@@ -743,17 +753,17 @@ void sort_rows(Graph& g, hipStream_t s) {
     if (g.col_sorted) return;
     const int64_t ns = 2 * g.m, n = g.n;
     if (ns > 0) {
-        // rows with more than T slots form a prefix (rows are ordered by length)
-        DBuf<unsigned long long> cnt;
-        cnt.alloc(1, s);
-        auto longer = [&](int64_t T) {
-            LDS_HIP(hipMemsetAsync(cnt.p, 0, sizeof(unsigned long long), s));
-            k_count_deg<<<grid_for(n, kT), kT, 0, s>>>(g.rowptr.p, n, T + 1, cnt.p);
-            LDS_HIP(hipGetLastError());
-            return (int64_t)d2h(cnt.p, s);
-        };
-        const int64_t rb = longer(4096), r64 = longer(64), r32 = longer(32), r16 = longer(16), r8 = longer(8),
-                      r4 = longer(4), r1 = longer(1);
+        // rows with more than T slots form a prefix (rows are ordered by
+        // length): the prefix lengths for every threshold in one pass
+        LongerThan lt{{4096, 64, 32, 16, 8, 4, 1}};
+        DBuf<int64_t> cnt;
+        cnt.alloc(kLongerThresholds, s);
+        k_rows_longer<<<1, 64, 0, s>>>(g.rowptr.p, n, lt, cnt.p);
+        LDS_HIP(hipGetLastError());
+        int64_t hc[kLongerThresholds];
+        LDS_HIP(hipMemcpyAsync(hc, cnt.p, sizeof(hc), hipMemcpyDeviceToHost, s));
+        LDS_HIP(hipStreamSynchronize(s));
+        const int64_t rb = hc[0], r64 = hc[1], r32 = hc[2], r16 = hc[3], r8 = hc[4], r4 = hc[5], r1 = hc[6];
         if (rb > 0) {  // long rows: radix sort of (row, column) keys
             int64_t nk = 0;
             LDS_HIP(hipMemcpyAsync(&nk, g.rowptr.p + rb, sizeof(int64_t), hipMemcpyDeviceToHost, s));
