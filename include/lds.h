@@ -137,8 +137,11 @@ lds_status lds_frank_wolfe(lds_graph g, lds_mode mode, int32_t iters, float* r_o
  * device float[n] by caller id, gap_out host double[iters].  With gap_out
  * the per-workgroup partial sums live in a fixed 4 MiB device array per GPU
  * (held until the process ends): iters is limited to
- * 4 MiB / (8 * (4 * compute units + 5)) = 509 on a 256-CU MI355X
- * (LDS_E_INVALID beyond).  Every call on one GPU shares that array: calls
+ * 4 MiB / (8 * (4 * compute units + 5)) = 509 on a 256-CU MI355X, and to
+ * 4 MiB / (8 * (8 * compute units + 5)) = 255 for an edge graph whose
+ * two-dimensional heavy-row sweep is switched on (LDS_HEAVY_DEG; its
+ * finishing kernel adds a workgroup per CU) (LDS_E_INVALID beyond, with the
+ * limit in the message).  Every call on one GPU shares that array: calls
  * with gap_out that overlap in time on the same GPU race and must be
  * serialised by the caller.  Leaves the state as lds_frank_wolfe does,
  * except that lds_loads reports no gap afterwards; with gap_out the call

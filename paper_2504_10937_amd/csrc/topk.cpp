@@ -1068,9 +1068,11 @@ void topk_run(Graph& g, int mode, int k, int iters, hipStream_t s, std::vector<T
             hg.host->h.load(g, 3, s);
             hg.host->tri_loaded = true;
         }
+        lap(&st.ms_copy);
         std::vector<int32_t>& core = hg.host->core[mode == 2 ? 0 : 1];
         if (core.empty()) core = device_cores(g, mode, nullptr, s);
         hcp = hg.host;
+        lap(&st.ms_core);
     }
     HostCache& hc = *hcp;
     Ctx c(hc.h);
@@ -1082,7 +1084,6 @@ void topk_run(Graph& g, int mode, int k, int iters, hipStream_t s, std::vector<T
     c.loc.assign(n, -1);
     c.mark.assign(n, -1);
     std::vector<char> alive(n, 1);
-    lap(&st.ms_copy);
     // bounds from core (tr-core) numbers
     {
         const std::vector<int32_t>& core = hc.core[mode == 2 ? 0 : 1];
