@@ -100,14 +100,43 @@ def bench_batched(lds, torch, synth, np, count, plain=True):
         tp = time.perf_counter() - t0
         same = all(np.array_equal(lds.lds_loads(g, m, want_num=True)["num"], a) for g, m, a in zip(gs, modes, nums))
     work = sum((lds.lds_sweep_info(g, m)["slots"]) * it for g, m, it in zip(gs, modes, iters))
+    del b
+    # the same comparison with the FP64 gap of every iteration on both sides
+    # (LDS_BATCH_GAP; lds_frank_wolfe with the gap): loads bit for bit and
+    # gaps within FP64 rounding of the same exact sums
+    bg = lds.lds_batch_create(gs, modes, iters, gap=True, tune=tune)
+    lds.lds_batch_run(bg)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        lds.lds_batch_run(bg)
+    torch.cuda.synchronize()
+    tbg = (time.perf_counter() - t0) / reps
+    gap_res = {"batched_ms": tbg * 1e3, "batched_graphs_per_s": count / tbg}
+    if plain:
+        states = [lds.lds_loads(g, m, want_num=True, want_gap=True) for g, m in zip(gs, modes)]
+        t0 = time.perf_counter()
+        for g, m, it in zip(gs, modes, iters):
+            lds.lds_frank_wolfe(g, m, it, want_gap=True)
+        torch.cuda.synchronize()
+        tpg = time.perf_counter() - t0
+        same_g = True
+        for g, m, st in zip(gs, modes, states):
+            now = lds.lds_loads(g, m, want_num=True, want_gap=True)
+            same_g = same_g and np.array_equal(now["num"], st["num"]) and \
+                bool(np.allclose(now["gap"], st["gap"], rtol=1e-12, atol=0.0))
+        gap_res.update({"plain_ms": tpg * 1e3, "plain_graphs_per_s": count / tpg, "speedup": tpg / tbg,
+                        "identical": same_g})
+    del bg
     for g in gs:
         g.destroy()
-    del b
     res = {"graphs": count, "batched_graphs_per_s": count / tb, "plain_graphs_per_s": count / tp,
            "speedup": tp / tb, "batched_ms": tb * 1e3, "plain_ms": tp * 1e3, "kernel_ms": info["kernel_ms"],
            "kernel_graphs": info["kernel_graphs"], "plain_path_graphs": info["plain_graphs"],
-           "incidence_updates_per_s": work / tb, "bit_identical": same, "tune": info["tune"]}
-    log("batched: %.1f ms vs plain %.1f ms (x%.1f), identical %s" % (tb * 1e3, tp * 1e3, tp / tb, same))
+           "incidence_updates_per_s": work / tb, "bit_identical": same, "tune": info["tune"],
+           "with_fp64_gap": gap_res}
+    log("batched: %.1f ms vs plain %.1f ms (x%.1f), identical %s; with the gap %.1f ms vs %s ms" %
+        (tb * 1e3, tp * 1e3, tp / tb, same, tbg * 1e3, "%.1f" % gap_res["plain_ms"] if plain else "-"))
     return res
 
 

@@ -302,8 +302,10 @@ lds_status lds_batch_info(lds_batch b, int32_t* kernel_graphs, int32_t* plain_gr
 lds_status lds_batch_destroy(lds_batch b);
 
 /* Autotuner: times the candidate launch shapes (workgroup size x workgroups
- * per CU, then queue order, then the per-graph work cutoff) on this batch, `reps` timed runs each after one
- * warm-up, and returns the fastest in *best.  With cache_path, a JSON file
+ * per CU x the LDS-resident vertex threshold lds_vertices in {8192, 4096,
+ * 2048, 0}, where the workgroups' key buffers fit a CU's LDS together; then
+ * queue order; then the per-graph work cutoff) on this batch, `reps` timed
+ * runs each after one warm-up, and returns the fastest in *best.  With cache_path, a JSON file
  * keyed by a coarse signature of the batch (graph count, total work, largest
  * graph, edge / triangle mix, CU count, each rounded to a power of two) is
  * read first (no timing when the signature is present, *best_ms = -1) and

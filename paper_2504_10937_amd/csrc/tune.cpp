@@ -57,7 +57,7 @@ std::string tune_signature(const std::vector<Graph*>& gs, const std::vector<int>
         ne += modes[i] == 2 ? 1 : 0;
     }
     std::ostringstream o;
-    o << "v1/count=" << log2i((double)gs.size()) << "/cost=" << log2i(cost) << "/maxn=" << log2i((double)maxn)
+    o << "v2/count=" << log2i((double)gs.size()) << "/cost=" << log2i(cost) << "/maxn=" << log2i((double)maxn)
       << "/edgefrac=" << (gs.empty() ? 0 : (int)(4 * ne / (int64_t)gs.size())) << "/cus=" << cus();
     return o.str();
 }
@@ -114,16 +114,23 @@ void tune_cache_store(const std::string& path, const std::string& key, const Bat
     LDS_CHECK(std::rename(tmp.c_str(), path.c_str()) == 0, ST_INVALID, "cannot replace the autotune cache " + path);
 }
 
+// launch shapes: workgroup size x workgroups per CU x the largest graph
+// whose keys live in LDS (two 8-byte buffers per vertex); a shape whose
+// workgroups' key buffers do not fit one CU's 160 KB of LDS together is left
+// out, since its extra workgroups could not be resident
 std::vector<BatchTune> tune_candidates() {
     std::vector<BatchTune> c;
     for (int th : {256, 512, 1024})
-        for (int wpc : {1, 2, 4}) {
-            if (th * wpc > 2048) continue;
-            BatchTune t;
-            t.threads = th;
-            t.wg_per_cu = wpc;
-            c.push_back(t);
-        }
+        for (int wpc : {1, 2, 4})
+            for (int lv : {8192, 4096, 2048, 0}) {
+                if (th * wpc > 2048) continue;
+                if ((size_t)wpc * 2 * 8 * (size_t)lv > (size_t)150 * 1024) continue;
+                BatchTune t;
+                t.threads = th;
+                t.wg_per_cu = wpc;
+                t.lds_vertices = lv;
+                c.push_back(t);
+            }
     return c;
 }
 
@@ -155,7 +162,7 @@ BatchTune autotune(Batch& b, const std::string& cache, int reps, hipStream_t s, 
     *from_cache = false;
     double best = 1e300;
     BatchTune bt;
-    // shape of the workgroups
+    // shape of the workgroups and the LDS-resident threshold
     for (const BatchTune& c : tune_candidates()) {
         b.tune = c;
         const double ms = time_batch(b, reps, s);
