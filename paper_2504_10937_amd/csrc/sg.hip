@@ -925,6 +925,85 @@ __device__ void scan_helper(const ScanArgs& g, long long (*sred)[4], int64_t* s_
     }
 }
 
+// The leader keeps the events of its last search window in LDS, one bit
+// per position (bit i of word w: position lo + 64 w + i) for candidates and
+// for stop positions.  Within a round nothing they depend on changes (T
+// changes only when a group is accepted: a change applied ahead by an
+// update walk is taken back before the next search; minH, R and I are
+// fixed), so the search that follows a rejected boundary inside the window
+// reads the bitmaps instead of memory.
+constexpr int kEvWords = 128;  // windows of at most 8192 positions are kept
+
+// first event at or after position `from` in the kept window [lo, hi) as a
+// search code (2 j + 1 stop, 2 j candidate; LLONG_MAX none), in sh[0] and
+// returned to every thread
+__device__ inline long long first_kept(int64_t lo, int64_t hi, int64_t from, const uint64_t* evb,
+                                       const uint64_t* stb, long long* sh) {
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        const int64_t w0 = (from - lo) / 64, w1 = (hi - lo + 63) / 64;
+        long long code = LLONG_MAX;
+        for (int64_t wb = w0; wb < w1 && code == LLONG_MAX; wb += 64) {
+            const int64_t wi = wb + lane;
+            uint64_t e = 0, st = 0;
+            if (wi < w1) {
+                e = evb[wi];
+                st = stb[wi];
+                const int64_t p0 = lo + 64 * wi;  // position of bit 0
+                uint64_t keep = ~0ull;
+                if (p0 < from) keep &= ~0ull << (from - p0);
+                if (p0 + 64 > hi) keep &= (hi - p0 >= 64) ? ~0ull : ((1ull << (hi - p0)) - 1);
+                e &= keep;
+                st &= keep;
+            }
+            const uint64_t any = __ballot((e | st) != 0);
+            if (any) {
+                const int src = __ffsll((long long)any) - 1;  // first word with an event
+                const uint64_t be = (uint64_t)__shfl((unsigned long long)e, src, 64);
+                const uint64_t bs = (uint64_t)__shfl((unsigned long long)st, src, 64);
+                const int bit = __ffsll((long long)(be | bs)) - 1;
+                const int64_t j = lo + 64 * (wb + src) + bit;
+                code = ((bs >> bit) & 1) ? 2 * j + 1 : 2 * j;
+            }
+        }
+        if (lane == 0) sh[0] = code;
+    }
+    __syncthreads();
+    return sh[0];
+}
+
+// leader: the events of [lo, hi) (hi - lo <= 64 kEvWords) into the bitmaps,
+// then the first one; the loads of up to 4 kRT positions are in flight at once
+__device__ inline long long search_kept(const ScanArgs& g, int64_t lo, int64_t hi, bool hasH, long long minH,
+                                        uint64_t* evb, uint64_t* stb, long long* sh) {
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    for (int64_t base = 0; base < hi - lo; base += 4 * kRT) {
+        int64_t Tv[4], Rn[4];
+        uint8_t in[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t j = lo + base + u * kRT + t;
+            Tv[u] = j < hi ? g.T[j] : 0;
+            in[u] = j < hi ? g.inI[j] : 0;
+            Rn[u] = (j < hi && j + 1 < g.n) ? g.R[j + 1] : LLONG_MIN;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t j = lo + base + u * kRT + t;
+            const bool st = j < hi && hasH && Tv[u] >= minH;
+            const bool ev = j < hi && !st && in[u] && Rn[u] < Tv[u];
+            const uint64_t be = __ballot(ev), bs = __ballot(st);
+            const int64_t wi = (base + u * kRT) / 64 + w;
+            if (lane == 0 && wi < kEvWords) {
+                evb[wi] = be;
+                stb[wi] = bs;
+            }
+        }
+    }
+    __syncthreads();
+    return first_kept(lo, hi, lo, evb, stb, sh);
+}
+
 template <int H>
 __device__ void scan_leader(const ScanArgs& g, long long (*sred)[4], long long* sh, int64_t* s_err) {
     const unsigned nwg = gridDim.x;
@@ -941,37 +1020,51 @@ __device__ void scan_leader(const ScanArgs& g, long long (*sred)[4], long long* 
     long long minH = 0;
     bool hasH = false, failed = false;
     bool spec = false;  // the last update walk applied the change of T of accepting S ahead
+    __shared__ uint64_t evb[kEvWords], stb[kEvWords];  // the kept search window's events
     while (S0 < n && !failed) {
         ++rounds;
         bool accepted = false, stop = false;
         int64_t from = S0, accb = -1;
         long long mnS = 0, mxS = 0;
         int64_t win = 4 * kRT;  // grows while windows come back empty
+        int64_t kept_lo = 0, kept_hi = 0;  // kept window (a round's windows only)
         while (!accepted && !stop && from < n && !failed) {
             heartbeat(g, beat);
-            // first event in [from, hi)
-            const int64_t hi = min(n, from + win);
+            // first event in [from, hi): from the kept window when it holds
+            // `from`, else by a new search
+            const bool inkept = from >= kept_lo && from < kept_hi;
+            const int64_t hi = inkept ? kept_hi : min(n, from + win);
             long long t0 = (long long)wall_clock64();
-            if (grid && hi - from > g.lead_pos) {
+            if (inkept) {
+                first_kept(kept_lo, kept_hi, from, evb, stb, sh);
+            } else if (grid && hi - from > g.lead_pos) {
+                kept_lo = kept_hi = 0;
+                searched += hi - from;
                 ++gridc[0];
                 const long long d[8] = {PH_SEARCH, ph, from, hi, hasH ? 1 : 0, minH, 0, 0};
                 post_phase(g, posted, d);
                 run_posted<H>(g, d, sred);
                 grid_barrier(g, nwg, s_err);
                 gather_partials(g, ph, nwg, sh);
+            } else if (hi - from <= 64 * kEvWords) {
+                searched += hi - from;
+                search_kept(g, from, hi, hasH, minH, evb, stb, sh);
+                kept_lo = from;
+                kept_hi = hi;
             } else {
+                searched += hi - from;
+                kept_lo = kept_hi = 0;
                 const long long first = search_part(g, from, hi, hasH, minH, t, kRT);
                 reduce_local(first, LLONG_MIN, LLONG_MIN, LLONG_MAX, sred, sh);
             }
             ticks[0] += (long long)wall_clock64() - t0;
-            searched += hi - from;
             ++ph;
             failed = *s_err != 0;
             const long long code = sh[0];
             if (failed) break;
             if (code == LLONG_MAX) {
                 from = hi;
-                win = min<int64_t>(2 * win, kSearchWin);
+                if (!inkept) win = min<int64_t>(2 * win, kSearchWin);
                 continue;
             }
             const long long e = code >> 1;
