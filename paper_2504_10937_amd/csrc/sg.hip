@@ -387,17 +387,25 @@ constexpr int kRT = 512;                 // threads per workgroup of the scan
 constexpr int kRW = kRT / 64;
 constexpr int64_t kSearchWin = 1 << 20;  // largest window of positions searched in one phase
 constexpr unsigned kSpinLimit = kGridSpinLimit;
-// defaults of the launch shape: at most kScanMaxWG workgroups (one per 16384
-// vertices), and the largest walk (records) and search window / min-max /
-// bounds range (positions) that the leader runs alone (a few trips of its
-// 512 threads).  The environment variables LDS_SCAN_WG, LDS_SCAN_LEAD_RECS
-// and LDS_SCAN_LEAD_POS override them (LDS_SCAN_WG also lifts the one per
-// 16384 vertices cap), e.g. to run the grid phases on small graphs.
-constexpr int kScanMaxWG = 64;
+// defaults of the launch shape: one workgroup up to 16384 vertices, else up
+// to kScanMaxWG (as many as are resident); a posted phase goes to one
+// workgroup per kPartWork records or positions of its work (at least 8, in
+// multiples of 8), so that only the large walks spread over a wide grid; and
+// the largest walk (records) and search window / min-max / bounds range
+// (positions) that the leader runs alone (a few trips of its 512 threads).
+// The environment variables LDS_SCAN_WG, LDS_SCAN_PART_WORK,
+// LDS_SCAN_LEAD_RECS and LDS_SCAN_LEAD_POS override them (LDS_SCAN_WG also
+// on graphs of at most 16384 vertices), e.g. to run the grid phases on small
+// graphs.
+constexpr int kScanMaxWG = 128;
+constexpr int64_t kPartWork = 2048;
 constexpr int64_t kLeadRecs = 4096;
 constexpr int64_t kLeadPos = 8192;
 
 enum : long long { PH_EXIT = 0, PH_SEARCH = 1, PH_UPDATE = 2, PH_MINMAX = 3, PH_ACCEPT = 4, PH_UNDO = 5 };
+// a posted phase: kind, parity, up to six arguments, then its workgroups
+// (the first `parts` of the grid) and its barrier target
+constexpr int kDesc = 10;
 
 struct ScanArgs {
     PassArgs a;
@@ -419,6 +427,7 @@ struct ScanArgs {
     long long* part;       // 2 * gridDim * 4 partial records
     unsigned* bar;         // [0] barrier arrivals, [2] posts, [3] leader heartbeat
     long long* desc;       // the posted phase: kind, parity, up to six arguments
+    int64_t part_work;     // records or positions per workgroup of a posted phase
     int64_t lead_recs;     // largest walk the leader runs alone
     int64_t lead_pos;      // largest position range the leader runs alone
     // compact records built once per scan (k_slot_records), one per
@@ -686,15 +695,40 @@ __global__ __launch_bounds__(kT) void k_slot_records(PassArgs a, const int64_t* 
     }
 }
 
-__device__ inline void grid_barrier(const ScanArgs& g, unsigned nwg, int64_t* err) { grid_sync(g.bar, nwg, err); }
+// Barrier of the workgroups of one posted phase: the first P workgroups
+// (P = parts of the phase), the leader among them.  The arrival counter only
+// grows; the leader keeps the total of the arrivals that every phase so far
+// has asked for and posts it as the phase's target, so each participant
+// adds one and waits until the counter reaches the target.  Otherwise as
+// grid_sync: one device-scope release / acquire per workgroup (thread 0),
+// a bounded wait that raises *err.
+__device__ inline void phase_barrier(const ScanArgs& g, unsigned target, int64_t* err) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_fetch_add(g.bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned spins = 0;
+        while ((int)(__hip_atomic_load(g.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) < 0) {
+            __builtin_amdgcn_s_sleep(2);
+            if (++spins > kGridSpinLimit) {
+                *err = 1;
+                break;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
 
 // reduce the partial records of phase `ph` (4 values per workgroup: min,
-// max, max, min) into sh[0..3]
-__device__ inline void gather_partials(const ScanArgs& g, int ph, unsigned nwg, long long* sh) {
+// max, max, min) of its `parts` workgroups into sh[0..3]
+__device__ inline void gather_partials(const ScanArgs& g, int ph, unsigned parts, long long* sh) {
     if (threadIdx.x < 64) {
         long long v0 = LLONG_MAX, v1 = LLONG_MIN, v2 = LLONG_MIN, v3 = LLONG_MAX;
-        const long long* P = g.part + (int64_t)(ph & 1) * nwg * 4;
-        for (unsigned w = threadIdx.x; w < nwg; w += 64) {
+        const long long* P = g.part + (int64_t)(ph & 1) * gridDim.x * 4;
+        for (unsigned w = threadIdx.x; w < parts; w += 64) {
             v0 = min(v0, P[4 * w]);
             v1 = max(v1, P[4 * w + 1]);
             v2 = max(v2, P[4 * w + 2]);
@@ -842,10 +876,11 @@ __device__ inline void accept_part(const ScanArgs& g, int64_t S0, int64_t b, int
     accept_walk<H>(g, S0, b, k0, k1, gw, nwave, 1);
 }
 
-// this workgroup's share of a posted phase (grid-wide thread and wave indices)
+// this workgroup's share of a posted phase (thread and wave indices over the
+// phase's d[8] workgroups)
 template <int H>
 __device__ inline void run_posted(const ScanArgs& g, const long long* d, long long (*sred)[4]) {
-    const int64_t t = (int64_t)blockIdx.x * kRT + threadIdx.x, nthr = (int64_t)gridDim.x * kRT;
+    const int64_t t = (int64_t)blockIdx.x * kRT + threadIdx.x, nthr = d[8] * kRT;
     const int64_t gw = t >> 6, nwave = nthr >> 6;
     const int ph = (int)d[1];
     if (d[0] == PH_SEARCH) {
@@ -864,15 +899,22 @@ __device__ inline void run_posted(const ScanArgs& g, const long long* d, long lo
     }
 }
 
-// leader: publish phase descriptor d (uniform over the workgroup) to the helpers
+// leader: publish phase descriptor d (uniform over the workgroup) to the
+// helpers.  The post word carries the phase's sequence number and its
+// workgroup count, (seq << 9) | (parts - 1), so that a helper outside the
+// phase learns it from one load, without reading the descriptor (which the
+// leader may already be rewriting for the next phase) or invalidating its
+// caches; a helper inside it reads the descriptor, which cannot change
+// before the helper arrives at the phase's barrier.
 __device__ inline void post_phase(const ScanArgs& g, unsigned& posted, const long long* d) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __syncthreads();
     ++posted;
     if (threadIdx.x == 0) {
-        for (int i = 0; i < 8; ++i) g.desc[i] = d[i];
+        for (int i = 0; i < kDesc; ++i) g.desc[i] = d[i];
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __hip_atomic_store(g.bar + 2, posted, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(g.bar + 2, (posted << 9) | (unsigned)(d[8] - 1), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -883,16 +925,19 @@ __device__ inline void heartbeat(const ScanArgs& g, unsigned& beat) {
 
 template <int H>
 __device__ void scan_helper(const ScanArgs& g, long long (*sred)[4], int64_t* s_err) {
-    __shared__ long long sd[8];
-    const unsigned nwg = gridDim.x;
-    for (unsigned want = 1;; ++want) {
+    __shared__ long long sd[kDesc];
+    __shared__ unsigned s_seq, s_in;
+    for (unsigned want = 1;;) {
         if (threadIdx.x == 0) {
             unsigned beat = __hip_atomic_load(g.bar + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            unsigned spins = 0;
+            unsigned spins = 0, word = 0;
             bool ok = true;
-            // posts never run ahead by more than one (each posted phase ends at a grid
-            // barrier this workgroup joins), except the final exit after an error
-            while ((int)(__hip_atomic_load(g.bar + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - want) < 0) {
+            // a phase this workgroup is part of ends at a barrier it joins, so
+            // the posts run ahead of it only by phases it is not part of (or
+            // by the final exit after an error)
+            for (;;) {
+                word = __hip_atomic_load(g.bar + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if ((int)((word >> 9) - want) >= 0) break;
                 __builtin_amdgcn_s_sleep(2);
                 if ((++spins & 63) == 0) {  // the heartbeat is read now and then
                     const unsigned nb = __hip_atomic_load(g.bar + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -906,21 +951,27 @@ __device__ void scan_helper(const ScanArgs& g, long long (*sred)[4], int64_t* s_
                     break;
                 }
             }
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            if (ok) {
-                for (int i = 0; i < 8; ++i) sd[i] = g.desc[i];
-            } else {
+            s_seq = word >> 9;
+            s_in = ok ? (blockIdx.x <= (word & 511u) ? 1u : 0u) : 1u;
+            if (!ok) {
                 *s_err = 1;
                 sd[0] = PH_EXIT;
+            } else if (s_in) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                for (int i = 0; i < kDesc; ++i) sd[i] = g.desc[i];
             }
         }
         __syncthreads();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        long long d[8];
-        for (int i = 0; i < 8; ++i) d[i] = sd[i];
+        const unsigned seq = s_seq, in = s_in;
+        __syncthreads();  // read by every thread before thread 0 rewrites them
+        want = seq + 1;
+        if (!in) continue;  // not one of this phase's workgroups
+        long long d[kDesc];
+        for (int i = 0; i < kDesc; ++i) d[i] = sd[i];
         if (d[0] == PH_EXIT) break;
         run_posted<H>(g, d, sred);
-        grid_barrier(g, nwg, s_err);
+        phase_barrier(g, (unsigned)d[9], s_err);
         if (*s_err) break;
     }
 }
@@ -1020,6 +1071,24 @@ __device__ void scan_leader(const ScanArgs& g, long long (*sred)[4], long long* 
     long long minH = 0;
     bool hasH = false, failed = false;
     bool spec = false;  // the last update walk applied the change of T of accepting S ahead
+    // a posted phase goes to the first parts_for(work) workgroups: one per
+    // part_work records or positions, in multiples of 8, at least 8, so
+    // that only the large walks occupy a wide grid
+    unsigned arrivals = 0;  // barrier arrivals that every phase posted so far asks for
+    auto parts_for = [&](int64_t work) -> long long {
+        int64_t p = (work + g.part_work - 1) / g.part_work;
+        p = max<int64_t>(8, (p + 7) / 8 * 8);
+        return (long long)min<int64_t>((int64_t)nwg, p);
+    };
+    auto grid_phase = [&](long long* d, bool gather) {
+        arrivals += (unsigned)d[8];
+        d[9] = (long long)arrivals;
+        post_phase(g, posted, d);
+        run_posted<H>(g, d, sred);
+        phase_barrier(g, arrivals, s_err);
+        if (gather) gather_partials(g, (int)d[1], (unsigned)d[8], sh);
+        if (posted >= (1u << 23) - 2) *s_err = 1;  // the post word holds 23 bits of sequence
+    };
     __shared__ uint64_t evb[kEvWords], stb[kEvWords];  // the kept search window's events
     while (S0 < n && !failed) {
         ++rounds;
@@ -1041,11 +1110,8 @@ __device__ void scan_leader(const ScanArgs& g, long long (*sred)[4], long long* 
                 kept_lo = kept_hi = 0;
                 searched += hi - from;
                 ++gridc[0];
-                const long long d[8] = {PH_SEARCH, ph, from, hi, hasH ? 1 : 0, minH, 0, 0};
-                post_phase(g, posted, d);
-                run_posted<H>(g, d, sred);
-                grid_barrier(g, nwg, s_err);
-                gather_partials(g, ph, nwg, sh);
+                long long d[kDesc] = {PH_SEARCH, ph, from, hi, hasH ? 1 : 0, minH, 0, 0, parts_for(hi - from), 0};
+                grid_phase(d, true);
             } else if (hi - from <= 64 * kEvWords) {
                 searched += hi - from;
                 search_kept(g, from, hi, hasH, minH, evb, stb, sh);
@@ -1086,10 +1152,8 @@ __device__ void scan_leader(const ScanArgs& g, long long (*sred)[4], long long* 
             spec = fb == S0 && grid && k1 - kfb > g.lead_recs;
             if (grid && k1 - kfb > g.lead_recs) {
                 ++gridc[1];
-                const long long d[8] = {PH_UPDATE, ph, S0, fb, b, kfb, k1, spec ? 1 : 0};
-                post_phase(g, posted, d);
-                run_posted<H>(g, d, sred);
-                grid_barrier(g, nwg, s_err);
+                long long d[kDesc] = {PH_UPDATE, ph, S0, fb, b, kfb, k1, spec ? 1 : 0, parts_for(k1 - kfb), 0};
+                grid_phase(d, false);
             } else {
                 update_walk<H>(g, S0, fb, b, kfb, k1, w, kRW, spec);
                 __syncthreads();
@@ -1104,11 +1168,8 @@ __device__ void scan_leader(const ScanArgs& g, long long (*sred)[4], long long* 
             t0 = (long long)wall_clock64();
             if (grid && mm > g.lead_pos) {
                 ++gridc[2];
-                const long long d[8] = {PH_MINMAX, ph, S0, b, 0, 0, 0, 0};
-                post_phase(g, posted, d);
-                run_posted<H>(g, d, sred);
-                grid_barrier(g, nwg, s_err);
-                gather_partials(g, ph, nwg, sh);
+                long long d[kDesc] = {PH_MINMAX, ph, S0, b, 0, 0, 0, 0, parts_for(mm), 0};
+                grid_phase(d, true);
             } else {
                 long long vmn, vmx, fmx;
                 minmax_part(g, S0, b, t, kRT, vmn, vmx, fmx);
@@ -1133,10 +1194,8 @@ __device__ void scan_leader(const ScanArgs& g, long long (*sred)[4], long long* 
                     walked += kfb - kS0;
                     if (grid && kfb - kS0 > g.lead_recs) {
                         ++gridc[3];
-                        const long long d[8] = {PH_UNDO, ph, S0, b, kS0, kfb, 0, 0};
-                        post_phase(g, posted, d);
-                        run_posted<H>(g, d, sred);
-                        grid_barrier(g, nwg, s_err);
+                        long long d[kDesc] = {PH_UNDO, ph, S0, b, kS0, kfb, 0, 0, parts_for(kfb - kS0), 0};
+                        grid_phase(d, false);
                     } else {
                         accept_walk<H>(g, S0, b, kS0, kfb, w, kRW, -1);
                         __syncthreads();
@@ -1156,10 +1215,8 @@ __device__ void scan_leader(const ScanArgs& g, long long (*sred)[4], long long* 
         walked += kfb - k0;
         if (grid && (b - S0 > g.lead_pos || kfb - k0 > g.lead_recs)) {
             ++gridc[3];
-            const long long d[8] = {PH_ACCEPT, ph, S0, b, k0, kfb, mnS, mxS};
-            post_phase(g, posted, d);
-            run_posted<H>(g, d, sred);
-            grid_barrier(g, nwg, s_err);
+            long long d[kDesc] = {PH_ACCEPT, ph, S0, b, k0, kfb, mnS, mxS, parts_for(max(b - S0, kfb - k0)), 0};
+            grid_phase(d, false);
         } else {
             accept_part<H>(g, S0, b, k0, kfb, mnS, mxS, t, kRT, w, kRW);
             __syncthreads();
@@ -1177,7 +1234,7 @@ __device__ void scan_leader(const ScanArgs& g, long long (*sred)[4], long long* 
         kS0 = kfb;
     }
     if (grid) {
-        const long long d[8] = {PH_EXIT, 0, 0, 0, 0, 0, 0, 0};
+        const long long d[kDesc] = {PH_EXIT, 0, 0, 0, 0, 0, 0, 0, (long long)nwg, 0};  // every helper leaves
         post_phase(g, posted, d);
     }
     if (threadIdx.x == 0) {
@@ -1432,24 +1489,25 @@ void sg_stable_groups(Graph& g, int mode, hipStream_t s) {
         LDS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[1], k_sg_scan<3>, kRT, 0));
     }
     const int64_t resident = (int64_t)cus * std::max(1, per[mode == 2 ? 0 : 1]);
-    // the helpers only join the large phases; a grid barrier costs more the
-    // more workgroups meet at it
+    // the helpers only join the large phases, and each phase only as many of
+    // them as its work needs
     auto env_i64 = [](const char* name, int64_t def) {
         const char* v = std::getenv(name);
         return (v && *v) ? std::max<int64_t>(0, std::atoll(v)) : def;
     };
     const int64_t wg_env = env_i64("LDS_SCAN_WG", 0);
     const int64_t grid = std::max<int64_t>(
-        1, std::min<int64_t>({resident, wg_env ? wg_env : (int64_t)kScanMaxWG, wg_env ? resident : (n + 16383) / 16384}));
+        1, wg_env ? std::min<int64_t>(resident, wg_env)
+                  : (n <= 16384 ? 1 : std::min<int64_t>(resident, (int64_t)kScanMaxWG)));
     groups.alloc(2 * n, s);
     info.alloc(16, s);
     part.alloc((size_t)2 * grid * 4, s);
     bar.alloc(4, s);
     DBuf<long long> desc;
-    desc.alloc(8, s);
+    desc.alloc(kDesc, s);
     k_fill_i64<<<1, kT, 0, s>>>(info.p, 16, 0);
     k_fill_i64<<<1, kT, 0, s>>>((int64_t*)bar.p, 2, 0);
-    k_fill_i64<<<1, kT, 0, s>>>((int64_t*)desc.p, 8, 0);
+    k_fill_i64<<<1, kT, 0, s>>>((int64_t*)desc.p, kDesc, 0);
     LDS_HIP(hipGetLastError());
     ScanArgs sa{};
     sa.a = a;
@@ -1472,6 +1530,7 @@ void sg_stable_groups(Graph& g, int mode, hipStream_t s) {
     sa.bar = bar.p;
     sa.desc = desc.p;
     sa.lead_recs = env_i64("LDS_SCAN_LEAD_RECS", kLeadRecs);
+    sa.part_work = std::max<int64_t>(1, env_i64("LDS_SCAN_PART_WORK", kPartWork));
     sa.lead_pos = env_i64("LDS_SCAN_LEAD_POS", kLeadPos);
     sa.P = rv.P;
     sa.own = rv.own;

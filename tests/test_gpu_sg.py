@@ -95,7 +95,37 @@ def test_grid_shapes(case, shape, monkeypatch):
     announce("sg grid", SHAPES[shape], kind, kw, mode, iters)
     n, s, d = synth.erdos_renyi(**kw) if kind == "er" else (
         synth.powerlaw_planted(**kw) if kind == "pl" else synth.holme_kim(**kw))
-    check_sg(n, s, d, mode, iters)
+    g, groups = check_sg(n, s, d, mode, iters)
+    check_scan_info(g, mode, groups, int(SHAPES[shape]["LDS_SCAN_WG"]))
+
+
+def check_scan_info(g, mode, groups, wg):
+    """the scan's phase profile (lds_sg_scan_info) is consistent with its
+    result and launch shape"""
+    info = lds.lds_sg_scan_info(g, mode)
+    assert info["groups"] == len(groups)
+    assert info["rounds"] >= info["groups"] and info["rounds"] <= info["groups"] + 1
+    assert info["verifications"] >= info["groups"]
+    assert info["workgroups"] == wg
+    for k in ("search", "update", "minmax", "accept"):
+        assert 0 <= info["grid_" + k] and info["us_" + k] >= 0
+    assert info["grid_update"] <= info["verifications"] and info["grid_minmax"] <= info["verifications"]
+    if wg == 1:
+        assert all(info["grid_" + k] == 0 for k in ("search", "update", "minmax", "accept"))
+    assert info["walked"] >= 0 and info["searched"] >= 0
+
+
+def test_scan_info_default_shape_and_errors():
+    """below 16,384 vertices the scan is one workgroup with no grid phase;
+    before any scan the profile is an error"""
+    n, s, d, mode, iters, _ = synth.workload("lds_small")
+    g = lds.lds_create_graph(n, s, d)
+    with pytest.raises(lds.LdsError):
+        lds.lds_sg_scan_info(g, mode)
+    lds.lds_frank_wolfe(g, mode, iters)
+    groups, _, _ = lds.lds_stable_groups(g, mode)
+    check_scan_info(g, mode, groups, 1)
+    g.destroy()
 
 
 @pytest.mark.parametrize("mode", [2, 3])
