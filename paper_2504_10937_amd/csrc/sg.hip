@@ -74,13 +74,40 @@ __global__ void k_order(const uint32_t* vals, int64_t n, int32_t* order, int64_t
 // that the bit position of a slot is known without a row search.  A block
 // takes one hub-row piece or one chunk (at most kPiece slots either way, so
 // the largest rows do not serialise in one block) in spans of kSpanW
-// decision words (64 slots each).  The span's words of kIterB iterations at a time are staged in LDS
-// by coalesced loads (a wave loads four whole 128-byte segments), and each
-// thread then tests the bits of its slots there (the lanes of a wave read
-// one word: a broadcast), so every decision word is read from memory once
-// per block, by vector loads.
+// decision words (64 slots each).  The span's words of kIterB = 64
+// iterations at a time are staged in LDS by coalesced loads.  A wave then
+// takes a word column (64 slots x 64 iterations, lane l holding iteration
+// l's word), transposes that bit matrix across its lanes (six exchange
+// steps), so that lane s holds slot s's 64 decisions, and sums the
+// increments c (j + 1) of the iterations j = i0 + i + 1 it won (bit i of
+// its mask m) with popcounts:
+//   sum over won i of (i0 + i + 2) = (i0 + 2) popc(m) + sum_k 2^k popc(m & M_k),
+// M_k the batch rows whose index i has bit k set.
 constexpr int kSpanW = 16;
 constexpr int kIterB = 64;
+
+__device__ inline uint64_t shfl_xor_u64(uint64_t v, int m) {
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m, 64);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// 64 x 64 bit transpose across a wave: on entry lane l holds row l, on exit
+// lane s holds column s (bit l = bit s of row l).  Step j swaps the
+// off-diagonal j x j blocks of every 2j x 2j block.  All 64 lanes active.
+__device__ inline uint64_t wave_transpose64(uint64_t x) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t masks[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull, 0x00FF00FF00FF00FFull,
+                               0x0F0F0F0F0F0F0F0Full, 0x3333333333333333ull, 0x5555555555555555ull};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const int j = 32 >> k;
+        const uint64_t m = masks[k];
+        const uint64_t p = shfl_xor_u64(x, j);
+        x = (lane & j) ? ((x & ~m) | ((p >> j) & m)) : ((x & m) | ((p & m) << j));
+    }
+    return x;
+}
 
 __global__ __launch_bounds__(kT) void k_slot_splits(const int64_t* rp, int64_t n_pieces, const int32_t* hp_row,
                                                     const int32_t* hp_off, const int64_t* hwo, int64_t n_chunks,
@@ -88,7 +115,9 @@ __global__ __launch_bounds__(kT) void k_slot_splits(const int64_t* rp, int64_t n
                                                     const uint64_t* bits, int64_t total_words, int iters, int tri,
                                                     int64_t heavy_positions, int64_t heavy_word0,
                                                     const uint32_t* heavy_csr, uint32_t* a_slot) {
-    __shared__ uint64_t sw[kIterB][kSpanW];
+    // one padding word per iteration row: the lanes of a wave read one
+    // column, 17 words apart, so their reads spread over the banks
+    __shared__ uint64_t sw[kIterB][kSpanW + 1];
     const int64_t b = blockIdx.x;
     int64_t s0, s1, word0;
     bool heavy = false;  // positions of the 2D part: the slot of position x is heavy_csr[x]
@@ -110,39 +139,41 @@ __global__ __launch_bounds__(kT) void k_slot_splits(const int64_t* rp, int64_t n
         word0 = heavy_word0 + s0 / 64;
         heavy = true;
     }
-    constexpr int kPer = 64 * kSpanW / kT;  // slots per thread and span
-    const int t = threadIdx.x;
-    // split numerators are at most D, which the 32-bit per-slot array holds;
-    // each iteration's test is one bit extract and one 24-bit multiply-add
-    // (the increments c2 (i + 1) are far below 2^24)
+    constexpr int kWaves = kT / 64;
+    constexpr int kCols = kSpanW / kWaves;  // word columns per wave and span
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    // split numerators are at most D, which the 32-bit per-slot array holds
     const uint32_t a0 = tri ? 2u : 1u, c2 = tri ? 6u : 2u;
-    const uint32_t* sw32 = reinterpret_cast<const uint32_t*>(&sw[0][0]);
     for (int64_t base = s0; base < s1; base += 64 * kSpanW) {
         const int64_t w0 = word0 + (base - s0) / 64;
         const int64_t nw = min<int64_t>(kSpanW, (s1 - base + 63) / 64);
-        uint32_t acc[kPer];
+        uint32_t acc[kCols];
 #pragma unroll
-        for (int q = 0; q < kPer; ++q) acc[q] = a0;
+        for (int q = 0; q < kCols; ++q) acc[q] = a0;
         for (int i0 = 0; i0 < iters; i0 += kIterB) {
             const int ni = min(kIterB, iters - i0);
             __syncthreads();  // the previous batch has been read
-            for (int e = t; e < ni * kSpanW; e += kT) {
+            for (int e = t; e < kIterB * kSpanW; e += kT) {
                 const int ii = e / kSpanW, ww = e % kSpanW;
-                sw[ii][ww] = (ww < nw) ? bits[(int64_t)(i0 + ii) * total_words + w0 + ww] : 0ull;
+                sw[ii][ww] = (ii < ni && ww < nw) ? bits[(int64_t)(i0 + ii) * total_words + w0 + ww] : 0ull;
             }
             __syncthreads();
 #pragma unroll
-            for (int q = 0; q < kPer; ++q) {
-                const int local = t + kT * q;
-                const int half = 2 * (local >> 6) + ((local >> 5) & 1), sh = local & 31;  // 32-bit half of the word
-                uint32_t inc = c2 * (uint32_t)(i0 + 2);                                 // iteration i0 + 1
-                for (int ii = 0; ii < ni; ++ii, inc += c2)
-                    acc[q] += __umul24(__builtin_amdgcn_ubfe(sw32[ii * 2 * kSpanW + half], sh, 1), inc);
+            for (int q = 0; q < kCols; ++q) {
+                const int c = w + kWaves * q;
+                const uint64_t m = wave_transpose64(sw[lane][c]);  // lane: its slot's 64 iterations
+                uint32_t sum = (uint32_t)(i0 + 2) * (uint32_t)__popcll(m);
+#pragma unroll
+                for (int k = 0; k < 6; ++k) {
+                    const uint64_t mk = ~0ull / ((1ull << (1 << k)) + 1ull) << (1 << k);  // bit k of the index set
+                    sum += (uint32_t)__popcll(m & mk) << k;
+                }
+                acc[q] += c2 * sum;
             }
         }
 #pragma unroll
-        for (int q = 0; q < kPer; ++q) {
-            const int64_t s = base + t + kT * q;
+        for (int q = 0; q < kCols; ++q) {
+            const int64_t s = base + 64 * (w + kWaves * q) + lane;
             if (s < s1) {
                 if (!heavy) {
                     a_slot[s] = acc[q];
