@@ -3,8 +3,9 @@ Alg. 2 (sort, prefix, index set I, stable groups and their bounds) on a
 120,000-vertex power-law graph with planted blocks, both modes, at the
 benchmark iteration counts (edges N = 100, triangles N = 200).
 
-The graph is large enough that the library's sweep gathers most codes from
-memory (internal ids >= 77,824) and its stable-group scan runs in its default
+The graph is large enough that the library's sweep gathers the codes of
+about a third of its vertices from memory (internal ids >= 77,824) and its
+stable-group scan runs in its default
 multi-workgroup shape (more than 16,384 vertices); the oracle's literal
 ExtractSG is O(|I| (n + |P|)), minutes at this size, too slow for a test, so
 its results are stored here as sha256 digests.

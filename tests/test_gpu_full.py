@@ -162,9 +162,9 @@ def test_ltds_hk_full_size():
 
 @pytest.mark.parametrize("which", ["edge", "triangle"])
 def test_mid_size_exact_alg2(which):
-    """120,000 vertices: most gathered codes come from memory (internal ids >=
-    77,824) and the stable-group scan runs in its default multi-workgroup
-    shape; loads, order, prefix, I, groups and bounds exactly as the oracle's
+    """120,000 vertices: the codes of about a third of them (internal ids >=
+    77,824) are gathered from memory, and the stable-group scan runs in its
+    default multi-workgroup shape; loads, order, prefix, I, groups and bounds exactly as the oracle's
     literal Alg. 2 (digests from tests/golden/make_mid_size.py)."""
     ref = golden("mid_size_%s.json" % which)
     n, s, d = synth.powerlaw_planted(**ref["graph"])
