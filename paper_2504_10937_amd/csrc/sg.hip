@@ -576,6 +576,11 @@ __device__ inline void update_walk(const ScanArgs& g, int64_t S0, int64_t f0, in
                 }
             }
         }
+        // the joining vertices' own loads first: their segmented sums need
+        // no value the returning atomics above bring back, so they run while
+        // those are in flight
+#pragma unroll
+        for (int u = 0; u < U; ++u) add_by_position(g.V, (int32_t)p[u][0], own[u]);
         // block maxima only grow (F only grows, bmax only by atomicMax): a
         // read that is at least the new value, even a stale one or one made
         // before the add, makes the atomic redundant
@@ -590,8 +595,6 @@ __device__ inline void update_walk(const ScanArgs& g, int64_t S0, int64_t f0, in
                         atomicMax(&g.bmax2[p[u][i + 1] / ((int64_t)kFB * kSB)], nv);
                     }
                 }
-#pragma unroll
-        for (int u = 0; u < U; ++u) add_by_position(g.V, (int32_t)p[u][0], own[u]);
     }
 }
 
