@@ -29,9 +29,10 @@ sys.path.insert(0, ROOT)
 # streams at once, whose small kernels otherwise wait behind each other on
 # four queues (20 s at 200 QPS offered: 137 completions/s with 4, 160 with 8,
 # 172 with 16).  Read by the runtime when it starts, so it is set before
-# torch or the library touch the GPU; a value already in the environment is
-# kept.  The single-stream sections do not depend on it.
-HW_QUEUES = os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
+# torch or the library touch the GPU (LDS_BENCH_HW_QUEUES chooses another
+# count, at most 32).  The single-stream sections do not depend on it.
+HW_QUEUES = str(min(32, max(1, int(os.environ.get("LDS_BENCH_HW_QUEUES", "16")))))
+os.environ["GPU_MAX_HW_QUEUES"] = HW_QUEUES
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
@@ -295,7 +296,7 @@ def _serve_run(lds, np, srv, gs, seconds, qps, seed, tag0, keep=0):
     return res, q, kept
 
 
-def bench_serving(lds, torch, synth, np, seconds, qps, ladder, plain_sample, p99_bound_ms=2000.0):
+def bench_serving(lds, torch, synth, np, seconds, qps, ladder, plain_sample, p99_bound_ms=2000.0, workers=12):
     """The serving workload: a resident pool of 64 graphs (pool member g,
     seed 5 + g, graph 0 pinned at n = 2M), Poisson arrivals, graph uniform
     over the pool, LDS / LTDS half and half (100 / 200 FW iterations), k
@@ -312,7 +313,7 @@ def bench_serving(lds, torch, synth, np, seconds, qps, ladder, plain_sample, p99
     for g in gs:
         lds.lds_triangles(g)
     torch.cuda.synchronize()
-    srv = lds.lds_server_create(0, max_slots=64, workers=12)
+    srv = lds.lds_server_create(0, max_slots=64, workers=workers)
     # warm-up: one query per (graph, mode), so that each graph's resident
     # host data (adjacency, core numbers) exists
     for i, g in enumerate(gs):
@@ -322,7 +323,7 @@ def bench_serving(lds, torch, synth, np, seconds, qps, ladder, plain_sample, p99
     while got < 2 * len(gs):
         got += len(lds.lds_server_poll(srv, 256, 1.0))
     res = {"pool_graphs": len(gs), "pool_vertices": int(sum(p[0] for p in pool)),
-           "pool_edges": int(sum(len(p[1]) for p in pool)), "workers": 12, "hw_queues": int(HW_QUEUES)}
+           "pool_edges": int(sum(len(p[1]) for p in pool)), "workers": workers, "hw_queues": int(HW_QUEUES)}
     log("serving: %g QPS for %g s" % (qps, seconds))
     res["offered"], stream, served = _serve_run(lds, np, srv, gs, seconds, qps, 5, 0, keep=plain_sample)
     log("serving: %s" % res["offered"])
@@ -388,8 +389,9 @@ def main():
     ap.add_argument("--clique4", default="clique4_pl", help="4-clique FW workload ('' to skip)")
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="arrival window of the serving run (0: skip)")
     ap.add_argument("--serve-qps", type=float, default=200.0)
-    ap.add_argument("--serve-ladder", default="50,100,150",
+    ap.add_argument("--serve-ladder", default="50,100,150,175",
                     help="offered rates (QPS) tried for the highest sustained load ('' to skip)")
+    ap.add_argument("--serve-workers", type=int, default=12, help="verification worker threads of the server")
     ap.add_argument("--serve-plain", type=int, default=200,
                     help="queries of the offered stream also run one at a time by lds_topk (0: skip)")
     args = ap.parse_args()
@@ -525,7 +527,8 @@ def main():
         out["clique4"] = bench_clique4(lds, torch, synth, args.clique4)
     if args.serve_seconds > 0:
         out["serving"] = bench_serving(lds, torch, synth, np, args.serve_seconds, args.serve_qps,
-                                       [float(x) for x in args.serve_ladder.split(",") if x], args.serve_plain)
+                                       [float(x) for x in args.serve_ladder.split(",") if x], args.serve_plain,
+                                       workers=args.serve_workers)
     if not args.no_cpu_baseline:
         import oracle
         log("cpu baseline: oracle ingest (untimed)")
