@@ -433,7 +433,11 @@ lds_status lds_footprint(lds_graph g, lds_mode mode, int32_t iters, size_t* byte
 /* hbm_budget: device bytes that admitted queries may add together (0 = 90%
  * of the device memory free now); max_slots: queries admitted at once;
  * workers: verification threads (1..64).  A query whose footprint exceeds
- * the budget completes with LDS_E_NOMEM. */
+ * the budget completes with LDS_E_NOMEM.  The server runs 5 + workers
+ * streams; the HIP runtime maps a process's streams onto GPU_MAX_HW_QUEUES
+ * hardware queues (4 unless set before the runtime starts), and with more
+ * queues (e.g. 16) the workers' small kernels stop waiting behind each
+ * other. */
 lds_status lds_server_create(size_t hbm_budget, int32_t max_slots, int32_t workers, lds_server* out);
 /* t_arrive < 0: now.  For a triangle query on a graph whose triangles are
  * not listed yet, lists them first (the call waits for it). */
