@@ -1530,9 +1530,10 @@ void sg_stable_groups(Graph& g, int mode, hipStream_t s) {
         return (v && *v) ? std::max<int64_t>(0, std::atoll(v)) : def;
     };
     const int64_t wg_env = env_i64("LDS_SCAN_WG", 0);
-    const int64_t grid = std::max<int64_t>(
-        1, wg_env ? std::min<int64_t>(resident, wg_env)
-                  : (n <= 16384 ? 1 : std::min<int64_t>(resident, (int64_t)kScanMaxWG)));
+    // (at most 512: the post word holds a phase's workgroup count in 9 bits)
+    const int64_t grid = std::min<int64_t>(
+        512, std::max<int64_t>(1, wg_env ? std::min<int64_t>(resident, wg_env)
+                                         : (n <= 16384 ? 1 : std::min<int64_t>(resident, (int64_t)kScanMaxWG))));
     groups.alloc(2 * n, s);
     info.alloc(16, s);
     part.alloc((size_t)2 * grid * 4, s);
