@@ -205,3 +205,40 @@ def test_split_width_limit():
     groups, lo, hi = lds.lds_stable_groups(g, 3)
     assert len(groups) >= 1
     g.destroy()
+
+
+def test_concurrent_wide_scans():
+    """Two stable-group scans of graphs above 16,384 vertices (so each is a
+    cooperative launch of the wide grid) run at once from two threads on two
+    streams, as serving workers do; each gives what it gives alone."""
+    import threading
+    graphs = [synth.powerlaw_planted(40000, 2.1, 10.0, n_blocks=12, s_lo=30, s_hi=200, p_block=0.3, seed=s)
+              for s in (41, 42)]
+    gs, want = [], []
+    for n, s, d in graphs:
+        announce("concurrent scans", n)
+        g = lds.lds_create_graph(n, s, d)
+        lds.lds_frank_wolfe(g, 2, 60)
+        want.append(lds.lds_stable_groups(g, 2))
+        assert lds.lds_sg_scan_info(g, 2)["workgroups"] > 1
+        gs.append(g)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        got = [None, None]
+        streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+
+        def run(i):
+            got[i] = lds.lds_stable_groups(gs[i], 2, stream=streams[i])
+
+        ts = [threading.Thread(target=run, args=(i,)) for i in range(2)]
+        for t in ts:
+            t.start()
+        for t in ts:
+            t.join()
+        torch.cuda.synchronize()
+        for (wg, wlo, whi), (gg, glo, ghi) in zip(want, got):
+            assert gg == wg
+            np.testing.assert_array_equal(glo, wlo)
+            np.testing.assert_array_equal(ghi, whi)
+    for g in gs:
+        g.destroy()
