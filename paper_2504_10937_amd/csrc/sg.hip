@@ -496,11 +496,15 @@ __device__ inline void rec_pattern<3>(const ScanArgs& g, int64_t k, int64_t* p, 
 }
 
 // Record walks.  A wave takes kRecRows(H) rows of 64 consecutive records per
-// trip (lane l reads record base + 64 u + l of row u, so every load is
-// coalesced) and keeps the loads, the atomics and the reads that depend on
-// them of all its rows in flight together: the walks are bound by the
-// latency of these dependent accesses, not by bandwidth, and a long row no
-// longer runs as one wave's serial loop.
+// trip (lane l reads record 64 r + l of row r, so every load is coalesced)
+// and keeps the loads, the atomics and the reads that depend on them of all
+// its rows in flight together: the walks are bound by the latency of these
+// dependent accesses, not by bandwidth, and a long row no longer runs as one
+// wave's serial loop.  Rows go round-robin over the walk's waves (row r to
+// wave r mod nwave), so a walk shorter than one full trip spreads over every
+// workgroup of its phase: a compute unit issues its scattered atomics and
+// reads about one address per cycle, and a walk that filled the first
+// workgroups' waves alone queued them on a few compute units.
 template <int H>
 constexpr int kRecRows = (H == 2) ? 8 : 4;
 
@@ -533,11 +537,11 @@ __device__ inline void update_walk(const ScanArgs& g, int64_t S0, int64_t f0, in
     constexpr int U = kRecRows<H>;
     const int lane = threadIdx.x & 63;
     const uint64_t D = g.a.D;
-    for (int64_t kb = k0 + gw * 64 * U; kb < k1; kb += nwave * 64 * U) {
+    for (int64_t r0 = gw; k0 + 64 * r0 < k1; r0 += nwave * U) {  // this trip: rows r0 + nwave u
         int64_t p[U][H], al[U][H];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t k = kb + 64 * u + lane;
+            const int64_t k = k0 + 64 * (r0 + nwave * u) + lane;
             if (k < k1) rec_pattern<H>(g, k, p[u], al[u]);
             else p[u][0] = -1;
         }
@@ -609,11 +613,11 @@ __device__ inline void accept_walk(const ScanArgs& g, int64_t S0, int64_t b, int
     constexpr int U = kRecRows<H>;
     const int lane = threadIdx.x & 63;
     const uint64_t D = g.a.D;
-    for (int64_t kb = k0 + gw * 64 * U; kb < k1; kb += nwave * 64 * U) {
+    for (int64_t r0 = gw; k0 + 64 * r0 < k1; r0 += nwave * U) {  // this trip: rows r0 + nwave u
         int64_t p[U][H], al[U][H];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t k = kb + 64 * u + lane;
+            const int64_t k = k0 + 64 * (r0 + nwave * u) + lane;
             if (k < k1) rec_pattern<H>(g, k, p[u], al[u]);
             else p[u][0] = -1;
         }
