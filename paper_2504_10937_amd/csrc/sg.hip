@@ -429,8 +429,8 @@ constexpr unsigned kSpinLimit = kGridSpinLimit;
 // on graphs of at most 16384 vertices), e.g. to run the grid phases on small
 // graphs.
 constexpr int kScanMaxWG = 128;
-constexpr int64_t kPartWork = 2048;
-constexpr int64_t kLeadRecs = 4096;
+constexpr int64_t kPartWork = 1024;
+constexpr int64_t kLeadRecs = 2048;
 constexpr int64_t kLeadPos = 8192;
 
 enum : long long { PH_EXIT = 0, PH_SEARCH = 1, PH_UPDATE = 2, PH_MINMAX = 3, PH_ACCEPT = 4, PH_UNDO = 5 };
