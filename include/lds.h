@@ -398,15 +398,20 @@ void lds_result_free(lds_result* r);
 /* ---- Serving: continuous batching of top-k queries on resident graphs -----
  * Queries (graph, mode, k, iters) are queued with their arrival time.  A
  * scheduler thread admits queued queries in arrival order while the device
- * memory they add (lds_footprint) fits the budget and a slot is free; a
- * query waits while an earlier query on the same (graph, mode) runs.  All
- * queries admitted together run their Frank-Wolfe iterations in one batched
- * launch (as lds_batch_run); worker threads then finish each query
- * (lds_topk's search, on their own streams) while the scheduler already
- * admits and launches the next batch.  Each query starts from the canonical
- * initial point, so its result equals lds_topk(g, mode, k, iters) run alone.
- * Graphs must stay alive until their queries complete; while the server
- * runs, the caller's own calls on a graph wait for the server's use of it. */
+ * memory they add (lds_footprint) fits the budget and a slot is free.  Each
+ * admitted query works on its own view of its graph (the graph's device data
+ * shared, its own FW and stable-group state), so queries on one (graph,
+ * mode) run at once.  The queries admitted together whose FW cost ((pattern
+ * incidences + vertices) x iters) is at most 2^22 run their Frank-Wolfe
+ * iterations in one batched launch (as lds_batch_run); larger ones run FW on
+ * their worker's stream (the environment variable LDS_SERVE_KERNEL_COST,
+ * read at lds_server_create, changes the cutoff).  Worker threads finish
+ * each query (lds_topk's search, on their own streams), taking the oldest
+ * query whose batched FW has finished, while the scheduler already admits
+ * and launches the next batch.  Each query starts from the canonical initial
+ * point, so its result equals lds_topk(g, mode, k, iters) run alone.  Graphs
+ * must stay alive until their queries complete; while the server runs, the
+ * caller's own calls on a graph wait for the server's use of it. */
 typedef struct lds_server_s* lds_server;
 
 typedef struct {

@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <set>
@@ -39,7 +40,10 @@ InFlight::~InFlight() {
 namespace {
 
 constexpr int kBatchStreams = 4;  // batched launches in flight at once
-constexpr int64_t kServeKernelCost = 1ll << 22;  // (incidences + vertices) * iters kept in the batched kernel
+// (incidences + vertices) * iters kept in the batched kernel; the
+// environment variable LDS_SERVE_KERNEL_COST overrides it
+constexpr int64_t kServeKernelCost = 1ll << 22;
+constexpr int kReadyPollUs = 500;  // a worker with only unfinished batched FW queued looks again after this
 
 double now_s(std::chrono::steady_clock::time_point t0) {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -66,6 +70,7 @@ struct Server::Impl {
     hipStream_t bstream[kBatchStreams] = {};
     int next_stream = 0;
     int device = 0;
+    int64_t kernel_cost = kServeKernelCost;
 
     void finish(SQuery& q, SDone&& d) {
         std::lock_guard<std::mutex> lk(mu);
@@ -136,7 +141,7 @@ struct Server::Impl {
                         std::lock_guard<std::mutex> g(q.h->mu);
                         cost = batch_cost(q.h->g, q.mode, q.iters);
                     }
-                    (cost > kServeKernelCost ? solo : keep).push_back(std::move(q));
+                    (cost > kernel_cost ? solo : keep).push_back(std::move(q));
                 }
                 adm.swap(keep);
             }
@@ -165,7 +170,7 @@ struct Server::Impl {
                     // latency first: a graph whose FW would keep one
                     // workgroup busy for more than a few ms runs on its own
                     // launches (the whole GPU per iteration) instead
-                    b.tune.max_kernel_cost = kServeKernelCost;
+                    b.tune.max_kernel_cost = kernel_cost;
                     for (auto& q : adm) {
                         b.gs.push_back(q.view.get());
                         b.modes.push_back(q.mode);
@@ -217,11 +222,23 @@ struct Server::Impl {
         for (;;) {
             SQuery q;
             {
+                // the oldest query that can run now: its batched FW has
+                // finished (or it has none), so the worker never sits on a
+                // launch that other queries' verification could overlap
                 std::unique_lock<std::mutex> lk(mu);
-                cv_work.wait(lk, [&] { return stop_workers || !verify.empty(); });
-                if (verify.empty()) break;  // stopping and nothing left
-                q = std::move(verify.front());
-                verify.pop_front();
+                auto ready = verify.end();
+                for (;;) {
+                    cv_work.wait(lk, [&] { return stop_workers || !verify.empty(); });
+                    if (verify.empty()) break;  // stopping and nothing left
+                    ready = std::find_if(verify.begin(), verify.end(), [](const SQuery& x) {
+                        return !x.fw || !x.fw->done || hipEventQuery(x.fw->done) != hipErrorNotReady;
+                    });
+                    if (ready != verify.end()) break;
+                    cv_work.wait_for(lk, std::chrono::microseconds(kReadyPollUs));
+                }
+                if (verify.empty()) break;
+                q = std::move(*ready);
+                verify.erase(ready);
             }
             SDone d;
             try {
@@ -254,6 +271,8 @@ struct Server::Impl {
 Server::Server(size_t budget, int max_slots, int workers) : p(new Impl) {
     p->budget = budget;
     p->max_slots = max_slots;
+    if (const char* e = std::getenv("LDS_SERVE_KERNEL_COST"))
+        if (*e) p->kernel_cost = std::max<int64_t>(0, std::atoll(e));
     LDS_HIP(hipGetDevice(&p->device));
     LDS_HIP(hipStreamCreateWithFlags(&p->sched_stream, hipStreamNonBlocking));
     for (auto& bs : p->bstream) LDS_HIP(hipStreamCreateWithFlags(&bs, hipStreamNonBlocking));
