@@ -100,6 +100,11 @@ inline unsigned grid_for(int64_t work, int per_block) {
     return static_cast<unsigned>(g);
 }
 
+// workgroups of a grid-stride reduction into a few global counters (one
+// atomic per wave): enough to fill the chip, few enough that the atomics on
+// one address stay cheap
+constexpr unsigned kReduceWG = 256;
+
 // ---------------------------------------------------------------- scan/sort
 // Exclusive prefix sum out[i] = sum_{j<i} in[i]; returns nothing, total is
 // written to *total_dev when non-null.  in and out may alias.

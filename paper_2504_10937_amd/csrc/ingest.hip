@@ -71,14 +71,23 @@ __global__ void k_row_deg(const int64_t* rstart, const int64_t* rend, int64_t n,
 }
 
 __global__ void k_maxdeg(const int32_t* deg, int64_t n, int* out, unsigned long long* nz) {
-    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
-    int d = (i < n) ? deg[i] : 0;
-    // wave-level reduction first, one atomic per wave
-    for (int off = 32; off > 0; off >>= 1) d = max(d, __shfl_xor(d, off, 64));
-    unsigned long long c = __popcll(__ballot(i < n && deg[i] > 0));
+    // grid-stride (the launch is capped at kReduceWG workgroups): one atomic
+    // per wave on each of the two counters; with a wave per 64 entries the
+    // waves of a 4M-entry array queued ~125k atomics on two addresses (0.75 ms)
+    int d = 0;
+    unsigned c = 0;  // entries > 0 (fewer than 2^32)
+    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
+        const int x = deg[i];
+        d = max(d, x);
+        c += x > 0 ? 1 : 0;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        d = max(d, __shfl_xor(d, off, 64));
+        c += (unsigned)__shfl_xor((int)c, off, 64);
+    }
     if ((threadIdx.x & 63) == 0) {
         atomicMax(out, d);
-        if (c) atomicAdd(nz, c);
+        if (c) atomicAdd(nz, (unsigned long long)c);
     }
 }
 
@@ -205,18 +214,23 @@ __global__ void k_sort_rows_lanes(const int64_t* rp, int64_t r0, int64_t r1, int
     if (e < len) col[s0 + e] = x;
 }
 
-__global__ __launch_bounds__(256) void k_sort_rows_block(const int64_t* rp, int64_t r0, int32_t* col) {
-    __shared__ int32_t v[4096];
+// rows of at most MAXP slots, one workgroup of NT threads each; the row
+// classes (65-128, 129-512, 513-4096 slots) get workgroups and LDS sized to
+// them, so that a short row neither idles a 256-thread workgroup nor holds
+// 16 KB of LDS
+template <int NT, int MAXP>
+__global__ __launch_bounds__(NT) void k_sort_rows_block(const int64_t* rp, int64_t r0, int32_t* col) {
+    __shared__ int32_t v[MAXP];
     const int64_t r = r0 + blockIdx.x;
     const int64_t s0 = rp[r];
     const int len = (int)(rp[r + 1] - s0);
     int P = 1;
     while (P < len) P <<= 1;
-    for (int i = threadIdx.x; i < P; i += 256) v[i] = (i < len) ? col[s0 + i] : INT32_MAX;
+    for (int i = threadIdx.x; i < P; i += NT) v[i] = (i < len) ? col[s0 + i] : INT32_MAX;
     __syncthreads();
     for (int k = 2; k <= P; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < P; i += 256) {
+            for (int i = threadIdx.x; i < P; i += NT) {
                 const int q = i ^ j;
                 if (q > i) {
                     const int32_t a = v[i], b = v[q];
@@ -229,7 +243,7 @@ __global__ __launch_bounds__(256) void k_sort_rows_block(const int64_t* rp, int6
             __syncthreads();
         }
     }
-    for (int i = threadIdx.x; i < len; i += 256) col[s0 + i] = v[i];
+    for (int i = threadIdx.x; i < len; i += NT) col[s0 + i] = v[i];
 }
 
 // keys (row << 32 | column) of the slots of rows [0, r1) and back
@@ -257,7 +271,7 @@ __global__ void k_count_deg(const int64_t* rp, int64_t nrows, int64_t deg_min, u
 // descending, so each count is the end of a prefix, found by binary search
 // (one thread per threshold; a count over every row with one atomic per
 // wave spent ~0.3 ms per threshold on the one contended counter)
-constexpr int kLongerThresholds = 7;
+constexpr int kLongerThresholds = 9;
 struct LongerThan {
     int64_t t[kLongerThresholds];
 };
@@ -518,7 +532,7 @@ void build_sweep_plan(SweepPlan& p, hipStream_t s, int64_t n_vertices) {
     // prefixes of the rows, which are ordered by slot count
     int64_t hub_big[kLongerThresholds] = {0, 0};
     if (nrows > 0) {
-        const LongerThan lt{{(int64_t)kChunk, 63, 0, 0, 0, 0, 0}};
+        const LongerThan lt{{(int64_t)kChunk, 63, 0, 0, 0, 0, 0, 0, 0}};
         DBuf<int64_t> cnt;
         cnt.alloc(kLongerThresholds, s);
         k_rows_longer<<<1, 64, 0, s>>>(p.rp, nrows, lt, cnt.p);
@@ -697,7 +711,7 @@ void build_graph(Graph& g, int64_t n, int64_t npairs, const int32_t* src, const 
     LDS_HIP(hipMemsetAsync(dmax.p, 0, sizeof(int), s));
     LDS_HIP(hipMemsetAsync(nz.p, 0, sizeof(unsigned long long), s));
     if (n > 0) {
-        k_maxdeg<<<grid_for(n, kT), kT, 0, s>>>(deg_orig.p, n, dmax.p, nz.p);
+        k_maxdeg<<<std::min(grid_for(n, kT), kReduceWG), kT, 0, s>>>(deg_orig.p, n, dmax.p, nz.p);
         LDS_HIP(hipGetLastError());
     }
     g.max_deg = d2h(dmax.p, s);
@@ -755,7 +769,7 @@ void sort_rows(Graph& g, hipStream_t s) {
     if (ns > 0) {
         // rows with more than T slots form a prefix (rows are ordered by
         // length): the prefix lengths for every threshold in one pass
-        LongerThan lt{{4096, 64, 32, 16, 8, 4, 1}};
+        LongerThan lt{{4096, 512, 128, 64, 32, 16, 8, 4, 1}};
         DBuf<int64_t> cnt;
         cnt.alloc(kLongerThresholds, s);
         k_rows_longer<<<1, 64, 0, s>>>(g.rowptr.p, n, lt, cnt.p);
@@ -763,7 +777,8 @@ void sort_rows(Graph& g, hipStream_t s) {
         int64_t hc[kLongerThresholds];
         LDS_HIP(hipMemcpyAsync(hc, cnt.p, sizeof(hc), hipMemcpyDeviceToHost, s));
         LDS_HIP(hipStreamSynchronize(s));
-        const int64_t rb = hc[0], r64 = hc[1], r32 = hc[2], r16 = hc[3], r8 = hc[4], r4 = hc[5], r1 = hc[6];
+        const int64_t rb = hc[0], r512 = hc[1], r128 = hc[2], r64 = hc[3], r32 = hc[4], r16 = hc[5], r8 = hc[6],
+                      r4 = hc[7], r1 = hc[8];
         if (rb > 0) {  // long rows: radix sort of (row, column) keys
             int64_t nk = 0;
             LDS_HIP(hipMemcpyAsync(&nk, g.rowptr.p + rb, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -777,7 +792,9 @@ void sort_rows(Graph& g, hipStream_t s) {
             k_row_unkeys<<<grid_for(nk, kT), kT, 0, s>>>(keys.p, nk, g.col.p);
             LDS_HIP(hipGetLastError());
         }
-        if (r64 > rb) k_sort_rows_block<<<(unsigned)(r64 - rb), 256, 0, s>>>(g.rowptr.p, rb, g.col.p);
+        if (r512 > rb) k_sort_rows_block<256, 4096><<<(unsigned)(r512 - rb), 256, 0, s>>>(g.rowptr.p, rb, g.col.p);
+        if (r128 > r512) k_sort_rows_block<128, 512><<<(unsigned)(r128 - r512), 128, 0, s>>>(g.rowptr.p, r512, g.col.p);
+        if (r64 > r128) k_sort_rows_block<64, 128><<<(unsigned)(r64 - r128), 64, 0, s>>>(g.rowptr.p, r128, g.col.p);
         LDS_HIP(hipGetLastError());
         auto lanes = [&](auto tag, int64_t a, int64_t b) {
             constexpr int S = decltype(tag)::value;

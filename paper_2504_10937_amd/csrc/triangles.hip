@@ -90,13 +90,23 @@ __global__ void k_tcount(const int32_t* tri, int64_t T, int32_t* tc) {
 }
 
 __global__ void k_tmax(const int32_t* tc, int64_t n, int* out, unsigned long long* nz) {
-    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
-    int d = (i < n) ? tc[i] : 0;
-    for (int off = 32; off > 0; off >>= 1) d = max(d, __shfl_xor(d, off, 64));
-    unsigned long long c = __popcll(__ballot(i < n && tc[i] > 0));
+    // grid-stride (the launch is capped at kReduceWG workgroups): one atomic
+    // per wave on each of the two counters; with a wave per 64 entries the
+    // waves of a 4M-entry array queued ~125k atomics on two addresses (0.75 ms)
+    int d = 0;
+    unsigned c = 0;  // entries > 0 (fewer than 2^32)
+    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
+        const int x = tc[i];
+        d = max(d, x);
+        c += x > 0 ? 1 : 0;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        d = max(d, __shfl_xor(d, off, 64));
+        c += (unsigned)__shfl_xor((int)c, off, 64);
+    }
     if ((threadIdx.x & 63) == 0) {
         atomicMax(out, d);
-        if (c) atomicAdd(nz, c);
+        if (c) atomicAdd(nz, (unsigned long long)c);
     }
 }
 
@@ -237,7 +247,7 @@ void build_incidence_plan(Graph& g, const int32_t* pat, int64_t np, const int32_
     LDS_HIP(hipMemsetAsync(tmax.p, 0, sizeof(int), s));
     LDS_HIP(hipMemsetAsync(nz.p, 0, sizeof(unsigned long long), s));
     if (n > 0) {
-        k_tmax<<<grid_for(n, kT), kT, 0, s>>>(count, n, tmax.p, nz.p);
+        k_tmax<<<std::min(grid_for(n, kT), kReduceWG), kT, 0, s>>>(count, n, tmax.p, nz.p);
         LDS_HIP(hipGetLastError());
     }
     cmax = d2h(tmax.p, s);

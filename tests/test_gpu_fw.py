@@ -224,14 +224,14 @@ def test_rows_sorted_in_every_length_class():
     """Ingest sorts every CSR row ascending (the triangle listing probes rows by
     binary search, and the sweep's slot order is fixed by it).  Rows of every
     length class of the row sort: radix-sorted (> 4096 slots), workgroup
-    bitonic (65..4096) and wave bitonic (2..64 in groups of 64, 32, 16, 8, 4
-    lanes).  lds_splits lists incidences in slot order; with the documented
+    bitonic (513..4096, 129..512 and 65..128, each with its own workgroup
+    size) and wave bitonic (2..64 in groups of 64, 32, 16, 8, 4 lanes).  lds_splits lists incidences in slot order; with the documented
     internal order (degree descending, ties by caller id) the neighbours of
     every row must be strictly increasing."""
     announce("row sort")
     rng = np.random.default_rng(11)
     n = 12000
-    centers = [5000, 4097, 4096, 3000, 100, 65, 64, 40, 33, 32, 20, 17, 16, 9, 8, 5, 4, 3, 2]
+    centers = [5000, 4097, 4096, 3000, 513, 512, 300, 129, 128, 100, 65, 64, 40, 33, 32, 20, 17, 16, 9, 8, 5, 4, 3, 2]
     src, dst = [], []
     for c, dgr in enumerate(centers):
         nb = rng.choice(np.arange(len(centers), n), size=dgr, replace=False)
