@@ -158,6 +158,8 @@ struct SgState {
     DBuf<int2> rec2;             // edges: (position of the other end, a_x)
     DBuf<int4> rec3;             // triangles: (position v, position w, a_x, a_v)
     DBuf<uint32_t> rec3w;        // triangles: a_w
+    DBuf<int64_t> R, T;          // built with the records: by position, the restricted load when every earlier
+                                 // vertex is above (R) and when S = [0, j] (T, which the scan then changes)
     std::vector<int64_t> gstart, gend;  // accepted groups (position ranges)
     DBuf<int64_t> lo, hi;        // per internal vertex: restricted min / max of its group, -1 if none
     int64_t rounds = 0, verifications = 0;
@@ -168,7 +170,8 @@ struct SgState {
     int64_t scan_wg = 0;  // workgroups of the last scan launch (0: none yet)
     size_t device_bytes() const {
         return order.bytes() + pos.bytes() + E.bytes() + inI.bytes() + a_slot.bytes() + a_tri.bytes() + lo.bytes() +
-               hi.bytes() + rec_P.bytes() + rec_own.bytes() + rec2.bytes() + rec3.bytes() + rec3w.bytes();
+               hi.bytes() + rec_P.bytes() + rec_own.bytes() + rec2.bytes() + rec3.bytes() + rec3w.bytes() + R.bytes() +
+               T.bytes();
     }
 };
 

@@ -640,66 +640,6 @@ __device__ inline void accept_walk(const ScanArgs& g, int64_t S0, int64_t b, int
     }
 }
 
-// R_x (every earlier vertex above x) and T_x for S0 = 0 (S = [0, x]), from
-// the records in one streaming pass: each record's pattern gives its own
-// vertex its share under those two cuts of the order, summed per position
-// (segmented over the lanes of a row, one atomic per position; R and T start
-// at zero, and positions without records keep it)
-template <int H>
-__global__ __launch_bounds__(kT) void k_rt_records(ScanArgs g, int64_t ns, int64_t* R, int64_t* T) {
-    constexpr int U = 4;
-    const int lane = threadIdx.x & 63;
-    const int64_t gw = ((int64_t)blockIdx.x * kT + threadIdx.x) >> 6, nwave = ((int64_t)gridDim.x * kT) >> 6;
-    const uint64_t D = g.a.D;
-    for (int64_t kb = gw * 64 * U; kb < ns; kb += nwave * 64 * U) {
-        int64_t p[U][H], al[U][H];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t k = kb + 64 * u + lane;
-            if (k < ns) rec_pattern<H>(g, k, p[u], al[u]);
-            else p[u][0] = -1;
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            int64_t r = 0, t = 0;
-            if (p[u][0] >= 0) {
-                r = pat_contrib<H>(0, p[u], al[u], D, p[u][0], p[u][0]);
-                t = pat_contrib<H>(0, p[u], al[u], D, 0, p[u][0] + 1);
-            }
-            add_by_position(R, (int32_t)p[u][0], r);
-            add_by_position(T, (int32_t)p[u][0], t);
-        }
-    }
-}
-
-
-// c_j (a8): the patterns whose latest vertex (largest position) is at
-// position j, from the records: each pattern has one record per vertex, and
-// exactly the one of its latest vertex sees every other position below its
-// own; summed per position like R and T (c starts at zero)
-template <int H>
-__global__ __launch_bounds__(kT) void k_count_records(ScanArgs g, int64_t ns, int64_t* c) {
-    constexpr int U = 4;
-    const int lane = threadIdx.x & 63;
-    const int64_t gw = ((int64_t)blockIdx.x * kT + threadIdx.x) >> 6, nwave = ((int64_t)gridDim.x * kT) >> 6;
-    for (int64_t kb = gw * 64 * U; kb < ns; kb += nwave * 64 * U) {
-        int64_t p[U][H], al[U][H];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t k = kb + 64 * u + lane;
-            if (k < ns) rec_pattern<H>(g, k, p[u], al[u]);
-            else p[u][0] = -1;
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            bool latest = p[u][0] >= 0;
-#pragma unroll
-            for (int i = 1; i < H; ++i) latest = latest && p[u][i] < p[u][0];
-            add_by_position(c, (int32_t)p[u][0], latest ? 1 : 0);
-        }
-    }
-}
-
 // slots per position (rows are vertices with slots; the rest stay 0)
 __global__ void k_pos_slots(PassArgs a, uint64_t* cnt) {
     const int64_t r = (int64_t)blockIdx.x * kT + threadIdx.x;
@@ -708,17 +648,27 @@ __global__ void k_pos_slots(PassArgs a, uint64_t* cnt) {
     cnt[a.pos[x]] = (uint64_t)(a.rp[r + 1] - a.rp[r]);
 }
 
-// records of every slot of row r (one wave per row), written in position
-// order: slot s of the row at position px goes to P[px] + (s - rp[r])
+// Records of every slot of row r (one wave per row), written in position
+// order: slot s of the row at position px goes to P[px] + (s - rp[r]).  The
+// same pass sums three values over the row's patterns, by position: c_px
+// (a8: the patterns whose latest vertex is px's; optional), R_px (its share
+// when every earlier vertex is above it) and T_px (its share when
+// S = [0, px]; the scan keeps T current from there).  A vertex has one row,
+// so the wave stores its vertex's sums; positions without slots keep the
+// zero they were filled with.  (Each of these sums was a pass of its own
+// over all the records, with a segmented sum per row of 64 records.)
 template <int H>
 __global__ __launch_bounds__(kT) void k_slot_records(PassArgs a, const int64_t* P, int32_t* own, int2* rec2,
-                                                     int4* rec3, uint32_t* rec3w) {
+                                                     int4* rec3, uint32_t* rec3w, int64_t* c, int64_t* R,
+                                                     int64_t* T) {
     const int lane = threadIdx.x & 63;
     const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (r >= a.nrows) return;
+    if (r >= a.nrows) return;  // uniform over the wave
     const int32_t x = a.rid ? a.rid[r] : (int32_t)r;
     const int64_t px = a.pos[x];
     const int64_t shift = P[px] - a.rp[r];
+    const uint64_t D = a.D;
+    int64_t cs = 0, rs = 0, ts = 0;
     for (int64_t s = a.rp[r] + lane; s < a.rp[r + 1]; s += 64) {
         int64_t p[H], al[H];
         int32_t id[H];
@@ -730,6 +680,21 @@ __global__ __launch_bounds__(kT) void k_slot_records(PassArgs a, const int64_t* 
             rec3[shift + s] = make_int4((int)p[1], (int)p[2], (int)(uint32_t)al[0], (int)(uint32_t)al[1]);
             rec3w[shift + s] = (uint32_t)al[2];
         }
+        bool latest = true;
+#pragma unroll
+        for (int i = 1; i < H; ++i) latest = latest && p[i] < p[0];
+        cs += latest ? 1 : 0;
+        rs += pat_contrib<H>(0, p, al, D, p[0], p[0]);
+        ts += pat_contrib<H>(0, p, al, D, 0, p[0] + 1);
+    }
+    auto plus = [](int64_t u, int64_t v) { return u + v; };
+    cs = wave::lane63(wave::scan(cs, 0, plus));
+    rs = wave::lane63(wave::scan(rs, 0, plus));
+    ts = wave::lane63(wave::scan(ts, 0, plus));
+    if (lane == 0) {
+        if (c) c[px] = cs;
+        R[px] = rs;
+        T[px] = ts;
     }
 }
 
@@ -1304,13 +1269,20 @@ __global__ __launch_bounds__(kRT) void k_sg_scan(ScanArgs g) {
 }
 
 // the records of every slot in position order (needs the order and the
-// split numerators)
-void build_records(Graph& g, int mode, const PassArgs& a, hipStream_t s) {
+// split numerators), with R and T by position (q.R, q.T) and, when c is
+// given, the a8 counts c_j (c: n entries, filled with zero by the caller)
+void build_records(Graph& g, int mode, const PassArgs& a, hipStream_t s, int64_t* c) {
     SgState& q = g.sg[mode == 2 ? 0 : 1];
     const SweepPlan& pl = (mode == 2) ? g.edge_plan : g.tri_plan;
     const int64_t n = g.n;
     q.rec_P.alloc(n + 1, s);
     k_fill_i64<<<grid_for(n + 1, kT), kT, 0, s>>>(q.rec_P.p, n + 1, 0);
+    q.R.alloc(n, s);
+    q.T.alloc(n, s);
+    if (n > 0) {
+        k_fill_i64<<<grid_for(n, kT), kT, 0, s>>>(q.R.p, n, 0);
+        k_fill_i64<<<grid_for(n, kT), kT, 0, s>>>(q.T.p, n, 0);
+    }
     LDS_HIP(hipGetLastError());
     q.rec_own.alloc(pl.nslots, s);
     if (mode == 2) {
@@ -1327,10 +1299,10 @@ void build_records(Graph& g, int mode, const PassArgs& a, hipStream_t s) {
     exclusive_scan_u64((const uint64_t*)q.rec_P.p, (uint64_t*)q.rec_P.p, n, (uint64_t*)q.rec_P.p + n, s);
     if (mode == 2)
         k_slot_records<2><<<grid_for(pl.nrows, 4), kT, 0, s>>>(a, q.rec_P.p, q.rec_own.p, q.rec2.p, q.rec3.p,
-                                                               q.rec3w.p);
+                                                               q.rec3w.p, c, q.R.p, q.T.p);
     else
         k_slot_records<3><<<grid_for(pl.nrows, 4), kT, 0, s>>>(a, q.rec_P.p, q.rec_own.p, q.rec2.p, q.rec3.p,
-                                                               q.rec3w.p);
+                                                               q.rec3w.p, c, q.R.p, q.T.p);
     LDS_HIP(hipGetLastError());
 }
 
@@ -1420,20 +1392,11 @@ void sg_sort_prefix(Graph& g, int mode, hipStream_t s) {
     a.pos = q.pos.p;
     a.D = fw_denom(mode, f.iters);
     a = plan_args(g, mode, a);
-    build_records(g, mode, a, s);
     DBuf<int64_t> c;
     c.alloc(n, s);
-    k_fill_i64<<<grid_for(n, kT), kT, 0, s>>>(c.p, n, 0);
+    if (n > 0) k_fill_i64<<<grid_for(n, kT), kT, 0, s>>>(c.p, n, 0);
     LDS_HIP(hipGetLastError());
-    if (p.nslots > 0) {
-        const ScanArgs ra = record_args(q, a);
-        const unsigned rg = std::min<unsigned>(grid_for(p.nslots, kT * 4), 8192u);
-        if (mode == 2)
-            k_count_records<2><<<rg, kT, 0, s>>>(ra, p.nslots, c.p);
-        else
-            k_count_records<3><<<rg, kT, 0, s>>>(ra, p.nslots, c.p);
-        LDS_HIP(hipGetLastError());
-    }
+    build_records(g, mode, a, s, c.p);
     {
         DBuf<uint64_t> ex;
         ex.alloc(n, s);
@@ -1472,12 +1435,6 @@ void sg_stable_groups(Graph& g, int mode, hipStream_t s) {
     if (n == 0) return;
     k_fill_i64<<<grid_for(n, kT), kT, 0, s>>>(q.lo.p, n, -1);
     k_fill_i64<<<grid_for(n, kT), kT, 0, s>>>(q.hi.p, n, -1);
-    DBuf<int64_t> R, T;
-    R.alloc(n, s);
-    T.alloc(n, s);
-    k_fill_i64<<<grid_for(n, kT), kT, 0, s>>>(R.p, n, 0);
-    k_fill_i64<<<grid_for(n, kT), kT, 0, s>>>(T.p, n, 0);
-    LDS_HIP(hipGetLastError());
     PassArgs a{};
     a.a_slot = q.a_slot.p;
     a.a_tri = q.a_tri.p;
@@ -1485,22 +1442,11 @@ void sg_stable_groups(Graph& g, int mode, hipStream_t s) {
     a.D = fw_denom(mode, f.iters);
     a = plan_args(g, mode, a);
 
-    // the slot records (kept from the sort / prefix pass unless a scan since
-    // released them)
-    const SweepPlan& pl = (mode == 2) ? g.edge_plan : g.tri_plan;
-    if (q.rec_P.n != (size_t)n + 1) build_records(g, mode, a, s);
+    // the slot records with R_w (w's restricted load when every earlier
+    // vertex is above it) and T_x for S0 = 0 (kept from the sort / prefix
+    // pass unless a scan since released them); the scan keeps T current
+    if (q.rec_P.n != (size_t)n + 1) build_records(g, mode, a, s, nullptr);
     const ScanArgs rv = record_args(q, a);
-    if (pl.nrows > 0) {
-        // R_w (w's restricted load when every earlier vertex is above it) and
-        // T_x for S0 = 0; T is afterwards maintained incrementally by the scan
-        const ScanArgs ra = rv;
-        const unsigned rg = std::min<unsigned>(grid_for(pl.nslots, kT * 4), 8192u);
-        if (mode == 2)
-            k_rt_records<2><<<rg, kT, 0, s>>>(ra, pl.nslots, R.p, T.p);
-        else
-            k_rt_records<3><<<rg, kT, 0, s>>>(ra, pl.nslots, R.p, T.p);
-    }
-    LDS_HIP(hipGetLastError());
 
     // the round loop: one cooperative launch
     const int64_t nblk = (n + kFB - 1) / kFB;
@@ -1552,8 +1498,8 @@ void sg_stable_groups(Graph& g, int mode, hipStream_t s) {
     sa.a = a;
     sa.order = q.order.p;
     sa.inI = q.inI.p;
-    sa.R = R.p;
-    sa.T = T.p;
+    sa.R = q.R.p;
+    sa.T = q.T.p;
     sa.F = F.p;
     sa.V = Vb.p;
     sa.bmax = bmax.p;
@@ -1609,6 +1555,8 @@ void sg_stable_groups(Graph& g, int mode, hipStream_t s) {
     q.rec2.release();
     q.rec3.release();
     q.rec3w.release();
+    q.R.release();
+    q.T.release();  // changed by the scan
     std::vector<int64_t> hg((size_t)2 * ng);
     if (ng > 0) {
         LDS_HIP(hipMemcpyAsync(hg.data(), groups.p, hg.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
