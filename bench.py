@@ -289,21 +289,28 @@ def _serve_run(lds, np, srv, gs, seconds, qps, seed, tag0, keep=0):
     lat = np.array([c["t_done"] - c["t_arrive"] for c in done])
     span = max(c["t_done"] for c in done) - base
     errs = sum(c["status"] != 0 for c in done)
+    in_window = sum(c["t_done"] - base <= seconds for c in done)
+    # completed_per_s: all queries over the time to the last completion (the
+    # drain of the last ones included); completed_in_window_per_s: what the
+    # server finished while queries were arriving, against arrived_per_s
     res = {"offered_qps": qps, "arrival_window_s": seconds, "queries": n, "errors": errs,
-           "completed_per_s": n / span, "p50_ms": float(np.percentile(lat, 50) * 1e3),
+           "completed_per_s": n / span, "arrived_per_s": n / seconds,
+           "completed_in_window_per_s": in_window / seconds, "p50_ms": float(np.percentile(lat, 50) * 1e3),
            "p99_ms": float(np.percentile(lat, 99) * 1e3), "max_ms": float(lat.max() * 1e3)}
     kept = {c["tag"] - tag0: c["sets"] for c in done if c["tag"] - tag0 < keep}
     return res, q, kept
 
 
-def bench_serving(lds, torch, synth, np, seconds, qps, ladder, plain_sample, p99_bound_ms=2000.0, workers=12):
+def bench_serving(lds, torch, synth, np, seconds, qps, ladder, plain_sample, p99_bound_ms=2000.0, workers=12,
+                  ladder_seconds=12.0):
     """The serving workload: a resident pool of 64 graphs (pool member g,
     seed 5 + g, graph 0 pinned at n = 2M), Poisson arrivals, graph uniform
     over the pool, LDS / LTDS half and half (100 / 200 FW iterations), k
     uniform in 1..10.  Latency = completion - arrival on the server clock.
     Reported: the offered load for `seconds` after a warm-up; the highest
-    offered rate of the ladder whose completions keep up (>= 95% of the
-    offered rate) with p99 within the bound; and the plain baseline: the
+    offered rate of the ladder at which the server keeps up (its completions
+    during the arrival window reach 95% of the arrivals) with p99 within the
+    bound; and the plain baseline: the
     first `plain_sample` queries of the offered stream through lds_topk one
     at a time on the same resident graphs, with their results compared to the
     served ones."""
@@ -329,14 +336,16 @@ def bench_serving(lds, torch, synth, np, seconds, qps, ladder, plain_sample, p99
     log("serving: %s" % res["offered"])
     steps = []
     for k, rate in enumerate(ladder):
-        r, _, _ = _serve_run(lds, np, srv, gs, 8.0, rate, 60 + k, 10 ** 6 * (k + 1))
+        r, _, _ = _serve_run(lds, np, srv, gs, ladder_seconds, rate, 60 + k, 10 ** 6 * (k + 1))
         steps.append(r)
         log("serving ladder: %s" % r)
     res["ladder"] = steps
     ok = [r["offered_qps"] for r in steps
-          if r["completed_per_s"] >= 0.95 * r["offered_qps"] and r["p99_ms"] <= p99_bound_ms and r["errors"] == 0]
+          if r["completed_in_window_per_s"] >= 0.95 * r["arrived_per_s"] and r["p99_ms"] <= p99_bound_ms
+          and r["errors"] == 0]
     res["max_sustained_qps"] = max(ok) if ok else None
-    res["sustain_rule"] = "completions >= 95%% of offered and p99 <= %g ms over an 8 s arrival window" % p99_bound_ms
+    res["sustain_rule"] = ("completions during the arrival window >= 95%% of the arrivals and p99 <= %g ms, "
+                           "over a %g s arrival window" % (p99_bound_ms, ladder_seconds))
     st = lds.lds_server_stats(srv)
     res["batches"] = st["batches"]
     res["max_batch"] = st["max_batch"]
@@ -389,9 +398,10 @@ def main():
     ap.add_argument("--clique4", default="clique4_pl", help="4-clique FW workload ('' to skip)")
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="arrival window of the serving run (0: skip)")
     ap.add_argument("--serve-qps", type=float, default=200.0)
-    ap.add_argument("--serve-ladder", default="50,100,150,175",
+    ap.add_argument("--serve-ladder", default="50,100,150,175,190",
                     help="offered rates (QPS) tried for the highest sustained load ('' to skip)")
     ap.add_argument("--serve-workers", type=int, default=12, help="verification worker threads of the server")
+    ap.add_argument("--serve-ladder-seconds", type=float, default=12.0, help="arrival window of each ladder rate")
     ap.add_argument("--serve-plain", type=int, default=200,
                     help="queries of the offered stream also run one at a time by lds_topk (0: skip)")
     args = ap.parse_args()
@@ -528,7 +538,7 @@ def main():
     if args.serve_seconds > 0:
         out["serving"] = bench_serving(lds, torch, synth, np, args.serve_seconds, args.serve_qps,
                                        [float(x) for x in args.serve_ladder.split(",") if x], args.serve_plain,
-                                       workers=args.serve_workers)
+                                       workers=args.serve_workers, ladder_seconds=args.serve_ladder_seconds)
     if not args.no_cpu_baseline:
         import oracle
         log("cpu baseline: oracle ingest (untimed)")
