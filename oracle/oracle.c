@@ -208,7 +208,7 @@ int64_t orc_triangles(const orc_graph *g, int32_t *tri, int64_t *tcount) {
     }
     free(mark); free(ooff); free(oadj);
     if (tri) {
-        qsort(buf, (size_t)cnt, sizeof(tri_t), cmp_tri);
+        if (cnt > 0) qsort(buf, (size_t)cnt, sizeof(tri_t), cmp_tri); /* buf is NULL without triangles */
         for (int64_t t = 0; t < cnt; t++) {
             tri[3 * t] = buf[t].a; tri[3 * t + 1] = buf[t].b; tri[3 * t + 2] = buf[t].c;
         }
