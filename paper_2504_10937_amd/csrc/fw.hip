@@ -27,6 +27,7 @@
 // the winning numerator, i.e. the minimum) are accumulated exactly in 128-bit
 // integers per workgroup and reduced once after the last iteration.
 #include "graph.hpp"
+#include "push.hpp"
 
 #include <mutex>
 
@@ -84,6 +85,14 @@ struct SweepArgs {
     int64_t n_heavy;
     int64_t hword0;
     int64_t nv;          // vertices (slabs are clipped to it)
+    // hub push (n_push > 0; edge plans only): the pieces above are those of
+    // the hub prefixes, hub_pre[r] slots of hub row r; every workgroup stores
+    // its hub counters (pstride words, two 16-bit counts each) at
+    // push_part + blockIdx * pstride
+    int64_t n_push;
+    const int32_t* hub_pre;
+    uint32_t* push_part;
+    int64_t pstride;
 };
 
 __device__ inline uint64_t readlane64(uint64_t v, int lane) {
@@ -338,6 +347,10 @@ __global__ __launch_bounds__(kPT) void k_fw_sweep(SweepArgs a) {
     // the 2D part first (its LDS layout), then the hot codes for the rest
     heavy_parts<H == 2 && IDENT>(a, reinterpret_cast<uint8_t*>(qc), reinterpret_cast<int64_t*>(&words[0][0]));
     for (int i = threadIdx.x; i < nc; i += kPT) qc[i] = a.Qin[i];
+    // hub push: the hub rows' win counters of this workgroup, after the codes
+    const int Hp = (H == 2 && IDENT) ? (int)a.n_push : 0;
+    uint32_t* hcnt = reinterpret_cast<uint32_t*>(qc + ((nc + 1) & ~1));
+    for (int i = threadIdx.x; i < (Hp + 1) / 2; i += kPT) hcnt[i] = 0u;
     __syncthreads();
     u128 sq = 0, mn = 0;
     // ---- hub rows: cut into word-aligned pieces of <= kPiece slots, one wave
@@ -345,12 +358,15 @@ __global__ __launch_bounds__(kPT) void k_fw_sweep(SweepArgs a) {
     //      wins to the row's counter with one atomic, so the wave whose add
     //      completes the row's last piece reads the row's total from the value
     //      returned, with no fence; it writes the row's key and clears the
-    //      counter for the next sweep.
+    //      counter for the next sweep.  With the hub push a piece covers only
+    //      the row's hub prefix and adds its wins alone: k_push_finish adds
+    //      the pushed wins and writes the key.
     for (int64_t pc = (int64_t)blockIdx.x * kWaves + w; pc < a.n_pieces; pc += (int64_t)gridDim.x * kWaves) {
         const int64_t r = a.hp_row[pc];
         const uint32_t u = IDENT ? (uint32_t)r : (uint32_t)a.rid[r];
         const int64_t rs = a.rp[r], re = a.rp[r + 1];
-        const int64_t s0 = rs + a.hp_off[pc], s1 = min(re, s0 + (int64_t)kPiece);
+        const int64_t s0 = rs + a.hp_off[pc];
+        const int64_t s1 = min(Hp > 0 ? rs + a.hub_pre[r] : re, s0 + (int64_t)kPiece);
         const uint64_t Ku = a.Kin[u];
         const uint16_t Qu = qcode(Ku >> a.B);
         uint64_t* bw = a.bits + a.chunk_words + a.hwo[r] + (s0 - rs) / 64;
@@ -381,7 +397,9 @@ __global__ __launch_bounds__(kPT) void k_fw_sweep(SweepArgs a) {
                 cnt += (uint32_t)__popcll(W);
             }
         }
-        if (lane == 0) {
+        if (lane == 0 && Hp > 0) {
+            atomicAdd(a.hub_ctr + r, (unsigned long long)cnt);
+        } else if (lane == 0) {
             const unsigned long long npc = (unsigned long long)((re - rs + kPiece - 1) / kPiece);
             const unsigned long long old = atomicAdd(a.hub_ctr + r, (1ull << 40) | (unsigned long long)cnt);
             if ((old >> 40) == npc - 1) {
@@ -456,6 +474,10 @@ __global__ __launch_bounds__(kPT) void k_fw_sweep(SweepArgs a) {
                             win = a.Kin[uu[j]] < a.Kin[(uint32_t)sl[j].v[q]];
                         }
                     }
+                    if (H == 2 && Hp > 0 && val[j] && !win) {  // a hub's win, pushed to its counter
+                        const uint32_t v = (uint32_t)sl[j].v[0];
+                        if (v < (uint32_t)Hp) atomicAdd(&hcnt[v >> 1], 1u << ((v & 1u) * 16));
+                    }
                     const uint64_t W = __ballot(win);
                     if (lane == t0 + j) mybits = W;
                 }
@@ -491,6 +513,11 @@ __global__ __launch_bounds__(kPT) void k_fw_sweep(SweepArgs a) {
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();  // words[w] is rewritten by the next chunk
+    }
+    if (Hp > 0) {  // this workgroup's hub counters (uniform branch)
+        __syncthreads();
+        uint32_t* o = a.push_part + (int64_t)blockIdx.x * a.pstride;
+        for (int i = threadIdx.x; i < (Hp + 1) / 2; i += kPT) o[i] = hcnt[i];
     }
     if (GAP) {
         sq = wave_sum128(sq);
@@ -547,6 +574,58 @@ __global__ __launch_bounds__(256) void k_gap_reduce(const uint64_t* partial, int
         out[4 * blockIdx.x + 1] = (uint64_t)(S >> 64);
         out[4 * blockIdx.x + 2] = (uint64_t)M;
         out[4 * blockIdx.x + 3] = (uint64_t)(M >> 64);
+    }
+}
+
+// After a sweep with the hub push: hub row r's wins are its prefix's wins
+// (hub_ctr, cleared here for the next sweep) plus the counts every sweep
+// workgroup pushed (the r & 1 half of word r >> 1 of its slice); then the
+// row's new key and code, and its gap terms (per workgroup, written after
+// the sweep's own partial sums of the iteration).  A workgroup takes 64 hub
+// rows, one per lane; its four waves each sum every fourth sweep
+// workgroup's counts (16 loads in flight per lane), and wave 0 finishes.
+template <bool GAP>
+__global__ __launch_bounds__(256) void k_push_finish(unsigned long long* hub_ctr, const uint32_t* push_part,
+                                                     int64_t pstride, int nblocks, int64_t n_push,
+                                                     const uint64_t* Kin, uint64_t* Kout, uint16_t* Qout,
+                                                     uint64_t inc, int B, uint64_t* partial) {
+    __shared__ uint64_t ps[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t r = (int64_t)blockIdx.x * 64 + lane;
+    uint64_t part = 0;
+    if (r < n_push) {
+        const uint32_t* col = push_part + (r >> 1);
+        const int sh = (int)(r & 1) * 16;
+#pragma unroll 16
+        for (int b = w; b < nblocks; b += 4) part += (col[(int64_t)b * pstride] >> sh) & 0xffffu;
+    }
+    ps[w][lane] = part;
+    __syncthreads();
+    if (w != 0) return;
+    u128 sq = 0, mn = 0;
+    if (r < n_push) {
+        const uint64_t tot = hub_ctr[r] + ps[0][lane] + ps[1][lane] + ps[2][lane] + ps[3][lane];
+        hub_ctr[r] = 0ull;
+        const uint64_t Ku = Kin[r];
+        const uint64_t Kn = Ku + ((tot * inc) << B);
+        Kout[r] = Kn;
+        Qout[r] = qcode(Kn >> B);
+        if (GAP) {
+            const uint64_t A = Ku >> B;
+            sq = (u128)A * A;
+            mn = (u128)A * tot;
+        }
+    }
+    if (GAP) {  // wave 0 alone: all 64 lanes active
+        sq = wave_sum128(sq);
+        mn = wave_sum128(mn);
+        if (lane == 0) {
+            uint64_t* o = partial + (int64_t)blockIdx.x * 4;
+            o[0] = (uint64_t)sq;
+            o[1] = (uint64_t)(sq >> 64);
+            o[2] = (uint64_t)mn;
+            o[3] = (uint64_t)(mn >> 64);
+        }
     }
 }
 
@@ -692,7 +771,8 @@ uint64_t denom(int mode, int64_t i) { return fw_denom(mode, i); }
 template <int H, bool IDENT>
 void launch_sweep(const SweepArgs& a, unsigned blocks, bool gap, hipStream_t s) {
     const bool heavy = H == 2 && IDENT && a.n_parts > 0;
-    const size_t lds = std::max((size_t)a.ncache * sizeof(uint16_t), heavy ? kHeavyLds : (size_t)0);
+    const size_t push_lds = a.n_push > 0 ? (size_t)((a.ncache + 1) & ~1) * 2 + (size_t)a.pstride * 4 : 0;
+    const size_t lds = std::max(std::max((size_t)a.ncache * sizeof(uint16_t), push_lds), heavy ? kHeavyLds : (size_t)0);
     const int max_lds = (int)std::max((size_t)kCacheQ * 2 + 16, (H == 2 && IDENT) ? kHeavyLds : (size_t)0);
     if (gap) {
         static bool attr = false;
@@ -728,6 +808,26 @@ unsigned sweep_grid() {
 // workgroups of the heavy rows' finishing kernel (0 without a 2D part); its
 // gap partial sums follow the sweep's in each iteration's slice
 unsigned finish_grid(const SweepPlan& p) { return p.heavy.n_parts > 0 ? sweep_grid() : 0u; }
+
+// workgroups of the hub push's finishing kernel (64 hub rows each); its gap
+// partial sums follow the sweep's likewise (a plan has a 2D part or the push,
+// never both)
+unsigned push_grid(const SweepPlan& p) { return (unsigned)((p.n_push + 63) / 64); }
+
+// switch the sweep arguments to the hub push of plan p (sweep workgroups
+// `blocks`; push_part sized here)
+void use_push(const SweepPlan& p, FwState& f, unsigned blocks, SweepArgs& a, hipStream_t s) {
+    a.n_push = p.n_push;
+    a.hub_pre = p.hub_pre.p;
+    a.n_pieces = p.n_ppieces;
+    a.hp_row = p.pp_row.p;
+    a.hp_off = p.pp_off.p;
+    a.ncache = (int)p.push_nc;
+    a.pstride = (p.n_push + 1) / 2;
+    const size_t words = (size_t)blocks * (size_t)a.pstride;
+    if (f.push_part.n < words) f.push_part.alloc(words, s);
+    a.push_part = f.push_part.p;
+}
 
 void fill_sweep_args(const Graph& g, const SweepPlan& p, SweepArgs& a) {
     a = SweepArgs{};
@@ -785,6 +885,16 @@ void sweep_iteration(FwState& f, const SweepPlan& p, SweepArgs& a, int mode, int
     else
         launch_sweep<4, false>(a, blocks, gap, s);
     LDS_HIP(hipGetLastError());
+    if (a.n_push > 0) {
+        const unsigned pg = push_grid(p);
+        if (gap)
+            k_push_finish<true><<<pg, 256, 0, s>>>(a.hub_ctr, a.push_part, a.pstride, (int)blocks, a.n_push, a.Kin,
+                                                   a.Kout, a.Qout, a.inc, a.B, partial + (size_t)blocks * 4);
+        else
+            k_push_finish<false><<<pg, 256, 0, s>>>(a.hub_ctr, a.push_part, a.pstride, (int)blocks, a.n_push,
+                                                    a.Kin, a.Kout, a.Qout, a.inc, a.B, nullptr);
+        LDS_HIP(hipGetLastError());
+    }
     const unsigned fb = finish_grid(p);
     if (fb > 0) {
         const HeavyPlan& h = p.heavy;
@@ -866,11 +976,12 @@ void fw_run(Graph& g, int mode, int iters, bool want_gap, hipStream_t s) {
     f.cur = 0;
     g.sg[mode_slot(mode)].valid = false;
     const unsigned blocks = sweep_grid();
-    const unsigned gblocks = blocks + finish_grid(p);  // gap partial sums per iteration
+    const unsigned gblocks = blocks + finish_grid(p) + push_grid(p);  // gap partial sums per iteration
     const size_t npart = want_gap ? (size_t)iters * gblocks * 4 : 0;
     if (f.partial.n < npart) f.partial.alloc(npart, s);
     SweepArgs a;
     fill_sweep_args(g, p, a);
+    if (p.n_push > 0) use_push(p, f, blocks, a, s);
     if (!f.ev[0]) {
         LDS_HIP(hipEventCreate(&f.ev[0]));
         LDS_HIP(hipEventCreate(&f.ev[1]));
@@ -1050,6 +1161,9 @@ void fw_splits(const Graph& g, int mode, int32_t* verts_host, uint64_t* num_host
             k_splits_heavy<<<grid_for(h.positions, 256), 256, 0, s>>>(h.csr.p, h.pay.p, h.positions, h.word0, p.rp,
                                                                       p.nrows, p.py, f.bits.p, p.total_words,
                                                                       f.iters, a0, incm, g.orig_of.p, v.p, a.p);
+        if (p.n_push > 0)  // the hub rows' slots against non-hub vertices, from their mirror slots
+            k_push_mirror<uint64_t><<<(unsigned)std::min<int64_t>(p.n_push, 4096), 256, 0, s>>>(
+                p.rp, p.py, p.hub_pre.p, p.n_push, denom(mode, f.iters), a.p);
     }
     else if (mode == 3)
         k_splits<3><<<grid_for(ns, 256), 256, 0, s>>>(p.rp, p.rid, p.py, p.bitbase.p, p.nrows, ns, f.bits.p,

@@ -29,6 +29,9 @@ namespace lds {
 
 constexpr int kChunk = 1024;  // target slots per wave; spans < 2*kChunk = 32 words
 constexpr int kPiece = 2048;  // slots of a hub-row piece (a multiple of 64)
+// LDS bytes of the persistent edge sweep for the staged codes and, with the
+// hub push, the per-workgroup win counters of the hub rows
+constexpr int64_t kSweepLds = 155648;
 constexpr int kHeavyRows = 8192;   // rows of a block of the 2D part (at most 2^16)
 constexpr int kHeavySlab = 24576;  // neighbour ids of a slab of the 2D part (at most 2^16)
 
@@ -108,6 +111,18 @@ struct SweepPlan {
     DBuf<int32_t> hp_row;       // per piece: hub row
     DBuf<int32_t> hp_off;       // per piece: first slot, relative to the row start (a multiple of 64)
     DBuf<unsigned long long> hub_ctr;  // n_hub: (pieces done << 40) | wins so far (zero between sweeps)
+    // Hub push (edge plans in internal order, n_push = n_hub > 0, else 0): a
+    // hub row compares itself only with the other hub rows (its first
+    // hub_pre[r] slots; rows are sorted by neighbour id), and every other row
+    // adds a hub's wins against it to the hub's counter in LDS (push_nc codes
+    // are staged beside those counters).  The hub rows' other slots get no
+    // decision bits; their splits follow from the mirror slots.
+    int64_t n_push = 0;
+    int64_t push_nc = 0;
+    DBuf<int32_t> hub_pre;      // n_push: slots of hub row r whose neighbour is a hub row
+    int64_t n_ppieces = 0;      // pieces of those prefixes (as hp_row / hp_off)
+    DBuf<int32_t> pp_row;
+    DBuf<int32_t> pp_off;
     int64_t n_chunks = 0;
     DBuf<int64_t> chunk_row;    // n_chunks + 1 (compact row index)
     DBuf<int64_t> cwo;          // n_chunks + 1 word offsets
@@ -117,7 +132,8 @@ struct SweepPlan {
     HeavyPlan heavy;            // edge plans of large graphs only
     size_t device_bytes() const {
         return own_rid.bytes() + own_rp.bytes() + own_py.bytes() + own_tos.bytes() + own_row_of.bytes() + hwo.bytes() + chunk_row.bytes() + cwo.bytes() +
-               head.bytes() + bitbase.bytes() + hp_row.bytes() + hp_off.bytes() + hub_ctr.bytes() + heavy.device_bytes();
+               head.bytes() + bitbase.bytes() + hp_row.bytes() + hp_off.bytes() + hub_ctr.bytes() + hub_pre.bytes() +
+               pp_row.bytes() + pp_off.bytes() + heavy.device_bytes();
     }
 };
 
@@ -128,13 +144,15 @@ struct FwState {
     DBuf<uint16_t> Q[2];         // 16-bit monotone codes of A (gathered first)
     DBuf<uint64_t> bits;         // iters * total_words decision words
     DBuf<uint64_t> partial;      // iters * blocks * 4 gap partial sums
+    DBuf<uint32_t> push_part;    // hub push: per sweep workgroup, the hub rows' win counts (two 16-bit halves a word)
     std::vector<double> gap, lb, fval;  // per iteration, filled on request: gap, lower bound, sum r^2 at r^(i-1)
     hipEvent_t ev[2] = {nullptr, nullptr};  // around the sweep launches of the last run
     int launches = 0;
     bool ran = false;            // keys hold the result of a completed run of `iters` iterations
     bool timed = false;          // ev[] bracket the last run (plain runs only)
     size_t device_bytes() const {
-        return K[0].bytes() + K[1].bytes() + Q[0].bytes() + Q[1].bytes() + bits.bytes() + partial.bytes();
+        return K[0].bytes() + K[1].bytes() + Q[0].bytes() + Q[1].bytes() + bits.bytes() + partial.bytes() +
+               push_part.bytes();
     }
 };
 

@@ -130,21 +130,39 @@ __global__ void k_hub_words(const int64_t* rp, int64_t n_hub, uint64_t* words) {
     words[r] = (uint64_t)((rp[r + 1] - rp[r] + 63) / 64);
 }
 
-__global__ void k_hub_pieces(const int64_t* rp, int64_t n_hub, uint32_t* np) {
+// pieces of the hub rows: of each whole row, or (pre given) of its first
+// pre[r] slots
+__global__ void k_hub_pieces(const int64_t* rp, int64_t n_hub, const int32_t* pre, uint32_t* np) {
     const int64_t r = (int64_t)blockIdx.x * kT + threadIdx.x;
-    if (r < n_hub) np[r] = (uint32_t)((rp[r + 1] - rp[r] + kPiece - 1) / kPiece);
+    if (r < n_hub) np[r] = (uint32_t)(((pre ? (int64_t)pre[r] : rp[r + 1] - rp[r]) + kPiece - 1) / kPiece);
 }
 
-__global__ void k_hub_piece_fill(const int64_t* rp, int64_t n_hub, const uint64_t* first, int32_t* hp_row,
-                                 int32_t* hp_off) {
+__global__ void k_hub_piece_fill(const int64_t* rp, int64_t n_hub, const int32_t* pre, const uint64_t* first,
+                                 int32_t* hp_row, int32_t* hp_off) {
     const int64_t r = (int64_t)blockIdx.x * kT + threadIdx.x;
     if (r >= n_hub) return;
-    const int64_t len = rp[r + 1] - rp[r];
+    const int64_t len = pre ? (int64_t)pre[r] : rp[r + 1] - rp[r];
     int64_t k = (int64_t)first[r];
     for (int64_t o = 0; o < len; o += kPiece, ++k) {
         hp_row[k] = (int32_t)r;
         hp_off[k] = (int32_t)o;
     }
+}
+
+// hub push: the slots of hub row r whose neighbour is a hub row (a prefix:
+// the row is sorted by neighbour id)
+__global__ void k_hub_prefix(const int64_t* rp, const int32_t* col, int64_t n_hub, int32_t* pre) {
+    const int64_t r = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (r >= n_hub) return;
+    int64_t lo = rp[r], hi = rp[r + 1];
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (col[mid] < (int32_t)n_hub)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    pre[r] = (int32_t)(lo - rp[r]);
 }
 
 __global__ void k_chunk_rows(const int64_t* rp, int64_t nrows, int64_t n_hub, int64_t n_chunks, int64_t* chunk_row) {
@@ -573,17 +591,51 @@ void build_sweep_plan(SweepPlan& p, hipStream_t s, int64_t n_vertices) {
         DBuf<uint64_t> first;
         npc.alloc(p.n_hub, s);
         first.alloc(p.n_hub, s);
-        k_hub_pieces<<<grid_for(p.n_hub, kT), kT, 0, s>>>(p.rp, p.n_hub, npc.p);
+        k_hub_pieces<<<grid_for(p.n_hub, kT), kT, 0, s>>>(p.rp, p.n_hub, nullptr, npc.p);
         LDS_HIP(hipGetLastError());
         exclusive_scan_u32_to_u64(npc.p, first.p, p.n_hub, tot.p, s);
         p.n_pieces = (int64_t)d2h(tot.p, s);
         LDS_CHECK(p.n_pieces < INT32_MAX, ST_INVALID, "too many hub pieces");
         p.hp_row.alloc(p.n_pieces, s);
         p.hp_off.alloc(p.n_pieces, s);
-        k_hub_piece_fill<<<grid_for(p.n_hub, kT), kT, 0, s>>>(p.rp, p.n_hub, first.p, p.hp_row.p, p.hp_off.p);
+        k_hub_piece_fill<<<grid_for(p.n_hub, kT), kT, 0, s>>>(p.rp, p.n_hub, nullptr, first.p, p.hp_row.p,
+                                                              p.hp_off.p);
         LDS_HIP(hipGetLastError());
         p.hub_ctr.alloc(p.n_hub, s);
         LDS_HIP(hipMemsetAsync(p.hub_ctr.p, 0, p.hub_ctr.bytes(), s));
+    }
+    // hub push (edge plans in internal order): the hub rows' codes and their
+    // 16-bit per-workgroup counters must fit the sweep's LDS beside each other,
+    // and no hub row may have 2^16 slots (a counter never wraps into the next)
+    p.n_push = p.push_nc = p.n_ppieces = 0;
+    if (p.h == 2 && p.rid == nullptr && n_heavy == 0 && p.n_hub > 0) {
+        int64_t r01[2] = {0, 0};
+        LDS_HIP(hipMemcpyAsync(r01, p.rp, sizeof(r01), hipMemcpyDeviceToHost, s));
+        LDS_HIP(hipStreamSynchronize(s));
+        const int64_t nc = ((kSweepLds - 4 * ((p.n_hub + 1) / 2)) / 2) & ~(int64_t)1;
+        const int64_t ncache = std::min<int64_t>(n_vertices, nc);
+        if (r01[1] - r01[0] < 65536 && ncache >= std::min<int64_t>(n_vertices, p.n_hub)) {
+            p.n_push = p.n_hub;
+            p.push_nc = ncache;
+            p.hub_pre.alloc(p.n_hub, s);
+            k_hub_prefix<<<grid_for(p.n_hub, kT), kT, 0, s>>>(p.rp, p.py, p.n_hub, p.hub_pre.p);
+            LDS_HIP(hipGetLastError());
+            DBuf<uint32_t> npc;
+            DBuf<uint64_t> first;
+            npc.alloc(p.n_hub, s);
+            first.alloc(p.n_hub, s);
+            k_hub_pieces<<<grid_for(p.n_hub, kT), kT, 0, s>>>(p.rp, p.n_hub, p.hub_pre.p, npc.p);
+            LDS_HIP(hipGetLastError());
+            exclusive_scan_u32_to_u64(npc.p, first.p, p.n_hub, tot.p, s);
+            p.n_ppieces = (int64_t)d2h(tot.p, s);
+            p.pp_row.alloc(p.n_ppieces, s);
+            p.pp_off.alloc(p.n_ppieces, s);
+            if (p.n_ppieces > 0) {
+                k_hub_piece_fill<<<grid_for(p.n_hub, kT), kT, 0, s>>>(p.rp, p.n_hub, p.hub_pre.p, first.p,
+                                                                      p.pp_row.p, p.pp_off.p);
+                LDS_HIP(hipGetLastError());
+            }
+        }
     }
     // chunks
     int64_t base = 0;
@@ -832,6 +884,12 @@ void view_plan(SweepPlan& d, const SweepPlan& p, hipStream_t s) {
     d.n_pieces = p.n_pieces;
     d.hp_row.borrow(p.hp_row);
     d.hp_off.borrow(p.hp_off);
+    d.n_push = p.n_push;
+    d.push_nc = p.push_nc;
+    d.hub_pre.borrow(p.hub_pre);
+    d.n_ppieces = p.n_ppieces;
+    d.pp_row.borrow(p.pp_row);
+    d.pp_off.borrow(p.pp_off);
     if (p.hub_ctr.n) {  // written by every sweep: the view's own, zero between sweeps
         d.hub_ctr.alloc(p.hub_ctr.n, s);
         LDS_HIP(hipMemsetAsync(d.hub_ctr.p, 0, d.hub_ctr.bytes(), s));

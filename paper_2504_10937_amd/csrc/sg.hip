@@ -44,6 +44,7 @@
 
 #include "graph.hpp"
 #include "gridsync.hpp"
+#include "push.hpp"
 #include "wave.hpp"
 
 namespace lds {
@@ -1375,6 +1376,11 @@ void sg_sort_prefix(Graph& g, int mode, hipStream_t s) {
                                                          p.total_words, f.iters, mode == 3, hv.positions, hv.word0,
                                                          hv.csr.p, q.a_slot.p);
         LDS_HIP(hipGetLastError());
+        if (p.n_push > 0) {  // the hub rows' slots against non-hub vertices, from their mirror slots
+            k_push_mirror<uint32_t><<<(unsigned)std::min<int64_t>(p.n_push, 4096), 256, 0, s>>>(
+                p.rp, p.py, p.hub_pre.p, p.n_push, fw_denom(mode, f.iters), q.a_slot.p);
+            LDS_HIP(hipGetLastError());
+        }
     }
     if (mode == 3) {
         q.a_tri.alloc(3 * g.T, s);

@@ -1018,7 +1018,8 @@ size_t topk_footprint(const Graph& g, int mode, int iters) {
     const SweepPlan& p = (mode == 2) ? g.edge_plan : g.tri_plan;
     const size_t n = (size_t)g.n, slots = (size_t)p.nslots;
     const size_t T = mode == 3 && g.T > 0 ? (size_t)g.T : 0;
-    const size_t fw = 2 * 8 * n + 2 * 2 * n + (size_t)iters * (size_t)p.total_words * 8 + (size_t)iters * 4 * 8 * 1024;
+    const size_t fw = 2 * 8 * n + 2 * 2 * n + (size_t)iters * (size_t)p.total_words * 8 + (size_t)iters * 4 * 8 * 1024 +
+                      (size_t)((p.n_push + 1) / 2) * 4 * 1024;  // the hub push's per-workgroup counters
     const size_t sg = 4 * n + 8 * n + 8 * n + n + 4 * slots + 12 * T + 16 * n;  // order pos E inI a_slot a_tri lo hi
     // sort keys / values, R T F V, counts, and the slot records (own position,
     // other positions and splits; record offsets by position)
