@@ -255,3 +255,57 @@ def test_rows_sorted_in_every_length_class():
     lens = np.bincount(row, minlength=n)
     for dgr in centers:
         assert (lens == dgr).any() or (lens >= dgr).any()
+
+
+def _hub_graph(seed):
+    """Six hub rows (more than 1024 slots each), some hub-hub edges and a
+    sparse background: the edge sweep's hub push on every path (hub prefixes,
+    wins pushed from the other rows, splits of the pushed slots from their
+    mirrors)."""
+    rng = np.random.default_rng(seed)
+    n = 9000
+    hubs = [3000, 2500, 1800, 1400, 1100, 1030]
+    src, dst = [], []
+    for h, dgr in enumerate(hubs):
+        nb = rng.choice(np.arange(len(hubs), n), size=dgr, replace=False)
+        src += [h] * dgr
+        dst += nb.tolist()
+    for x in range(len(hubs)):
+        for y in range(x + 1, len(hubs)):
+            if (x + y) % 3:
+                src.append(x)
+                dst.append(y)
+    bs = rng.integers(len(hubs), n, 25000)
+    bd = rng.integers(len(hubs), n, 25000)
+    return n, np.array(src + bs.tolist(), np.int32), np.array(dst + bd.tolist(), np.int32)
+
+
+@pytest.mark.parametrize("iters", [1, 60])
+def test_hub_push_exact(iters):
+    """Loads, every split numerator and the gap exactly as the oracle's with
+    the hub rows pushed; then Alg. 2 (sort, prefix, I, stable groups and their
+    bounds, which read the mirrored splits) exactly, and the no-allocation
+    path (which pulls the hub rows) leaves the same splits."""
+    announce("hub push", iters)
+    n, s, d = _hub_graph(5)
+    G = oracle.Graph(n, s, d)
+    g = lds.lds_create_graph(n, s, d)
+    assert lds.lds_sweep_info(g, 2)["hub_rows"] >= 6
+    check_fw(n, s, d, 2, iters, G=G, gpu_graph=g)
+    ref = oracle.fw_exact(G, 2, iters, with_gap=False)
+    order, E, inI = lds.lds_sort_prefix(g, 2)
+    o_order, o_E, o_inI = oracle.sort_prefix(G, 2, ref["A"])
+    np.testing.assert_array_equal(order, o_order)
+    np.testing.assert_array_equal(E, o_E)
+    np.testing.assert_array_equal(inI, o_inI)
+    groups, lo, hi = lds.lds_stable_groups(g, 2)
+    o_groups, o_lo, o_hi = oracle.extract_sg(G, 2, ref["A"], ref["split"], ref["D"])
+    assert groups == o_groups
+    np.testing.assert_array_equal(lo, o_lo)
+    np.testing.assert_array_equal(hi, o_hi)
+    verts, num = lds.lds_splits(g, 2)
+    lds.lds_frank_wolfe_noalloc(g, 2, iters)
+    verts2, num2 = lds.lds_splits(g, 2)
+    np.testing.assert_array_equal(verts, verts2)
+    np.testing.assert_array_equal(num, num2)
+    g.destroy()
