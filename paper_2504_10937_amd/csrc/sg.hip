@@ -1370,8 +1370,13 @@ void sg_sort_prefix(Graph& g, int mode, hipStream_t s) {
     q.a_slot.alloc(p.nslots, s);
     if (p.nslots > 0 && f.iters >= 0) {
         const HeavyPlan& hv = p.heavy;
-        const int64_t blocks = p.n_pieces + p.n_chunks + (hv.positions + kPiece - 1) / kPiece;
-        k_slot_splits<<<grid_for(blocks, 1), kT, 0, s>>>(p.rp, p.n_pieces, p.hp_row.p, p.hp_off.p, p.hwo.p, p.n_chunks,
+        // with the hub push only the pieces of the hub prefixes carry decision
+        // bits; the rest of the hub rows comes from the mirror slots below
+        const bool push = p.n_push > 0;
+        const int64_t npc = push ? p.n_ppieces : p.n_pieces;
+        const int64_t blocks = npc + p.n_chunks + (hv.positions + kPiece - 1) / kPiece;
+        k_slot_splits<<<grid_for(blocks, 1), kT, 0, s>>>(p.rp, npc, push ? p.pp_row.p : p.hp_row.p,
+                                                         push ? p.pp_off.p : p.hp_off.p, p.hwo.p, p.n_chunks,
                                                          p.chunk_row.p, p.cwo.p, p.chunk_words, f.bits.p,
                                                          p.total_words, f.iters, mode == 3, hv.positions, hv.word0,
                                                          hv.csr.p, q.a_slot.p);
