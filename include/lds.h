@@ -128,8 +128,10 @@ lds_status lds_frank_wolfe(lds_graph g, lds_mode mode, int32_t iters, float* r_o
 
 /* lds_frank_wolfe without any device allocation, for callers that cannot
  * allocate (tight serving loops, code that must not call hipMalloc): the same
- * kernels and the same exact result (loads bit for bit; gap within FP64
- * rounding, as it is formed on the device from the same exact sums).
+ * sweep kernel (hub rows pulled rather than pushed: the push's per-workgroup
+ * counters do not fit the fixed scratch) and the same exact result (loads bit
+ * for bit; gap within FP64 rounding, as it is formed on the device from the
+ * same exact sums).
  * The graph's FW state for this mode must already be sized for `iters`
  * iterations by an earlier lds_frank_wolfe (or lds_batch_create) with at
  * least `iters` iterations, and triangles (4-cliques) must be listed;
