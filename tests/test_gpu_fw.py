@@ -280,18 +280,52 @@ def _hub_graph(seed):
     return n, np.array(src + bs.tolist(), np.int32), np.array(dst + bd.tolist(), np.int32)
 
 
-@pytest.mark.parametrize("iters", [1, 60])
-def test_hub_push_exact(iters):
+def _all_hub_graph(seed):
+    """G(1200, 0.95): every row has more than 1024 slots, so every row is a
+    hub row, there are no chunks and no pushed slots."""
+    rng = np.random.default_rng(seed)
+    n = 1200
+    u, v = np.triu_indices(n, 1)
+    keep = rng.random(len(u)) < 0.95
+    return n, u[keep].astype(np.int32), v[keep].astype(np.int32)
+
+
+def _star_hub_graph(seed):
+    """A star of 70,000 leaves beside five hubs of 2,000 slots: row 0 has
+    2^16 slots or more, so the hub rows are pulled, not pushed."""
+    rng = np.random.default_rng(seed)
+    n = 80000
+    src = [0] * 70000
+    dst = list(range(1, 70001))
+    for h in range(1, 6):
+        nb = rng.choice(np.arange(6, n), size=2000, replace=False)
+        src += [h] * 2000
+        dst += nb.tolist()
+    bs = rng.integers(6, n, 40000)
+    bd = rng.integers(6, n, 40000)
+    return n, np.array(src + bs.tolist(), np.int32), np.array(dst + bd.tolist(), np.int32)
+
+
+@pytest.mark.parametrize("shape,iters", [("hubs", 1), ("hubs", 60), ("all_hubs", 1), ("all_hubs", 40),
+                                         ("star", 1), ("star", 40)])
+def test_hub_push_exact(shape, iters):
     """Loads, every split numerator and the gap exactly as the oracle's with
-    the hub rows pushed; then Alg. 2 (sort, prefix, I, stable groups and their
-    bounds, which read the mirrored splits) exactly, and the no-allocation
-    path (which pulls the hub rows) leaves the same splits."""
-    announce("hub push", iters)
-    n, s, d = _hub_graph(5)
+    the hub rows pushed (hubs), with every row a hub row (all_hubs) and with
+    the push refused for a row of 2^16 slots (star); then, with the push,
+    Alg. 2 (sort, prefix, I, stable groups and their bounds, which read the
+    mirrored splits) exactly, and the no-allocation path (which pulls the hub
+    rows) leaves the same splits."""
+    announce("hub push", shape, iters)
+    n, s, d = {"hubs": _hub_graph, "all_hubs": _all_hub_graph, "star": _star_hub_graph}[shape](5)
     G = oracle.Graph(n, s, d)
     g = lds.lds_create_graph(n, s, d)
     assert lds.lds_sweep_info(g, 2)["hub_rows"] >= 6
     check_fw(n, s, d, 2, iters, G=G, gpu_graph=g)
+    if shape == "star":
+        # the pulled hub rows' splits are the ordinary ones (the oracle's
+        # stable groups of this graph take over a minute)
+        g.destroy()
+        return
     ref = oracle.fw_exact(G, 2, iters, with_gap=False)
     order, E, inI = lds.lds_sort_prefix(g, 2)
     o_order, o_E, o_inI = oracle.sort_prefix(G, 2, ref["A"])
