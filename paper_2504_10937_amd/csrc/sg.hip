@@ -41,6 +41,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <climits>
+#include <type_traits>
 
 #include "graph.hpp"
 #include "gridsync.hpp"
@@ -708,54 +709,83 @@ __global__ void k_pos_slots(PassArgs a, uint64_t* cnt) {
     cnt[a.pos[x]] = (uint64_t)(a.rp[r + 1] - a.rp[r]);
 }
 
-// Records of every slot of row r (one wave per row), written in position
-// order: slot s of the row at position px goes to P[px] + (s - rp[r]).  The
-// same pass sums three values over the row's patterns, by position: c_px
-// (a8: the patterns whose latest vertex is px's; optional), R_px (its share
-// when every earlier vertex is above it) and T_px (its share when
-// S = [0, px]; the scan keeps T current from there).  A vertex has one row,
-// so the wave stores its vertex's sums; positions without slots keep the
-// zero they were filled with.  (Each of these sums was a pass of its own
-// over all the records, with a segmented sum per row of 64 records.)
-template <int H>
-__global__ __launch_bounds__(kT) void k_slot_records(PassArgs a, const int64_t* P, int32_t* own, int2* rec2,
-                                                     int4* rec3, uint32_t* rec3w, int64_t* c, int64_t* R,
-                                                     int64_t* T) {
+// Records of every slot of row r, written in position order: slot s of the
+// row at position px goes to P[px] + (s - rp[r]).  The same pass sums three
+// values over the row's patterns, by position: c_px (a8: the patterns whose
+// latest vertex is px's; optional), R_px (its share when every earlier
+// vertex is above it) and T_px (its share when S = [0, px]; the scan keeps T
+// current from there).  A vertex has one row, so the row's group of lanes
+// stores its vertex's sums; positions without slots keep the zero they were
+// filled with.  G lanes per row, 64 / G rows per wave: rows [r0, r1) of one
+// length class, so that short rows do not leave most of a wave idle (every
+// lane loops over its row with stride G, so any row length is handled).
+template <int H, int G>
+__global__ __launch_bounds__(kT) void k_slot_records(PassArgs a, int64_t r0, int64_t r1, const int64_t* P,
+                                                     int32_t* own, int2* rec2, int4* rec3, uint32_t* rec3w,
+                                                     int64_t* c, int64_t* R, int64_t* T) {
+    static_assert(G == 8 || G == 16 || G == 64, "lanes per row: 8, 16 or 64");
     const int lane = threadIdx.x & 63;
-    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (r >= a.nrows) return;  // uniform over the wave
-    const int32_t x = a.rid ? a.rid[r] : (int32_t)r;
-    const int64_t px = a.pos[x];
-    const int64_t shift = P[px] - a.rp[r];
-    const uint64_t D = a.D;
-    int64_t cs = 0, rs = 0, ts = 0;
-    for (int64_t s = a.rp[r] + lane; s < a.rp[r + 1]; s += 64) {
-        int64_t p[H], al[H];
-        int32_t id[H];
-        load_pattern<H>(a, s, x, p, al, id);
-        own[shift + s] = (int32_t)px;
-        if (H == 2) {
-            rec2[shift + s] = make_int2((int)p[1], (int)(uint32_t)al[0]);
-        } else {
-            rec3[shift + s] = make_int4((int)p[1], (int)p[2], (int)(uint32_t)al[0], (int)(uint32_t)al[1]);
-            rec3w[shift + s] = (uint32_t)al[2];
-        }
-        bool latest = true;
+    const int64_t rw = r0 + ((int64_t)blockIdx.x * (kT / 64) + (threadIdx.x >> 6)) * (64 / G);
+    if (rw >= r1) return;  // uniform over the wave
+    const int64_t r = rw + lane / G;
+    const bool live = r < r1;
+    int64_t cs = 0, rs = 0, ts = 0, px = 0;
+    if (live) {
+        const int32_t x = a.rid ? a.rid[r] : (int32_t)r;
+        px = a.pos[x];
+        const int64_t shift = P[px] - a.rp[r];
+        const uint64_t D = a.D;
+        for (int64_t s = a.rp[r] + lane % G; s < a.rp[r + 1]; s += G) {
+            int64_t p[H], al[H];
+            int32_t id[H];
+            load_pattern<H>(a, s, x, p, al, id);
+            own[shift + s] = (int32_t)px;
+            if (H == 2) {
+                rec2[shift + s] = make_int2((int)p[1], (int)(uint32_t)al[0]);
+            } else {
+                rec3[shift + s] = make_int4((int)p[1], (int)p[2], (int)(uint32_t)al[0], (int)(uint32_t)al[1]);
+                rec3w[shift + s] = (uint32_t)al[2];
+            }
+            bool latest = true;
 #pragma unroll
-        for (int i = 1; i < H; ++i) latest = latest && p[i] < p[0];
-        cs += latest ? 1 : 0;
-        rs += pat_contrib<H>(0, p, al, D, p[0], p[0]);
-        ts += pat_contrib<H>(0, p, al, D, 0, p[0] + 1);
+            for (int i = 1; i < H; ++i) latest = latest && p[i] < p[0];
+            cs += latest ? 1 : 0;
+            rs += pat_contrib<H>(0, p, al, D, p[0], p[0]);
+            ts += pat_contrib<H>(0, p, al, D, 0, p[0] + 1);
+        }
     }
-    auto plus = [](int64_t u, int64_t v) { return u + v; };
-    cs = wave::lane63(wave::scan(cs, 0, plus));
-    rs = wave::lane63(wave::scan(rs, 0, plus));
-    ts = wave::lane63(wave::scan(ts, 0, plus));
-    if (lane == 0) {
+    // every lane of the wave takes part in the sums
+    if (G == 64) {
+        auto plus = [](int64_t u, int64_t v) { return u + v; };
+        cs = wave::lane63(wave::scan(cs, 0, plus));
+        rs = wave::lane63(wave::scan(rs, 0, plus));
+        ts = wave::lane63(wave::scan(ts, 0, plus));
+    } else {
+        // the row's last lane ends with the row's totals
+        cs = wave::seg_prefix_sum(lane / G, cs);
+        rs = wave::seg_prefix_sum(lane / G, rs);
+        ts = wave::seg_prefix_sum(lane / G, ts);
+    }
+    if (live && lane % G == (G == 64 ? 0 : G - 1)) {
         if (c) c[px] = cs;
         R[px] = rs;
         T[px] = ts;
     }
+}
+
+// first row with at most t[i] slots, for the two class limits of
+// k_slot_records (rows are ordered by slot count, longest first)
+__global__ void k_record_classes(const int64_t* rp, int64_t nrows, int64_t t0, int64_t t1, int64_t* out) {
+    const int i = threadIdx.x;
+    if (i >= 2) return;
+    const int64_t t = i == 0 ? t0 : t1;
+    int64_t lo = 0, hi = nrows;
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (rp[mid + 1] - rp[mid] > t) lo = mid + 1;
+        else hi = mid;
+    }
+    out[i] = lo;
 }
 
 // Barrier of the workgroups of one posted phase: the first P workgroups
@@ -1357,13 +1387,41 @@ void build_records(Graph& g, int mode, const PassArgs& a, hipStream_t s, int64_t
     if (pl.nrows == 0) return;
     k_pos_slots<<<grid_for(pl.nrows, kT), kT, 0, s>>>(a, (uint64_t*)q.rec_P.p);
     exclusive_scan_u64((const uint64_t*)q.rec_P.p, (uint64_t*)q.rec_P.p, n, (uint64_t*)q.rec_P.p + n, s);
-    if (mode == 2)
-        k_slot_records<2><<<grid_for(pl.nrows, 4), kT, 0, s>>>(a, q.rec_P.p, q.rec_own.p, q.rec2.p, q.rec3.p,
-                                                               q.rec3w.p, c, q.R.p, q.T.p);
-    else
-        k_slot_records<3><<<grid_for(pl.nrows, 4), kT, 0, s>>>(a, q.rec_P.p, q.rec_own.p, q.rec2.p, q.rec3.p,
-                                                               q.rec3w.p, c, q.R.p, q.T.p);
-    LDS_HIP(hipGetLastError());
+    // length classes: more than 32 slots (a wave per row), 9-32 (16 lanes),
+    // at most 8 (8 lanes)
+    int64_t cls[2] = {0, 0};
+    {
+        DBuf<int64_t> d;
+        d.alloc(2, s);
+        k_record_classes<<<1, 64, 0, s>>>(pl.rp, pl.nrows, 32, 8, d.p);
+        LDS_HIP(hipGetLastError());
+        LDS_HIP(hipMemcpyAsync(cls, d.p, sizeof(cls), hipMemcpyDeviceToHost, s));
+        LDS_HIP(hipStreamSynchronize(s));
+    }
+    const int64_t b0 = 0, b1 = cls[0], b2 = std::max(cls[0], cls[1]), b3 = pl.nrows;
+    const int wpb = kT / 64;  // waves per workgroup
+    auto launch = [&](auto h, int64_t lo, int64_t hi, auto gl) {
+        constexpr int H = decltype(h)::value, G = decltype(gl)::value;
+        if (hi <= lo) return;
+        const int64_t waves = (hi - lo + 64 / G - 1) / (64 / G);
+        k_slot_records<H, G><<<grid_for(waves, wpb), kT, 0, s>>>(a, lo, hi, q.rec_P.p, q.rec_own.p, q.rec2.p,
+                                                                 q.rec3.p, q.rec3w.p, c, q.R.p, q.T.p);
+        LDS_HIP(hipGetLastError());
+    };
+    using G64 = std::integral_constant<int, 64>;
+    using G16 = std::integral_constant<int, 16>;
+    using G8 = std::integral_constant<int, 8>;
+    if (mode == 2) {
+        using H2 = std::integral_constant<int, 2>;
+        launch(H2{}, b0, b1, G64{});
+        launch(H2{}, b1, b2, G16{});
+        launch(H2{}, b2, b3, G8{});
+    } else {
+        using H3 = std::integral_constant<int, 3>;
+        launch(H3{}, b0, b1, G64{});
+        launch(H3{}, b1, b2, G16{});
+        launch(H3{}, b2, b3, G8{});
+    }
 }
 
 // the hub rows' slots past their hub prefixes, from the non-hub rows' splits
