@@ -23,12 +23,6 @@
 //     pieces of at most kPiece slots, one wave each, scheduled before the
 //     chunks over all waves; a piece adds its wins to the row's counter and
 //     the wave that completes the row's last piece writes the row's key.
-//   * hub push (edges): a hub row only compares itself with the other hub
-//     rows; every other row that loses a slot to a hub neighbour adds the
-//     hub's win to a per-workgroup counter in LDS, and k_push_finish sums the
-//     counters and writes the hub rows' keys.  The hub rows' slots against
-//     the other rows are then neither streamed nor gathered; their splits
-//     follow from the mirror slots (push.hpp).
 // The duality-gap terms sum_u A_u^2 and sum_u A_u b_u (= sum over patterns of
 // the winning numerator, i.e. the minimum) are accumulated exactly in 128-bit
 // integers per workgroup and reduced once after the last iteration.

@@ -1,7 +1,11 @@
-// Hub push of the edge sweep: the hub rows' slots against non-hub vertices
-// carry no decision bits (the other row of the pair decides and adds the
-// hub's wins to its counter), so their split numerators follow from the
-// mirror slot: the two shares of an edge sum to D.
+// Hub push of the edge sweep (k_fw_sweep, k_push_finish): a hub row only
+// compares itself with the other hub rows (its hub prefix); every other row
+// that loses a slot to a hub neighbour adds 1 to that hub's 16-bit
+// per-workgroup counter in LDS, and k_push_finish sums the counters and
+// writes the hub rows' keys.  The hub rows' slots against non-hub vertices
+// are thus neither streamed nor gathered and carry no decision bits, so
+// their split numerators follow from the mirror slot: the two shares of an
+// edge sum to D.
 #pragma once
 #include <hip/hip_runtime.h>
 

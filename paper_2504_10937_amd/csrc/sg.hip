@@ -349,17 +349,35 @@ __global__ __launch_bounds__(kT) void k_tile_inI(const int64_t* E, int64_t n, co
     }
 }
 
-// exclusive suffix maximum of the tile maxima (one thread; tiles are few)
-__global__ void k_tile_carry(const int64_t* tn, const int64_t* td, int64_t tiles, int64_t* cn, int64_t* cd) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    int64_t rn = 0, rd = 0;  // max over later tiles (den 0: minus infinity)
-    for (int64_t t = tiles - 1; t >= 0; --t) {
+// exclusive suffix maximum of the tile maxima, one workgroup: thread i owns
+// a contiguous block of tiles (its maximum, then an exclusive suffix maximum
+// over the threads' maxima in LDS, then its block walked backwards)
+__global__ __launch_bounds__(kT) void k_tile_carry(const int64_t* tn, const int64_t* td, int64_t tiles, int64_t* cn,
+                                                 int64_t* cd) {
+    __shared__ int64_t sn[kT], sd[kT];
+    const int64_t per = (tiles + kT - 1) / kT;
+    const int64_t t0 = (int64_t)threadIdx.x * per, t1 = min(tiles, t0 + per);
+    int64_t bn = 0, bd = 0;  // den 0: minus infinity
+    for (int64_t t = t0; t < t1; ++t)
+        if (frac_gt(tn[t], td[t], bn, bd)) { bn = tn[t]; bd = td[t]; }
+    sn[threadIdx.x] = bn;
+    sd[threadIdx.x] = bd;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t rn = 0, rd = 0;
+        for (int i = kT - 1; i >= 0; --i) {
+            const int64_t xn = sn[i], xd = sd[i];
+            sn[i] = rn;
+            sd[i] = rd;
+            if (frac_gt(xn, xd, rn, rd)) { rn = xn; rd = xd; }
+        }
+    }
+    __syncthreads();
+    int64_t rn = sn[threadIdx.x], rd = sd[threadIdx.x];
+    for (int64_t t = t1 - 1; t >= t0; --t) {
         cn[t] = rn;
         cd[t] = rd;
-        if (frac_gt(tn[t], td[t], rn, rd)) {
-            rn = tn[t];
-            rd = td[t];
-        }
+        if (frac_gt(tn[t], td[t], rn, rd)) { rn = tn[t]; rd = td[t]; }
     }
 }
 
@@ -1573,7 +1591,7 @@ void sg_sort_prefix(Graph& g, int mode, hipStream_t s) {
     DBuf<int64_t> cn, cd;
     cn.alloc(tiles, s);
     cd.alloc(tiles, s);
-    k_tile_carry<<<1, 64, 0, s>>>(tn.p, td.p, tiles, cn.p, cd.p);
+    k_tile_carry<<<1, kT, 0, s>>>(tn.p, td.p, tiles, cn.p, cd.p);
     LDS_HIP(hipGetLastError());
     k_tile_inI<<<grid_for(tiles, 1), kT, 0, s>>>(q.E.p, n, cn.p, cd.p, q.inI.p);
     LDS_HIP(hipGetLastError());
