@@ -76,8 +76,9 @@ __global__ void k_order(const uint32_t* vals, int64_t n, int32_t* order, int64_t
 // that the bit position of a slot is known without a row search.  A block
 // takes one hub-row piece or one chunk (at most kPiece slots either way, so
 // the largest rows do not serialise in one block) in spans of kSpanW
-// decision words (64 slots each).  The span's words of kIterB = 64
-// iterations at a time are staged in LDS by coalesced loads.  A wave then
+// decision words (64 slots each).  The span's words of two batches of
+// kIterB = 64 iterations at a time are staged in LDS by coalesced loads,
+// all issued before the first is waited for.  A wave then
 // takes a word column (64 slots x 64 iterations, lane l holding iteration
 // l's word), transposes that bit matrix across its lanes (six exchange
 // steps), so that lane s holds slot s's 64 decisions, and sums the
@@ -119,7 +120,7 @@ __global__ __launch_bounds__(kT) void k_slot_splits(const int64_t* rp, int64_t n
                                                     const uint32_t* heavy_csr, uint32_t* a_slot) {
     // one padding word per iteration row: the lanes of a wave read one
     // column, 17 words apart, so their reads spread over the banks
-    __shared__ uint64_t sw[kIterB][kSpanW + 1];
+    __shared__ uint64_t sw[2][kIterB][kSpanW + 1];
     const int64_t b = blockIdx.x;
     int64_t s0, s1, word0;
     bool heavy = false;  // positions of the 2D part: the slot of position x is heavy_csr[x]
@@ -152,25 +153,36 @@ __global__ __launch_bounds__(kT) void k_slot_splits(const int64_t* rp, int64_t n
         uint32_t acc[kCols];
 #pragma unroll
         for (int q = 0; q < kCols; ++q) acc[q] = a0;
-        for (int i0 = 0; i0 < iters; i0 += kIterB) {
-            const int ni = min(kIterB, iters - i0);
-            __syncthreads();  // the previous batch has been read
-            for (int e = t; e < kIterB * kSpanW; e += kT) {
-                const int ii = e / kSpanW, ww = e % kSpanW;
-                sw[ii][ww] = (ii < ni && ww < nw) ? bits[(int64_t)(i0 + ii) * total_words + w0 + ww] : 0ull;
+        for (int i2 = 0; i2 < iters; i2 += 2 * kIterB) {
+            constexpr int kLoads = 2 * kIterB * kSpanW / kT;  // words per thread
+            static_assert(2 * kIterB * kSpanW % kT == 0, "whole loads per thread");
+            uint64_t v[kLoads];
+#pragma unroll
+            for (int l = 0; l < kLoads; ++l) {
+                const int e = t + l * kT, it = i2 + e / kSpanW, ww = e % kSpanW;
+                v[l] = (it < iters && ww < nw) ? bits[(int64_t)it * total_words + w0 + ww] : 0ull;
+            }
+            __syncthreads();  // the previous batches have been read
+#pragma unroll
+            for (int l = 0; l < kLoads; ++l) {
+                const int e = t + l * kT, ii = e / kSpanW;
+                sw[ii / kIterB][ii % kIterB][e % kSpanW] = v[l];
             }
             __syncthreads();
+            for (int bb = 0; bb < 2 && i2 + bb * kIterB < iters; ++bb) {
+                const int i0 = i2 + bb * kIterB;
 #pragma unroll
-            for (int q = 0; q < kCols; ++q) {
-                const int c = w + kWaves * q;
-                const uint64_t m = wave_transpose64(sw[lane][c]);  // lane: its slot's 64 iterations
-                uint32_t sum = (uint32_t)(i0 + 2) * (uint32_t)__popcll(m);
+                for (int q = 0; q < kCols; ++q) {
+                    const int c = w + kWaves * q;
+                    const uint64_t m = wave_transpose64(sw[bb][lane][c]);  // lane: its slot's 64 iterations
+                    uint32_t sum = (uint32_t)(i0 + 2) * (uint32_t)__popcll(m);
 #pragma unroll
-                for (int k = 0; k < 6; ++k) {
-                    const uint64_t mk = ~0ull / ((1ull << (1 << k)) + 1ull) << (1 << k);  // bit k of the index set
-                    sum += (uint32_t)__popcll(m & mk) << k;
+                    for (int k = 0; k < 6; ++k) {
+                        const uint64_t mk = ~0ull / ((1ull << (1 << k)) + 1ull) << (1 << k);  // bit k of the index set
+                        sum += (uint32_t)__popcll(m & mk) << k;
+                    }
+                    acc[q] += c2 * sum;
                 }
-                acc[q] += c2 * sum;
             }
         }
 #pragma unroll
