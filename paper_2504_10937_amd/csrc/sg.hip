@@ -747,13 +747,14 @@ __global__ void k_pos_slots(PassArgs a, uint64_t* cnt) {
 // current from there).  A vertex has one row, so the row's group of lanes
 // stores its vertex's sums; positions without slots keep the zero they were
 // filled with.  G lanes per row, 64 / G rows per wave: rows [r0, r1) of one
-// length class, so that short rows do not leave most of a wave idle (every
-// lane loops over its row with stride G, so any row length is handled).
+// length class, so that short rows do not leave most of a wave idle, and a
+// row of at most 64 slots takes one trip of dependent loads (every lane
+// loops over its row with stride G, so any row length is handled).
 template <int H, int G>
 __global__ __launch_bounds__(kT) void k_slot_records(PassArgs a, int64_t r0, int64_t r1, const int64_t* P,
                                                      int32_t* own, int2* rec2, int4* rec3, uint32_t* rec3w,
                                                      int64_t* c, int64_t* R, int64_t* T) {
-    static_assert(G == 8 || G == 16 || G == 64, "lanes per row: 8, 16 or 64");
+    static_assert(G == 8 || G == 16 || G == 32 || G == 64, "lanes per row: 8, 16, 32 or 64");
     const int lane = threadIdx.x & 63;
     const int64_t rw = r0 + ((int64_t)blockIdx.x * (kT / 64) + (threadIdx.x >> 6)) * (64 / G);
     if (rw >= r1) return;  // uniform over the wave
@@ -803,12 +804,12 @@ __global__ __launch_bounds__(kT) void k_slot_records(PassArgs a, int64_t r0, int
     }
 }
 
-// first row with at most t[i] slots, for the two class limits of
+// first row with at most 32, 16 and 8 slots: the class limits of
 // k_slot_records (rows are ordered by slot count, longest first)
-__global__ void k_record_classes(const int64_t* rp, int64_t nrows, int64_t t0, int64_t t1, int64_t* out) {
+__global__ void k_record_classes(const int64_t* rp, int64_t nrows, int64_t* out) {
     const int i = threadIdx.x;
-    if (i >= 2) return;
-    const int64_t t = i == 0 ? t0 : t1;
+    if (i >= 3) return;
+    const int64_t t = (int64_t)32 >> i;
     int64_t lo = 0, hi = nrows;
     while (lo < hi) {
         const int64_t mid = lo + (hi - lo) / 2;
@@ -1417,18 +1418,18 @@ void build_records(Graph& g, int mode, const PassArgs& a, hipStream_t s, int64_t
     if (pl.nrows == 0) return;
     k_pos_slots<<<grid_for(pl.nrows, kT), kT, 0, s>>>(a, (uint64_t*)q.rec_P.p);
     exclusive_scan_u64((const uint64_t*)q.rec_P.p, (uint64_t*)q.rec_P.p, n, (uint64_t*)q.rec_P.p + n, s);
-    // length classes: more than 32 slots (a wave per row), 9-32 (16 lanes),
-    // at most 8 (8 lanes)
-    int64_t cls[2] = {0, 0};
+    // length classes: more than 32 slots (a wave per row), 17-32 (32 lanes),
+    // 9-16 (16 lanes), at most 8 (8 lanes)
+    int64_t cls[3] = {0, 0, 0};
     {
         DBuf<int64_t> d;
-        d.alloc(2, s);
-        k_record_classes<<<1, 64, 0, s>>>(pl.rp, pl.nrows, 32, 8, d.p);
+        d.alloc(3, s);
+        k_record_classes<<<1, 64, 0, s>>>(pl.rp, pl.nrows, d.p);
         LDS_HIP(hipGetLastError());
         LDS_HIP(hipMemcpyAsync(cls, d.p, sizeof(cls), hipMemcpyDeviceToHost, s));
         LDS_HIP(hipStreamSynchronize(s));
     }
-    const int64_t b0 = 0, b1 = cls[0], b2 = std::max(cls[0], cls[1]), b3 = pl.nrows;
+    const int64_t b1 = cls[0], b2 = std::max(b1, cls[1]), b3 = std::max(b2, cls[2]), b4 = pl.nrows;
     const int wpb = kT / 64;  // waves per workgroup
     auto launch = [&](auto h, int64_t lo, int64_t hi, auto gl) {
         constexpr int H = decltype(h)::value, G = decltype(gl)::value;
@@ -1438,19 +1439,18 @@ void build_records(Graph& g, int mode, const PassArgs& a, hipStream_t s, int64_t
                                                                  q.rec3.p, q.rec3w.p, c, q.R.p, q.T.p);
         LDS_HIP(hipGetLastError());
     };
-    using G64 = std::integral_constant<int, 64>;
-    using G16 = std::integral_constant<int, 16>;
-    using G8 = std::integral_constant<int, 8>;
+    // (triangle rows stay one per wave: their slots gather the pattern's
+    // vertices, split numerators and positions, and the shared waves were
+    // slower there: 1.86 against 1.66 ms on ltds_hk; edges: 2.5 against 3.3 ms
+    // on lds_large)
     if (mode == 2) {
         using H2 = std::integral_constant<int, 2>;
-        launch(H2{}, b0, b1, G64{});
-        launch(H2{}, b1, b2, G16{});
-        launch(H2{}, b2, b3, G8{});
+        launch(H2{}, 0, b1, std::integral_constant<int, 64>{});
+        launch(H2{}, b1, b2, std::integral_constant<int, 32>{});
+        launch(H2{}, b2, b3, std::integral_constant<int, 16>{});
+        launch(H2{}, b3, b4, std::integral_constant<int, 8>{});
     } else {
-        using H3 = std::integral_constant<int, 3>;
-        launch(H3{}, b0, b1, G64{});
-        launch(H3{}, b1, b2, G16{});
-        launch(H3{}, b2, b3, G8{});
+        launch(std::integral_constant<int, 3>{}, 0, b4, std::integral_constant<int, 64>{});
     }
 }
 
